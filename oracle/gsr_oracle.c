@@ -391,7 +391,11 @@ void or_default_opts(or_opts *o)
 {
     o->tile_w = 16; o->tile_h = 16;
     o->alpha_max = 0.99; o->alpha_min = 1.0 / 255.0; o->t_min = 1e-4;
-    o->eps_alpha = 2e-6; o->eps_t = 2e-8; o->eps_z_rel = 5e-7;
+    /* margins sized to an FP32 compositing path: alpha carries ~1e-7 relative
+       rounding (5e-6 relative margin at 1/255), the transmittance product ~1e-6
+       relative after a few hundred factors (2e-5 relative margin at 1e-4),
+       depth keys come from an FP64 projection (near-exact ties only) */
+    o->eps_alpha = 2e-8; o->eps_t = 2e-9; o->eps_z_rel = 1e-9;
 }
 
 /*

@@ -1,0 +1,438 @@
+// gsr_api.hip -- host side of the C ABI declared in include/gsr.h: argument
+// checks, workspace layout and the launch sequence of each pass.  The library
+// never allocates device memory; all state of a pass lives in the caller's
+// workspace.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "gsr_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int check_hip(hipError_t e, const char *what) {
+    if (e == hipSuccess) return GSR_OK;
+    return fail(GSR_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+int build_views(int32_t n_views, const gsr_camera *cams, const gsr_launch_config *cfg, gsr::ViewTable &vt) {
+    if (n_views < 1 || n_views > GSR_MAX_VIEWS)
+        return fail(GSR_ERR_INVALID_ARGUMENT, "n_views=%d outside 1..%d", n_views, GSR_MAX_VIEWS);
+    if (!cams) return fail(GSR_ERR_INVALID_ARGUMENT, "cams is NULL");
+    int tile_h = cfg && cfg->tile_h ? cfg->tile_h : 16;
+    if (tile_h != 4 && tile_h != 8 && tile_h != 16 && tile_h != 32)
+        return fail(GSR_ERR_UNSUPPORTED, "tile_h=%d (supported: 4, 8, 16, 32)", tile_h);
+    std::memset(&vt, 0, sizeof(vt));
+    vt.n_views = n_views;
+    vt.tile_h = tile_h;
+    uint64_t tiles = 0, pixels = 0;
+    for (int v = 0; v < n_views; ++v) {
+        const gsr_camera &c = cams[v];
+        if (c.width < 1 || c.height < 1 || c.width > 65535 || c.height > 65535)
+            return fail(GSR_ERR_INVALID_ARGUMENT, "view %d: size %dx%d outside 1..65535", v, c.width, c.height);
+        if (!(c.fx > 0.f) || !(c.fy > 0.f))
+            return fail(GSR_ERR_INVALID_ARGUMENT, "view %d: focal lengths must be positive", v);
+        if (!(c.near_plane >= 0.f)) return fail(GSR_ERR_INVALID_ARGUMENT, "view %d: near_plane < 0", v);
+        gsr::ViewInfo &vi = vt.v[v];
+        vi.width = c.width;
+        vi.height = c.height;
+        vi.tiles_x = (c.width + gsr::kTileW - 1) / gsr::kTileW;
+        vi.tiles_y = (c.height + tile_h - 1) / tile_h;
+        vi.fx = c.fx;
+        vi.fy = c.fy;
+        vi.cx = c.cx;
+        vi.cy = c.cy;
+        vi.near_plane = c.near_plane;
+        // Jacobian evaluated at x/z, y/z clamped to 1.3 x the half-FOV tangent
+        vi.limx = 1.3f * ((float)c.width / (2.0f * c.fx));
+        vi.limy = 1.3f * ((float)c.height / (2.0f * c.fy));
+        vi.tile_off = (uint32_t)tiles;
+        vi.pix_off = (uint32_t)pixels;
+        tiles += (uint64_t)vi.tiles_x * vi.tiles_y;
+        pixels += (uint64_t)c.width * c.height;
+    }
+    if (tiles >= 0xffffffffull || pixels >= 0xffffffffull)
+        return fail(GSR_ERR_INVALID_ARGUMENT, "too many tiles or pixels in one call");
+    vt.total_tiles = (uint32_t)tiles;
+    vt.total_pixels = (uint32_t)pixels;
+    return GSR_OK;
+}
+
+int tile_bits(uint32_t total_tiles) {
+    int b = 1;
+    while ((1ull << b) < total_tiles) ++b;
+    return b;
+}
+
+gsr::WsLayout make_layout(uint64_t n, const gsr::ViewTable &vt, uint64_t cap) {
+    using namespace gsr;
+    WsLayout L{};
+    const uint64_t items = n * (uint64_t)vt.n_views;
+    L.items = items;
+    L.cap = cap;
+    const uint64_t hb_items = (items + kSortTile - 1) / kSortTile;
+    const uint64_t hb_pairs = (cap + kSortTile - 1) / kSortTile;
+    L.hist_blocks = (uint32_t)std::max<uint64_t>(1, std::max(hb_items, hb_pairs));
+    L.pose_blocks = (uint32_t)std::max<uint64_t>(1, (n + kProjThreads - 1) / kProjThreads);
+    const uint64_t scan_blocks = std::max<uint64_t>(1, (items + kScanTile - 1) / kScanTile);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    L.header = take(sizeof(WsHeader));
+    L.rec = take(sizeof(Rec) * items);
+    L.ulo = take(sizeof(float2) * items);
+    L.zkey = take(4 * items);
+    L.count = take(4 * items);
+    L.scan_tmp = take(4 * scan_blocks);
+    L.ckey[0] = take(4 * items);
+    L.ckey[1] = take(4 * items);
+    L.cval[0] = take(4 * items);
+    L.cval[1] = take(4 * items);
+    L.poff = take(4 * items);
+    L.pkey[0] = take(4 * cap);
+    L.pkey[1] = take(4 * cap);
+    L.pval[0] = take(4 * cap);
+    L.pval[1] = take(4 * cap);
+    L.hist = take(4ull * 256 * L.hist_blocks);
+    L.digit_total = take(4 * 256);
+    L.ranges = take(8ull * vt.total_tiles);
+    L.pix_T = take(4ull * vt.total_pixels);
+    L.pix_n = take(4ull * vt.total_pixels);
+    L.partial = take(4ull * kPartialStride * cap);
+    L.pose_part = take(4ull * 12 * vt.n_views * L.pose_blocks);
+    L.total = o;
+    return L;
+}
+
+int check_gaussians(const gsr_gaussians *g) {
+    if (!g) return fail(GSR_ERR_INVALID_ARGUMENT, "gaussians is NULL");
+    if (g->n < 0 || g->n > 0x7fffffffll) return fail(GSR_ERR_INVALID_ARGUMENT, "n=%lld outside 0..2^31-1", (long long)g->n);
+    if (g->sh_degree < 0 || g->sh_degree > 3)
+        return fail(GSR_ERR_UNSUPPORTED, "sh_degree=%d (supported: 0..3)", g->sh_degree);
+    if (g->n > 0) {
+        const void *ptrs[5] = {g->means, g->log_scales, g->quats, g->opacities, g->sh};
+        for (int k = 0; k < 5; ++k) {
+            if (!ptrs[k]) return fail(GSR_ERR_INVALID_ARGUMENT, "Gaussian parameter pointer %d is NULL", k);
+            if (reinterpret_cast<uintptr_t>(ptrs[k]) & 15u)
+                return fail(GSR_ERR_INVALID_ARGUMENT, "Gaussian parameter pointer %d is not 16-byte aligned", k);
+        }
+    }
+    return GSR_OK;
+}
+
+struct Ptrs {
+    gsr::WsHeader *hdr;
+    gsr::Rec *rec;
+    float2 *ulo;
+    uint32_t *zkey, *count, *scan_tmp, *ckey[2], *cval[2], *poff, *pkey[2], *pval[2], *hist, *digit_total;
+    uint2 *ranges;
+    float *pix_T;
+    uint32_t *pix_n;
+    float *partial, *pose_part;
+};
+
+Ptrs carve(void *ws, const gsr::WsLayout &L) {
+    char *b = static_cast<char *>(ws);
+    Ptrs p;
+    p.hdr = reinterpret_cast<gsr::WsHeader *>(b + L.header);
+    p.rec = reinterpret_cast<gsr::Rec *>(b + L.rec);
+    p.ulo = reinterpret_cast<float2 *>(b + L.ulo);
+    p.zkey = reinterpret_cast<uint32_t *>(b + L.zkey);
+    p.count = reinterpret_cast<uint32_t *>(b + L.count);
+    p.scan_tmp = reinterpret_cast<uint32_t *>(b + L.scan_tmp);
+    for (int k = 0; k < 2; ++k) {
+        p.ckey[k] = reinterpret_cast<uint32_t *>(b + L.ckey[k]);
+        p.cval[k] = reinterpret_cast<uint32_t *>(b + L.cval[k]);
+        p.pkey[k] = reinterpret_cast<uint32_t *>(b + L.pkey[k]);
+        p.pval[k] = reinterpret_cast<uint32_t *>(b + L.pval[k]);
+    }
+    p.poff = reinterpret_cast<uint32_t *>(b + L.poff);
+    p.hist = reinterpret_cast<uint32_t *>(b + L.hist);
+    p.digit_total = reinterpret_cast<uint32_t *>(b + L.digit_total);
+    p.ranges = reinterpret_cast<uint2 *>(b + L.ranges);
+    p.pix_T = reinterpret_cast<float *>(b + L.pix_T);
+    p.pix_n = reinterpret_cast<uint32_t *>(b + L.pix_n);
+    p.partial = reinterpret_cast<float *>(b + L.partial);
+    p.pose_part = reinterpret_cast<float *>(b + L.pose_part);
+    return p;
+}
+
+// Workspace capacity is recorded in the header; recover it from ws_bytes for
+// the query entry points by reading the header instead.
+int persistent_ctas(const gsr_launch_config *cfg) {
+    if (cfg && cfg->persistent_ctas > 0) return cfg->persistent_ctas;
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0, c = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && c > 0)
+            cus = c;
+        else
+            cus = 256;
+    }
+    return cus * 8;
+}
+
+// The pair capacity is whatever the workspace holds beyond the fixed regions;
+// forward, backward and introspection all derive it the same way.
+int layout_from_bytes(uint64_t n, const gsr::ViewTable &vt, size_t ws_bytes, gsr::WsLayout &L, uint64_t &cap) {
+    const gsr::WsLayout L0 = make_layout(n, vt, 1);
+    if (ws_bytes < L0.total) return fail(GSR_ERR_WORKSPACE_TOO_SMALL, "workspace %zu < %zu bytes", ws_bytes, L0.total);
+    // largest capacity whose layout fits (the layout size grows with it);
+    // per pair the workspace holds 4 key/value words and 9 gradient floats
+    uint64_t lo = 1, hi = (ws_bytes - L0.total) / (16 + 4 * gsr::kPartialStride) + 2;
+    if (hi > 0x7ffffffeull) hi = 0x7ffffffeull;
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo + 1) / 2;
+        if (make_layout(n, vt, mid).total <= ws_bytes)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    cap = lo;
+    L = make_layout(n, vt, cap);
+    if (L.total > ws_bytes) return fail(GSR_ERR_WORKSPACE_TOO_SMALL, "workspace too small");
+    return GSR_OK;
+}
+
+// Optional per-stage timing events (caller-owned hipEvent_t array).
+struct StageMark {
+    hipEvent_t *ev;
+    hipStream_t st;
+    void begin(int s) const {
+        if (ev) (void)hipEventRecord(ev[2 * s], st);
+    }
+    void end(int s) const {
+        if (ev) (void)hipEventRecord(ev[2 * s + 1], st);
+    }
+};
+
+// Number of tile-sort passes decides which ping-pong buffer holds the result.
+int pair_result_buffer(uint32_t total_tiles) { return ((tile_bits(total_tiles) + 7) / 8) & 1; }
+
+}  // namespace
+
+extern "C" {
+
+int gsr_version(void) { return GSR_ABI_VERSION; }
+
+const char *gsr_status_string(int status) {
+    switch (status) {
+        case GSR_OK: return "GSR_OK";
+        case GSR_ERR_INVALID_ARGUMENT: return "GSR_ERR_INVALID_ARGUMENT";
+        case GSR_ERR_WORKSPACE_TOO_SMALL: return "GSR_ERR_WORKSPACE_TOO_SMALL";
+        case GSR_ERR_CAPACITY: return "GSR_ERR_CAPACITY";
+        case GSR_ERR_HIP: return "GSR_ERR_HIP";
+        case GSR_ERR_UNSUPPORTED: return "GSR_ERR_UNSUPPORTED";
+        default: return "GSR_ERR_UNKNOWN";
+    }
+}
+
+const char *gsr_last_error(void) { return g_last_error.c_str(); }
+
+size_t gsr_workspace_bytes(int64_t n, int32_t n_views, const gsr_camera *cams, int64_t pair_capacity,
+                           const gsr_launch_config *cfg) {
+    gsr::ViewTable vt;
+    if (n < 0 || n > 0x7fffffffll) return (size_t)fail(0, "n=%lld outside 0..2^31-1", (long long)n);
+    if (pair_capacity < 1 || pair_capacity >= 0x7fffffffll)
+        return (size_t)fail(0, "pair_capacity=%lld outside 1..2^31-2", (long long)pair_capacity);
+    if (build_views(n_views, cams, cfg, vt) != GSR_OK) return 0;
+    if ((uint64_t)n * (uint64_t)n_views >= 0x7fffffffull)
+        return (size_t)fail(0, "n * n_views must stay below 2^31");
+    return make_layout((uint64_t)n, vt, (uint64_t)pair_capacity).total;
+}
+
+int gsr_rasterize_forward(void *ws, size_t ws_bytes, const gsr_gaussians *g, int32_t n_views,
+                          const gsr_camera *cams, const float *world_to_cam, const float *bg,
+                          const gsr_launch_config *cfg, float *out_rgb, float *out_T, uint32_t flags, void *stream) {
+    using namespace gsr;
+    int rc = check_gaussians(g);
+    if (rc) return rc;
+    ViewTable vt;
+    if ((rc = build_views(n_views, cams, cfg, vt))) return rc;
+    if (!ws || !world_to_cam || !bg || !out_rgb)
+        return fail(GSR_ERR_INVALID_ARGUMENT, "ws, world_to_cam, bg and out_rgb must not be NULL");
+    if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(GSR_ERR_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
+    if ((uint64_t)g->n * (uint64_t)n_views >= 0x7fffffffull)
+        return fail(GSR_ERR_INVALID_ARGUMENT, "n * n_views must stay below 2^31");
+    WsLayout L;
+    uint64_t cap = 0;
+    if ((rc = layout_from_bytes((uint64_t)g->n, vt, ws_bytes, L, cap))) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Ptrs p = carve(ws, L);
+    const uint64_t n = (uint64_t)g->n;
+    const float3 bgc = make_float3(bg[0], bg[1], bg[2]);
+
+    const StageMark mark{cfg ? static_cast<hipEvent_t *>(cfg->stage_events) : nullptr, st};
+
+    mark.begin(GSR_STAGE_PROJECT);
+    launch_reset_header(p.hdr, (uint32_t)cap, st);
+    launch_project_fwd(*g, vt, world_to_cam, n, p.rec, p.ulo, p.zkey, p.count, st);
+    mark.end(GSR_STAGE_PROJECT);
+    mark.begin(GSR_STAGE_DEPTH_SORT);
+    launch_compact_visible(p.count, p.zkey, L.items, p.ckey[0], p.cval[0], p.scan_tmp, p.hdr, st);
+    int cur = 0;
+    {
+        uint32_t *k2[2] = {p.ckey[0], p.ckey[1]}, *v2[2] = {p.cval[0], p.cval[1]};
+        radix_sort_u32(k2, v2, SortCount{&p.hdr->n_visible, nullptr}, L.items, 0, 32, p.hist, L.hist_blocks,
+                       p.digit_total, cur, st);
+    }
+    mark.end(GSR_STAGE_DEPTH_SORT);
+    const uint32_t *sorted_items = p.cval[cur];
+    mark.begin(GSR_STAGE_EMIT);
+    launch_pair_offsets(sorted_items, p.count, L.items, p.poff, p.scan_tmp, p.hdr, st);
+    uint64_t pair_grid = cap;
+    if (flags & GSR_FLAG_SYNC) {
+        WsHeader h;
+        if ((rc = check_hip(hipMemcpyAsync(&h, p.hdr, sizeof(h), hipMemcpyDeviceToHost, st), "header copy"))) return rc;
+        if ((rc = check_hip(hipStreamSynchronize(st), "stream sync"))) return rc;
+        if (h.overflow)
+            return fail(GSR_ERR_CAPACITY, "needs %u pairs, workspace holds %llu", h.n_pairs, (unsigned long long)cap);
+        pair_grid = h.n_pairs;
+    }
+    launch_emit_pairs(vt, sorted_items, p.poff, n, L.items, p.rec, p.pkey[0], p.pval[0], p.hdr, st);
+    mark.end(GSR_STAGE_EMIT);
+    mark.begin(GSR_STAGE_TILE_SORT);
+    int pc = 0;
+    {
+        uint32_t *k2[2] = {p.pkey[0], p.pkey[1]}, *v2[2] = {p.pval[0], p.pval[1]};
+        radix_sort_u32(k2, v2, SortCount{nullptr, p.hdr}, pair_grid, 0, tile_bits(vt.total_tiles), p.hist,
+                       L.hist_blocks, p.digit_total, pc, st);
+    }
+    launch_tile_ranges(p.pkey[pc], pair_grid, p.ranges, vt.total_tiles, p.hdr, st);
+    mark.end(GSR_STAGE_TILE_SORT);
+    const bool pers = (flags & GSR_FLAG_PERSISTENT) != 0;
+    mark.begin(GSR_STAGE_COMPOSITE_FWD);
+    launch_composite_fwd(vt, p.ranges, p.pval[pc], p.rec, p.ulo, bgc, out_rgb, out_T, p.pix_T, p.pix_n, p.hdr, pers,
+                         persistent_ctas(cfg), st);
+    mark.end(GSR_STAGE_COMPOSITE_FWD);
+    return check_hip(hipGetLastError(), "forward launch");
+}
+
+int gsr_rasterize_backward(void *ws, size_t ws_bytes, const gsr_gaussians *g, int32_t n_views,
+                           const gsr_camera *cams, const float *world_to_cam, const float *bg,
+                           const gsr_launch_config *cfg, const float *out_rgb, const float *dL_drgb,
+                           const gsr_gaussian_grads *grads, float *dL_dworld_to_cam, float *dL_dtwist, uint32_t flags,
+                           void *stream) {
+    using namespace gsr;
+    (void)bg;
+    int rc = check_gaussians(g);
+    if (rc) return rc;
+    ViewTable vt;
+    if ((rc = build_views(n_views, cams, cfg, vt))) return rc;
+    if (!ws || !world_to_cam || !out_rgb || !dL_drgb || !grads)
+        return fail(GSR_ERR_INVALID_ARGUMENT, "ws, world_to_cam, out_rgb, dL_drgb and grads must not be NULL");
+    if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacities || !grads->sh))
+        return fail(GSR_ERR_INVALID_ARGUMENT, "a gradient output pointer is NULL");
+    if (g->n > 0 && (reinterpret_cast<uintptr_t>(grads->quats) & 15u))
+        return fail(GSR_ERR_INVALID_ARGUMENT, "grads->quats must be 16-byte aligned");
+    WsLayout L;
+    uint64_t cap = 0;
+    if ((rc = layout_from_bytes((uint64_t)g->n, vt, ws_bytes, L, cap))) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Ptrs p = carve(ws, L);
+    const int pc = pair_result_buffer(vt.total_tiles);
+    const bool pers = (flags & GSR_FLAG_PERSISTENT) != 0;
+    const StageMark mark{cfg ? static_cast<hipEvent_t *>(cfg->stage_events) : nullptr, st};
+    mark.begin(GSR_STAGE_COMPOSITE_BWD);
+    launch_reset_queue(p.hdr, 1, st);
+    launch_composite_bwd(vt, p.ranges, p.pval[pc], p.rec, p.ulo, out_rgb, dL_drgb, p.pix_T, p.pix_n, p.partial, p.hdr,
+                         pers, persistent_ctas(cfg), st);
+    mark.end(GSR_STAGE_COMPOSITE_BWD);
+    mark.begin(GSR_STAGE_PROJECT_BWD);
+    launch_project_bwd(*g, vt, world_to_cam, (uint64_t)g->n, p.rec, p.count, p.hdr, p.partial, *grads, p.pose_part,
+                       L.pose_blocks, st);
+    if (g->n == 0)  // no Gaussian wrote a partial: the pose gradient is zero
+        launch_fill_u32(reinterpret_cast<uint32_t *>(p.pose_part), 0u, 12ull * vt.n_views * L.pose_blocks, st);
+    launch_pose_finalize(vt, world_to_cam, p.pose_part, L.pose_blocks, dL_dworld_to_cam, dL_dtwist, st);
+    mark.end(GSR_STAGE_PROJECT_BWD);
+    return check_hip(hipGetLastError(), "backward launch");
+}
+
+int gsr_query_pairs(const void *ws, size_t ws_bytes, int64_t *needed, int64_t *capacity, int32_t *overflowed,
+                    void *stream) {
+    if (!ws || ws_bytes < sizeof(gsr::WsHeader)) return fail(GSR_ERR_INVALID_ARGUMENT, "bad workspace");
+    gsr::WsHeader h;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int rc = check_hip(hipMemcpyAsync(&h, ws, sizeof(h), hipMemcpyDeviceToHost, st), "header copy");
+    if (rc) return rc;
+    if ((rc = check_hip(hipStreamSynchronize(st), "stream sync"))) return rc;
+    if (needed) *needed = h.n_pairs;
+    if (capacity) *capacity = h.pair_capacity;
+    if (overflowed) *overflowed = (int32_t)h.overflow;
+    return GSR_OK;
+}
+
+int gsr_query_stats(const void *ws, size_t ws_bytes, gsr_stats *out, void *stream) {
+    if (!ws || ws_bytes < sizeof(gsr::WsHeader) || !out) return fail(GSR_ERR_INVALID_ARGUMENT, "bad arguments");
+    gsr::WsHeader h;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int rc = check_hip(hipMemcpyAsync(&h, ws, sizeof(h), hipMemcpyDeviceToHost, st), "header copy");
+    if (rc) return rc;
+    if ((rc = check_hip(hipStreamSynchronize(st), "stream sync"))) return rc;
+    out->visible = h.n_visible;
+    out->pairs = h.n_pairs;
+    out->evaluations = (int64_t)h.evaluations;
+    out->contributors = (int64_t)h.contributors;
+    out->replays = (int64_t)h.replays;
+    return GSR_OK;
+}
+
+int gsr_export_state(const void *ws, size_t ws_bytes, const gsr_gaussians *g, int32_t n_views, const gsr_camera *cams,
+                     const gsr_launch_config *cfg, uint32_t *pair_tiles, uint32_t *pair_items, uint32_t *ranges,
+                     float *records, float *centre_lo, uint32_t *depth_keys, uint32_t *tile_counts, void *stream) {
+    using namespace gsr;
+    int rc = check_gaussians(g);
+    if (rc) return rc;
+    ViewTable vt;
+    if ((rc = build_views(n_views, cams, cfg, vt))) return rc;
+    if (!ws) return fail(GSR_ERR_INVALID_ARGUMENT, "ws is NULL");
+    WsLayout L;
+    uint64_t cap = 0;
+    if ((rc = layout_from_bytes((uint64_t)g->n, vt, ws_bytes, L, cap))) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Ptrs p = carve(const_cast<void *>(ws), L);
+    WsHeader h;
+    if ((rc = check_hip(hipMemcpyAsync(&h, p.hdr, sizeof(h), hipMemcpyDeviceToHost, st), "header copy"))) return rc;
+    if ((rc = check_hip(hipStreamSynchronize(st), "stream sync"))) return rc;
+    const uint64_t m = h.overflow ? 0 : std::min<uint64_t>(h.n_pairs, cap);
+    const int pc = pair_result_buffer(vt.total_tiles);
+    struct Copy {
+        void *dst;
+        const void *src;
+        size_t bytes;
+    } copies[] = {
+        {pair_tiles, p.pkey[pc], 4 * m},
+        {pair_items, p.pval[pc], 4 * m},
+        {ranges, p.ranges, 8ull * vt.total_tiles},
+        {records, p.rec, sizeof(Rec) * L.items},
+        {centre_lo, p.ulo, sizeof(float2) * L.items},
+        {depth_keys, p.zkey, 4 * L.items},
+        {tile_counts, p.count, 4 * L.items},
+    };
+    for (const Copy &c : copies) {
+        if (!c.dst || c.bytes == 0) continue;
+        if ((rc = check_hip(hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyDeviceToDevice, st), "export copy"))) return rc;
+    }
+    return GSR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,158 @@
+// gsr_internal.h -- definitions shared by the HIP translation units of the
+// rasterizer library (gfx950, wave64).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gsr.h"
+
+namespace gsr {
+
+constexpr int kWave = 64;
+constexpr int kTileW = 16;           // tile width in pixels (one row of a wave's 16 lanes)
+constexpr float kAlphaMax = 0.99f;   // alpha clamp
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kTMin = 1e-4f;       // stop before transmittance falls below this
+constexpr float kLowPass = 0.3f;     // added to the 2D covariance diagonal
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr uint32_t kCulledKey = 0xffffffffu;
+
+// Per-view constants passed by value in kernel arguments.
+struct ViewInfo {
+    int32_t width, height, tiles_x, tiles_y;
+    float fx, fy, cx, cy, near_plane, limx, limy;
+    uint32_t tile_off;   // first global tile id of the view
+    uint32_t pix_off;    // first pixel of the view in the concatenated images
+};
+
+struct ViewTable {
+    int32_t n_views;
+    int32_t tile_h;        // tile height in pixels (4, 8, 16 or 32)
+    uint32_t total_tiles;
+    uint32_t total_pixels;
+    ViewInfo v[GSR_MAX_VIEWS];
+};
+
+// Workspace header (first 256 bytes of the workspace, device memory).
+struct WsHeader {
+    uint32_t n_visible;      // visible (view, Gaussian) items
+    uint32_t n_pairs;        // pairs needed (saturates at 0xffffffff)
+    uint32_t overflow;       // 1 if n_pairs > capacity: binning was skipped
+    uint32_t pair_capacity;
+    unsigned long long evaluations;   // sum over pixels of list entries evaluated
+    unsigned long long replays;       // sum over pixels of n_contrib
+    unsigned long long contributors;  // sum over pixels of Gaussians composited
+    uint32_t queue[4];       // persistent-launch work counters
+    uint32_t pad[50];
+};
+static_assert(sizeof(WsHeader) == 256, "header is 256 bytes");
+
+// Projected record of one (view, Gaussian) item, three float4:
+//   r0 = (u_hi, v_hi, A, B)      conic (A, B, C) = inverse 2D covariance
+//   r1 = (C, opacity, red, green)
+//   r2 = (blue, bits(x0 | x1 << 16), bits(y0 | y1 << 16), bits(pair_offset))
+// The inclusive pixel box (x0..x1, y0..y1) is that of the alpha >= 1/255
+// ellipse.  The centre is stored as u = u_hi + u_lo (double-float) so that
+// tile-relative offsets keep ~1e-6 px accuracy; the low parts live in `ulo`.
+struct Rec {
+    float4 r0, r1, r2;
+};
+
+// Offsets of the workspace regions, all 256-byte aligned.
+struct WsLayout {
+    size_t header;
+    size_t rec;         // Rec[items]
+    size_t ulo;         // float2[items] low parts of (u, v)
+    size_t zkey;        // u32[items] depth key (float bits) or kCulledKey
+    size_t count;       // u32[items] tiles touched
+    size_t scan_tmp;    // u32 scratch for scans (block sums)
+    size_t ckey[2];     // u32[items] depth sort ping-pong keys
+    size_t cval[2];     // u32[items] depth sort ping-pong values (item ids)
+    size_t poff;        // u32[items] pair offset, in depth order
+    size_t pkey[2];     // u32[cap] tile keys ping-pong
+    size_t pval[2];     // u32[cap] item ids ping-pong
+    size_t hist;        // u32[256 * max_blocks] radix histograms
+    size_t digit_total; // u32[256] radix digit totals
+    size_t ranges;      // uint2[total_tiles]
+    size_t pix_T;       // float[total_pixels] final transmittance
+    size_t pix_n;       // u32[total_pixels] last contributor + 1
+    size_t partial;     // float[cap * 9] per-pair screen-space gradients
+    size_t pose_part;   // float[views * pose_blocks * 12]
+    size_t total;
+    uint64_t items, cap;
+    uint32_t hist_blocks, pose_blocks;
+};
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;     // 2048
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;     // 4096
+constexpr int kProjThreads = 256;
+constexpr int kPartialStride = 9;                         // floats per pair gradient
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip files).  All enqueue on `st`.
+// ---------------------------------------------------------------------------
+void launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t st);
+void launch_reset_header(WsHeader *h, uint32_t cap, hipStream_t st);
+
+void launch_project_fwd(const gsr_gaussians &g, const ViewTable &vt, const float *w2c, uint64_t n,
+                        Rec *rec, float2 *ulo, uint32_t *zkey, uint32_t *count, hipStream_t st);
+
+// Exclusive scans / compaction / sorting / binning.
+void launch_compact_visible(const uint32_t *count, const uint32_t *zkey, uint64_t items, uint32_t *ckey,
+                            uint32_t *cval, uint32_t *block_tmp, WsHeader *hdr, hipStream_t st);
+// Element count of a sort, read on the device: *n_dev, or (hdr set) the pair
+// count, 0 if the binning overflowed.
+struct SortCount {
+    const uint32_t *n_dev;
+    const WsHeader *hdr;
+    __device__ uint64_t operator()() const {
+        if (hdr) return hdr->overflow ? 0ull : (uint64_t)hdr->n_pairs;
+        return (uint64_t)*n_dev;
+    }
+};
+// Stable LSD sort of (key, value) on bits [begin_bit, end_bit), 8 per pass,
+// ping-ponging between keys[cur]/keys[cur ^ 1]; `cur` ends at the result.
+void radix_sort_u32(uint32_t *keys[2], uint32_t *vals[2], SortCount sc, uint64_t n_cap, int begin_bit, int end_bit,
+                    uint32_t *hist, uint32_t hist_blocks, uint32_t *digit_total, int &cur, hipStream_t st);
+void launch_reset_queue(WsHeader *h, int which, hipStream_t st);
+void launch_pair_offsets(const uint32_t *sorted_items, const uint32_t *count, uint64_t items_cap,
+                         uint32_t *poff, uint32_t *block_tmp, WsHeader *hdr, hipStream_t st);
+void launch_emit_pairs(const ViewTable &vt, const uint32_t *sorted_items, const uint32_t *poff, uint64_t n,
+                       uint64_t items_cap, Rec *rec, uint32_t *pkey, uint32_t *pval, const WsHeader *hdr,
+                       hipStream_t st);
+void launch_tile_ranges(const uint32_t *pkey, uint64_t cap, uint2 *ranges, uint32_t total_tiles,
+                        const WsHeader *hdr, hipStream_t st);
+
+void launch_composite_fwd(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
+                          const float2 *ulo, float3 bg, float *out_rgb, float *out_T, float *pix_T,
+                          uint32_t *pix_n, WsHeader *hdr, bool persistent, int persistent_ctas,
+                          hipStream_t st);
+void launch_composite_bwd(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
+                          const float2 *ulo, const float *out_rgb, const float *dL_drgb, const float *pix_T,
+                          const uint32_t *pix_n, float *partial, WsHeader *hdr, bool persistent,
+                          int persistent_ctas, hipStream_t st);
+
+void launch_project_bwd(const gsr_gaussians &g, const ViewTable &vt, const float *w2c, uint64_t n,
+                        const Rec *rec, const uint32_t *count, const WsHeader *hdr, const float *partial,
+                        const gsr_gaussian_grads &gr, float *pose_part, uint32_t pose_blocks, hipStream_t st);
+void launch_pose_finalize(const ViewTable &vt, const float *w2c, const float *pose_part, uint32_t pose_blocks,
+                          float *dL_dw2c, float *dL_dtwist, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float wave_sum(float x) {
+    // butterfly over the 64 lanes; every lane ends with the total
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+    return x;
+}
+
+__device__ __forceinline__ uint32_t pack_u16(uint32_t lo, uint32_t hi) { return lo | (hi << 16); }
+
+}  // namespace gsr

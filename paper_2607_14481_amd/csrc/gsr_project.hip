@@ -1,0 +1,583 @@
+// gsr_project.hip -- per-Gaussian stages of the rasterizer on gfx950:
+//   A1 k_project_fwd  : EWA projection, SH colour, alpha >= 1/255 box, tile count
+//   A8+A9 k_project_bwd: per-Gaussian sum of the per-pair screen-space
+//                        gradients, chain rule to every parameter, per-block
+//                        partial sums of each view's pose gradient
+//   k_pose_finalize    : fixed-order sum of those partials, 4x4 and 6-DoF twist
+//
+// The geometric part of A1 runs in FP64: it is HBM-bound (~100-300 bytes per
+// Gaussian against a few hundred flops), so double precision costs nothing
+// measurable and keeps the centre, box and depth key within an ulp of the exact
+// values (world coordinates of tens of metres otherwise cost ~1e-4 px).
+#include "gsr_internal.h"
+
+namespace gsr {
+
+// Real SH basis of degree <= 3 in the 3DGS order and signs (real harmonics with
+// the Condon-Shortley phase, m = -l..l).  Normalisations: c0 = 1/(2 sqrt(pi)),
+// c1 = sqrt(3/(4 pi)), c2a = sqrt(15/pi)/2, c2b = sqrt(5/pi)/4,
+// c2c = sqrt(15/pi)/4, c3a = sqrt(35/(2 pi))/4, c3b = sqrt(105/pi)/2,
+// c3c = sqrt(21/(2 pi))/4, c3d = sqrt(7/pi)/4, c3e = sqrt(105/pi)/4.
+struct ShC {
+    static constexpr double c0 = 0.28209479177387814, c1 = 0.4886025119029199;
+    static constexpr double c2a = 1.0925484305920792, c2b = 0.31539156525252005, c2c = 0.5462742152960396;
+    static constexpr double c3a = 0.5900435899266435, c3b = 2.890611442640554, c3c = 0.4570457994644658;
+    static constexpr double c3d = 0.3731763325901154, c3e = 1.445305721320277;
+};
+
+template <int DEG, typename T>
+__device__ __forceinline__ void sh_eval(T x, T y, T z, T *Y) {
+    Y[0] = T(ShC::c0);
+    if constexpr (DEG >= 1) {
+        Y[1] = -T(ShC::c1) * y;
+        Y[2] = T(ShC::c1) * z;
+        Y[3] = -T(ShC::c1) * x;
+    }
+    if constexpr (DEG >= 2) {
+        const T xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = T(ShC::c2a) * x * y;
+        Y[5] = -T(ShC::c2a) * y * z;
+        Y[6] = T(ShC::c2b) * (T(2) * zz - xx - yy);
+        Y[7] = -T(ShC::c2a) * x * z;
+        Y[8] = T(ShC::c2c) * (xx - yy);
+        if constexpr (DEG >= 3) {
+            Y[9] = -T(ShC::c3a) * y * (T(3) * xx - yy);
+            Y[10] = T(ShC::c3b) * x * y * z;
+            Y[11] = -T(ShC::c3c) * y * (T(4) * zz - xx - yy);
+            Y[12] = T(ShC::c3d) * z * (T(2) * zz - T(3) * xx - T(3) * yy);
+            Y[13] = -T(ShC::c3c) * x * (T(4) * zz - xx - yy);
+            Y[14] = T(ShC::c3e) * z * (xx - yy);
+            Y[15] = -T(ShC::c3a) * x * (xx - T(3) * yy);
+        }
+    }
+}
+
+// Gradient of sum_k w_k Y_k(x, y, z) with respect to (x, y, z), for weights w.
+template <int DEG>
+__device__ __forceinline__ void sh_grad_dir(float x, float y, float z, const float *w, float &gx, float &gy,
+                                            float &gz) {
+    gx = gy = gz = 0.f;
+    if constexpr (DEG >= 1) {
+        const float c1 = float(ShC::c1);
+        gy -= c1 * w[1];
+        gz += c1 * w[2];
+        gx -= c1 * w[3];
+    }
+    if constexpr (DEG >= 2) {
+        const float a = float(ShC::c2a), b = float(ShC::c2b), c = float(ShC::c2c);
+        gx += a * y * w[4];
+        gy += a * x * w[4];
+        gy -= a * z * w[5];
+        gz -= a * y * w[5];
+        gx -= 2.f * b * x * w[6];
+        gy -= 2.f * b * y * w[6];
+        gz += 4.f * b * z * w[6];
+        gx -= a * z * w[7];
+        gz -= a * x * w[7];
+        gx += 2.f * c * x * w[8];
+        gy -= 2.f * c * y * w[8];
+    }
+    if constexpr (DEG >= 3) {
+        const float a = float(ShC::c3a), b = float(ShC::c3b), c = float(ShC::c3c);
+        const float d = float(ShC::c3d), e = float(ShC::c3e);
+        const float xx = x * x, yy = y * y, zz = z * z;
+        // y(3x^2 - y^2)
+        gx -= a * 6.f * x * y * w[9];
+        gy -= a * (3.f * xx - 3.f * yy) * w[9];
+        // xyz
+        gx += b * y * z * w[10];
+        gy += b * x * z * w[10];
+        gz += b * x * y * w[10];
+        // y(4z^2 - x^2 - y^2)
+        gx += c * 2.f * x * y * w[11];
+        gy -= c * (4.f * zz - xx - 3.f * yy) * w[11];
+        gz -= c * 8.f * y * z * w[11];
+        // z(2z^2 - 3x^2 - 3y^2)
+        gx -= d * 6.f * x * z * w[12];
+        gy -= d * 6.f * y * z * w[12];
+        gz += d * (6.f * zz - 3.f * xx - 3.f * yy) * w[12];
+        // x(4z^2 - x^2 - y^2)
+        gx -= c * (4.f * zz - 3.f * xx - yy) * w[13];
+        gy += c * 2.f * x * y * w[13];
+        gz -= c * 8.f * x * z * w[13];
+        // z(x^2 - y^2)
+        gx += e * 2.f * x * z * w[14];
+        gy -= e * 2.f * y * z * w[14];
+        gz += e * (xx - yy) * w[14];
+        // x(x^2 - 3y^2)
+        gx -= a * (3.f * xx - 3.f * yy) * w[15];
+        gy += a * 6.f * x * y * w[15];
+    }
+}
+
+// Rotation matrix of a unit quaternion (w, x, y, z).
+template <typename T>
+__device__ __forceinline__ void quat_rot(T w, T x, T y, T z, T R[9]) {
+    R[0] = T(1) - T(2) * (y * y + z * z);
+    R[1] = T(2) * (x * y - w * z);
+    R[2] = T(2) * (x * z + w * y);
+    R[3] = T(2) * (x * y + w * z);
+    R[4] = T(1) - T(2) * (x * x + z * z);
+    R[5] = T(2) * (y * z - w * x);
+    R[6] = T(2) * (x * z - w * y);
+    R[7] = T(2) * (y * z + w * x);
+    R[8] = T(1) - T(2) * (x * x + y * y);
+}
+
+__device__ __forceinline__ void load_pose(const float *__restrict__ w2c, int v, float W[9], float t[3]) {
+    const float *m = w2c + 16 * v;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        W[3 * r + 0] = m[4 * r + 0];
+        W[3 * r + 1] = m[4 * r + 1];
+        W[3 * r + 2] = m[4 * r + 2];
+        t[r] = m[4 * r + 3];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// A1: projection forward.  One thread per (view, Gaussian) item, item = v n + i.
+// ---------------------------------------------------------------------------
+template <int DEG>
+__global__ __launch_bounds__(kProjThreads) void k_project_fwd(gsr_gaussians g, ViewTable vt,
+                                                              const float *__restrict__ w2c, uint64_t n,
+                                                              Rec *__restrict__ rec, float2 *__restrict__ ulo,
+                                                              uint32_t *__restrict__ zkey,
+                                                              uint32_t *__restrict__ count) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    const uint64_t item = (uint64_t)blockIdx.x * kProjThreads + threadIdx.x;
+    if (item >= n * (uint64_t)vt.n_views) return;
+    const int v = (int)(item / n);
+    const uint64_t i = item - (uint64_t)v * n;
+    const ViewInfo cam = vt.v[v];
+
+    float Wf[9], tf[3];
+    load_pose(w2c, v, Wf, tf);
+    const double mx = g.means[3 * i + 0], my = g.means[3 * i + 1], mz = g.means[3 * i + 2];
+    const double px = (double)Wf[0] * mx + (double)Wf[1] * my + (double)Wf[2] * mz + (double)tf[0];
+    const double py = (double)Wf[3] * mx + (double)Wf[4] * my + (double)Wf[5] * mz + (double)tf[1];
+    const double pz = (double)Wf[6] * mx + (double)Wf[7] * my + (double)Wf[8] * mz + (double)tf[2];
+
+    uint32_t cnt = 0;
+    uint32_t key = kCulledKey;
+    do {
+        if (!(pz > (double)cam.near_plane)) break;
+        const float4 qf = reinterpret_cast<const float4 *>(g.quats)[i];
+        const double qn = sqrt((double)qf.x * qf.x + (double)qf.y * qf.y + (double)qf.z * qf.z + (double)qf.w * qf.w);
+        if (!(qn > 0.0)) break;
+        double R[9];
+        quat_rot<double>(qf.x / qn, qf.y / qn, qf.z / qn, qf.w / qn, R);
+        const double s0 = exp((double)g.log_scales[3 * i + 0]);
+        const double s1 = exp((double)g.log_scales[3 * i + 1]);
+        const double s2 = exp((double)g.log_scales[3 * i + 2]);
+        // M = R diag(s); Sigma = M M^T (symmetric, 6 entries)
+        const double M[9] = {R[0] * s0, R[1] * s1, R[2] * s2, R[3] * s0, R[4] * s1,
+                             R[5] * s2, R[6] * s0, R[7] * s1, R[8] * s2};
+        double Sg[9];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                Sg[3 * a + b] = M[3 * a] * M[3 * b] + M[3 * a + 1] * M[3 * b + 1] + M[3 * a + 2] * M[3 * b + 2];
+        const double rx = px / pz, ry = py / pz;
+        const double rxc = fmin(fmax(rx, -(double)cam.limx), (double)cam.limx);
+        const double ryc = fmin(fmax(ry, -(double)cam.limy), (double)cam.limy);
+        const double j00 = cam.fx / pz, j02 = -cam.fx * rxc / pz;
+        const double j11 = cam.fy / pz, j12 = -cam.fy * ryc / pz;
+        // T = J W (2x3)
+        double T0[3], T1[3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            T0[b] = j00 * Wf[b] + j02 * Wf[6 + b];
+            T1[b] = j11 * Wf[3 + b] + j12 * Wf[6 + b];
+        }
+        double TS0[3], TS1[3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            TS0[b] = T0[0] * Sg[b] + T0[1] * Sg[3 + b] + T0[2] * Sg[6 + b];
+            TS1[b] = T1[0] * Sg[b] + T1[1] * Sg[3 + b] + T1[2] * Sg[6 + b];
+        }
+        const double ca = TS0[0] * T0[0] + TS0[1] * T0[1] + TS0[2] * T0[2] + (double)kLowPass;
+        const double cb = TS0[0] * T1[0] + TS0[1] * T1[1] + TS0[2] * T1[2];
+        const double cc = TS1[0] * T1[0] + TS1[1] * T1[1] + TS1[2] * T1[2] + (double)kLowPass;
+        const double det = ca * cc - cb * cb;
+        if (!(det > 0.0)) break;
+        const float op = g.opacities[i];
+        if (!(op >= kAlphaMin)) break;
+        const double u = cam.fx * rx + cam.cx, vv = cam.fy * ry + cam.cy;
+        // exact box of the alpha >= 1/255 ellipse, pixel centres at i + 1/2
+        const double k2 = 2.0 * log(255.0 * (double)op);
+        const double ex = sqrt(k2 * ca), ey = sqrt(k2 * cc);
+        double x0 = ceil(u - ex - 0.5), x1 = floor(u + ex - 0.5);
+        double y0 = ceil(vv - ey - 0.5), y1 = floor(vv + ey - 0.5);
+        x0 = fmax(x0, 0.0);
+        y0 = fmax(y0, 0.0);
+        x1 = fmin(x1, (double)(cam.width - 1));
+        y1 = fmin(y1, (double)(cam.height - 1));
+        if (!(x0 <= x1) || !(y0 <= y1)) break;
+        const uint32_t ix0 = (uint32_t)x0, ix1 = (uint32_t)x1, iy0 = (uint32_t)y0, iy1 = (uint32_t)y1;
+        cnt = (ix1 / kTileW - ix0 / kTileW + 1) * (iy1 / vt.tile_h - iy0 / vt.tile_h + 1);
+        key = __float_as_uint((float)pz);
+
+        // colour: direction from the camera centre c = -W^T t, world frame
+        const double cx = -((double)Wf[0] * tf[0] + (double)Wf[3] * tf[1] + (double)Wf[6] * tf[2]);
+        const double cy = -((double)Wf[1] * tf[0] + (double)Wf[4] * tf[1] + (double)Wf[7] * tf[2]);
+        const double cz = -((double)Wf[2] * tf[0] + (double)Wf[5] * tf[1] + (double)Wf[8] * tf[2]);
+        double dx = mx - cx, dy = my - cy, dz = mz - cz;
+        const double dn = sqrt(dx * dx + dy * dy + dz * dz);
+        dx /= dn;
+        dy /= dn;
+        dz /= dn;
+        double Y[K];
+        sh_eval<DEG, double>(dx, dy, dz, Y);
+        double col[3] = {0.5, 0.5, 0.5};
+        const float *shp = g.sh + (size_t)i * K * 3;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            col[0] += (double)shp[3 * k + 0] * Y[k];
+            col[1] += (double)shp[3 * k + 1] * Y[k];
+            col[2] += (double)shp[3 * k + 2] * Y[k];
+        }
+        const float uh = (float)u, vh = (float)vv;
+        Rec r;
+        r.r0 = make_float4(uh, vh, (float)(cc / det), (float)(-cb / det));
+        r.r1 = make_float4((float)(ca / det), op, (float)fmax(col[0], 0.0), (float)fmax(col[1], 0.0));
+        r.r2 = make_float4((float)fmax(col[2], 0.0), __uint_as_float(pack_u16(ix0, ix1)),
+                           __uint_as_float(pack_u16(iy0, iy1)), 0.f);
+        rec[item] = r;
+        ulo[item] = make_float2((float)(u - (double)uh), (float)(vv - (double)vh));
+    } while (0);
+    zkey[item] = key;
+    count[item] = cnt;
+}
+
+void launch_project_fwd(const gsr_gaussians &g, const ViewTable &vt, const float *w2c, uint64_t n, Rec *rec,
+                        float2 *ulo, uint32_t *zkey, uint32_t *count, hipStream_t st) {
+    const uint64_t items = n * (uint64_t)vt.n_views;
+    if (items == 0) return;
+    const dim3 grid((unsigned)((items + kProjThreads - 1) / kProjThreads));
+    switch (g.sh_degree) {
+        case 0: hipLaunchKernelGGL(k_project_fwd<0>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, ulo, zkey, count); break;
+        case 1: hipLaunchKernelGGL(k_project_fwd<1>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, ulo, zkey, count); break;
+        case 2: hipLaunchKernelGGL(k_project_fwd<2>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, ulo, zkey, count); break;
+        default: hipLaunchKernelGGL(k_project_fwd<3>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, ulo, zkey, count); break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// A8 + A9: projection backward.  One thread per Gaussian; loops over views.
+// Screen-space gradient per item = fixed-order sum over its pairs (which the
+// binning laid out contiguously), so the result is deterministic.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float block_sum_256(float x, float *red /* [4] */) {
+    x = wave_sum(x);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[w] = x;
+    __syncthreads();
+    const float s = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    return s;
+}
+
+template <int DEG>
+__global__ __launch_bounds__(kProjThreads) void k_project_bwd(
+    gsr_gaussians g, ViewTable vt, const float *__restrict__ w2c, uint64_t n, const Rec *__restrict__ rec,
+    const uint32_t *__restrict__ count, const WsHeader *__restrict__ hdr, const float *__restrict__ partial,
+    gsr_gaussian_grads gr, float *__restrict__ pose_part, uint32_t pose_blocks) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    __shared__ float red[4];
+    const uint64_t i = (uint64_t)blockIdx.x * kProjThreads + threadIdx.x;
+    // after a pair overflow no pair gradient exists: every Gaussian gets zero
+    const bool live = i < n && hdr->overflow == 0u;
+
+    float gmu[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gop = 0.f;
+    float gsh[K][3];
+#pragma unroll
+    for (int k = 0; k < K; ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.f;
+
+    for (int v = 0; v < vt.n_views; ++v) {
+        float gW[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gt[3] = {0, 0, 0};
+        const uint64_t item = (uint64_t)v * n + i;
+        const uint32_t cnt = live ? count[item] : 0u;
+        if (cnt > 0) {
+            const ViewInfo cam = vt.v[v];
+            // A8: sum this item's per-pair screen-space gradients
+            const uint32_t off = __float_as_uint(rec[item].r2.w);
+            float s[kPartialStride] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+            const float *pp = partial + (size_t)off * kPartialStride;
+            for (uint32_t k = 0; k < cnt; ++k)
+#pragma unroll
+                for (int c = 0; c < kPartialStride; ++c) s[c] += pp[(size_t)k * kPartialStride + c];
+            const float gu = s[0], gv = s[1], gA = s[2], gB = s[3], gC = s[4], go = s[5];
+            const float grgb[3] = {s[6], s[7], s[8]};
+
+            float W[9], t[3];
+            load_pose(w2c, v, W, t);
+            const float mu[3] = {g.means[3 * i], g.means[3 * i + 1], g.means[3 * i + 2]};
+            const double pxd = (double)W[0] * mu[0] + (double)W[1] * mu[1] + (double)W[2] * mu[2] + (double)t[0];
+            const double pyd = (double)W[3] * mu[0] + (double)W[4] * mu[1] + (double)W[5] * mu[2] + (double)t[1];
+            const double pzd = (double)W[6] * mu[0] + (double)W[7] * mu[1] + (double)W[8] * mu[2] + (double)t[2];
+            const float p[3] = {(float)pxd, (float)pyd, (float)pzd};
+
+            gop += go;
+
+            // ---- colour -> SH coefficients and direction
+            const float cxw = -(W[0] * t[0] + W[3] * t[1] + W[6] * t[2]);
+            const float cyw = -(W[1] * t[0] + W[4] * t[1] + W[7] * t[2]);
+            const float czw = -(W[2] * t[0] + W[5] * t[1] + W[8] * t[2]);
+            float dvec[3] = {mu[0] - cxw, mu[1] - cyw, mu[2] - czw};
+            const float dn = sqrtf(dvec[0] * dvec[0] + dvec[1] * dvec[1] + dvec[2] * dvec[2]);
+            const float dir[3] = {dvec[0] / dn, dvec[1] / dn, dvec[2] / dn};
+            float Y[K];
+            sh_eval<DEG, float>(dir[0], dir[1], dir[2], Y);
+            const float *shp = g.sh + (size_t)i * K * 3;
+            float col[3] = {0.5f, 0.5f, 0.5f};
+            float shv[K][3];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                shv[k][0] = shp[3 * k];
+                shv[k][1] = shp[3 * k + 1];
+                shv[k][2] = shp[3 * k + 2];
+                col[0] += shv[k][0] * Y[k];
+                col[1] += shv[k][1] * Y[k];
+                col[2] += shv[k][2] * Y[k];
+            }
+            float gc[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) gc[c] = col[c] < 0.f ? 0.f : grgb[c];
+            float wdir[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                gsh[k][0] += gc[0] * Y[k];
+                gsh[k][1] += gc[1] * Y[k];
+                gsh[k][2] += gc[2] * Y[k];
+                wdir[k] = gc[0] * shv[k][0] + gc[1] * shv[k][1] + gc[2] * shv[k][2];
+            }
+            float gdx, gdy, gdz;
+            sh_grad_dir<DEG>(dir[0], dir[1], dir[2], wdir, gdx, gdy, gdz);
+            const float dd = gdx * dir[0] + gdy * dir[1] + gdz * dir[2];
+            const float gd[3] = {(gdx - dir[0] * dd) / dn, (gdy - dir[1] * dd) / dn, (gdz - dir[2] * dd) / dn};
+            // mean gets +gd, camera centre gets -gd; c_a = -sum_b W[b][a] t_b
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                gmu[a] += gd[a];
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    gW[3 * b + a] += t[b] * gd[a];
+                    gt[b] += W[3 * b + a] * gd[a];
+                }
+            }
+
+            // ---- recompute the covariance chain
+            const float4 qf = reinterpret_cast<const float4 *>(g.quats)[i];
+            const float qn = sqrtf(qf.x * qf.x + qf.y * qf.y + qf.z * qf.z + qf.w * qf.w);
+            const float q[4] = {qf.x / qn, qf.y / qn, qf.z / qn, qf.w / qn};
+            float R[9];
+            quat_rot<float>(q[0], q[1], q[2], q[3], R);
+            const float sc[3] = {expf(g.log_scales[3 * i]), expf(g.log_scales[3 * i + 1]),
+                                 expf(g.log_scales[3 * i + 2])};
+            float M[9];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) M[3 * a + b] = R[3 * a + b] * sc[b];
+            float Sg[9];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+                    Sg[3 * a + b] = M[3 * a] * M[3 * b] + M[3 * a + 1] * M[3 * b + 1] + M[3 * a + 2] * M[3 * b + 2];
+            const float rx = (float)(pxd / pzd), ry = (float)(pyd / pzd);
+            const float rxc = fminf(fmaxf(rx, -cam.limx), cam.limx);
+            const float ryc = fminf(fmaxf(ry, -cam.limy), cam.limy);
+            const float iz = 1.f / p[2];
+            float J[6] = {cam.fx * iz, 0.f, -cam.fx * rxc * iz, 0.f, cam.fy * iz, -cam.fy * ryc * iz};
+            float T[6];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+                    T[3 * a + b] = J[3 * a] * W[b] + J[3 * a + 1] * W[3 + b] + J[3 * a + 2] * W[6 + b];
+            float TS[6];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+                    TS[3 * a + b] = T[3 * a] * Sg[b] + T[3 * a + 1] * Sg[3 + b] + T[3 * a + 2] * Sg[6 + b];
+            const double ca = (double)(TS[0] * T[0] + TS[1] * T[1] + TS[2] * T[2]) + (double)kLowPass;
+            const double cb = (double)(TS[0] * T[3] + TS[1] * T[4] + TS[2] * T[5]);
+            const double cc = (double)(TS[3] * T[3] + TS[4] * T[4] + TS[5] * T[5]) + (double)kLowPass;
+            // ---- conic (A, B, C) -> covariance (a, b, c)
+            const double D = ca * cc - cb * cb;
+            const double iD2 = 1.0 / (D * D);
+            const float ga = (float)((-cc * cc * gA + cb * cc * gB - cb * cb * gC) * iD2);
+            const float gb = (float)((2.0 * cb * cc * gA - (ca * cc + cb * cb) * gB + 2.0 * ca * cb * gC) * iD2);
+            const float gcv = (float)((-cb * cb * gA + ca * cb * gB - ca * ca * gC) * iD2);
+            const float G2[4] = {ga, 0.5f * gb, 0.5f * gb, gcv};
+            // gSigma = T^T G2 T (3x3), gT = 2 G2 T Sigma (2x3)
+            float gS[9];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+                    gS[3 * a + b] = T[a] * (G2[0] * T[b] + G2[1] * T[3 + b]) + T[3 + a] * (G2[2] * T[b] + G2[3] * T[3 + b]);
+            float gT[6];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+                    gT[3 * a + b] = 2.f * (G2[2 * a] * TS[b] + G2[2 * a + 1] * TS[3 + b]);
+            // T = J W: gJ = gT W^T, gW += J^T gT
+            float gJ[6];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+                    gJ[3 * a + b] = gT[3 * a] * W[3 * b] + gT[3 * a + 1] * W[3 * b + 1] + gT[3 * a + 2] * W[3 * b + 2];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) gW[3 * a + b] += J[a] * gT[b] + J[3 + a] * gT[3 + b];
+            // J entries -> camera-space mean
+            float gp[3] = {0.f, 0.f, 0.f};
+            const float iz2 = iz * iz;
+            gp[2] += -cam.fx * iz2 * gJ[0] - cam.fy * iz2 * gJ[4];
+            const float grxc = -cam.fx * iz * gJ[2];
+            const float gryc = -cam.fy * iz * gJ[5];
+            gp[2] += cam.fx * rxc * iz2 * gJ[2] + cam.fy * ryc * iz2 * gJ[5];
+            if (rx >= -cam.limx && rx <= cam.limx) {
+                gp[0] += grxc * iz;
+                gp[2] -= grxc * p[0] * iz2;
+            }
+            if (ry >= -cam.limy && ry <= cam.limy) {
+                gp[1] += gryc * iz;
+                gp[2] -= gryc * p[1] * iz2;
+            }
+            // centre (u, v)
+            gp[0] += gu * cam.fx * iz;
+            gp[1] += gv * cam.fy * iz;
+            gp[2] -= (gu * cam.fx * p[0] + gv * cam.fy * p[1]) * iz2;
+            // p = W mu + t
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                gmu[a] += W[a] * gp[0] + W[3 + a] * gp[1] + W[6 + a] * gp[2];
+                gt[a] += gp[a];
+#pragma unroll
+                for (int b = 0; b < 3; ++b) gW[3 * a + b] += gp[a] * mu[b];
+            }
+            // Sigma = M M^T, M = R diag(s): gM = 2 gSigma M
+            float gR[9];
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                float gsb = 0.f;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const float gM = 2.f * (gS[3 * a] * M[b] + gS[3 * a + 1] * M[3 + b] + gS[3 * a + 2] * M[6 + b]);
+                    gR[3 * a + b] = gM * sc[b];
+                    gsb += gM * R[3 * a + b];
+                }
+                gls[b] += gsb * sc[b];
+            }
+            // R(q_hat) -> q_hat
+            const float w = q[0], x = q[1], y = q[2], z = q[3];
+            float gqh[4];
+            gqh[0] = 2.f * (-z * gR[1] + y * gR[2] + z * gR[3] - x * gR[5] - y * gR[6] + x * gR[7]);
+            gqh[1] = 2.f * (y * gR[1] + z * gR[2] + y * gR[3] - w * gR[5] + z * gR[6] + w * gR[7]) -
+                     4.f * x * (gR[4] + gR[8]);
+            gqh[2] = 2.f * (x * gR[1] + w * gR[2] + x * gR[3] + z * gR[5] - w * gR[6] + z * gR[7]) -
+                     4.f * y * (gR[0] + gR[8]);
+            gqh[3] = 2.f * (-w * gR[1] + x * gR[2] + w * gR[3] + y * gR[5] + x * gR[6] + y * gR[7]) -
+                     4.f * z * (gR[0] + gR[4]);
+            const float qd = gqh[0] * q[0] + gqh[1] * q[1] + gqh[2] * q[2] + gqh[3] * q[3];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) gq[k] += (gqh[k] - q[k] * qd) / qn;
+        }
+        // per-block partial of this view's pose gradient (all threads take part)
+        float *dst = pose_part + ((size_t)v * pose_blocks + blockIdx.x) * 12;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const float s = block_sum_256(gW[k], red);
+            if (threadIdx.x == 0) dst[(k / 3) * 4 + (k % 3)] = s;
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float s = block_sum_256(gt[k], red);
+            if (threadIdx.x == 0) dst[k * 4 + 3] = s;
+        }
+    }
+    if (i >= n) return;
+    gr.means[3 * i] = gmu[0];
+    gr.means[3 * i + 1] = gmu[1];
+    gr.means[3 * i + 2] = gmu[2];
+    gr.log_scales[3 * i] = gls[0];
+    gr.log_scales[3 * i + 1] = gls[1];
+    gr.log_scales[3 * i + 2] = gls[2];
+    reinterpret_cast<float4 *>(gr.quats)[i] = make_float4(gq[0], gq[1], gq[2], gq[3]);
+    gr.opacities[i] = gop;
+    float *gs = gr.sh + (size_t)i * K * 3;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        gs[3 * k] = gsh[k][0];
+        gs[3 * k + 1] = gsh[k][1];
+        gs[3 * k + 2] = gsh[k][2];
+    }
+}
+
+void launch_project_bwd(const gsr_gaussians &g, const ViewTable &vt, const float *w2c, uint64_t n, const Rec *rec,
+                        const uint32_t *count, const WsHeader *hdr, const float *partial, const gsr_gaussian_grads &gr, float *pose_part,
+                        uint32_t pose_blocks, hipStream_t st) {
+    if (n == 0) return;
+    const dim3 grid(pose_blocks);
+    switch (g.sh_degree) {
+        case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, partial, gr, pose_part, pose_blocks); break;
+        case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, partial, gr, pose_part, pose_blocks); break;
+        case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, partial, gr, pose_part, pose_blocks); break;
+        default: hipLaunchKernelGGL(k_project_bwd<3>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, partial, gr, pose_part, pose_blocks); break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pose gradient: one workgroup per view sums the per-block partials in a fixed
+// order, writes the 4x4 gradient (last row zero) and the left-perturbation
+// twist: M = G T^T, d/drho = M[0:3, 3], d/dphi = (M21 - M12, M02 - M20, M10 - M01).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_pose_finalize(const float *__restrict__ w2c,
+                                                       const float *__restrict__ pose_part, uint32_t pose_blocks,
+                                                       float *__restrict__ dL_dw2c, float *__restrict__ dL_dtwist) {
+    __shared__ float red[4];
+    __shared__ float G[16];
+    const int v = blockIdx.x;
+    for (int k = 0; k < 12; ++k) {
+        float acc = 0.f;
+        for (uint32_t b = threadIdx.x; b < pose_blocks; b += 256) acc += pose_part[((size_t)v * pose_blocks + b) * 12 + k];
+        const float s = block_sum_256(acc, red);
+        if (threadIdx.x == 0) G[k] = s;
+    }
+    if (threadIdx.x == 0) G[12] = G[13] = G[14] = G[15] = 0.f;
+    __syncthreads();
+    if (threadIdx.x < 16 && dL_dw2c) dL_dw2c[16 * v + threadIdx.x] = G[threadIdx.x];
+    if (threadIdx.x == 0 && dL_dtwist) {
+        const float *T = w2c + 16 * v;
+        float M[16];
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b)
+                M[4 * a + b] = G[4 * a] * T[4 * b] + G[4 * a + 1] * T[4 * b + 1] + G[4 * a + 2] * T[4 * b + 2] +
+                               G[4 * a + 3] * T[4 * b + 3];
+        float *o = dL_dtwist + 6 * v;
+        o[0] = M[3];
+        o[1] = M[7];
+        o[2] = M[11];
+        o[3] = M[9] - M[6];
+        o[4] = M[2] - M[8];
+        o[5] = M[4] - M[1];
+    }
+}
+
+void launch_pose_finalize(const ViewTable &vt, const float *w2c, const float *pose_part, uint32_t pose_blocks,
+                          float *dL_dw2c, float *dL_dtwist, hipStream_t st) {
+    if (!dL_dw2c && !dL_dtwist) return;
+    hipLaunchKernelGGL(k_pose_finalize, dim3(vt.n_views), dim3(256), 0, st, w2c, pose_part, pose_blocks, dL_dw2c,
+                       dL_dtwist);
+}
+
+}  // namespace gsr

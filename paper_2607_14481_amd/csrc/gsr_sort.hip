@@ -1,0 +1,406 @@
+// gsr_sort.hip -- binning stages of the rasterizer on gfx950:
+//   A2 scans: visible-item compaction and per-item pair offsets (exclusive
+//      scans in u32 with saturating adds, reduce-then-scan, no spin waits)
+//   A4 radix sort: stable LSD passes of 8 bits over (key u32, value u32)
+//   A3 emission: (tile, item) pairs, written in depth order
+//   A5 tile ranges: [start, end) of each tile in the sorted pairs
+//
+// Order of work.  The pairs must end up sorted by (tile, depth bits, item).
+// Rather than sorting 48-bit (tile, depth) keys over all M pairs (six 8-bit
+// passes over 12-byte records), the items are first sorted by depth (four
+// passes over the visible items only, M/N ~ 5-15 times fewer elements), the
+// pairs are emitted in that order, and a stable sort on the tile id alone
+// (ceil(tile_bits / 8) passes, two at 1080p) finishes the job.  Stability of
+// every pass gives the (tile, depth, item) order exactly.
+//
+// Every kernel reads its element count from the workspace header, so the
+// launch grid can be sized for a capacity and the call needs no host
+// synchronisation (graph capture).
+#include "gsr_internal.h"
+
+namespace gsr {
+
+__device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) {
+    const uint32_t s = a + b;
+    return s < a ? 0xffffffffu : s;
+}
+
+// Block-wide exclusive scan of one value per thread (256 threads), saturating.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t *lds /* [4] */, uint32_t &total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t inc = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc = sat_add(inc, y);
+    }
+    if (lane == 63) lds[w] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int k = 0; k < w; ++k) before = sat_add(before, lds[k]);
+    total = sat_add(sat_add(lds[0], lds[1]), sat_add(lds[2], lds[3]));
+    __syncthreads();
+    return sat_add(before, inc - x);
+}
+
+// ---------------------------------------------------------------------------
+// Generic reduce-then-scan.  Phase 1: per-block sums of a per-element value.
+// Phase 2: one block scans the block sums.  Phase 3: per-block scan + offset,
+// handing each element its exclusive prefix to an epilogue.
+// ---------------------------------------------------------------------------
+struct VisibleFlag {  // value = item visible (tiles touched > 0)
+    const uint32_t *count;
+    __device__ uint32_t operator()(uint64_t i) const { return count[i] > 0u ? 1u : 0u; }
+};
+struct CountInDepthOrder {  // value = tiles touched by the i-th item in depth order
+    const uint32_t *items;
+    const uint32_t *count;
+    __device__ uint32_t operator()(uint64_t i) const { return count[items[i]]; }
+};
+
+template <class F>
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(F f, const uint32_t *__restrict__ n_dev, uint64_t n_host,
+                                                              uint32_t *__restrict__ block_sums) {
+    __shared__ uint32_t lds[4];
+    const uint64_t n = n_dev ? (uint64_t)*n_dev : n_host;
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    uint32_t acc = 0;
+    if (base < n) {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            const uint64_t i = base + (uint64_t)threadIdx.x * kScanItems + k;
+            if (i < n) acc = sat_add(acc, f(i));
+        }
+    }
+    uint32_t total;
+    block_exclusive_scan(acc, lds, total);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+// Single workgroup: exclusive scan of nb block sums in place; total -> *out_total.
+__global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t *__restrict__ block_sums, uint32_t nb,
+                                                      uint32_t *__restrict__ out_total) {
+    __shared__ uint32_t lds[16];
+    __shared__ uint32_t carry;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (uint32_t base = 0; base < nb; base += 1024) {
+        const uint32_t i = base + threadIdx.x;
+        const uint32_t x = i < nb ? block_sums[i] : 0u;
+        uint32_t inc = x;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(inc, o, 64);
+            if (lane >= o) inc = sat_add(inc, y);
+        }
+        if (lane == 63) lds[w] = inc;
+        __syncthreads();
+        uint32_t before = carry;
+        for (int k = 0; k < w; ++k) before = sat_add(before, lds[k]);
+        if (i < nb) block_sums[i] = sat_add(before, inc - x);
+        __syncthreads();
+        if (threadIdx.x == 1023) carry = sat_add(before, inc);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out_total = carry;
+}
+
+// Phase 3 for the compaction: visible items get their depth key and id written
+// at their exclusive prefix.
+__global__ __launch_bounds__(kScanThreads) void k_compact_apply(const uint32_t *__restrict__ count,
+                                                                const uint32_t *__restrict__ zkey, uint64_t n,
+                                                                const uint32_t *__restrict__ block_sums,
+                                                                uint32_t *__restrict__ ckey,
+                                                                uint32_t *__restrict__ cval) {
+    __shared__ uint32_t lds[4];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+    uint32_t flags = 0, cnt = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const uint64_t i = base + k;
+        const bool vis = i < n && count[i] > 0u;
+        flags |= (vis ? 1u : 0u) << k;
+        cnt += vis;
+    }
+    uint32_t total;
+    uint32_t pos = block_sums[blockIdx.x] + block_exclusive_scan(cnt, lds, total);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (flags & (1u << k)) {
+            ckey[pos] = zkey[base + k];
+            cval[pos] = (uint32_t)(base + k);
+            ++pos;
+        }
+    }
+}
+
+void launch_compact_visible(const uint32_t *count, const uint32_t *zkey, uint64_t items, uint32_t *ckey,
+                            uint32_t *cval, uint32_t *block_tmp, WsHeader *hdr, hipStream_t st) {
+    const uint32_t nb = (uint32_t)((items + kScanTile - 1) / kScanTile);
+    if (nb == 0) return;
+    hipLaunchKernelGGL(k_scan_reduce<VisibleFlag>, dim3(nb), dim3(kScanThreads), 0, st, VisibleFlag{count},
+                       (const uint32_t *)nullptr, items, block_tmp);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, block_tmp, nb, &hdr->n_visible);
+    hipLaunchKernelGGL(k_compact_apply, dim3(nb), dim3(kScanThreads), 0, st, count, zkey, items, block_tmp, ckey,
+                       cval);
+}
+
+// Phase 3 for the pair offsets: poff[i] = exclusive prefix of counts in depth
+// order; the total lands in the header (n_pairs) together with the overflow
+// decision.
+__global__ __launch_bounds__(kScanThreads) void k_offsets_apply(CountInDepthOrder f,
+                                                                const uint32_t *__restrict__ block_sums,
+                                                                uint32_t *__restrict__ poff, WsHeader *hdr) {
+    __shared__ uint32_t lds[4];
+    const uint64_t n = hdr->n_visible;
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+    if ((uint64_t)blockIdx.x * kScanTile >= n) return;  // uniform per block
+    uint32_t c[kScanItems];
+    uint32_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        c[k] = base + k < n ? f(base + k) : 0u;
+        acc = sat_add(acc, c[k]);
+    }
+    uint32_t total;
+    uint32_t run = sat_add(block_sums[blockIdx.x], block_exclusive_scan(acc, lds, total));
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n) poff[base + k] = run;
+        run = sat_add(run, c[k]);
+    }
+}
+
+__global__ void k_pairs_finish(WsHeader *hdr) {
+    const uint32_t m = hdr->n_pairs;
+    hdr->overflow = m > hdr->pair_capacity ? 1u : 0u;
+}
+
+void launch_pair_offsets(const uint32_t *sorted_items, const uint32_t *count, uint64_t items_cap, uint32_t *poff,
+                         uint32_t *block_tmp, WsHeader *hdr, hipStream_t st) {
+    const uint32_t nb = (uint32_t)((items_cap + kScanTile - 1) / kScanTile);
+    if (nb == 0) return;
+    CountInDepthOrder f{sorted_items, count};
+    hipLaunchKernelGGL(k_scan_reduce<CountInDepthOrder>, dim3(nb), dim3(kScanThreads), 0, st, f, &hdr->n_visible,
+                       items_cap, block_tmp);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, block_tmp, nb, &hdr->n_pairs);
+    hipLaunchKernelGGL(k_offsets_apply, dim3(nb), dim3(kScanThreads), 0, st, f, block_tmp, poff, hdr);
+    hipLaunchKernelGGL(k_pairs_finish, dim3(1), dim3(1), 0, st, hdr);
+}
+
+// ---------------------------------------------------------------------------
+// A4: LSD radix sort, one 8-bit digit per pass.
+//   k_radix_hist    per-block digit histogram -> hist[digit][block]
+//   k_radix_scan    per digit: exclusive scan over blocks (in place) + total
+//   k_radix_scatter stable rank within the block (wave ballots), scatter
+// The element count is read on the device: either *n_dev or, for the pair
+// sort, 0 when the header flags an overflow.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *__restrict__ keys, SortCount sc,
+                                                             int shift, uint32_t *__restrict__ hist,
+                                                             uint32_t hist_blocks) {
+    __shared__ uint32_t h[256];
+    const uint64_t n = sc();
+    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+    if (base >= n) return;  // blocks past the end are never scanned
+    h[threadIdx.x] = 0;
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < kSortItems; ++k) {
+        const uint64_t i = base + (uint64_t)k * kSortThreads + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(size_t)threadIdx.x * hist_blocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// One workgroup per digit: exclusive scan of hist[d][0..nb) in place.
+__global__ __launch_bounds__(256) void k_radix_scan(uint32_t *__restrict__ hist, uint32_t hist_blocks, SortCount sc,
+                                                    uint32_t *__restrict__ digit_total) {
+    __shared__ uint32_t lds[4];
+    __shared__ uint32_t carry;
+    const uint64_t n = sc();
+    const uint32_t nb = (uint32_t)((n + kSortTile - 1) / kSortTile);
+    uint32_t *row = hist + (size_t)blockIdx.x * hist_blocks;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (uint32_t b0 = 0; b0 < nb; b0 += 256) {
+        const uint32_t b = b0 + threadIdx.x;
+        const uint32_t x = b < nb ? row[b] : 0u;
+        uint32_t total;
+        const uint32_t ex = block_exclusive_scan(x, lds, total);
+        if (b < nb) row[b] = carry + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *__restrict__ kin,
+                                                                const uint32_t *__restrict__ vin,
+                                                                uint32_t *__restrict__ kout,
+                                                                uint32_t *__restrict__ vout, SortCount sc, int shift,
+                                                                const uint32_t *__restrict__ hist,
+                                                                uint32_t hist_blocks,
+                                                                const uint32_t *__restrict__ digit_total) {
+    __shared__ uint32_t base_off[256];   // global offset of each digit for this block
+    __shared__ uint32_t wave_cnt[4][256];
+    __shared__ uint32_t lds[4];
+    const uint64_t n = sc();
+    const uint64_t blk = (uint64_t)blockIdx.x * kSortTile;
+    if (blk >= n) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    {
+        // digit base = exclusive scan of digit totals + this block's prefix
+        uint32_t total;
+        const uint32_t ex = block_exclusive_scan(digit_total[threadIdx.x], lds, total);
+        base_off[threadIdx.x] = ex + hist[(size_t)threadIdx.x * hist_blocks + blockIdx.x];
+    }
+    for (int k = 0; k < 4; ++k) wave_cnt[k][threadIdx.x] = 0;
+    __syncthreads();
+    const unsigned long long lt_mask = (1ull << lane) - 1ull;
+    for (int r = 0; r < kSortItems; ++r) {
+        const uint64_t i = blk + (uint64_t)r * kSortThreads + threadIdx.x;
+        const bool ok = i < n;
+        uint32_t key = 0, val = 0, d = 0;
+        if (ok) {
+            key = kin[i];
+            val = vin[i];
+            d = (key >> shift) & 255u;
+        }
+        // lanes of this wave holding the same digit
+        unsigned long long match = __ballot(ok);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const unsigned long long bal = __ballot(ok && ((d >> b) & 1u));
+            match &= ((d >> b) & 1u) ? bal : ~bal;
+        }
+        const uint32_t rank = __popcll(match & lt_mask);
+        const uint32_t cnt = __popcll(match);
+        const bool leader = ok && (rank == cnt - 1);  // highest lane of its group
+        if (leader) wave_cnt[w][d] = cnt;
+        __syncthreads();
+        if (ok) {
+            uint32_t pos = base_off[d] + rank;
+            for (int k = 0; k < w; ++k) pos += wave_cnt[k][d];
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        // advance digit bases by this round's counts, clear the wave counts
+        {
+            const uint32_t t = threadIdx.x;
+            base_off[t] += wave_cnt[0][t] + wave_cnt[1][t] + wave_cnt[2][t] + wave_cnt[3][t];
+            wave_cnt[0][t] = wave_cnt[1][t] = wave_cnt[2][t] = wave_cnt[3][t] = 0;
+        }
+        __syncthreads();
+        if (blk + (uint64_t)(r + 1) * kSortThreads >= n) break;  // uniform
+    }
+}
+
+void radix_sort_u32(uint32_t *keys[2], uint32_t *vals[2], SortCount sc, uint64_t n_cap, int begin_bit, int end_bit,
+                    uint32_t *hist, uint32_t hist_blocks, uint32_t *digit_total, int &cur, hipStream_t st) {
+    const uint32_t nb = (uint32_t)((n_cap + kSortTile - 1) / kSortTile);
+    for (int shift = begin_bit; shift < end_bit; shift += 8) {
+        // the result buffer depends only on the number of passes, not on n
+        if (nb == 0) {
+            cur ^= 1;
+            continue;
+        }
+        hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kSortThreads), 0, st, keys[cur], sc, shift, hist,
+                           hist_blocks);
+        hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(256), 0, st, hist, hist_blocks, sc, digit_total);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kSortThreads), 0, st, keys[cur], vals[cur],
+                           keys[cur ^ 1], vals[cur ^ 1], sc, shift, hist, hist_blocks, digit_total);
+        cur ^= 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// A3: emission.  The i-th item in depth order writes its pairs at poff[i], in
+// row-major order over its tile box, and records the offset in its record.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_emit(ViewTable vt, const uint32_t *__restrict__ sorted_items,
+                                              const uint32_t *__restrict__ poff, uint64_t n, Rec *__restrict__ rec,
+                                              uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval,
+                                              const WsHeader *__restrict__ hdr) {
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= hdr->n_visible || hdr->overflow) return;
+    const uint32_t item = sorted_items[i];
+    const uint32_t off = poff[i];
+    const int v = (int)(item / n);
+    const ViewInfo &cam = vt.v[v];
+    const float4 r2 = rec[item].r2;
+    rec[item].r2.w = __uint_as_float(off);
+    const uint32_t bx = __float_as_uint(r2.y), by = __float_as_uint(r2.z);
+    const uint32_t tx0 = (bx & 0xffffu) / kTileW, tx1 = (bx >> 16) / kTileW;
+    const uint32_t ty0 = (by & 0xffffu) / vt.tile_h, ty1 = (by >> 16) / vt.tile_h;
+    uint32_t o = off;
+    for (uint32_t ty = ty0; ty <= ty1; ++ty)
+        for (uint32_t tx = tx0; tx <= tx1; ++tx) {
+            pkey[o] = cam.tile_off + ty * cam.tiles_x + tx;
+            pval[o] = item;
+            ++o;
+        }
+}
+
+void launch_emit_pairs(const ViewTable &vt, const uint32_t *sorted_items, const uint32_t *poff, uint64_t n,
+                       uint64_t items_cap, Rec *rec, uint32_t *pkey, uint32_t *pval, const WsHeader *hdr,
+                       hipStream_t st) {
+    if (items_cap == 0) return;
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)((items_cap + 255) / 256)), dim3(256), 0, st, vt, sorted_items, poff, n,
+                       rec, pkey, pval, hdr);
+}
+
+// ---------------------------------------------------------------------------
+// A5: per-tile [start, end) over the sorted pairs (ranges pre-cleared).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t *__restrict__ pkey, uint2 *__restrict__ ranges,
+                                                     const WsHeader *__restrict__ hdr) {
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    const uint64_t m = hdr->overflow ? 0ull : (uint64_t)hdr->n_pairs;
+    if (i >= m) return;
+    const uint32_t t = pkey[i];
+    if (i == 0 || pkey[i - 1] != t) ranges[t].x = (uint32_t)i;
+    if (i == m - 1 || pkey[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
+}
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *__restrict__ p, uint32_t value, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) p[i] = value;
+}
+
+void launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t st) {
+    if (n == 0) return;
+    uint64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, value, n);
+}
+
+__global__ void k_reset_header(WsHeader *h, uint32_t cap) {
+    const uint32_t t = threadIdx.x;
+    uint32_t *w = reinterpret_cast<uint32_t *>(h);
+    if (t < sizeof(WsHeader) / 4) w[t] = 0u;
+    __syncthreads();
+    if (t == 0) h->pair_capacity = cap;
+}
+
+void launch_reset_header(WsHeader *h, uint32_t cap, hipStream_t st) {
+    hipLaunchKernelGGL(k_reset_header, dim3(1), dim3(64), 0, st, h, cap);
+}
+
+__global__ void k_reset_queue(WsHeader *h, int which) { h->queue[which] = 0u; }
+
+void launch_reset_queue(WsHeader *h, int which, hipStream_t st) {
+    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(1), 0, st, h, which);
+}
+
+void launch_tile_ranges(const uint32_t *pkey, uint64_t cap, uint2 *ranges, uint32_t total_tiles, const WsHeader *hdr,
+                        hipStream_t st) {
+    launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, 2ull * total_tiles, st);
+    if (cap == 0) return;
+    hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, st, pkey, ranges, hdr);
+}
+
+}  // namespace gsr

@@ -1,0 +1,265 @@
+"""ctypes binding of the C ABI in include/gsr.h (argument marshalling only).
+
+Every step of the rasterizer runs in the HIP library; this module only turns
+torch tensors into pointers and status codes into exceptions.  Loading fails
+loudly when the library has not been built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgsr.so")
+
+GSR_OK = 0
+GSR_ERR_INVALID_ARGUMENT = 1
+GSR_ERR_WORKSPACE_TOO_SMALL = 2
+GSR_ERR_CAPACITY = 3
+GSR_ERR_HIP = 4
+GSR_ERR_UNSUPPORTED = 5
+GSR_MAX_VIEWS = 32
+GSR_FLAG_SYNC = 1
+GSR_FLAG_PERSISTENT = 2
+
+EXPORTED = ("gsr_version", "gsr_status_string", "gsr_last_error", "gsr_workspace_bytes",
+            "gsr_rasterize_forward", "gsr_rasterize_backward", "gsr_query_pairs", "gsr_query_stats",
+            "gsr_export_state")
+
+
+class GsrError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{status_string(status)}: {message}")
+        self.status = status
+
+
+class CapacityError(GsrError):
+    pass
+
+
+class gsr_camera(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("near_plane", C.c_float)]
+
+
+class gsr_gaussians(C.Structure):
+    _fields_ = [("n", C.c_int64), ("sh_degree", C.c_int32), ("means", C.c_void_p), ("log_scales", C.c_void_p),
+                ("quats", C.c_void_p), ("opacities", C.c_void_p), ("sh", C.c_void_p)]
+
+
+class gsr_gaussian_grads(C.Structure):
+    _fields_ = [("means", C.c_void_p), ("log_scales", C.c_void_p), ("quats", C.c_void_p),
+                ("opacities", C.c_void_p), ("sh", C.c_void_p)]
+
+
+class gsr_launch_config(C.Structure):
+    _fields_ = [("tile_h", C.c_int32), ("persistent_ctas", C.c_int32), ("stage_events", C.c_void_p),
+                ("reserved", C.c_int32 * 4)]
+
+
+class gsr_stats(C.Structure):
+    _fields_ = [("visible", C.c_int64), ("pairs", C.c_int64), ("evaluations", C.c_int64),
+                ("contributors", C.c_int64), ("replays", C.c_int64)]
+
+
+STAGES = ("project", "depth_sort", "emit", "tile_sort", "composite_fwd", "composite_bwd", "project_bwd")
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it was not built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP rasterizer library not built: {LIB_PATH} is missing "
+                               "(run `python -m paper_2607_14481_amd.build`)")
+        L = C.CDLL(LIB_PATH)
+        vp, sz = C.c_void_p, C.c_size_t
+        L.gsr_version.restype = C.c_int
+        L.gsr_status_string.restype = C.c_char_p
+        L.gsr_status_string.argtypes = [C.c_int]
+        L.gsr_last_error.restype = C.c_char_p
+        L.gsr_workspace_bytes.restype = sz
+        L.gsr_workspace_bytes.argtypes = [C.c_int64, C.c_int32, C.POINTER(gsr_camera), C.c_int64,
+                                          C.POINTER(gsr_launch_config)]
+        L.gsr_rasterize_forward.restype = C.c_int
+        L.gsr_rasterize_forward.argtypes = [vp, sz, C.POINTER(gsr_gaussians), C.c_int32, C.POINTER(gsr_camera),
+                                            vp, C.POINTER(C.c_float), C.POINTER(gsr_launch_config), vp, vp,
+                                            C.c_uint32, vp]
+        L.gsr_rasterize_backward.restype = C.c_int
+        L.gsr_rasterize_backward.argtypes = [vp, sz, C.POINTER(gsr_gaussians), C.c_int32, C.POINTER(gsr_camera),
+                                             vp, C.POINTER(C.c_float), C.POINTER(gsr_launch_config), vp, vp,
+                                             C.POINTER(gsr_gaussian_grads), vp, vp, C.c_uint32, vp]
+        L.gsr_query_pairs.restype = C.c_int
+        L.gsr_query_pairs.argtypes = [vp, sz, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32), vp]
+        L.gsr_query_stats.restype = C.c_int
+        L.gsr_query_stats.argtypes = [vp, sz, C.POINTER(gsr_stats), vp]
+        L.gsr_export_state.restype = C.c_int
+        L.gsr_export_state.argtypes = [vp, sz, C.POINTER(gsr_gaussians), C.c_int32, C.POINTER(gsr_camera),
+                                       C.POINTER(gsr_launch_config), vp, vp, vp, vp, vp, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def version() -> int:
+    return lib().gsr_version()
+
+
+def status_string(status: int) -> str:
+    return lib().gsr_status_string(status).decode()
+
+
+def last_error() -> str:
+    return lib().gsr_last_error().decode()
+
+
+def _check(status: int):
+    if status != GSR_OK:
+        cls = CapacityError if status == GSR_ERR_CAPACITY else GsrError
+        raise cls(status, last_error())
+
+
+# ----------------------------------------------------------------------------
+# marshalling helpers
+# ----------------------------------------------------------------------------
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream) -> C.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def cameras(cams: Sequence) -> "C.Array[gsr_camera]":
+    """Host array of gsr_camera from objects with width/height/fx/fy/cx/cy/near."""
+    arr = (gsr_camera * len(cams))()
+    for i, c in enumerate(cams):
+        arr[i].width, arr[i].height = int(c.width), int(c.height)
+        arr[i].fx, arr[i].fy, arr[i].cx, arr[i].cy = float(c.fx), float(c.fy), float(c.cx), float(c.cy)
+        arr[i].near_plane = float(getattr(c, "near", 0.2))
+    return arr
+
+
+def launch_config(tile_h: int = 16, persistent_ctas: int = 0) -> gsr_launch_config:
+    cfg = gsr_launch_config()
+    cfg.tile_h = int(tile_h)
+    cfg.persistent_ctas = int(persistent_ctas)
+    return cfg
+
+
+def _as_param(t: torch.Tensor, name: str) -> torch.Tensor:
+    if t.dtype != torch.float32 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float32 GPU tensor")
+    return t.contiguous()
+
+
+def gaussians_struct(means, log_scales, quats, opacities, sh, sh_degree: int) -> gsr_gaussians:
+    g = gsr_gaussians()
+    g.n = int(means.shape[0])
+    g.sh_degree = int(sh_degree)
+    g.means, g.log_scales, g.quats = _ptr(means), _ptr(log_scales), _ptr(quats)
+    g.opacities, g.sh = _ptr(opacities), _ptr(sh)
+    return g
+
+
+# ----------------------------------------------------------------------------
+# entry points (same names as the C ABI, minus the prefix)
+# ----------------------------------------------------------------------------
+
+def workspace_bytes(n: int, cams: Sequence, pair_capacity: int, cfg: Optional[gsr_launch_config] = None) -> int:
+    arr = cameras(cams)
+    nb = lib().gsr_workspace_bytes(int(n), len(cams), arr, int(pair_capacity),
+                                   C.byref(cfg) if cfg is not None else None)
+    if nb == 0:
+        raise GsrError(GSR_ERR_INVALID_ARGUMENT, last_error())
+    return int(nb)
+
+
+def rasterize_forward(ws: torch.Tensor, params: Sequence[torch.Tensor], sh_degree: int, cams: Sequence,
+                      world_to_cam: torch.Tensor, bg: Sequence[float], out_rgb: torch.Tensor,
+                      out_T: Optional[torch.Tensor] = None, flags: int = 0,
+                      cfg: Optional[gsr_launch_config] = None, stream=None):
+    g = gaussians_struct(*params, sh_degree)
+    arr = cameras(cams)
+    bgc = (C.c_float * 3)(*[float(x) for x in bg])
+    _check(lib().gsr_rasterize_forward(_ptr(ws), ws.numel(), C.byref(g), len(cams), arr, _ptr(world_to_cam), bgc,
+                                       C.byref(cfg) if cfg is not None else None, _ptr(out_rgb), _ptr(out_T),
+                                       int(flags), _stream_ptr(stream)))
+
+
+def rasterize_backward(ws: torch.Tensor, params: Sequence[torch.Tensor], sh_degree: int, cams: Sequence,
+                       world_to_cam: torch.Tensor, bg: Sequence[float], out_rgb: torch.Tensor,
+                       dL_drgb: torch.Tensor, grads: Sequence[torch.Tensor],
+                       dL_dworld_to_cam: Optional[torch.Tensor] = None, dL_dtwist: Optional[torch.Tensor] = None,
+                       flags: int = 0, cfg: Optional[gsr_launch_config] = None, stream=None):
+    g = gaussians_struct(*params, sh_degree)
+    gr = gsr_gaussian_grads()
+    gr.means, gr.log_scales, gr.quats, gr.opacities, gr.sh = [_ptr(t) for t in grads]
+    arr = cameras(cams)
+    bgc = (C.c_float * 3)(*[float(x) for x in bg])
+    _check(lib().gsr_rasterize_backward(_ptr(ws), ws.numel(), C.byref(g), len(cams), arr, _ptr(world_to_cam), bgc,
+                                        C.byref(cfg) if cfg is not None else None, _ptr(out_rgb), _ptr(dL_drgb),
+                                        C.byref(gr), _ptr(dL_dworld_to_cam), _ptr(dL_dtwist), int(flags),
+                                        _stream_ptr(stream)))
+
+
+def query_pairs(ws: torch.Tensor, stream=None):
+    needed, cap, ovf = C.c_int64(), C.c_int64(), C.c_int32()
+    _check(lib().gsr_query_pairs(_ptr(ws), ws.numel(), C.byref(needed), C.byref(cap), C.byref(ovf),
+                                 _stream_ptr(stream)))
+    return int(needed.value), int(cap.value), bool(ovf.value)
+
+
+def query_stats(ws: torch.Tensor, stream=None) -> dict:
+    st = gsr_stats()
+    _check(lib().gsr_query_stats(_ptr(ws), ws.numel(), C.byref(st), _stream_ptr(stream)))
+    return {k: int(getattr(st, k)) for k, _ in gsr_stats._fields_}
+
+
+def export_state(ws: torch.Tensor, params: Sequence[torch.Tensor], sh_degree: int, cams: Sequence,
+                 cfg: Optional[gsr_launch_config] = None, stream=None) -> dict:
+    """Copies of the last forward's sorted pairs, ranges and per-item records."""
+    needed, cap, ovf = query_pairs(ws, stream)
+    m = 0 if ovf else min(needed, cap)
+    n = int(params[0].shape[0])
+    items = n * len(cams)
+    dev = ws.device
+    cfg_ = cfg if cfg is not None else launch_config()
+    th = cfg_.tile_h or 16
+    tiles = sum(((int(c.width) + 15) // 16) * ((int(c.height) + th - 1) // th) for c in cams)
+    out = dict(
+        pair_tiles=torch.zeros(max(m, 1), dtype=torch.int32, device=dev),
+        pair_items=torch.zeros(max(m, 1), dtype=torch.int32, device=dev),
+        ranges=torch.zeros((tiles, 2), dtype=torch.int32, device=dev),
+        records=torch.zeros((max(items, 1), 12), dtype=torch.float32, device=dev),
+        centre_lo=torch.zeros((max(items, 1), 2), dtype=torch.float32, device=dev),
+        depth_keys=torch.zeros(max(items, 1), dtype=torch.int32, device=dev),
+        tile_counts=torch.zeros(max(items, 1), dtype=torch.int32, device=dev),
+    )
+    g = gaussians_struct(*params, sh_degree)
+    arr = cameras(cams)
+    _check(lib().gsr_export_state(_ptr(ws), ws.numel(), C.byref(g), len(cams), arr, C.byref(cfg_),
+                                  _ptr(out["pair_tiles"]), _ptr(out["pair_items"]), _ptr(out["ranges"]),
+                                  _ptr(out["records"]), _ptr(out["centre_lo"]), _ptr(out["depth_keys"]),
+                                  _ptr(out["tile_counts"]), _stream_ptr(stream)))
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    res = {k: v.cpu().numpy() for k, v in out.items()}
+    res["pair_tiles"] = res["pair_tiles"][:m].view("uint32")
+    res["pair_items"] = res["pair_items"][:m].view("uint32")
+    res["ranges"] = res["ranges"].view("uint32")
+    res["depth_keys"] = res["depth_keys"][:items].view("uint32")
+    res["tile_counts"] = res["tile_counts"][:items].view("uint32")
+    res["records"] = res["records"][:items]
+    res["centre_lo"] = res["centre_lo"][:items]
+    res["M"] = m
+    return res

@@ -223,11 +223,28 @@ def multi_view_ring(seed=3, n=1_000_000, n_views=8, radius=15.0) -> Workload:
     return Workload("multi_view_ring", scene, cams, meta={"seed": seed, "res_idx": res.tolist()})
 
 
+def perturbed_pose(world_to_cam, seed, degrees=0.5, metres=0.02) -> np.ndarray:
+    """Left-multiplies a pose by a rotation of `degrees` about a random axis and
+    a translation of `metres` in a random direction (seeded)."""
+    rng = _rng(seed)
+    axis = rng.standard_normal(3)
+    tdir = rng.standard_normal(3)
+    tdir /= np.linalg.norm(tdir)
+    delta = np.eye(4)
+    delta[:3, :3] = axis_angle_matrix(axis, np.deg2rad(degrees))
+    delta[:3, 3] = metres * tdir
+    return (delta @ np.asarray(world_to_cam, np.float64)).astype(np.float32)
+
+
 def headline_view(seed=3, n=1_000_000) -> Workload:
-    """The first 1920x1080 camera of the 8-view ring over the 1M-Gaussian scene."""
+    """The first 1920x1080 camera of the 8-view ring over the 1M-Gaussian scene;
+    the optimisation target is rendered from that pose perturbed by 0.5 degrees
+    and 2 cm (as for the single-view 1080p workload)."""
     wl = multi_view_ring(seed=seed, n=n)
     idx = next(i for i, c in enumerate(wl.cameras) if c.width == 1920)
-    return Workload("headline_1080p_1M", wl.scene, [wl.cameras[idx]],
+    cam = wl.cameras[idx]
+    target = cam.copy_with_pose(perturbed_pose(cam.world_to_cam, seed + 1000))
+    return Workload("headline_1080p_1M", wl.scene, [cam], target_cameras=[target],
                     meta={"seed": seed, "ring_index": idx})
 
 
