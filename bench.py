@@ -72,6 +72,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--tile-h", type=int, default=16)
+    ap.add_argument("--persistent", action="store_true", help="compositing as persistent work-queue launches")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the rasterizer's multi-GPU sharding (one view per GPU, one "
@@ -95,7 +96,7 @@ def main():
               for k in ("means", "log_scales", "quats", "opacities", "sh")]
     w2c = torch.tensor(np.asarray(cams[0].world_to_cam, np.float32)[None], device=dev)
     bg = (0.0, 0.0, 0.0)
-    rast = GaussianRasterizer(cams, sc.sh_degree, tile_h=args.tile_h, device=dev)
+    rast = GaussianRasterizer(cams, sc.sh_degree, tile_h=args.tile_h, persistent=args.persistent, device=dev)
 
     # target image (untimed)
     if wl.target_cameras is not None:
@@ -149,7 +150,8 @@ def main():
     graph_err = None
     if not args.no_graph:
         try:
-            grast = GaussianRasterizer(cams, sc.sh_degree, tile_h=args.tile_h, sync=False, device=dev)
+            grast = GaussianRasterizer(cams, sc.sh_degree, tile_h=args.tile_h, persistent=args.persistent, sync=False,
+                                       device=dev)
             grast.capacity = int(stats["pairs"] * 1.3) + 4096
             gws = grast.workspace(sc.n)
             gout = torch.empty_like(target)
@@ -223,7 +225,7 @@ def main():
         "config": {"workload": f"{args.workload}: {desc}", "n_gaussians": sc.n,
                    "resolution": f"{cams[0].width}x{cams[0].height}", "sh_degree": sc.sh_degree,
                    "form": "plain: one view per launch sequence, synchronous pair-capacity check",
-                   "tile": f"16x{args.tile_h}"},
+                   "tile": f"16x{args.tile_h}", "persistent": bool(args.persistent)},
         "graph_form": {"iters_per_s": round(1000.0 / graph_ms, 3) if graph_ms else None,
                        "ms_per_step": round(graph_ms, 4) if graph_ms else None, "error": graph_err},
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},

@@ -107,6 +107,9 @@ gsr::WsLayout make_layout(uint64_t n, const gsr::ViewTable &vt, uint64_t cap) {
     L.cval[0] = take(4 * items);
     L.cval[1] = take(4 * items);
     L.poff = take(4 * items);
+    L.rank = take(4 * items);
+    L.big_list = take(4 * items);
+    L.screen = take(48 * items);
     L.pkey[0] = take(4 * cap);
     L.pkey[1] = take(4 * cap);
     L.pval[0] = take(4 * cap);
@@ -114,6 +117,7 @@ gsr::WsLayout make_layout(uint64_t n, const gsr::ViewTable &vt, uint64_t cap) {
     L.hist = take(4ull * 256 * L.hist_blocks);
     L.digit_total = take(4 * 256);
     L.ranges = take(8ull * vt.total_tiles);
+    L.tile_cut = take(8ull * vt.total_tiles);
     L.pix_T = take(4ull * vt.total_pixels);
     L.pix_n = take(4ull * vt.total_pixels);
     L.partial = take(4ull * kPartialStride * cap);
@@ -142,8 +146,10 @@ struct Ptrs {
     gsr::WsHeader *hdr;
     gsr::Rec *rec;
     float2 *ulo;
-    uint32_t *zkey, *count, *scan_tmp, *ckey[2], *cval[2], *poff, *pkey[2], *pval[2], *hist, *digit_total;
-    uint2 *ranges;
+    uint32_t *zkey, *count, *scan_tmp, *ckey[2], *cval[2], *poff, *rank, *big_list, *pkey[2], *pval[2], *hist,
+        *digit_total;
+    float4 *screen;
+    uint2 *ranges, *tile_cut;
     float *pix_T;
     uint32_t *pix_n;
     float *partial, *pose_part;
@@ -165,6 +171,10 @@ Ptrs carve(void *ws, const gsr::WsLayout &L) {
         p.pval[k] = reinterpret_cast<uint32_t *>(b + L.pval[k]);
     }
     p.poff = reinterpret_cast<uint32_t *>(b + L.poff);
+    p.rank = reinterpret_cast<uint32_t *>(b + L.rank);
+    p.big_list = reinterpret_cast<uint32_t *>(b + L.big_list);
+    p.screen = reinterpret_cast<float4 *>(b + L.screen);
+    p.tile_cut = reinterpret_cast<uint2 *>(b + L.tile_cut);
     p.hist = reinterpret_cast<uint32_t *>(b + L.hist);
     p.digit_total = reinterpret_cast<uint32_t *>(b + L.digit_total);
     p.ranges = reinterpret_cast<uint2 *>(b + L.ranges);
@@ -308,7 +318,7 @@ int gsr_rasterize_forward(void *ws, size_t ws_bytes, const gsr_gaussians *g, int
             return fail(GSR_ERR_CAPACITY, "needs %u pairs, workspace holds %llu", h.n_pairs, (unsigned long long)cap);
         pair_grid = h.n_pairs;
     }
-    launch_emit_pairs(vt, sorted_items, p.poff, n, L.items, p.rec, p.pkey[0], p.pval[0], p.hdr, st);
+    launch_emit_pairs(vt, sorted_items, p.poff, n, L.items, p.rec, p.rank, p.pkey[0], p.pval[0], p.hdr, st);
     mark.end(GSR_STAGE_EMIT);
     mark.begin(GSR_STAGE_TILE_SORT);
     int pc = 0;
@@ -321,8 +331,8 @@ int gsr_rasterize_forward(void *ws, size_t ws_bytes, const gsr_gaussians *g, int
     mark.end(GSR_STAGE_TILE_SORT);
     const bool pers = (flags & GSR_FLAG_PERSISTENT) != 0;
     mark.begin(GSR_STAGE_COMPOSITE_FWD);
-    launch_composite_fwd(vt, p.ranges, p.pval[pc], p.rec, p.ulo, bgc, out_rgb, out_T, p.pix_T, p.pix_n, p.hdr, pers,
-                         persistent_ctas(cfg), st);
+    launch_composite_fwd(vt, p.ranges, p.pval[pc], p.rec, p.ulo, p.rank, bgc, out_rgb, out_T, p.pix_T, p.pix_n,
+                         p.tile_cut, p.hdr, pers, persistent_ctas(cfg), st);
     mark.end(GSR_STAGE_COMPOSITE_FWD);
     return check_hip(hipGetLastError(), "forward launch");
 }
@@ -354,11 +364,14 @@ int gsr_rasterize_backward(void *ws, size_t ws_bytes, const gsr_gaussians *g, in
     const StageMark mark{cfg ? static_cast<hipEvent_t *>(cfg->stage_events) : nullptr, st};
     mark.begin(GSR_STAGE_COMPOSITE_BWD);
     launch_reset_queue(p.hdr, 1, st);
-    launch_composite_bwd(vt, p.ranges, p.pval[pc], p.rec, p.ulo, out_rgb, dL_drgb, p.pix_T, p.pix_n, p.partial, p.hdr,
-                         pers, persistent_ctas(cfg), st);
+    launch_composite_bwd(vt, p.ranges, p.pval[pc], p.rec, p.ulo, out_rgb, dL_drgb, p.pix_n, p.tile_cut, p.partial,
+                         p.hdr, pers, persistent_ctas(cfg), st);
     mark.end(GSR_STAGE_COMPOSITE_BWD);
     mark.begin(GSR_STAGE_PROJECT_BWD);
-    launch_project_bwd(*g, vt, world_to_cam, (uint64_t)g->n, p.rec, p.count, p.hdr, p.partial, *grads, p.pose_part,
+    // the depth sort's result buffer: four 8-bit passes end where they started
+    launch_pair_reduce(vt, p.cval[0], p.poff, (uint64_t)g->n, L.items, p.rec, p.tile_cut, p.partial, p.screen,
+                       p.big_list, p.hdr, persistent_ctas(cfg) / 2, st);
+    launch_project_bwd(*g, vt, world_to_cam, (uint64_t)g->n, p.rec, p.count, p.hdr, p.screen, *grads, p.pose_part,
                        L.pose_blocks, st);
     if (g->n == 0)  // no Gaussian wrote a partial: the pose gradient is zero
         launch_fill_u32(reinterpret_cast<uint32_t *>(p.pose_part), 0u, 12ull * vt.n_views * L.pose_blocks, st);

@@ -9,15 +9,25 @@
 // one k) is skipped as a whole when the Gaussian's alpha >= 1/255 box misses
 // it.  Both passes take every decision (box slab skip, sigma < 0, alpha <
 // 1/255, the stop) with the same instructions on the same values, so the
-// backward replays exactly the forward's contributors.
+// backward replays exactly the forward's contributors.  The per-pixel updates
+// are branch-free (selects), so the only branches are wave-uniform.
+//
+// Early stop.  Dense scenes saturate long before the end of a tile's list:
+// the forward records per tile the number of list positions any of its
+// pixels used (nmax) and, for the first unused position, the depth rank of
+// its Gaussian.  The backward replays only [start, start + nmax), and the
+// per-Gaussian reduction skips pairs at or beyond a tile's cut, so unused
+// pairs cost neither a replay nor a write.
 //
 // Backward.  Front to back again (nothing per (pixel, Gaussian) is stored):
 // from the forward's output C_out and the running accumulation, the colour
 // behind contributor k is B_k = C_out - sum_{j<=k} c_j a_j T_j; only its
 // projection on the upstream gradient g is needed, g.B_k = g.C_out - sum.
-// Each lane sums its pixels' contributions in registers; the wave then reduces
-// the nine screen-space gradient components and writes them once to the pair's
-// slot in emission order (no atomics, deterministic).
+// Each lane sums its pixels' contributions in registers.  The wave-wide sum of
+// the nine screen-space components is a transpose through LDS: for a group of
+// four Gaussians each lane writes its 36 partial values, then lane r < 36 adds
+// the 64 values of component r in a fixed order (no atomics, deterministic)
+// and the pair's slot in emission order is written once.
 #include "gsr_internal.h"
 
 namespace gsr {
@@ -50,7 +60,7 @@ __device__ __forceinline__ TileCtx tile_ctx(const ViewTable &vt, uint32_t t) {
 // Staged record (LDS): three float4 per Gaussian.
 //   a = (u - ox, v - oy, -A log2e / 2, -B log2e)
 //   b = (-C log2e / 2, log2(opacity), red, green)
-//   c = (blue, bits(y0 - oy | (y1 - oy) << 16), bits(pair index), opacity)
+//   d = (blue, bits(y0 - oy | (y1 - oy) << 16), bits(pair index), opacity)
 // so that sigma * log2e = -(a.z dx^2 + a.w dx dy + b.x dy^2) and
 // alpha = min(0.99, exp2(-sigma log2e + b.y)).
 __device__ __forceinline__ void stage_record(const Rec &r, const float2 lo, const TileCtx &c, uint32_t tile_h,
@@ -72,9 +82,10 @@ __device__ __forceinline__ void stage_record(const Rec &r, const float2 lo, cons
 }
 
 // Does the record's box (rows y0..y1 relative to the tile, stored +1) touch
-// rows [r0, r0 + 3] of the tile?
+// rows [r0, r0 + 3] of the tile?  The operand is wave-uniform (an LDS
+// broadcast), so the branch on it is a scalar branch.
 __device__ __forceinline__ bool slab_hit(float packed, int r0) {
-    const uint32_t u = __float_as_uint(packed);
+    const uint32_t u = __builtin_amdgcn_readfirstlane(__float_as_uint(packed));
     const int y0 = (int)(u & 0xffffu) - 1, y1 = (int)(u >> 16) - 1;
     return y0 <= r0 + 3 && y1 >= r0;
 }
@@ -86,6 +97,11 @@ __device__ __forceinline__ uint32_t next_tile(bool persistent, uint32_t *queue, 
     return __shfl(t, 0, kWave);
 }
 
+// exponent of alpha, e2 = -sigma log2e, for the pixel at (dx, dy) from the centre
+__device__ __forceinline__ float neg_sigma_log2e(const float4 &a, const float4 &b, float dx, float dy) {
+    return fmaf(fmaf(a.z, dx, a.w * dy), dx, b.x * dy * dy);
+}
+
 // ---------------------------------------------------------------------------
 // A6: forward
 // ---------------------------------------------------------------------------
@@ -93,9 +109,10 @@ template <int RPL>
 __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uint2 *__restrict__ ranges,
                                                          const uint32_t *__restrict__ pval,
                                                          const Rec *__restrict__ rec, const float2 *__restrict__ ulo,
-                                                         float3 bg, float *__restrict__ out_rgb,
-                                                         float *__restrict__ out_T, float *__restrict__ pix_T,
-                                                         uint32_t *__restrict__ pix_n, WsHeader *hdr, int persistent) {
+                                                         const uint32_t *__restrict__ rank, float3 bg,
+                                                         float *__restrict__ out_rgb, float *__restrict__ out_T,
+                                                         float *__restrict__ pix_T, uint32_t *__restrict__ pix_n,
+                                                         uint2 *__restrict__ tile_cut, WsHeader *hdr, int persistent) {
     __shared__ float4 sa[kWave], sb[kWave], sd[kWave];
     const int lane = threadIdx.x;
     const int lx = lane & 15, ly = lane >> 4;
@@ -138,35 +155,34 @@ __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uin
             const int cnt = (int)min((uint32_t)kWave, rg.y - b0);
             for (int j = 0; j < cnt; ++j) {
                 const float4 a = sa[j], b = sb[j], d = sd[j];
+                const uint32_t pos = b0 - rg.x + (uint32_t)j;
                 const float dx = a.x - pxl;
 #pragma unroll
                 for (int k = 0; k < RPL; ++k) {
-                    if (!slab_hit(d.y, 4 * k)) continue;  // uniform across the wave
+                    if (!slab_hit(d.y, 4 * k)) continue;
                     const float dy = a.y - ((float)(ly + 4 * k) + 0.5f);
-                    const float e2 = a.z * dx * dx + a.w * dx * dy + b.x * dy * dy;
-                    const float alpha = fminf(kAlphaMax, exp2f(e2 + b.y));
-                    if (live[k] && e2 <= 0.f && alpha >= kAlphaMin) {
-                        const float Tn = T[k] * (1.f - alpha);
-                        if (Tn < kTMin) {
-                            live[k] = false;
-                            stop_at[k] = b0 - rg.x + (uint32_t)j;
-                        } else {
-                            const float w = alpha * T[k];
-                            C0[k] += b.z * w;
-                            C1[k] += b.w * w;
-                            C2[k] += d.x * w;
-                            T[k] = Tn;
-                            last[k] = b0 - rg.x + (uint32_t)j + 1;
-                            ++ncontrib[k];
-                        }
-                    }
+                    const float e2 = neg_sigma_log2e(a, b, dx, dy);
+                    const float alpha = fminf(kAlphaMax, __builtin_amdgcn_exp2f(e2 + b.y));
+                    const bool ok = live[k] && e2 <= 0.f && alpha >= kAlphaMin;
+                    const float Tn = T[k] * (1.f - alpha);
+                    const bool stop = ok && Tn < kTMin;
+                    const bool add = ok && !stop;
+                    const float w = add ? alpha * T[k] : 0.f;
+                    C0[k] = fmaf(b.z, w, C0[k]);
+                    C1[k] = fmaf(b.w, w, C1[k]);
+                    C2[k] = fmaf(d.x, w, C2[k]);
+                    T[k] = add ? Tn : T[k];
+                    last[k] = add ? pos + 1 : last[k];
+                    ncontrib[k] += add ? 1u : 0u;
+                    stop_at[k] = stop ? pos : stop_at[k];
+                    live[k] = live[k] && !stop;
                 }
             }
             __syncthreads();
         }
         // outputs
         const uint32_t len = rg.y - rg.x;
-        uint32_t evals = 0, replays = 0, contrib = 0;
+        uint32_t evals = 0, replays = 0, contrib = 0, nmax = 0;
         const size_t plane = (size_t)c.width * c.height;
         float *img = out_rgb + 3 * (size_t)c.pix_off;
 #pragma unroll
@@ -183,21 +199,26 @@ __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uin
                 evals += stop_at[k] != 0xffffffffu ? stop_at[k] + 1 : len;
                 replays += last[k];
                 contrib += ncontrib[k];
+                nmax = max(nmax, last[k]);
             }
         }
-        // per-tile work counters for the measurement harness (integer adds:
-        // order independent)
+        // work counters for the measurement harness (integer adds: order independent)
         unsigned long long e = evals, rp = replays, cc = contrib;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
             e += __shfl_xor(e, o, kWave);
             rp += __shfl_xor(rp, o, kWave);
             cc += __shfl_xor(cc, o, kWave);
+            nmax = max(nmax, (uint32_t)__shfl_xor((int)nmax, o, kWave));
         }
         if (lane == 0) {
             atomicAdd(&hdr->evaluations, e);
             atomicAdd(&hdr->replays, rp);
             atomicAdd(&hdr->contributors, cc);
+            // positions the backward replays, and the depth rank of the first
+            // Gaussian it does not
+            const uint32_t cut = nmax < len ? rank[pval[rg.x + nmax]] : 0xffffffffu;
+            tile_cut[t] = make_uint2(nmax, cut);
         }
     }
 }
@@ -205,6 +226,10 @@ __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uin
 // ---------------------------------------------------------------------------
 // A7: backward
 // ---------------------------------------------------------------------------
+constexpr int kGroup = 4;                          // Gaussians per LDS transpose
+constexpr int kRedCols = kGroup * kPartialStride;  // 36 values per lane
+constexpr int kRedStride = kRedCols + 1;           // padded row: conflict-free
+
 template <int RPL>
 __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uint2 *__restrict__ ranges,
                                                          const uint32_t *__restrict__ pval,
@@ -212,8 +237,10 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
                                                          const float *__restrict__ out_rgb,
                                                          const float *__restrict__ dL_drgb,
                                                          const uint32_t *__restrict__ pix_n,
+                                                         const uint2 *__restrict__ tile_cut,
                                                          float *__restrict__ partial, WsHeader *hdr, int persistent) {
     __shared__ float4 sa[kWave], sb[kWave], sd[kWave];
+    __shared__ float red[kWave * kRedStride];
     const int lane = threadIdx.x;
     const int lx = lane & 15, ly = lane >> 4;
     const float pxl = (float)lx + 0.5f;
@@ -228,7 +255,6 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
         const float *gimg = dL_drgb + 3 * (size_t)c.pix_off;
         float T[RPL], g0[RPL], g1[RPL], g2[RPL], gout[RPL], gacc[RPL];
         uint32_t ncon[RPL];
-        uint32_t nmax = 0;
 #pragma unroll
         for (int k = 0; k < RPL; ++k) {
             const uint32_t py = c.oy + ly + 4 * k;
@@ -245,14 +271,12 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
                 ncon[k] = 0;
                 g0[k] = g1[k] = g2[k] = gout[k] = 0.f;
             }
-            nmax = max(nmax, ncon[k]);
         }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) nmax = max(nmax, (uint32_t)__shfl_xor((int)nmax, o, kWave));
         const uint2 rg = ranges[t];
-        for (uint32_t b0 = rg.x; b0 < rg.y; b0 += kWave) {
+        const uint32_t end = rg.x + tile_cut[t].x;  // positions any pixel of the tile used
+        for (uint32_t b0 = rg.x; b0 < end; b0 += kWave) {
             const uint32_t idx = b0 + lane;
-            if (idx < rg.y) {
+            if (idx < end) {
                 const uint32_t item = pval[idx];
                 float4 a, b, d;
                 stage_record(rec[item], ulo[item], c, (uint32_t)vt.tile_h, a, b, d);
@@ -261,103 +285,125 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
                 sd[lane] = d;
             }
             __syncthreads();
-            const int cnt = (int)min((uint32_t)kWave, rg.y - b0);
-            for (int j = 0; j < cnt; ++j) {
-                const uint32_t pos = b0 - rg.x + (uint32_t)j;
-                const float4 a = sa[j], b = sb[j], d = sd[j];
-                float s[kPartialStride] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // Swx Swy Sxx Sxy Syy So gr gg gb
-                bool any = false;
-                if (pos < nmax) {
-                    const float dx = a.x - pxl;
+            const int cnt = (int)min((uint32_t)kWave, end - b0);
+            for (int j0 = 0; j0 < cnt; j0 += kGroup) {
 #pragma unroll
-                    for (int k = 0; k < RPL; ++k) {
-                        if (!slab_hit(d.y, 4 * k)) continue;
-                        const float dy = a.y - ((float)(ly + 4 * k) + 0.5f);
-                        const float e2 = a.z * dx * dx + a.w * dx * dy + b.x * dy * dy;
-                        const float araw = exp2f(e2 + b.y);
-                        const float alpha = fminf(kAlphaMax, araw);
-                        if (pos < ncon[k] && e2 <= 0.f && alpha >= kAlphaMin) {
-                            any = true;
-                            const float w = alpha * T[k];
-                            s[6] += w * g0[k];
-                            s[7] += w * g1[k];
-                            s[8] += w * g2[k];
-                            const float grgb = g0[k] * b.z + g1[k] * b.w + g2[k] * d.x;
-                            gacc[k] += w * grgb;
+                for (int q = 0; q < kGroup; ++q) {
+                    const int j = j0 + q;
+                    // Swx Swy Sxx Sxy Syy (moments of dL/dsigma), So, dL/drgb
+                    float s[kPartialStride] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+                    if (j < cnt) {
+                        const uint32_t pos = b0 - rg.x + (uint32_t)j;
+                        const float4 a = sa[j], b = sb[j], d = sd[j];
+                        const float dx = a.x - pxl;
+#pragma unroll
+                        for (int k = 0; k < RPL; ++k) {
+                            if (!slab_hit(d.y, 4 * k)) continue;
+                            const float dy = a.y - ((float)(ly + 4 * k) + 0.5f);
+                            const float e2 = neg_sigma_log2e(a, b, dx, dy);
+                            const float araw = __builtin_amdgcn_exp2f(e2 + b.y);
+                            const float alpha = fminf(kAlphaMax, araw);
+                            const bool ok = pos < ncon[k] && e2 <= 0.f && alpha >= kAlphaMin;
+                            const float w = ok ? alpha * T[k] : 0.f;
+                            s[6] = fmaf(w, g0[k], s[6]);
+                            s[7] = fmaf(w, g1[k], s[7]);
+                            s[8] = fmaf(w, g2[k], s[8]);
+                            const float grgb = fmaf(g0[k], b.z, fmaf(g1[k], b.w, g2[k] * d.x));
+                            gacc[k] = fmaf(w, grgb, gacc[k]);
                             const float one_m = 1.f - alpha;
-                            const float dalpha = T[k] * grgb - (gout[k] - gacc[k]) / one_m;
-                            T[k] *= one_m;
-                            if (araw < kAlphaMax) {
-                                const float sa_ = dalpha * alpha;  // dL/dsigma = -sa_, dL/do = sa_ / o
-                                s[5] += sa_;
-                                const float wx = -sa_ * dx, wy = -sa_ * dy;
-                                s[0] += wx;
-                                s[1] += wy;
-                                s[2] += wx * dx;
-                                s[3] += wx * dy;
-                                s[4] += wy * dy;
-                            }
+                            const float dalpha =
+                                fmaf(T[k], grgb, -(gout[k] - gacc[k]) * __builtin_amdgcn_rcpf(one_m));
+                            T[k] = ok ? T[k] * one_m : T[k];
+                            // dL/dsigma = -sa, dL/do = sa / o (zero through the 0.99 clamp)
+                            const float sa_ = (ok && araw < kAlphaMax) ? dalpha * alpha : 0.f;
+                            s[5] += sa_;
+                            const float wx = -sa_ * dx, wy = -sa_ * dy;
+                            s[0] += wx;
+                            s[1] += wy;
+                            s[2] = fmaf(wx, dx, s[2]);
+                            s[3] = fmaf(wx, dy, s[3]);
+                            s[4] = fmaf(wy, dy, s[4]);
                         }
                     }
-                }
-                const uint32_t p = __float_as_uint(d.z);
-                float *dst = partial + (size_t)p * kPartialStride;
-                if (__ballot(any) != 0ull) {
 #pragma unroll
-                    for (int q = 0; q < kPartialStride; ++q) s[q] = wave_sum(s[q]);
-                    // screen-space gradient of (u, v, A, B, C, o, r, g, b)
-                    const float A = -2.f * a.z / kLog2e, B = -a.w / kLog2e, Cc = -2.f * b.x / kLog2e;
-                    float outv = 0.f;
-                    switch (lane) {
-                        case 0: outv = A * s[0] + B * s[1]; break;
-                        case 1: outv = Cc * s[1] + B * s[0]; break;
-                        case 2: outv = 0.5f * s[2]; break;
-                        case 3: outv = s[3]; break;
-                        case 4: outv = 0.5f * s[4]; break;
-                        case 5: outv = s[5] / d.w; break;
-                        case 6: outv = s[6]; break;
-                        case 7: outv = s[7]; break;
-                        case 8: outv = s[8]; break;
-                        default: break;
-                    }
-                    if (lane < kPartialStride) dst[lane] = outv;
-                } else if (lane < kPartialStride) {
-                    dst[lane] = 0.f;
+                    for (int cc = 0; cc < kPartialStride; ++cc)
+                        red[lane * kRedStride + q * kPartialStride + cc] = s[cc];
                 }
+                __syncthreads();
+                // lane r < 36 sums component r % 9 of Gaussian j0 + r / 9 over the 64 lanes
+                float tot = 0.f;
+                if (lane < kRedCols) {
+                    float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+#pragma unroll 4
+                    for (int l = 0; l < kWave; l += 4) {
+                        p0 += red[(l + 0) * kRedStride + lane];
+                        p1 += red[(l + 1) * kRedStride + lane];
+                        p2 += red[(l + 2) * kRedStride + lane];
+                        p3 += red[(l + 3) * kRedStride + lane];
+                    }
+                    tot = (p0 + p1) + (p2 + p3);
+                }
+                // moments -> screen-space gradient of (u, v, A, B, C, o, r, g, b)
+                const int q = lane / kPartialStride, cc = lane - q * kPartialStride;
+                const float nb1 = __shfl_down(tot, 1, kWave);  // Swy, read by the Swx lane
+                const float nb0 = __shfl_up(tot, 1, kWave);    // Swx, read by the Swy lane
+                const int j = j0 + q;
+                if (lane < kRedCols && j < cnt) {
+                    const float4 a = sa[j], b = sb[j], d = sd[j];
+                    const float A = -2.f * a.z / kLog2e, B = -a.w / kLog2e, Cc = -2.f * b.x / kLog2e;
+                    float outv;
+                    switch (cc) {
+                        case 0: outv = A * tot + B * nb1; break;
+                        case 1: outv = Cc * tot + B * nb0; break;
+                        case 2: outv = 0.5f * tot; break;
+                        case 4: outv = 0.5f * tot; break;
+                        case 5: outv = tot / d.w; break;
+                        default: outv = tot; break;
+                    }
+                    partial[(size_t)__float_as_uint(d.z) * kPartialStride + cc] = outv;
+                }
+                __syncthreads();
             }
-            __syncthreads();
         }
     }
 }
 
 void launch_composite_fwd(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
-                          const float2 *ulo, float3 bg, float *out_rgb, float *out_T, float *pix_T, uint32_t *pix_n,
-                          WsHeader *hdr, bool persistent, int persistent_ctas, hipStream_t st) {
+                          const float2 *ulo, const uint32_t *rank, float3 bg, float *out_rgb, float *out_T,
+                          float *pix_T, uint32_t *pix_n, uint2 *tile_cut, WsHeader *hdr, bool persistent,
+                          int persistent_ctas, hipStream_t st) {
     if (vt.total_tiles == 0) return;
     const dim3 grid(persistent ? (unsigned)persistent_ctas : vt.total_tiles);
     const int p = persistent ? 1 : 0;
+#define GSR_FWD(R)                                                                                               \
+    hipLaunchKernelGGL(k_composite_fwd<R>, grid, dim3(kWave), 0, st, vt, ranges, pval, rec, ulo, rank, bg, out_rgb, \
+                       out_T, pix_T, pix_n, tile_cut, hdr, p)
     switch (vt.tile_h) {
-        case 4: hipLaunchKernelGGL(k_composite_fwd<1>, grid, dim3(kWave), 0, st, vt, ranges, pval, rec, ulo, bg, out_rgb, out_T, pix_T, pix_n, hdr, p); break;
-        case 8: hipLaunchKernelGGL(k_composite_fwd<2>, grid, dim3(kWave), 0, st, vt, ranges, pval, rec, ulo, bg, out_rgb, out_T, pix_T, pix_n, hdr, p); break;
-        case 32: hipLaunchKernelGGL(k_composite_fwd<8>, grid, dim3(kWave), 0, st, vt, ranges, pval, rec, ulo, bg, out_rgb, out_T, pix_T, pix_n, hdr, p); break;
-        default: hipLaunchKernelGGL(k_composite_fwd<4>, grid, dim3(kWave), 0, st, vt, ranges, pval, rec, ulo, bg, out_rgb, out_T, pix_T, pix_n, hdr, p); break;
+        case 4: GSR_FWD(1); break;
+        case 8: GSR_FWD(2); break;
+        case 32: GSR_FWD(8); break;
+        default: GSR_FWD(4); break;
     }
+#undef GSR_FWD
 }
 
 void launch_composite_bwd(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
-                          const float2 *ulo, const float *out_rgb, const float *dL_drgb, const float *pix_T,
-                          const uint32_t *pix_n, float *partial, WsHeader *hdr, bool persistent, int persistent_ctas,
+                          const float2 *ulo, const float *out_rgb, const float *dL_drgb, const uint32_t *pix_n,
+                          const uint2 *tile_cut, float *partial, WsHeader *hdr, bool persistent, int persistent_ctas,
                           hipStream_t st) {
-    (void)pix_T;
     if (vt.total_tiles == 0) return;
     const dim3 grid(persistent ? (unsigned)persistent_ctas : vt.total_tiles);
     const int p = persistent ? 1 : 0;
+#define GSR_BWD(R)                                                                                                  \
+    hipLaunchKernelGGL(k_composite_bwd<R>, grid, dim3(kWave), 0, st, vt, ranges, pval, rec, ulo, out_rgb, dL_drgb, \
+                       pix_n, tile_cut, partial, hdr, p)
     switch (vt.tile_h) {
-        case 4: hipLaunchKernelGGL(k_composite_bwd<1>, grid, dim3(kWave), 0, st, vt, ranges, pval, rec, ulo, out_rgb, dL_drgb, pix_n, partial, hdr, p); break;
-        case 8: hipLaunchKernelGGL(k_composite_bwd<2>, grid, dim3(kWave), 0, st, vt, ranges, pval, rec, ulo, out_rgb, dL_drgb, pix_n, partial, hdr, p); break;
-        case 32: hipLaunchKernelGGL(k_composite_bwd<8>, grid, dim3(kWave), 0, st, vt, ranges, pval, rec, ulo, out_rgb, dL_drgb, pix_n, partial, hdr, p); break;
-        default: hipLaunchKernelGGL(k_composite_bwd<4>, grid, dim3(kWave), 0, st, vt, ranges, pval, rec, ulo, out_rgb, dL_drgb, pix_n, partial, hdr, p); break;
+        case 4: GSR_BWD(1); break;
+        case 8: GSR_BWD(2); break;
+        case 32: GSR_BWD(8); break;
+        default: GSR_BWD(4); break;
     }
+#undef GSR_BWD
 }
 
 }  // namespace gsr

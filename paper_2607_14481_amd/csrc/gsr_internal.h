@@ -44,7 +44,8 @@ struct WsHeader {
     unsigned long long replays;       // sum over pixels of n_contrib
     unsigned long long contributors;  // sum over pixels of Gaussians composited
     uint32_t queue[4];       // persistent-launch work counters
-    uint32_t pad[50];
+    uint32_t n_big;          // items listed for the workgroup-wide pair reduction
+    uint32_t pad[49];
 };
 static_assert(sizeof(WsHeader) == 256, "header is 256 bytes");
 
@@ -70,11 +71,15 @@ struct WsLayout {
     size_t ckey[2];     // u32[items] depth sort ping-pong keys
     size_t cval[2];     // u32[items] depth sort ping-pong values (item ids)
     size_t poff;        // u32[items] pair offset, in depth order
+    size_t rank;        // u32[items] depth rank of each visible item
+    size_t big_list;    // u32[items] depth ranks of items reduced by a whole workgroup
+    size_t screen;      // float4[items * 3] per-item screen-space gradient
     size_t pkey[2];     // u32[cap] tile keys ping-pong
     size_t pval[2];     // u32[cap] item ids ping-pong
     size_t hist;        // u32[256 * max_blocks] radix histograms
     size_t digit_total; // u32[256] radix digit totals
     size_t ranges;      // uint2[total_tiles]
+    size_t tile_cut;    // uint2[total_tiles] (positions replayed, depth rank cut)
     size_t pix_T;       // float[total_pixels] final transmittance
     size_t pix_n;       // u32[total_pixels] last contributor + 1
     size_t partial;     // float[cap * 9] per-pair screen-space gradients
@@ -123,22 +128,25 @@ void launch_reset_queue(WsHeader *h, int which, hipStream_t st);
 void launch_pair_offsets(const uint32_t *sorted_items, const uint32_t *count, uint64_t items_cap,
                          uint32_t *poff, uint32_t *block_tmp, WsHeader *hdr, hipStream_t st);
 void launch_emit_pairs(const ViewTable &vt, const uint32_t *sorted_items, const uint32_t *poff, uint64_t n,
-                       uint64_t items_cap, Rec *rec, uint32_t *pkey, uint32_t *pval, const WsHeader *hdr,
-                       hipStream_t st);
+                       uint64_t items_cap, Rec *rec, uint32_t *rank, uint32_t *pkey, uint32_t *pval,
+                       const WsHeader *hdr, hipStream_t st);
 void launch_tile_ranges(const uint32_t *pkey, uint64_t cap, uint2 *ranges, uint32_t total_tiles,
                         const WsHeader *hdr, hipStream_t st);
 
 void launch_composite_fwd(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
-                          const float2 *ulo, float3 bg, float *out_rgb, float *out_T, float *pix_T,
-                          uint32_t *pix_n, WsHeader *hdr, bool persistent, int persistent_ctas,
-                          hipStream_t st);
-void launch_composite_bwd(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
-                          const float2 *ulo, const float *out_rgb, const float *dL_drgb, const float *pix_T,
-                          const uint32_t *pix_n, float *partial, WsHeader *hdr, bool persistent,
+                          const float2 *ulo, const uint32_t *rank, float3 bg, float *out_rgb, float *out_T,
+                          float *pix_T, uint32_t *pix_n, uint2 *tile_cut, WsHeader *hdr, bool persistent,
                           int persistent_ctas, hipStream_t st);
+void launch_composite_bwd(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
+                          const float2 *ulo, const float *out_rgb, const float *dL_drgb, const uint32_t *pix_n,
+                          const uint2 *tile_cut, float *partial, WsHeader *hdr, bool persistent,
+                          int persistent_ctas, hipStream_t st);
+void launch_pair_reduce(const ViewTable &vt, const uint32_t *sorted_items, const uint32_t *poff, uint64_t n,
+                        uint64_t items_cap, const Rec *rec, const uint2 *tile_cut, const float *partial,
+                        float4 *screen, uint32_t *big_list, WsHeader *hdr, int big_ctas, hipStream_t st);
 
 void launch_project_bwd(const gsr_gaussians &g, const ViewTable &vt, const float *w2c, uint64_t n,
-                        const Rec *rec, const uint32_t *count, const WsHeader *hdr, const float *partial,
+                        const Rec *rec, const uint32_t *count, const WsHeader *hdr, const float4 *screen,
                         const gsr_gaussian_grads &gr, float *pose_part, uint32_t pose_blocks, hipStream_t st);
 void launch_pose_finalize(const ViewTable &vt, const float *w2c, const float *pose_part, uint32_t pose_blocks,
                           float *dL_dw2c, float *dL_dtwist, hipStream_t st);
@@ -146,11 +154,26 @@ void launch_pose_finalize(const ViewTable &vt, const float *w2c, const float *po
 // ---------------------------------------------------------------------------
 // Device helpers
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float wave_sum(float x) {
-    // butterfly over the 64 lanes; every lane ends with the total
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
-    return x;
+// One DPP step: v + (v moved across lanes by `ctrl`), only in the rows enabled
+// by `row_mask` (other rows add 0).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float v) {
+    return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+}
+
+// Sum over the 64 lanes of a wave, with VALU data-parallel-primitive moves
+// (no LDS round trips): swaps within quads, mirrors within half-rows and rows
+// leave every lane with its 16-lane row's sum; two row broadcasts then
+// accumulate rows 0..3 into row 3.  The total is read from lane 63 and
+// returned to every lane.  Fixed order, so the result is deterministic.
+__device__ __forceinline__ float wave_sum(float v) {
+    v = dpp_add<0xB1, 0xf>(v);   // quad_perm [1, 0, 3, 2]
+    v = dpp_add<0x4E, 0xf>(v);   // quad_perm [2, 3, 0, 1]
+    v = dpp_add<0x141, 0xf>(v);  // row_half_mirror
+    v = dpp_add<0x140, 0xf>(v);  // row_mirror
+    v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 __device__ __forceinline__ uint32_t pack_u16(uint32_t lo, uint32_t hi) { return lo | (hi << 16); }

@@ -265,9 +265,162 @@ void launch_project_fwd(const gsr_gaussians &g, const ViewTable &vt, const float
 }
 
 // ---------------------------------------------------------------------------
-// A8 + A9: projection backward.  One thread per Gaussian; loops over views.
-// Screen-space gradient per item = fixed-order sum over its pairs (which the
-// binning laid out contiguously), so the result is deterministic.
+// A8: per-item sum of the per-pair screen-space gradients, in a fixed order.
+// Items are visited in depth order (their pairs are contiguous in emission
+// order).  An item with at most kSmallItem pairs is summed by one lane, four
+// pairs per step so that the loads overlap.  Larger items (splats near the
+// camera can cover thousands of tiles, and they all sit at the front of the
+// depth order) are appended to a list and summed by a whole workgroup each in
+// k_pair_reduce_big, which spreads them over the chip.  Pairs whose tile
+// stopped before reaching the item (depth rank >= the tile's cut) were never
+// written by the backward compositing and are masked out; their loads are
+// issued anyway so that no load waits for the mask.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kSmallItem = 32;
+
+struct PairSpan {
+    uint32_t p0;       // first pair (emission order)
+    uint32_t tile0;    // global tile id of the box's first tile
+    uint32_t w, cnt;   // box width in tiles, number of pairs
+    uint32_t tiles_x;  // tiles per row of the view
+};
+
+__device__ __forceinline__ PairSpan item_span(const ViewTable &vt, const Rec *__restrict__ rec, uint32_t item,
+                                              uint64_t n, uint32_t p0) {
+    const float4 r2 = rec[item].r2;
+    const uint32_t bx = __float_as_uint(r2.y), by = __float_as_uint(r2.z);
+    const uint32_t tx0 = (bx & 0xffffu) / kTileW, tx1 = (bx >> 16) / kTileW;
+    const uint32_t ty0 = (by & 0xffffu) / vt.tile_h, ty1 = (by >> 16) / vt.tile_h;
+    const int v = (int)(item / n);
+    PairSpan sp;
+    sp.tiles_x = (uint32_t)vt.v[v].tiles_x;
+    sp.tile0 = vt.v[v].tile_off + ty0 * sp.tiles_x + tx0;
+    sp.w = tx1 - tx0 + 1;
+    sp.cnt = sp.w * (ty1 - ty0 + 1);
+    sp.p0 = p0;
+    return sp;
+}
+
+// pair q of the span lies in tile row `row`, column `col` of the item's box
+__device__ __forceinline__ void add_pair(const PairSpan &sp, uint32_t q, uint32_t rank_i, uint32_t row, uint32_t col,
+                                         const uint2 *__restrict__ tile_cut, const float *__restrict__ partial,
+                                         float s[kPartialStride]) {
+    const bool valid = rank_i < tile_cut[sp.tile0 + row * sp.tiles_x + col].y;
+    const float *pp = partial + (size_t)(sp.p0 + q) * kPartialStride;
+    float x[kPartialStride];
+#pragma unroll
+    for (int c = 0; c < kPartialStride; ++c) x[c] = pp[c];
+#pragma unroll
+    for (int c = 0; c < kPartialStride; ++c) s[c] += valid ? x[c] : 0.f;
+}
+
+__device__ __forceinline__ void step_rc(uint32_t w, uint32_t &row, uint32_t &col) {
+    if (++col == w) col = 0, ++row;
+}
+
+__global__ __launch_bounds__(256) void k_pair_reduce(ViewTable vt, const uint32_t *__restrict__ sorted_items,
+                                                     const uint32_t *__restrict__ poff, uint64_t n,
+                                                     const Rec *__restrict__ rec, const uint2 *__restrict__ tile_cut,
+                                                     const float *__restrict__ partial, float4 *__restrict__ screen,
+                                                     uint32_t *__restrict__ big_list, WsHeader *__restrict__ hdr) {
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (hdr->overflow || i >= hdr->n_visible) return;
+    const uint32_t item = sorted_items[i];
+    const PairSpan sp = item_span(vt, rec, item, n, poff[i]);
+    if (sp.cnt > kSmallItem) {
+        big_list[atomicAdd(&hdr->n_big, 1u)] = i;  // list order is irrelevant to the sums
+        return;
+    }
+    float s[kPartialStride] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    uint32_t row = 0, col = 0, q = 0;
+    for (; q + 4 <= sp.cnt; q += 4) {
+        uint32_t r[4], c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            r[u] = row;
+            c[u] = col;
+            step_rc(sp.w, row, col);
+        }
+        float acc[4][kPartialStride];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int cc = 0; cc < kPartialStride; ++cc) acc[u][cc] = 0.f;
+            add_pair(sp, q + u, i, r[u], c[u], tile_cut, partial, acc[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int cc = 0; cc < kPartialStride; ++cc) s[cc] += acc[u][cc];
+    }
+    for (; q < sp.cnt; ++q) {
+        add_pair(sp, q, i, row, col, tile_cut, partial, s);
+        step_rc(sp.w, row, col);
+    }
+    screen[3 * (size_t)item + 0] = make_float4(s[0], s[1], s[2], s[3]);
+    screen[3 * (size_t)item + 1] = make_float4(s[4], s[5], s[6], s[7]);
+    screen[3 * (size_t)item + 2] = make_float4(s[8], 0.f, 0.f, 0.f);
+}
+
+// One workgroup per listed large item (looping over the list): threads stride
+// over the item's pairs, then a fixed-shape tree combines them.
+__global__ __launch_bounds__(256) void k_pair_reduce_big(ViewTable vt, const uint32_t *__restrict__ sorted_items,
+                                                         const uint32_t *__restrict__ poff, uint64_t n,
+                                                         const Rec *__restrict__ rec,
+                                                         const uint2 *__restrict__ tile_cut,
+                                                         const float *__restrict__ partial,
+                                                         float4 *__restrict__ screen,
+                                                         const uint32_t *__restrict__ big_list,
+                                                         const WsHeader *__restrict__ hdr) {
+    __shared__ float red[4][kPartialStride];
+    if (hdr->overflow) return;
+    const uint32_t nbig = hdr->n_big;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (uint32_t b = blockIdx.x; b < nbig; b += gridDim.x) {
+        const uint32_t i = big_list[b];
+        const uint32_t item = sorted_items[i];
+        const PairSpan sp = item_span(vt, rec, item, n, poff[i]);
+        float s[kPartialStride] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        uint32_t row = threadIdx.x / sp.w, col = threadIdx.x - row * sp.w;
+        const uint32_t drow = 256u / sp.w, dcol = 256u - drow * sp.w;
+        for (uint32_t q = threadIdx.x; q < sp.cnt; q += 256u) {
+            add_pair(sp, q, i, row, col, tile_cut, partial, s);
+            row += drow;
+            col += dcol;
+            if (col >= sp.w) col -= sp.w, ++row;
+        }
+#pragma unroll
+        for (int c = 0; c < kPartialStride; ++c) {
+            const float t = wave_sum(s[c]);
+            if (lane == 0) red[w][c] = t;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float o[kPartialStride];
+#pragma unroll
+            for (int c = 0; c < kPartialStride; ++c) o[c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+            screen[3 * (size_t)item + 0] = make_float4(o[0], o[1], o[2], o[3]);
+            screen[3 * (size_t)item + 1] = make_float4(o[4], o[5], o[6], o[7]);
+            screen[3 * (size_t)item + 2] = make_float4(o[8], 0.f, 0.f, 0.f);
+        }
+        __syncthreads();
+    }
+}
+
+void launch_pair_reduce(const ViewTable &vt, const uint32_t *sorted_items, const uint32_t *poff, uint64_t n,
+                        uint64_t items_cap, const Rec *rec, const uint2 *tile_cut, const float *partial,
+                        float4 *screen, uint32_t *big_list, WsHeader *hdr, int big_ctas, hipStream_t st) {
+    if (items_cap == 0) return;
+    hipLaunchKernelGGL(k_pair_reduce, dim3((unsigned)((items_cap + 255) / 256)), dim3(256), 0, st, vt, sorted_items,
+                       poff, n, rec, tile_cut, partial, screen, big_list, hdr);
+    hipLaunchKernelGGL(k_pair_reduce_big, dim3((unsigned)big_ctas), dim3(256), 0, st, vt, sorted_items, poff, n, rec,
+                       tile_cut, partial, screen, big_list, hdr);
+}
+
+// ---------------------------------------------------------------------------
+// A9: projection backward.  One thread per Gaussian; loops over views and
+// chains each visible item's screen-space gradient (from A8) back to the
+// parameters and to the view's pose.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float block_sum_256(float x, float *red /* [4] */) {
     x = wave_sum(x);
@@ -282,7 +435,7 @@ __device__ __forceinline__ float block_sum_256(float x, float *red /* [4] */) {
 template <int DEG>
 __global__ __launch_bounds__(kProjThreads) void k_project_bwd(
     gsr_gaussians g, ViewTable vt, const float *__restrict__ w2c, uint64_t n, const Rec *__restrict__ rec,
-    const uint32_t *__restrict__ count, const WsHeader *__restrict__ hdr, const float *__restrict__ partial,
+    const uint32_t *__restrict__ count, const WsHeader *__restrict__ hdr, const float4 *__restrict__ screen,
     gsr_gaussian_grads gr, float *__restrict__ pose_part, uint32_t pose_blocks) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     __shared__ float red[4];
@@ -291,9 +444,8 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(
     const bool live = i < n && hdr->overflow == 0u;
 
     float gmu[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gop = 0.f;
-    float gsh[K][3];
-#pragma unroll
-    for (int k = 0; k < K; ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.f;
+    bool sh_written = false;  // SH gradient rows are stored by the first visible view, added to by later ones
+    float *gsh = gr.sh + (size_t)i * K * 3;
 
     for (int v = 0; v < vt.n_views; ++v) {
         float gW[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gt[3] = {0, 0, 0};
@@ -301,15 +453,9 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(
         const uint32_t cnt = live ? count[item] : 0u;
         if (cnt > 0) {
             const ViewInfo cam = vt.v[v];
-            // A8: sum this item's per-pair screen-space gradients
-            const uint32_t off = __float_as_uint(rec[item].r2.w);
-            float s[kPartialStride] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-            const float *pp = partial + (size_t)off * kPartialStride;
-            for (uint32_t k = 0; k < cnt; ++k)
-#pragma unroll
-                for (int c = 0; c < kPartialStride; ++c) s[c] += pp[(size_t)k * kPartialStride + c];
-            const float gu = s[0], gv = s[1], gA = s[2], gB = s[3], gC = s[4], go = s[5];
-            const float grgb[3] = {s[6], s[7], s[8]};
+            const float4 s0 = screen[3 * item], s1 = screen[3 * item + 1], s2 = screen[3 * item + 2];
+            const float gu = s0.x, gv = s0.y, gA = s0.z, gB = s0.w, gC = s1.x, go = s1.y;
+            const float grgb[3] = {s1.z, s1.w, s2.x};
 
             float W[9], t[3];
             load_pose(w2c, v, W, t);
@@ -331,28 +477,34 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(
             float Y[K];
             sh_eval<DEG, float>(dir[0], dir[1], dir[2], Y);
             const float *shp = g.sh + (size_t)i * K * 3;
+            // pass 1: colour, to know which channels the forward clamped at 0
             float col[3] = {0.5f, 0.5f, 0.5f};
-            float shv[K][3];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                shv[k][0] = shp[3 * k];
-                shv[k][1] = shp[3 * k + 1];
-                shv[k][2] = shp[3 * k + 2];
-                col[0] += shv[k][0] * Y[k];
-                col[1] += shv[k][1] * Y[k];
-                col[2] += shv[k][2] * Y[k];
+                col[0] = fmaf(shp[3 * k], Y[k], col[0]);
+                col[1] = fmaf(shp[3 * k + 1], Y[k], col[1]);
+                col[2] = fmaf(shp[3 * k + 2], Y[k], col[2]);
             }
             float gc[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) gc[c] = col[c] < 0.f ? 0.f : grgb[c];
+            // pass 2: coefficient gradients and the weights of dRGB/ddir
             float wdir[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                gsh[k][0] += gc[0] * Y[k];
-                gsh[k][1] += gc[1] * Y[k];
-                gsh[k][2] += gc[2] * Y[k];
-                wdir[k] = gc[0] * shv[k][0] + gc[1] * shv[k][1] + gc[2] * shv[k][2];
+                const float a0 = shp[3 * k], a1 = shp[3 * k + 1], a2 = shp[3 * k + 2];
+                float o0 = gc[0] * Y[k], o1 = gc[1] * Y[k], o2 = gc[2] * Y[k];
+                if (sh_written) {
+                    o0 += gsh[3 * k];
+                    o1 += gsh[3 * k + 1];
+                    o2 += gsh[3 * k + 2];
+                }
+                gsh[3 * k] = o0;
+                gsh[3 * k + 1] = o1;
+                gsh[3 * k + 2] = o2;
+                wdir[k] = fmaf(gc[0], a0, fmaf(gc[1], a1, gc[2] * a2));
             }
+            sh_written = true;
             float gdx, gdy, gdz;
             sh_grad_dir<DEG>(dir[0], dir[1], dir[2], wdir, gdx, gdy, gdz);
             const float dd = gdx * dir[0] + gdy * dir[1] + gdz * dir[2];
@@ -493,16 +645,17 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(
             for (int k = 0; k < 4; ++k) gq[k] += (gqh[k] - q[k] * qd) / qn;
         }
         // per-block partial of this view's pose gradient (all threads take part)
-        float *dst = pose_part + ((size_t)v * pose_blocks + blockIdx.x) * 12;
+        // layout [view][entry of the 3x4 block][workgroup]
+        float *dst = pose_part + (size_t)v * 12 * pose_blocks + blockIdx.x;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
             const float s = block_sum_256(gW[k], red);
-            if (threadIdx.x == 0) dst[(k / 3) * 4 + (k % 3)] = s;
+            if (threadIdx.x == 0) dst[(size_t)((k / 3) * 4 + (k % 3)) * pose_blocks] = s;
         }
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const float s = block_sum_256(gt[k], red);
-            if (threadIdx.x == 0) dst[k * 4 + 3] = s;
+            if (threadIdx.x == 0) dst[(size_t)(k * 4 + 3) * pose_blocks] = s;
         }
     }
     if (i >= n) return;
@@ -514,25 +667,22 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(
     gr.log_scales[3 * i + 2] = gls[2];
     reinterpret_cast<float4 *>(gr.quats)[i] = make_float4(gq[0], gq[1], gq[2], gq[3]);
     gr.opacities[i] = gop;
-    float *gs = gr.sh + (size_t)i * K * 3;
+    if (!sh_written) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        gs[3 * k] = gsh[k][0];
-        gs[3 * k + 1] = gsh[k][1];
-        gs[3 * k + 2] = gsh[k][2];
+        for (int k = 0; k < 3 * K; ++k) gsh[k] = 0.f;
     }
 }
 
 void launch_project_bwd(const gsr_gaussians &g, const ViewTable &vt, const float *w2c, uint64_t n, const Rec *rec,
-                        const uint32_t *count, const WsHeader *hdr, const float *partial, const gsr_gaussian_grads &gr, float *pose_part,
+                        const uint32_t *count, const WsHeader *hdr, const float4 *screen, const gsr_gaussian_grads &gr, float *pose_part,
                         uint32_t pose_blocks, hipStream_t st) {
     if (n == 0) return;
     const dim3 grid(pose_blocks);
     switch (g.sh_degree) {
-        case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, partial, gr, pose_part, pose_blocks); break;
-        case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, partial, gr, pose_part, pose_blocks); break;
-        case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, partial, gr, pose_part, pose_blocks); break;
-        default: hipLaunchKernelGGL(k_project_bwd<3>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, partial, gr, pose_part, pose_blocks); break;
+        case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, screen, gr, pose_part, pose_blocks); break;
+        case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, screen, gr, pose_part, pose_blocks); break;
+        case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, screen, gr, pose_part, pose_blocks); break;
+        default: hipLaunchKernelGGL(k_project_bwd<3>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, screen, gr, pose_part, pose_blocks); break;
     }
 }
 
@@ -541,18 +691,18 @@ void launch_project_bwd(const gsr_gaussians &g, const ViewTable &vt, const float
 // order, writes the 4x4 gradient (last row zero) and the left-perturbation
 // twist: M = G T^T, d/drho = M[0:3, 3], d/dphi = (M21 - M12, M02 - M20, M10 - M01).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_pose_finalize(const float *__restrict__ w2c,
+__global__ __launch_bounds__(768) void k_pose_finalize(const float *__restrict__ w2c,
                                                        const float *__restrict__ pose_part, uint32_t pose_blocks,
                                                        float *__restrict__ dL_dw2c, float *__restrict__ dL_dtwist) {
-    __shared__ float red[4];
+    // one workgroup per view, one wave per entry of the top 3x4 block
     __shared__ float G[16];
     const int v = blockIdx.x;
-    for (int k = 0; k < 12; ++k) {
-        float acc = 0.f;
-        for (uint32_t b = threadIdx.x; b < pose_blocks; b += 256) acc += pose_part[((size_t)v * pose_blocks + b) * 12 + k];
-        const float s = block_sum_256(acc, red);
-        if (threadIdx.x == 0) G[k] = s;
-    }
+    const int k = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const float *src = pose_part + ((size_t)v * 12 + k) * pose_blocks;
+    float acc = 0.f;
+    for (uint32_t b = lane; b < pose_blocks; b += 64) acc += src[b];
+    acc = wave_sum(acc);
+    if (lane == 0) G[k] = acc;
     if (threadIdx.x == 0) G[12] = G[13] = G[14] = G[15] = 0.f;
     __syncthreads();
     if (threadIdx.x < 16 && dL_dw2c) dL_dw2c[16 * v + threadIdx.x] = G[threadIdx.x];
@@ -576,7 +726,7 @@ __global__ __launch_bounds__(256) void k_pose_finalize(const float *__restrict__
 void launch_pose_finalize(const ViewTable &vt, const float *w2c, const float *pose_part, uint32_t pose_blocks,
                           float *dL_dw2c, float *dL_dtwist, hipStream_t st) {
     if (!dL_dw2c && !dL_dtwist) return;
-    hipLaunchKernelGGL(k_pose_finalize, dim3(vt.n_views), dim3(256), 0, st, w2c, pose_part, pose_blocks, dL_dw2c,
+    hipLaunchKernelGGL(k_pose_finalize, dim3(vt.n_views), dim3(768), 0, st, w2c, pose_part, pose_blocks, dL_dw2c,
                        dL_dtwist);
 }
 

@@ -238,6 +238,11 @@ __global__ __launch_bounds__(256) void k_radix_scan(uint32_t *__restrict__ hist,
     if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
 }
 
+// Stable scatter of one block's kSortTile elements.  Ranks come from wave
+// ballots (16 rounds of 256 consecutive elements, so order is preserved); the
+// block's elements are first placed in LDS in digit order, then written out in
+// contiguous runs per digit (coalesced, instead of one random 4-byte write per
+// element).
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *__restrict__ kin,
                                                                 const uint32_t *__restrict__ vin,
                                                                 uint32_t *__restrict__ kout,
@@ -245,32 +250,41 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
                                                                 const uint32_t *__restrict__ hist,
                                                                 uint32_t hist_blocks,
                                                                 const uint32_t *__restrict__ digit_total) {
-    __shared__ uint32_t base_off[256];   // global offset of each digit for this block
+    __shared__ uint32_t gbase[256];      // global position of this block's first element of each digit
+    __shared__ uint32_t lbase[256];      // block-local position of the same
+    __shared__ uint32_t running[256];    // elements of each digit placed so far
     __shared__ uint32_t wave_cnt[4][256];
     __shared__ uint32_t lds[4];
+    __shared__ uint32_t skey[kSortTile], sval[kSortTile];
     const uint64_t n = sc();
     const uint64_t blk = (uint64_t)blockIdx.x * kSortTile;
     if (blk >= n) return;
+    const uint32_t nb = (uint32_t)((n + kSortTile - 1) / kSortTile);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t t = threadIdx.x;
     {
-        // digit base = exclusive scan of digit totals + this block's prefix
         uint32_t total;
-        const uint32_t ex = block_exclusive_scan(digit_total[threadIdx.x], lds, total);
-        base_off[threadIdx.x] = ex + hist[(size_t)threadIdx.x * hist_blocks + blockIdx.x];
+        const uint32_t ex = block_exclusive_scan(digit_total[t], lds, total);
+        const uint32_t mine = hist[(size_t)t * hist_blocks + blockIdx.x];
+        const uint32_t next = blockIdx.x + 1 < nb ? hist[(size_t)t * hist_blocks + blockIdx.x + 1] : digit_total[t];
+        gbase[t] = ex + mine;
+        const uint32_t lex = block_exclusive_scan(next - mine, lds, total);
+        lbase[t] = lex;
+        running[t] = lex;
     }
-    for (int k = 0; k < 4; ++k) wave_cnt[k][threadIdx.x] = 0;
+    for (int k = 0; k < 4; ++k) wave_cnt[k][t] = 0;
     __syncthreads();
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
+    const uint32_t m = (uint32_t)min((uint64_t)kSortTile, n - blk);
     for (int r = 0; r < kSortItems; ++r) {
-        const uint64_t i = blk + (uint64_t)r * kSortThreads + threadIdx.x;
-        const bool ok = i < n;
+        const uint32_t li = (uint32_t)r * kSortThreads + t;
+        const bool ok = li < m;
         uint32_t key = 0, val = 0, d = 0;
         if (ok) {
-            key = kin[i];
-            val = vin[i];
+            key = kin[blk + li];
+            val = vin[blk + li];
             d = (key >> shift) & 255u;
         }
-        // lanes of this wave holding the same digit
         unsigned long long match = __ballot(ok);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -279,24 +293,27 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
         }
         const uint32_t rank = __popcll(match & lt_mask);
         const uint32_t cnt = __popcll(match);
-        const bool leader = ok && (rank == cnt - 1);  // highest lane of its group
-        if (leader) wave_cnt[w][d] = cnt;
+        if (ok && rank == cnt - 1) wave_cnt[w][d] = cnt;  // one writer per (wave, digit)
         __syncthreads();
         if (ok) {
-            uint32_t pos = base_off[d] + rank;
+            uint32_t pos = running[d] + rank;
             for (int k = 0; k < w; ++k) pos += wave_cnt[k][d];
-            kout[pos] = key;
-            vout[pos] = val;
+            skey[pos] = key;
+            sval[pos] = val;
         }
         __syncthreads();
-        // advance digit bases by this round's counts, clear the wave counts
-        {
-            const uint32_t t = threadIdx.x;
-            base_off[t] += wave_cnt[0][t] + wave_cnt[1][t] + wave_cnt[2][t] + wave_cnt[3][t];
-            wave_cnt[0][t] = wave_cnt[1][t] = wave_cnt[2][t] = wave_cnt[3][t] = 0;
-        }
+        running[t] += wave_cnt[0][t] + wave_cnt[1][t] + wave_cnt[2][t] + wave_cnt[3][t];
+        wave_cnt[0][t] = wave_cnt[1][t] = wave_cnt[2][t] = wave_cnt[3][t] = 0;
         __syncthreads();
-        if (blk + (uint64_t)(r + 1) * kSortThreads >= n) break;  // uniform
+        if ((r + 1) * kSortThreads >= (int)m) break;  // uniform
+    }
+    // write out in local order: runs of one digit go to consecutive addresses
+    for (uint32_t pos = t; pos < m; pos += kSortThreads) {
+        const uint32_t key = skey[pos];
+        const uint32_t d = (key >> shift) & 255u;
+        const uint32_t g = gbase[d] + (pos - lbase[d]);
+        kout[g] = key;
+        vout[g] = sval[pos];
     }
 }
 
@@ -319,39 +336,64 @@ void radix_sort_u32(uint32_t *keys[2], uint32_t *vals[2], SortCount sc, uint64_t
 }
 
 // ---------------------------------------------------------------------------
-// A3: emission.  The i-th item in depth order writes its pairs at poff[i], in
-// row-major order over its tile box, and records the offset in its record.
+// A3: emission.  The i-th item in depth order owns pairs [poff[i], poff[i] +
+// count) in row-major order over its tile box.  A wave takes 64 consecutive
+// items and writes their pairs cooperatively (lanes stride over one item's
+// tiles), so the writes are coalesced and large Gaussians do not serialise a
+// lane.  The item's depth rank and pair offset are recorded for the backward.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_emit(ViewTable vt, const uint32_t *__restrict__ sorted_items,
                                               const uint32_t *__restrict__ poff, uint64_t n, Rec *__restrict__ rec,
-                                              uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval,
-                                              const WsHeader *__restrict__ hdr) {
-    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= hdr->n_visible || hdr->overflow) return;
-    const uint32_t item = sorted_items[i];
-    const uint32_t off = poff[i];
-    const int v = (int)(item / n);
-    const ViewInfo &cam = vt.v[v];
-    const float4 r2 = rec[item].r2;
-    rec[item].r2.w = __uint_as_float(off);
-    const uint32_t bx = __float_as_uint(r2.y), by = __float_as_uint(r2.z);
-    const uint32_t tx0 = (bx & 0xffffu) / kTileW, tx1 = (bx >> 16) / kTileW;
-    const uint32_t ty0 = (by & 0xffffu) / vt.tile_h, ty1 = (by >> 16) / vt.tile_h;
-    uint32_t o = off;
-    for (uint32_t ty = ty0; ty <= ty1; ++ty)
-        for (uint32_t tx = tx0; tx <= tx1; ++tx) {
-            pkey[o] = cam.tile_off + ty * cam.tiles_x + tx;
-            pval[o] = item;
-            ++o;
+                                              uint32_t *__restrict__ rank, uint32_t *__restrict__ pkey,
+                                              uint32_t *__restrict__ pval, const WsHeader *__restrict__ hdr) {
+    const uint32_t nvis = hdr->n_visible;
+    if (hdr->overflow) return;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t base = (blockIdx.x * 256u + threadIdx.x) & ~63u;  // first depth index of this wave
+    if (base >= nvis) return;                                        // uniform per wave
+    const uint32_t i = base + lane;
+    uint32_t item = 0, off = 0, w = 1, cnt = 0, t0 = 0, tiles_x = 0;
+    if (i < nvis) {
+        item = sorted_items[i];
+        off = poff[i];
+        rank[item] = i;
+        const float4 r2 = rec[item].r2;
+        rec[item].r2.w = __uint_as_float(off);
+        const uint32_t bx = __float_as_uint(r2.y), by = __float_as_uint(r2.z);
+        const uint32_t tx0 = (bx & 0xffffu) / kTileW, tx1 = (bx >> 16) / kTileW;
+        const uint32_t ty0 = (by & 0xffffu) / vt.tile_h, ty1 = (by >> 16) / vt.tile_h;
+        const int v = (int)(item / n);
+        tiles_x = (uint32_t)vt.v[v].tiles_x;
+        w = tx1 - tx0 + 1;
+        cnt = w * (ty1 - ty0 + 1);
+        t0 = vt.v[v].tile_off + ty0 * tiles_x + tx0;
+    }
+    const uint32_t nj = min(64u, nvis - base);
+    for (uint32_t j = 0; j < nj; ++j) {
+        // item j's box, broadcast through scalar registers
+        const uint32_t cj = __builtin_amdgcn_readlane(cnt, j), oj = __builtin_amdgcn_readlane(off, j);
+        const uint32_t wj = __builtin_amdgcn_readlane(w, j), tj = __builtin_amdgcn_readlane(t0, j);
+        const uint32_t sxj = __builtin_amdgcn_readlane(tiles_x, j), itj = __builtin_amdgcn_readlane(item, j);
+        if (lane >= cj) continue;
+        // lane walks q = lane, lane + 64, ... keeping (row, col) of q incrementally
+        uint32_t row = lane / wj, col = lane - row * wj;
+        const uint32_t drow = 64u / wj, dcol = 64u - drow * wj;
+        for (uint32_t q = lane; q < cj; q += 64u) {
+            pkey[oj + q] = tj + row * sxj + col;
+            pval[oj + q] = itj;
+            row += drow;
+            col += dcol;
+            if (col >= wj) col -= wj, ++row;
         }
+    }
 }
 
 void launch_emit_pairs(const ViewTable &vt, const uint32_t *sorted_items, const uint32_t *poff, uint64_t n,
-                       uint64_t items_cap, Rec *rec, uint32_t *pkey, uint32_t *pval, const WsHeader *hdr,
-                       hipStream_t st) {
+                       uint64_t items_cap, Rec *rec, uint32_t *rank, uint32_t *pkey, uint32_t *pval,
+                       const WsHeader *hdr, hipStream_t st) {
     if (items_cap == 0) return;
     hipLaunchKernelGGL(k_emit, dim3((unsigned)((items_cap + 255) / 256)), dim3(256), 0, st, vt, sorted_items, poff, n,
-                       rec, pkey, pval, hdr);
+                       rec, rank, pkey, pval, hdr);
 }
 
 // ---------------------------------------------------------------------------
@@ -390,7 +432,11 @@ void launch_reset_header(WsHeader *h, uint32_t cap, hipStream_t st) {
     hipLaunchKernelGGL(k_reset_header, dim3(1), dim3(64), 0, st, h, cap);
 }
 
-__global__ void k_reset_queue(WsHeader *h, int which) { h->queue[which] = 0u; }
+// Start of a backward pass: its work queue and its list of large items.
+__global__ void k_reset_queue(WsHeader *h, int which) {
+    h->queue[which] = 0u;
+    h->n_big = 0u;
+}
 
 void launch_reset_queue(WsHeader *h, int which, hipStream_t st) {
     hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(1), 0, st, h, which);
