@@ -119,6 +119,9 @@ def main():
     # ---- plain form: synchronous capacity check, one view per launch sequence
     for _ in range(args.warmup):
         _, ws, _, _ = step()
+    rast.stats = True  # one instrumented step for the work counters, outside the timed region
+    _, ws, _, _ = step()
+    rast.stats = False
     torch.cuda.synchronize()
     stats = gsr.query_stats(ws)
     log(f"[bench] stats {stats}")

@@ -85,6 +85,7 @@ extern "C" {
 /* Flags. */
 #define GSR_FLAG_SYNC 1u        /* forward: synchronise once to check the pair capacity */
 #define GSR_FLAG_PERSISTENT 2u  /* compositing as persistent work-queue launches */
+#define GSR_FLAG_STATS 4u       /* forward: also count the work (gsr_query_stats); slower */
 
 /* Intrinsics of one view (host struct).  The pose is passed separately, as a
    device array, so that it can be optimised on the device. */
@@ -201,7 +202,9 @@ int gsr_query_pairs(const void *ws, size_t ws_bytes, int64_t *needed, int64_t *c
                     int32_t *overflowed, void *stream);
 
 /*
- * Work counters of the last forward on ws (for measurement).  Blocking, like
+ * Work counters of the last forward on ws (for measurement).  visible and
+ * pairs are always counted; evaluations, contributors and replays only by a
+ * forward run with GSR_FLAG_STATS (zero otherwise).  Blocking, like
  * gsr_query_pairs.
  */
 int gsr_query_stats(const void *ws, size_t ws_bytes, gsr_stats *out, void *stream);

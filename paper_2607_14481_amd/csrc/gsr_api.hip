@@ -332,7 +332,7 @@ int gsr_rasterize_forward(void *ws, size_t ws_bytes, const gsr_gaussians *g, int
     const bool pers = (flags & GSR_FLAG_PERSISTENT) != 0;
     mark.begin(GSR_STAGE_COMPOSITE_FWD);
     launch_composite_fwd(vt, p.ranges, p.pval[pc], p.rec, p.ulo, p.rank, bgc, out_rgb, out_T, p.pix_T, p.pix_n,
-                         p.tile_cut, p.hdr, pers, persistent_ctas(cfg), st);
+                         p.tile_cut, p.hdr, pers, persistent_ctas(cfg), (flags & GSR_FLAG_STATS) != 0, st);
     mark.end(GSR_STAGE_COMPOSITE_FWD);
     return check_hip(hipGetLastError(), "forward launch");
 }

@@ -105,7 +105,7 @@ __device__ __forceinline__ float neg_sigma_log2e(const float4 &a, const float4 &
 // ---------------------------------------------------------------------------
 // A6: forward
 // ---------------------------------------------------------------------------
-template <int RPL>
+template <int RPL, bool STATS>
 __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uint2 *__restrict__ ranges,
                                                          const uint32_t *__restrict__ pval,
                                                          const Rec *__restrict__ rec, const float2 *__restrict__ ulo,
@@ -154,6 +154,12 @@ __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uin
             __syncthreads();
             const int cnt = (int)min((uint32_t)kWave, rg.y - b0);
             for (int j = 0; j < cnt; ++j) {
+                if ((j & 15) == 15) {  // leave the batch once every pixel of the tile has stopped
+                    bool any = false;
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k) any |= live[k];
+                    if (__ballot(any) == 0ull) break;
+                }
                 const float4 a = sa[j], b = sb[j], d = sd[j];
                 const uint32_t pos = b0 - rg.x + (uint32_t)j;
                 const float dx = a.x - pxl;
@@ -173,8 +179,10 @@ __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uin
                     C2[k] = fmaf(d.x, w, C2[k]);
                     T[k] = add ? Tn : T[k];
                     last[k] = add ? pos + 1 : last[k];
-                    ncontrib[k] += add ? 1u : 0u;
-                    stop_at[k] = stop ? pos : stop_at[k];
+                    if constexpr (STATS) {
+                        ncontrib[k] += add ? 1u : 0u;
+                        stop_at[k] = stop ? pos : stop_at[k];
+                    }
                     live[k] = live[k] && !stop;
                 }
             }
@@ -202,19 +210,24 @@ __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uin
                 nmax = max(nmax, last[k]);
             }
         }
-        // work counters for the measurement harness (integer adds: order independent)
-        unsigned long long e = evals, rp = replays, cc = contrib;
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            e += __shfl_xor(e, o, kWave);
-            rp += __shfl_xor(rp, o, kWave);
-            cc += __shfl_xor(cc, o, kWave);
-            nmax = max(nmax, (uint32_t)__shfl_xor((int)nmax, o, kWave));
+        for (int o = 32; o > 0; o >>= 1) nmax = max(nmax, (uint32_t)__shfl_xor((int)nmax, o, kWave));
+        if constexpr (STATS) {
+            // work counters for the measurement harness (integer adds: order independent)
+            unsigned long long e = evals, rp = replays, cc = contrib;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                e += __shfl_xor(e, o, kWave);
+                rp += __shfl_xor(rp, o, kWave);
+                cc += __shfl_xor(cc, o, kWave);
+            }
+            if (lane == 0) {
+                atomicAdd(&hdr->evaluations, e);
+                atomicAdd(&hdr->replays, rp);
+                atomicAdd(&hdr->contributors, cc);
+            }
         }
         if (lane == 0) {
-            atomicAdd(&hdr->evaluations, e);
-            atomicAdd(&hdr->replays, rp);
-            atomicAdd(&hdr->contributors, cc);
             // positions the backward replays, and the depth rank of the first
             // Gaussian it does not
             const uint32_t cut = nmax < len ? rank[pval[rg.x + nmax]] : 0xffffffffu;
@@ -371,19 +384,22 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
 void launch_composite_fwd(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
                           const float2 *ulo, const uint32_t *rank, float3 bg, float *out_rgb, float *out_T,
                           float *pix_T, uint32_t *pix_n, uint2 *tile_cut, WsHeader *hdr, bool persistent,
-                          int persistent_ctas, hipStream_t st) {
+                          int persistent_ctas, bool stats, hipStream_t st) {
     if (vt.total_tiles == 0) return;
     const dim3 grid(persistent ? (unsigned)persistent_ctas : vt.total_tiles);
     const int p = persistent ? 1 : 0;
-#define GSR_FWD(R)                                                                                               \
-    hipLaunchKernelGGL(k_composite_fwd<R>, grid, dim3(kWave), 0, st, vt, ranges, pval, rec, ulo, rank, bg, out_rgb, \
-                       out_T, pix_T, pix_n, tile_cut, hdr, p)
+#define GSR_FWD(R, S)                                                                                             \
+    hipLaunchKernelGGL((k_composite_fwd<R, S>), grid, dim3(kWave), 0, st, vt, ranges, pval, rec, ulo, rank, bg,     \
+                       out_rgb, out_T, pix_T, pix_n, tile_cut, hdr, p)
+#define GSR_FWD_RPL(R) \
+    if (stats) GSR_FWD(R, true); else GSR_FWD(R, false)
     switch (vt.tile_h) {
-        case 4: GSR_FWD(1); break;
-        case 8: GSR_FWD(2); break;
-        case 32: GSR_FWD(8); break;
-        default: GSR_FWD(4); break;
+        case 4: GSR_FWD_RPL(1); break;
+        case 8: GSR_FWD_RPL(2); break;
+        case 32: GSR_FWD_RPL(8); break;
+        default: GSR_FWD_RPL(4); break;
     }
+#undef GSR_FWD_RPL
 #undef GSR_FWD
 }
 

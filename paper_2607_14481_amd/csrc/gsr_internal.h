@@ -136,7 +136,7 @@ void launch_tile_ranges(const uint32_t *pkey, uint64_t cap, uint2 *ranges, uint3
 void launch_composite_fwd(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
                           const float2 *ulo, const uint32_t *rank, float3 bg, float *out_rgb, float *out_T,
                           float *pix_T, uint32_t *pix_n, uint2 *tile_cut, WsHeader *hdr, bool persistent,
-                          int persistent_ctas, hipStream_t st);
+                          int persistent_ctas, bool stats, hipStream_t st);
 void launch_composite_bwd(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
                           const float2 *ulo, const float *out_rgb, const float *dL_drgb, const uint32_t *pix_n,
                           const uint2 *tile_cut, float *partial, WsHeader *hdr, bool persistent,

@@ -699,9 +699,16 @@ __global__ __launch_bounds__(768) void k_pose_finalize(const float *__restrict__
     const int v = blockIdx.x;
     const int k = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const float *src = pose_part + ((size_t)v * 12 + k) * pose_blocks;
-    float acc = 0.f;
-    for (uint32_t b = lane; b < pose_blocks; b += 64) acc += src[b];
-    acc = wave_sum(acc);
+    float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;  // independent loads in flight
+    uint32_t b = lane;
+    for (; b + 192 < pose_blocks; b += 256) {
+        acc0 += src[b];
+        acc1 += src[b + 64];
+        acc2 += src[b + 128];
+        acc3 += src[b + 192];
+    }
+    for (; b < pose_blocks; b += 64) acc0 += src[b];
+    const float acc = wave_sum((acc0 + acc1) + (acc2 + acc3));
     if (lane == 0) G[k] = acc;
     if (threadIdx.x == 0) G[12] = G[13] = G[14] = G[15] = 0.f;
     __syncthreads();

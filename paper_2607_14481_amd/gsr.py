@@ -24,6 +24,7 @@ GSR_ERR_UNSUPPORTED = 5
 GSR_MAX_VIEWS = 32
 GSR_FLAG_SYNC = 1
 GSR_FLAG_PERSISTENT = 2
+GSR_FLAG_STATS = 4
 
 EXPORTED = ("gsr_version", "gsr_status_string", "gsr_last_error", "gsr_workspace_bytes",
             "gsr_rasterize_forward", "gsr_rasterize_backward", "gsr_query_pairs", "gsr_query_stats",

@@ -46,12 +46,14 @@ class GaussianRasterizer:
         self.device = torch.device("cuda") if device is None else torch.device(device)
         self.sizes = [(int(c.height), int(c.width)) for c in self.cams]
         self.total_pixels = sum(h * w for h, w in self.sizes)
+        self.stats = False  # count work in the forward (slower; for measurement)
         self.last_pairs = None
         self.last_twist_grad = None
 
     @property
     def flags(self) -> int:
-        return (gsr.GSR_FLAG_SYNC if self.sync else 0) | (gsr.GSR_FLAG_PERSISTENT if self.persistent else 0)
+        return ((gsr.GSR_FLAG_SYNC if self.sync else 0) | (gsr.GSR_FLAG_PERSISTENT if self.persistent else 0)
+                | (gsr.GSR_FLAG_STATS if self.stats else 0))
 
     def workspace(self, n: int, capacity: Optional[int] = None) -> torch.Tensor:
         cap = self.capacity if capacity is None else int(capacity)

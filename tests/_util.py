@@ -46,6 +46,7 @@ def gpu_render(scene, cams, bg=(0.0, 0.0, 0.0), upstream=None, tile_h=16, persis
     from paper_2607_14481_amd.rasterizer import GaussianRasterizer
 
     rast = GaussianRasterizer(cams, scene.sh_degree, tile_h=tile_h, persistent=persistent, sync=sync)
+    rast.stats = True
     params = params_to_device(scene)
     w2c = poses_to_device(cams)
     rgb, ws = rast.forward(params, w2c, bg)
