@@ -63,6 +63,86 @@ def make_workload(name):
     return wl, desc
 
 
+def run_ring(steps, warmup):
+    """8 cameras (mixed 640x480 / 1280x720 / 1920x1080) on a 15 m ring around
+    1M Gaussians, SH degree 3: one step = fwd + L1 + bwd over all 8 views,
+    gradients summed over views.  Plain = one view per launch sequence;
+    batched = the autotuned launch grouping, captured in a HIP graph."""
+    import numpy as np
+    import torch
+    from paper_2607_14481_amd import gsr
+    from paper_2607_14481_amd import scenes as S
+    from paper_2607_14481_amd.autotune import MultiViewStep, autotune
+    from paper_2607_14481_amd.rasterizer import GaussianRasterizer
+    wl = S.multi_view_ring()
+    sc, cams = wl.scene, wl.cameras
+    dev = torch.device("cuda")
+    params = [torch.tensor(np.asarray(getattr(sc, k), np.float32), device=dev)
+              for k in ("means", "log_scales", "quats", "opacities", "sh")]
+    w2c = torch.tensor(np.stack([np.asarray(c.world_to_cam, np.float32) for c in cams]), device=dev)
+    targets, pairs = [], []
+    for v, c in enumerate(cams):
+        r = GaussianRasterizer([c], sc.sh_degree)
+        tw = torch.tensor(S.perturbed_pose(c.world_to_cam, 3000 + v)[None], device=dev)
+        t, _ = r.forward(params, tw)
+        targets.append(t.clone())
+        _, ws = r.forward(params, w2c[v:v + 1])
+        pairs.append(gsr.query_pairs(ws)[0])
+    plain = MultiViewStep(cams, sc.sh_degree, params, w2c, targets, views_per_launch=1)
+    from paper_2607_14481_amd.autotune import _time
+    ms_plain = _time(plain, steps, warmup)
+    log(f"[bench] ring plain (8 launch sequences): {ms_plain:.3f} ms/step")
+    tuned = autotune(cams, sc.sh_degree, params, w2c, targets, cache_path=None, log=log, steps=3, warmup=1)
+    best = tuned["best"]
+    step = MultiViewStep(cams, sc.sh_degree, params, w2c, targets, sync=False, capacity_hint=pairs, **best)
+    s_ = torch.cuda.Stream()
+    s_.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s_):
+        for _ in range(2):
+            step(keep_workspaces=True)
+    torch.cuda.current_stream().wait_stream(s_)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step(keep_workspaces=True)
+    ms_graph = _time(graph.replay, steps, warmup)
+    ovf = any(g[0].check_overflow(ws) for g, ws in zip(step.groups, step.ws))
+    log(f"[bench] ring batched {best} graph: {ms_graph:.3f} ms/step (overflow {ovf})")
+    return {"workload": "8-camera ring (r = 15 m), resolutions " + ", ".join(f"{c.width}x{c.height}" for c in cams)
+                        + ", 1,000,000 Gaussians SH 3, fwd+bwd over all views, gradients summed",
+            "pairs_per_view": pairs,
+            "plain_ms_per_step": round(ms_plain, 4), "plain_iters_per_s": round(1000 / ms_plain, 3),
+            "batched_config": best, "batched_graph_ms_per_step": round(ms_graph, 4),
+            "batched_graph_iters_per_s": round(1000 / ms_graph, 3), "overflow": bool(ovf),
+            "autotune_ms": tuned["ms"]}
+
+
+def run_serving(seconds, rate=200.0, start=500_000, per_keyframe=10_000, period=0.5, seed=5):
+    """Poisson arrivals (mean `rate`/s) of render / optimise requests (50/50;
+    resolutions uniform over 256x256..1920x1080; optimise = 1-4 views, fwd+bwd
+    vs a U(0,1) target) against a scene that starts at `start` Gaussians and
+    grows by `per_keyframe` every `period` seconds.  Returns latency/throughput
+    for one request at a time and for continuous batching."""
+    import torch
+    from paper_2607_14481_amd.serve import GrowingScene, Server, make_requests
+    kfs = int(seconds / period) + 2
+    out = {"arrival_rate_per_s": rate, "window_s": seconds, "start_gaussians": start,
+           "growth": f"{per_keyframe} Gaussians per {period} s keyframe"}
+    for name, slots, group in (("one_at_a_time", 1, False), ("continuous_batching", 4, True)):
+        scene = GrowingScene(capacity=start + per_keyframe * kfs, start=start, per_keyframe=per_keyframe)
+        warm = make_requests(seed + 1000, rate=rate, duration=0.1)
+        Server(scene, slots=slots, group_renders=group).run(warm, keyframe_period=1e9, bind_versions=True)
+        torch.cuda.synchronize()
+        reqs = make_requests(seed, rate=rate, duration=seconds)
+        st = Server(scene, slots=slots, group_renders=group).run(reqs, keyframe_period=period)
+        log(f"[bench] serving {name}: {st['requests']} req, p50 {st['p50_ms']:.2f} ms, p99 {st['p99_ms']:.2f} ms, "
+            f"{st['throughput_req_s']:.1f} req/s, final {st['final_gaussians']} Gaussians")
+        out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
+        del scene
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +153,9 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--tile-h", type=int, default=16)
     ap.add_argument("--persistent", action="store_true", help="compositing as persistent work-queue launches")
+    ap.add_argument("--no-ring", action="store_true", help="skip the batched 8-view measurement")
+    ap.add_argument("--serve-seconds", type=float, default=5.0,
+                    help="length of the Poisson request window of the serving measurement (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the rasterizer's multi-GPU sharding (one view per GPU, one "
@@ -186,6 +269,16 @@ def main():
             graph_err = repr(e)
             log(f"[bench] graph form failed: {graph_err}")
 
+    # ---- batched views: the 8-camera ring, plain vs autotuned + graph
+    ring = None
+    if not args.no_ring:
+        ring = run_ring(max(5, args.steps // 5), 2)
+
+    # ---- serving: the same seeded arrivals, one request at a time vs continuous batching
+    served = None
+    if args.serve_seconds > 0:
+        served = run_serving(args.serve_seconds)
+
     # ---- roofline of the dominant kernel (compositing, ALU-bound)
     comp = {"composite_fwd": stage_ms["composite_fwd"], "composite_bwd": stage_ms["composite_bwd"]}
     dom = max(comp, key=comp.get)
@@ -235,6 +328,8 @@ def main():
         "work": stats,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched_views": ring,
+        "serving": served,
     }
     print(json.dumps(out), flush=True)
 

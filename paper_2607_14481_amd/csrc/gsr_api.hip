@@ -185,10 +185,11 @@ Ptrs carve(void *ws, const gsr::WsLayout &L) {
     return p;
 }
 
-// Workspace capacity is recorded in the header; recover it from ws_bytes for
-// the query entry points by reading the header instead.
-int persistent_ctas(const gsr_launch_config *cfg) {
-    if (cfg && cfg->persistent_ctas > 0) return cfg->persistent_ctas;
+// Caller-fixed workgroup count for persistent launches (0: as many as fit).
+int persistent_ctas(const gsr_launch_config *cfg) { return cfg && cfg->persistent_ctas > 0 ? cfg->persistent_ctas : 0; }
+
+// Workgroups for the large-item pair reduction: a few per compute unit.
+int big_item_ctas() {
     static int cus = 0;
     if (cus == 0) {
         int dev = 0, c = 0;
@@ -198,7 +199,7 @@ int persistent_ctas(const gsr_launch_config *cfg) {
         else
             cus = 256;
     }
-    return cus * 8;
+    return cus * 4;
 }
 
 // The pair capacity is whatever the workspace holds beyond the fixed regions;
@@ -370,7 +371,7 @@ int gsr_rasterize_backward(void *ws, size_t ws_bytes, const gsr_gaussians *g, in
     mark.begin(GSR_STAGE_PROJECT_BWD);
     // the depth sort's result buffer: four 8-bit passes end where they started
     launch_pair_reduce(vt, p.cval[0], p.poff, (uint64_t)g->n, L.items, p.rec, p.tile_cut, p.partial, p.screen,
-                       p.big_list, p.hdr, persistent_ctas(cfg) / 2, st);
+                       p.big_list, p.hdr, big_item_ctas(), st);
     launch_project_bwd(*g, vt, world_to_cam, (uint64_t)g->n, p.rec, p.count, p.hdr, p.screen, *grads, p.pose_part,
                        L.pose_blocks, st);
     if (g->n == 0)  // no Gaussian wrote a partial: the pose gradient is zero

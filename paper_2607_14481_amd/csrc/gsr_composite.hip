@@ -381,16 +381,36 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
     }
 }
 
+// Workgroups of a persistent launch: as many as can be resident at once
+// (occupancy of this kernel x compute units), unless the caller fixed it.
+template <typename Kernel>
+static int resident_ctas(Kernel kernel, int requested) {
+    if (requested > 0) return requested;
+    static int cache[64][2];  // per device: (compute units, blocks per CU); written once, same value each time
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    if (cache[dev][0] == 0) {
+        int cus = 0, per = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kWave, 0) != hipSuccess || per <= 0) per = 8;
+        cache[dev][1] = per;
+        cache[dev][0] = cus;
+    }
+    return cache[dev][0] * cache[dev][1];
+}
+
 void launch_composite_fwd(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
                           const float2 *ulo, const uint32_t *rank, float3 bg, float *out_rgb, float *out_T,
                           float *pix_T, uint32_t *pix_n, uint2 *tile_cut, WsHeader *hdr, bool persistent,
                           int persistent_ctas, bool stats, hipStream_t st) {
     if (vt.total_tiles == 0) return;
-    const dim3 grid(persistent ? (unsigned)persistent_ctas : vt.total_tiles);
     const int p = persistent ? 1 : 0;
-#define GSR_FWD(R, S)                                                                                             \
-    hipLaunchKernelGGL((k_composite_fwd<R, S>), grid, dim3(kWave), 0, st, vt, ranges, pval, rec, ulo, rank, bg,     \
-                       out_rgb, out_T, pix_T, pix_n, tile_cut, hdr, p)
+#define GSR_FWD(R, S)                                                                                               \
+    hipLaunchKernelGGL((k_composite_fwd<R, S>),                                                                     \
+                       dim3(persistent ? (unsigned)resident_ctas(k_composite_fwd<R, S>, persistent_ctas)            \
+                                       : vt.total_tiles),                                                           \
+                       dim3(kWave), 0, st, vt, ranges, pval, rec, ulo, rank, bg, out_rgb, out_T, pix_T, pix_n,      \
+                       tile_cut, hdr, p)
 #define GSR_FWD_RPL(R) \
     if (stats) GSR_FWD(R, true); else GSR_FWD(R, false)
     switch (vt.tile_h) {
@@ -408,11 +428,13 @@ void launch_composite_bwd(const ViewTable &vt, const uint2 *ranges, const uint32
                           const uint2 *tile_cut, float *partial, WsHeader *hdr, bool persistent, int persistent_ctas,
                           hipStream_t st) {
     if (vt.total_tiles == 0) return;
-    const dim3 grid(persistent ? (unsigned)persistent_ctas : vt.total_tiles);
     const int p = persistent ? 1 : 0;
 #define GSR_BWD(R)                                                                                                  \
-    hipLaunchKernelGGL(k_composite_bwd<R>, grid, dim3(kWave), 0, st, vt, ranges, pval, rec, ulo, out_rgb, dL_drgb, \
-                       pix_n, tile_cut, partial, hdr, p)
+    hipLaunchKernelGGL(k_composite_bwd<R>,                                                                          \
+                       dim3(persistent ? (unsigned)resident_ctas(k_composite_bwd<R>, persistent_ctas)               \
+                                       : vt.total_tiles),                                                           \
+                       dim3(kWave), 0, st, vt, ranges, pval, rec, ulo, out_rgb, dL_drgb, pix_n, tile_cut, partial,  \
+                       hdr, p)
     switch (vt.tile_h) {
         case 4: GSR_BWD(1); break;
         case 8: GSR_BWD(2); break;
