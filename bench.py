@@ -39,9 +39,41 @@ PEAK_FP32_TFLOPS = 157.3
 FLOPS_FWD_EVAL, FLOPS_FWD_CONTRIB = 13, 9
 FLOPS_BWD_EVAL, FLOPS_BWD_CONTRIB = 13, 34
 
+# Plain copy used to calibrate the HBM byte counters: every dispatch reads and
+# writes exactly this many bytes.
+COPY_CAL_MIB, COPY_CAL_REPS = 384, 4
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per dispatch of `kernel` from the committed byte-counter
+    profile, if it covers this workload and the kernel sources it was taken on
+    are the current ones (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{TRAFFIC_PROFILES.get(workload, '-')}_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    info = None
+    for line in open(path):
+        if line.startswith("traffic-json: "):
+            info = json.loads(line[len("traffic-json: "):])
+    if info is None or kernel not in info["kernel"]:
+        return None
+    h = hashlib.sha256()
+    for f in info["sources"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != info["sources_sha256"]:
+        return None
+    return {"bytes": int(info["read_bytes"] + info["write_bytes"]),
+            "note": f"FETCH_SIZE/{info['fetch_factor']} + WRITE_SIZE/{info['write_factor']} per dispatch "
+                    f"({info['read_bytes'] / 1e6:.1f} MB read, {info['write_bytes'] / 1e6:.1f} MB written), "
+                    f"from profiles/{os.path.basename(path)}"}
+
+
+TRAFFIC_PROFILES = {"headline": "headline_1080p_1M"}
 
 
 def make_workload(name):
@@ -156,6 +188,9 @@ def main():
     ap.add_argument("--no-ring", action="store_true", help="skip the batched 8-view measurement")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="length of the Poisson request window of the serving measurement (0: skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help=f"first run {COPY_CAL_REPS} plain device copies of {COPY_CAL_MIB} MiB (the reference "
+                         "kernel that scales HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the rasterizer's multi-GPU sharding (one view per GPU, one "
@@ -170,6 +205,13 @@ def main():
 
     torch.cuda.init()
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(COPY_CAL_MIB << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(COPY_CAL_REPS):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t0 = time.time()
     wl, desc = make_workload(args.workload)
     sc, cams = wl.scene, wl.cameras
@@ -208,6 +250,19 @@ def main():
     torch.cuda.synchronize()
     stats = gsr.query_stats(ws)
     log(f"[bench] stats {stats}")
+    # timed region: plain steps, nothing else on the stream
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(args.steps):
+        step()
+    end.record()
+    torch.cuda.synchronize()
+    ms_plain = start.elapsed_time(end) / args.steps
+    log(f"[bench] plain: {ms_plain:.3f} ms/step")
+
+    # the same steps again with HIP events recorded by the library between its
+    # stages, on the stream the kernels run on (per-stage and per-kernel times)
     stage_ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2 * len(gsr.STAGES))]
                 for _ in range(args.steps)]
     for evs in stage_ev:
@@ -215,7 +270,6 @@ def main():
             e.record()  # creates the underlying HIP events
     torch.cuda.synchronize()
     handles = [(gsr.C.c_void_p * (2 * len(gsr.STAGES)))(*[e.cuda_event for e in evs]) for evs in stage_ev]
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record()
     for k in range(args.steps):
@@ -224,12 +278,13 @@ def main():
     end.record()
     torch.cuda.synchronize()
     rast.cfg.stage_events = None
-    ms_plain = start.elapsed_time(end) / args.steps
+    ms_instrumented = start.elapsed_time(end) / args.steps
     stage_ms = {}
     for s, name in enumerate(gsr.STAGES):
         vals = [evs[2 * s].elapsed_time(evs[2 * s + 1]) for evs in stage_ev]
         stage_ms[name] = float(np.mean(vals))
-    log(f"[bench] plain: {ms_plain:.3f} ms/step; stages " + ", ".join(f"{k} {v:.3f}" for k, v in stage_ms.items()))
+    log(f"[bench] with stage events: {ms_instrumented:.3f} ms/step; stages "
+        + ", ".join(f"{k} {v:.3f}" for k, v in stage_ms.items()))
 
     # ---- graph form: the same step, no host synchronisation, replayed
     graph_ms = None
@@ -287,8 +342,11 @@ def main():
     else:
         flops = FLOPS_FWD_EVAL * stats["evaluations"] + FLOPS_FWD_CONTRIB * stats["contributors"]
     achieved = flops / (comp[dom] * 1e-3) / 1e12
+    traffic = measured_traffic(args.workload, dom)
     roofline = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "traffic": traffic["bytes"] if traffic else None,
+                "traffic_note": traffic["note"] if traffic else "no byte-counter profile of the current kernel sources",
                 "algorithmic_flops": int(flops), "ms": round(comp[dom], 4)}
 
     # ---- CPU baseline: the FP64 oracle as it stands, one full iteration
@@ -325,6 +383,7 @@ def main():
         "graph_form": {"iters_per_s": round(1000.0 / graph_ms, 3) if graph_ms else None,
                        "ms_per_step": round(graph_ms, 4) if graph_ms else None, "error": graph_err},
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "ms_per_step_with_stage_events": round(ms_instrumented, 4),
         "work": stats,
         "roofline": roofline,
         "cpu_baseline": cpu,

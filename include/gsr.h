@@ -131,7 +131,7 @@ typedef struct gsr_gaussian_grads {
    the gradients are independent of the tile shape. */
 typedef struct gsr_launch_config {
     int32_t tile_h;          /* tile height in pixels: 4, 8, 16 (default) or 32; width is 16 */
-    int32_t persistent_ctas; /* workgroups of a persistent launch; 0 = 8 per CU */
+    int32_t persistent_ctas; /* workgroups of a persistent launch; 0 = as many as can be resident at once */
     /* NULL, or a host array of 2 * GSR_NUM_STAGES hipEvent_t owned by the
        caller: events[2 s] / events[2 s + 1] are recorded on the stream just
        before / after stage s of the pass being enqueued. */

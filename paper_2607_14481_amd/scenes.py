@@ -251,3 +251,22 @@ def headline_view(seed=3, n=1_000_000) -> Workload:
 def random_upstream(seed, shape) -> np.ndarray:
     """Fixed N(0, 1) upstream gradient used by parity tests in place of a loss."""
     return _rng(seed).standard_normal(shape).astype(np.float32)
+
+
+def slab_leaves(seed=4, n=4_000_000, half=100.0, height=10.0, eye_height=2.0):
+    """Leaf Gaussians of the hierarchical level-of-detail workload: centres
+    uniform in a 200 m x 200 m x 10 m slab (x, y in [-100, 100], z in [0, 10]),
+    the box scene's other distributions (log-scales ~ N(-3, 0.5), SH degree 3);
+    one 1920x1080 camera at (0, 0, 2) looking horizontally at a seeded azimuth
+    (up = +z), and the target pose perturbed by 0.5 degrees and 2 cm.
+    Returns (leaves, camera, target camera)."""
+    rng = _rng(seed)
+    means = np.empty((n, 3))
+    means[:, :2] = rng.uniform(-half, half, (n, 2))
+    means[:, 2] = rng.uniform(0.0, height, n)
+    leaves = _gaussian_body(rng, means, 3)
+    az = rng.uniform(0.0, 2 * np.pi)
+    eye = np.array([0.0, 0.0, eye_height])
+    cam = pinhole(1920, 1080, look_at(eye, eye + np.array([np.cos(az), np.sin(az), 0.0])))
+    target = cam.copy_with_pose(perturbed_pose(cam.world_to_cam, seed + 1000))
+    return leaves, cam, target
