@@ -74,6 +74,7 @@ def measured_traffic(workload, kernel):
 
 
 TRAFFIC_PROFILES = {"headline": "headline_1080p_1M"}
+OTHER_WORKLOADS = ("small_view", "single_view_1080p", "lod_cut")
 
 
 def make_workload(name):
@@ -90,9 +91,136 @@ def make_workload(name):
     elif name == "small_view":
         wl = S.small_view()
         desc = "128x128 view, 1,000 Gaussians, SH degree 0; L1 loss vs a render of jittered means"
+    elif name == "lod_cut":
+        from paper_2607_14481_amd import hierarchy
+        wl = hierarchy.lod_workload()
+        desc = ("level-of-detail cut: 4,000,000 leaves along a 2 km street in a 7-level branching-8 hierarchy "
+                "(moment-matched merges), 1.5 px screen-size cut for one 1920x1080 view down the street "
+                f"({wl.scene.n} nodes, per level {wl.meta['cut_per_level']}); L1 loss vs a render from the pose "
+                "perturbed by 0.5 deg / 2 cm; fwd + bwd incl. pose gradient")
     else:
         raise SystemExit(f"unknown workload {name}")
     return wl, desc
+
+
+def measure_view(wl, steps, warmup, tile_h=16, persistent=False, graph=True):
+    """Times one workload's step (fwd + L1 + bwd incl. pose) in the plain form,
+    again with per-stage HIP events, and replayed from a HIP graph."""
+    import numpy as np
+    import torch
+    from paper_2607_14481_amd import gsr
+    from paper_2607_14481_amd.rasterizer import GaussianRasterizer
+    dev = torch.device("cuda:0")
+    sc, cams = wl.scene, wl.cameras
+    params = [torch.tensor(np.asarray(getattr(sc, k), np.float32), device=dev)
+              for k in ("means", "log_scales", "quats", "opacities", "sh")]
+    w2c = torch.tensor(np.asarray(cams[0].world_to_cam, np.float32)[None], device=dev)
+    bg = (0.0, 0.0, 0.0)
+    rast = GaussianRasterizer(cams, sc.sh_degree, tile_h=tile_h, persistent=persistent, device=dev)
+
+    # target image (untimed)
+    if wl.target_cameras is not None:
+        tw2c = torch.tensor(np.asarray(wl.target_cameras[0].world_to_cam, np.float32)[None], device=dev)
+        target, _ = rast.forward(params, tw2c, bg)
+    else:
+        tparams = list(params)
+        tparams[0] = torch.tensor(np.asarray(wl.target_scene.means, np.float32), device=dev)
+        target, _ = rast.forward(tparams, w2c, bg)
+    target = target.clone()
+    numel = target.numel()
+
+    def step(ws=None, out=None):
+        rgb, ws = rast.forward(params, w2c, bg, ws=ws, out=out)
+        diff = rgb - target
+        grad = torch.sign(diff) / numel  # d/d img of mean |img - target|
+        grads, g_w2c, g_tw = rast.backward(ws, params, w2c, bg, rgb, grad)
+        return rgb, ws, grads, g_tw
+
+    # ---- plain form: synchronous capacity check, one view per launch sequence
+    for _ in range(warmup):
+        _, ws, _, _ = step()
+    rast.stats = True  # one instrumented step for the work counters, outside the timed region
+    _, ws, _, _ = step()
+    rast.stats = False
+    torch.cuda.synchronize()
+    stats = gsr.query_stats(ws)
+    log(f"[bench] stats {stats}")
+    # timed region: plain steps, nothing else on the stream
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(steps):
+        step()
+    end.record()
+    torch.cuda.synchronize()
+    ms_plain = start.elapsed_time(end) / steps
+    log(f"[bench] plain: {ms_plain:.3f} ms/step")
+
+    # the same steps again with HIP events recorded by the library between its
+    # stages, on the stream the kernels run on (per-stage and per-kernel times)
+    stage_ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2 * len(gsr.STAGES))]
+                for _ in range(steps)]
+    for evs in stage_ev:
+        for e in evs:
+            e.record()  # creates the underlying HIP events
+    torch.cuda.synchronize()
+    handles = [(gsr.C.c_void_p * (2 * len(gsr.STAGES)))(*[e.cuda_event for e in evs]) for evs in stage_ev]
+    torch.cuda.synchronize()
+    start.record()
+    for k in range(steps):
+        rast.cfg.stage_events = gsr.C.cast(handles[k], gsr.C.c_void_p)
+        step()
+    end.record()
+    torch.cuda.synchronize()
+    rast.cfg.stage_events = None
+    ms_instrumented = start.elapsed_time(end) / steps
+    stage_ms = {}
+    for s, name in enumerate(gsr.STAGES):
+        vals = [evs[2 * s].elapsed_time(evs[2 * s + 1]) for evs in stage_ev]
+        stage_ms[name] = float(np.mean(vals))
+    log(f"[bench] with stage events: {ms_instrumented:.3f} ms/step; stages "
+        + ", ".join(f"{k} {v:.3f}" for k, v in stage_ms.items()))
+
+    # ---- graph form: the same step, no host synchronisation, replayed
+    graph_ms = None
+    graph_err = None
+    if graph:
+        try:
+            grast = GaussianRasterizer(cams, sc.sh_degree, tile_h=tile_h, persistent=persistent, sync=False,
+                                       device=dev)
+            grast.capacity = int(stats["pairs"] * 1.3) + 4096
+            gws = grast.workspace(sc.n)
+            gout = torch.empty_like(target)
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s):
+                for _ in range(3):
+                    rgb, _ = grast.forward(params, w2c, bg, ws=gws, out=gout)
+                    gr, _, _ = grast.backward(gws, params, w2c, bg, rgb, torch.sign(rgb - target) / numel)
+            torch.cuda.current_stream().wait_stream(s)
+            torch.cuda.synchronize()
+            assert not grast.check_overflow(gws)
+            cg = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(cg):
+                rgb, _ = grast.forward(params, w2c, bg, ws=gws, out=gout)
+                gr, _, _ = grast.backward(gws, params, w2c, bg, rgb, torch.sign(rgb - target) / numel)
+            for _ in range(warmup):
+                cg.replay()
+            torch.cuda.synchronize()
+            start.record()
+            for _ in range(steps):
+                cg.replay()
+            end.record()
+            torch.cuda.synchronize()
+            graph_ms = start.elapsed_time(end) / steps
+            assert not grast.check_overflow(gws)
+            log(f"[bench] graph: {graph_ms:.3f} ms/step")
+        except Exception as e:  # reported, never hidden
+            graph_err = repr(e)
+            log(f"[bench] graph form failed: {graph_err}")
+
+    return {"ms_plain": ms_plain, "ms_instrumented": ms_instrumented, "stage_ms": stage_ms, "stats": stats,
+            "graph_ms": graph_ms, "graph_err": graph_err}
 
 
 def run_ring(steps, warmup):
@@ -186,6 +314,8 @@ def main():
     ap.add_argument("--tile-h", type=int, default=16)
     ap.add_argument("--persistent", action="store_true", help="compositing as persistent work-queue launches")
     ap.add_argument("--no-ring", action="store_true", help="skip the batched 8-view measurement")
+    ap.add_argument("--no-other-workloads", action="store_true",
+                    help="skip the small-view, 200k-at-1080p and level-of-detail measurements")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="length of the Poisson request window of the serving measurement (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -217,112 +347,33 @@ def main():
     sc, cams = wl.scene, wl.cameras
     log(f"[bench] workload {args.workload}: n={sc.n} view {cams[0].width}x{cams[0].height} "
         f"(inputs built in {time.time() - t0:.1f}s)")
-    params = [torch.tensor(np.asarray(getattr(sc, k), np.float32), device=dev)
-              for k in ("means", "log_scales", "quats", "opacities", "sh")]
-    w2c = torch.tensor(np.asarray(cams[0].world_to_cam, np.float32)[None], device=dev)
-    bg = (0.0, 0.0, 0.0)
-    rast = GaussianRasterizer(cams, sc.sh_degree, tile_h=args.tile_h, persistent=args.persistent, device=dev)
+    m = measure_view(wl, args.steps, args.warmup, args.tile_h, args.persistent, not args.no_graph)
+    ms_plain, ms_instrumented, stage_ms, stats = m["ms_plain"], m["ms_instrumented"], m["stage_ms"], m["stats"]
+    graph_ms, graph_err = m["graph_ms"], m["graph_err"]
 
-    # target image (untimed)
-    if wl.target_cameras is not None:
-        tw2c = torch.tensor(np.asarray(wl.target_cameras[0].world_to_cam, np.float32)[None], device=dev)
-        target, _ = rast.forward(params, tw2c, bg)
-    else:
-        tparams = list(params)
-        tparams[0] = torch.tensor(np.asarray(wl.target_scene.means, np.float32), device=dev)
-        target, _ = rast.forward(tparams, w2c, bg)
-    target = target.clone()
-    numel = target.numel()
-
-    def step(ws=None, out=None):
-        rgb, ws = rast.forward(params, w2c, bg, ws=ws, out=out)
-        diff = rgb - target
-        grad = torch.sign(diff) / numel  # d/d img of mean |img - target|
-        grads, g_w2c, g_tw = rast.backward(ws, params, w2c, bg, rgb, grad)
-        return rgb, ws, grads, g_tw
-
-    # ---- plain form: synchronous capacity check, one view per launch sequence
-    for _ in range(args.warmup):
-        _, ws, _, _ = step()
-    rast.stats = True  # one instrumented step for the work counters, outside the timed region
-    _, ws, _, _ = step()
-    rast.stats = False
-    torch.cuda.synchronize()
-    stats = gsr.query_stats(ws)
-    log(f"[bench] stats {stats}")
-    # timed region: plain steps, nothing else on the stream
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record()
-    for _ in range(args.steps):
-        step()
-    end.record()
-    torch.cuda.synchronize()
-    ms_plain = start.elapsed_time(end) / args.steps
-    log(f"[bench] plain: {ms_plain:.3f} ms/step")
-
-    # the same steps again with HIP events recorded by the library between its
-    # stages, on the stream the kernels run on (per-stage and per-kernel times)
-    stage_ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2 * len(gsr.STAGES))]
-                for _ in range(args.steps)]
-    for evs in stage_ev:
-        for e in evs:
-            e.record()  # creates the underlying HIP events
-    torch.cuda.synchronize()
-    handles = [(gsr.C.c_void_p * (2 * len(gsr.STAGES)))(*[e.cuda_event for e in evs]) for evs in stage_ev]
-    torch.cuda.synchronize()
-    start.record()
-    for k in range(args.steps):
-        rast.cfg.stage_events = gsr.C.cast(handles[k], gsr.C.c_void_p)
-        step()
-    end.record()
-    torch.cuda.synchronize()
-    rast.cfg.stage_events = None
-    ms_instrumented = start.elapsed_time(end) / args.steps
-    stage_ms = {}
-    for s, name in enumerate(gsr.STAGES):
-        vals = [evs[2 * s].elapsed_time(evs[2 * s + 1]) for evs in stage_ev]
-        stage_ms[name] = float(np.mean(vals))
-    log(f"[bench] with stage events: {ms_instrumented:.3f} ms/step; stages "
-        + ", ".join(f"{k} {v:.3f}" for k, v in stage_ms.items()))
-
-    # ---- graph form: the same step, no host synchronisation, replayed
-    graph_ms = None
-    graph_err = None
-    if not args.no_graph:
-        try:
-            grast = GaussianRasterizer(cams, sc.sh_degree, tile_h=args.tile_h, persistent=args.persistent, sync=False,
-                                       device=dev)
-            grast.capacity = int(stats["pairs"] * 1.3) + 4096
-            gws = grast.workspace(sc.n)
-            gout = torch.empty_like(target)
-            s = torch.cuda.Stream()
-            s.wait_stream(torch.cuda.current_stream())
-            with torch.cuda.stream(s):
-                for _ in range(3):
-                    rgb, _ = grast.forward(params, w2c, bg, ws=gws, out=gout)
-                    gr, _, _ = grast.backward(gws, params, w2c, bg, rgb, torch.sign(rgb - target) / numel)
-            torch.cuda.current_stream().wait_stream(s)
-            torch.cuda.synchronize()
-            assert not grast.check_overflow(gws)
-            graph = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(graph):
-                rgb, _ = grast.forward(params, w2c, bg, ws=gws, out=gout)
-                gr, _, _ = grast.backward(gws, params, w2c, bg, rgb, torch.sign(rgb - target) / numel)
-            for _ in range(args.warmup):
-                graph.replay()
-            torch.cuda.synchronize()
-            start.record()
-            for _ in range(args.steps):
-                graph.replay()
-            end.record()
-            torch.cuda.synchronize()
-            graph_ms = start.elapsed_time(end) / args.steps
-            assert not grast.check_overflow(gws)
-            log(f"[bench] graph: {graph_ms:.3f} ms/step")
-        except Exception as e:  # reported, never hidden
-            graph_err = repr(e)
-            log(f"[bench] graph form failed: {graph_err}")
+    # ---- the other single-view workloads: small view, 200k at 1080p, the level-of-detail cut
+    others = None
+    if not args.no_other_workloads:
+        others = {}
+        for name in OTHER_WORKLOADS:
+            if name == args.workload:
+                continue
+            t0 = time.time()
+            owl, odesc = make_workload(name)
+            log(f"[bench] workload {name}: n={owl.scene.n} (inputs built in {time.time() - t0:.1f}s)")
+            om = measure_view(owl, max(10, args.steps // 2), max(3, args.warmup // 2), args.tile_h,
+                              args.persistent, not args.no_graph)
+            others[name] = {"workload": odesc, "n_gaussians": owl.scene.n,
+                            "resolution": f"{owl.cameras[0].width}x{owl.cameras[0].height}",
+                            "plain_iters_per_s": round(1000.0 / om["ms_plain"], 3),
+                            "plain_ms_per_step": round(om["ms_plain"], 4),
+                            "graph_iters_per_s": round(1000.0 / om["graph_ms"], 3) if om["graph_ms"] else None,
+                            "graph_ms_per_step": round(om["graph_ms"], 4) if om["graph_ms"] else None,
+                            "graph_error": om["graph_err"],
+                            "stage_ms": {k: round(v, 4) for k, v in om["stage_ms"].items()},
+                            "work": om["stats"], "meta": owl.meta, "_wl": owl}
+            del om
+            torch.cuda.empty_cache()
 
     # ---- batched views: the 8-camera ring, plain vs autotuned + graph
     ring = None
@@ -353,15 +404,27 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import oracle as O
-        rng = np.random.default_rng(0)
-        g = np.sign(rng.standard_normal((cams[0].height, cams[0].width, 3))) / numel  # L1-shaped upstream
-        t = time.time()
-        O.render(sc, cams[0], bg=bg, dL_dimg=g)
-        tfb = time.time() - t
+
+        def oracle_iteration(scene, cam):
+            rng = np.random.default_rng(0)
+            shape = (cam.height, cam.width, 3)
+            g = np.sign(rng.standard_normal(shape)) / float(np.prod(shape))  # L1-shaped upstream
+            t = time.time()
+            O.render(scene, cam, bg=(0.0, 0.0, 0.0), dL_dimg=g)
+            return time.time() - t
+
+        tfb = oracle_iteration(sc, cams[0])
         cpu = {"value": round(1.0 / tfb, 5), "unit": "iters/s", "cores": 1, "kind": "oracle",
                "sample": f"one full fwd+bwd iteration of the same view and scene ({tfb:.1f} s), "
                          "single-threaded C, FP64"}
         log(f"[bench] oracle fwd+bwd {tfb:.1f}s")
+        if others:
+            cpu["other_workloads_s_per_iter"] = {}
+            for name, o in others.items():
+                t_o = oracle_iteration(o["_wl"].scene, o["_wl"].cameras[0])
+                cpu["other_workloads_s_per_iter"][name] = round(t_o, 4)
+                o["oracle_s_per_iter"] = round(t_o, 4)
+                log(f"[bench] oracle {name} fwd+bwd {t_o:.2f}s")
 
     out = {
         "metric": "fwd+bwd raster iters/s @1080p, 1M Gaussians; p50/p99 request latency",
@@ -387,6 +450,8 @@ def main():
         "work": stats,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "other_workloads": ({k: {a: b for a, b in v.items() if a != "_wl"} for k, v in others.items()}
+                            if others else None),
         "batched_views": ring,
         "serving": served,
     }

@@ -69,10 +69,13 @@ def _spread_bits(v: np.ndarray) -> np.ndarray:
 
 
 def morton_codes(points: np.ndarray) -> np.ndarray:
-    """63-bit Morton codes of points quantised to 2^21 cells per axis of their bounding box."""
+    """63-bit Morton codes of points quantised to 2^21 cubic cells along the
+    longest side of their bounding box (cubic, so that a run of 8 codes is a
+    compact cell whatever the box's aspect ratio)."""
     p = np.asarray(points, np.float64)
     lo, hi = p.min(0), p.max(0)
-    q = np.floor((p - lo) / np.maximum(hi - lo, 1e-30) * (2 ** 21 - 1) + 0.5).astype(np.int64)
+    ext = max(float((hi - lo).max()), 1e-30)
+    q = np.floor((p - lo) / ext * (2 ** 21 - 1) + 0.5).astype(np.int64)
     return _spread_bits(q[:, 0]) | (_spread_bits(q[:, 1]) << np.uint64(1)) | (_spread_bits(q[:, 2]) << np.uint64(2))
 
 
@@ -97,19 +100,20 @@ def rotation_to_quat(r: np.ndarray) -> np.ndarray:
     sq = np.stack([1 + tr, 1 + 2 * r[:, 0, 0] - tr, 1 + 2 * r[:, 1, 1] - tr, 1 + 2 * r[:, 2, 2] - tr], 1)
     k = np.argmax(sq, axis=1)
     s = np.sqrt(np.maximum(sq[np.arange(len(r)), k], 1e-300))  # = 2 |component k|
+    d = 2.0 * s  # the other components are (sums or differences of entries) / (4 |component k|)
     q = np.empty((len(r), 4))
     m = k == 0
-    q[m] = np.stack([s[m] / 4, (r[m, 2, 1] - r[m, 1, 2]) / s[m], (r[m, 0, 2] - r[m, 2, 0]) / s[m],
-                     (r[m, 1, 0] - r[m, 0, 1]) / s[m]], 1)
+    q[m] = np.stack([s[m] / 2, (r[m, 2, 1] - r[m, 1, 2]) / d[m], (r[m, 0, 2] - r[m, 2, 0]) / d[m],
+                     (r[m, 1, 0] - r[m, 0, 1]) / d[m]], 1)
     m = k == 1
-    q[m] = np.stack([(r[m, 2, 1] - r[m, 1, 2]) / s[m], s[m] / 4, (r[m, 0, 1] + r[m, 1, 0]) / s[m],
-                     (r[m, 0, 2] + r[m, 2, 0]) / s[m]], 1)
+    q[m] = np.stack([(r[m, 2, 1] - r[m, 1, 2]) / d[m], s[m] / 2, (r[m, 0, 1] + r[m, 1, 0]) / d[m],
+                     (r[m, 0, 2] + r[m, 2, 0]) / d[m]], 1)
     m = k == 2
-    q[m] = np.stack([(r[m, 0, 2] - r[m, 2, 0]) / s[m], (r[m, 0, 1] + r[m, 1, 0]) / s[m], s[m] / 4,
-                     (r[m, 1, 2] + r[m, 2, 1]) / s[m]], 1)
+    q[m] = np.stack([(r[m, 0, 2] - r[m, 2, 0]) / d[m], (r[m, 0, 1] + r[m, 1, 0]) / d[m], s[m] / 2,
+                     (r[m, 1, 2] + r[m, 2, 1]) / d[m]], 1)
     m = k == 3
-    q[m] = np.stack([(r[m, 1, 0] - r[m, 0, 1]) / s[m], (r[m, 0, 2] + r[m, 2, 0]) / s[m],
-                     (r[m, 1, 2] + r[m, 2, 1]) / s[m], s[m] / 4], 1)
+    q[m] = np.stack([(r[m, 1, 0] - r[m, 0, 1]) / d[m], (r[m, 0, 2] + r[m, 2, 0]) / d[m],
+                     (r[m, 1, 2] + r[m, 2, 1]) / d[m], s[m] / 2], 1)
     q *= np.where(q[:, :1] < 0, -1.0, 1.0)
     return q / np.linalg.norm(q, axis=1, keepdims=True)
 
@@ -213,10 +217,11 @@ def select_cut(h: Hierarchy, cam: Camera, tau: float = 1.5) -> np.ndarray:
 
 def lod_workload(seed=4, n_leaves=4_000_000, levels=7, tau=1.5):
     """The hierarchical level-of-detail workload: a 7-level, branching-8
-    hierarchy over 4M slab leaves and its 1.5 px cut for one 1920x1080 view.
-    The Workload's scene is the cut; meta holds its size and per-level counts."""
-    from .scenes import Workload, slab_leaves
-    leaves, cam, target = slab_leaves(seed, n_leaves)
+    hierarchy over 4M leaves along a 2 km street and its 1.5 px cut for one
+    1920x1080 view down the street.  The Workload's scene is the cut; meta
+    holds its size and per-level counts."""
+    from .scenes import Workload, street_leaves
+    leaves, cam, target = street_leaves(seed, n_leaves)
     h = build(leaves, levels)
     cut = select_cut(h, cam, tau)
     per_level = np.bincount(h.level_of(cut), minlength=h.levels)

@@ -253,20 +253,23 @@ def random_upstream(seed, shape) -> np.ndarray:
     return _rng(seed).standard_normal(shape).astype(np.float32)
 
 
-def slab_leaves(seed=4, n=4_000_000, half=100.0, height=10.0, eye_height=2.0):
-    """Leaf Gaussians of the hierarchical level-of-detail workload: centres
-    uniform in a 200 m x 200 m x 10 m slab (x, y in [-100, 100], z in [0, 10]),
-    the box scene's other distributions (log-scales ~ N(-3, 0.5), SH degree 3);
-    one 1920x1080 camera at (0, 0, 2) looking horizontally at a seeded azimuth
-    (up = +z), and the target pose perturbed by 0.5 degrees and 2 cm.
+def street_leaves(seed=4, n=4_000_000, length=2000.0, width=20.0, height=10.0, eye_height=2.0,
+                  max_heading_deg=10.0):
+    """Leaf Gaussians of the hierarchical level-of-detail workload: a 2 km street
+    (x in [0, 2000], y in [-10, 10], z in [0, 10] metres) with centres uniform
+    in it and the box scene's other distributions (log-scales ~ N(-3, 0.5),
+    SH degree 3); one 1920x1080 camera at the start of the street, (-1, 0, 2),
+    looking down it at a seeded heading within +-10 degrees (up = +z); the
+    target pose is perturbed by 0.5 degrees and 2 cm.
     Returns (leaves, camera, target camera)."""
     rng = _rng(seed)
     means = np.empty((n, 3))
-    means[:, :2] = rng.uniform(-half, half, (n, 2))
+    means[:, 0] = rng.uniform(0.0, length, n)
+    means[:, 1] = rng.uniform(-width / 2, width / 2, n)
     means[:, 2] = rng.uniform(0.0, height, n)
     leaves = _gaussian_body(rng, means, 3)
-    az = rng.uniform(0.0, 2 * np.pi)
-    eye = np.array([0.0, 0.0, eye_height])
+    az = np.deg2rad(rng.uniform(-max_heading_deg, max_heading_deg))
+    eye = np.array([-1.0, 0.0, eye_height])
     cam = pinhole(1920, 1080, look_at(eye, eye + np.array([np.cos(az), np.sin(az), 0.0])))
     target = cam.copy_with_pose(perturbed_pose(cam.world_to_cam, seed + 1000))
     return leaves, cam, target

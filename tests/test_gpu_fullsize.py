@@ -58,3 +58,10 @@ def test_headline_1080p_1M_sampled_parity():
 
 def test_single_view_1080p_200k_sampled_parity():
     _sampled_parity(S.single_view_1080p(), n_tiles=24, seed=102, bg=(0.1, 0.1, 0.1))
+
+
+def test_lod_cut_1080p_sampled_parity():
+    from paper_2607_14481_amd import hierarchy
+    wl = hierarchy.lod_workload()
+    log(f"lod cut: {wl.meta}")
+    _sampled_parity(wl, n_tiles=24, seed=103)
