@@ -85,6 +85,7 @@ gsr::WsLayout make_layout(uint64_t n, const gsr::ViewTable &vt, uint64_t cap) {
     const uint64_t items = n * (uint64_t)vt.n_views;
     L.items = items;
     L.cap = cap;
+    L.chunks = chunk_count(cap);
     const uint64_t hb_items = (items + kSortTile - 1) / kSortTile;
     const uint64_t hb_pairs = (cap + kSortTile - 1) / kSortTile;
     L.hist_blocks = (uint32_t)std::max<uint64_t>(1, std::max(hb_items, hb_pairs));
@@ -108,7 +109,8 @@ gsr::WsLayout make_layout(uint64_t n, const gsr::ViewTable &vt, uint64_t cap) {
     L.cval[1] = take(4 * items);
     L.poff = take(4 * items);
     L.rank = take(4 * items);
-    L.big_list = take(4 * items);
+    L.chunk_item = take(4 * (L.chunks + 1));
+    L.carry = take(4ull * 2 * kPartialStride * L.chunks);
     L.screen = take(48 * items);
     L.pkey[0] = take(4 * cap);
     L.pkey[1] = take(4 * cap);
@@ -146,9 +148,10 @@ struct Ptrs {
     gsr::WsHeader *hdr;
     gsr::Rec *rec;
     float2 *ulo;
-    uint32_t *zkey, *count, *scan_tmp, *ckey[2], *cval[2], *poff, *rank, *big_list, *pkey[2], *pval[2], *hist,
+    uint32_t *zkey, *count, *scan_tmp, *ckey[2], *cval[2], *poff, *rank, *chunk_item, *pkey[2], *pval[2], *hist,
         *digit_total;
     float4 *screen;
+    float *carry;
     uint2 *ranges, *tile_cut;
     float *pix_T;
     uint32_t *pix_n;
@@ -172,7 +175,8 @@ Ptrs carve(void *ws, const gsr::WsLayout &L) {
     }
     p.poff = reinterpret_cast<uint32_t *>(b + L.poff);
     p.rank = reinterpret_cast<uint32_t *>(b + L.rank);
-    p.big_list = reinterpret_cast<uint32_t *>(b + L.big_list);
+    p.chunk_item = reinterpret_cast<uint32_t *>(b + L.chunk_item);
+    p.carry = reinterpret_cast<float *>(b + L.carry);
     p.screen = reinterpret_cast<float4 *>(b + L.screen);
     p.tile_cut = reinterpret_cast<uint2 *>(b + L.tile_cut);
     p.hist = reinterpret_cast<uint32_t *>(b + L.hist);
@@ -188,27 +192,13 @@ Ptrs carve(void *ws, const gsr::WsLayout &L) {
 // Caller-fixed workgroup count for persistent launches (0: as many as fit).
 int persistent_ctas(const gsr_launch_config *cfg) { return cfg && cfg->persistent_ctas > 0 ? cfg->persistent_ctas : 0; }
 
-// Workgroups for the large-item pair reduction: a few per compute unit.
-int big_item_ctas() {
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0, c = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && c > 0)
-            cus = c;
-        else
-            cus = 256;
-    }
-    return cus * 4;
-}
-
 // The pair capacity is whatever the workspace holds beyond the fixed regions;
 // forward, backward and introspection all derive it the same way.
 int layout_from_bytes(uint64_t n, const gsr::ViewTable &vt, size_t ws_bytes, gsr::WsLayout &L, uint64_t &cap) {
     const gsr::WsLayout L0 = make_layout(n, vt, 1);
     if (ws_bytes < L0.total) return fail(GSR_ERR_WORKSPACE_TOO_SMALL, "workspace %zu < %zu bytes", ws_bytes, L0.total);
     // largest capacity whose layout fits (the layout size grows with it);
-    // per pair the workspace holds 4 key/value words and 9 gradient floats
+    // per pair the workspace holds 4 key/value words and 9 moment floats
     uint64_t lo = 1, hi = (ws_bytes - L0.total) / (16 + 4 * gsr::kPartialStride) + 2;
     if (hi > 0x7ffffffeull) hi = 0x7ffffffeull;
     while (lo < hi) {
@@ -309,7 +299,7 @@ int gsr_rasterize_forward(void *ws, size_t ws_bytes, const gsr_gaussians *g, int
     mark.end(GSR_STAGE_DEPTH_SORT);
     const uint32_t *sorted_items = p.cval[cur];
     mark.begin(GSR_STAGE_EMIT);
-    launch_pair_offsets(sorted_items, p.count, L.items, p.poff, p.scan_tmp, p.hdr, st);
+    launch_pair_offsets(sorted_items, p.count, L.items, p.poff, p.chunk_item, L.chunks, p.scan_tmp, p.hdr, st);
     uint64_t pair_grid = cap;
     if (flags & GSR_FLAG_SYNC) {
         WsHeader h;
@@ -319,7 +309,8 @@ int gsr_rasterize_forward(void *ws, size_t ws_bytes, const gsr_gaussians *g, int
             return fail(GSR_ERR_CAPACITY, "needs %u pairs, workspace holds %llu", h.n_pairs, (unsigned long long)cap);
         pair_grid = h.n_pairs;
     }
-    launch_emit_pairs(vt, sorted_items, p.poff, n, L.items, p.rec, p.rank, p.pkey[0], p.pval[0], p.hdr, st);
+    launch_emit_pairs(vt, sorted_items, p.poff, p.chunk_item, n, pair_grid, p.rec, p.rank, p.pkey[0], p.pval[0],
+                      p.hdr, st);
     mark.end(GSR_STAGE_EMIT);
     mark.begin(GSR_STAGE_TILE_SORT);
     int pc = 0;
@@ -370,10 +361,10 @@ int gsr_rasterize_backward(void *ws, size_t ws_bytes, const gsr_gaussians *g, in
     mark.end(GSR_STAGE_COMPOSITE_BWD);
     mark.begin(GSR_STAGE_PROJECT_BWD);
     // the depth sort's result buffer: four 8-bit passes end where they started
-    launch_pair_reduce(vt, p.cval[0], p.poff, (uint64_t)g->n, L.items, p.rec, p.tile_cut, p.partial, p.screen,
-                       p.big_list, p.hdr, big_item_ctas(), st);
-    launch_project_bwd(*g, vt, world_to_cam, (uint64_t)g->n, p.rec, p.count, p.hdr, p.screen, *grads, p.pose_part,
-                       L.pose_blocks, st);
+    launch_pair_reduce(vt, p.cval[0], p.poff, p.chunk_item, (uint64_t)g->n, cap, p.rec, p.tile_cut, p.partial,
+                       p.screen, p.carry, p.hdr, st);
+    launch_project_bwd(*g, vt, world_to_cam, (uint64_t)g->n, p.rec, p.count, p.hdr, p.screen, p.carry, *grads,
+                       p.pose_part, L.pose_blocks, st);
     if (g->n == 0)  // no Gaussian wrote a partial: the pose gradient is zero
         launch_fill_u32(reinterpret_cast<uint32_t *>(p.pose_part), 0u, 12ull * vt.n_views * L.pose_blocks, st);
     launch_pose_finalize(vt, world_to_cam, p.pose_part, L.pose_blocks, dL_dworld_to_cam, dL_dtwist, st);

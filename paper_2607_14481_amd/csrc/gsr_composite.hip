@@ -23,11 +23,16 @@
 // from the forward's output C_out and the running accumulation, the colour
 // behind contributor k is B_k = C_out - sum_{j<=k} c_j a_j T_j; only its
 // projection on the upstream gradient g is needed, g.B_k = g.C_out - sum.
-// Each lane sums its pixels' contributions in registers.  The wave-wide sum of
-// the nine screen-space components is a transpose through LDS: for a group of
-// four Gaussians each lane writes its 36 partial values, then lane r < 36 adds
-// the 64 values of component r in a fixed order (no atomics, deterministic)
-// and the pair's slot in emission order is written once.
+// Per pair the kernel produces nine moments over the tile's pixels: with
+// w = dL/dsigma, the sums of w dx, w dy, w dx^2, w dx dy, w dy^2, of
+// alpha dL/dalpha and of the colour gradient; they are linear in the per-pixel
+// terms, so the conversion to (u, v, conic, opacity) gradients happens once
+// per Gaussian after the reduction over its tiles.  Each lane sums its pixels'
+// terms in registers; neighbouring lanes are added with a DPP swap, and the
+// 32 lane-pair sums are transposed through LDS in groups of seven Gaussians
+// (63 values per row), after which lane r < 63 adds the 32 values of one
+// (Gaussian, moment) in a fixed order (no atomics, deterministic) and the
+// pair's slot in emission order is written once.
 #include "gsr_internal.h"
 
 namespace gsr {
@@ -239,9 +244,10 @@ __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uin
 // ---------------------------------------------------------------------------
 // A7: backward
 // ---------------------------------------------------------------------------
-constexpr int kGroup = 4;                          // Gaussians per LDS transpose
-constexpr int kRedCols = kGroup * kPartialStride;  // 36 values per lane
-constexpr int kRedStride = kRedCols + 1;           // padded row: conflict-free
+constexpr int kGroup = 7;                          // Gaussians per LDS transpose
+constexpr int kRedCols = kGroup * kPartialStride;  // 63 values per row
+constexpr int kRedRows = kWave / 2;                // lane pairs are summed first
+constexpr int kRedStride = kRedCols + 2;           // odd row stride: conflict-free rows and columns
 
 template <int RPL>
 __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uint2 *__restrict__ ranges,
@@ -253,10 +259,12 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
                                                          const uint2 *__restrict__ tile_cut,
                                                          float *__restrict__ partial, WsHeader *hdr, int persistent) {
     __shared__ float4 sa[kWave], sb[kWave], sd[kWave];
-    __shared__ float red[kWave * kRedStride];
+    __shared__ float red[kRedRows * kRedStride];
     const int lane = threadIdx.x;
     const int lx = lane & 15, ly = lane >> 4;
     const float pxl = (float)lx + 0.5f;
+    // the (Gaussian of the group, moment) this lane finalises
+    const int fq = lane / kPartialStride, fc = lane - fq * kPartialStride;
     uint32_t iter = 0;
     for (;;) {
         const uint32_t t = next_tile(persistent != 0, &hdr->queue[1], blockIdx.x, iter);
@@ -303,7 +311,7 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
 #pragma unroll
                 for (int q = 0; q < kGroup; ++q) {
                     const int j = j0 + q;
-                    // Swx Swy Sxx Sxy Syy (moments of dL/dsigma), So, dL/drgb
+                    // S_x S_y S_xx S_xy S_yy (moments of dL/dsigma), S_o, colour gradient
                     float s[kPartialStride] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
                     if (j < cnt) {
                         const uint32_t pos = b0 - rg.x + (uint32_t)j;
@@ -327,7 +335,7 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
                             const float dalpha =
                                 fmaf(T[k], grgb, -(gout[k] - gacc[k]) * __builtin_amdgcn_rcpf(one_m));
                             T[k] = ok ? T[k] * one_m : T[k];
-                            // dL/dsigma = -sa, dL/do = sa / o (zero through the 0.99 clamp)
+                            // dL/dsigma = -sa, alpha dL/dalpha = sa (zero through the 0.99 clamp)
                             const float sa_ = (ok && araw < kAlphaMax) ? dalpha * alpha : 0.f;
                             s[5] += sa_;
                             const float wx = -sa_ * dx, wy = -sa_ * dy;
@@ -338,42 +346,27 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
                             s[4] = fmaf(wy, dy, s[4]);
                         }
                     }
+                    // add the neighbouring lane (quad_perm [1, 0, 3, 2]); even lanes store the pair sum
 #pragma unroll
-                    for (int cc = 0; cc < kPartialStride; ++cc)
-                        red[lane * kRedStride + q * kPartialStride + cc] = s[cc];
+                    for (int cc = 0; cc < kPartialStride; ++cc) s[cc] = dpp_add<0xB1, 0xf>(s[cc]);
+                    if ((lane & 1) == 0) {
+#pragma unroll
+                        for (int cc = 0; cc < kPartialStride; ++cc)
+                            red[(lane >> 1) * kRedStride + q * kPartialStride + cc] = s[cc];
+                    }
                 }
                 __syncthreads();
-                // lane r < 36 sums component r % 9 of Gaussian j0 + r / 9 over the 64 lanes
-                float tot = 0.f;
-                if (lane < kRedCols) {
+                if (lane < kRedCols && j0 + fq < cnt) {
                     float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
-#pragma unroll 4
-                    for (int l = 0; l < kWave; l += 4) {
-                        p0 += red[(l + 0) * kRedStride + lane];
-                        p1 += red[(l + 1) * kRedStride + lane];
-                        p2 += red[(l + 2) * kRedStride + lane];
-                        p3 += red[(l + 3) * kRedStride + lane];
+#pragma unroll
+                    for (int r = 0; r < kRedRows; r += 4) {
+                        p0 += red[(r + 0) * kRedStride + lane];
+                        p1 += red[(r + 1) * kRedStride + lane];
+                        p2 += red[(r + 2) * kRedStride + lane];
+                        p3 += red[(r + 3) * kRedStride + lane];
                     }
-                    tot = (p0 + p1) + (p2 + p3);
-                }
-                // moments -> screen-space gradient of (u, v, A, B, C, o, r, g, b)
-                const int q = lane / kPartialStride, cc = lane - q * kPartialStride;
-                const float nb1 = __shfl_down(tot, 1, kWave);  // Swy, read by the Swx lane
-                const float nb0 = __shfl_up(tot, 1, kWave);    // Swx, read by the Swy lane
-                const int j = j0 + q;
-                if (lane < kRedCols && j < cnt) {
-                    const float4 a = sa[j], b = sb[j], d = sd[j];
-                    const float A = -2.f * a.z / kLog2e, B = -a.w / kLog2e, Cc = -2.f * b.x / kLog2e;
-                    float outv;
-                    switch (cc) {
-                        case 0: outv = A * tot + B * nb1; break;
-                        case 1: outv = Cc * tot + B * nb0; break;
-                        case 2: outv = 0.5f * tot; break;
-                        case 4: outv = 0.5f * tot; break;
-                        case 5: outv = tot / d.w; break;
-                        default: outv = tot; break;
-                    }
-                    partial[(size_t)__float_as_uint(d.z) * kPartialStride + cc] = outv;
+                    const uint32_t p = __float_as_uint(sd[j0 + fq].z);
+                    partial[(size_t)p * kPartialStride + fc] = (p0 + p1) + (p2 + p3);
                 }
                 __syncthreads();
             }

@@ -44,8 +44,7 @@ struct WsHeader {
     unsigned long long replays;       // sum over pixels of n_contrib
     unsigned long long contributors;  // sum over pixels of Gaussians composited
     uint32_t queue[4];       // persistent-launch work counters
-    uint32_t n_big;          // items listed for the workgroup-wide pair reduction
-    uint32_t pad[49];
+    uint32_t pad[50];
 };
 static_assert(sizeof(WsHeader) == 256, "header is 256 bytes");
 
@@ -72,8 +71,9 @@ struct WsLayout {
     size_t cval[2];     // u32[items] depth sort ping-pong values (item ids)
     size_t poff;        // u32[items] pair offset, in depth order
     size_t rank;        // u32[items] depth rank of each visible item
-    size_t big_list;    // u32[items] depth ranks of items reduced by a whole workgroup
-    size_t screen;      // float4[items * 3] per-item screen-space gradient
+    size_t chunk_item;  // u32[chunks + 1] depth rank of the item holding each chunk's first pair
+    size_t carry;       // float[chunks * 2 * 9] chunk-boundary partial sums of the pair moments
+    size_t screen;      // float4[items * 3] per-item sums of the pair moments
     size_t pkey[2];     // u32[cap] tile keys ping-pong
     size_t pval[2];     // u32[cap] item ids ping-pong
     size_t hist;        // u32[256 * max_blocks] radix histograms
@@ -82,10 +82,10 @@ struct WsLayout {
     size_t tile_cut;    // uint2[total_tiles] (positions replayed, depth rank cut)
     size_t pix_T;       // float[total_pixels] final transmittance
     size_t pix_n;       // u32[total_pixels] last contributor + 1
-    size_t partial;     // float[cap * 9] per-pair screen-space gradients
+    size_t partial;     // float[cap * 9] per-pair moments of the pixel gradients
     size_t pose_part;   // float[views * pose_blocks * 12]
     size_t total;
-    uint64_t items, cap;
+    uint64_t items, cap, chunks;
     uint32_t hist_blocks, pose_blocks;
 };
 
@@ -97,6 +97,12 @@ constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;     // 4096
 constexpr int kProjThreads = 256;
 constexpr int kPartialStride = 9;                         // floats per pair gradient
+// Pairs are also processed in fixed chunks of consecutive emission-order
+// slots (A3 emission, A8 reduction): 256 threads x 4 pairs.
+constexpr uint32_t kChunkPairs = 1024;
+constexpr uint32_t kChunkThreads = 256;
+constexpr uint32_t kChunkPerThread = kChunkPairs / kChunkThreads;
+__host__ __device__ constexpr uint64_t chunk_count(uint64_t pairs) { return (pairs + kChunkPairs - 1) / kChunkPairs; }
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (defined in the .hip files).  All enqueue on `st`.
@@ -126,10 +132,11 @@ void radix_sort_u32(uint32_t *keys[2], uint32_t *vals[2], SortCount sc, uint64_t
                     uint32_t *hist, uint32_t hist_blocks, uint32_t *digit_total, int &cur, hipStream_t st);
 void launch_reset_queue(WsHeader *h, int which, hipStream_t st);
 void launch_pair_offsets(const uint32_t *sorted_items, const uint32_t *count, uint64_t items_cap,
-                         uint32_t *poff, uint32_t *block_tmp, WsHeader *hdr, hipStream_t st);
-void launch_emit_pairs(const ViewTable &vt, const uint32_t *sorted_items, const uint32_t *poff, uint64_t n,
-                       uint64_t items_cap, Rec *rec, uint32_t *rank, uint32_t *pkey, uint32_t *pval,
-                       const WsHeader *hdr, hipStream_t st);
+                         uint32_t *poff, uint32_t *chunk_item, uint64_t chunks_cap, uint32_t *block_tmp,
+                         WsHeader *hdr, hipStream_t st);
+void launch_emit_pairs(const ViewTable &vt, const uint32_t *sorted_items, const uint32_t *poff,
+                       const uint32_t *chunk_item, uint64_t n, uint64_t pair_grid, Rec *rec, uint32_t *rank,
+                       uint32_t *pkey, uint32_t *pval, const WsHeader *hdr, hipStream_t st);
 void launch_tile_ranges(const uint32_t *pkey, uint64_t cap, uint2 *ranges, uint32_t total_tiles,
                         const WsHeader *hdr, hipStream_t st);
 
@@ -141,13 +148,15 @@ void launch_composite_bwd(const ViewTable &vt, const uint2 *ranges, const uint32
                           const float2 *ulo, const float *out_rgb, const float *dL_drgb, const uint32_t *pix_n,
                           const uint2 *tile_cut, float *partial, WsHeader *hdr, bool persistent,
                           int persistent_ctas, hipStream_t st);
-void launch_pair_reduce(const ViewTable &vt, const uint32_t *sorted_items, const uint32_t *poff, uint64_t n,
-                        uint64_t items_cap, const Rec *rec, const uint2 *tile_cut, const float *partial,
-                        float4 *screen, uint32_t *big_list, WsHeader *hdr, int big_ctas, hipStream_t st);
+void launch_pair_reduce(const ViewTable &vt, const uint32_t *sorted_items, const uint32_t *poff,
+                        const uint32_t *chunk_item, uint64_t n, uint64_t pair_grid, const Rec *rec,
+                        const uint2 *tile_cut, const float *partial, float4 *screen, float *carry,
+                        const WsHeader *hdr, hipStream_t st);
 
 void launch_project_bwd(const gsr_gaussians &g, const ViewTable &vt, const float *w2c, uint64_t n,
                         const Rec *rec, const uint32_t *count, const WsHeader *hdr, const float4 *screen,
-                        const gsr_gaussian_grads &gr, float *pose_part, uint32_t pose_blocks, hipStream_t st);
+                        const float *carry, const gsr_gaussian_grads &gr, float *pose_part, uint32_t pose_blocks,
+                        hipStream_t st);
 void launch_pose_finalize(const ViewTable &vt, const float *w2c, const float *pose_part, uint32_t pose_blocks,
                           float *dL_dw2c, float *dL_dtwist, hipStream_t st);
 
@@ -177,5 +186,74 @@ __device__ __forceinline__ float wave_sum(float v) {
 }
 
 __device__ __forceinline__ uint32_t pack_u16(uint32_t lo, uint32_t hi) { return lo | (hi << 16); }
+
+
+// ---------------------------------------------------------------------------
+// The items whose pairs fall in one chunk of emission-order slots.  Items own
+// contiguous pair ranges [poff[i], poff[i + 1]) in depth order, so a chunk
+// meets the depth ranks chunk_item[c] .. chunk_item[c + 1] (the last one only
+// if it starts before the chunk's end).  Each local item k gets its first pair,
+// the global id of its box's first tile, its box width in tiles (low 16 bits)
+// with its view's tiles per row (high 16 bits), and its item id; p0[nloc] is
+// the end of the last one.  Returns nloc.  Every thread of the workgroup calls it.
+// ---------------------------------------------------------------------------
+struct ChunkItems {
+    uint32_t p0[kChunkPairs + 2];
+    uint32_t tile0[kChunkPairs + 1];
+    uint32_t wx[kChunkPairs + 1];
+    uint32_t item[kChunkPairs + 1];
+};
+
+__device__ __forceinline__ uint32_t load_chunk_items(const ViewTable &vt, const uint32_t *__restrict__ sorted_items,
+                                                     const uint32_t *__restrict__ poff,
+                                                     const uint32_t *__restrict__ chunk_item, uint64_t n,
+                                                     const Rec *__restrict__ rec, uint32_t c, uint32_t m,
+                                                     uint32_t nvis, ChunkItems &ci, uint32_t &i_lo) {
+    const uint32_t c0 = c * kChunkPairs;
+    i_lo = chunk_item[c];
+    const uint32_t i_hi = c0 + kChunkPairs < m ? chunk_item[c + 1] : nvis - 1;
+    const uint32_t nloc = i_hi - i_lo + 1;
+    for (uint32_t k = threadIdx.x; k <= nloc; k += kChunkThreads) {
+        const uint32_t i = i_lo + k;
+        if (k == nloc) {
+            ci.p0[k] = i < nvis ? poff[i] : m;
+            continue;
+        }
+        const uint32_t item = sorted_items[i];
+        const float4 r2 = rec[item].r2;
+        const uint32_t bx = __float_as_uint(r2.y), by = __float_as_uint(r2.z);
+        const uint32_t tx0 = (bx & 0xffffu) / kTileW, tx1 = (bx >> 16) / kTileW;
+        const uint32_t ty0 = (by & 0xffffu) / (uint32_t)vt.tile_h;
+        const int v = (int)(item / n);
+        const uint32_t tiles_x = (uint32_t)vt.v[v].tiles_x;
+        ci.p0[k] = poff[i];
+        ci.tile0[k] = vt.v[v].tile_off + ty0 * tiles_x + tx0;
+        ci.wx[k] = (tx1 - tx0 + 1) | (tiles_x << 16);
+        ci.item[k] = item;
+    }
+    __syncthreads();
+    return nloc;
+}
+
+// largest local index k < nloc with p0[k] <= p (p0[0] <= p holds)
+__device__ __forceinline__ uint32_t find_chunk_item(const ChunkItems &ci, uint32_t nloc, uint32_t p) {
+    uint32_t lo = 0, hi = nloc - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (ci.p0[mid] <= p)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// global tile of pair p, which belongs to local item k
+__device__ __forceinline__ uint32_t pair_tile(const ChunkItems &ci, uint32_t k, uint32_t p) {
+    const uint32_t q = p - ci.p0[k];
+    const uint32_t w = ci.wx[k] & 0xffffu, tiles_x = ci.wx[k] >> 16;
+    const uint32_t row = q / w;
+    return ci.tile0[k] + row * tiles_x + (q - row * w);
+}
 
 }  // namespace gsr

@@ -265,163 +265,235 @@ void launch_project_fwd(const gsr_gaussians &g, const ViewTable &vt, const float
 }
 
 // ---------------------------------------------------------------------------
-// A8: per-item sum of the per-pair screen-space gradients, in a fixed order.
-// Items are visited in depth order (their pairs are contiguous in emission
-// order).  An item with at most kSmallItem pairs is summed by one lane, four
-// pairs per step so that the loads overlap.  Larger items (splats near the
-// camera can cover thousands of tiles, and they all sit at the front of the
-// depth order) are appended to a list and summed by a whole workgroup each in
-// k_pair_reduce_big, which spreads them over the chip.  Pairs whose tile
-// stopped before reaching the item (depth rank >= the tile's cut) were never
-// written by the backward compositing and are masked out; their loads are
-// issued anyway so that no load waits for the mask.
+// A8: per-item sums of the per-pair moments, in a fixed order.
+//
+// An item's pairs are contiguous in emission order, but their number ranges
+// from one to thousands (splats near the camera), so the work is split by
+// pairs, not by items: a workgroup takes one chunk of 1024 consecutive pair
+// slots, 4 per thread (nine float4 loads per thread, coalesced).  Pairs whose
+// tile stopped before reaching the item (depth rank >= the tile's cut) were
+// never written by the backward compositing and count as zero.
+//
+// Within the chunk a segmented inclusive scan over the threads (keys = local
+// item index, wave-level shuffles then a carry across the four waves) gives
+// each item's sum at the thread holding its last pair.  Items that lie wholly
+// in the chunk are written to `screen`; an item that starts before the chunk
+// leaves its part of this chunk in carry[c][0], one that ends after it in
+// carry[c][1], and A9 adds an item's parts from its first chunk to its last
+// in chunk order.  Every sum is a fixed function of the layout, so two runs
+// agree bit for bit.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kSmallItem = 32;
+constexpr uint32_t kNoKey = 0xffffffffu;
 
-struct PairSpan {
-    uint32_t p0;       // first pair (emission order)
-    uint32_t tile0;    // global tile id of the box's first tile
-    uint32_t w, cnt;   // box width in tiles, number of pairs
-    uint32_t tiles_x;  // tiles per row of the view
-};
-
-__device__ __forceinline__ PairSpan item_span(const ViewTable &vt, const Rec *__restrict__ rec, uint32_t item,
-                                              uint64_t n, uint32_t p0) {
-    const float4 r2 = rec[item].r2;
-    const uint32_t bx = __float_as_uint(r2.y), by = __float_as_uint(r2.z);
-    const uint32_t tx0 = (bx & 0xffffu) / kTileW, tx1 = (bx >> 16) / kTileW;
-    const uint32_t ty0 = (by & 0xffffu) / vt.tile_h, ty1 = (by >> 16) / vt.tile_h;
-    const int v = (int)(item / n);
-    PairSpan sp;
-    sp.tiles_x = (uint32_t)vt.v[v].tiles_x;
-    sp.tile0 = vt.v[v].tile_off + ty0 * sp.tiles_x + tx0;
-    sp.w = tx1 - tx0 + 1;
-    sp.cnt = sp.w * (ty1 - ty0 + 1);
-    sp.p0 = p0;
-    return sp;
-}
-
-// pair q of the span lies in tile row `row`, column `col` of the item's box
-__device__ __forceinline__ void add_pair(const PairSpan &sp, uint32_t q, uint32_t rank_i, uint32_t row, uint32_t col,
-                                         const uint2 *__restrict__ tile_cut, const float *__restrict__ partial,
-                                         float s[kPartialStride]) {
-    const bool valid = rank_i < tile_cut[sp.tile0 + row * sp.tiles_x + col].y;
-    const float *pp = partial + (size_t)(sp.p0 + q) * kPartialStride;
-    float x[kPartialStride];
-#pragma unroll
-    for (int c = 0; c < kPartialStride; ++c) x[c] = pp[c];
-#pragma unroll
-    for (int c = 0; c < kPartialStride; ++c) s[c] += valid ? x[c] : 0.f;
-}
-
-__device__ __forceinline__ void step_rc(uint32_t w, uint32_t &row, uint32_t &col) {
-    if (++col == w) col = 0, ++row;
-}
-
-__global__ __launch_bounds__(256) void k_pair_reduce(ViewTable vt, const uint32_t *__restrict__ sorted_items,
-                                                     const uint32_t *__restrict__ poff, uint64_t n,
-                                                     const Rec *__restrict__ rec, const uint2 *__restrict__ tile_cut,
-                                                     const float *__restrict__ partial, float4 *__restrict__ screen,
-                                                     uint32_t *__restrict__ big_list, WsHeader *__restrict__ hdr) {
-    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
-    if (hdr->overflow || i >= hdr->n_visible) return;
-    const uint32_t item = sorted_items[i];
-    const PairSpan sp = item_span(vt, rec, item, n, poff[i]);
-    if (sp.cnt > kSmallItem) {
-        big_list[atomicAdd(&hdr->n_big, 1u)] = i;  // list order is irrelevant to the sums
+__device__ __forceinline__ void write_item_sum(const ChunkItems &ci, uint32_t k, uint32_t c0, uint32_t cend,
+                                               uint32_t c, const float v[kPartialStride], float4 *__restrict__ screen,
+                                               float *__restrict__ carry) {
+    const bool before = ci.p0[k] < c0, after = ci.p0[k + 1] > cend;
+    if (!before && !after) {
+        float4 *o = screen + 3 * (size_t)ci.item[k];
+        o[0] = make_float4(v[0], v[1], v[2], v[3]);
+        o[1] = make_float4(v[4], v[5], v[6], v[7]);
+        o[2] = make_float4(v[8], 0.f, 0.f, 0.f);
         return;
     }
-    float s[kPartialStride] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    uint32_t row = 0, col = 0, q = 0;
-    for (; q + 4 <= sp.cnt; q += 4) {
-        uint32_t r[4], c[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            r[u] = row;
-            c[u] = col;
-            step_rc(sp.w, row, col);
+    for (int q = 0; q < 2; ++q) {
+        if (q == 0 ? before : after) {
+            float *o = carry + ((size_t)c * 2 + q) * kPartialStride;
+#pragma unroll
+            for (int j = 0; j < kPartialStride; ++j) o[j] = v[j];
         }
-        float acc[4][kPartialStride];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-#pragma unroll
-            for (int cc = 0; cc < kPartialStride; ++cc) acc[u][cc] = 0.f;
-            add_pair(sp, q + u, i, r[u], c[u], tile_cut, partial, acc[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int cc = 0; cc < kPartialStride; ++cc) s[cc] += acc[u][cc];
     }
-    for (; q < sp.cnt; ++q) {
-        add_pair(sp, q, i, row, col, tile_cut, partial, s);
-        step_rc(sp.w, row, col);
-    }
-    screen[3 * (size_t)item + 0] = make_float4(s[0], s[1], s[2], s[3]);
-    screen[3 * (size_t)item + 1] = make_float4(s[4], s[5], s[6], s[7]);
-    screen[3 * (size_t)item + 2] = make_float4(s[8], 0.f, 0.f, 0.f);
 }
 
-// One workgroup per listed large item (looping over the list): threads stride
-// over the item's pairs, then a fixed-shape tree combines them.
-__global__ __launch_bounds__(256) void k_pair_reduce_big(ViewTable vt, const uint32_t *__restrict__ sorted_items,
-                                                         const uint32_t *__restrict__ poff, uint64_t n,
-                                                         const Rec *__restrict__ rec,
-                                                         const uint2 *__restrict__ tile_cut,
-                                                         const float *__restrict__ partial,
-                                                         float4 *__restrict__ screen,
-                                                         const uint32_t *__restrict__ big_list,
-                                                         const WsHeader *__restrict__ hdr) {
-    __shared__ float red[4][kPartialStride];
+__global__ __launch_bounds__(kChunkThreads) void k_pair_reduce(ViewTable vt, const uint32_t *__restrict__ sorted_items,
+                                                               const uint32_t *__restrict__ poff,
+                                                               const uint32_t *__restrict__ chunk_item, uint64_t n,
+                                                               const Rec *__restrict__ rec,
+                                                               const uint2 *__restrict__ tile_cut,
+                                                               const float *__restrict__ partial,
+                                                               float4 *__restrict__ screen, float *__restrict__ carry,
+                                                               const WsHeader *__restrict__ hdr) {
+    __shared__ ChunkItems ci;
+    __shared__ uint32_t s_kf[kChunkThreads], s_kl[kChunkThreads];
+    __shared__ float s_wv[4][kPartialStride];
+    __shared__ uint32_t s_wf[4];
     if (hdr->overflow) return;
-    const uint32_t nbig = hdr->n_big;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (uint32_t b = blockIdx.x; b < nbig; b += gridDim.x) {
-        const uint32_t i = big_list[b];
-        const uint32_t item = sorted_items[i];
-        const PairSpan sp = item_span(vt, rec, item, n, poff[i]);
-        float s[kPartialStride] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-        uint32_t row = threadIdx.x / sp.w, col = threadIdx.x - row * sp.w;
-        const uint32_t drow = 256u / sp.w, dcol = 256u - drow * sp.w;
-        for (uint32_t q = threadIdx.x; q < sp.cnt; q += 256u) {
-            add_pair(sp, q, i, row, col, tile_cut, partial, s);
-            row += drow;
-            col += dcol;
-            if (col >= sp.w) col -= sp.w, ++row;
-        }
+    const uint32_t m = hdr->n_pairs, nvis = hdr->n_visible;
+    const uint32_t c = blockIdx.x, c0 = c * kChunkPairs;
+    if (c0 >= m) return;  // uniform per workgroup
+    const uint32_t cend = min(c0 + kChunkPairs, m);
+    uint32_t i_lo;
+    const uint32_t nloc = load_chunk_items(vt, sorted_items, poff, chunk_item, n, rec, c, m, nvis, ci, i_lo);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+
+    // ---- this thread's pairs: keys, cut mask, values
+    const uint32_t pb = c0 + (uint32_t)tid * kChunkPerThread;
+    uint32_t key[kChunkPerThread];
+    float x[kChunkPerThread][kPartialStride];
+    if (pb + kChunkPerThread <= cend) {
+        const float4 *src = reinterpret_cast<const float4 *>(partial + (size_t)pb * kPartialStride);
+        float4 f[9];
 #pragma unroll
-        for (int c = 0; c < kPartialStride; ++c) {
-            const float t = wave_sum(s[c]);
-            if (lane == 0) red[w][c] = t;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            float o[kPartialStride];
+        for (int j = 0; j < 9; ++j) f[j] = src[j];
 #pragma unroll
-            for (int c = 0; c < kPartialStride; ++c) o[c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
-            screen[3 * (size_t)item + 0] = make_float4(o[0], o[1], o[2], o[3]);
-            screen[3 * (size_t)item + 1] = make_float4(o[4], o[5], o[6], o[7]);
-            screen[3 * (size_t)item + 2] = make_float4(o[8], 0.f, 0.f, 0.f);
+        for (int j = 0; j < 9; ++j) {
+            x[(4 * j + 0) / 9][(4 * j + 0) % 9] = f[j].x;
+            x[(4 * j + 1) / 9][(4 * j + 1) % 9] = f[j].y;
+            x[(4 * j + 2) / 9][(4 * j + 2) % 9] = f[j].z;
+            x[(4 * j + 3) / 9][(4 * j + 3) % 9] = f[j].w;
         }
-        __syncthreads();
+    } else {
+#pragma unroll
+        for (uint32_t u = 0; u < kChunkPerThread; ++u)
+#pragma unroll
+            for (int j = 0; j < kPartialStride; ++j)
+                x[u][j] = pb + u < cend ? partial[(size_t)(pb + u) * kPartialStride + j] : 0.f;
     }
+    if (pb < cend) {
+        uint32_t k = find_chunk_item(ci, nloc, pb);
+#pragma unroll
+        for (uint32_t u = 0; u < kChunkPerThread; ++u) {
+            const uint32_t p = pb + u;
+            if (p < cend) {
+                while (k + 1 < nloc && ci.p0[k + 1] <= p) ++k;
+                key[u] = k;
+                const bool valid = i_lo + k < tile_cut[pair_tile(ci, k, p)].y;
+#pragma unroll
+                for (int j = 0; j < kPartialStride; ++j) x[u][j] = valid ? x[u][j] : 0.f;
+            } else {
+                key[u] = kNoKey;
+            }
+        }
+    } else {
+#pragma unroll
+        for (uint32_t u = 0; u < kChunkPerThread; ++u) key[u] = kNoKey;
+    }
+
+    // ---- segments inside the thread: head (first), complete middles, tail (last)
+    float head[kPartialStride], v[kPartialStride];
+    bool multi = false;
+    uint32_t kc = key[0];
+#pragma unroll
+    for (int j = 0; j < kPartialStride; ++j) v[j] = x[0][j], head[j] = 0.f;
+#pragma unroll
+    for (uint32_t u = 1; u < kChunkPerThread; ++u) {
+        if (key[u] == kc) {
+#pragma unroll
+            for (int j = 0; j < kPartialStride; ++j) v[j] += x[u][j];
+        } else {
+            if (!multi) {
+#pragma unroll
+                for (int j = 0; j < kPartialStride; ++j) head[j] = v[j];
+                multi = true;
+            } else if (kc != kNoKey) {
+                write_item_sum(ci, kc, c0, cend, c, v, screen, carry);  // started and ended in this thread
+            }
+            kc = key[u];
+#pragma unroll
+            for (int j = 0; j < kPartialStride; ++j) v[j] = x[u][j];
+        }
+    }
+    const uint32_t kf = key[0], kl = kc;
+    s_kf[tid] = kf;
+    s_kl[tid] = kl;
+    __syncthreads();
+    const uint32_t kl_prev = tid > 0 ? s_kl[tid - 1] : kNoKey;
+    const uint32_t kf_next = tid + 1 < (int)kChunkThreads ? s_kf[tid + 1] : kNoKey;
+
+    // ---- segmented inclusive scan of the tails: (v, f) with f = "a segment starts in range"
+    bool f = multi || kl_prev != kf;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        float o[kPartialStride];
+#pragma unroll
+        for (int j = 0; j < kPartialStride; ++j) o[j] = __shfl_up(v[j], d, kWave);
+        const bool of = __shfl_up((int)f, d, kWave) != 0;
+        if (lane >= d) {
+            if (!f) {
+#pragma unroll
+                for (int j = 0; j < kPartialStride; ++j) v[j] = o[j] + v[j];
+            }
+            f = f || of;
+        }
+    }
+    if (lane == kWave - 1) {
+#pragma unroll
+        for (int j = 0; j < kPartialStride; ++j) s_wv[wv][j] = v[j];
+        s_wf[wv] = f ? 1u : 0u;
+    }
+    __syncthreads();
+    // running value of the segment open at the end of the previous waves
+    float cin[kPartialStride];
+#pragma unroll
+    for (int j = 0; j < kPartialStride; ++j) cin[j] = 0.f;
+    for (int w = 0; w < wv; ++w) {
+#pragma unroll
+        for (int j = 0; j < kPartialStride; ++j) cin[j] = s_wf[w] ? s_wv[w][j] : cin[j] + s_wv[w][j];
+    }
+    if (!f) {
+#pragma unroll
+        for (int j = 0; j < kPartialStride; ++j) v[j] = cin[j] + v[j];
+    }
+    // inclusive value of the previous thread's tail segment
+    float prev[kPartialStride];
+#pragma unroll
+    for (int j = 0; j < kPartialStride; ++j) {
+        const float up = __shfl_up(v[j], 1, kWave);
+        prev[j] = lane == 0 ? cin[j] : up;
+    }
+
+    // ---- finished segments
+    if (multi && kf != kNoKey) {  // the head segment ends in this thread
+        float tot[kPartialStride];
+#pragma unroll
+        for (int j = 0; j < kPartialStride; ++j) tot[j] = kl_prev == kf ? prev[j] + head[j] : head[j];
+        write_item_sum(ci, kf, c0, cend, c, tot, screen, carry);
+    }
+    if (kl != kNoKey && kf_next != kl) write_item_sum(ci, kl, c0, cend, c, v, screen, carry);
 }
 
-void launch_pair_reduce(const ViewTable &vt, const uint32_t *sorted_items, const uint32_t *poff, uint64_t n,
-                        uint64_t items_cap, const Rec *rec, const uint2 *tile_cut, const float *partial,
-                        float4 *screen, uint32_t *big_list, WsHeader *hdr, int big_ctas, hipStream_t st) {
-    if (items_cap == 0) return;
-    hipLaunchKernelGGL(k_pair_reduce, dim3((unsigned)((items_cap + 255) / 256)), dim3(256), 0, st, vt, sorted_items,
-                       poff, n, rec, tile_cut, partial, screen, big_list, hdr);
-    hipLaunchKernelGGL(k_pair_reduce_big, dim3((unsigned)big_ctas), dim3(256), 0, st, vt, sorted_items, poff, n, rec,
-                       tile_cut, partial, screen, big_list, hdr);
+void launch_pair_reduce(const ViewTable &vt, const uint32_t *sorted_items, const uint32_t *poff,
+                        const uint32_t *chunk_item, uint64_t n, uint64_t pair_grid, const Rec *rec,
+                        const uint2 *tile_cut, const float *partial, float4 *screen, float *carry,
+                        const WsHeader *hdr, hipStream_t st) {
+    const uint64_t chunks = chunk_count(pair_grid);
+    if (chunks == 0) return;
+    hipLaunchKernelGGL(k_pair_reduce, dim3((unsigned)chunks), dim3(kChunkThreads), 0, st, vt, sorted_items, poff,
+                       chunk_item, n, rec, tile_cut, partial, screen, carry, hdr);
 }
 
 // ---------------------------------------------------------------------------
 // A9: projection backward.  One thread per Gaussian; loops over views and
-// chains each visible item's screen-space gradient (from A8) back to the
-// parameters and to the view's pose.
+// chains each visible item's screen-space gradient back to the parameters and
+// to the view's pose.  The item's pair moments come from A8 (or, when its
+// pairs span several chunks, from their chunk-boundary parts added in chunk
+// order) and turn into the gradient of (u, v, A, B, C, opacity, colour) with
+// the item's own conic and opacity: sigma = A dx^2 / 2 + B dx dy + C dy^2 / 2
+// with (dx, dy) = (u, v) - pixel, so dL/du = A S_x + B S_y,
+// dL/dv = B S_x + C S_y, dL/d(A, B, C) = (S_xx / 2, S_xy, S_yy / 2) and
+// dL/do = S_o / o, where S_x = sum w dx, S_xx = sum w dx^2, ... over the
+// item's pixels with w = dL/dsigma and S_o = sum alpha dL/dalpha.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void item_moments(const float4 *__restrict__ screen, const float *__restrict__ carry,
+                                             uint64_t item, uint32_t p0, uint32_t cnt, float S[kPartialStride]) {
+    const uint32_t cf = p0 / kChunkPairs, cl = (p0 + cnt - 1) / kChunkPairs;
+    if (cf == cl) {
+        const float4 s0 = screen[3 * item], s1 = screen[3 * item + 1], s2 = screen[3 * item + 2];
+        S[0] = s0.x, S[1] = s0.y, S[2] = s0.z, S[3] = s0.w;
+        S[4] = s1.x, S[5] = s1.y, S[6] = s1.z, S[7] = s1.w, S[8] = s2.x;
+        return;
+    }
+    const float *t = carry + ((size_t)cf * 2 + 1) * kPartialStride;  // its part of the first chunk
+#pragma unroll
+    for (int j = 0; j < kPartialStride; ++j) S[j] = t[j];
+    for (uint32_t c = cf + 1; c <= cl; ++c) {
+        const float *h = carry + (size_t)c * 2 * kPartialStride;  // the chunk's first item is this one
+#pragma unroll
+        for (int j = 0; j < kPartialStride; ++j) S[j] += h[j];
+    }
+}
+
 __device__ __forceinline__ float block_sum_256(float x, float *red /* [4] */) {
     x = wave_sum(x);
     const int w = threadIdx.x >> 6;
@@ -436,7 +508,7 @@ template <int DEG>
 __global__ __launch_bounds__(kProjThreads) void k_project_bwd(
     gsr_gaussians g, ViewTable vt, const float *__restrict__ w2c, uint64_t n, const Rec *__restrict__ rec,
     const uint32_t *__restrict__ count, const WsHeader *__restrict__ hdr, const float4 *__restrict__ screen,
-    gsr_gaussian_grads gr, float *__restrict__ pose_part, uint32_t pose_blocks) {
+    const float *__restrict__ carry, gsr_gaussian_grads gr, float *__restrict__ pose_part, uint32_t pose_blocks) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     __shared__ float red[4];
     const uint64_t i = (uint64_t)blockIdx.x * kProjThreads + threadIdx.x;
@@ -453,9 +525,12 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(
         const uint32_t cnt = live ? count[item] : 0u;
         if (cnt > 0) {
             const ViewInfo cam = vt.v[v];
-            const float4 s0 = screen[3 * item], s1 = screen[3 * item + 1], s2 = screen[3 * item + 2];
-            const float gu = s0.x, gv = s0.y, gA = s0.z, gB = s0.w, gC = s1.x, go = s1.y;
-            const float grgb[3] = {s1.z, s1.w, s2.x};
+            const float4 r0 = rec[item].r0, r1 = rec[item].r1;
+            float S[kPartialStride];
+            item_moments(screen, carry, item, __float_as_uint(rec[item].r2.w), cnt, S);
+            const float gu = fmaf(r0.z, S[0], r0.w * S[1]), gv = fmaf(r0.w, S[0], r1.x * S[1]);
+            const float gA = 0.5f * S[2], gB = S[3], gC = 0.5f * S[4], go = S[5] / r1.y;
+            const float grgb[3] = {S[6], S[7], S[8]};
 
             float W[9], t[3];
             load_pose(w2c, v, W, t);
@@ -674,15 +749,15 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(
 }
 
 void launch_project_bwd(const gsr_gaussians &g, const ViewTable &vt, const float *w2c, uint64_t n, const Rec *rec,
-                        const uint32_t *count, const WsHeader *hdr, const float4 *screen, const gsr_gaussian_grads &gr, float *pose_part,
-                        uint32_t pose_blocks, hipStream_t st) {
+                        const uint32_t *count, const WsHeader *hdr, const float4 *screen, const float *carry,
+                        const gsr_gaussian_grads &gr, float *pose_part, uint32_t pose_blocks, hipStream_t st) {
     if (n == 0) return;
     const dim3 grid(pose_blocks);
     switch (g.sh_degree) {
-        case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, screen, gr, pose_part, pose_blocks); break;
-        case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, screen, gr, pose_part, pose_blocks); break;
-        case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, screen, gr, pose_part, pose_blocks); break;
-        default: hipLaunchKernelGGL(k_project_bwd<3>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, screen, gr, pose_part, pose_blocks); break;
+        case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks); break;
+        case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks); break;
+        case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks); break;
+        default: hipLaunchKernelGGL(k_project_bwd<3>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks); break;
     }
 }
 

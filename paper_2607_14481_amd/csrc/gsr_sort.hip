@@ -78,8 +78,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(F f, const uint32_
 }
 
 // Single workgroup: exclusive scan of nb block sums in place; total -> *out_total.
+// With `cap_hdr` set the total is the pair count and the overflow decision
+// (total > capacity) is taken here too.
 __global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t *__restrict__ block_sums, uint32_t nb,
-                                                      uint32_t *__restrict__ out_total) {
+                                                      uint32_t *__restrict__ out_total, WsHeader *cap_hdr) {
     __shared__ uint32_t lds[16];
     __shared__ uint32_t carry;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -103,7 +105,10 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t *__restrict__ blo
         if (threadIdx.x == 1023) carry = sat_add(before, inc);
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out_total = carry;
+    if (threadIdx.x == 0) {
+        *out_total = carry;
+        if (cap_hdr) cap_hdr->overflow = carry > cap_hdr->pair_capacity ? 1u : 0u;
+    }
 }
 
 // Phase 3 for the compaction: visible items get their depth key and id written
@@ -141,17 +146,20 @@ void launch_compact_visible(const uint32_t *count, const uint32_t *zkey, uint64_
     if (nb == 0) return;
     hipLaunchKernelGGL(k_scan_reduce<VisibleFlag>, dim3(nb), dim3(kScanThreads), 0, st, VisibleFlag{count},
                        (const uint32_t *)nullptr, items, block_tmp);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, block_tmp, nb, &hdr->n_visible);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, block_tmp, nb, &hdr->n_visible,
+                       (WsHeader *)nullptr);
     hipLaunchKernelGGL(k_compact_apply, dim3(nb), dim3(kScanThreads), 0, st, count, zkey, items, block_tmp, ckey,
                        cval);
 }
 
 // Phase 3 for the pair offsets: poff[i] = exclusive prefix of counts in depth
-// order; the total lands in the header (n_pairs) together with the overflow
-// decision.
+// order (the total and the overflow decision are already in the header).  The
+// item whose range holds a chunk's first pair is recorded for that chunk.
 __global__ __launch_bounds__(kScanThreads) void k_offsets_apply(CountInDepthOrder f,
                                                                 const uint32_t *__restrict__ block_sums,
-                                                                uint32_t *__restrict__ poff, WsHeader *hdr) {
+                                                                uint32_t *__restrict__ poff,
+                                                                uint32_t *__restrict__ chunk_item,
+                                                                uint64_t chunks_cap, const WsHeader *hdr) {
     __shared__ uint32_t lds[4];
     const uint64_t n = hdr->n_visible;
     const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
@@ -167,26 +175,28 @@ __global__ __launch_bounds__(kScanThreads) void k_offsets_apply(CountInDepthOrde
     uint32_t run = sat_add(block_sums[blockIdx.x], block_exclusive_scan(acc, lds, total));
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < n) poff[base + k] = run;
+        if (base + k < n) {
+            poff[base + k] = run;
+            // chunks whose first pair lies in [run, run + c[k])
+            const uint32_t end = sat_add(run, c[k]);
+            for (uint64_t ch = chunk_count(run); ch < chunks_cap && ch * kChunkPairs < end; ++ch)
+                chunk_item[ch] = (uint32_t)(base + k);
+        }
         run = sat_add(run, c[k]);
     }
 }
 
-__global__ void k_pairs_finish(WsHeader *hdr) {
-    const uint32_t m = hdr->n_pairs;
-    hdr->overflow = m > hdr->pair_capacity ? 1u : 0u;
-}
-
 void launch_pair_offsets(const uint32_t *sorted_items, const uint32_t *count, uint64_t items_cap, uint32_t *poff,
-                         uint32_t *block_tmp, WsHeader *hdr, hipStream_t st) {
+                         uint32_t *chunk_item, uint64_t chunks_cap, uint32_t *block_tmp, WsHeader *hdr,
+                         hipStream_t st) {
     const uint32_t nb = (uint32_t)((items_cap + kScanTile - 1) / kScanTile);
     if (nb == 0) return;
     CountInDepthOrder f{sorted_items, count};
     hipLaunchKernelGGL(k_scan_reduce<CountInDepthOrder>, dim3(nb), dim3(kScanThreads), 0, st, f, &hdr->n_visible,
                        items_cap, block_tmp);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, block_tmp, nb, &hdr->n_pairs);
-    hipLaunchKernelGGL(k_offsets_apply, dim3(nb), dim3(kScanThreads), 0, st, f, block_tmp, poff, hdr);
-    hipLaunchKernelGGL(k_pairs_finish, dim3(1), dim3(1), 0, st, hdr);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, block_tmp, nb, &hdr->n_pairs, hdr);
+    hipLaunchKernelGGL(k_offsets_apply, dim3(nb), dim3(kScanThreads), 0, st, f, block_tmp, poff, chunk_item,
+                       chunks_cap, (const WsHeader *)hdr);
 }
 
 // ---------------------------------------------------------------------------
@@ -337,63 +347,64 @@ void radix_sort_u32(uint32_t *keys[2], uint32_t *vals[2], SortCount sc, uint64_t
 
 // ---------------------------------------------------------------------------
 // A3: emission.  The i-th item in depth order owns pairs [poff[i], poff[i] +
-// count) in row-major order over its tile box.  A wave takes 64 consecutive
-// items and writes their pairs cooperatively (lanes stride over one item's
-// tiles), so the writes are coalesced and large Gaussians do not serialise a
-// lane.  The item's depth rank and pair offset are recorded for the backward.
+// count) in row-major order over its tile box.  A workgroup writes one chunk
+// of 1024 consecutive pair slots, 4 per thread (16-byte stores, so the writes
+// are coalesced and equal per thread however the tile counts are spread): the
+// chunk's items are staged in LDS and each thread finds its pairs' item by
+// binary search there.  An item's depth rank and pair offset are recorded, by
+// the chunk in which its pairs start, for the backward.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_emit(ViewTable vt, const uint32_t *__restrict__ sorted_items,
-                                              const uint32_t *__restrict__ poff, uint64_t n, Rec *__restrict__ rec,
-                                              uint32_t *__restrict__ rank, uint32_t *__restrict__ pkey,
-                                              uint32_t *__restrict__ pval, const WsHeader *__restrict__ hdr) {
-    const uint32_t nvis = hdr->n_visible;
+__global__ __launch_bounds__(kChunkThreads) void k_emit(ViewTable vt, const uint32_t *__restrict__ sorted_items,
+                                                        const uint32_t *__restrict__ poff,
+                                                        const uint32_t *__restrict__ chunk_item, uint64_t n,
+                                                        Rec *__restrict__ rec, uint32_t *__restrict__ rank,
+                                                        uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval,
+                                                        const WsHeader *__restrict__ hdr) {
+    __shared__ ChunkItems ci;
     if (hdr->overflow) return;
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t base = (blockIdx.x * 256u + threadIdx.x) & ~63u;  // first depth index of this wave
-    if (base >= nvis) return;                                        // uniform per wave
-    const uint32_t i = base + lane;
-    uint32_t item = 0, off = 0, w = 1, cnt = 0, t0 = 0, tiles_x = 0;
-    if (i < nvis) {
-        item = sorted_items[i];
-        off = poff[i];
-        rank[item] = i;
-        const float4 r2 = rec[item].r2;
-        rec[item].r2.w = __uint_as_float(off);
-        const uint32_t bx = __float_as_uint(r2.y), by = __float_as_uint(r2.z);
-        const uint32_t tx0 = (bx & 0xffffu) / kTileW, tx1 = (bx >> 16) / kTileW;
-        const uint32_t ty0 = (by & 0xffffu) / vt.tile_h, ty1 = (by >> 16) / vt.tile_h;
-        const int v = (int)(item / n);
-        tiles_x = (uint32_t)vt.v[v].tiles_x;
-        w = tx1 - tx0 + 1;
-        cnt = w * (ty1 - ty0 + 1);
-        t0 = vt.v[v].tile_off + ty0 * tiles_x + tx0;
+    const uint32_t m = hdr->n_pairs, nvis = hdr->n_visible;
+    const uint32_t c0 = blockIdx.x * kChunkPairs;
+    if (c0 >= m) return;  // uniform per workgroup
+    const uint32_t cend = min(c0 + kChunkPairs, m);
+    uint32_t i_lo;
+    const uint32_t nloc = load_chunk_items(vt, sorted_items, poff, chunk_item, n, rec, blockIdx.x, m, nvis, ci, i_lo);
+    for (uint32_t k = threadIdx.x; k < nloc; k += kChunkThreads) {
+        const uint32_t p = ci.p0[k];
+        if (p >= c0 && p < cend) {
+            const uint32_t item = ci.item[k];
+            rank[item] = i_lo + k;
+            rec[item].r2.w = __uint_as_float(p);
+        }
     }
-    const uint32_t nj = min(64u, nvis - base);
-    for (uint32_t j = 0; j < nj; ++j) {
-        // item j's box, broadcast through scalar registers
-        const uint32_t cj = __builtin_amdgcn_readlane(cnt, j), oj = __builtin_amdgcn_readlane(off, j);
-        const uint32_t wj = __builtin_amdgcn_readlane(w, j), tj = __builtin_amdgcn_readlane(t0, j);
-        const uint32_t sxj = __builtin_amdgcn_readlane(tiles_x, j), itj = __builtin_amdgcn_readlane(item, j);
-        if (lane >= cj) continue;
-        // lane walks q = lane, lane + 64, ... keeping (row, col) of q incrementally
-        uint32_t row = lane / wj, col = lane - row * wj;
-        const uint32_t drow = 64u / wj, dcol = 64u - drow * wj;
-        for (uint32_t q = lane; q < cj; q += 64u) {
-            pkey[oj + q] = tj + row * sxj + col;
-            pval[oj + q] = itj;
-            row += drow;
-            col += dcol;
-            if (col >= wj) col -= wj, ++row;
+    const uint32_t pb = c0 + threadIdx.x * kChunkPerThread;
+    if (pb >= cend) return;
+    uint32_t key[kChunkPerThread], val[kChunkPerThread];
+    uint32_t k = find_chunk_item(ci, nloc, pb);
+#pragma unroll
+    for (uint32_t u = 0; u < kChunkPerThread; ++u) {
+        const uint32_t p = pb + u;
+        while (k + 1 < nloc && ci.p0[k + 1] <= p) ++k;
+        key[u] = pair_tile(ci, k, p);
+        val[u] = ci.item[k];
+    }
+    if (pb + kChunkPerThread <= cend) {
+        *reinterpret_cast<uint4 *>(pkey + pb) = make_uint4(key[0], key[1], key[2], key[3]);
+        *reinterpret_cast<uint4 *>(pval + pb) = make_uint4(val[0], val[1], val[2], val[3]);
+    } else {
+        for (uint32_t u = 0; pb + u < cend; ++u) {
+            pkey[pb + u] = key[u];
+            pval[pb + u] = val[u];
         }
     }
 }
 
-void launch_emit_pairs(const ViewTable &vt, const uint32_t *sorted_items, const uint32_t *poff, uint64_t n,
-                       uint64_t items_cap, Rec *rec, uint32_t *rank, uint32_t *pkey, uint32_t *pval,
-                       const WsHeader *hdr, hipStream_t st) {
-    if (items_cap == 0) return;
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)((items_cap + 255) / 256)), dim3(256), 0, st, vt, sorted_items, poff, n,
-                       rec, rank, pkey, pval, hdr);
+void launch_emit_pairs(const ViewTable &vt, const uint32_t *sorted_items, const uint32_t *poff,
+                       const uint32_t *chunk_item, uint64_t n, uint64_t pair_grid, Rec *rec, uint32_t *rank,
+                       uint32_t *pkey, uint32_t *pval, const WsHeader *hdr, hipStream_t st) {
+    const uint64_t chunks = chunk_count(pair_grid);
+    if (chunks == 0) return;
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)chunks), dim3(kChunkThreads), 0, st, vt, sorted_items, poff, chunk_item,
+                       n, rec, rank, pkey, pval, hdr);
 }
 
 // ---------------------------------------------------------------------------
@@ -432,11 +443,8 @@ void launch_reset_header(WsHeader *h, uint32_t cap, hipStream_t st) {
     hipLaunchKernelGGL(k_reset_header, dim3(1), dim3(64), 0, st, h, cap);
 }
 
-// Start of a backward pass: its work queue and its list of large items.
-__global__ void k_reset_queue(WsHeader *h, int which) {
-    h->queue[which] = 0u;
-    h->n_big = 0u;
-}
+// Start of a backward pass: its work queue.
+__global__ void k_reset_queue(WsHeader *h, int which) { h->queue[which] = 0u; }
 
 void launch_reset_queue(WsHeader *h, int which, hipStream_t st) {
     hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(1), 0, st, h, which);
