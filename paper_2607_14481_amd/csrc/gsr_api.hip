@@ -344,8 +344,8 @@ int gsr_rasterize_backward(void *ws, size_t ws_bytes, const gsr_gaussians *g, in
         return fail(GSR_ERR_INVALID_ARGUMENT, "ws, world_to_cam, out_rgb, dL_drgb and grads must not be NULL");
     if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacities || !grads->sh))
         return fail(GSR_ERR_INVALID_ARGUMENT, "a gradient output pointer is NULL");
-    if (g->n > 0 && (reinterpret_cast<uintptr_t>(grads->quats) & 15u))
-        return fail(GSR_ERR_INVALID_ARGUMENT, "grads->quats must be 16-byte aligned");
+    if (g->n > 0 && ((reinterpret_cast<uintptr_t>(grads->quats) | reinterpret_cast<uintptr_t>(grads->sh)) & 15u))
+        return fail(GSR_ERR_INVALID_ARGUMENT, "grads->quats and grads->sh must be 16-byte aligned");
     WsLayout L;
     uint64_t cap = 0;
     if ((rc = layout_from_bytes((uint64_t)g->n, vt, ws_bytes, L, cap))) return rc;

@@ -494,14 +494,16 @@ __device__ __forceinline__ void item_moments(const float4 *__restrict__ screen, 
     }
 }
 
-__device__ __forceinline__ float block_sum_256(float x, float *red /* [4] */) {
-    x = wave_sum(x);
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) red[w] = x;
-    __syncthreads();
-    const float s = (red[0] + red[1]) + (red[2] + red[3]);
-    __syncthreads();
-    return s;
+template <int K, bool VEC>
+__device__ __forceinline__ void store_sh_row(float *__restrict__ dst, const float (&v)[3 * K]) {
+    if constexpr (VEC) {
+        float4 *d4 = reinterpret_cast<float4 *>(dst);
+#pragma unroll
+        for (int k = 0; k < 3 * K / 4; ++k) d4[k] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 3 * K; ++k) dst[k] = v[k];
+    }
 }
 
 template <int DEG>
@@ -510,7 +512,8 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(
     const uint32_t *__restrict__ count, const WsHeader *__restrict__ hdr, const float4 *__restrict__ screen,
     const float *__restrict__ carry, gsr_gaussian_grads gr, float *__restrict__ pose_part, uint32_t pose_blocks) {
     constexpr int K = (DEG + 1) * (DEG + 1);
-    __shared__ float red[4];
+    constexpr bool kVecSH = (3 * K) % 4 == 0;  // SH rows of 16-byte multiples: float4 loads and stores
+    __shared__ float red[4 * 12];
     const uint64_t i = (uint64_t)blockIdx.x * kProjThreads + threadIdx.x;
     // after a pair overflow no pair gradient exists: every Gaussian gets zero
     const bool live = i < n && hdr->overflow == 0u;
@@ -551,34 +554,43 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(
             const float dir[3] = {dvec[0] / dn, dvec[1] / dn, dvec[2] / dn};
             float Y[K];
             sh_eval<DEG, float>(dir[0], dir[1], dir[2], Y);
-            const float *shp = g.sh + (size_t)i * K * 3;
-            // pass 1: colour, to know which channels the forward clamped at 0
+            float shv[3 * K];
+            if constexpr (kVecSH) {
+                const float4 *src = reinterpret_cast<const float4 *>(g.sh) + (size_t)i * (3 * K / 4);
+#pragma unroll
+                for (int k = 0; k < 3 * K / 4; ++k) {
+                    const float4 f = src[k];
+                    shv[4 * k] = f.x, shv[4 * k + 1] = f.y, shv[4 * k + 2] = f.z, shv[4 * k + 3] = f.w;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 3 * K; ++k) shv[k] = g.sh[(size_t)i * K * 3 + k];
+            }
+            // colour, to know which channels the forward clamped at 0
             float col[3] = {0.5f, 0.5f, 0.5f};
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                col[0] = fmaf(shp[3 * k], Y[k], col[0]);
-                col[1] = fmaf(shp[3 * k + 1], Y[k], col[1]);
-                col[2] = fmaf(shp[3 * k + 2], Y[k], col[2]);
+                col[0] = fmaf(shv[3 * k], Y[k], col[0]);
+                col[1] = fmaf(shv[3 * k + 1], Y[k], col[1]);
+                col[2] = fmaf(shv[3 * k + 2], Y[k], col[2]);
             }
             float gc[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) gc[c] = col[c] < 0.f ? 0.f : grgb[c];
-            // pass 2: coefficient gradients and the weights of dRGB/ddir
-            float wdir[K];
+            // coefficient gradients (added to an earlier view's) and the weights of dRGB/ddir
+            float wdir[K], o[3 * K];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                const float a0 = shp[3 * k], a1 = shp[3 * k + 1], a2 = shp[3 * k + 2];
-                float o0 = gc[0] * Y[k], o1 = gc[1] * Y[k], o2 = gc[2] * Y[k];
-                if (sh_written) {
-                    o0 += gsh[3 * k];
-                    o1 += gsh[3 * k + 1];
-                    o2 += gsh[3 * k + 2];
-                }
-                gsh[3 * k] = o0;
-                gsh[3 * k + 1] = o1;
-                gsh[3 * k + 2] = o2;
-                wdir[k] = fmaf(gc[0], a0, fmaf(gc[1], a1, gc[2] * a2));
+                o[3 * k] = gc[0] * Y[k];
+                o[3 * k + 1] = gc[1] * Y[k];
+                o[3 * k + 2] = gc[2] * Y[k];
+                wdir[k] = fmaf(gc[0], shv[3 * k], fmaf(gc[1], shv[3 * k + 1], gc[2] * shv[3 * k + 2]));
             }
+            if (sh_written) {
+#pragma unroll
+                for (int k = 0; k < 3 * K; ++k) o[k] += gsh[k];
+            }
+            store_sh_row<K, kVecSH>(gsh, o);
             sh_written = true;
             float gdx, gdy, gdz;
             sh_grad_dir<DEG>(dir[0], dir[1], dir[2], wdir, gdx, gdy, gdz);
@@ -719,18 +731,32 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(
 #pragma unroll
             for (int k = 0; k < 4; ++k) gq[k] += (gqh[k] - q[k] * qd) / qn;
         }
-        // per-block partial of this view's pose gradient (all threads take part)
+        // per-block partial of this view's pose gradient (all threads take part):
+        // wave sums, then the four waves in a fixed order;
         // layout [view][entry of the 3x4 block][workgroup]
-        float *dst = pose_part + (size_t)v * 12 * pose_blocks + blockIdx.x;
+        {
+            float pv[12];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            const float s = block_sum_256(gW[k], red);
-            if (threadIdx.x == 0) dst[(size_t)((k / 3) * 4 + (k % 3)) * pose_blocks] = s;
-        }
+            for (int r = 0; r < 3; ++r) {
+                pv[4 * r] = gW[3 * r];
+                pv[4 * r + 1] = gW[3 * r + 1];
+                pv[4 * r + 2] = gW[3 * r + 2];
+                pv[4 * r + 3] = gt[r];
+            }
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const float s = block_sum_256(gt[k], red);
-            if (threadIdx.x == 0) dst[(size_t)(k * 4 + 3) * pose_blocks] = s;
+            for (int k = 0; k < 12; ++k) pv[k] = wave_sum(pv[k]);
+            const int wv = threadIdx.x >> 6;
+            if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+                for (int k = 0; k < 12; ++k) red[wv * 12 + k] = pv[k];
+            }
+            __syncthreads();
+            if (threadIdx.x < 12) {
+                const int k = threadIdx.x;
+                pose_part[((size_t)v * 12 + k) * pose_blocks + blockIdx.x] =
+                    (red[k] + red[12 + k]) + (red[24 + k] + red[36 + k]);
+            }
+            __syncthreads();
         }
     }
     if (i >= n) return;
@@ -743,8 +769,10 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(
     reinterpret_cast<float4 *>(gr.quats)[i] = make_float4(gq[0], gq[1], gq[2], gq[3]);
     gr.opacities[i] = gop;
     if (!sh_written) {
+        float z[3 * K];
 #pragma unroll
-        for (int k = 0; k < 3 * K; ++k) gsh[k] = 0.f;
+        for (int k = 0; k < 3 * K; ++k) z[k] = 0.f;
+        store_sh_row<K, kVecSH>(gsh, z);
     }
 }
 

@@ -207,20 +207,43 @@ void launch_pair_offsets(const uint32_t *sorted_items, const uint32_t *count, ui
 // The element count is read on the device: either *n_dev or, for the pair
 // sort, 0 when the header flags an overflow.
 // ---------------------------------------------------------------------------
+// Rounds of 64 consecutive elements per wave: wave w of a block owns the
+// block's elements [w * kSortTile / 4, (w + 1) * kSortTile / 4), which keeps the
+// block's order (wave, round, lane) equal to the input order.
+constexpr int kWaveSpan = kSortTile / (kSortThreads / 64);  // 1024
+constexpr int kRounds = kWaveSpan / 64;                     // 16
+
+// Lanes of the wave holding the same 8-bit digit as this lane (8 ballots).
+__device__ __forceinline__ unsigned long long digit_peers(bool ok, uint32_t d) {
+    unsigned long long match = __ballot(ok);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const unsigned long long bal = __ballot(ok && ((d >> b) & 1u));
+        match &= ((d >> b) & 1u) ? bal : ~bal;
+    }
+    return match;
+}
+
+// Per-block digit histogram (LDS atomics; all loads are issued first).
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *__restrict__ keys, SortCount sc,
                                                              int shift, uint32_t *__restrict__ hist,
                                                              uint32_t hist_blocks) {
     __shared__ uint32_t h[256];
     const uint64_t n = sc();
-    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
-    if (base >= n) return;  // blocks past the end are never scanned
+    const uint64_t blk = (uint64_t)blockIdx.x * kSortTile;
+    if (blk >= n) return;  // blocks past the end are never scanned
+    const uint32_t m = (uint32_t)min((uint64_t)kSortTile, n - blk);
+    uint32_t k[kSortItems];
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const uint32_t li = (uint32_t)r * kSortThreads + threadIdx.x;
+        k[r] = li < m ? keys[blk + li] : 0u;
+    }
     h[threadIdx.x] = 0;
     __syncthreads();
-#pragma unroll 4
-    for (int k = 0; k < kSortItems; ++k) {
-        const uint64_t i = base + (uint64_t)k * kSortThreads + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
-    }
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r)
+        if ((uint32_t)r * kSortThreads + threadIdx.x < m) atomicAdd(&h[(k[r] >> shift) & 255u], 1u);
     __syncthreads();
     hist[(size_t)threadIdx.x * hist_blocks + blockIdx.x] = h[threadIdx.x];
 }
@@ -248,11 +271,12 @@ __global__ __launch_bounds__(256) void k_radix_scan(uint32_t *__restrict__ hist,
     if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
 }
 
-// Stable scatter of one block's kSortTile elements.  Ranks come from wave
-// ballots (16 rounds of 256 consecutive elements, so order is preserved); the
-// block's elements are first placed in LDS in digit order, then written out in
-// contiguous runs per digit (coalesced, instead of one random 4-byte write per
-// element).
+// Stable scatter of one block's kSortTile elements.  Each wave loads its 1024
+// consecutive elements up front, then ranks them round by round against its
+// own running digit counts (ballot peers; no block barrier inside the loop).
+// One barrier later the waves' counts become offsets, the block's elements
+// are placed in LDS in digit order, and written out in contiguous runs per
+// digit (coalesced, instead of one random 4-byte write per element).
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *__restrict__ kin,
                                                                 const uint32_t *__restrict__ vin,
                                                                 uint32_t *__restrict__ kout,
@@ -262,8 +286,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
                                                                 const uint32_t *__restrict__ digit_total) {
     __shared__ uint32_t gbase[256];      // global position of this block's first element of each digit
     __shared__ uint32_t lbase[256];      // block-local position of the same
-    __shared__ uint32_t running[256];    // elements of each digit placed so far
-    __shared__ uint32_t wave_cnt[4][256];
+    __shared__ uint32_t wcnt[4][256];    // per-wave running digit counts, then per-wave block-local offsets
     __shared__ uint32_t lds[4];
     __shared__ uint32_t skey[kSortTile], sval[kSortTile];
     const uint64_t n = sc();
@@ -272,58 +295,67 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
     const uint32_t nb = (uint32_t)((n + kSortTile - 1) / kSortTile);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t t = threadIdx.x;
+    const uint32_t m = (uint32_t)min((uint64_t)kSortTile, n - blk);
+    uint32_t key[kRounds], val[kRounds];
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const uint32_t li = (uint32_t)(w * kWaveSpan + r * 64 + lane);
+        key[r] = li < m ? kin[blk + li] : 0u;
+        val[r] = li < m ? vin[blk + li] : 0u;
+    }
     {
         uint32_t total;
         const uint32_t ex = block_exclusive_scan(digit_total[t], lds, total);
         const uint32_t mine = hist[(size_t)t * hist_blocks + blockIdx.x];
         const uint32_t next = blockIdx.x + 1 < nb ? hist[(size_t)t * hist_blocks + blockIdx.x + 1] : digit_total[t];
         gbase[t] = ex + mine;
-        const uint32_t lex = block_exclusive_scan(next - mine, lds, total);
-        lbase[t] = lex;
-        running[t] = lex;
+        lbase[t] = block_exclusive_scan(next - mine, lds, total);
     }
-    for (int k = 0; k < 4; ++k) wave_cnt[k][t] = 0;
+    for (int k = 0; k < 4; ++k) wcnt[k][t] = 0;
     __syncthreads();
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
-    const uint32_t m = (uint32_t)min((uint64_t)kSortTile, n - blk);
-    for (int r = 0; r < kSortItems; ++r) {
-        const uint32_t li = (uint32_t)r * kSortThreads + t;
-        const bool ok = li < m;
-        uint32_t key = 0, val = 0, d = 0;
-        if (ok) {
-            key = kin[blk + li];
-            val = vin[blk + li];
-            d = (key >> shift) & 255u;
-        }
-        unsigned long long match = __ballot(ok);
+    uint32_t pos[kRounds];
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const unsigned long long bal = __ballot(ok && ((d >> b) & 1u));
-            match &= ((d >> b) & 1u) ? bal : ~bal;
-        }
-        const uint32_t rank = __popcll(match & lt_mask);
-        const uint32_t cnt = __popcll(match);
-        if (ok && rank == cnt - 1) wave_cnt[w][d] = cnt;  // one writer per (wave, digit)
-        __syncthreads();
-        if (ok) {
-            uint32_t pos = running[d] + rank;
-            for (int k = 0; k < w; ++k) pos += wave_cnt[k][d];
-            skey[pos] = key;
-            sval[pos] = val;
-        }
-        __syncthreads();
-        running[t] += wave_cnt[0][t] + wave_cnt[1][t] + wave_cnt[2][t] + wave_cnt[3][t];
-        wave_cnt[0][t] = wave_cnt[1][t] = wave_cnt[2][t] = wave_cnt[3][t] = 0;
-        __syncthreads();
-        if ((r + 1) * kSortThreads >= (int)m) break;  // uniform
+    for (int r = 0; r < kRounds; ++r) {
+        const uint32_t li = (uint32_t)(w * kWaveSpan + r * 64 + lane);
+        const bool ok = li < m;
+        const uint32_t d = (key[r] >> shift) & 255u;
+        const unsigned long long peers = digit_peers(ok, d);
+        const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+        const uint32_t before = ok ? wcnt[w][d] : 0u;
+        pos[r] = before + rank;
+        // the digit's last lane advances the wave's count (read above by every lane first)
+        __builtin_amdgcn_wave_barrier();
+        if (ok && (peers >> lane) == 1ull) wcnt[w][d] = before + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
     }
+    __syncthreads();
+    {
+        const uint32_t c0 = wcnt[0][t], c1 = wcnt[1][t], c2 = wcnt[2][t];
+        const uint32_t b = lbase[t];
+        wcnt[0][t] = b;
+        wcnt[1][t] = b + c0;
+        wcnt[2][t] = b + c0 + c1;
+        wcnt[3][t] = b + c0 + c1 + c2;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const uint32_t li = (uint32_t)(w * kWaveSpan + r * 64 + lane);
+        if (li < m) {
+            const uint32_t p = wcnt[w][(key[r] >> shift) & 255u] + pos[r];
+            skey[p] = key[r];
+            sval[p] = val[r];
+        }
+    }
+    __syncthreads();
     // write out in local order: runs of one digit go to consecutive addresses
-    for (uint32_t pos = t; pos < m; pos += kSortThreads) {
-        const uint32_t key = skey[pos];
-        const uint32_t d = (key >> shift) & 255u;
-        const uint32_t g = gbase[d] + (pos - lbase[d]);
-        kout[g] = key;
-        vout[g] = sval[pos];
+    for (uint32_t p = t; p < m; p += kSortThreads) {
+        const uint32_t k = skey[p];
+        const uint32_t d = (k >> shift) & 255u;
+        const uint32_t g = gbase[d] + (p - lbase[d]);
+        kout[g] = k;
+        vout[g] = sval[p];
     }
 }
 
