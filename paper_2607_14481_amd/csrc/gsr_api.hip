@@ -86,7 +86,7 @@ gsr::WsLayout make_layout(uint64_t n, const gsr::ViewTable &vt, uint64_t cap) {
     L.items = items;
     L.cap = cap;
     L.chunks = chunk_count(cap);
-    const uint64_t hb_items = (items + kSortTile - 1) / kSortTile;
+    const uint64_t hb_items = (items + kSortTileShort - 1) / kSortTileShort;
     const uint64_t hb_pairs = (cap + kSortTile - 1) / kSortTile;
     L.hist_blocks = (uint32_t)std::max<uint64_t>(1, std::max(hb_items, hb_pairs));
     L.pose_blocks = (uint32_t)std::max<uint64_t>(1, (n + kProjThreads - 1) / kProjThreads);
@@ -293,8 +293,8 @@ int gsr_rasterize_forward(void *ws, size_t ws_bytes, const gsr_gaussians *g, int
     int cur = 0;
     {
         uint32_t *k2[2] = {p.ckey[0], p.ckey[1]}, *v2[2] = {p.cval[0], p.cval[1]};
-        radix_sort_u32(k2, v2, SortCount{&p.hdr->n_visible, nullptr}, L.items, 0, 32, p.hist, L.hist_blocks,
-                       p.digit_total, cur, st);
+        radix_sort_u32(k2, v2, SortCount{&p.hdr->n_visible, nullptr}, L.items, 0, 32, true, p.hist,
+                       L.hist_blocks, p.digit_total, cur, st);
     }
     mark.end(GSR_STAGE_DEPTH_SORT);
     const uint32_t *sorted_items = p.cval[cur];
@@ -316,7 +316,7 @@ int gsr_rasterize_forward(void *ws, size_t ws_bytes, const gsr_gaussians *g, int
     int pc = 0;
     {
         uint32_t *k2[2] = {p.pkey[0], p.pkey[1]}, *v2[2] = {p.pval[0], p.pval[1]};
-        radix_sort_u32(k2, v2, SortCount{nullptr, p.hdr}, pair_grid, 0, tile_bits(vt.total_tiles), p.hist,
+        radix_sort_u32(k2, v2, SortCount{nullptr, p.hdr}, pair_grid, 0, tile_bits(vt.total_tiles), false, p.hist,
                        L.hist_blocks, p.digit_total, pc, st);
     }
     launch_tile_ranges(p.pkey[pc], pair_grid, p.ranges, vt.total_tiles, p.hdr, st);

@@ -128,14 +128,14 @@ __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uin
         if (t >= vt.total_tiles) break;
         const TileCtx c = tile_ctx(vt, t);
         const uint32_t px = c.ox + lx;
+        // T > 0: the pixel is still compositing; T < 0: it stopped (or lies outside
+        // the image) and -T is its final transmittance
         float T[RPL], C0[RPL], C1[RPL], C2[RPL];
         uint32_t last[RPL], stop_at[RPL], ncontrib[RPL];
-        bool live[RPL];
 #pragma unroll
         for (int k = 0; k < RPL; ++k) {
             const uint32_t py = c.oy + ly + 4 * k;
-            live[k] = px < c.width && py < c.height;
-            T[k] = 1.f;
+            T[k] = (px < c.width && py < c.height) ? 1.f : -1.f;
             C0[k] = C1[k] = C2[k] = 0.f;
             last[k] = 0;
             ncontrib[k] = 0;
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uin
         for (uint32_t b0 = rg.x; b0 < rg.y; b0 += kWave) {
             bool any_live = false;
 #pragma unroll
-            for (int k = 0; k < RPL; ++k) any_live |= live[k];
+            for (int k = 0; k < RPL; ++k) any_live |= T[k] > 0.f;
             if (__ballot(any_live) == 0ull) break;
             const uint32_t idx = b0 + lane;
             if (idx < rg.y) {
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uin
                 if ((j & 15) == 15) {  // leave the batch once every pixel of the tile has stopped
                     bool any = false;
 #pragma unroll
-                    for (int k = 0; k < RPL; ++k) any |= live[k];
+                    for (int k = 0; k < RPL; ++k) any |= T[k] > 0.f;
                     if (__ballot(any) == 0ull) break;
                 }
                 const float4 a = sa[j], b = sb[j], d = sd[j];
@@ -174,21 +174,21 @@ __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uin
                     const float dy = a.y - ((float)(ly + 4 * k) + 0.5f);
                     const float e2 = neg_sigma_log2e(a, b, dx, dy);
                     const float alpha = fminf(kAlphaMax, __builtin_amdgcn_exp2f(e2 + b.y));
-                    const bool ok = live[k] && e2 <= 0.f && alpha >= kAlphaMin;
+                    const bool ok = e2 <= 0.f && alpha >= kAlphaMin;
                     const float Tn = T[k] * (1.f - alpha);
+                    // a stopped pixel has Tn <= 0 < kTMin, so it never adds again
                     const bool stop = ok && Tn < kTMin;
                     const bool add = ok && !stop;
                     const float w = add ? alpha * T[k] : 0.f;
                     C0[k] = fmaf(b.z, w, C0[k]);
                     C1[k] = fmaf(b.w, w, C1[k]);
                     C2[k] = fmaf(d.x, w, C2[k]);
-                    T[k] = add ? Tn : T[k];
                     last[k] = add ? pos + 1 : last[k];
                     if constexpr (STATS) {
                         ncontrib[k] += add ? 1u : 0u;
-                        stop_at[k] = stop ? pos : stop_at[k];
+                        stop_at[k] = (stop && T[k] > 0.f) ? pos : stop_at[k];
                     }
-                    live[k] = live[k] && !stop;
+                    T[k] = add ? Tn : (stop ? -fabsf(T[k]) : T[k]);
                 }
             }
             __syncthreads();
@@ -203,12 +203,13 @@ __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uin
             const uint32_t py = c.oy + ly + 4 * k;
             if (px < c.width && py < c.height) {
                 const size_t pix = (size_t)py * c.width + px;
-                img[pix] = C0[k] + T[k] * bg.x;
-                img[plane + pix] = C1[k] + T[k] * bg.y;
-                img[2 * plane + pix] = C2[k] + T[k] * bg.z;
-                pix_T[c.pix_off + pix] = T[k];
+                const float Tf = fabsf(T[k]);
+                img[pix] = C0[k] + Tf * bg.x;
+                img[plane + pix] = C1[k] + Tf * bg.y;
+                img[2 * plane + pix] = C2[k] + Tf * bg.z;
+                pix_T[c.pix_off + pix] = Tf;
                 pix_n[c.pix_off + pix] = last[k];
-                if (out_T) out_T[c.pix_off + pix] = T[k];
+                if (out_T) out_T[c.pix_off + pix] = Tf;
                 evals += stop_at[k] != 0xffffffffu ? stop_at[k] + 1 : len;
                 replays += last[k];
                 contrib += ncontrib[k];

@@ -93,8 +93,8 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;     // 2048
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
-constexpr int kSortTile = kSortThreads * kSortItems;     // 4096
+constexpr int kSortTile = 4096;                           // elements per sort block (pairs)
+constexpr int kSortTileShort = 1024;                      // elements per sort block (visible items)
 constexpr int kProjThreads = 256;
 constexpr int kPartialStride = 9;                         // floats per pair gradient
 // Pairs are also processed in fixed chunks of consecutive emission-order
@@ -128,8 +128,10 @@ struct SortCount {
 };
 // Stable LSD sort of (key, value) on bits [begin_bit, end_bit), 8 per pass,
 // ping-ponging between keys[cur]/keys[cur ^ 1]; `cur` ends at the result.
+// short_list: blocks of kSortTileShort elements instead of kSortTile.
 void radix_sort_u32(uint32_t *keys[2], uint32_t *vals[2], SortCount sc, uint64_t n_cap, int begin_bit, int end_bit,
-                    uint32_t *hist, uint32_t hist_blocks, uint32_t *digit_total, int &cur, hipStream_t st);
+                    bool short_list, uint32_t *hist, uint32_t hist_blocks, uint32_t *digit_total, int &cur,
+                    hipStream_t st);
 void launch_reset_queue(WsHeader *h, int which, hipStream_t st);
 void launch_pair_offsets(const uint32_t *sorted_items, const uint32_t *count, uint64_t items_cap,
                          uint32_t *poff, uint32_t *chunk_item, uint64_t chunks_cap, uint32_t *block_tmp,
@@ -248,12 +250,31 @@ __device__ __forceinline__ uint32_t find_chunk_item(const ChunkItems &ci, uint32
     return lo;
 }
 
-// global tile of pair p, which belongs to local item k
-__device__ __forceinline__ uint32_t pair_tile(const ChunkItems &ci, uint32_t k, uint32_t p) {
-    const uint32_t q = p - ci.p0[k];
-    const uint32_t w = ci.wx[k] & 0xffffu, tiles_x = ci.wx[k] >> 16;
-    const uint32_t row = q / w;
-    return ci.tile0[k] + row * tiles_x + (q - row * w);
-}
+// Global tiles of consecutive pairs p, p + 1, ...: the walker keeps the
+// (row, column) of the current pair in its item's box, so only the first pair
+// needs a division.
+struct PairWalker {
+    uint32_t k, row, col;
+    __device__ __forceinline__ void start(const ChunkItems &ci, uint32_t nloc, uint32_t p) {
+        k = find_chunk_item(ci, nloc, p);
+        const uint32_t q = p - ci.p0[k], w = ci.wx[k] & 0xffffu;
+        row = q / w;
+        col = q - row * w;
+    }
+    // move to pair p (the pair after the previous one)
+    __device__ __forceinline__ void next(const ChunkItems &ci, uint32_t nloc, uint32_t p) {
+        if (k + 1 < nloc && ci.p0[k + 1] <= p) {
+            ++k;
+            while (k + 1 < nloc && ci.p0[k + 1] <= p) ++k;  // (items own at least one pair: not taken)
+            row = col = 0;
+        } else if (++col == (ci.wx[k] & 0xffffu)) {
+            col = 0;
+            ++row;
+        }
+    }
+    __device__ __forceinline__ uint32_t tile(const ChunkItems &ci) const {
+        return ci.tile0[k] + row * (ci.wx[k] >> 16) + col;
+    }
+};
 
 }  // namespace gsr

@@ -323,11 +323,9 @@ __global__ __launch_bounds__(kChunkThreads) void k_pair_reduce(ViewTable vt, con
     const uint32_t c = blockIdx.x, c0 = c * kChunkPairs;
     if (c0 >= m) return;  // uniform per workgroup
     const uint32_t cend = min(c0 + kChunkPairs, m);
-    uint32_t i_lo;
-    const uint32_t nloc = load_chunk_items(vt, sorted_items, poff, chunk_item, n, rec, c, m, nvis, ci, i_lo);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
 
-    // ---- this thread's pairs: keys, cut mask, values
+    // ---- this thread's pairs: values first (their loads overlap the item staging)
     const uint32_t pb = c0 + (uint32_t)tid * kChunkPerThread;
     uint32_t key[kChunkPerThread];
     float x[kChunkPerThread][kPartialStride];
@@ -350,15 +348,19 @@ __global__ __launch_bounds__(kChunkThreads) void k_pair_reduce(ViewTable vt, con
             for (int j = 0; j < kPartialStride; ++j)
                 x[u][j] = pb + u < cend ? partial[(size_t)(pb + u) * kPartialStride + j] : 0.f;
     }
+    uint32_t i_lo;
+    const uint32_t nloc = load_chunk_items(vt, sorted_items, poff, chunk_item, n, rec, c, m, nvis, ci, i_lo);
+    // keys and the cut mask (pairs beyond their tile's cut were never written)
     if (pb < cend) {
-        uint32_t k = find_chunk_item(ci, nloc, pb);
+        PairWalker pw;
+        pw.start(ci, nloc, pb);
 #pragma unroll
         for (uint32_t u = 0; u < kChunkPerThread; ++u) {
             const uint32_t p = pb + u;
             if (p < cend) {
-                while (k + 1 < nloc && ci.p0[k + 1] <= p) ++k;
-                key[u] = k;
-                const bool valid = i_lo + k < tile_cut[pair_tile(ci, k, p)].y;
+                if (u > 0) pw.next(ci, nloc, p);
+                key[u] = pw.k;
+                const bool valid = i_lo + pw.k < tile_cut[pw.tile(ci)].y;
 #pragma unroll
                 for (int j = 0; j < kPartialStride; ++j) x[u][j] = valid ? x[u][j] : 0.f;
             } else {
@@ -514,9 +516,54 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(
     constexpr int K = (DEG + 1) * (DEG + 1);
     constexpr bool kVecSH = (3 * K) % 4 == 0;  // SH rows of 16-byte multiples: float4 loads and stores
     __shared__ float red[4 * 12];
-    const uint64_t i = (uint64_t)blockIdx.x * kProjThreads + threadIdx.x;
+    __shared__ uint32_t s_list[kProjThreads];  // block-local indices of the Gaussians seen by some view
+    __shared__ uint32_t s_wcnt[4];
+    __shared__ uint8_t s_vis[kProjThreads];
+    const uint64_t base = (uint64_t)blockIdx.x * kProjThreads;
+    const uint32_t nb = (uint32_t)min((uint64_t)kProjThreads, n - base);
     // after a pair overflow no pair gradient exists: every Gaussian gets zero
-    const bool live = i < n && hdr->overflow == 0u;
+    const bool ovf = hdr->overflow != 0u;
+
+    // ---- the block's Gaussians that some view sees, compacted so that the
+    // chain rule below runs on full waves (most Gaussians are off-screen)
+    {
+        bool vis = false;
+        if (!ovf && threadIdx.x < nb)
+            for (int v = 0; v < vt.n_views; ++v) vis |= count[(uint64_t)v * n + base + threadIdx.x] > 0u;
+        const unsigned long long bal = __ballot(vis);
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        if (lane == 0) s_wcnt[wv] = (uint32_t)__popcll(bal);
+        s_vis[threadIdx.x] = vis ? 1 : 0;
+        __syncthreads();
+        uint32_t off = 0;
+        for (int w = 0; w < wv; ++w) off += s_wcnt[w];
+        if (vis) s_list[off + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull))] = threadIdx.x;
+        __syncthreads();
+    }
+    const uint32_t nlist = s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3];
+    // ---- zero rows of the others, block-wide and coalesced
+    {
+        float *zm = gr.means + 3 * base, *zl = gr.log_scales + 3 * base;
+        for (uint32_t f = threadIdx.x; f < 3 * nb; f += kProjThreads)
+            if (!s_vis[f / 3]) zm[f] = 0.f, zl[f] = 0.f;
+        for (uint32_t f = threadIdx.x; f < nb; f += kProjThreads)
+            if (!s_vis[f]) {
+                reinterpret_cast<float4 *>(gr.quats)[base + f] = make_float4(0.f, 0.f, 0.f, 0.f);
+                gr.opacities[base + f] = 0.f;
+            }
+        if constexpr (kVecSH) {
+            constexpr uint32_t R4 = 3 * K / 4;  // float4 per SH row
+            float4 *zs = reinterpret_cast<float4 *>(gr.sh) + base * R4;
+            for (uint32_t f = threadIdx.x; f < R4 * nb; f += kProjThreads)
+                if (!s_vis[f / R4]) zs[f] = make_float4(0.f, 0.f, 0.f, 0.f);
+        } else {
+            float *zs = gr.sh + base * 3 * K;
+            for (uint32_t f = threadIdx.x; f < 3 * K * nb; f += kProjThreads)
+                if (!s_vis[f / (3 * K)]) zs[f] = 0.f;
+        }
+    }
+    const bool live = threadIdx.x < nlist;
+    const uint64_t i = base + (live ? s_list[threadIdx.x] : 0u);
 
     float gmu[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gop = 0.f;
     bool sh_written = false;  // SH gradient rows are stored by the first visible view, added to by later ones
@@ -759,7 +806,7 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(
             __syncthreads();
         }
     }
-    if (i >= n) return;
+    if (!live) return;  // its rows were zeroed above (or it is one of the zeroed ones)
     gr.means[3 * i] = gmu[0];
     gr.means[3 * i + 1] = gmu[1];
     gr.means[3 * i + 2] = gmu[2];
@@ -768,12 +815,6 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(
     gr.log_scales[3 * i + 2] = gls[2];
     reinterpret_cast<float4 *>(gr.quats)[i] = make_float4(gq[0], gq[1], gq[2], gq[3]);
     gr.opacities[i] = gop;
-    if (!sh_written) {
-        float z[3 * K];
-#pragma unroll
-        for (int k = 0; k < 3 * K; ++k) z[k] = 0.f;
-        store_sh_row<K, kVecSH>(gsh, z);
-    }
 }
 
 void launch_project_bwd(const gsr_gaussians &g, const ViewTable &vt, const float *w2c, uint64_t n, const Rec *rec,

@@ -207,11 +207,17 @@ void launch_pair_offsets(const uint32_t *sorted_items, const uint32_t *count, ui
 // The element count is read on the device: either *n_dev or, for the pair
 // sort, 0 when the header flags an overflow.
 // ---------------------------------------------------------------------------
+// A block sorts TILE consecutive elements (4096 for the pairs; 1024 for the
+// much shorter list of visible items, so that more of the chip takes part).
 // Rounds of 64 consecutive elements per wave: wave w of a block owns the
-// block's elements [w * kSortTile / 4, (w + 1) * kSortTile / 4), which keeps the
-// block's order (wave, round, lane) equal to the input order.
-constexpr int kWaveSpan = kSortTile / (kSortThreads / 64);  // 1024
-constexpr int kRounds = kWaveSpan / 64;                     // 16
+// block's elements [w * TILE / 4, (w + 1) * TILE / 4), which keeps the block's
+// order (wave, round, lane) equal to the input order.
+template <int TILE>
+struct SortShape {
+    static constexpr int kWaveSpan = TILE / (kSortThreads / 64);
+    static constexpr int kRounds = kWaveSpan / 64;
+    static constexpr int kItems = TILE / kSortThreads;
+};
 
 // Lanes of the wave holding the same 8-bit digit as this lane (8 ballots).
 __device__ __forceinline__ unsigned long long digit_peers(bool ok, uint32_t d) {
@@ -225,36 +231,38 @@ __device__ __forceinline__ unsigned long long digit_peers(bool ok, uint32_t d) {
 }
 
 // Per-block digit histogram (LDS atomics; all loads are issued first).
+template <int TILE>
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *__restrict__ keys, SortCount sc,
                                                              int shift, uint32_t *__restrict__ hist,
                                                              uint32_t hist_blocks) {
     __shared__ uint32_t h[256];
     const uint64_t n = sc();
-    const uint64_t blk = (uint64_t)blockIdx.x * kSortTile;
+    const uint64_t blk = (uint64_t)blockIdx.x * TILE;
     if (blk >= n) return;  // blocks past the end are never scanned
-    const uint32_t m = (uint32_t)min((uint64_t)kSortTile, n - blk);
-    uint32_t k[kSortItems];
+    const uint32_t m = (uint32_t)min((uint64_t)TILE, n - blk);
+    uint32_t k[SortShape<TILE>::kItems];
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
+    for (int r = 0; r < SortShape<TILE>::kItems; ++r) {
         const uint32_t li = (uint32_t)r * kSortThreads + threadIdx.x;
         k[r] = li < m ? keys[blk + li] : 0u;
     }
     h[threadIdx.x] = 0;
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r)
+    for (int r = 0; r < SortShape<TILE>::kItems; ++r)
         if ((uint32_t)r * kSortThreads + threadIdx.x < m) atomicAdd(&h[(k[r] >> shift) & 255u], 1u);
     __syncthreads();
     hist[(size_t)threadIdx.x * hist_blocks + blockIdx.x] = h[threadIdx.x];
 }
 
 // One workgroup per digit: exclusive scan of hist[d][0..nb) in place.
+template <int TILE>
 __global__ __launch_bounds__(256) void k_radix_scan(uint32_t *__restrict__ hist, uint32_t hist_blocks, SortCount sc,
                                                     uint32_t *__restrict__ digit_total) {
     __shared__ uint32_t lds[4];
     __shared__ uint32_t carry;
     const uint64_t n = sc();
-    const uint32_t nb = (uint32_t)((n + kSortTile - 1) / kSortTile);
+    const uint32_t nb = (uint32_t)((n + TILE - 1) / TILE);
     uint32_t *row = hist + (size_t)blockIdx.x * hist_blocks;
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
@@ -271,12 +279,13 @@ __global__ __launch_bounds__(256) void k_radix_scan(uint32_t *__restrict__ hist,
     if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
 }
 
-// Stable scatter of one block's kSortTile elements.  Each wave loads its 1024
+// Stable scatter of one block's TILE elements.  Each wave loads its TILE / 4
 // consecutive elements up front, then ranks them round by round against its
 // own running digit counts (ballot peers; no block barrier inside the loop).
 // One barrier later the waves' counts become offsets, the block's elements
 // are placed in LDS in digit order, and written out in contiguous runs per
 // digit (coalesced, instead of one random 4-byte write per element).
+template <int TILE>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *__restrict__ kin,
                                                                 const uint32_t *__restrict__ vin,
                                                                 uint32_t *__restrict__ kout,
@@ -288,18 +297,18 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
     __shared__ uint32_t lbase[256];      // block-local position of the same
     __shared__ uint32_t wcnt[4][256];    // per-wave running digit counts, then per-wave block-local offsets
     __shared__ uint32_t lds[4];
-    __shared__ uint32_t skey[kSortTile], sval[kSortTile];
+    __shared__ uint32_t skey[TILE], sval[TILE];
     const uint64_t n = sc();
-    const uint64_t blk = (uint64_t)blockIdx.x * kSortTile;
+    const uint64_t blk = (uint64_t)blockIdx.x * TILE;
     if (blk >= n) return;
-    const uint32_t nb = (uint32_t)((n + kSortTile - 1) / kSortTile);
+    const uint32_t nb = (uint32_t)((n + TILE - 1) / TILE);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t t = threadIdx.x;
-    const uint32_t m = (uint32_t)min((uint64_t)kSortTile, n - blk);
-    uint32_t key[kRounds], val[kRounds];
+    const uint32_t m = (uint32_t)min((uint64_t)TILE, n - blk);
+    uint32_t key[SortShape<TILE>::kRounds], val[SortShape<TILE>::kRounds];
 #pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
-        const uint32_t li = (uint32_t)(w * kWaveSpan + r * 64 + lane);
+    for (int r = 0; r < SortShape<TILE>::kRounds; ++r) {
+        const uint32_t li = (uint32_t)(w * SortShape<TILE>::kWaveSpan + r * 64 + lane);
         key[r] = li < m ? kin[blk + li] : 0u;
         val[r] = li < m ? vin[blk + li] : 0u;
     }
@@ -314,10 +323,10 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
     for (int k = 0; k < 4; ++k) wcnt[k][t] = 0;
     __syncthreads();
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
-    uint32_t pos[kRounds];
+    uint32_t pos[SortShape<TILE>::kRounds];
 #pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
-        const uint32_t li = (uint32_t)(w * kWaveSpan + r * 64 + lane);
+    for (int r = 0; r < SortShape<TILE>::kRounds; ++r) {
+        const uint32_t li = (uint32_t)(w * SortShape<TILE>::kWaveSpan + r * 64 + lane);
         const bool ok = li < m;
         const uint32_t d = (key[r] >> shift) & 255u;
         const unsigned long long peers = digit_peers(ok, d);
@@ -340,8 +349,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
-        const uint32_t li = (uint32_t)(w * kWaveSpan + r * 64 + lane);
+    for (int r = 0; r < SortShape<TILE>::kRounds; ++r) {
+        const uint32_t li = (uint32_t)(w * SortShape<TILE>::kWaveSpan + r * 64 + lane);
         if (li < m) {
             const uint32_t p = wcnt[w][(key[r] >> shift) & 255u] + pos[r];
             skey[p] = key[r];
@@ -359,22 +368,33 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
     }
 }
 
-void radix_sort_u32(uint32_t *keys[2], uint32_t *vals[2], SortCount sc, uint64_t n_cap, int begin_bit, int end_bit,
-                    uint32_t *hist, uint32_t hist_blocks, uint32_t *digit_total, int &cur, hipStream_t st) {
-    const uint32_t nb = (uint32_t)((n_cap + kSortTile - 1) / kSortTile);
+template <int TILE>
+static void radix_passes(uint32_t *keys[2], uint32_t *vals[2], SortCount sc, uint64_t n_cap, int begin_bit,
+                         int end_bit, uint32_t *hist, uint32_t hist_blocks, uint32_t *digit_total, int &cur,
+                         hipStream_t st) {
+    const uint32_t nb = (uint32_t)((n_cap + TILE - 1) / TILE);
     for (int shift = begin_bit; shift < end_bit; shift += 8) {
         // the result buffer depends only on the number of passes, not on n
         if (nb == 0) {
             cur ^= 1;
             continue;
         }
-        hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kSortThreads), 0, st, keys[cur], sc, shift, hist,
+        hipLaunchKernelGGL(k_radix_hist<TILE>, dim3(nb), dim3(kSortThreads), 0, st, keys[cur], sc, shift, hist,
                            hist_blocks);
-        hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(256), 0, st, hist, hist_blocks, sc, digit_total);
-        hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kSortThreads), 0, st, keys[cur], vals[cur],
+        hipLaunchKernelGGL(k_radix_scan<TILE>, dim3(256), dim3(256), 0, st, hist, hist_blocks, sc, digit_total);
+        hipLaunchKernelGGL(k_radix_scatter<TILE>, dim3(nb), dim3(kSortThreads), 0, st, keys[cur], vals[cur],
                            keys[cur ^ 1], vals[cur ^ 1], sc, shift, hist, hist_blocks, digit_total);
         cur ^= 1;
     }
+}
+
+void radix_sort_u32(uint32_t *keys[2], uint32_t *vals[2], SortCount sc, uint64_t n_cap, int begin_bit, int end_bit,
+                    bool short_list, uint32_t *hist, uint32_t hist_blocks, uint32_t *digit_total, int &cur,
+                    hipStream_t st) {
+    if (short_list)
+        radix_passes<kSortTileShort>(keys, vals, sc, n_cap, begin_bit, end_bit, hist, hist_blocks, digit_total, cur, st);
+    else
+        radix_passes<kSortTile>(keys, vals, sc, n_cap, begin_bit, end_bit, hist, hist_blocks, digit_total, cur, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -411,13 +431,13 @@ __global__ __launch_bounds__(kChunkThreads) void k_emit(ViewTable vt, const uint
     const uint32_t pb = c0 + threadIdx.x * kChunkPerThread;
     if (pb >= cend) return;
     uint32_t key[kChunkPerThread], val[kChunkPerThread];
-    uint32_t k = find_chunk_item(ci, nloc, pb);
+    PairWalker pw;
+    pw.start(ci, nloc, pb);
 #pragma unroll
     for (uint32_t u = 0; u < kChunkPerThread; ++u) {
-        const uint32_t p = pb + u;
-        while (k + 1 < nloc && ci.p0[k + 1] <= p) ++k;
-        key[u] = pair_tile(ci, k, p);
-        val[u] = ci.item[k];
+        if (u > 0) pw.next(ci, nloc, pb + u);
+        key[u] = pw.tile(ci);
+        val[u] = ci.item[pw.k];
     }
     if (pb + kChunkPerThread <= cend) {
         *reinterpret_cast<uint4 *>(pkey + pb) = make_uint4(key[0], key[1], key[2], key[3]);
