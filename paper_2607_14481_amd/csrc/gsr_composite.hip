@@ -65,9 +65,10 @@ __device__ __forceinline__ TileCtx tile_ctx(const ViewTable &vt, uint32_t t) {
 // Staged record (LDS): three float4 per Gaussian.
 //   a = (u - ox, v - oy, -A log2e / 2, -B log2e)
 //   b = (-C log2e / 2, log2(opacity), red, green)
-//   d = (blue, bits(y0 - oy | (y1 - oy) << 16), bits(pair index), opacity)
+//   d = (blue, bits(slab mask), bits(pair index), opacity)
 // so that sigma * log2e = -(a.z dx^2 + a.w dx dy + b.x dy^2) and
-// alpha = min(0.99, exp2(-sigma log2e + b.y)).
+// alpha = min(0.99, exp2(-sigma log2e + b.y)).  Bit k of the slab mask is set
+// when the Gaussian's alpha >= 1/255 box reaches rows [4k, 4k + 3] of the tile.
 __device__ __forceinline__ void stage_record(const Rec &r, const float2 lo, const TileCtx &c, uint32_t tile_h,
                                              float4 &a, float4 &b, float4 &d) {
     const float ut = (r.r0.x - (float)c.ox) + lo.x;
@@ -75,25 +76,25 @@ __device__ __forceinline__ void stage_record(const Rec &r, const float2 lo, cons
     a = make_float4(ut, vt, -0.5f * kLog2e * r.r0.z, -kLog2e * r.r0.w);
     b = make_float4(-0.5f * kLog2e * r.r1.x, __log2f(r.r1.y), r.r1.z, r.r1.w);
     const uint32_t by = __float_as_uint(r.r2.z);
-    const int y0 = (int)(by & 0xffffu) - (int)c.oy, y1 = (int)(by >> 16) - (int)c.oy;
-    // clamp into [-1, tile_h] so the packed fields stay non-negative 16-bit values
-    const uint32_t y0c = (uint32_t)(max(y0, -1) + 1), y1c = (uint32_t)(min(y1, (int)tile_h) + 1);
+    const int y0 = max((int)(by & 0xffffu) - (int)c.oy, 0), y1 = min((int)(by >> 16) - (int)c.oy, (int)tile_h - 1);
+    const uint32_t smask = y0 <= y1 ? ((2u << (y1 >> 2)) - 1u) & ~((1u << (y0 >> 2)) - 1u) : 0u;
     // pair index in emission order: offset + row-major position in the tile box
     const uint32_t bx = __float_as_uint(r.r2.y);
     const uint32_t tx0 = (bx & 0xffffu) / kTileW, tx1 = (bx >> 16) / kTileW;
     const uint32_t ty0 = (by & 0xffffu) / tile_h;
     const uint32_t p = __float_as_uint(r.r2.w) + (c.ty - ty0) * (tx1 - tx0 + 1) + (c.tx - tx0);
-    d = make_float4(r.r2.x, __uint_as_float(y0c | (y1c << 16)), __uint_as_float(p), r.r1.y);
+    d = make_float4(r.r2.x, __uint_as_float(smask), __uint_as_float(p), r.r1.y);
 }
 
-// Does the record's box (rows y0..y1 relative to the tile, stored +1) touch
-// rows [r0, r0 + 3] of the tile?  The operand is wave-uniform (an LDS
-// broadcast), so the branch on it is a scalar branch.
-__device__ __forceinline__ bool slab_hit(float packed, int r0) {
-    const uint32_t u = __builtin_amdgcn_readfirstlane(__float_as_uint(packed));
-    const int y0 = (int)(u & 0xffffu) - 1, y1 = (int)(u >> 16) - 1;
-    return y0 <= r0 + 3 && y1 >= r0;
+// The slab mask of a staged record, as a scalar (the record is an LDS broadcast).
+__device__ __forceinline__ uint32_t slab_mask(float packed) {
+    return __builtin_amdgcn_readfirstlane(__float_as_uint(packed));
 }
+
+// A slab whose every pixel has exponent below this (log2 of alpha before the
+// clamp) cannot reach alpha >= 1/255: skipping it changes no decision (the
+// margin dwarfs the exponential's rounding).
+constexpr float kLog2AlphaSkip = -7.9943534f - 0.01f;  // log2(1/255) - 0.01
 
 __device__ __forceinline__ uint32_t next_tile(bool persistent, uint32_t *queue, uint32_t first, uint32_t &iter) {
     if (!persistent) return iter++ == 0 ? first : 0xffffffffu;
@@ -168,12 +169,15 @@ __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uin
                 const float4 a = sa[j], b = sb[j], d = sd[j];
                 const uint32_t pos = b0 - rg.x + (uint32_t)j;
                 const float dx = a.x - pxl;
+                const uint32_t smask = slab_mask(d.y);
 #pragma unroll
                 for (int k = 0; k < RPL; ++k) {
-                    if (!slab_hit(d.y, 4 * k)) continue;
+                    if (!(smask & (1u << k))) continue;
                     const float dy = a.y - ((float)(ly + 4 * k) + 0.5f);
                     const float e2 = neg_sigma_log2e(a, b, dx, dy);
-                    const float alpha = fminf(kAlphaMax, __builtin_amdgcn_exp2f(e2 + b.y));
+                    const float ex = e2 + b.y;
+                    if (__ballot(T[k] > 0.f && ex >= kLog2AlphaSkip) == 0ull) continue;
+                    const float alpha = fminf(kAlphaMax, __builtin_amdgcn_exp2f(ex));
                     const bool ok = e2 <= 0.f && alpha >= kAlphaMin;
                     const float Tn = T[k] * (1.f - alpha);
                     // a stopped pixel has Tn <= 0 < kTMin, so it never adds again
@@ -318,12 +322,15 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
                         const uint32_t pos = b0 - rg.x + (uint32_t)j;
                         const float4 a = sa[j], b = sb[j], d = sd[j];
                         const float dx = a.x - pxl;
+                        const uint32_t smask = slab_mask(d.y);
 #pragma unroll
                         for (int k = 0; k < RPL; ++k) {
-                            if (!slab_hit(d.y, 4 * k)) continue;
+                            if (!(smask & (1u << k))) continue;
                             const float dy = a.y - ((float)(ly + 4 * k) + 0.5f);
                             const float e2 = neg_sigma_log2e(a, b, dx, dy);
-                            const float araw = __builtin_amdgcn_exp2f(e2 + b.y);
+                            const float ex = e2 + b.y;
+                            if (__ballot(pos < ncon[k] && ex >= kLog2AlphaSkip) == 0ull) continue;
+                            const float araw = __builtin_amdgcn_exp2f(ex);
                             const float alpha = fminf(kAlphaMax, araw);
                             const bool ok = pos < ncon[k] && e2 <= 0.f && alpha >= kAlphaMin;
                             const float w = ok ? alpha * T[k] : 0.f;
