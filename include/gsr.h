@@ -228,6 +228,78 @@ int gsr_export_state(const void *ws, size_t ws_bytes, const gsr_gaussians *g, in
                      uint32_t *pair_items, uint32_t *ranges, float *records, float *centre_lo,
                      uint32_t *depth_keys, uint32_t *tile_counts, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Parameter updates around the rasterizer.  All arrays are device memory,
+ * caller-owned, 16-byte aligned, and updated in place on `stream`; no entry
+ * point allocates.  Status codes and gsr_last_error() as above.
+ * ------------------------------------------------------------------------ */
+
+/* Mutable views of the five Gaussian arrays (shapes and layout of
+   gsr_gaussians); also used for the optimiser's two moment arrays. */
+typedef struct gsr_param_set {
+    float *means;
+    float *log_scales;
+    float *quats;
+    float *opacities;
+    float *sh;
+} gsr_param_set;
+
+typedef struct gsr_adam_config {
+    float lr_means, lr_log_scales, lr_quats, lr_opacities;
+    float lr_sh_dc;    /* SH coefficient k = 0 */
+    float lr_sh_rest;  /* SH coefficients k >= 1 */
+    float beta1, beta2, eps;
+    int32_t sparse;    /* 1: only Gaussians that some view of the last forward on ws saw are
+                          updated (parameters and moments); the others are left untouched */
+    int32_t reserved[4];
+} gsr_adam_config;
+
+/*
+ * One Adam step of the joint optimisation (each keyframe trains the model for
+ * 30 iterations of render, loss and update: Sec. 5.2; the renderer's lineage
+ * optimises with Adam) from gradients such as gsr_rasterize_backward writes.
+ * For every array element, with t = step >= 1:
+ *   m <- b1 m + (1 - b1) g,  v <- b2 v + (1 - b2) g^2,
+ *   p <- p - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+ * Opacities are activated values in (0, 1): their step is taken on the logit
+ * l = ln(o / (1 - o)), with g = o (1 - o) dL/do, and o <- 1 / (1 + e^-l); their
+ * moments therefore refer to the logit.  Opacities are first clamped to
+ * [1e-7, 1 - 1e-7].  ws/ws_bytes/n_views/cams/cfg are those of the last
+ * forward (read only when acfg->sparse is set; ws may then not be NULL).
+ * exp_avg and exp_avg_sq start at zero and are owned by the caller.
+ */
+int gsr_adam_step(void *ws, size_t ws_bytes, int64_t n, int32_t sh_degree, int32_t n_views,
+                  const gsr_camera *cams, const gsr_launch_config *cfg, const gsr_param_set *params,
+                  const gsr_gaussian_grads *grads, const gsr_param_set *exp_avg,
+                  const gsr_param_set *exp_avg_sq, int64_t step, const gsr_adam_config *acfg, void *stream);
+
+/*
+ * Pose update of the joint optimisation: one Adam step on each view's 6-DoF
+ * twist gradient (translation first, the convention of dL_dtwist in
+ * gsr_rasterize_backward), then the SE(3) retraction
+ *   world_to_cam <- exp(xi^) world_to_cam,  xi = -lr m_hat / (sqrt(v_hat) + eps),
+ * with exp the closed-form SE(3) exponential (Rodrigues' rotation and its
+ * left Jacobian for the translation), evaluated in double precision.
+ * world_to_cam [n_views][16] row-major; dL_dtwist, exp_avg, exp_avg_sq
+ * [n_views][6]; step >= 1; 1 <= n_views <= GSR_MAX_VIEWS.
+ */
+int gsr_pose_step(float *world_to_cam, const float *dL_dtwist, float *exp_avg, float *exp_avg_sq,
+                  int32_t n_views, int64_t step, float lr, float beta1, float beta2, float eps, void *stream);
+
+/*
+ * Loop-closure relocation (Sec. 6.3: every Gaussian follows the Sim(3)
+ * correction of the keyframe that spawned it, with its scale and rotation
+ * updated accordingly).  For Gaussian i with k = keyframe_of[i] in
+ * [0, n_keyframes) and sim3[k] = (s, qw, qx, qy, qz, tx, ty, tz) (unit q):
+ *   mean <- s R(q) mean + t,  quat <- q * quat (Hamilton product),
+ *   log-scales <- log-scales + ln s;  opacity and SH are unchanged.
+ * Gaussians with k outside [0, n_keyframes) are left as they are.  The same
+ * call moves hierarchy nodes (pass each node's keyframe).  keyframe_of [n]
+ * and sim3 [n_keyframes][8] are device arrays.
+ */
+int gsr_sim3_relocate(const gsr_param_set *params, int64_t n, const int32_t *keyframe_of, const float *sim3,
+                      int32_t n_keyframes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

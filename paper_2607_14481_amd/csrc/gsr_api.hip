@@ -2,6 +2,7 @@
 // checks, workspace layout and the launch sequence of each pass.  The library
 // never allocates device memory; all state of a pass lives in the caller's
 // workspace.
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -438,6 +439,124 @@ int gsr_export_state(const void *ws, size_t ws_bytes, const gsr_gaussians *g, in
         if ((rc = check_hip(hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyDeviceToDevice, st), "export copy"))) return rc;
     }
     return GSR_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+gsr::AdamScalars adam_scalars(float beta1, float beta2, float eps, int64_t step, double &bc1) {
+    gsr::AdamScalars a;
+    a.b1 = beta1;
+    a.b2 = beta2;
+    a.one_m_b1 = 1.f - beta1;
+    a.one_m_b2 = 1.f - beta2;
+    a.eps = eps;
+    bc1 = 1.0 - std::pow((double)beta1, (double)step);
+    a.inv_sqrt_bc2 = (float)(1.0 / std::sqrt(1.0 - std::pow((double)beta2, (double)step)));
+    return a;
+}
+
+int check_adam_hyper(float beta1, float beta2, float eps, int64_t step) {
+    if (step < 1) return fail(GSR_ERR_INVALID_ARGUMENT, "step=%lld must be >= 1", (long long)step);
+    if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+        return fail(GSR_ERR_INVALID_ARGUMENT, "need 0 <= beta1, beta2 < 1 and eps > 0");
+    return GSR_OK;
+}
+
+int check_param_set(const float *const ptrs[5], bool sh_vec, const char *what) {
+    for (int k = 0; k < 5; ++k)
+        if (!ptrs[k]) return fail(GSR_ERR_INVALID_ARGUMENT, "%s: array %d is NULL", what, k);
+    if (reinterpret_cast<uintptr_t>(ptrs[2]) & 15u) return fail(GSR_ERR_INVALID_ARGUMENT, "%s: quats not 16-byte aligned", what);
+    if (sh_vec && (reinterpret_cast<uintptr_t>(ptrs[4]) & 15u))
+        return fail(GSR_ERR_INVALID_ARGUMENT, "%s: sh not 16-byte aligned", what);
+    return GSR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gsr_adam_step(void *ws, size_t ws_bytes, int64_t n, int32_t sh_degree, int32_t n_views, const gsr_camera *cams,
+                  const gsr_launch_config *cfg, const gsr_param_set *params, const gsr_gaussian_grads *grads,
+                  const gsr_param_set *exp_avg, const gsr_param_set *exp_avg_sq, int64_t step,
+                  const gsr_adam_config *acfg, void *stream) {
+    using namespace gsr;
+    if (n < 0 || n > 0x7fffffffll) return fail(GSR_ERR_INVALID_ARGUMENT, "n=%lld outside 0..2^31-1", (long long)n);
+    if (sh_degree < 0 || sh_degree > 3) return fail(GSR_ERR_UNSUPPORTED, "sh_degree=%d (supported: 0..3)", sh_degree);
+    if (!params || !grads || !exp_avg || !exp_avg_sq || !acfg)
+        return fail(GSR_ERR_INVALID_ARGUMENT, "params, grads, exp_avg, exp_avg_sq and acfg must not be NULL");
+    int rc = check_adam_hyper(acfg->beta1, acfg->beta2, acfg->eps, step);
+    if (rc) return rc;
+    const int K = (sh_degree + 1) * (sh_degree + 1);
+    const bool sh_vec = (3 * K) % 4 == 0;
+    if (n > 0) {
+        const float *const sets[4][5] = {
+            {params->means, params->log_scales, params->quats, params->opacities, params->sh},
+            {grads->means, grads->log_scales, grads->quats, grads->opacities, grads->sh},
+            {exp_avg->means, exp_avg->log_scales, exp_avg->quats, exp_avg->opacities, exp_avg->sh},
+            {exp_avg_sq->means, exp_avg_sq->log_scales, exp_avg_sq->quats, exp_avg_sq->opacities, exp_avg_sq->sh}};
+        const char *names[4] = {"params", "grads", "exp_avg", "exp_avg_sq"};
+        for (int s = 0; s < 4; ++s)
+            if ((rc = check_param_set(sets[s], sh_vec, names[s]))) return rc;
+    }
+    AdamArgs A{};
+    A.p = *params;
+    A.g = *grads;
+    A.m = *exp_avg;
+    A.v = *exp_avg_sq;
+    A.n = (uint64_t)n;
+    A.sh_k = K;
+    A.n_views = n_views;
+    A.count = nullptr;
+    if (acfg->sparse) {
+        ViewTable vt;
+        if (!ws) return fail(GSR_ERR_INVALID_ARGUMENT, "sparse Adam needs the workspace of the last forward");
+        if ((rc = build_views(n_views, cams, cfg, vt))) return rc;
+        WsLayout L;
+        uint64_t cap = 0;
+        if ((rc = layout_from_bytes((uint64_t)n, vt, ws_bytes, L, cap))) return rc;
+        A.count = reinterpret_cast<const uint32_t *>(static_cast<const char *>(ws) + L.count);
+    }
+    double bc1 = 0.0;
+    A.a = adam_scalars(acfg->beta1, acfg->beta2, acfg->eps, step, bc1);
+    const float lrs[6] = {acfg->lr_means, acfg->lr_log_scales, acfg->lr_quats, acfg->lr_opacities, acfg->lr_sh_dc,
+                          acfg->lr_sh_rest};
+    for (int k = 0; k < 6; ++k) A.step_size[k] = (float)((double)lrs[k] / bc1);
+    launch_adam_step(A, static_cast<hipStream_t>(stream));
+    return check_hip(hipGetLastError(), "adam launch");
+}
+
+int gsr_pose_step(float *world_to_cam, const float *dL_dtwist, float *exp_avg, float *exp_avg_sq, int32_t n_views,
+                  int64_t step, float lr, float beta1, float beta2, float eps, void *stream) {
+    using namespace gsr;
+    if (n_views < 1 || n_views > GSR_MAX_VIEWS)
+        return fail(GSR_ERR_INVALID_ARGUMENT, "n_views=%d outside 1..%d", n_views, GSR_MAX_VIEWS);
+    if (!world_to_cam || !dL_dtwist || !exp_avg || !exp_avg_sq)
+        return fail(GSR_ERR_INVALID_ARGUMENT, "world_to_cam, dL_dtwist, exp_avg and exp_avg_sq must not be NULL");
+    int rc = check_adam_hyper(beta1, beta2, eps, step);
+    if (rc) return rc;
+    double bc1 = 0.0;
+    const AdamScalars a = adam_scalars(beta1, beta2, eps, step, bc1);
+    launch_pose_step(world_to_cam, dL_dtwist, exp_avg, exp_avg_sq, n_views, a, (float)((double)lr / bc1),
+                     static_cast<hipStream_t>(stream));
+    return check_hip(hipGetLastError(), "pose step launch");
+}
+
+int gsr_sim3_relocate(const gsr_param_set *params, int64_t n, const int32_t *keyframe_of, const float *sim3,
+                      int32_t n_keyframes, void *stream) {
+    using namespace gsr;
+    if (n < 0 || n > 0x7fffffffll) return fail(GSR_ERR_INVALID_ARGUMENT, "n=%lld outside 0..2^31-1", (long long)n);
+    if (n_keyframes < 0) return fail(GSR_ERR_INVALID_ARGUMENT, "n_keyframes=%d is negative", n_keyframes);
+    if (!params) return fail(GSR_ERR_INVALID_ARGUMENT, "params must not be NULL");
+    if (n == 0) return GSR_OK;
+    if (!params->means || !params->quats || !params->log_scales || !keyframe_of || (n_keyframes > 0 && !sim3))
+        return fail(GSR_ERR_INVALID_ARGUMENT, "means, quats, log_scales, keyframe_of and sim3 must not be NULL");
+    if (reinterpret_cast<uintptr_t>(params->quats) & 15u)
+        return fail(GSR_ERR_INVALID_ARGUMENT, "quats must be 16-byte aligned");
+    launch_sim3_relocate(params->means, params->quats, params->log_scales, (uint64_t)n, keyframe_of, sim3, n_keyframes,
+                         static_cast<hipStream_t>(stream));
+    return check_hip(hipGetLastError(), "relocation launch");
 }
 
 }  // extern "C"

@@ -162,6 +162,26 @@ void launch_project_bwd(const gsr_gaussians &g, const ViewTable &vt, const float
 void launch_pose_finalize(const ViewTable &vt, const float *w2c, const float *pose_part, uint32_t pose_blocks,
                           float *dL_dw2c, float *dL_dtwist, hipStream_t st);
 
+// Parameter updates (gsr_update.hip).
+struct AdamScalars {
+    float b1, b2, one_m_b1, one_m_b2, eps;
+    float inv_sqrt_bc2;  // 1 / sqrt(1 - b2^t)
+};
+struct AdamArgs {
+    gsr_param_set p, m, v;
+    gsr_gaussian_grads g;
+    const uint32_t *count;  // tiles touched per (view, Gaussian) of the last forward; NULL = update all
+    uint64_t n;
+    int32_t n_views, sh_k;  // sh_k = (degree + 1)^2
+    AdamScalars a;
+    float step_size[6];     // lr / (1 - b1^t): means, log-scales, quats, opacities, SH DC, SH rest
+};
+void launch_adam_step(const AdamArgs &A, hipStream_t st);
+void launch_pose_step(float *w2c, const float *g, float *m, float *v, int n_views, const AdamScalars &a,
+                      float step_size, hipStream_t st);
+void launch_sim3_relocate(float *means, float *quats, float *log_scales, uint64_t n, const int32_t *keyframe_of,
+                          const float *sim3, int32_t n_keyframes, hipStream_t st);
+
 // ---------------------------------------------------------------------------
 // Device helpers
 // ---------------------------------------------------------------------------

@@ -28,7 +28,7 @@ GSR_FLAG_STATS = 4
 
 EXPORTED = ("gsr_version", "gsr_status_string", "gsr_last_error", "gsr_workspace_bytes",
             "gsr_rasterize_forward", "gsr_rasterize_backward", "gsr_query_pairs", "gsr_query_stats",
-            "gsr_export_state")
+            "gsr_export_state", "gsr_adam_step", "gsr_pose_step", "gsr_sim3_relocate")
 
 
 class GsrError(RuntimeError):
@@ -58,6 +58,18 @@ class gsr_gaussian_grads(C.Structure):
 
 class gsr_launch_config(C.Structure):
     _fields_ = [("tile_h", C.c_int32), ("persistent_ctas", C.c_int32), ("stage_events", C.c_void_p),
+                ("reserved", C.c_int32 * 4)]
+
+
+class gsr_param_set(C.Structure):
+    _fields_ = [("means", C.c_void_p), ("log_scales", C.c_void_p), ("quats", C.c_void_p),
+                ("opacities", C.c_void_p), ("sh", C.c_void_p)]
+
+
+class gsr_adam_config(C.Structure):
+    _fields_ = [("lr_means", C.c_float), ("lr_log_scales", C.c_float), ("lr_quats", C.c_float),
+                ("lr_opacities", C.c_float), ("lr_sh_dc", C.c_float), ("lr_sh_rest", C.c_float),
+                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float), ("sparse", C.c_int32),
                 ("reserved", C.c_int32 * 4)]
 
 
@@ -103,6 +115,16 @@ def lib():
         L.gsr_export_state.restype = C.c_int
         L.gsr_export_state.argtypes = [vp, sz, C.POINTER(gsr_gaussians), C.c_int32, C.POINTER(gsr_camera),
                                        C.POINTER(gsr_launch_config), vp, vp, vp, vp, vp, vp, vp, vp]
+        L.gsr_adam_step.restype = C.c_int
+        L.gsr_adam_step.argtypes = [vp, sz, C.c_int64, C.c_int32, C.c_int32, C.POINTER(gsr_camera),
+                                    C.POINTER(gsr_launch_config), C.POINTER(gsr_param_set),
+                                    C.POINTER(gsr_gaussian_grads), C.POINTER(gsr_param_set),
+                                    C.POINTER(gsr_param_set), C.c_int64, C.POINTER(gsr_adam_config), vp]
+        L.gsr_pose_step.restype = C.c_int
+        L.gsr_pose_step.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int64, C.c_float, C.c_float, C.c_float,
+                                    C.c_float, vp]
+        L.gsr_sim3_relocate.restype = C.c_int
+        L.gsr_sim3_relocate.argtypes = [C.POINTER(gsr_param_set), C.c_int64, vp, vp, C.c_int32, vp]
         _lib = L
     return _lib
 
@@ -264,3 +286,51 @@ def export_state(ws: torch.Tensor, params: Sequence[torch.Tensor], sh_degree: in
     res["centre_lo"] = res["centre_lo"][:items]
     res["M"] = m
     return res
+
+
+def param_set(tensors: Sequence[torch.Tensor]) -> gsr_param_set:
+    ps = gsr_param_set()
+    ps.means, ps.log_scales, ps.quats, ps.opacities, ps.sh = [_ptr(t) for t in tensors]
+    return ps
+
+
+def adam_config(lr_means=1.6e-4, lr_log_scales=5e-3, lr_quats=1e-3, lr_opacities=5e-2, lr_sh_dc=2.5e-3,
+                lr_sh_rest=2.5e-3 / 20, beta1=0.9, beta2=0.999, eps=1e-15, sparse=False) -> gsr_adam_config:
+    """Defaults are the 3DGS lineage's learning rates (position rate without its decay schedule)."""
+    a = gsr_adam_config()
+    a.lr_means, a.lr_log_scales, a.lr_quats, a.lr_opacities = lr_means, lr_log_scales, lr_quats, lr_opacities
+    a.lr_sh_dc, a.lr_sh_rest = lr_sh_dc, lr_sh_rest
+    a.beta1, a.beta2, a.eps, a.sparse = beta1, beta2, eps, int(bool(sparse))
+    return a
+
+
+def adam_step(params: Sequence[torch.Tensor], grads: Sequence[torch.Tensor], exp_avg: Sequence[torch.Tensor],
+              exp_avg_sq: Sequence[torch.Tensor], sh_degree: int, step: int, acfg: gsr_adam_config,
+              ws: Optional[torch.Tensor] = None, cams: Optional[Sequence] = None,
+              cfg: Optional[gsr_launch_config] = None, stream=None):
+    """In-place Adam step on the five Gaussian arrays (see gsr_adam_step)."""
+    gr = gsr_gaussian_grads()
+    gr.means, gr.log_scales, gr.quats, gr.opacities, gr.sh = [_ptr(t) for t in grads]
+    p, m, v = param_set(params), param_set(exp_avg), param_set(exp_avg_sq)
+    arr = cameras(cams) if cams is not None else None
+    _check(lib().gsr_adam_step(_ptr(ws), ws.numel() if ws is not None else 0, int(params[0].shape[0]),
+                               int(sh_degree), len(cams) if cams is not None else 0, arr,
+                               C.byref(cfg) if cfg is not None else None, C.byref(p), C.byref(gr), C.byref(m),
+                               C.byref(v), int(step), C.byref(acfg), _stream_ptr(stream)))
+
+
+def pose_step(world_to_cam: torch.Tensor, dL_dtwist: torch.Tensor, exp_avg: torch.Tensor,
+              exp_avg_sq: torch.Tensor, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+              eps: float = 1e-15, stream=None):
+    """In-place Adam step on the twists and SE(3) retraction of world_to_cam [V, 4, 4]."""
+    _check(lib().gsr_pose_step(_ptr(world_to_cam), _ptr(dL_dtwist), _ptr(exp_avg), _ptr(exp_avg_sq),
+                               int(world_to_cam.shape[0]), int(step), float(lr), float(beta1), float(beta2),
+                               float(eps), _stream_ptr(stream)))
+
+
+def sim3_relocate(params: Sequence[torch.Tensor], keyframe_of: torch.Tensor, sim3: torch.Tensor, stream=None):
+    """In-place Sim(3) relocation: sim3 [K, 8] = (s, qw, qx, qy, qz, tx, ty, tz); keyframe_of [n] int32."""
+    if keyframe_of.dtype != torch.int32 or sim3.dtype != torch.float32:
+        raise TypeError("keyframe_of must be int32 and sim3 float32")
+    _check(lib().gsr_sim3_relocate(C.byref(param_set(params)), int(params[0].shape[0]), _ptr(keyframe_of),
+                                   _ptr(sim3), int(sim3.shape[0]), _stream_ptr(stream)))

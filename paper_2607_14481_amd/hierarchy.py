@@ -4,7 +4,7 @@ Host-side preparation of the hierarchical workload; the rasterizer then runs
 over the selected cut like over any other Gaussian set.
 
 The paper keeps large scenes tractable with a hierarchy whose inner nodes are
-merges of their children, chosen per view by screen size (Sec. 6, "A
+merges of their children, chosen per view by screen size (Sec. 7, "A
 Progressive Gaussian Hierarchy": nodes hold full Gaussian parameters; children
 are merged by a KL-divergence criterion; rendering descends from the roots
 until nodes are finer than a pixel threshold or are leaves).  This module builds

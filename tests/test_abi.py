@@ -14,7 +14,7 @@ LIB = os.path.join(ROOT, "paper_2607_14481_amd", "libgsr.so")
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(gsr_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(gsr_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_declares_the_boundary():
