@@ -299,6 +299,46 @@ def run_keyframe(wl, iterations=30, repeats=3):
                                 "algorithmic_bytes": nbytes, "GB_per_s": round(nbytes / us / 1e3, 1)}}
 
 
+def run_lod_cut_gpu(wl, reps=10):
+    """The level-of-detail cut on the GPU for the street hierarchy (all nodes
+    resident in HBM): cut selection (blocking: includes reading the count
+    back) and the gather of the cut's rows, checked against the host cut."""
+    import numpy as np
+    import torch
+    from paper_2607_14481_amd import gsr
+    h, host_cut = wl.extra["hierarchy"], wl.extra["cut"]
+    cam = wl.cameras[0]
+    dev = torch.device("cuda")
+    nodes = [torch.tensor(np.asarray(getattr(h.nodes, k), np.float32), device=dev)
+             for k in ("means", "log_scales", "quats", "opacities", "sh")]
+    parent = torch.tensor(h.parent.astype(np.int32), device=dev)
+    counts = torch.tensor(h.child_count.astype(np.int32), device=dev)
+    w2c = torch.tensor(np.asarray(cam.world_to_cam, np.float32), device=dev)
+    scratch = torch.empty(gsr.lib().gsr_hierarchy_cut_scratch_bytes(int(h.nodes.n)), dtype=torch.uint8, device=dev)
+    out = torch.empty(int(h.nodes.n), dtype=torch.int32, device=dev)
+    cut = gsr.hierarchy_cut(nodes, 3, parent, counts, cam, w2c, 1.5, scratch=scratch, out=out)
+    same = bool(np.array_equal(cut.cpu().numpy(), host_cut))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        cut = gsr.hierarchy_cut(nodes, 3, parent, counts, cam, w2c, 1.5, scratch=scratch, out=out)
+    ms_cut = (time.perf_counter() - t) * 1e3 / reps
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    sub = gsr.gather_gaussians(nodes, 3, cut)
+    a.record()
+    for _ in range(reps):
+        sub = gsr.gather_gaussians(nodes, 3, cut)
+    b.record()
+    torch.cuda.synchronize()
+    ms_gather = a.elapsed_time(b) / reps
+    row = 4 * (3 + 3 + 4 + 1 + 48)
+    log(f"[bench] lod cut on the GPU: {cut.numel()} of {h.nodes.n} nodes in {ms_cut:.3f} ms (same as host: {same}); "
+        f"gather {ms_gather:.3f} ms")
+    return {"nodes": int(h.nodes.n), "cut": int(cut.numel()), "same_as_host_cut": same,
+            "cut_ms_blocking": round(ms_cut, 4), "gather_ms": round(ms_gather, 4),
+            "gather_GB_per_s": round(2 * row * cut.numel() / (ms_gather * 1e-3) / 1e9, 1)}
+
+
 def run_ring(steps, warmup):
     """8 cameras (mixed 640x480 / 1280x720 / 1920x1080) on a 15 m ring around
     1M Gaussians, SH degree 3: one step = fwd + L1 + bwd over all 8 views,
@@ -450,6 +490,8 @@ def main():
                             "graph_error": om["graph_err"],
                             "stage_ms": {k: round(v, 4) for k, v in om["stage_ms"].items()},
                             "work": om["stats"], "meta": owl.meta, "_wl": owl}
+            if name == "lod_cut":
+                others[name]["gpu_cut"] = run_lod_cut_gpu(owl)
             del om
             torch.cuda.empty_cache()
 

@@ -300,6 +300,38 @@ int gsr_pose_step(float *world_to_cam, const float *dL_dtwist, float *exp_avg, f
 int gsr_sim3_relocate(const gsr_param_set *params, int64_t n, const int32_t *keyframe_of, const float *sim3,
                       int32_t n_keyframes, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Level of detail (Sec. 7).
+ * ------------------------------------------------------------------------ */
+
+/* Bytes of device scratch memory gsr_hierarchy_cut needs for n_nodes nodes
+   (0 with gsr_last_error() set for a bad n_nodes). */
+size_t gsr_hierarchy_cut_scratch_bytes(int64_t n_nodes);
+
+/*
+ * Per-view cut of a Gaussian hierarchy (Sec. 7.2: rendering starts at the
+ * roots and descends until a node is finer than a screen-size threshold or
+ * is a leaf).  nodes: every node's parameters (only means and log_scales are
+ * read; n = nodes->n); parent [n] (negative for roots), child_count [n] (0 for
+ * leaves), device int32.  With S(i) = max(fx, fy) exp(max_a log_scale_a(i)) /
+ * |mean(i) - camera centre| (double precision), node i is in the cut when it
+ * is a leaf or S(i) < tau, and every ancestor has children and S >= tau.
+ * cut_nodes [n] (device) receives the cut in ascending node order and *n_cut
+ * (host) its size.  world_to_cam: device [16] of the view.  scratch: device
+ * memory of gsr_hierarchy_cut_scratch_bytes(n) bytes, 256-byte aligned.
+ * Blocking: waits for `stream` to read the count.  Ancestor chains longer than
+ * 64 (or cyclic parent links) end the chain: such a node is not in the cut.
+ */
+int gsr_hierarchy_cut(const gsr_gaussians *nodes, const int32_t *parent, const int32_t *child_count,
+                      const gsr_camera *cam, const float *world_to_cam, float tau, void *scratch,
+                      size_t scratch_bytes, int32_t *cut_nodes, int64_t *n_cut, void *stream);
+
+/* Copies rows index[0 .. n_index) of src into rows 0 .. n_index of dst (all
+   five arrays; src->sh_degree gives the SH row length), e.g. to rasterize a
+   cut.  index: device int32, each in [0, src->n). */
+int gsr_gather_gaussians(const gsr_gaussians *src, const int32_t *index, int64_t n_index,
+                         const gsr_param_set *dst, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

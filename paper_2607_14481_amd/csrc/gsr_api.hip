@@ -560,3 +560,83 @@ int gsr_sim3_relocate(const gsr_param_set *params, int64_t n, const int32_t *key
 }
 
 }  // extern "C"
+
+namespace {
+
+struct CutScratch {
+    size_t descend, in_cut, block_tmp, count, total;
+};
+
+CutScratch cut_scratch_layout(uint64_t n) {
+    CutScratch c{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    c.descend = take(n);
+    c.in_cut = take(n);
+    c.block_tmp = take(4 * std::max<uint64_t>(1, gsr::scan_blocks_for(n)));
+    c.count = take(4);
+    c.total = o;
+    return c;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t gsr_hierarchy_cut_scratch_bytes(int64_t n_nodes) {
+    if (n_nodes < 0 || n_nodes > 0x7fffffffll) return (size_t)fail(0, "n_nodes=%lld outside 0..2^31-1", (long long)n_nodes);
+    return cut_scratch_layout((uint64_t)n_nodes).total;
+}
+
+int gsr_hierarchy_cut(const gsr_gaussians *nodes, const int32_t *parent, const int32_t *child_count,
+                      const gsr_camera *cam, const float *world_to_cam, float tau, void *scratch, size_t scratch_bytes,
+                      int32_t *cut_nodes, int64_t *n_cut, void *stream) {
+    using namespace gsr;
+    if (!nodes || !cam || !n_cut) return fail(GSR_ERR_INVALID_ARGUMENT, "nodes, cam and n_cut must not be NULL");
+    if (nodes->n < 0 || nodes->n > 0x7fffffffll)
+        return fail(GSR_ERR_INVALID_ARGUMENT, "n=%lld outside 0..2^31-1", (long long)nodes->n);
+    if (!(tau > 0.f)) return fail(GSR_ERR_INVALID_ARGUMENT, "tau must be positive");
+    const uint64_t n = (uint64_t)nodes->n;
+    *n_cut = 0;
+    if (n == 0) return GSR_OK;
+    if (!nodes->means || !nodes->log_scales || !parent || !child_count || !world_to_cam || !scratch || !cut_nodes)
+        return fail(GSR_ERR_INVALID_ARGUMENT, "a device pointer is NULL");
+    if (reinterpret_cast<uintptr_t>(scratch) & 255u) return fail(GSR_ERR_INVALID_ARGUMENT, "scratch must be 256-byte aligned");
+    const CutScratch L = cut_scratch_layout(n);
+    if (scratch_bytes < L.total) return fail(GSR_ERR_WORKSPACE_TOO_SMALL, "scratch %zu < %zu bytes", scratch_bytes, L.total);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *b = static_cast<char *>(scratch);
+    uint8_t *descend = reinterpret_cast<uint8_t *>(b + L.descend), *in_cut = reinterpret_cast<uint8_t *>(b + L.in_cut);
+    uint32_t *count = reinterpret_cast<uint32_t *>(b + L.count);
+    launch_hierarchy_cut_flags(nodes->means, nodes->log_scales, parent, child_count, n, world_to_cam,
+                               std::max(cam->fx, cam->fy), tau, descend, in_cut, st);
+    launch_compact_flags(in_cut, n, reinterpret_cast<uint32_t *>(cut_nodes), reinterpret_cast<uint32_t *>(b + L.block_tmp),
+                         count, st);
+    uint32_t h = 0;
+    int rc = check_hip(hipMemcpyAsync(&h, count, 4, hipMemcpyDeviceToHost, st), "cut count copy");
+    if (rc) return rc;
+    if ((rc = check_hip(hipStreamSynchronize(st), "stream sync"))) return rc;
+    *n_cut = h;
+    return GSR_OK;
+}
+
+int gsr_gather_gaussians(const gsr_gaussians *src, const int32_t *index, int64_t n_index, const gsr_param_set *dst,
+                         void *stream) {
+    using namespace gsr;
+    int rc = check_gaussians(src);
+    if (rc) return rc;
+    if (!dst || n_index < 0) return fail(GSR_ERR_INVALID_ARGUMENT, "dst is NULL or n_index < 0");
+    if (n_index == 0) return GSR_OK;
+    if (!index || !dst->means || !dst->log_scales || !dst->quats || !dst->opacities || !dst->sh)
+        return fail(GSR_ERR_INVALID_ARGUMENT, "index or a destination array is NULL");
+    if ((reinterpret_cast<uintptr_t>(dst->quats) | reinterpret_cast<uintptr_t>(dst->sh)) & 15u)
+        return fail(GSR_ERR_INVALID_ARGUMENT, "dst quats and sh must be 16-byte aligned");
+    launch_gather_gaussians(*src, index, (uint64_t)n_index, *dst, static_cast<hipStream_t>(stream));
+    return check_hip(hipGetLastError(), "gather launch");
+}
+
+}  // extern "C"

@@ -162,6 +162,18 @@ void launch_project_bwd(const gsr_gaussians &g, const ViewTable &vt, const float
 void launch_pose_finalize(const ViewTable &vt, const float *w2c, const float *pose_part, uint32_t pose_blocks,
                           float *dL_dw2c, float *dL_dtwist, hipStream_t st);
 
+// Ordered compaction of byte flags (gsr_sort.hip).
+void launch_compact_flags(const uint8_t *flags, uint64_t n, uint32_t *out_idx, uint32_t *block_tmp,
+                          uint32_t *out_count, hipStream_t st);
+inline uint64_t scan_blocks_for(uint64_t n) { return (n + kScanTile - 1) / kScanTile; }
+
+// Level-of-detail cut and row gather (gsr_hierarchy.hip).
+void launch_hierarchy_cut_flags(const float *means, const float *log_scales, const int32_t *parent,
+                                const int32_t *child_count, uint64_t n, const float *w2c, float focal, float tau,
+                                uint8_t *descend, uint8_t *in_cut, hipStream_t st);
+void launch_gather_gaussians(const gsr_gaussians &src, const int32_t *index, uint64_t n_out, const gsr_param_set &dst,
+                             hipStream_t st);
+
 // Parameter updates (gsr_update.hip).
 struct AdamScalars {
     float b1, b2, one_m_b1, one_m_b2, eps;

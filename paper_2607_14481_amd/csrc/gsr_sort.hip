@@ -152,6 +152,42 @@ void launch_compact_visible(const uint32_t *count, const uint32_t *zkey, uint64_
                        cval);
 }
 
+// Ordered compaction of byte flags: out_idx receives, in ascending order, the
+// indices i < n with flags[i] != 0; their number goes to *out_count.
+struct ByteFlag {
+    const uint8_t *f;
+    __device__ uint32_t operator()(uint64_t i) const { return f[i] ? 1u : 0u; }
+};
+
+__global__ __launch_bounds__(kScanThreads) void k_flag_compact_apply(const uint8_t *__restrict__ flags, uint64_t n,
+                                                                     const uint32_t *__restrict__ block_sums,
+                                                                     uint32_t *__restrict__ out_idx) {
+    __shared__ uint32_t lds[4];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+    uint32_t bits = 0, cnt = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const bool on = base + k < n && flags[base + k] != 0;
+        bits |= (on ? 1u : 0u) << k;
+        cnt += on;
+    }
+    uint32_t total;
+    uint32_t pos = block_sums[blockIdx.x] + block_exclusive_scan(cnt, lds, total);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        if (bits & (1u << k)) out_idx[pos++] = (uint32_t)(base + k);
+}
+
+void launch_compact_flags(const uint8_t *flags, uint64_t n, uint32_t *out_idx, uint32_t *block_tmp,
+                          uint32_t *out_count, hipStream_t st) {
+    const uint32_t nb = (uint32_t)((n + kScanTile - 1) / kScanTile);
+    if (nb == 0) return;
+    hipLaunchKernelGGL(k_scan_reduce<ByteFlag>, dim3(nb), dim3(kScanThreads), 0, st, ByteFlag{flags},
+                       (const uint32_t *)nullptr, n, block_tmp);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, block_tmp, nb, out_count, (WsHeader *)nullptr);
+    hipLaunchKernelGGL(k_flag_compact_apply, dim3(nb), dim3(kScanThreads), 0, st, flags, n, block_tmp, out_idx);
+}
+
 // Phase 3 for the pair offsets: poff[i] = exclusive prefix of counts in depth
 // order (the total and the overflow decision are already in the header).  The
 // item whose range holds a chunk's first pair is recorded for that chunk.

@@ -28,7 +28,8 @@ GSR_FLAG_STATS = 4
 
 EXPORTED = ("gsr_version", "gsr_status_string", "gsr_last_error", "gsr_workspace_bytes",
             "gsr_rasterize_forward", "gsr_rasterize_backward", "gsr_query_pairs", "gsr_query_stats",
-            "gsr_export_state", "gsr_adam_step", "gsr_pose_step", "gsr_sim3_relocate")
+            "gsr_export_state", "gsr_adam_step", "gsr_pose_step", "gsr_sim3_relocate",
+            "gsr_hierarchy_cut_scratch_bytes", "gsr_hierarchy_cut", "gsr_gather_gaussians")
 
 
 class GsrError(RuntimeError):
@@ -125,6 +126,13 @@ def lib():
                                     C.c_float, vp]
         L.gsr_sim3_relocate.restype = C.c_int
         L.gsr_sim3_relocate.argtypes = [C.POINTER(gsr_param_set), C.c_int64, vp, vp, C.c_int32, vp]
+        L.gsr_hierarchy_cut_scratch_bytes.restype = sz
+        L.gsr_hierarchy_cut_scratch_bytes.argtypes = [C.c_int64]
+        L.gsr_hierarchy_cut.restype = C.c_int
+        L.gsr_hierarchy_cut.argtypes = [C.POINTER(gsr_gaussians), vp, vp, C.POINTER(gsr_camera), vp, C.c_float, vp,
+                                        sz, vp, C.POINTER(C.c_int64), vp]
+        L.gsr_gather_gaussians.restype = C.c_int
+        L.gsr_gather_gaussians.argtypes = [C.POINTER(gsr_gaussians), vp, C.c_int64, C.POINTER(gsr_param_set), vp]
         _lib = L
     return _lib
 
@@ -334,3 +342,32 @@ def sim3_relocate(params: Sequence[torch.Tensor], keyframe_of: torch.Tensor, sim
         raise TypeError("keyframe_of must be int32 and sim3 float32")
     _check(lib().gsr_sim3_relocate(C.byref(param_set(params)), int(params[0].shape[0]), _ptr(keyframe_of),
                                    _ptr(sim3), int(sim3.shape[0]), _stream_ptr(stream)))
+
+
+def hierarchy_cut(nodes: Sequence[torch.Tensor], sh_degree: int, parent: torch.Tensor, child_count: torch.Tensor,
+                  cam, world_to_cam: torch.Tensor, tau: float = 1.5, scratch: Optional[torch.Tensor] = None,
+                  out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Node indices (int32, ascending) of the per-view cut; see gsr_hierarchy_cut."""
+    n = int(nodes[0].shape[0])
+    if parent.dtype != torch.int32 or child_count.dtype != torch.int32:
+        raise TypeError("parent and child_count must be int32")
+    need = int(lib().gsr_hierarchy_cut_scratch_bytes(n))
+    if scratch is None or scratch.numel() < need:
+        scratch = torch.empty(max(need, 1), dtype=torch.uint8, device=nodes[0].device)
+    if out is None or out.numel() < n:
+        out = torch.empty(max(n, 1), dtype=torch.int32, device=nodes[0].device)
+    g = gaussians_struct(*nodes, sh_degree)
+    arr = cameras([cam])
+    n_cut = C.c_int64()
+    _check(lib().gsr_hierarchy_cut(C.byref(g), _ptr(parent), _ptr(child_count), arr, _ptr(world_to_cam), float(tau),
+                                   _ptr(scratch), scratch.numel(), _ptr(out), C.byref(n_cut), _stream_ptr(stream)))
+    return out[:n_cut.value]
+
+
+def gather_gaussians(src: Sequence[torch.Tensor], sh_degree: int, index: torch.Tensor, stream=None):
+    """New contiguous tensors holding rows `index` of the five arrays."""
+    m = int(index.numel())
+    dst = [torch.empty((m,) + tuple(t.shape[1:]), dtype=t.dtype, device=t.device) for t in src]
+    g = gaussians_struct(*src, sh_degree)
+    _check(lib().gsr_gather_gaussians(C.byref(g), _ptr(index), m, C.byref(param_set(dst)), _stream_ptr(stream)))
+    return dst

@@ -219,7 +219,7 @@ def lod_workload(seed=4, n_leaves=4_000_000, levels=7, tau=1.5):
     """The hierarchical level-of-detail workload: a 7-level, branching-8
     hierarchy over 4M leaves along a 2 km street and its 1.5 px cut for one
     1920x1080 view down the street.  The Workload's scene is the cut; meta
-    holds its size and per-level counts."""
+    holds its size and per-level counts, extra["hierarchy"] the hierarchy."""
     from .scenes import Workload, street_leaves
     leaves, cam, target = street_leaves(seed, n_leaves)
     h = build(leaves, levels)
@@ -227,4 +227,5 @@ def lod_workload(seed=4, n_leaves=4_000_000, levels=7, tau=1.5):
     per_level = np.bincount(h.level_of(cut), minlength=h.levels)
     meta = {"seed": seed, "leaves": n_leaves, "nodes": int(h.level_start[-1]), "levels": h.levels - 1,
             "tau_px": tau, "cut": int(cut.size), "cut_per_level": per_level.tolist()}
-    return Workload("lod_cut_1080p", h.nodes.subset(cut), [cam], target_cameras=[target], meta=meta)
+    return Workload("lod_cut_1080p", h.nodes.subset(cut), [cam], target_cameras=[target], meta=meta,
+                    extra={"hierarchy": h, "cut": cut})

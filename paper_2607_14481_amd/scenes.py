@@ -83,6 +83,7 @@ class Workload:
     target_scene: Optional[Scene] = None
     target_cameras: Optional[List[Camera]] = None
     meta: dict = field(default_factory=dict)
+    extra: dict = field(default_factory=dict)  # objects that do not serialise (e.g. a hierarchy)
 
 
 def _rng(seed: int) -> np.random.Generator:
