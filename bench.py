@@ -441,8 +441,8 @@ def main():
                          "kernel that scales HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the rasterizer's multi-GPU sharding (one view per GPU, one "
-              "gradient reduce-scatter) is a design note only in this build; run with --gpus 1.",
+        print("bench.py measures one GPU: sharding the rasterizer over GPUs (one view per GPU, one "
+              "gradient reduce-scatter) is not implemented; run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 

@@ -3,8 +3,8 @@
  * splat rasterizer.
  *
  * The operation.  The paper optimises its Gaussians (and, jointly, the camera
- * poses) for 30 iterations per keyframe with "a custom differentiable renderer
- * based on Taming 3DGS" (Sec. 5.2; joint pose/Gaussian optimisation: Sec. 1,
+ * poses) for 30 iterations per keyframe with its own differentiable renderer,
+ * derived from Taming 3DGS (Sec. 5.2; joint pose/Gaussian optimisation: Sec. 1,
  * Sec. 3, Sec. 7; a node holds position, opacity, rotation, scale and SH
  * coefficients: Sec. 7).  The renderer is the 3DGS rasterizer of that lineage:
  *

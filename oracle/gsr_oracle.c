@@ -7,9 +7,9 @@
  * code, header, table or constant with the GPU library, and the GPU library
  * never calls it.
  *
- * What it computes.  The paper trains its Gaussians with "a custom
- * differentiable renderer based on Taming 3DGS" (Sec. 5.2, "Gaussian Placement
- * and Optimization"); poses and Gaussians are optimised jointly (Sec. 1, Sec. 3,
+ * What it computes.  The paper trains its Gaussians with its own
+ * differentiable renderer, derived from Taming 3DGS (Sec. 5.2, Gaussian
+ * placement and optimisation); poses and Gaussians are optimised jointly (Sec. 1, Sec. 3,
  * Sec. 7).  The paper does not write the renderer down, so this oracle follows
  * the 3DGS rasterizer that both cited works define (EWA splatting with a
  * +0.3 I low-pass, 16x16 tiles, alpha <= 0.99, skip alpha < 1/255, stop when
