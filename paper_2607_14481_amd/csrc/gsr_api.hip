@@ -356,7 +356,7 @@ int gsr_rasterize_backward(void *ws, size_t ws_bytes, const gsr_gaussians *g, in
     const bool pers = (flags & GSR_FLAG_PERSISTENT) != 0;
     const StageMark mark{cfg ? static_cast<hipEvent_t *>(cfg->stage_events) : nullptr, st};
     mark.begin(GSR_STAGE_COMPOSITE_BWD);
-    launch_reset_queue(p.hdr, 1, st);
+    if (pers) launch_reset_queue(p.hdr, 1, st);
     launch_composite_bwd(vt, p.ranges, p.pval[pc], p.rec, p.ulo, out_rgb, dL_drgb, p.pix_n, p.tile_cut, p.partial,
                          p.hdr, pers, persistent_ctas(cfg), st);
     mark.end(GSR_STAGE_COMPOSITE_BWD);

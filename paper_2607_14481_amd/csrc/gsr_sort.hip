@@ -496,16 +496,21 @@ void launch_emit_pairs(const ViewTable &vt, const uint32_t *sorted_items, const 
 }
 
 // ---------------------------------------------------------------------------
-// A5: per-tile [start, end) over the sorted pairs (ranges pre-cleared).
+// A5: per-tile [start, end) over the sorted pairs.  The thread at the first
+// pair of each tile (and one more at i = m) closes the previous tile, opens its
+// own, and marks the tiles in between empty, so no pre-clearing pass is needed.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t *__restrict__ pkey, uint2 *__restrict__ ranges,
-                                                     const WsHeader *__restrict__ hdr) {
+                                                     uint32_t total_tiles, const WsHeader *__restrict__ hdr) {
     const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     const uint64_t m = hdr->overflow ? 0ull : (uint64_t)hdr->n_pairs;
-    if (i >= m) return;
-    const uint32_t t = pkey[i];
-    if (i == 0 || pkey[i - 1] != t) ranges[t].x = (uint32_t)i;
-    if (i == m - 1 || pkey[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
+    if (i > m) return;
+    const int64_t t = i < m ? (int64_t)pkey[i] : (int64_t)total_tiles;
+    const int64_t prev = i > 0 ? (int64_t)pkey[i - 1] : -1;
+    if (i > 0 && prev == t) return;
+    for (int64_t u = prev + 1; u < t; ++u) ranges[u] = make_uint2((uint32_t)i, (uint32_t)i);
+    if (i < m) ranges[t].x = (uint32_t)i;
+    if (i > 0) ranges[prev].y = (uint32_t)i;
 }
 
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *__restrict__ p, uint32_t value, uint64_t n) {
@@ -540,9 +545,9 @@ void launch_reset_queue(WsHeader *h, int which, hipStream_t st) {
 
 void launch_tile_ranges(const uint32_t *pkey, uint64_t cap, uint2 *ranges, uint32_t total_tiles, const WsHeader *hdr,
                         hipStream_t st) {
-    launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, 2ull * total_tiles, st);
-    if (cap == 0) return;
-    hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, st, pkey, ranges, hdr);
+    if (total_tiles == 0) return;
+    hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((cap + 1 + 255) / 256)), dim3(256), 0, st, pkey, ranges,
+                       total_tiles, hdr);
 }
 
 }  // namespace gsr
