@@ -357,15 +357,22 @@ int gsr_rasterize_backward(void *ws, size_t ws_bytes, const gsr_gaussians *g, in
     const StageMark mark{cfg ? static_cast<hipEvent_t *>(cfg->stage_events) : nullptr, st};
     mark.begin(GSR_STAGE_COMPOSITE_BWD);
     if (pers) launch_reset_queue(p.hdr, 1, st);
+    ZeroRows zr{};
+    zr.g = *grads;
+    zr.count = p.count;
+    zr.n = (uint64_t)g->n;
+    zr.n_views = vt.n_views;
+    zr.sh_k = (g->sh_degree + 1) * (g->sh_degree + 1);
+    zr.per_tile = vt.total_tiles ? (zr.n + vt.total_tiles - 1) / vt.total_tiles : 0;
     launch_composite_bwd(vt, p.ranges, p.pval[pc], p.rec, p.ulo, out_rgb, dL_drgb, p.pix_n, p.tile_cut, p.partial,
-                         p.hdr, pers, persistent_ctas(cfg), st);
+                         zr, p.hdr, pers, persistent_ctas(cfg), st);
     mark.end(GSR_STAGE_COMPOSITE_BWD);
     mark.begin(GSR_STAGE_PROJECT_BWD);
     // the depth sort's result buffer: four 8-bit passes end where they started
     launch_pair_reduce(vt, p.cval[0], p.poff, p.chunk_item, (uint64_t)g->n, cap, p.rec, p.tile_cut, p.partial,
                        p.screen, p.carry, p.hdr, st);
     launch_project_bwd(*g, vt, world_to_cam, (uint64_t)g->n, p.rec, p.count, p.hdr, p.screen, p.carry, *grads,
-                       p.pose_part, L.pose_blocks, st);
+                       p.pose_part, L.pose_blocks, vt.total_tiles == 0, st);
     if (g->n == 0)  // no Gaussian wrote a partial: the pose gradient is zero
         launch_fill_u32(reinterpret_cast<uint32_t *>(p.pose_part), 0u, 12ull * vt.n_views * L.pose_blocks, st);
     launch_pose_finalize(vt, world_to_cam, p.pose_part, L.pose_blocks, dL_dworld_to_cam, dL_dtwist, st);

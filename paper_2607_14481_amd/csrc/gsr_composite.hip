@@ -254,6 +254,29 @@ constexpr int kRedCols = kGroup * kPartialStride;  // 63 values per row
 constexpr int kRedRows = kWave / 2;                // lane pairs are summed first
 constexpr int kRedStride = kRedCols + 2;           // odd row stride: conflict-free rows and columns
 
+// Zero gradient rows of the Gaussians of tile t's slice that no view saw, one
+// row per lane (fire-and-forget stores that overlap the tile's ALU work).
+__device__ __forceinline__ void zero_unseen_rows(const ZeroRows &z, uint32_t t, bool overflow, int lane) {
+    const uint64_t g0 = (uint64_t)t * z.per_tile, g1 = min(z.n, g0 + z.per_tile);
+    const int K3 = 3 * z.sh_k;
+    for (uint64_t i = g0 + (uint64_t)lane; i < g1; i += kWave) {
+        bool seen = false;
+        if (!overflow)
+            for (int v = 0; v < z.n_views; ++v) seen |= z.count[(uint64_t)v * z.n + i] > 0u;
+        if (seen) continue;
+        for (int a = 0; a < 3; ++a) z.g.means[3 * i + a] = 0.f, z.g.log_scales[3 * i + a] = 0.f;
+        reinterpret_cast<float4 *>(z.g.quats)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        z.g.opacities[i] = 0.f;
+        if ((K3 & 3) == 0) {
+            float4 *row = reinterpret_cast<float4 *>(z.g.sh + (uint64_t)K3 * i);
+            for (int k = 0; k < K3 / 4; ++k) row[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+        } else {
+            float *row = z.g.sh + (uint64_t)K3 * i;
+            for (int k = 0; k < K3; ++k) row[k] = 0.f;
+        }
+    }
+}
+
 template <int RPL>
 __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uint2 *__restrict__ ranges,
                                                          const uint32_t *__restrict__ pval,
@@ -262,7 +285,8 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
                                                          const float *__restrict__ dL_drgb,
                                                          const uint32_t *__restrict__ pix_n,
                                                          const uint2 *__restrict__ tile_cut,
-                                                         float *__restrict__ partial, WsHeader *hdr, int persistent) {
+                                                         float *__restrict__ partial, ZeroRows zr, WsHeader *hdr,
+                                                         int persistent) {
     __shared__ float4 sa[kWave], sb[kWave], sd[kWave];
     __shared__ float red[kRedRows * kRedStride];
     const int lane = threadIdx.x;
@@ -274,6 +298,7 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
     for (;;) {
         const uint32_t t = next_tile(persistent != 0, &hdr->queue[1], blockIdx.x, iter);
         if (t >= vt.total_tiles) break;
+        zero_unseen_rows(zr, t, hdr->overflow != 0u, lane);
         const TileCtx c = tile_ctx(vt, t);
         const uint32_t px = c.ox + lx;
         const size_t plane = (size_t)c.width * c.height;
@@ -426,8 +451,8 @@ void launch_composite_fwd(const ViewTable &vt, const uint2 *ranges, const uint32
 
 void launch_composite_bwd(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
                           const float2 *ulo, const float *out_rgb, const float *dL_drgb, const uint32_t *pix_n,
-                          const uint2 *tile_cut, float *partial, WsHeader *hdr, bool persistent, int persistent_ctas,
-                          hipStream_t st) {
+                          const uint2 *tile_cut, float *partial, const ZeroRows &zr, WsHeader *hdr, bool persistent,
+                          int persistent_ctas, hipStream_t st) {
     if (vt.total_tiles == 0) return;
     const int p = persistent ? 1 : 0;
 #define GSR_BWD(R)                                                                                                  \
@@ -435,7 +460,7 @@ void launch_composite_bwd(const ViewTable &vt, const uint2 *ranges, const uint32
                        dim3(persistent ? (unsigned)resident_ctas(k_composite_bwd<R>, persistent_ctas)               \
                                        : vt.total_tiles),                                                           \
                        dim3(kWave), 0, st, vt, ranges, pval, rec, ulo, out_rgb, dL_drgb, pix_n, tile_cut, partial,  \
-                       hdr, p)
+                       zr, hdr, p)
     switch (vt.tile_h) {
         case 4: GSR_BWD(1); break;
         case 8: GSR_BWD(2); break;

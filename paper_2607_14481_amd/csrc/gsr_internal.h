@@ -146,19 +146,30 @@ void launch_composite_fwd(const ViewTable &vt, const uint2 *ranges, const uint32
                           const float2 *ulo, const uint32_t *rank, float3 bg, float *out_rgb, float *out_T,
                           float *pix_T, uint32_t *pix_n, uint2 *tile_cut, WsHeader *hdr, bool persistent,
                           int persistent_ctas, bool stats, hipStream_t st);
+// Gradient rows of the Gaussians no view saw are zeroed by the backward
+// compositing (memory work hidden under its ALU work): tile t takes Gaussians
+// [t * per_tile, (t + 1) * per_tile).
+struct ZeroRows {
+    gsr_gaussian_grads g;
+    const uint32_t *count;  // tiles touched per (view, Gaussian)
+    uint64_t n, per_tile;
+    int32_t n_views, sh_k;
+};
 void launch_composite_bwd(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
                           const float2 *ulo, const float *out_rgb, const float *dL_drgb, const uint32_t *pix_n,
-                          const uint2 *tile_cut, float *partial, WsHeader *hdr, bool persistent,
+                          const uint2 *tile_cut, float *partial, const ZeroRows &zr, WsHeader *hdr, bool persistent,
                           int persistent_ctas, hipStream_t st);
 void launch_pair_reduce(const ViewTable &vt, const uint32_t *sorted_items, const uint32_t *poff,
                         const uint32_t *chunk_item, uint64_t n, uint64_t pair_grid, const Rec *rec,
                         const uint2 *tile_cut, const float *partial, float4 *screen, float *carry,
                         const WsHeader *hdr, hipStream_t st);
 
+// zero_unseen: also write the zero rows of the Gaussians no view saw (when the
+// backward compositing did not).
 void launch_project_bwd(const gsr_gaussians &g, const ViewTable &vt, const float *w2c, uint64_t n,
                         const Rec *rec, const uint32_t *count, const WsHeader *hdr, const float4 *screen,
                         const float *carry, const gsr_gaussian_grads &gr, float *pose_part, uint32_t pose_blocks,
-                        hipStream_t st);
+                        bool zero_unseen, hipStream_t st);
 void launch_pose_finalize(const ViewTable &vt, const float *w2c, const float *pose_part, uint32_t pose_blocks,
                           float *dL_dw2c, float *dL_dtwist, hipStream_t st);
 

@@ -512,7 +512,8 @@ template <int DEG>
 __global__ __launch_bounds__(kProjThreads) void k_project_bwd(
     gsr_gaussians g, ViewTable vt, const float *__restrict__ w2c, uint64_t n, const Rec *__restrict__ rec,
     const uint32_t *__restrict__ count, const WsHeader *__restrict__ hdr, const float4 *__restrict__ screen,
-    const float *__restrict__ carry, gsr_gaussian_grads gr, float *__restrict__ pose_part, uint32_t pose_blocks) {
+    const float *__restrict__ carry, gsr_gaussian_grads gr, float *__restrict__ pose_part, uint32_t pose_blocks,
+    int zero_unseen) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     constexpr bool kVecSH = (3 * K) % 4 == 0;  // SH rows of 16-byte multiples: float4 loads and stores
     __shared__ float red[4 * 12];
@@ -541,8 +542,9 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(
         __syncthreads();
     }
     const uint32_t nlist = s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3];
-    // ---- zero rows of the others, block-wide and coalesced
-    {
+    // ---- zero rows of the others, block-wide and coalesced (unless the backward
+    // compositing already did)
+    if (zero_unseen) {
         float *zm = gr.means + 3 * base, *zl = gr.log_scales + 3 * base;
         for (uint32_t f = threadIdx.x; f < 3 * nb; f += kProjThreads)
             if (!s_vis[f / 3]) zm[f] = 0.f, zl[f] = 0.f;
@@ -819,14 +821,15 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(
 
 void launch_project_bwd(const gsr_gaussians &g, const ViewTable &vt, const float *w2c, uint64_t n, const Rec *rec,
                         const uint32_t *count, const WsHeader *hdr, const float4 *screen, const float *carry,
-                        const gsr_gaussian_grads &gr, float *pose_part, uint32_t pose_blocks, hipStream_t st) {
+                        const gsr_gaussian_grads &gr, float *pose_part, uint32_t pose_blocks, bool zero_unseen,
+                        hipStream_t st) {
     if (n == 0) return;
     const dim3 grid(pose_blocks);
     switch (g.sh_degree) {
-        case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks); break;
-        case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks); break;
-        case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks); break;
-        default: hipLaunchKernelGGL(k_project_bwd<3>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks); break;
+        case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks, zero_unseen ? 1 : 0); break;
+        case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks, zero_unseen ? 1 : 0); break;
+        case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks, zero_unseen ? 1 : 0); break;
+        default: hipLaunchKernelGGL(k_project_bwd<3>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks, zero_unseen ? 1 : 0); break;
     }
 }
 
