@@ -111,6 +111,7 @@ gsr::WsLayout make_layout(uint64_t n, const gsr::ViewTable &vt, uint64_t cap) {
     L.poff = take(4 * items);
     L.rank = take(4 * items);
     L.chunk_item = take(4 * (L.chunks + 1));
+    L.item_box = take(8 * items);
     L.carry = take(4ull * 2 * kPartialStride * L.chunks);
     L.screen = take(48 * items);
     L.pkey[0] = take(4 * cap);
@@ -153,6 +154,7 @@ struct Ptrs {
         *digit_total;
     float4 *screen;
     float *carry;
+    uint2 *item_box;
     uint2 *ranges, *tile_cut;
     float *pix_T;
     uint32_t *pix_n;
@@ -178,6 +180,7 @@ Ptrs carve(void *ws, const gsr::WsLayout &L) {
     p.rank = reinterpret_cast<uint32_t *>(b + L.rank);
     p.chunk_item = reinterpret_cast<uint32_t *>(b + L.chunk_item);
     p.carry = reinterpret_cast<float *>(b + L.carry);
+    p.item_box = reinterpret_cast<uint2 *>(b + L.item_box);
     p.screen = reinterpret_cast<float4 *>(b + L.screen);
     p.tile_cut = reinterpret_cast<uint2 *>(b + L.tile_cut);
     p.hist = reinterpret_cast<uint32_t *>(b + L.hist);
@@ -310,8 +313,8 @@ int gsr_rasterize_forward(void *ws, size_t ws_bytes, const gsr_gaussians *g, int
             return fail(GSR_ERR_CAPACITY, "needs %u pairs, workspace holds %llu", h.n_pairs, (unsigned long long)cap);
         pair_grid = h.n_pairs;
     }
-    launch_emit_pairs(vt, sorted_items, p.poff, p.chunk_item, n, pair_grid, p.rec, p.rank, p.pkey[0], p.pval[0],
-                      p.hdr, st);
+    launch_emit_pairs(vt, sorted_items, p.poff, p.chunk_item, n, pair_grid, p.rec, p.rank, p.item_box, p.pkey[0],
+                      p.pval[0], p.hdr, st);
     mark.end(GSR_STAGE_EMIT);
     mark.begin(GSR_STAGE_TILE_SORT);
     int pc = 0;
@@ -369,7 +372,7 @@ int gsr_rasterize_backward(void *ws, size_t ws_bytes, const gsr_gaussians *g, in
     mark.end(GSR_STAGE_COMPOSITE_BWD);
     mark.begin(GSR_STAGE_PROJECT_BWD);
     // the depth sort's result buffer: four 8-bit passes end where they started
-    launch_pair_reduce(vt, p.cval[0], p.poff, p.chunk_item, (uint64_t)g->n, cap, p.rec, p.tile_cut, p.partial,
+    launch_pair_reduce(vt, p.cval[0], p.poff, p.chunk_item, (uint64_t)g->n, cap, p.item_box, p.tile_cut, p.partial,
                        p.screen, p.carry, p.hdr, st);
     launch_project_bwd(*g, vt, world_to_cam, (uint64_t)g->n, p.rec, p.count, p.hdr, p.screen, p.carry, *grads,
                        p.pose_part, L.pose_blocks, vt.total_tiles == 0, st);

@@ -72,6 +72,7 @@ struct WsLayout {
     size_t poff;        // u32[items] pair offset, in depth order
     size_t rank;        // u32[items] depth rank of each visible item
     size_t chunk_item;  // u32[chunks + 1] depth rank of the item holding each chunk's first pair
+    size_t item_box;    // uint2[items] per depth rank: (global id of the box's first tile, width | tiles_x << 16)
     size_t carry;       // float[chunks * 2 * 9] chunk-boundary partial sums of the pair moments
     size_t screen;      // float4[items * 3] per-item sums of the pair moments
     size_t pkey[2];     // u32[cap] tile keys ping-pong
@@ -138,7 +139,7 @@ void launch_pair_offsets(const uint32_t *sorted_items, const uint32_t *count, ui
                          WsHeader *hdr, hipStream_t st);
 void launch_emit_pairs(const ViewTable &vt, const uint32_t *sorted_items, const uint32_t *poff,
                        const uint32_t *chunk_item, uint64_t n, uint64_t pair_grid, Rec *rec, uint32_t *rank,
-                       uint32_t *pkey, uint32_t *pval, const WsHeader *hdr, hipStream_t st);
+                       uint2 *item_box, uint32_t *pkey, uint32_t *pval, const WsHeader *hdr, hipStream_t st);
 void launch_tile_ranges(const uint32_t *pkey, uint64_t cap, uint2 *ranges, uint32_t total_tiles,
                         const WsHeader *hdr, hipStream_t st);
 
@@ -160,7 +161,7 @@ void launch_composite_bwd(const ViewTable &vt, const uint2 *ranges, const uint32
                           const uint2 *tile_cut, float *partial, const ZeroRows &zr, WsHeader *hdr, bool persistent,
                           int persistent_ctas, hipStream_t st);
 void launch_pair_reduce(const ViewTable &vt, const uint32_t *sorted_items, const uint32_t *poff,
-                        const uint32_t *chunk_item, uint64_t n, uint64_t pair_grid, const Rec *rec,
+                        const uint32_t *chunk_item, uint64_t n, uint64_t pair_grid, const uint2 *item_box,
                         const uint2 *tile_cut, const float *partial, float4 *screen, float *carry,
                         const WsHeader *hdr, hipStream_t st);
 
@@ -249,11 +250,16 @@ struct ChunkItems {
     uint32_t item[kChunkPairs + 1];
 };
 
+// The chunk's item range; every thread of the workgroup calls it (it ends
+// with a barrier).  Boxes come from the records (`boxes` NULL, emission) or
+// from the per-depth-rank box words emission wrote (later passes: one
+// coalesced load instead of a gather through the record).
 __device__ __forceinline__ uint32_t load_chunk_items(const ViewTable &vt, const uint32_t *__restrict__ sorted_items,
                                                      const uint32_t *__restrict__ poff,
                                                      const uint32_t *__restrict__ chunk_item, uint64_t n,
-                                                     const Rec *__restrict__ rec, uint32_t c, uint32_t m,
-                                                     uint32_t nvis, ChunkItems &ci, uint32_t &i_lo) {
+                                                     const Rec *__restrict__ rec, const uint2 *__restrict__ boxes,
+                                                     uint32_t c, uint32_t m, uint32_t nvis, ChunkItems &ci,
+                                                     uint32_t &i_lo) {
     const uint32_t c0 = c * kChunkPairs;
     i_lo = chunk_item[c];
     const uint32_t i_hi = c0 + kChunkPairs < m ? chunk_item[c + 1] : nvis - 1;
@@ -265,16 +271,22 @@ __device__ __forceinline__ uint32_t load_chunk_items(const ViewTable &vt, const 
             continue;
         }
         const uint32_t item = sorted_items[i];
-        const float4 r2 = rec[item].r2;
-        const uint32_t bx = __float_as_uint(r2.y), by = __float_as_uint(r2.z);
-        const uint32_t tx0 = (bx & 0xffffu) / kTileW, tx1 = (bx >> 16) / kTileW;
-        const uint32_t ty0 = (by & 0xffffu) / (uint32_t)vt.tile_h;
-        const int v = (int)(item / n);
-        const uint32_t tiles_x = (uint32_t)vt.v[v].tiles_x;
         ci.p0[k] = poff[i];
-        ci.tile0[k] = vt.v[v].tile_off + ty0 * tiles_x + tx0;
-        ci.wx[k] = (tx1 - tx0 + 1) | (tiles_x << 16);
         ci.item[k] = item;
+        if (boxes) {
+            const uint2 bw = boxes[i];
+            ci.tile0[k] = bw.x;
+            ci.wx[k] = bw.y;
+        } else {
+            const float4 r2 = rec[item].r2;
+            const uint32_t bx = __float_as_uint(r2.y), by = __float_as_uint(r2.z);
+            const uint32_t tx0 = (bx & 0xffffu) / kTileW, tx1 = (bx >> 16) / kTileW;
+            const uint32_t ty0 = (by & 0xffffu) / (uint32_t)vt.tile_h;
+            const int v = (int)(item / n);
+            const uint32_t tiles_x = (uint32_t)vt.v[v].tiles_x;
+            ci.tile0[k] = vt.v[v].tile_off + ty0 * tiles_x + tx0;
+            ci.wx[k] = (tx1 - tx0 + 1) | (tiles_x << 16);
+        }
     }
     __syncthreads();
     return nloc;

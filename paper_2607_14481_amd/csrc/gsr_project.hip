@@ -309,7 +309,7 @@ __device__ __forceinline__ void write_item_sum(const ChunkItems &ci, uint32_t k,
 __global__ __launch_bounds__(kChunkThreads) void k_pair_reduce(ViewTable vt, const uint32_t *__restrict__ sorted_items,
                                                                const uint32_t *__restrict__ poff,
                                                                const uint32_t *__restrict__ chunk_item, uint64_t n,
-                                                               const Rec *__restrict__ rec,
+                                                               const uint2 *__restrict__ item_box,
                                                                const uint2 *__restrict__ tile_cut,
                                                                const float *__restrict__ partial,
                                                                float4 *__restrict__ screen, float *__restrict__ carry,
@@ -349,7 +349,8 @@ __global__ __launch_bounds__(kChunkThreads) void k_pair_reduce(ViewTable vt, con
                 x[u][j] = pb + u < cend ? partial[(size_t)(pb + u) * kPartialStride + j] : 0.f;
     }
     uint32_t i_lo;
-    const uint32_t nloc = load_chunk_items(vt, sorted_items, poff, chunk_item, n, rec, c, m, nvis, ci, i_lo);
+    const uint32_t nloc =
+        load_chunk_items(vt, sorted_items, poff, chunk_item, n, nullptr, item_box, c, m, nvis, ci, i_lo);
     // keys and the cut mask (pairs beyond their tile's cut were never written)
     if (pb < cend) {
         PairWalker pw;
@@ -456,13 +457,13 @@ __global__ __launch_bounds__(kChunkThreads) void k_pair_reduce(ViewTable vt, con
 }
 
 void launch_pair_reduce(const ViewTable &vt, const uint32_t *sorted_items, const uint32_t *poff,
-                        const uint32_t *chunk_item, uint64_t n, uint64_t pair_grid, const Rec *rec,
+                        const uint32_t *chunk_item, uint64_t n, uint64_t pair_grid, const uint2 *item_box,
                         const uint2 *tile_cut, const float *partial, float4 *screen, float *carry,
                         const WsHeader *hdr, hipStream_t st) {
     const uint64_t chunks = chunk_count(pair_grid);
     if (chunks == 0) return;
     hipLaunchKernelGGL(k_pair_reduce, dim3((unsigned)chunks), dim3(kChunkThreads), 0, st, vt, sorted_items, poff,
-                       chunk_item, n, rec, tile_cut, partial, screen, carry, hdr);
+                       chunk_item, n, item_box, tile_cut, partial, screen, carry, hdr);
 }
 
 // ---------------------------------------------------------------------------

@@ -446,8 +446,8 @@ __global__ __launch_bounds__(kChunkThreads) void k_emit(ViewTable vt, const uint
                                                         const uint32_t *__restrict__ poff,
                                                         const uint32_t *__restrict__ chunk_item, uint64_t n,
                                                         Rec *__restrict__ rec, uint32_t *__restrict__ rank,
-                                                        uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval,
-                                                        const WsHeader *__restrict__ hdr) {
+                                                        uint2 *__restrict__ item_box, uint32_t *__restrict__ pkey,
+                                                        uint32_t *__restrict__ pval, const WsHeader *__restrict__ hdr) {
     __shared__ ChunkItems ci;
     if (hdr->overflow) return;
     const uint32_t m = hdr->n_pairs, nvis = hdr->n_visible;
@@ -455,13 +455,15 @@ __global__ __launch_bounds__(kChunkThreads) void k_emit(ViewTable vt, const uint
     if (c0 >= m) return;  // uniform per workgroup
     const uint32_t cend = min(c0 + kChunkPairs, m);
     uint32_t i_lo;
-    const uint32_t nloc = load_chunk_items(vt, sorted_items, poff, chunk_item, n, rec, blockIdx.x, m, nvis, ci, i_lo);
+    const uint32_t nloc =
+        load_chunk_items(vt, sorted_items, poff, chunk_item, n, rec, nullptr, blockIdx.x, m, nvis, ci, i_lo);
     for (uint32_t k = threadIdx.x; k < nloc; k += kChunkThreads) {
         const uint32_t p = ci.p0[k];
         if (p >= c0 && p < cend) {
             const uint32_t item = ci.item[k];
             rank[item] = i_lo + k;
             rec[item].r2.w = __uint_as_float(p);
+            item_box[i_lo + k] = make_uint2(ci.tile0[k], ci.wx[k]);
         }
     }
     const uint32_t pb = c0 + threadIdx.x * kChunkPerThread;
@@ -488,11 +490,11 @@ __global__ __launch_bounds__(kChunkThreads) void k_emit(ViewTable vt, const uint
 
 void launch_emit_pairs(const ViewTable &vt, const uint32_t *sorted_items, const uint32_t *poff,
                        const uint32_t *chunk_item, uint64_t n, uint64_t pair_grid, Rec *rec, uint32_t *rank,
-                       uint32_t *pkey, uint32_t *pval, const WsHeader *hdr, hipStream_t st) {
+                       uint2 *item_box, uint32_t *pkey, uint32_t *pval, const WsHeader *hdr, hipStream_t st) {
     const uint64_t chunks = chunk_count(pair_grid);
     if (chunks == 0) return;
     hipLaunchKernelGGL(k_emit, dim3((unsigned)chunks), dim3(kChunkThreads), 0, st, vt, sorted_items, poff, chunk_item,
-                       n, rec, rank, pkey, pval, hdr);
+                       n, rec, rank, item_box, pkey, pval, hdr);
 }
 
 // ---------------------------------------------------------------------------
