@@ -118,9 +118,9 @@ typedef struct gsr_gaussian_grads {
 
 /* Stages of the two passes, for the optional per-stage timing events. */
 #define GSR_STAGE_PROJECT 0        /* forward: per-Gaussian projection */
-#define GSR_STAGE_DEPTH_SORT 1     /* forward: visible compaction + depth sort */
+#define GSR_STAGE_COMPACT 1        /* forward: visible-item compaction */
 #define GSR_STAGE_EMIT 2           /* forward: pair offsets + pair emission */
-#define GSR_STAGE_TILE_SORT 3      /* forward: tile sort + tile ranges */
+#define GSR_STAGE_TILE_SORT 3      /* forward: tile sort, tile ranges, per-tile depth sort */
 #define GSR_STAGE_COMPOSITE_FWD 4  /* forward: compositing */
 #define GSR_STAGE_COMPOSITE_BWD 5  /* backward: compositing */
 #define GSR_STAGE_PROJECT_BWD 6    /* backward: per-Gaussian reduction, chain rule, pose */

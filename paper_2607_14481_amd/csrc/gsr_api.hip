@@ -87,9 +87,7 @@ gsr::WsLayout make_layout(uint64_t n, const gsr::ViewTable &vt, uint64_t cap) {
     L.items = items;
     L.cap = cap;
     L.chunks = chunk_count(cap);
-    const uint64_t hb_items = (items + kSortTileShort - 1) / kSortTileShort;
-    const uint64_t hb_pairs = (cap + kSortTile - 1) / kSortTile;
-    L.hist_blocks = (uint32_t)std::max<uint64_t>(1, std::max(hb_items, hb_pairs));
+    L.hist_blocks = (uint32_t)std::max<uint64_t>(1, (cap + kSortTile - 1) / kSortTile);
     L.pose_blocks = (uint32_t)std::max<uint64_t>(1, (n + kProjThreads - 1) / kProjThreads);
     const uint64_t scan_blocks = std::max<uint64_t>(1, (items + kScanTile - 1) / kScanTile);
     size_t o = 0;
@@ -104,14 +102,10 @@ gsr::WsLayout make_layout(uint64_t n, const gsr::ViewTable &vt, uint64_t cap) {
     L.zkey = take(4 * items);
     L.count = take(4 * items);
     L.scan_tmp = take(4 * scan_blocks);
-    L.ckey[0] = take(4 * items);
-    L.ckey[1] = take(4 * items);
-    L.cval[0] = take(4 * items);
-    L.cval[1] = take(4 * items);
+    L.vis = take(4 * items);
     L.poff = take(4 * items);
-    L.rank = take(4 * items);
     L.chunk_item = take(4 * (L.chunks + 1));
-    L.item_box = take(8 * items);
+    L.item_box = take(16 * items);
     L.carry = take(4ull * 2 * kPartialStride * L.chunks);
     L.screen = take(48 * items);
     L.pkey[0] = take(4 * cap);
@@ -121,7 +115,7 @@ gsr::WsLayout make_layout(uint64_t n, const gsr::ViewTable &vt, uint64_t cap) {
     L.hist = take(4ull * 256 * L.hist_blocks);
     L.digit_total = take(4 * 256);
     L.ranges = take(8ull * vt.total_tiles);
-    L.tile_cut = take(8ull * vt.total_tiles);
+    L.tile_cut = take(16ull * vt.total_tiles);
     L.pix_T = take(4ull * vt.total_pixels);
     L.pix_n = take(4ull * vt.total_pixels);
     L.partial = take(4ull * kPartialStride * cap);
@@ -150,12 +144,12 @@ struct Ptrs {
     gsr::WsHeader *hdr;
     gsr::Rec *rec;
     float2 *ulo;
-    uint32_t *zkey, *count, *scan_tmp, *ckey[2], *cval[2], *poff, *rank, *chunk_item, *pkey[2], *pval[2], *hist,
-        *digit_total;
+    uint32_t *zkey, *count, *scan_tmp, *vis, *poff, *chunk_item, *pkey[2], *pval[2], *hist, *digit_total;
     float4 *screen;
     float *carry;
-    uint2 *item_box;
-    uint2 *ranges, *tile_cut;
+    uint4 *item_box;
+    uint2 *ranges;
+    uint4 *tile_cut;
     float *pix_T;
     uint32_t *pix_n;
     float *partial, *pose_part;
@@ -171,18 +165,16 @@ Ptrs carve(void *ws, const gsr::WsLayout &L) {
     p.count = reinterpret_cast<uint32_t *>(b + L.count);
     p.scan_tmp = reinterpret_cast<uint32_t *>(b + L.scan_tmp);
     for (int k = 0; k < 2; ++k) {
-        p.ckey[k] = reinterpret_cast<uint32_t *>(b + L.ckey[k]);
-        p.cval[k] = reinterpret_cast<uint32_t *>(b + L.cval[k]);
         p.pkey[k] = reinterpret_cast<uint32_t *>(b + L.pkey[k]);
         p.pval[k] = reinterpret_cast<uint32_t *>(b + L.pval[k]);
     }
+    p.vis = reinterpret_cast<uint32_t *>(b + L.vis);
     p.poff = reinterpret_cast<uint32_t *>(b + L.poff);
-    p.rank = reinterpret_cast<uint32_t *>(b + L.rank);
     p.chunk_item = reinterpret_cast<uint32_t *>(b + L.chunk_item);
     p.carry = reinterpret_cast<float *>(b + L.carry);
-    p.item_box = reinterpret_cast<uint2 *>(b + L.item_box);
+    p.item_box = reinterpret_cast<uint4 *>(b + L.item_box);
     p.screen = reinterpret_cast<float4 *>(b + L.screen);
-    p.tile_cut = reinterpret_cast<uint2 *>(b + L.tile_cut);
+    p.tile_cut = reinterpret_cast<uint4 *>(b + L.tile_cut);
     p.hist = reinterpret_cast<uint32_t *>(b + L.hist);
     p.digit_total = reinterpret_cast<uint32_t *>(b + L.digit_total);
     p.ranges = reinterpret_cast<uint2 *>(b + L.ranges);
@@ -292,18 +284,11 @@ int gsr_rasterize_forward(void *ws, size_t ws_bytes, const gsr_gaussians *g, int
     launch_reset_header(p.hdr, (uint32_t)cap, st);
     launch_project_fwd(*g, vt, world_to_cam, n, p.rec, p.ulo, p.zkey, p.count, st);
     mark.end(GSR_STAGE_PROJECT);
-    mark.begin(GSR_STAGE_DEPTH_SORT);
-    launch_compact_visible(p.count, p.zkey, L.items, p.ckey[0], p.cval[0], p.scan_tmp, p.hdr, st);
-    int cur = 0;
-    {
-        uint32_t *k2[2] = {p.ckey[0], p.ckey[1]}, *v2[2] = {p.cval[0], p.cval[1]};
-        radix_sort_u32(k2, v2, SortCount{&p.hdr->n_visible, nullptr}, L.items, 0, 32, true, p.hist,
-                       L.hist_blocks, p.digit_total, cur, st);
-    }
-    mark.end(GSR_STAGE_DEPTH_SORT);
-    const uint32_t *sorted_items = p.cval[cur];
+    mark.begin(GSR_STAGE_COMPACT);
+    launch_compact_visible(p.count, L.items, p.vis, p.scan_tmp, p.hdr, st);
+    mark.end(GSR_STAGE_COMPACT);
     mark.begin(GSR_STAGE_EMIT);
-    launch_pair_offsets(sorted_items, p.count, L.items, p.poff, p.chunk_item, L.chunks, p.scan_tmp, p.hdr, st);
+    launch_pair_offsets(p.vis, p.count, L.items, p.poff, p.chunk_item, L.chunks, p.scan_tmp, p.hdr, st);
     uint64_t pair_grid = cap;
     if (flags & GSR_FLAG_SYNC) {
         WsHeader h;
@@ -313,21 +298,22 @@ int gsr_rasterize_forward(void *ws, size_t ws_bytes, const gsr_gaussians *g, int
             return fail(GSR_ERR_CAPACITY, "needs %u pairs, workspace holds %llu", h.n_pairs, (unsigned long long)cap);
         pair_grid = h.n_pairs;
     }
-    launch_emit_pairs(vt, sorted_items, p.poff, p.chunk_item, n, pair_grid, p.rec, p.rank, p.item_box, p.pkey[0],
-                      p.pval[0], p.hdr, st);
+    launch_emit_pairs(vt, p.vis, p.poff, p.chunk_item, n, pair_grid, p.rec, p.zkey, p.item_box, p.pkey[0], p.pval[0],
+                      p.hdr, st);
     mark.end(GSR_STAGE_EMIT);
     mark.begin(GSR_STAGE_TILE_SORT);
     int pc = 0;
     {
         uint32_t *k2[2] = {p.pkey[0], p.pkey[1]}, *v2[2] = {p.pval[0], p.pval[1]};
-        radix_sort_u32(k2, v2, SortCount{nullptr, p.hdr}, pair_grid, 0, tile_bits(vt.total_tiles), false, p.hist,
+        radix_sort_u32(k2, v2, SortCount{nullptr, p.hdr}, pair_grid, 0, tile_bits(vt.total_tiles), p.hist,
                        L.hist_blocks, p.digit_total, pc, st);
     }
     launch_tile_ranges(p.pkey[pc], pair_grid, p.ranges, vt.total_tiles, p.hdr, st);
+    launch_tile_depth_sort(p.ranges, vt.total_tiles, p.pval[pc], p.zkey, p.pkey[pc ^ 1], p.pval[pc ^ 1], p.hdr, st);
     mark.end(GSR_STAGE_TILE_SORT);
     const bool pers = (flags & GSR_FLAG_PERSISTENT) != 0;
     mark.begin(GSR_STAGE_COMPOSITE_FWD);
-    launch_composite_fwd(vt, p.ranges, p.pval[pc], p.rec, p.ulo, p.rank, bgc, out_rgb, out_T, p.pix_T, p.pix_n,
+    launch_composite_fwd(vt, p.ranges, p.pval[pc], p.rec, p.ulo, p.zkey, bgc, out_rgb, out_T, p.pix_T, p.pix_n,
                          p.tile_cut, p.hdr, pers, persistent_ctas(cfg), (flags & GSR_FLAG_STATS) != 0, st);
     mark.end(GSR_STAGE_COMPOSITE_FWD);
     return check_hip(hipGetLastError(), "forward launch");
@@ -371,8 +357,7 @@ int gsr_rasterize_backward(void *ws, size_t ws_bytes, const gsr_gaussians *g, in
                          zr, p.hdr, pers, persistent_ctas(cfg), st);
     mark.end(GSR_STAGE_COMPOSITE_BWD);
     mark.begin(GSR_STAGE_PROJECT_BWD);
-    // the depth sort's result buffer: four 8-bit passes end where they started
-    launch_pair_reduce(vt, p.cval[0], p.poff, p.chunk_item, (uint64_t)g->n, cap, p.item_box, p.tile_cut, p.partial,
+    launch_pair_reduce(vt, p.poff, p.chunk_item, (uint64_t)g->n, cap, p.item_box, p.tile_cut, p.partial,
                        p.screen, p.carry, p.hdr, st);
     launch_project_bwd(*g, vt, world_to_cam, (uint64_t)g->n, p.rec, p.count, p.hdr, p.screen, p.carry, *grads,
                        p.pose_part, L.pose_blocks, vt.total_tiles == 0, st);

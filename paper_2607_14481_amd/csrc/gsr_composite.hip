@@ -14,10 +14,11 @@
 //
 // Early stop.  Dense scenes saturate long before the end of a tile's list:
 // the forward records per tile the number of list positions any of its
-// pixels used (nmax) and, for the first unused position, the depth rank of
-// its Gaussian.  The backward replays only [start, start + nmax), and the
-// per-Gaussian reduction skips pairs at or beyond a tile's cut, so unused
-// pairs cost neither a replay nor a write.
+// pixels used (nmax) and, for the first unused position, the (depth key,
+// item) of its Gaussian -- the list's sort key.  The backward replays only
+// [start, start + nmax), and the per-Gaussian reduction skips pairs whose key
+// is at or beyond a tile's cut, so unused pairs cost neither a replay nor a
+// write.
 //
 // Backward.  Front to back again (nothing per (pixel, Gaussian) is stored):
 // from the forward's output C_out and the running accumulation, the colour
@@ -115,10 +116,10 @@ template <int RPL, bool STATS>
 __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uint2 *__restrict__ ranges,
                                                          const uint32_t *__restrict__ pval,
                                                          const Rec *__restrict__ rec, const float2 *__restrict__ ulo,
-                                                         const uint32_t *__restrict__ rank, float3 bg,
+                                                         const uint32_t *__restrict__ zkey, float3 bg,
                                                          float *__restrict__ out_rgb, float *__restrict__ out_T,
                                                          float *__restrict__ pix_T, uint32_t *__restrict__ pix_n,
-                                                         uint2 *__restrict__ tile_cut, WsHeader *hdr, int persistent) {
+                                                         uint4 *__restrict__ tile_cut, WsHeader *hdr, int persistent) {
     __shared__ float4 sa[kWave], sb[kWave], sd[kWave];
     const int lane = threadIdx.x;
     const int lx = lane & 15, ly = lane >> 4;
@@ -238,10 +239,10 @@ __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uin
             }
         }
         if (lane == 0) {
-            // positions the backward replays, and the depth rank of the first
-            // Gaussian it does not
-            const uint32_t cut = nmax < len ? rank[pval[rg.x + nmax]] : 0xffffffffu;
-            tile_cut[t] = make_uint2(nmax, cut);
+            // positions the backward replays, and the sort key of the first
+            // entry it does not (above every key when it replays them all)
+            const uint32_t item = nmax < len ? pval[rg.x + nmax] : 0xffffffffu;
+            tile_cut[t] = make_uint4(nmax, nmax < len ? zkey[item] : 0xffffffffu, item, 0u);
         }
     }
 }
@@ -284,7 +285,7 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
                                                          const float *__restrict__ out_rgb,
                                                          const float *__restrict__ dL_drgb,
                                                          const uint32_t *__restrict__ pix_n,
-                                                         const uint2 *__restrict__ tile_cut,
+                                                         const uint4 *__restrict__ tile_cut,
                                                          float *__restrict__ partial, ZeroRows zr, WsHeader *hdr,
                                                          int persistent) {
     __shared__ float4 sa[kWave], sb[kWave], sd[kWave];
@@ -426,8 +427,8 @@ static int resident_ctas(Kernel kernel, int requested) {
 }
 
 void launch_composite_fwd(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
-                          const float2 *ulo, const uint32_t *rank, float3 bg, float *out_rgb, float *out_T,
-                          float *pix_T, uint32_t *pix_n, uint2 *tile_cut, WsHeader *hdr, bool persistent,
+                          const float2 *ulo, const uint32_t *zkey, float3 bg, float *out_rgb, float *out_T,
+                          float *pix_T, uint32_t *pix_n, uint4 *tile_cut, WsHeader *hdr, bool persistent,
                           int persistent_ctas, bool stats, hipStream_t st) {
     if (vt.total_tiles == 0) return;
     const int p = persistent ? 1 : 0;
@@ -435,7 +436,7 @@ void launch_composite_fwd(const ViewTable &vt, const uint2 *ranges, const uint32
     hipLaunchKernelGGL((k_composite_fwd<R, S>),                                                                     \
                        dim3(persistent ? (unsigned)resident_ctas(k_composite_fwd<R, S>, persistent_ctas)            \
                                        : vt.total_tiles),                                                           \
-                       dim3(kWave), 0, st, vt, ranges, pval, rec, ulo, rank, bg, out_rgb, out_T, pix_T, pix_n,      \
+                       dim3(kWave), 0, st, vt, ranges, pval, rec, ulo, zkey, bg, out_rgb, out_T, pix_T, pix_n,      \
                        tile_cut, hdr, p)
 #define GSR_FWD_RPL(R) \
     if (stats) GSR_FWD(R, true); else GSR_FWD(R, false)
@@ -451,7 +452,7 @@ void launch_composite_fwd(const ViewTable &vt, const uint2 *ranges, const uint32
 
 void launch_composite_bwd(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
                           const float2 *ulo, const float *out_rgb, const float *dL_drgb, const uint32_t *pix_n,
-                          const uint2 *tile_cut, float *partial, const ZeroRows &zr, WsHeader *hdr, bool persistent,
+                          const uint4 *tile_cut, float *partial, const ZeroRows &zr, WsHeader *hdr, bool persistent,
                           int persistent_ctas, hipStream_t st) {
     if (vt.total_tiles == 0) return;
     const int p = persistent ? 1 : 0;

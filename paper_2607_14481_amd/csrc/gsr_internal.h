@@ -67,12 +67,10 @@ struct WsLayout {
     size_t zkey;        // u32[items] depth key (float bits) or kCulledKey
     size_t count;       // u32[items] tiles touched
     size_t scan_tmp;    // u32 scratch for scans (block sums)
-    size_t ckey[2];     // u32[items] depth sort ping-pong keys
-    size_t cval[2];     // u32[items] depth sort ping-pong values (item ids)
-    size_t poff;        // u32[items] pair offset, in depth order
-    size_t rank;        // u32[items] depth rank of each visible item
-    size_t chunk_item;  // u32[chunks + 1] depth rank of the item holding each chunk's first pair
-    size_t item_box;    // uint2[items] per depth rank: (global id of the box's first tile, width | tiles_x << 16)
+    size_t vis;         // u32[items] visible item ids in ascending order
+    size_t poff;        // u32[items] pair offset of the k-th visible item
+    size_t chunk_item;  // u32[chunks + 1] index (into vis) of the item holding each chunk's first pair
+    size_t item_box;    // uint4[items] per visible index: (first tile of the box, width | tiles_x << 16, depth key, item)
     size_t carry;       // float[chunks * 2 * 9] chunk-boundary partial sums of the pair moments
     size_t screen;      // float4[items * 3] per-item sums of the pair moments
     size_t pkey[2];     // u32[cap] tile keys ping-pong
@@ -80,7 +78,7 @@ struct WsLayout {
     size_t hist;        // u32[256 * max_blocks] radix histograms
     size_t digit_total; // u32[256] radix digit totals
     size_t ranges;      // uint2[total_tiles]
-    size_t tile_cut;    // uint2[total_tiles] (positions replayed, depth rank cut)
+    size_t tile_cut;    // uint4[total_tiles] (positions replayed, depth key and item of the first one not replayed)
     size_t pix_T;       // float[total_pixels] final transmittance
     size_t pix_n;       // u32[total_pixels] last contributor + 1
     size_t partial;     // float[cap * 9] per-pair moments of the pixel gradients
@@ -94,8 +92,8 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;     // 2048
 constexpr int kSortThreads = 256;
-constexpr int kSortTile = 4096;                           // elements per sort block (pairs)
-constexpr int kSortTileShort = 1024;                      // elements per sort block (visible items)
+constexpr int kSortTile = 4096;                           // elements per sort block
+constexpr int kTileSortCap = 4096;                        // per-tile depth sort in LDS up to this length
 constexpr int kProjThreads = 256;
 constexpr int kPartialStride = 9;                         // floats per pair gradient
 // Pairs are also processed in fixed chunks of consecutive emission-order
@@ -115,8 +113,8 @@ void launch_project_fwd(const gsr_gaussians &g, const ViewTable &vt, const float
                         Rec *rec, float2 *ulo, uint32_t *zkey, uint32_t *count, hipStream_t st);
 
 // Exclusive scans / compaction / sorting / binning.
-void launch_compact_visible(const uint32_t *count, const uint32_t *zkey, uint64_t items, uint32_t *ckey,
-                            uint32_t *cval, uint32_t *block_tmp, WsHeader *hdr, hipStream_t st);
+void launch_compact_visible(const uint32_t *count, uint64_t items, uint32_t *vis, uint32_t *block_tmp, WsHeader *hdr,
+                            hipStream_t st);
 // Element count of a sort, read on the device: *n_dev, or (hdr set) the pair
 // count, 0 if the binning overflowed.
 struct SortCount {
@@ -129,23 +127,26 @@ struct SortCount {
 };
 // Stable LSD sort of (key, value) on bits [begin_bit, end_bit), 8 per pass,
 // ping-ponging between keys[cur]/keys[cur ^ 1]; `cur` ends at the result.
-// short_list: blocks of kSortTileShort elements instead of kSortTile.
 void radix_sort_u32(uint32_t *keys[2], uint32_t *vals[2], SortCount sc, uint64_t n_cap, int begin_bit, int end_bit,
-                    bool short_list, uint32_t *hist, uint32_t hist_blocks, uint32_t *digit_total, int &cur,
-                    hipStream_t st);
+                    uint32_t *hist, uint32_t hist_blocks, uint32_t *digit_total, int &cur, hipStream_t st);
+// Each tile's list (items in ascending id order after the stable tile sort)
+// sorted by (depth key, item); alt_hi/alt_lo: the free ping-pong buffers, used
+// for lists longer than kTileSortCap.
+void launch_tile_depth_sort(const uint2 *ranges, uint32_t total_tiles, uint32_t *pval, const uint32_t *zkey,
+                            uint32_t *alt_hi, uint32_t *alt_lo, const WsHeader *hdr, hipStream_t st);
 void launch_reset_queue(WsHeader *h, int which, hipStream_t st);
-void launch_pair_offsets(const uint32_t *sorted_items, const uint32_t *count, uint64_t items_cap,
+void launch_pair_offsets(const uint32_t *vis, const uint32_t *count, uint64_t items_cap,
                          uint32_t *poff, uint32_t *chunk_item, uint64_t chunks_cap, uint32_t *block_tmp,
                          WsHeader *hdr, hipStream_t st);
-void launch_emit_pairs(const ViewTable &vt, const uint32_t *sorted_items, const uint32_t *poff,
-                       const uint32_t *chunk_item, uint64_t n, uint64_t pair_grid, Rec *rec, uint32_t *rank,
-                       uint2 *item_box, uint32_t *pkey, uint32_t *pval, const WsHeader *hdr, hipStream_t st);
+void launch_emit_pairs(const ViewTable &vt, const uint32_t *vis, const uint32_t *poff, const uint32_t *chunk_item,
+                       uint64_t n, uint64_t pair_grid, Rec *rec, const uint32_t *zkey, uint4 *item_box,
+                       uint32_t *pkey, uint32_t *pval, const WsHeader *hdr, hipStream_t st);
 void launch_tile_ranges(const uint32_t *pkey, uint64_t cap, uint2 *ranges, uint32_t total_tiles,
                         const WsHeader *hdr, hipStream_t st);
 
 void launch_composite_fwd(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
-                          const float2 *ulo, const uint32_t *rank, float3 bg, float *out_rgb, float *out_T,
-                          float *pix_T, uint32_t *pix_n, uint2 *tile_cut, WsHeader *hdr, bool persistent,
+                          const float2 *ulo, const uint32_t *zkey, float3 bg, float *out_rgb, float *out_T,
+                          float *pix_T, uint32_t *pix_n, uint4 *tile_cut, WsHeader *hdr, bool persistent,
                           int persistent_ctas, bool stats, hipStream_t st);
 // Gradient rows of the Gaussians no view saw are zeroed by the backward
 // compositing (memory work hidden under its ALU work): tile t takes Gaussians
@@ -158,12 +159,11 @@ struct ZeroRows {
 };
 void launch_composite_bwd(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
                           const float2 *ulo, const float *out_rgb, const float *dL_drgb, const uint32_t *pix_n,
-                          const uint2 *tile_cut, float *partial, const ZeroRows &zr, WsHeader *hdr, bool persistent,
+                          const uint4 *tile_cut, float *partial, const ZeroRows &zr, WsHeader *hdr, bool persistent,
                           int persistent_ctas, hipStream_t st);
-void launch_pair_reduce(const ViewTable &vt, const uint32_t *sorted_items, const uint32_t *poff,
-                        const uint32_t *chunk_item, uint64_t n, uint64_t pair_grid, const uint2 *item_box,
-                        const uint2 *tile_cut, const float *partial, float4 *screen, float *carry,
-                        const WsHeader *hdr, hipStream_t st);
+void launch_pair_reduce(const ViewTable &vt, const uint32_t *poff, const uint32_t *chunk_item, uint64_t n,
+                        uint64_t pair_grid, const uint4 *item_box, const uint4 *tile_cut, const float *partial,
+                        float4 *screen, float *carry, const WsHeader *hdr, hipStream_t st);
 
 // zero_unseen: also write the zero rows of the Gaussians no view saw (when the
 // backward compositing did not).
@@ -235,31 +235,33 @@ __device__ __forceinline__ uint32_t pack_u16(uint32_t lo, uint32_t hi) { return 
 
 
 // ---------------------------------------------------------------------------
-// The items whose pairs fall in one chunk of emission-order slots.  Items own
-// contiguous pair ranges [poff[i], poff[i + 1]) in depth order, so a chunk
-// meets the depth ranks chunk_item[c] .. chunk_item[c + 1] (the last one only
-// if it starts before the chunk's end).  Each local item k gets its first pair,
-// the global id of its box's first tile, its box width in tiles (low 16 bits)
-// with its view's tiles per row (high 16 bits), and its item id; p0[nloc] is
-// the end of the last one.  Returns nloc.  Every thread of the workgroup calls it.
+// The items whose pairs fall in one chunk of emission-order slots.  The k-th
+// visible item (ascending item id) owns the contiguous pair range
+// [poff[k], poff[k + 1]), so a chunk meets the visible indices
+// chunk_item[c] .. chunk_item[c + 1] (the last one only if it starts before
+// the chunk's end).  Each local item gets its first pair, the global id of its
+// box's first tile, its box width in tiles (low 16 bits) with its view's tiles
+// per row (high 16 bits), its depth key and its item id; p0[nloc] is the end of
+// the last one.
 // ---------------------------------------------------------------------------
 struct ChunkItems {
     uint32_t p0[kChunkPairs + 2];
     uint32_t tile0[kChunkPairs + 1];
     uint32_t wx[kChunkPairs + 1];
     uint32_t item[kChunkPairs + 1];
+    uint32_t zkey[kChunkPairs + 1];
 };
 
 // The chunk's item range; every thread of the workgroup calls it (it ends
 // with a barrier).  Boxes come from the records (`boxes` NULL, emission) or
-// from the per-depth-rank box words emission wrote (later passes: one
-// coalesced load instead of a gather through the record).
-__device__ __forceinline__ uint32_t load_chunk_items(const ViewTable &vt, const uint32_t *__restrict__ sorted_items,
+// from the per-index box words emission wrote (later passes: one coalesced
+// 16-byte load instead of gathers through the item id).
+__device__ __forceinline__ uint32_t load_chunk_items(const ViewTable &vt, const uint32_t *__restrict__ vis,
                                                      const uint32_t *__restrict__ poff,
                                                      const uint32_t *__restrict__ chunk_item, uint64_t n,
-                                                     const Rec *__restrict__ rec, const uint2 *__restrict__ boxes,
-                                                     uint32_t c, uint32_t m, uint32_t nvis, ChunkItems &ci,
-                                                     uint32_t &i_lo) {
+                                                     const Rec *__restrict__ rec, const uint32_t *__restrict__ zkey,
+                                                     const uint4 *__restrict__ boxes, uint32_t c, uint32_t m,
+                                                     uint32_t nvis, ChunkItems &ci, uint32_t &i_lo) {
     const uint32_t c0 = c * kChunkPairs;
     i_lo = chunk_item[c];
     const uint32_t i_hi = c0 + kChunkPairs < m ? chunk_item[c + 1] : nvis - 1;
@@ -270,14 +272,15 @@ __device__ __forceinline__ uint32_t load_chunk_items(const ViewTable &vt, const 
             ci.p0[k] = i < nvis ? poff[i] : m;
             continue;
         }
-        const uint32_t item = sorted_items[i];
         ci.p0[k] = poff[i];
-        ci.item[k] = item;
         if (boxes) {
-            const uint2 bw = boxes[i];
+            const uint4 bw = boxes[i];
             ci.tile0[k] = bw.x;
             ci.wx[k] = bw.y;
+            ci.zkey[k] = bw.z;
+            ci.item[k] = bw.w;
         } else {
+            const uint32_t item = vis[i];
             const float4 r2 = rec[item].r2;
             const uint32_t bx = __float_as_uint(r2.y), by = __float_as_uint(r2.z);
             const uint32_t tx0 = (bx & 0xffffu) / kTileW, tx1 = (bx >> 16) / kTileW;
@@ -286,6 +289,8 @@ __device__ __forceinline__ uint32_t load_chunk_items(const ViewTable &vt, const 
             const uint32_t tiles_x = (uint32_t)vt.v[v].tiles_x;
             ci.tile0[k] = vt.v[v].tile_off + ty0 * tiles_x + tx0;
             ci.wx[k] = (tx1 - tx0 + 1) | (tiles_x << 16);
+            ci.zkey[k] = zkey[item];
+            ci.item[k] = item;
         }
     }
     __syncthreads();

@@ -271,8 +271,9 @@ void launch_project_fwd(const gsr_gaussians &g, const ViewTable &vt, const float
 // from one to thousands (splats near the camera), so the work is split by
 // pairs, not by items: a workgroup takes one chunk of 1024 consecutive pair
 // slots, 4 per thread (nine float4 loads per thread, coalesced).  Pairs whose
-// tile stopped before reaching the item (depth rank >= the tile's cut) were
-// never written by the backward compositing and count as zero.
+// tile stopped before reaching the item (its (depth key, item) at or beyond
+// the tile's cut) were never written by the backward compositing and count as
+// zero.
 //
 // Within the chunk a segmented inclusive scan over the threads (keys = local
 // item index, wave-level shuffles then a carry across the four waves) gives
@@ -306,11 +307,10 @@ __device__ __forceinline__ void write_item_sum(const ChunkItems &ci, uint32_t k,
     }
 }
 
-__global__ __launch_bounds__(kChunkThreads) void k_pair_reduce(ViewTable vt, const uint32_t *__restrict__ sorted_items,
-                                                               const uint32_t *__restrict__ poff,
+__global__ __launch_bounds__(kChunkThreads) void k_pair_reduce(ViewTable vt, const uint32_t *__restrict__ poff,
                                                                const uint32_t *__restrict__ chunk_item, uint64_t n,
-                                                               const uint2 *__restrict__ item_box,
-                                                               const uint2 *__restrict__ tile_cut,
+                                                               const uint4 *__restrict__ item_box,
+                                                               const uint4 *__restrict__ tile_cut,
                                                                const float *__restrict__ partial,
                                                                float4 *__restrict__ screen, float *__restrict__ carry,
                                                                const WsHeader *__restrict__ hdr) {
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(kChunkThreads) void k_pair_reduce(ViewTable vt, con
     }
     uint32_t i_lo;
     const uint32_t nloc =
-        load_chunk_items(vt, sorted_items, poff, chunk_item, n, nullptr, item_box, c, m, nvis, ci, i_lo);
+        load_chunk_items(vt, nullptr, poff, chunk_item, n, nullptr, nullptr, item_box, c, m, nvis, ci, i_lo);
     // keys and the cut mask (pairs beyond their tile's cut were never written)
     if (pb < cend) {
         PairWalker pw;
@@ -361,7 +361,9 @@ __global__ __launch_bounds__(kChunkThreads) void k_pair_reduce(ViewTable vt, con
             if (p < cend) {
                 if (u > 0) pw.next(ci, nloc, p);
                 key[u] = pw.k;
-                const bool valid = i_lo + pw.k < tile_cut[pw.tile(ci)].y;
+                const uint4 cut = tile_cut[pw.tile(ci)];
+                const uint32_t zk = ci.zkey[pw.k];
+                const bool valid = zk < cut.y || (zk == cut.y && ci.item[pw.k] < cut.z);
 #pragma unroll
                 for (int j = 0; j < kPartialStride; ++j) x[u][j] = valid ? x[u][j] : 0.f;
             } else {
@@ -456,14 +458,13 @@ __global__ __launch_bounds__(kChunkThreads) void k_pair_reduce(ViewTable vt, con
     if (kl != kNoKey && kf_next != kl) write_item_sum(ci, kl, c0, cend, c, v, screen, carry);
 }
 
-void launch_pair_reduce(const ViewTable &vt, const uint32_t *sorted_items, const uint32_t *poff,
-                        const uint32_t *chunk_item, uint64_t n, uint64_t pair_grid, const uint2 *item_box,
-                        const uint2 *tile_cut, const float *partial, float4 *screen, float *carry,
+void launch_pair_reduce(const ViewTable &vt, const uint32_t *poff, const uint32_t *chunk_item, uint64_t n,
+                        uint64_t pair_grid, const uint4 *item_box, const uint4 *tile_cut, const float *partial, float4 *screen, float *carry,
                         const WsHeader *hdr, hipStream_t st) {
     const uint64_t chunks = chunk_count(pair_grid);
     if (chunks == 0) return;
-    hipLaunchKernelGGL(k_pair_reduce, dim3((unsigned)chunks), dim3(kChunkThreads), 0, st, vt, sorted_items, poff,
-                       chunk_item, n, item_box, tile_cut, partial, screen, carry, hdr);
+    hipLaunchKernelGGL(k_pair_reduce, dim3((unsigned)chunks), dim3(kChunkThreads), 0, st, vt, poff, chunk_item,
+                       n, item_box, tile_cut, partial, screen, carry, hdr);
 }
 
 // ---------------------------------------------------------------------------

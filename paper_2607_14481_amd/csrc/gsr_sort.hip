@@ -1,17 +1,18 @@
 // gsr_sort.hip -- binning stages of the rasterizer on gfx950:
 //   A2 scans: visible-item compaction and per-item pair offsets (exclusive
 //      scans in u32 with saturating adds, reduce-then-scan, no spin waits)
-//   A4 radix sort: stable LSD passes of 8 bits over (key u32, value u32)
-//   A3 emission: (tile, item) pairs, written in depth order
+//   A3 emission: (tile, item) pairs, written in ascending item order
+//   A4 radix sort: stable LSD passes of 8 bits over (tile u32, item u32)
+//   A4c per-tile depth order: each tile's list sorted by (depth bits, item)
 //   A5 tile ranges: [start, end) of each tile in the sorted pairs
 //
 // Order of work.  The pairs must end up sorted by (tile, depth bits, item).
 // Rather than sorting 48-bit (tile, depth) keys over all M pairs (six 8-bit
-// passes over 12-byte records), the items are first sorted by depth (four
-// passes over the visible items only, M/N ~ 5-15 times fewer elements), the
-// pairs are emitted in that order, and a stable sort on the tile id alone
-// (ceil(tile_bits / 8) passes, two at 1080p) finishes the job.  Stability of
-// every pass gives the (tile, depth, item) order exactly.
+// passes over the pairs), the pairs are emitted in ascending item order, a
+// stable sort on the tile id alone (ceil(tile_bits / 8) passes, two at 1080p)
+// groups them by tile with each tile's list still in item order, and one
+// workgroup per tile sorts its short list by (depth bits, item) in LDS.  The
+// result is the (tile, depth, item) order exactly.
 //
 // Every kernel reads its element count from the workspace header, so the
 // launch grid can be sized for a capacity and the call needs no host
@@ -52,7 +53,7 @@ struct VisibleFlag {  // value = item visible (tiles touched > 0)
     const uint32_t *count;
     __device__ uint32_t operator()(uint64_t i) const { return count[i] > 0u ? 1u : 0u; }
 };
-struct CountInDepthOrder {  // value = tiles touched by the i-th item in depth order
+struct CountOfVisible {  // value = tiles touched by the i-th visible item
     const uint32_t *items;
     const uint32_t *count;
     __device__ uint32_t operator()(uint64_t i) const { return count[items[i]]; }
@@ -113,11 +114,9 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t *__restrict__ blo
 
 // Phase 3 for the compaction: visible items get their depth key and id written
 // at their exclusive prefix.
-__global__ __launch_bounds__(kScanThreads) void k_compact_apply(const uint32_t *__restrict__ count,
-                                                                const uint32_t *__restrict__ zkey, uint64_t n,
+__global__ __launch_bounds__(kScanThreads) void k_compact_apply(const uint32_t *__restrict__ count, uint64_t n,
                                                                 const uint32_t *__restrict__ block_sums,
-                                                                uint32_t *__restrict__ ckey,
-                                                                uint32_t *__restrict__ cval) {
+                                                                uint32_t *__restrict__ vis) {
     __shared__ uint32_t lds[4];
     const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
     uint32_t flags = 0, cnt = 0;
@@ -132,24 +131,19 @@ __global__ __launch_bounds__(kScanThreads) void k_compact_apply(const uint32_t *
     uint32_t pos = block_sums[blockIdx.x] + block_exclusive_scan(cnt, lds, total);
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        if (flags & (1u << k)) {
-            ckey[pos] = zkey[base + k];
-            cval[pos] = (uint32_t)(base + k);
-            ++pos;
-        }
+        if (flags & (1u << k)) vis[pos++] = (uint32_t)(base + k);
     }
 }
 
-void launch_compact_visible(const uint32_t *count, const uint32_t *zkey, uint64_t items, uint32_t *ckey,
-                            uint32_t *cval, uint32_t *block_tmp, WsHeader *hdr, hipStream_t st) {
+void launch_compact_visible(const uint32_t *count, uint64_t items, uint32_t *vis, uint32_t *block_tmp, WsHeader *hdr,
+                            hipStream_t st) {
     const uint32_t nb = (uint32_t)((items + kScanTile - 1) / kScanTile);
     if (nb == 0) return;
     hipLaunchKernelGGL(k_scan_reduce<VisibleFlag>, dim3(nb), dim3(kScanThreads), 0, st, VisibleFlag{count},
                        (const uint32_t *)nullptr, items, block_tmp);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, block_tmp, nb, &hdr->n_visible,
                        (WsHeader *)nullptr);
-    hipLaunchKernelGGL(k_compact_apply, dim3(nb), dim3(kScanThreads), 0, st, count, zkey, items, block_tmp, ckey,
-                       cval);
+    hipLaunchKernelGGL(k_compact_apply, dim3(nb), dim3(kScanThreads), 0, st, count, items, block_tmp, vis);
 }
 
 // Ordered compaction of byte flags: out_idx receives, in ascending order, the
@@ -188,10 +182,10 @@ void launch_compact_flags(const uint8_t *flags, uint64_t n, uint32_t *out_idx, u
     hipLaunchKernelGGL(k_flag_compact_apply, dim3(nb), dim3(kScanThreads), 0, st, flags, n, block_tmp, out_idx);
 }
 
-// Phase 3 for the pair offsets: poff[i] = exclusive prefix of counts in depth
-// order (the total and the overflow decision are already in the header).  The
+// Phase 3 for the pair offsets: poff[i] = exclusive prefix of the counts of the
+// visible items (the total and the overflow decision are already in the header).  The
 // item whose range holds a chunk's first pair is recorded for that chunk.
-__global__ __launch_bounds__(kScanThreads) void k_offsets_apply(CountInDepthOrder f,
+__global__ __launch_bounds__(kScanThreads) void k_offsets_apply(CountOfVisible f,
                                                                 const uint32_t *__restrict__ block_sums,
                                                                 uint32_t *__restrict__ poff,
                                                                 uint32_t *__restrict__ chunk_item,
@@ -222,13 +216,13 @@ __global__ __launch_bounds__(kScanThreads) void k_offsets_apply(CountInDepthOrde
     }
 }
 
-void launch_pair_offsets(const uint32_t *sorted_items, const uint32_t *count, uint64_t items_cap, uint32_t *poff,
+void launch_pair_offsets(const uint32_t *vis, const uint32_t *count, uint64_t items_cap, uint32_t *poff,
                          uint32_t *chunk_item, uint64_t chunks_cap, uint32_t *block_tmp, WsHeader *hdr,
                          hipStream_t st) {
     const uint32_t nb = (uint32_t)((items_cap + kScanTile - 1) / kScanTile);
     if (nb == 0) return;
-    CountInDepthOrder f{sorted_items, count};
-    hipLaunchKernelGGL(k_scan_reduce<CountInDepthOrder>, dim3(nb), dim3(kScanThreads), 0, st, f, &hdr->n_visible,
+    CountOfVisible f{vis, count};
+    hipLaunchKernelGGL(k_scan_reduce<CountOfVisible>, dim3(nb), dim3(kScanThreads), 0, st, f, &hdr->n_visible,
                        items_cap, block_tmp);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, block_tmp, nb, &hdr->n_pairs, hdr);
     hipLaunchKernelGGL(k_offsets_apply, dim3(nb), dim3(kScanThreads), 0, st, f, block_tmp, poff, chunk_item,
@@ -243,8 +237,7 @@ void launch_pair_offsets(const uint32_t *sorted_items, const uint32_t *count, ui
 // The element count is read on the device: either *n_dev or, for the pair
 // sort, 0 when the header flags an overflow.
 // ---------------------------------------------------------------------------
-// A block sorts TILE consecutive elements (4096 for the pairs; 1024 for the
-// much shorter list of visible items, so that more of the chip takes part).
+// A block sorts TILE consecutive elements.
 // Rounds of 64 consecutive elements per wave: wave w of a block owns the
 // block's elements [w * TILE / 4, (w + 1) * TILE / 4), which keeps the block's
 // order (wave, round, lane) equal to the input order.
@@ -425,28 +418,25 @@ static void radix_passes(uint32_t *keys[2], uint32_t *vals[2], SortCount sc, uin
 }
 
 void radix_sort_u32(uint32_t *keys[2], uint32_t *vals[2], SortCount sc, uint64_t n_cap, int begin_bit, int end_bit,
-                    bool short_list, uint32_t *hist, uint32_t hist_blocks, uint32_t *digit_total, int &cur,
-                    hipStream_t st) {
-    if (short_list)
-        radix_passes<kSortTileShort>(keys, vals, sc, n_cap, begin_bit, end_bit, hist, hist_blocks, digit_total, cur, st);
-    else
-        radix_passes<kSortTile>(keys, vals, sc, n_cap, begin_bit, end_bit, hist, hist_blocks, digit_total, cur, st);
+                    uint32_t *hist, uint32_t hist_blocks, uint32_t *digit_total, int &cur, hipStream_t st) {
+    radix_passes<kSortTile>(keys, vals, sc, n_cap, begin_bit, end_bit, hist, hist_blocks, digit_total, cur, st);
 }
 
 // ---------------------------------------------------------------------------
-// A3: emission.  The i-th item in depth order owns pairs [poff[i], poff[i] +
-// count) in row-major order over its tile box.  A workgroup writes one chunk
-// of 1024 consecutive pair slots, 4 per thread (16-byte stores, so the writes
-// are coalesced and equal per thread however the tile counts are spread): the
-// chunk's items are staged in LDS and each thread finds its pairs' item by
-// binary search there.  An item's depth rank and pair offset are recorded, by
-// the chunk in which its pairs start, for the backward.
+// A3: emission.  The k-th visible item (ascending item id) owns pairs
+// [poff[k], poff[k] + count) in row-major order over its tile box.  A workgroup
+// writes one chunk of 1024 consecutive pair slots, 4 per thread (16-byte
+// stores, so the writes are coalesced and equal per thread however the tile
+// counts are spread): the chunk's items are staged in LDS and each thread finds
+// its pairs' item by binary search there.  The chunk in which an item's pairs
+// start records its pair offset (in its record) and its box word (by visible
+// index) for the later passes.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kChunkThreads) void k_emit(ViewTable vt, const uint32_t *__restrict__ sorted_items,
+__global__ __launch_bounds__(kChunkThreads) void k_emit(ViewTable vt, const uint32_t *__restrict__ vis,
                                                         const uint32_t *__restrict__ poff,
                                                         const uint32_t *__restrict__ chunk_item, uint64_t n,
-                                                        Rec *__restrict__ rec, uint32_t *__restrict__ rank,
-                                                        uint2 *__restrict__ item_box, uint32_t *__restrict__ pkey,
+                                                        Rec *__restrict__ rec, const uint32_t *__restrict__ zkey,
+                                                        uint4 *__restrict__ item_box, uint32_t *__restrict__ pkey,
                                                         uint32_t *__restrict__ pval, const WsHeader *__restrict__ hdr) {
     __shared__ ChunkItems ci;
     if (hdr->overflow) return;
@@ -456,14 +446,12 @@ __global__ __launch_bounds__(kChunkThreads) void k_emit(ViewTable vt, const uint
     const uint32_t cend = min(c0 + kChunkPairs, m);
     uint32_t i_lo;
     const uint32_t nloc =
-        load_chunk_items(vt, sorted_items, poff, chunk_item, n, rec, nullptr, blockIdx.x, m, nvis, ci, i_lo);
+        load_chunk_items(vt, vis, poff, chunk_item, n, rec, zkey, nullptr, blockIdx.x, m, nvis, ci, i_lo);
     for (uint32_t k = threadIdx.x; k < nloc; k += kChunkThreads) {
         const uint32_t p = ci.p0[k];
         if (p >= c0 && p < cend) {
-            const uint32_t item = ci.item[k];
-            rank[item] = i_lo + k;
-            rec[item].r2.w = __uint_as_float(p);
-            item_box[i_lo + k] = make_uint2(ci.tile0[k], ci.wx[k]);
+            rec[ci.item[k]].r2.w = __uint_as_float(p);
+            item_box[i_lo + k] = make_uint4(ci.tile0[k], ci.wx[k], ci.zkey[k], ci.item[k]);
         }
     }
     const uint32_t pb = c0 + threadIdx.x * kChunkPerThread;
@@ -488,13 +476,331 @@ __global__ __launch_bounds__(kChunkThreads) void k_emit(ViewTable vt, const uint
     }
 }
 
-void launch_emit_pairs(const ViewTable &vt, const uint32_t *sorted_items, const uint32_t *poff,
-                       const uint32_t *chunk_item, uint64_t n, uint64_t pair_grid, Rec *rec, uint32_t *rank,
-                       uint2 *item_box, uint32_t *pkey, uint32_t *pval, const WsHeader *hdr, hipStream_t st) {
+void launch_emit_pairs(const ViewTable &vt, const uint32_t *vis, const uint32_t *poff, const uint32_t *chunk_item,
+                       uint64_t n, uint64_t pair_grid, Rec *rec, const uint32_t *zkey, uint4 *item_box,
+                       uint32_t *pkey, uint32_t *pval, const WsHeader *hdr, hipStream_t st) {
     const uint64_t chunks = chunk_count(pair_grid);
     if (chunks == 0) return;
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)chunks), dim3(kChunkThreads), 0, st, vt, sorted_items, poff, chunk_item,
-                       n, rec, rank, item_box, pkey, pval, hdr);
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)chunks), dim3(kChunkThreads), 0, st, vt, vis, poff, chunk_item, n, rec,
+                       zkey, item_box, pkey, pval, hdr);
+}
+
+// ---------------------------------------------------------------------------
+// A4c: per-tile depth order.  After the stable tile sort each tile's list holds
+// its items in ascending id order; it is sorted here by the 64-bit key
+// (depth key << 32 | item), the unique order of the compositing definition.
+//
+// The network is bitonic with every comparator oriented low-to-high: each
+// merge starts with a "flip" that pairs mirrored positions, then half-cleaners
+// at halving distances.  Lists are padded to a power of two with keys above
+// every real key, which the network leaves at the end.
+//
+// A workgroup of four waves takes four tiles.  A list of up to 1024 entries is
+// sorted by one wave, by a bucket pass (below) when the depths allow, else by
+// the network in registers: each lane holds
+// E (1..16) consecutive entries, so comparators closer than E are register
+// operations and the others pair lane l with lane l ^ m, fetched with DPP or
+// ds_swizzle (within 32 lanes) or ds_bpermute; a flip also mirrors the
+// register index.  Lists of 1025..4096 entries are sorted by all four waves
+// (16 entries per lane), exchanging through LDS only for the comparators that
+// cross waves (three steps).  Longer lists run the same network over global
+// memory, one comparator per thread and step.
+// ---------------------------------------------------------------------------
+typedef unsigned long long u64;
+constexpr u64 kPadKey = ~0ull;
+constexpr int kWaveSortMax = 1024;   // one wave, 16 entries per lane
+constexpr int kGroupSortMax = 4096;  // four waves, 16 entries per lane
+
+// v from lane (lane ^ M)
+template <int M>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v, int lane) {
+    if constexpr (M == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+    else if constexpr (M == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
+    else if constexpr (M == 3) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x1B, 0xF, 0xF, false);  // quad_perm 3,2,1,0
+    else if constexpr (M == 7) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, false); // row_half_mirror
+    else if constexpr (M == 8) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false); // row_ror 8
+    else if constexpr (M == 15) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, false); // row_mirror
+    else if constexpr (M < 32) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (M << 10));  // xor in 32 lanes
+    else return (uint32_t)__builtin_amdgcn_ds_bpermute((lane ^ M) << 2, (int)v);
+}
+
+template <int M>
+__device__ __forceinline__ u64 lane_xor64(u64 v, int lane) {
+    const uint32_t lo = lane_xor<M>((uint32_t)v, lane), hi = lane_xor<M>((uint32_t)(v >> 32), lane);
+    return ((u64)hi << 32) | lo;
+}
+
+__device__ __forceinline__ void order_regs(u64 &a, u64 &b) {
+    const u64 x = a, y = b;
+    a = x < y ? x : y;
+    b = x < y ? y : x;
+}
+
+// keep the smaller of (mine, other) when `low`, else the larger
+__device__ __forceinline__ u64 keep(u64 mine, u64 other, bool low) { return (other < mine) == low ? other : mine; }
+
+// One comparator step of the network over P = 64 * E * W keys: merge size K,
+// distance J (J == K / 2 is the flip).  key[r] of lane `lane` in wave `wave`
+// is entry wave * 64E + lane * E + r.  W > 1 exchanges across waves through
+// `xs` (64 * E * W words) and requires every thread of the W waves.
+template <int E, int W, int K, int J>
+__device__ __forceinline__ void bitonic_step(u64 (&key)[E], int lane, int wave, uint32_t *xs) {
+    constexpr bool kFlip = J == K / 2;
+    if constexpr (J < E) {  // both entries in this lane's registers
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            if constexpr (kFlip) {
+                if ((r ^ (K - 1)) > r) order_regs(key[r], key[r ^ (K - 1)]);
+            } else {
+                if (!(r & J)) order_regs(key[r], key[r + J]);
+            }
+        }
+    } else if constexpr (J < 64 * E) {  // another lane of this wave
+        if constexpr (kFlip) {
+            const bool low = !(lane & (K / (2 * E)));
+            u64 o[E];
+#pragma unroll
+            for (int r = 0; r < E; ++r) o[r] = lane_xor64<K / E - 1>(key[E - 1 - r], lane);
+#pragma unroll
+            for (int r = 0; r < E; ++r) key[r] = keep(key[r], o[r], low);
+        } else {
+            const bool low = !(lane & (J / E));
+#pragma unroll
+            for (int r = 0; r < E; ++r) key[r] = keep(key[r], lane_xor64<J / E>(key[r], lane), low);
+        }
+    } else {  // another wave: through LDS, one 32-bit half at a time
+        static_assert(W > 1, "cross-wave steps need several waves");
+        constexpr int M = kFlip ? K / (64 * E) - 1 : J / (64 * E);
+        const bool low = !(wave & (kFlip ? K / (128 * E) : M));
+        const int pw = wave ^ M, pl = kFlip ? lane ^ 63 : lane;
+        uint32_t half[2][E];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int r = 0; r < E; ++r) xs[(r * W + wave) * 64 + lane] = (uint32_t)(key[r] >> (32 * h));
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < E; ++r) half[h][r] = xs[((kFlip ? E - 1 - r : r) * W + pw) * 64 + pl];
+            __syncthreads();
+        }
+#pragma unroll
+        for (int r = 0; r < E; ++r) key[r] = keep(key[r], ((u64)half[1][r] << 32) | half[0][r], low);
+    }
+}
+
+template <int E, int W, int K, int J>
+__device__ __forceinline__ void bitonic_merge(u64 (&key)[E], int lane, int wave, uint32_t *xs) {
+    bitonic_step<E, W, K, J>(key, lane, wave, xs);
+    if constexpr (J > 1) bitonic_merge<E, W, K, J / 2>(key, lane, wave, xs);
+}
+
+template <int E, int W, int K = 2>
+__device__ __forceinline__ void register_bitonic(u64 (&key)[E], int lane, int wave, uint32_t *xs) {
+    bitonic_merge<E, W, K, K / 2>(key, lane, wave, xs);
+    if constexpr (K < 64 * E * W) register_bitonic<E, W, 2 * K>(key, lane, wave, xs);
+}
+
+// Sort list[0, len) of item ids by (zkey[item], item); the caller's threads
+// are `W` whole waves and 64 * E * W >= len.
+template <int E, int W>
+__device__ __forceinline__ void sort_list_regs(uint32_t *__restrict__ list, uint32_t len,
+                                               const uint32_t *__restrict__ zkey, int lane, int wave, uint32_t *xs) {
+    u64 key[E];
+    const uint32_t base = (uint32_t)(wave * 64 + lane) * E;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const uint32_t i = base + r;
+        const uint32_t item = i < len ? list[i] : 0u;
+        key[r] = i < len ? (((u64)zkey[item] << 32) | item) : kPadKey;
+    }
+    register_bitonic<E, W>(key, lane, wave, xs);
+#pragma unroll
+    for (int r = 0; r < E; ++r)
+        if (base + r < len) list[base + r] = (uint32_t)key[r];
+}
+
+// Fast path for one wave: a counting sort on a bucket index that is a
+// monotone function of the depth key, b = floor((z - zmin) * NB / (zmax - zmin
+// + 1)) in FP32 (conversion, product and truncation are all non-decreasing, so
+// bucket order never contradicts key order).  Entries are dropped into their
+// bucket in arrival order; each then counts the bucket-mates with a smaller
+// 64-bit key and stores itself at bucket start + that count.  For depths
+// spread over the tile's range a bucket holds about one entry, so the ranking
+// costs a read or two per entry, all independent.  Returns false, having
+// written nothing, when some bucket holds more than kMaxBucket entries
+// (clustered depths): the caller then sorts with the network, whose cost does
+// not depend on the keys.
+constexpr uint32_t kMaxBucket = 16;
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int E>
+__device__ bool bucket_sort_wave(uint32_t *__restrict__ list, uint32_t len, const uint32_t *__restrict__ zkey,
+                                 int lane, u64 *buf, uint32_t *cnt) {
+    constexpr uint32_t NB = 64 * E;
+#pragma unroll
+    for (int r = 0; r < E; ++r) cnt[r * 64 + lane] = 0u;
+    u64 key[E];
+    uint32_t zmin = 0xffffffffu, zmax = 0u;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const uint32_t i = (uint32_t)(r * 64 + lane);
+        const uint32_t item = i < len ? list[i] : 0u;
+        const uint32_t z = i < len ? zkey[item] : 0u;
+        key[r] = ((u64)z << 32) | item;
+        if (i < len) zmin = min(zmin, z), zmax = max(zmax, z);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        zmin = min(zmin, (uint32_t)__shfl_xor((int)zmin, o, 64));
+        zmax = max(zmax, (uint32_t)__shfl_xor((int)zmax, o, 64));
+    }
+    wave_sync();
+    const float scale = (float)NB / ((float)(zmax - zmin) + 1.0f);
+    uint32_t bk[E], slot[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        if ((uint32_t)(r * 64 + lane) < len) {
+            const uint32_t z = (uint32_t)(key[r] >> 32);
+            bk[r] = min(NB - 1, (uint32_t)((float)(z - zmin) * scale));
+            slot[r] = atomicAdd(&cnt[bk[r]], 1u);
+        }
+    }
+    wave_sync();
+    // lane owns buckets [lane * E, lane * E + E): their exclusive starts
+    uint32_t c[E], run = 0, big = 0;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        c[j] = cnt[lane * E + j];
+        run += c[j];
+        big = max(big, c[j]);
+    }
+    uint32_t incl = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) big = max(big, (uint32_t)__shfl_xor((int)big, o, 64));
+    if (big > kMaxBucket) return false;  // uniform
+    uint32_t st = incl - run;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        cnt[lane * E + j] = (st << 16) | c[j];  // start < 2^16, count <= kMaxBucket
+        st += c[j];
+    }
+    wave_sync();
+    uint32_t sc[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        if ((uint32_t)(r * 64 + lane) < len) {
+            sc[r] = cnt[bk[r]];
+            buf[(sc[r] >> 16) + slot[r]] = key[r];
+        }
+    }
+    wave_sync();
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        if ((uint32_t)(r * 64 + lane) < len) {
+            const uint32_t s0 = sc[r] >> 16, n = sc[r] & 0xffffu;
+            uint32_t rank = 0;
+            for (uint32_t q = 0; q < n; ++q) rank += buf[s0 + q] < key[r] ? 1u : 0u;
+            list[s0 + rank] = (uint32_t)key[r];
+        }
+    }
+    return true;
+}
+
+template <int E>
+__device__ __forceinline__ void sort_list_wave(uint32_t *__restrict__ list, uint32_t len,
+                                               const uint32_t *__restrict__ zkey, int lane, u64 *buf, uint32_t *cnt) {
+    if (!bucket_sort_wave<E>(list, len, zkey, lane, buf, cnt)) sort_list_regs<E, 1>(list, len, zkey, lane, 0, nullptr);
+}
+
+// The same network over global memory, for lists beyond kGroupSortMax
+// (comparators with an entry past the end are skipped: those entries act as
+// +infinity).  Runs on the whole workgroup.
+__device__ void sort_list_global(uint32_t *__restrict__ list, uint32_t len, const uint32_t *__restrict__ zkey,
+                                 uint32_t *__restrict__ hi, uint32_t *__restrict__ lo) {
+    for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
+        const uint32_t item = list[i];
+        hi[i] = zkey[item];
+        lo[i] = item;
+    }
+    __syncthreads();
+    uint32_t p2 = 1;
+    while (p2 < len) p2 <<= 1;
+    for (uint32_t k = 2; k <= p2; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t c = threadIdx.x; c < p2 / 2; c += blockDim.x) {
+                const uint32_t a = ((c & ~(j - 1)) << 1) | (c & (j - 1));
+                const uint32_t b = j == (k >> 1) ? (a ^ (k - 1)) : (a + j);
+                if (b < len) {
+                    const uint32_t ha = hi[a], hb = hi[b], la = lo[a], lb = lo[b];
+                    if (ha > hb || (ha == hb && la > lb)) hi[a] = hb, hi[b] = ha, lo[a] = lb, lo[b] = la;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) list[i] = lo[i];
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_tile_depth_sort(const uint2 *__restrict__ ranges, uint32_t total_tiles,
+                                                         uint32_t *__restrict__ pval, const uint32_t *__restrict__ zkey,
+                                                         uint32_t *__restrict__ alt_hi, uint32_t *__restrict__ alt_lo,
+                                                         const WsHeader *__restrict__ hdr) {
+    __shared__ u64 s_buf[4][kWaveSortMax];
+    __shared__ uint32_t s_cnt[4][kWaveSortMax];
+    if (hdr->overflow) return;  // uniform
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t t0 = blockIdx.x * 4;
+    // one wave per list of up to kWaveSortMax entries
+    const uint32_t t = t0 + wave;
+    if (t < total_tiles) {
+        const uint2 rg = ranges[t];
+        const uint32_t len = rg.y - rg.x;
+        uint32_t *list = pval + rg.x;
+        u64 *buf = s_buf[wave];
+        uint32_t *cnt = s_cnt[wave];
+        if (len <= 1) {
+        } else if (len <= 64) {
+            sort_list_wave<1>(list, len, zkey, lane, buf, cnt);
+        } else if (len <= 128) {
+            sort_list_wave<2>(list, len, zkey, lane, buf, cnt);
+        } else if (len <= 256) {
+            sort_list_wave<4>(list, len, zkey, lane, buf, cnt);
+        } else if (len <= 512) {
+            sort_list_wave<8>(list, len, zkey, lane, buf, cnt);
+        } else if (len <= (uint32_t)kWaveSortMax) {
+            sort_list_wave<16>(list, len, zkey, lane, buf, cnt);
+        }
+    }
+    // longer lists: the whole workgroup, one list at a time (uniform branches;
+    // the exchange area reuses the waves' buffers once every wave is done)
+    __syncthreads();
+    uint32_t *xs = reinterpret_cast<uint32_t *>(&s_buf[0][0]);
+    for (uint32_t u = t0; u < t0 + 4 && u < total_tiles; ++u) {
+        const uint2 rg = ranges[u];
+        const uint32_t len = rg.y - rg.x;
+        if (len <= (uint32_t)kWaveSortMax) continue;
+        if (len <= (uint32_t)kGroupSortMax)
+            sort_list_regs<16, 4>(pval + rg.x, len, zkey, lane, wave, xs);
+        else
+            sort_list_global(pval + rg.x, len, zkey, alt_hi + rg.x, alt_lo + rg.x);
+    }
+}
+
+void launch_tile_depth_sort(const uint2 *ranges, uint32_t total_tiles, uint32_t *pval, const uint32_t *zkey,
+                            uint32_t *alt_hi, uint32_t *alt_lo, const WsHeader *hdr, hipStream_t st) {
+    if (total_tiles == 0) return;
+    hipLaunchKernelGGL(k_tile_depth_sort, dim3((total_tiles + 3) / 4), dim3(256), 0, st, ranges, total_tiles, pval,
+                       zkey, alt_hi, alt_lo, hdr);
 }
 
 // ---------------------------------------------------------------------------

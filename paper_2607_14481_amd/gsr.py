@@ -79,7 +79,7 @@ class gsr_stats(C.Structure):
                 ("contributors", C.c_int64), ("replays", C.c_int64)]
 
 
-STAGES = ("project", "depth_sort", "emit", "tile_sort", "composite_fwd", "composite_bwd", "project_bwd")
+STAGES = ("project", "compact", "emit", "tile_sort", "composite_fwd", "composite_bwd", "project_bwd")
 
 
 _lib = None

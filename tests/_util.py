@@ -72,3 +72,30 @@ def rel_err(a, b):
 
 
 GRAD_KEYS = ("means", "log_scales", "quats", "opacities", "sh")
+
+
+def oracle_bin_from_gpu_state(st, cams, n, tile_h=16):
+    """Tier (i): the oracle's integer binning fed with the GPU's boxes and depth bits."""
+    from oracle import oracle as O
+    rec = st["records"]
+    bx = rec[:, 9].view(np.uint32)
+    by = rec[:, 10].view(np.uint32)
+    vis = st["tile_counts"] > 0
+    tiles_all, items_all = [], []
+    tile_off = 0
+    ranges = []
+    for v, c in enumerate(cams):
+        sl = slice(v * n, (v + 1) * n)
+        trect = np.stack([(bx[sl] & 0xffff) // 16, (by[sl] & 0xffff) // tile_h,
+                          (bx[sl] >> 16) // 16, (by[sl] >> 16) // tile_h], 1).astype(np.int32)
+        tx, ty = O.tile_grid(c, (16, tile_h))
+        t, g, r = O.bin_pairs(vis[sl], trect, st["depth_keys"][sl], tx, ty)
+        base = sum(len(x) for x in tiles_all)
+        tiles_all.append(t.astype(np.uint64) + tile_off)
+        items_all.append(g.astype(np.uint64) + v * n)
+        rr = r.astype(np.int64)
+        nonempty = rr[:, 1] > rr[:, 0]
+        rr[nonempty] += base
+        ranges.append(rr)
+        tile_off += tx * ty
+    return (np.concatenate(tiles_all), np.concatenate(items_all), np.concatenate(ranges))

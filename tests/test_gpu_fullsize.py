@@ -11,7 +11,7 @@ import pytest
 from oracle import oracle as O
 from paper_2607_14481_amd import scenes as S
 
-from ._util import GRAD_KEYS, gpu_render, log, rel_err
+from ._util import GRAD_KEYS, gpu_render, log, oracle_bin_from_gpu_state, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -54,6 +54,21 @@ def _sampled_parity(wl, n_tiles, seed, bg=(0.0, 0.0, 0.0)):
 
 def test_headline_1080p_1M_sampled_parity():
     _sampled_parity(S.headline_view(), n_tiles=24, seed=101)
+
+
+def test_headline_1080p_1M_binning_bit_exact():
+    """The whole tile list of the benchmark view (5M+ pairs, lists up to ~2000
+    entries) against the oracle's integer binning fed the GPU's boxes and
+    depth bits."""
+    wl = S.headline_view()
+    sc, cams = wl.scene, wl.cameras
+    st = gpu_render(sc, cams, export=True)["state"]
+    tiles, items, ranges = oracle_bin_from_gpu_state(st, cams, sc.n)
+    lens = ranges[:, 1].astype(np.int64) - ranges[:, 0]
+    log(f"headline binning: M gpu={st['M']} oracle={len(tiles)}; longest list {int(lens.max())}")
+    assert st["M"] == len(tiles)
+    np.testing.assert_array_equal(st["pair_tiles"].astype(np.uint64), tiles)
+    np.testing.assert_array_equal(st["pair_items"].astype(np.uint64), items)
 
 
 def test_single_view_1080p_200k_sampled_parity():

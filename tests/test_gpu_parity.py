@@ -13,7 +13,7 @@ import pytest
 from oracle import oracle as O
 from paper_2607_14481_amd import scenes as S
 
-from ._util import GRAD_KEYS, gpu_render, log, rel_err
+from ._util import GRAD_KEYS, gpu_render, log, oracle_bin_from_gpu_state, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -59,32 +59,6 @@ def test_small_view_forward_backward_parity():
     assert rel_err(gpu["twist"][0], ref["twist"]) <= GRAD_TOL
 
 
-def _oracle_bin_from_gpu_state(st, cams, n, tile_h=16):
-    """Tier (i): the oracle's integer binning fed with the GPU's boxes and depth bits."""
-    rec = st["records"]
-    bx = rec[:, 9].view(np.uint32)
-    by = rec[:, 10].view(np.uint32)
-    vis = st["tile_counts"] > 0
-    tiles_all, items_all = [], []
-    tile_off = 0
-    ranges = []
-    for v, c in enumerate(cams):
-        sl = slice(v * n, (v + 1) * n)
-        trect = np.stack([(bx[sl] & 0xffff) // 16, (by[sl] & 0xffff) // tile_h,
-                          (bx[sl] >> 16) // 16, (by[sl] >> 16) // tile_h], 1).astype(np.int32)
-        tx, ty = O.tile_grid(c, (16, tile_h))
-        t, g, r = O.bin_pairs(vis[sl], trect, st["depth_keys"][sl], tx, ty)
-        base = sum(len(x) for x in tiles_all)
-        tiles_all.append(t.astype(np.uint64) + tile_off)
-        items_all.append(g.astype(np.uint64) + v * n)
-        rr = r.astype(np.int64)
-        nonempty = rr[:, 1] > rr[:, 0]
-        rr[nonempty] += base
-        ranges.append(rr)
-        tile_off += tx * ty
-    return (np.concatenate(tiles_all), np.concatenate(items_all), np.concatenate(ranges))
-
-
 @pytest.mark.parametrize("case", ["small", "ring3"])
 def test_binning_bit_exact(case):
     if case == "small":
@@ -98,7 +72,7 @@ def test_binning_bit_exact(case):
     log(f"binning {case}: n={sc.n} views={len(cams)}")
     gpu = gpu_render(sc, cams, export=True)
     st = gpu["state"]
-    tiles, items, ranges = _oracle_bin_from_gpu_state(st, cams, sc.n)
+    tiles, items, ranges = oracle_bin_from_gpu_state(st, cams, sc.n)
     log(f"binning {case}: M gpu={st['M']} oracle={len(tiles)}")
     assert st["M"] == len(tiles)
     np.testing.assert_array_equal(st["pair_tiles"].astype(np.uint64), tiles)
@@ -130,6 +104,32 @@ def test_binning_bit_exact(case):
         np.testing.assert_allclose(rec[sl, 6:9][gvis], pr["rgb"][gvis], rtol=1e-6, atol=1e-7)
     log(f"binning {case}: FP64-vs-GPU box/depth mismatches = {mism}")
     assert mism == 0
+
+
+@pytest.mark.parametrize("n,step", [(2, 0.25), (63, 0.25), (64, 0.25), (65, 0.25), (129, 0.25), (1023, 0.25),
+                                    (1024, 0.25), (1025, 0.25), (2049, 0.25), (4096, 0.25), (4097, 0.25), (9000, 0.25),
+                                    (65, 1e-4), (700, 1e-4), (1024, 1e-4), (1000, 0.0)])
+def test_single_tile_list_lengths(n, step):
+    """Every Gaussian lands in one tile, so that tile's list has exactly n
+    entries: the lengths at which the per-tile depth sort changes form (one
+    wave with 1..16 entries per lane, four waves, global memory).  Depths are
+    rounded to `step` metres: at 0.25 m most keys tie (clustered depths, the
+    network path); at 0.1 mm a few keys tie among well-spread ones (the bucket
+    path, where the item must still break the tie); 0 leaves them as drawn."""
+    wl = S.small_view(seed=30 + n % 97, n=n, width=40, height=24, log_scale_mean=-7.0, xy_half=0.002)
+    m = wl.scene.means.copy()
+    if step > 0:
+        m[:, 2] = np.round(m[:, 2] / step) * step
+    sc, cams = wl.scene.with_means(m), wl.cameras
+    log(f"single-tile list: n={n} step={step}")
+    st = gpu_render(sc, cams, export=True)["state"]
+    tiles, items, ranges = oracle_bin_from_gpu_state(st, cams, sc.n)
+    lens = ranges[:, 1] - ranges[:, 0]
+    log(f"single-tile list: n={n} tile lengths {lens.tolist()}")
+    assert lens.max() == n
+    assert st["M"] == len(tiles)
+    np.testing.assert_array_equal(st["pair_tiles"].astype(np.uint64), tiles)
+    np.testing.assert_array_equal(st["pair_items"].astype(np.uint64), items)
 
 
 @pytest.mark.parametrize("deg,w,h,n,seed", [(0, 50, 37, 300, 11), (1, 64, 64, 400, 12), (2, 33, 90, 350, 13),
