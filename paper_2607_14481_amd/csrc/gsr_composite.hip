@@ -104,9 +104,16 @@ __device__ __forceinline__ uint32_t next_tile(bool persistent, uint32_t *queue, 
     return __shfl(t, 0, kWave);
 }
 
-// exponent of alpha, e2 = -sigma log2e, for the pixel at (dx, dy) from the centre
-__device__ __forceinline__ float neg_sigma_log2e(const float4 &a, const float4 &b, float dx, float dy) {
-    return fmaf(fmaf(a.z, dx, a.w * dy), dx, b.x * dy * dy);
+// Exponent of alpha, e2 = -sigma log2e = a.z dx^2 + a.w dx dy + b.x dy^2, for
+// the pixel at (dx, dy) from the centre.  A lane's pixels share dx, so the dx
+// terms are formed once per Gaussian (RowQuad) and each row evaluates
+// (b.x dy + a.w dx) dy + a.z dx^2 by two fused multiply-adds.
+struct RowQuad {
+    float p, q;  // a.z dx^2, a.w dx
+};
+__device__ __forceinline__ RowQuad row_quad(const float4 &a, float dx) { return RowQuad{a.z * dx * dx, a.w * dx}; }
+__device__ __forceinline__ float neg_sigma_log2e(const RowQuad &rq, const float4 &b, float dy) {
+    return fmaf(fmaf(b.x, dy, rq.q), dy, rq.p);
 }
 
 // ---------------------------------------------------------------------------
@@ -171,11 +178,12 @@ __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uin
                 const uint32_t pos = b0 - rg.x + (uint32_t)j;
                 const float dx = a.x - pxl;
                 const uint32_t smask = slab_mask(d.y);
+                const RowQuad rq = row_quad(a, dx);
 #pragma unroll
                 for (int k = 0; k < RPL; ++k) {
                     if (!(smask & (1u << k))) continue;
                     const float dy = a.y - ((float)(ly + 4 * k) + 0.5f);
-                    const float e2 = neg_sigma_log2e(a, b, dx, dy);
+                    const float e2 = neg_sigma_log2e(rq, b, dy);
                     const float ex = e2 + b.y;
                     if (__ballot(T[k] > 0.f && ex >= kLog2AlphaSkip) == 0ull) continue;
                     const float alpha = fminf(kAlphaMax, __builtin_amdgcn_exp2f(ex));
@@ -349,11 +357,13 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
                         const float4 a = sa[j], b = sb[j], d = sd[j];
                         const float dx = a.x - pxl;
                         const uint32_t smask = slab_mask(d.y);
+                        const RowQuad rq = row_quad(a, dx);
+                        float sy = 0.f, syy = 0.f;  // sums over this lane's rows of sa dy, sa dy^2
 #pragma unroll
                         for (int k = 0; k < RPL; ++k) {
                             if (!(smask & (1u << k))) continue;
                             const float dy = a.y - ((float)(ly + 4 * k) + 0.5f);
-                            const float e2 = neg_sigma_log2e(a, b, dx, dy);
+                            const float e2 = neg_sigma_log2e(rq, b, dy);
                             const float ex = e2 + b.y;
                             if (__ballot(pos < ncon[k] && ex >= kLog2AlphaSkip) == 0ull) continue;
                             const float araw = __builtin_amdgcn_exp2f(ex);
@@ -372,13 +382,17 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
                             // dL/dsigma = -sa, alpha dL/dalpha = sa (zero through the 0.99 clamp)
                             const float sa_ = (ok && araw < kAlphaMax) ? dalpha * alpha : 0.f;
                             s[5] += sa_;
-                            const float wx = -sa_ * dx, wy = -sa_ * dy;
-                            s[0] += wx;
-                            s[1] += wy;
-                            s[2] = fmaf(wx, dx, s[2]);
-                            s[3] = fmaf(wx, dy, s[3]);
-                            s[4] = fmaf(wy, dy, s[4]);
+                            const float say = sa_ * dy;
+                            sy += say;
+                            syy = fmaf(say, dy, syy);
                         }
+                        // moments of dL/dsigma = -sa; the lane's rows share dx
+                        const float ndx = -dx;
+                        s[0] = ndx * s[5];
+                        s[1] = -sy;
+                        s[2] = ndx * dx * s[5];
+                        s[3] = ndx * sy;
+                        s[4] = -syy;
                     }
                     // add the neighbouring lane (quad_perm [1, 0, 3, 2]); even lanes store the pair sum
 #pragma unroll

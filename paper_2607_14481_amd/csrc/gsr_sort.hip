@@ -248,11 +248,12 @@ struct SortShape {
     static constexpr int kItems = TILE / kSortThreads;
 };
 
-// Lanes of the wave holding the same 8-bit digit as this lane (8 ballots).
-__device__ __forceinline__ unsigned long long digit_peers(bool ok, uint32_t d) {
+// Lanes of the wave holding the same digit (of `bits` <= 8 bits) as this lane.
+__device__ __forceinline__ unsigned long long digit_peers(bool ok, uint32_t d, int bits) {
     unsigned long long match = __ballot(ok);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
+        if (b >= bits) break;
         const unsigned long long bal = __ballot(ok && ((d >> b) & 1u));
         match &= ((d >> b) & 1u) ? bal : ~bal;
     }
@@ -262,7 +263,7 @@ __device__ __forceinline__ unsigned long long digit_peers(bool ok, uint32_t d) {
 // Per-block digit histogram (LDS atomics; all loads are issued first).
 template <int TILE>
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *__restrict__ keys, SortCount sc,
-                                                             int shift, uint32_t *__restrict__ hist,
+                                                             int shift, uint32_t mask, uint32_t *__restrict__ hist,
                                                              uint32_t hist_blocks) {
     __shared__ uint32_t h[256];
     const uint64_t n = sc();
@@ -279,7 +280,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *__r
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < SortShape<TILE>::kItems; ++r)
-        if ((uint32_t)r * kSortThreads + threadIdx.x < m) atomicAdd(&h[(k[r] >> shift) & 255u], 1u);
+        if ((uint32_t)r * kSortThreads + threadIdx.x < m) atomicAdd(&h[(k[r] >> shift) & mask], 1u);
     __syncthreads();
     hist[(size_t)threadIdx.x * hist_blocks + blockIdx.x] = h[threadIdx.x];
 }
@@ -319,7 +320,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
                                                                 const uint32_t *__restrict__ vin,
                                                                 uint32_t *__restrict__ kout,
                                                                 uint32_t *__restrict__ vout, SortCount sc, int shift,
-                                                                const uint32_t *__restrict__ hist,
+                                                                int bits, const uint32_t *__restrict__ hist,
                                                                 uint32_t hist_blocks,
                                                                 const uint32_t *__restrict__ digit_total) {
     __shared__ uint32_t gbase[256];      // global position of this block's first element of each digit
@@ -334,6 +335,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t t = threadIdx.x;
     const uint32_t m = (uint32_t)min((uint64_t)TILE, n - blk);
+    const uint32_t mask = (1u << bits) - 1u;
     uint32_t key[SortShape<TILE>::kRounds], val[SortShape<TILE>::kRounds];
 #pragma unroll
     for (int r = 0; r < SortShape<TILE>::kRounds; ++r) {
@@ -343,9 +345,12 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
     }
     {
         uint32_t total;
-        const uint32_t ex = block_exclusive_scan(digit_total[t], lds, total);
-        const uint32_t mine = hist[(size_t)t * hist_blocks + blockIdx.x];
-        const uint32_t next = blockIdx.x + 1 < nb ? hist[(size_t)t * hist_blocks + blockIdx.x + 1] : digit_total[t];
+        // digits above the mask do not occur in this pass (their totals were not scanned)
+        const bool used = t <= mask;
+        const uint32_t tot = used ? digit_total[t] : 0u;
+        const uint32_t ex = block_exclusive_scan(tot, lds, total);
+        const uint32_t mine = used ? hist[(size_t)t * hist_blocks + blockIdx.x] : 0u;
+        const uint32_t next = !used ? 0u : blockIdx.x + 1 < nb ? hist[(size_t)t * hist_blocks + blockIdx.x + 1] : tot;
         gbase[t] = ex + mine;
         lbase[t] = block_exclusive_scan(next - mine, lds, total);
     }
@@ -357,8 +362,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
     for (int r = 0; r < SortShape<TILE>::kRounds; ++r) {
         const uint32_t li = (uint32_t)(w * SortShape<TILE>::kWaveSpan + r * 64 + lane);
         const bool ok = li < m;
-        const uint32_t d = (key[r] >> shift) & 255u;
-        const unsigned long long peers = digit_peers(ok, d);
+        const uint32_t d = (key[r] >> shift) & mask;
+        const unsigned long long peers = digit_peers(ok, d, bits);
         const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
         const uint32_t before = ok ? wcnt[w][d] : 0u;
         pos[r] = before + rank;
@@ -381,7 +386,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
     for (int r = 0; r < SortShape<TILE>::kRounds; ++r) {
         const uint32_t li = (uint32_t)(w * SortShape<TILE>::kWaveSpan + r * 64 + lane);
         if (li < m) {
-            const uint32_t p = wcnt[w][(key[r] >> shift) & 255u] + pos[r];
+            const uint32_t p = wcnt[w][(key[r] >> shift) & mask] + pos[r];
             skey[p] = key[r];
             sval[p] = val[r];
         }
@@ -390,7 +395,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
     // write out in local order: runs of one digit go to consecutive addresses
     for (uint32_t p = t; p < m; p += kSortThreads) {
         const uint32_t k = skey[p];
-        const uint32_t d = (k >> shift) & 255u;
+        const uint32_t d = (k >> shift) & mask;
         const uint32_t g = gbase[d] + (p - lbase[d]);
         kout[g] = k;
         vout[g] = sval[p];
@@ -402,18 +407,27 @@ static void radix_passes(uint32_t *keys[2], uint32_t *vals[2], SortCount sc, uin
                          int end_bit, uint32_t *hist, uint32_t hist_blocks, uint32_t *digit_total, int &cur,
                          hipStream_t st) {
     const uint32_t nb = (uint32_t)((n_cap + TILE - 1) / TILE);
-    for (int shift = begin_bit; shift < end_bit; shift += 8) {
+    // as many 8-bit passes as the key needs, with the bits spread evenly over
+    // them (13 bits: 7 + 6): fewer digits per pass means longer runs per digit
+    // in each block's output, so better coalesced writes
+    const int total_bits = end_bit - begin_bit;
+    const int passes = (total_bits + 7) / 8;
+    for (int pass = 0, shift = begin_bit; pass < passes; ++pass) {
+        const int bits = (end_bit - shift + (passes - pass) - 1) / (passes - pass);
         // the result buffer depends only on the number of passes, not on n
         if (nb == 0) {
             cur ^= 1;
+            shift += bits;
             continue;
         }
-        hipLaunchKernelGGL(k_radix_hist<TILE>, dim3(nb), dim3(kSortThreads), 0, st, keys[cur], sc, shift, hist,
+        const uint32_t mask = (1u << bits) - 1u;
+        hipLaunchKernelGGL(k_radix_hist<TILE>, dim3(nb), dim3(kSortThreads), 0, st, keys[cur], sc, shift, mask, hist,
                            hist_blocks);
-        hipLaunchKernelGGL(k_radix_scan<TILE>, dim3(256), dim3(256), 0, st, hist, hist_blocks, sc, digit_total);
+        hipLaunchKernelGGL(k_radix_scan<TILE>, dim3(1u << bits), dim3(256), 0, st, hist, hist_blocks, sc, digit_total);
         hipLaunchKernelGGL(k_radix_scatter<TILE>, dim3(nb), dim3(kSortThreads), 0, st, keys[cur], vals[cur],
-                           keys[cur ^ 1], vals[cur ^ 1], sc, shift, hist, hist_blocks, digit_total);
+                           keys[cur ^ 1], vals[cur ^ 1], sc, shift, bits, hist, hist_blocks, digit_total);
         cur ^= 1;
+        shift += bits;
     }
 }
 
@@ -508,8 +522,8 @@ void launch_emit_pairs(const ViewTable &vt, const uint32_t *vis, const uint32_t 
 // ---------------------------------------------------------------------------
 typedef unsigned long long u64;
 constexpr u64 kPadKey = ~0ull;
-constexpr int kWaveSortMax = 1024;   // one wave, 16 entries per lane
-constexpr int kGroupSortMax = 4096;  // four waves, 16 entries per lane
+constexpr int kBlockBucketMax = 1024;  // bucket path: four waves, up to 4 entries per lane
+constexpr int kGroupSortMax = 4096;    // network in registers: four waves, 16 entries per lane
 
 // v from lane (lane ^ M)
 template <int M>
@@ -619,93 +633,96 @@ __device__ __forceinline__ void sort_list_regs(uint32_t *__restrict__ list, uint
         if (base + r < len) list[base + r] = (uint32_t)key[r];
 }
 
-// Fast path for one wave: a counting sort on a bucket index that is a
-// monotone function of the depth key, b = floor((z - zmin) * NB / (zmax - zmin
-// + 1)) in FP32 (conversion, product and truncation are all non-decreasing, so
-// bucket order never contradicts key order).  Entries are dropped into their
-// bucket in arrival order; each then counts the bucket-mates with a smaller
-// 64-bit key and stores itself at bucket start + that count.  For depths
-// spread over the tile's range a bucket holds about one entry, so the ranking
-// costs a read or two per entry, all independent.  Returns false, having
-// written nothing, when some bucket holds more than kMaxBucket entries
-// (clustered depths): the caller then sorts with the network, whose cost does
-// not depend on the keys.
+// Fast path: a counting sort on a bucket index that is a monotone function of
+// the depth key, b = floor((z - zmin) * NB / (zmax - zmin + 1)) in FP32
+// (conversion, product and truncation are all non-decreasing, so bucket order
+// never contradicts key order).  Entries are dropped into their bucket in
+// arrival order; each then counts the bucket-mates with a smaller 64-bit key
+// and stores itself at bucket start + that count.  For depths spread over the
+// tile's range a bucket holds about one entry, so the ranking costs a read or
+// two per entry, all independent.  Returns false, having written nothing, when
+// some bucket holds more than kMaxBucket entries (clustered depths): the
+// caller then sorts with the network, whose cost does not depend on the keys.
+// Runs on the whole workgroup (256 threads, E entries each: NB = 256 E).
 constexpr uint32_t kMaxBucket = 16;
 
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
 }
 
 template <int E>
-__device__ bool bucket_sort_wave(uint32_t *__restrict__ list, uint32_t len, const uint32_t *__restrict__ zkey,
-                                 int lane, u64 *buf, uint32_t *cnt) {
-    constexpr uint32_t NB = 64 * E;
+__device__ bool bucket_sort_block(uint32_t *__restrict__ list, uint32_t len, const uint32_t *__restrict__ zkey,
+                                  u64 *buf, uint32_t *cnt, uint32_t *red /* [8] */) {
+    constexpr uint32_t NB = 256 * E;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 #pragma unroll
-    for (int r = 0; r < E; ++r) cnt[r * 64 + lane] = 0u;
+    for (int r = 0; r < E; ++r) cnt[r * 256 + tid] = 0u;
     u64 key[E];
     uint32_t zmin = 0xffffffffu, zmax = 0u;
 #pragma unroll
     for (int r = 0; r < E; ++r) {
-        const uint32_t i = (uint32_t)(r * 64 + lane);
+        const uint32_t i = (uint32_t)r * 256 + tid;
         const uint32_t item = i < len ? list[i] : 0u;
         const uint32_t z = i < len ? zkey[item] : 0u;
         key[r] = ((u64)z << 32) | item;
         if (i < len) zmin = min(zmin, z), zmax = max(zmax, z);
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        zmin = min(zmin, (uint32_t)__shfl_xor((int)zmin, o, 64));
-        zmax = max(zmax, (uint32_t)__shfl_xor((int)zmax, o, 64));
-    }
-    wave_sync();
+    zmin = wave_min_u32(zmin);
+    zmax = wave_max_u32(zmax);
+    if (lane == 0) red[wave] = zmin, red[4 + wave] = zmax;
+    __syncthreads();
+    zmin = min(min(red[0], red[1]), min(red[2], red[3]));
+    zmax = max(max(red[4], red[5]), max(red[6], red[7]));
     const float scale = (float)NB / ((float)(zmax - zmin) + 1.0f);
     uint32_t bk[E], slot[E];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
-        if ((uint32_t)(r * 64 + lane) < len) {
+        if ((uint32_t)r * 256 + tid < len) {
             const uint32_t z = (uint32_t)(key[r] >> 32);
             bk[r] = min(NB - 1, (uint32_t)((float)(z - zmin) * scale));
             slot[r] = atomicAdd(&cnt[bk[r]], 1u);
         }
     }
-    wave_sync();
-    // lane owns buckets [lane * E, lane * E + E): their exclusive starts
+    __syncthreads();
+    // thread owns buckets [tid * E, tid * E + E): their exclusive starts
     uint32_t c[E], run = 0, big = 0;
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-        c[j] = cnt[lane * E + j];
+        c[j] = cnt[tid * E + j];
         run += c[j];
         big = max(big, c[j]);
     }
-    uint32_t incl = run;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = (uint32_t)__shfl_up((int)incl, o, 64);
-        if (lane >= o) incl += y;
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) big = max(big, (uint32_t)__shfl_xor((int)big, o, 64));
+    big = wave_max_u32(big);
+    if (lane == 0) red[wave] = big;  // (red was last read before the barrier above)
+    uint32_t total;
+    uint32_t st = block_exclusive_scan(run, red + 4, total);  // ends with a barrier
+    big = max(max(red[0], red[1]), max(red[2], red[3]));
     if (big > kMaxBucket) return false;  // uniform
-    uint32_t st = incl - run;
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-        cnt[lane * E + j] = (st << 16) | c[j];  // start < 2^16, count <= kMaxBucket
+        cnt[tid * E + j] = (st << 16) | c[j];  // start < 2^16, count <= kMaxBucket
         st += c[j];
     }
-    wave_sync();
+    __syncthreads();
     uint32_t sc[E];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
-        if ((uint32_t)(r * 64 + lane) < len) {
+        if ((uint32_t)r * 256 + tid < len) {
             sc[r] = cnt[bk[r]];
             buf[(sc[r] >> 16) + slot[r]] = key[r];
         }
     }
-    wave_sync();
+    __syncthreads();
 #pragma unroll
     for (int r = 0; r < E; ++r) {
-        if ((uint32_t)(r * 64 + lane) < len) {
+        if ((uint32_t)r * 256 + tid < len) {
             const uint32_t s0 = sc[r] >> 16, n = sc[r] & 0xffffu;
             uint32_t rank = 0;
             for (uint32_t q = 0; q < n; ++q) rank += buf[s0 + q] < key[r] ? 1u : 0u;
@@ -716,9 +733,13 @@ __device__ bool bucket_sort_wave(uint32_t *__restrict__ list, uint32_t len, cons
 }
 
 template <int E>
-__device__ __forceinline__ void sort_list_wave(uint32_t *__restrict__ list, uint32_t len,
-                                               const uint32_t *__restrict__ zkey, int lane, u64 *buf, uint32_t *cnt) {
-    if (!bucket_sort_wave<E>(list, len, zkey, lane, buf, cnt)) sort_list_regs<E, 1>(list, len, zkey, lane, 0, nullptr);
+__device__ __forceinline__ void sort_list_block(uint32_t *__restrict__ list, uint32_t len,
+                                                const uint32_t *__restrict__ zkey, u64 *buf, uint32_t *cnt,
+                                                uint32_t *red, uint32_t *xs) {
+    if (!bucket_sort_block<E>(list, len, zkey, buf, cnt, red)) {
+        __syncthreads();  // the network reuses the exchange area
+        sort_list_regs<E, 4>(list, len, zkey, threadIdx.x & 63, threadIdx.x >> 6, xs);
+    }
 }
 
 // The same network over global memory, for lists beyond kGroupSortMax
@@ -755,52 +776,34 @@ __global__ __launch_bounds__(256) void k_tile_depth_sort(const uint2 *__restrict
                                                          uint32_t *__restrict__ pval, const uint32_t *__restrict__ zkey,
                                                          uint32_t *__restrict__ alt_hi, uint32_t *__restrict__ alt_lo,
                                                          const WsHeader *__restrict__ hdr) {
-    __shared__ u64 s_buf[4][kWaveSortMax];
-    __shared__ uint32_t s_cnt[4][kWaveSortMax];
+    __shared__ u64 s_buf[kGroupSortMax / 2];  // bucket entries; the network's exchange area (16 KB)
+    __shared__ uint32_t s_cnt[kBlockBucketMax];
+    __shared__ uint32_t s_red[8];
     if (hdr->overflow) return;  // uniform
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint32_t t0 = blockIdx.x * 4;
-    // one wave per list of up to kWaveSortMax entries
-    const uint32_t t = t0 + wave;
-    if (t < total_tiles) {
-        const uint2 rg = ranges[t];
-        const uint32_t len = rg.y - rg.x;
-        uint32_t *list = pval + rg.x;
-        u64 *buf = s_buf[wave];
-        uint32_t *cnt = s_cnt[wave];
-        if (len <= 1) {
-        } else if (len <= 64) {
-            sort_list_wave<1>(list, len, zkey, lane, buf, cnt);
-        } else if (len <= 128) {
-            sort_list_wave<2>(list, len, zkey, lane, buf, cnt);
-        } else if (len <= 256) {
-            sort_list_wave<4>(list, len, zkey, lane, buf, cnt);
-        } else if (len <= 512) {
-            sort_list_wave<8>(list, len, zkey, lane, buf, cnt);
-        } else if (len <= (uint32_t)kWaveSortMax) {
-            sort_list_wave<16>(list, len, zkey, lane, buf, cnt);
-        }
-    }
-    // longer lists: the whole workgroup, one list at a time (uniform branches;
-    // the exchange area reuses the waves' buffers once every wave is done)
-    __syncthreads();
-    uint32_t *xs = reinterpret_cast<uint32_t *>(&s_buf[0][0]);
-    for (uint32_t u = t0; u < t0 + 4 && u < total_tiles; ++u) {
-        const uint2 rg = ranges[u];
-        const uint32_t len = rg.y - rg.x;
-        if (len <= (uint32_t)kWaveSortMax) continue;
-        if (len <= (uint32_t)kGroupSortMax)
-            sort_list_regs<16, 4>(pval + rg.x, len, zkey, lane, wave, xs);
-        else
-            sort_list_global(pval + rg.x, len, zkey, alt_hi + rg.x, alt_lo + rg.x);
-    }
+    const uint32_t t = blockIdx.x;
+    if (t >= total_tiles) return;
+    const uint2 rg = ranges[t];
+    const uint32_t len = rg.y - rg.x;
+    uint32_t *list = pval + rg.x;
+    uint32_t *xs = reinterpret_cast<uint32_t *>(s_buf);
+    if (len <= 1) return;
+    if (len <= 256)
+        sort_list_block<1>(list, len, zkey, s_buf, s_cnt, s_red, xs);
+    else if (len <= 512)
+        sort_list_block<2>(list, len, zkey, s_buf, s_cnt, s_red, xs);
+    else if (len <= (uint32_t)kBlockBucketMax)
+        sort_list_block<4>(list, len, zkey, s_buf, s_cnt, s_red, xs);
+    else if (len <= (uint32_t)kGroupSortMax)
+        sort_list_regs<16, 4>(list, len, zkey, threadIdx.x & 63, threadIdx.x >> 6, xs);
+    else
+        sort_list_global(list, len, zkey, alt_hi + rg.x, alt_lo + rg.x);
 }
 
 void launch_tile_depth_sort(const uint2 *ranges, uint32_t total_tiles, uint32_t *pval, const uint32_t *zkey,
                             uint32_t *alt_hi, uint32_t *alt_lo, const WsHeader *hdr, hipStream_t st) {
     if (total_tiles == 0) return;
-    hipLaunchKernelGGL(k_tile_depth_sort, dim3((total_tiles + 3) / 4), dim3(256), 0, st, ranges, total_tiles, pval,
-                       zkey, alt_hi, alt_lo, hdr);
+    hipLaunchKernelGGL(k_tile_depth_sort, dim3(total_tiles), dim3(256), 0, st, ranges, total_tiles, pval, zkey,
+                       alt_hi, alt_lo, hdr);
 }
 
 // ---------------------------------------------------------------------------

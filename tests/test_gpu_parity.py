@@ -106,13 +106,13 @@ def test_binning_bit_exact(case):
     assert mism == 0
 
 
-@pytest.mark.parametrize("n,step", [(2, 0.25), (63, 0.25), (64, 0.25), (65, 0.25), (129, 0.25), (1023, 0.25),
+@pytest.mark.parametrize("n,step", [(2, 0.25), (63, 0.25), (256, 0.25), (257, 0.25), (512, 0.25), (513, 0.25),
                                     (1024, 0.25), (1025, 0.25), (2049, 0.25), (4096, 0.25), (4097, 0.25), (9000, 0.25),
-                                    (65, 1e-4), (700, 1e-4), (1024, 1e-4), (1000, 0.0)])
+                                    (65, 1e-4), (257, 1e-4), (700, 1e-4), (1024, 1e-4), (1000, 0.0)])
 def test_single_tile_list_lengths(n, step):
     """Every Gaussian lands in one tile, so that tile's list has exactly n
-    entries: the lengths at which the per-tile depth sort changes form (one
-    wave with 1..16 entries per lane, four waves, global memory).  Depths are
+    entries: the lengths at which the per-tile depth sort changes form (1, 2
+    or 4 entries per thread, 16 per thread in registers, global memory).  Depths are
     rounded to `step` metres: at 0.25 m most keys tie (clustered depths, the
     network path); at 0.1 mm a few keys tie among well-spread ones (the bucket
     path, where the item must still break the tie); 0 leaves them as drawn."""
