@@ -359,7 +359,7 @@ int gsr_rasterize_backward(void *ws, size_t ws_bytes, const gsr_gaussians *g, in
     mark.begin(GSR_STAGE_PROJECT_BWD);
     launch_pair_reduce(vt, p.poff, p.chunk_item, (uint64_t)g->n, cap, p.item_box, p.tile_cut, p.partial,
                        p.screen, p.carry, p.hdr, st);
-    launch_project_bwd(*g, vt, world_to_cam, (uint64_t)g->n, p.rec, p.count, p.hdr, p.screen, p.carry, *grads,
+    launch_project_bwd(*g, vt, world_to_cam, (uint64_t)g->n, p.rec, p.count, p.vis, p.hdr, p.screen, p.carry, *grads,
                        p.pose_part, L.pose_blocks, vt.total_tiles == 0, st);
     if (g->n == 0)  // no Gaussian wrote a partial: the pose gradient is zero
         launch_fill_u32(reinterpret_cast<uint32_t *>(p.pose_part), 0u, 12ull * vt.n_views * L.pose_blocks, st);

@@ -188,11 +188,12 @@ __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uin
                     if (__ballot(T[k] > 0.f && ex >= kLog2AlphaSkip) == 0ull) continue;
                     const float alpha = fminf(kAlphaMax, __builtin_amdgcn_exp2f(ex));
                     const bool ok = e2 <= 0.f && alpha >= kAlphaMin;
-                    const float Tn = T[k] * (1.f - alpha);
+                    const float wa = alpha * T[k];
+                    const float Tn = T[k] - wa;  // T (1 - alpha)
                     // a stopped pixel has Tn <= 0 < kTMin, so it never adds again
                     const bool stop = ok && Tn < kTMin;
                     const bool add = ok && !stop;
-                    const float w = add ? alpha * T[k] : 0.f;
+                    const float w = add ? wa : 0.f;
                     C0[k] = fmaf(b.z, w, C0[k]);
                     C1[k] = fmaf(b.w, w, C1[k]);
                     C2[k] = fmaf(d.x, w, C2[k]);
@@ -350,15 +351,15 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
 #pragma unroll
                 for (int q = 0; q < kGroup; ++q) {
                     const int j = j0 + q;
-                    // S_x S_y S_xx S_xy S_yy (moments of dL/dsigma), S_o, colour gradient
-                    float s[kPartialStride] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+                    // per-lane sums over the rows: colour-gradient weights w, sa = alpha
+                    // dL/dalpha, sa dy and sa dy^2 (the rows share dx)
+                    float a_c0 = 0.f, a_c1 = 0.f, a_c2 = 0.f, a_sa = 0.f, a_say = 0.f, a_sayy = 0.f, dx = 0.f;
                     if (j < cnt) {
                         const uint32_t pos = b0 - rg.x + (uint32_t)j;
                         const float4 a = sa[j], b = sb[j], d = sd[j];
-                        const float dx = a.x - pxl;
+                        dx = a.x - pxl;
                         const uint32_t smask = slab_mask(d.y);
                         const RowQuad rq = row_quad(a, dx);
-                        float sy = 0.f, syy = 0.f;  // sums over this lane's rows of sa dy, sa dy^2
 #pragma unroll
                         for (int k = 0; k < RPL; ++k) {
                             if (!(smask & (1u << k))) continue;
@@ -370,30 +371,35 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
                             const float alpha = fminf(kAlphaMax, araw);
                             const bool ok = pos < ncon[k] && e2 <= 0.f && alpha >= kAlphaMin;
                             const float w = ok ? alpha * T[k] : 0.f;
-                            s[6] = fmaf(w, g0[k], s[6]);
-                            s[7] = fmaf(w, g1[k], s[7]);
-                            s[8] = fmaf(w, g2[k], s[8]);
+                            a_c0 = fmaf(w, g0[k], a_c0);
+                            a_c1 = fmaf(w, g1[k], a_c1);
+                            a_c2 = fmaf(w, g2[k], a_c2);
                             const float grgb = fmaf(g0[k], b.z, fmaf(g1[k], b.w, g2[k] * d.x));
                             gacc[k] = fmaf(w, grgb, gacc[k]);
                             const float one_m = 1.f - alpha;
                             const float dalpha =
                                 fmaf(T[k], grgb, -(gout[k] - gacc[k]) * __builtin_amdgcn_rcpf(one_m));
-                            T[k] = ok ? T[k] * one_m : T[k];
+                            T[k] -= w;  // T (1 - alpha) where the Gaussian contributed
                             // dL/dsigma = -sa, alpha dL/dalpha = sa (zero through the 0.99 clamp)
                             const float sa_ = (ok && araw < kAlphaMax) ? dalpha * alpha : 0.f;
-                            s[5] += sa_;
+                            a_sa += sa_;
                             const float say = sa_ * dy;
-                            sy += say;
-                            syy = fmaf(say, dy, syy);
+                            a_say += say;
+                            a_sayy = fmaf(say, dy, a_sayy);
                         }
-                        // moments of dL/dsigma = -sa; the lane's rows share dx
-                        const float ndx = -dx;
-                        s[0] = ndx * s[5];
-                        s[1] = -sy;
-                        s[2] = ndx * dx * s[5];
-                        s[3] = ndx * sy;
-                        s[4] = -syy;
                     }
+                    // S_x S_y S_xx S_xy S_yy (moments of dL/dsigma = -sa), S_o, colour gradient
+                    float s[kPartialStride];
+                    const float ndx = -dx;
+                    s[0] = ndx * a_sa;
+                    s[1] = -a_say;
+                    s[2] = ndx * dx * a_sa;
+                    s[3] = ndx * a_say;
+                    s[4] = -a_sayy;
+                    s[5] = a_sa;
+                    s[6] = a_c0;
+                    s[7] = a_c1;
+                    s[8] = a_c2;
                     // add the neighbouring lane (quad_perm [1, 0, 3, 2]); even lanes store the pair sum
 #pragma unroll
                     for (int cc = 0; cc < kPartialStride; ++cc) s[cc] = dpp_add<0xB1, 0xf>(s[cc]);

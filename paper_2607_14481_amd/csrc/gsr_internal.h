@@ -168,9 +168,9 @@ void launch_pair_reduce(const ViewTable &vt, const uint32_t *poff, const uint32_
 // zero_unseen: also write the zero rows of the Gaussians no view saw (when the
 // backward compositing did not).
 void launch_project_bwd(const gsr_gaussians &g, const ViewTable &vt, const float *w2c, uint64_t n,
-                        const Rec *rec, const uint32_t *count, const WsHeader *hdr, const float4 *screen,
-                        const float *carry, const gsr_gaussian_grads &gr, float *pose_part, uint32_t pose_blocks,
-                        bool zero_unseen, hipStream_t st);
+                        const Rec *rec, const uint32_t *count, const uint32_t *vis, const WsHeader *hdr,
+                        const float4 *screen, const float *carry, const gsr_gaussian_grads &gr, float *pose_part,
+                        uint32_t pose_blocks, bool zero_unseen, hipStream_t st);
 void launch_pose_finalize(const ViewTable &vt, const float *w2c, const float *pose_part, uint32_t pose_blocks,
                           float *dL_dw2c, float *dL_dtwist, hipStream_t st);
 
@@ -213,7 +213,10 @@ void launch_sim3_relocate(float *means, float *quats, float *log_scales, uint64_
 // by `row_mask` (other rows add 0).
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float dpp_add(float v) {
-    return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+    if constexpr (ROW_MASK == 0xf)  // every lane reads a source lane: no "old" value needed, the move folds into the add
+        return v + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
+    else
+        return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
 }
 
 // Sum over the 64 lanes of a wave, with VALU data-parallel-primitive moves

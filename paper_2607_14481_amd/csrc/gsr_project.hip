@@ -510,6 +510,251 @@ __device__ __forceinline__ void store_sh_row(float *__restrict__ dst, const floa
     }
 }
 
+// Chain rule of one visible (view, Gaussian) item: its screen-space gradient
+// (from the pair moments) back to the Gaussian's parameters (added to gmu, gls,
+// gq, gop and to the SH row gsh: stored by the first view, added to by later
+// ones) and to the view's pose (added to gW, gt).
+template <int DEG>
+__device__ __forceinline__ void item_backward(const gsr_gaussians &g, const ViewInfo &cam, const float *__restrict__ w2c,
+                                              int v, uint64_t i, uint64_t item, uint32_t cnt,
+                                              const Rec *__restrict__ rec, const float4 *__restrict__ screen,
+                                              const float *__restrict__ carry, float *__restrict__ gsh,
+                                              bool &sh_written, float (&gmu)[3], float (&gls)[3], float (&gq)[4],
+                                              float &gop, float (&gW)[9], float (&gt)[3]) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    constexpr bool kVecSH = (3 * K) % 4 == 0;
+    const float4 r0 = rec[item].r0, r1 = rec[item].r1;
+    float S[kPartialStride];
+    item_moments(screen, carry, item, __float_as_uint(rec[item].r2.w), cnt, S);
+    const float gu = fmaf(r0.z, S[0], r0.w * S[1]), gv = fmaf(r0.w, S[0], r1.x * S[1]);
+    const float gA = 0.5f * S[2], gB = S[3], gC = 0.5f * S[4], go = S[5] / r1.y;
+    const float grgb[3] = {S[6], S[7], S[8]};
+
+    float W[9], t[3];
+    load_pose(w2c, v, W, t);
+    const float mu[3] = {g.means[3 * i], g.means[3 * i + 1], g.means[3 * i + 2]};
+    const double pxd = (double)W[0] * mu[0] + (double)W[1] * mu[1] + (double)W[2] * mu[2] + (double)t[0];
+    const double pyd = (double)W[3] * mu[0] + (double)W[4] * mu[1] + (double)W[5] * mu[2] + (double)t[1];
+    const double pzd = (double)W[6] * mu[0] + (double)W[7] * mu[1] + (double)W[8] * mu[2] + (double)t[2];
+    const float p[3] = {(float)pxd, (float)pyd, (float)pzd};
+
+    gop += go;
+
+    // ---- colour -> SH coefficients and direction
+    const float cxw = -(W[0] * t[0] + W[3] * t[1] + W[6] * t[2]);
+    const float cyw = -(W[1] * t[0] + W[4] * t[1] + W[7] * t[2]);
+    const float czw = -(W[2] * t[0] + W[5] * t[1] + W[8] * t[2]);
+    float dvec[3] = {mu[0] - cxw, mu[1] - cyw, mu[2] - czw};
+    const float dn = sqrtf(dvec[0] * dvec[0] + dvec[1] * dvec[1] + dvec[2] * dvec[2]);
+    const float dir[3] = {dvec[0] / dn, dvec[1] / dn, dvec[2] / dn};
+    float Y[K];
+    sh_eval<DEG, float>(dir[0], dir[1], dir[2], Y);
+    float shv[3 * K];
+    if constexpr (kVecSH) {
+        const float4 *src = reinterpret_cast<const float4 *>(g.sh) + (size_t)i * (3 * K / 4);
+#pragma unroll
+        for (int k = 0; k < 3 * K / 4; ++k) {
+            const float4 f = src[k];
+            shv[4 * k] = f.x, shv[4 * k + 1] = f.y, shv[4 * k + 2] = f.z, shv[4 * k + 3] = f.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 3 * K; ++k) shv[k] = g.sh[(size_t)i * K * 3 + k];
+    }
+    // colour, to know which channels the forward clamped at 0
+    float col[3] = {0.5f, 0.5f, 0.5f};
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        col[0] = fmaf(shv[3 * k], Y[k], col[0]);
+        col[1] = fmaf(shv[3 * k + 1], Y[k], col[1]);
+        col[2] = fmaf(shv[3 * k + 2], Y[k], col[2]);
+    }
+    float gc[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gc[c] = col[c] < 0.f ? 0.f : grgb[c];
+    // coefficient gradients (added to an earlier view's) and the weights of dRGB/ddir
+    float wdir[K], o[3 * K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        o[3 * k] = gc[0] * Y[k];
+        o[3 * k + 1] = gc[1] * Y[k];
+        o[3 * k + 2] = gc[2] * Y[k];
+        wdir[k] = fmaf(gc[0], shv[3 * k], fmaf(gc[1], shv[3 * k + 1], gc[2] * shv[3 * k + 2]));
+    }
+    if (sh_written) {
+#pragma unroll
+        for (int k = 0; k < 3 * K; ++k) o[k] += gsh[k];
+    }
+    store_sh_row<K, kVecSH>(gsh, o);
+    sh_written = true;
+    float gdx, gdy, gdz;
+    sh_grad_dir<DEG>(dir[0], dir[1], dir[2], wdir, gdx, gdy, gdz);
+    const float dd = gdx * dir[0] + gdy * dir[1] + gdz * dir[2];
+    const float gd[3] = {(gdx - dir[0] * dd) / dn, (gdy - dir[1] * dd) / dn, (gdz - dir[2] * dd) / dn};
+    // mean gets +gd, camera centre gets -gd; c_a = -sum_b W[b][a] t_b
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        gmu[a] += gd[a];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            gW[3 * b + a] += t[b] * gd[a];
+            gt[b] += W[3 * b + a] * gd[a];
+        }
+    }
+
+    // ---- recompute the covariance chain
+    const float4 qf = reinterpret_cast<const float4 *>(g.quats)[i];
+    const float qn = sqrtf(qf.x * qf.x + qf.y * qf.y + qf.z * qf.z + qf.w * qf.w);
+    const float q[4] = {qf.x / qn, qf.y / qn, qf.z / qn, qf.w / qn};
+    float R[9];
+    quat_rot<float>(q[0], q[1], q[2], q[3], R);
+    const float sc[3] = {expf(g.log_scales[3 * i]), expf(g.log_scales[3 * i + 1]),
+                         expf(g.log_scales[3 * i + 2])};
+    float M[9];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) M[3 * a + b] = R[3 * a + b] * sc[b];
+    float Sg[9];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            Sg[3 * a + b] = M[3 * a] * M[3 * b] + M[3 * a + 1] * M[3 * b + 1] + M[3 * a + 2] * M[3 * b + 2];
+    const float rx = (float)(pxd / pzd), ry = (float)(pyd / pzd);
+    const float rxc = fminf(fmaxf(rx, -cam.limx), cam.limx);
+    const float ryc = fminf(fmaxf(ry, -cam.limy), cam.limy);
+    const float iz = 1.f / p[2];
+    float J[6] = {cam.fx * iz, 0.f, -cam.fx * rxc * iz, 0.f, cam.fy * iz, -cam.fy * ryc * iz};
+    float T[6];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            T[3 * a + b] = J[3 * a] * W[b] + J[3 * a + 1] * W[3 + b] + J[3 * a + 2] * W[6 + b];
+    float TS[6];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            TS[3 * a + b] = T[3 * a] * Sg[b] + T[3 * a + 1] * Sg[3 + b] + T[3 * a + 2] * Sg[6 + b];
+    const double ca = (double)(TS[0] * T[0] + TS[1] * T[1] + TS[2] * T[2]) + (double)kLowPass;
+    const double cb = (double)(TS[0] * T[3] + TS[1] * T[4] + TS[2] * T[5]);
+    const double cc = (double)(TS[3] * T[3] + TS[4] * T[4] + TS[5] * T[5]) + (double)kLowPass;
+    // ---- conic (A, B, C) -> covariance (a, b, c)
+    const double D = ca * cc - cb * cb;
+    const double iD2 = 1.0 / (D * D);
+    const float ga = (float)((-cc * cc * gA + cb * cc * gB - cb * cb * gC) * iD2);
+    const float gb = (float)((2.0 * cb * cc * gA - (ca * cc + cb * cb) * gB + 2.0 * ca * cb * gC) * iD2);
+    const float gcv = (float)((-cb * cb * gA + ca * cb * gB - ca * ca * gC) * iD2);
+    const float G2[4] = {ga, 0.5f * gb, 0.5f * gb, gcv};
+    // gSigma = T^T G2 T (3x3), gT = 2 G2 T Sigma (2x3)
+    float gS[9];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            gS[3 * a + b] = T[a] * (G2[0] * T[b] + G2[1] * T[3 + b]) + T[3 + a] * (G2[2] * T[b] + G2[3] * T[3 + b]);
+    float gT[6];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            gT[3 * a + b] = 2.f * (G2[2 * a] * TS[b] + G2[2 * a + 1] * TS[3 + b]);
+    // T = J W: gJ = gT W^T, gW += J^T gT
+    float gJ[6];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            gJ[3 * a + b] = gT[3 * a] * W[3 * b] + gT[3 * a + 1] * W[3 * b + 1] + gT[3 * a + 2] * W[3 * b + 2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) gW[3 * a + b] += J[a] * gT[b] + J[3 + a] * gT[3 + b];
+    // J entries -> camera-space mean
+    float gp[3] = {0.f, 0.f, 0.f};
+    const float iz2 = iz * iz;
+    gp[2] += -cam.fx * iz2 * gJ[0] - cam.fy * iz2 * gJ[4];
+    const float grxc = -cam.fx * iz * gJ[2];
+    const float gryc = -cam.fy * iz * gJ[5];
+    gp[2] += cam.fx * rxc * iz2 * gJ[2] + cam.fy * ryc * iz2 * gJ[5];
+    if (rx >= -cam.limx && rx <= cam.limx) {
+        gp[0] += grxc * iz;
+        gp[2] -= grxc * p[0] * iz2;
+    }
+    if (ry >= -cam.limy && ry <= cam.limy) {
+        gp[1] += gryc * iz;
+        gp[2] -= gryc * p[1] * iz2;
+    }
+    // centre (u, v)
+    gp[0] += gu * cam.fx * iz;
+    gp[1] += gv * cam.fy * iz;
+    gp[2] -= (gu * cam.fx * p[0] + gv * cam.fy * p[1]) * iz2;
+    // p = W mu + t
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        gmu[a] += W[a] * gp[0] + W[3 + a] * gp[1] + W[6 + a] * gp[2];
+        gt[a] += gp[a];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) gW[3 * a + b] += gp[a] * mu[b];
+    }
+    // Sigma = M M^T, M = R diag(s): gM = 2 gSigma M
+    float gR[9];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        float gsb = 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float gM = 2.f * (gS[3 * a] * M[b] + gS[3 * a + 1] * M[3 + b] + gS[3 * a + 2] * M[6 + b]);
+            gR[3 * a + b] = gM * sc[b];
+            gsb += gM * R[3 * a + b];
+        }
+        gls[b] += gsb * sc[b];
+    }
+    // R(q_hat) -> q_hat
+    const float w = q[0], x = q[1], y = q[2], z = q[3];
+    float gqh[4];
+    gqh[0] = 2.f * (-z * gR[1] + y * gR[2] + z * gR[3] - x * gR[5] - y * gR[6] + x * gR[7]);
+    gqh[1] = 2.f * (y * gR[1] + z * gR[2] + y * gR[3] - w * gR[5] + z * gR[6] + w * gR[7]) -
+             4.f * x * (gR[4] + gR[8]);
+    gqh[2] = 2.f * (x * gR[1] + w * gR[2] + x * gR[3] + z * gR[5] - w * gR[6] + z * gR[7]) -
+             4.f * y * (gR[0] + gR[8]);
+    gqh[3] = 2.f * (-w * gR[1] + x * gR[2] + w * gR[3] + y * gR[5] + x * gR[6] + y * gR[7]) -
+             4.f * z * (gR[0] + gR[4]);
+    const float qd = gqh[0] * q[0] + gqh[1] * q[1] + gqh[2] * q[2] + gqh[3] * q[3];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) gq[k] += (gqh[k] - q[k] * qd) / qn;
+}
+
+// Per-block partial of one view's pose gradient (every thread of the block
+// takes part): wave sums, then the four waves in a fixed order; layout
+// [view][entry of the 3x4 block][workgroup].
+__device__ __forceinline__ void pose_block_partial(const float (&gW)[9], const float (&gt)[3], float *red,
+                                                   float *__restrict__ pose_part, int v, uint32_t pose_blocks) {
+    float pv[12];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        pv[4 * r] = gW[3 * r];
+        pv[4 * r + 1] = gW[3 * r + 1];
+        pv[4 * r + 2] = gW[3 * r + 2];
+        pv[4 * r + 3] = gt[r];
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) pv[k] = wave_sum(pv[k]);
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) red[wv * 12 + k] = pv[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < 12) {
+        const int k = threadIdx.x;
+        pose_part[((size_t)v * 12 + k) * pose_blocks + blockIdx.x] = (red[k] + red[12 + k]) + (red[24 + k] + red[36 + k]);
+    }
+    __syncthreads();
+}
+
 template <int DEG>
 __global__ __launch_bounds__(kProjThreads) void k_project_bwd(
     gsr_gaussians g, ViewTable vt, const float *__restrict__ w2c, uint64_t n, const Rec *__restrict__ rec,
@@ -577,238 +822,10 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(
         float gW[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gt[3] = {0, 0, 0};
         const uint64_t item = (uint64_t)v * n + i;
         const uint32_t cnt = live ? count[item] : 0u;
-        if (cnt > 0) {
-            const ViewInfo cam = vt.v[v];
-            const float4 r0 = rec[item].r0, r1 = rec[item].r1;
-            float S[kPartialStride];
-            item_moments(screen, carry, item, __float_as_uint(rec[item].r2.w), cnt, S);
-            const float gu = fmaf(r0.z, S[0], r0.w * S[1]), gv = fmaf(r0.w, S[0], r1.x * S[1]);
-            const float gA = 0.5f * S[2], gB = S[3], gC = 0.5f * S[4], go = S[5] / r1.y;
-            const float grgb[3] = {S[6], S[7], S[8]};
-
-            float W[9], t[3];
-            load_pose(w2c, v, W, t);
-            const float mu[3] = {g.means[3 * i], g.means[3 * i + 1], g.means[3 * i + 2]};
-            const double pxd = (double)W[0] * mu[0] + (double)W[1] * mu[1] + (double)W[2] * mu[2] + (double)t[0];
-            const double pyd = (double)W[3] * mu[0] + (double)W[4] * mu[1] + (double)W[5] * mu[2] + (double)t[1];
-            const double pzd = (double)W[6] * mu[0] + (double)W[7] * mu[1] + (double)W[8] * mu[2] + (double)t[2];
-            const float p[3] = {(float)pxd, (float)pyd, (float)pzd};
-
-            gop += go;
-
-            // ---- colour -> SH coefficients and direction
-            const float cxw = -(W[0] * t[0] + W[3] * t[1] + W[6] * t[2]);
-            const float cyw = -(W[1] * t[0] + W[4] * t[1] + W[7] * t[2]);
-            const float czw = -(W[2] * t[0] + W[5] * t[1] + W[8] * t[2]);
-            float dvec[3] = {mu[0] - cxw, mu[1] - cyw, mu[2] - czw};
-            const float dn = sqrtf(dvec[0] * dvec[0] + dvec[1] * dvec[1] + dvec[2] * dvec[2]);
-            const float dir[3] = {dvec[0] / dn, dvec[1] / dn, dvec[2] / dn};
-            float Y[K];
-            sh_eval<DEG, float>(dir[0], dir[1], dir[2], Y);
-            float shv[3 * K];
-            if constexpr (kVecSH) {
-                const float4 *src = reinterpret_cast<const float4 *>(g.sh) + (size_t)i * (3 * K / 4);
-#pragma unroll
-                for (int k = 0; k < 3 * K / 4; ++k) {
-                    const float4 f = src[k];
-                    shv[4 * k] = f.x, shv[4 * k + 1] = f.y, shv[4 * k + 2] = f.z, shv[4 * k + 3] = f.w;
-                }
-            } else {
-#pragma unroll
-                for (int k = 0; k < 3 * K; ++k) shv[k] = g.sh[(size_t)i * K * 3 + k];
-            }
-            // colour, to know which channels the forward clamped at 0
-            float col[3] = {0.5f, 0.5f, 0.5f};
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                col[0] = fmaf(shv[3 * k], Y[k], col[0]);
-                col[1] = fmaf(shv[3 * k + 1], Y[k], col[1]);
-                col[2] = fmaf(shv[3 * k + 2], Y[k], col[2]);
-            }
-            float gc[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) gc[c] = col[c] < 0.f ? 0.f : grgb[c];
-            // coefficient gradients (added to an earlier view's) and the weights of dRGB/ddir
-            float wdir[K], o[3 * K];
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                o[3 * k] = gc[0] * Y[k];
-                o[3 * k + 1] = gc[1] * Y[k];
-                o[3 * k + 2] = gc[2] * Y[k];
-                wdir[k] = fmaf(gc[0], shv[3 * k], fmaf(gc[1], shv[3 * k + 1], gc[2] * shv[3 * k + 2]));
-            }
-            if (sh_written) {
-#pragma unroll
-                for (int k = 0; k < 3 * K; ++k) o[k] += gsh[k];
-            }
-            store_sh_row<K, kVecSH>(gsh, o);
-            sh_written = true;
-            float gdx, gdy, gdz;
-            sh_grad_dir<DEG>(dir[0], dir[1], dir[2], wdir, gdx, gdy, gdz);
-            const float dd = gdx * dir[0] + gdy * dir[1] + gdz * dir[2];
-            const float gd[3] = {(gdx - dir[0] * dd) / dn, (gdy - dir[1] * dd) / dn, (gdz - dir[2] * dd) / dn};
-            // mean gets +gd, camera centre gets -gd; c_a = -sum_b W[b][a] t_b
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                gmu[a] += gd[a];
-#pragma unroll
-                for (int b = 0; b < 3; ++b) {
-                    gW[3 * b + a] += t[b] * gd[a];
-                    gt[b] += W[3 * b + a] * gd[a];
-                }
-            }
-
-            // ---- recompute the covariance chain
-            const float4 qf = reinterpret_cast<const float4 *>(g.quats)[i];
-            const float qn = sqrtf(qf.x * qf.x + qf.y * qf.y + qf.z * qf.z + qf.w * qf.w);
-            const float q[4] = {qf.x / qn, qf.y / qn, qf.z / qn, qf.w / qn};
-            float R[9];
-            quat_rot<float>(q[0], q[1], q[2], q[3], R);
-            const float sc[3] = {expf(g.log_scales[3 * i]), expf(g.log_scales[3 * i + 1]),
-                                 expf(g.log_scales[3 * i + 2])};
-            float M[9];
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) M[3 * a + b] = R[3 * a + b] * sc[b];
-            float Sg[9];
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b)
-                    Sg[3 * a + b] = M[3 * a] * M[3 * b] + M[3 * a + 1] * M[3 * b + 1] + M[3 * a + 2] * M[3 * b + 2];
-            const float rx = (float)(pxd / pzd), ry = (float)(pyd / pzd);
-            const float rxc = fminf(fmaxf(rx, -cam.limx), cam.limx);
-            const float ryc = fminf(fmaxf(ry, -cam.limy), cam.limy);
-            const float iz = 1.f / p[2];
-            float J[6] = {cam.fx * iz, 0.f, -cam.fx * rxc * iz, 0.f, cam.fy * iz, -cam.fy * ryc * iz};
-            float T[6];
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b)
-                    T[3 * a + b] = J[3 * a] * W[b] + J[3 * a + 1] * W[3 + b] + J[3 * a + 2] * W[6 + b];
-            float TS[6];
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b)
-                    TS[3 * a + b] = T[3 * a] * Sg[b] + T[3 * a + 1] * Sg[3 + b] + T[3 * a + 2] * Sg[6 + b];
-            const double ca = (double)(TS[0] * T[0] + TS[1] * T[1] + TS[2] * T[2]) + (double)kLowPass;
-            const double cb = (double)(TS[0] * T[3] + TS[1] * T[4] + TS[2] * T[5]);
-            const double cc = (double)(TS[3] * T[3] + TS[4] * T[4] + TS[5] * T[5]) + (double)kLowPass;
-            // ---- conic (A, B, C) -> covariance (a, b, c)
-            const double D = ca * cc - cb * cb;
-            const double iD2 = 1.0 / (D * D);
-            const float ga = (float)((-cc * cc * gA + cb * cc * gB - cb * cb * gC) * iD2);
-            const float gb = (float)((2.0 * cb * cc * gA - (ca * cc + cb * cb) * gB + 2.0 * ca * cb * gC) * iD2);
-            const float gcv = (float)((-cb * cb * gA + ca * cb * gB - ca * ca * gC) * iD2);
-            const float G2[4] = {ga, 0.5f * gb, 0.5f * gb, gcv};
-            // gSigma = T^T G2 T (3x3), gT = 2 G2 T Sigma (2x3)
-            float gS[9];
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b)
-                    gS[3 * a + b] = T[a] * (G2[0] * T[b] + G2[1] * T[3 + b]) + T[3 + a] * (G2[2] * T[b] + G2[3] * T[3 + b]);
-            float gT[6];
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b)
-                    gT[3 * a + b] = 2.f * (G2[2 * a] * TS[b] + G2[2 * a + 1] * TS[3 + b]);
-            // T = J W: gJ = gT W^T, gW += J^T gT
-            float gJ[6];
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b)
-                    gJ[3 * a + b] = gT[3 * a] * W[3 * b] + gT[3 * a + 1] * W[3 * b + 1] + gT[3 * a + 2] * W[3 * b + 2];
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) gW[3 * a + b] += J[a] * gT[b] + J[3 + a] * gT[3 + b];
-            // J entries -> camera-space mean
-            float gp[3] = {0.f, 0.f, 0.f};
-            const float iz2 = iz * iz;
-            gp[2] += -cam.fx * iz2 * gJ[0] - cam.fy * iz2 * gJ[4];
-            const float grxc = -cam.fx * iz * gJ[2];
-            const float gryc = -cam.fy * iz * gJ[5];
-            gp[2] += cam.fx * rxc * iz2 * gJ[2] + cam.fy * ryc * iz2 * gJ[5];
-            if (rx >= -cam.limx && rx <= cam.limx) {
-                gp[0] += grxc * iz;
-                gp[2] -= grxc * p[0] * iz2;
-            }
-            if (ry >= -cam.limy && ry <= cam.limy) {
-                gp[1] += gryc * iz;
-                gp[2] -= gryc * p[1] * iz2;
-            }
-            // centre (u, v)
-            gp[0] += gu * cam.fx * iz;
-            gp[1] += gv * cam.fy * iz;
-            gp[2] -= (gu * cam.fx * p[0] + gv * cam.fy * p[1]) * iz2;
-            // p = W mu + t
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                gmu[a] += W[a] * gp[0] + W[3 + a] * gp[1] + W[6 + a] * gp[2];
-                gt[a] += gp[a];
-#pragma unroll
-                for (int b = 0; b < 3; ++b) gW[3 * a + b] += gp[a] * mu[b];
-            }
-            // Sigma = M M^T, M = R diag(s): gM = 2 gSigma M
-            float gR[9];
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                float gsb = 0.f;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const float gM = 2.f * (gS[3 * a] * M[b] + gS[3 * a + 1] * M[3 + b] + gS[3 * a + 2] * M[6 + b]);
-                    gR[3 * a + b] = gM * sc[b];
-                    gsb += gM * R[3 * a + b];
-                }
-                gls[b] += gsb * sc[b];
-            }
-            // R(q_hat) -> q_hat
-            const float w = q[0], x = q[1], y = q[2], z = q[3];
-            float gqh[4];
-            gqh[0] = 2.f * (-z * gR[1] + y * gR[2] + z * gR[3] - x * gR[5] - y * gR[6] + x * gR[7]);
-            gqh[1] = 2.f * (y * gR[1] + z * gR[2] + y * gR[3] - w * gR[5] + z * gR[6] + w * gR[7]) -
-                     4.f * x * (gR[4] + gR[8]);
-            gqh[2] = 2.f * (x * gR[1] + w * gR[2] + x * gR[3] + z * gR[5] - w * gR[6] + z * gR[7]) -
-                     4.f * y * (gR[0] + gR[8]);
-            gqh[3] = 2.f * (-w * gR[1] + x * gR[2] + w * gR[3] + y * gR[5] + x * gR[6] + y * gR[7]) -
-                     4.f * z * (gR[0] + gR[4]);
-            const float qd = gqh[0] * q[0] + gqh[1] * q[1] + gqh[2] * q[2] + gqh[3] * q[3];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) gq[k] += (gqh[k] - q[k] * qd) / qn;
-        }
-        // per-block partial of this view's pose gradient (all threads take part):
-        // wave sums, then the four waves in a fixed order;
-        // layout [view][entry of the 3x4 block][workgroup]
-        {
-            float pv[12];
-#pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                pv[4 * r] = gW[3 * r];
-                pv[4 * r + 1] = gW[3 * r + 1];
-                pv[4 * r + 2] = gW[3 * r + 2];
-                pv[4 * r + 3] = gt[r];
-            }
-#pragma unroll
-            for (int k = 0; k < 12; ++k) pv[k] = wave_sum(pv[k]);
-            const int wv = threadIdx.x >> 6;
-            if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-                for (int k = 0; k < 12; ++k) red[wv * 12 + k] = pv[k];
-            }
-            __syncthreads();
-            if (threadIdx.x < 12) {
-                const int k = threadIdx.x;
-                pose_part[((size_t)v * 12 + k) * pose_blocks + blockIdx.x] =
-                    (red[k] + red[12 + k]) + (red[24 + k] + red[36 + k]);
-            }
-            __syncthreads();
-        }
+        if (cnt > 0)
+            item_backward<DEG>(g, vt.v[v], w2c, v, i, item, cnt, rec, screen, carry, gsh, sh_written, gmu, gls, gq,
+                               gop, gW, gt);
+        pose_block_partial(gW, gt, red, pose_part, v, pose_blocks);
     }
     if (!live) return;  // its rows were zeroed above (or it is one of the zeroed ones)
     gr.means[3 * i] = gmu[0];
@@ -821,17 +838,65 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(
     gr.opacities[i] = gop;
 }
 
+// The same for a single view, over the visible-item list instead of over all
+// Gaussians: every thread of a block has a seen Gaussian (the list is dense),
+// where the per-block compaction above leaves two of every three threads idle
+// when a third of the Gaussians is seen.  Unseen rows were zeroed by the
+// backward compositing.
+template <int DEG>
+__global__ __launch_bounds__(kProjThreads) void k_project_bwd_vis(
+    gsr_gaussians g, ViewTable vt, const float *__restrict__ w2c, const uint32_t *__restrict__ vis,
+    const Rec *__restrict__ rec, const uint32_t *__restrict__ count, const WsHeader *__restrict__ hdr,
+    const float4 *__restrict__ screen, const float *__restrict__ carry, gsr_gaussian_grads gr,
+    float *__restrict__ pose_part, uint32_t pose_blocks) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    __shared__ float red[4 * 12];
+    const uint32_t nvis = hdr->overflow ? 0u : hdr->n_visible;
+    if (blockIdx.x * kProjThreads >= nvis) {  // uniform: no item, a zero partial
+        if (threadIdx.x < 12) pose_part[(size_t)threadIdx.x * pose_blocks + blockIdx.x] = 0.f;
+        return;
+    }
+    const uint32_t k = blockIdx.x * kProjThreads + threadIdx.x;
+    float gW[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gt[3] = {0, 0, 0};
+    if (k < nvis) {
+        const uint64_t i = vis[k];  // one view: the item is the Gaussian
+        float gmu[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gop = 0.f;
+        bool sh_written = false;
+        item_backward<DEG>(g, vt.v[0], w2c, 0, i, i, count[i], rec, screen, carry, gr.sh + (size_t)i * K * 3,
+                           sh_written, gmu, gls, gq, gop, gW, gt);
+        gr.means[3 * i] = gmu[0];
+        gr.means[3 * i + 1] = gmu[1];
+        gr.means[3 * i + 2] = gmu[2];
+        gr.log_scales[3 * i] = gls[0];
+        gr.log_scales[3 * i + 1] = gls[1];
+        gr.log_scales[3 * i + 2] = gls[2];
+        reinterpret_cast<float4 *>(gr.quats)[i] = make_float4(gq[0], gq[1], gq[2], gq[3]);
+        gr.opacities[i] = gop;
+    }
+    pose_block_partial(gW, gt, red, pose_part, 0, pose_blocks);
+}
+
 void launch_project_bwd(const gsr_gaussians &g, const ViewTable &vt, const float *w2c, uint64_t n, const Rec *rec,
-                        const uint32_t *count, const WsHeader *hdr, const float4 *screen, const float *carry,
-                        const gsr_gaussian_grads &gr, float *pose_part, uint32_t pose_blocks, bool zero_unseen,
-                        hipStream_t st) {
+                        const uint32_t *count, const uint32_t *vis, const WsHeader *hdr, const float4 *screen,
+                        const float *carry, const gsr_gaussian_grads &gr, float *pose_part, uint32_t pose_blocks,
+                        bool zero_unseen, hipStream_t st) {
     if (n == 0) return;
     const dim3 grid(pose_blocks);
+    const int z = zero_unseen ? 1 : 0;
+    if (vt.n_views == 1 && !zero_unseen) {
+        switch (g.sh_degree) {
+            case 0: hipLaunchKernelGGL(k_project_bwd_vis<0>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, vis, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks); break;
+            case 1: hipLaunchKernelGGL(k_project_bwd_vis<1>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, vis, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks); break;
+            case 2: hipLaunchKernelGGL(k_project_bwd_vis<2>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, vis, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks); break;
+            default: hipLaunchKernelGGL(k_project_bwd_vis<3>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, vis, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks); break;
+        }
+        return;
+    }
     switch (g.sh_degree) {
-        case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks, zero_unseen ? 1 : 0); break;
-        case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks, zero_unseen ? 1 : 0); break;
-        case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks, zero_unseen ? 1 : 0); break;
-        default: hipLaunchKernelGGL(k_project_bwd<3>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks, zero_unseen ? 1 : 0); break;
+        case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks, z); break;
+        case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks, z); break;
+        case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks, z); break;
+        default: hipLaunchKernelGGL(k_project_bwd<3>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks, z); break;
     }
 }
 
