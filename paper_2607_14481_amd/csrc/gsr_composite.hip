@@ -63,13 +63,50 @@ __device__ __forceinline__ TileCtx tile_ctx(const ViewTable &vt, uint32_t t) {
     return c;
 }
 
+// Rows [y0, y1] of the tile (tile-relative pixel rows) narrowed to those that
+// the Gaussian's alpha >= 1/255 ellipse reaches within the tile's columns.
+// With (dx, dy) = pixel - centre and sigma = A dx^2 / 2 + B dx dy + C dy^2 / 2,
+// the ellipse sigma <= s over the column band dx in [lo, hi] spans
+// dy in [min h, max g] with g, h = (-B dx +- sqrt(2 C s - det dx^2)) / C,
+// det = A C - B^2: g is concave with its peak at dx = -B sqrt(2 s / (A det)),
+// h convex with its trough at the opposite dx, so each extreme is at that
+// point clamped to the band.  FP32 with slack: s = 1.001 (ln(255 o) + 0.01)
+// + 0.01 (the 1.001 grows the extents by far more than the evaluation's
+// rounding, about 1e-6 relative, at any scale) and 0.01 px more on each
+// side; a row left out then has alpha below 0.99 / 255 at every pixel, which
+// the compositing's own FP32 evaluation cannot round up to 1/255, so leaving
+// it out changes nothing but the work.  Degenerate conics keep the box's rows.
+__device__ __forceinline__ void ellipse_rows_in_band(float A, float B, float C, float opacity, float ut, float vt,
+                                                     int &y0, int &y1) {
+    if (y0 > y1) return;
+    const float det = A * C - B * B;
+    const float s = 1.001f * (__logf(255.f * opacity) + 0.01f) + 0.01f;
+    if (!(det > 0.f) || !(A > 0.f) || !(C > 0.f) || !(s > 0.f)) return;
+    const float idet = __builtin_amdgcn_rcpf(det), iC = __builtin_amdgcn_rcpf(C);
+    const float X = __builtin_sqrtf(2.f * C * s * idet);  // half-width of the ellipse
+    const float lo = fmaxf(0.5f - ut - 0.01f, -X), hi = fminf((float)kTileW - 0.5f - ut + 0.01f, X);
+    if (lo > hi) {  // the ellipse misses the tile's columns
+        y1 = y0 - 1;
+        return;
+    }
+    const float xs = -B * __builtin_sqrtf(2.f * s * idet * __builtin_amdgcn_rcpf(A));
+    const float xt = fminf(fmaxf(xs, lo), hi), xb = fminf(fmaxf(-xs, lo), hi);
+    const float top = (-B * xt + __builtin_sqrtf(fmaxf(0.f, 2.f * C * s - det * xt * xt))) * iC;
+    const float bot = (-B * xb - __builtin_sqrtf(fmaxf(0.f, 2.f * C * s - det * xb * xb))) * iC;
+    // pixel row r (centre r + 0.5) lies in [vt + bot, vt + top]
+    const float r0 = ceilf(vt + bot - 0.51f), r1 = floorf(vt + top - 0.49f);
+    y0 = max(y0, (int)fmaxf(r0, -1.f));
+    y1 = min(y1, (int)fminf(r1, 65536.f));
+}
+
 // Staged record (LDS): three float4 per Gaussian.
 //   a = (u - ox, v - oy, -A log2e / 2, -B log2e)
 //   b = (-C log2e / 2, log2(opacity), red, green)
 //   d = (blue, bits(slab mask), bits(pair index), opacity)
 // so that sigma * log2e = -(a.z dx^2 + a.w dx dy + b.x dy^2) and
 // alpha = min(0.99, exp2(-sigma log2e + b.y)).  Bit k of the slab mask is set
-// when the Gaussian's alpha >= 1/255 box reaches rows [4k, 4k + 3] of the tile.
+// when the Gaussian's alpha >= 1/255 ellipse (with slack) reaches rows
+// [4k, 4k + 3] of the tile within its columns.
 __device__ __forceinline__ void stage_record(const Rec &r, const float2 lo, const TileCtx &c, uint32_t tile_h,
                                              float4 &a, float4 &b, float4 &d) {
     const float ut = (r.r0.x - (float)c.ox) + lo.x;
@@ -77,7 +114,8 @@ __device__ __forceinline__ void stage_record(const Rec &r, const float2 lo, cons
     a = make_float4(ut, vt, -0.5f * kLog2e * r.r0.z, -kLog2e * r.r0.w);
     b = make_float4(-0.5f * kLog2e * r.r1.x, __log2f(r.r1.y), r.r1.z, r.r1.w);
     const uint32_t by = __float_as_uint(r.r2.z);
-    const int y0 = max((int)(by & 0xffffu) - (int)c.oy, 0), y1 = min((int)(by >> 16) - (int)c.oy, (int)tile_h - 1);
+    int y0 = max((int)(by & 0xffffu) - (int)c.oy, 0), y1 = min((int)(by >> 16) - (int)c.oy, (int)tile_h - 1);
+    ellipse_rows_in_band(r.r0.z, r.r0.w, r.r1.x, r.r1.y, ut, vt, y0, y1);
     const uint32_t smask = y0 <= y1 ? ((2u << (y1 >> 2)) - 1u) & ~((1u << (y0 >> 2)) - 1u) : 0u;
     // pair index in emission order: offset + row-major position in the tile box
     const uint32_t bx = __float_as_uint(r.r2.y);

@@ -59,6 +59,31 @@ def test_small_view_forward_backward_parity():
     assert rel_err(gpu["twist"][0], ref["twist"]) <= GRAD_TOL
 
 
+@pytest.mark.parametrize("stretch,opacity", [(2.5, None), (4.0, 0.02)])
+def test_elongated_gaussians_parity(stretch, opacity):
+    """Needle-like Gaussians at every orientation: their alpha >= 1/255 box
+    holds many tiles that the ellipse itself misses, the case where the
+    compositing narrows each staged Gaussian's rows to the ellipse's extent
+    within the tile's columns.  A faint variant puts the ellipse's edge near
+    the threshold everywhere."""
+    wl = S.small_view(seed=21, n=1200, width=176, height=144, log_scale_mean=-3.0)
+    sc = wl.scene
+    ls = sc.log_scales.copy()
+    ls[:, 0] += stretch
+    ls[:, 1] -= 0.5
+    op = sc.opacities.copy() if opacity is None else np.full_like(sc.opacities, opacity)
+    sc = S.Scene(sc.means, ls, sc.quats, op, sc.sh, sc.sh_degree)
+    cams = wl.cameras
+    up = _upstream(17, cams)
+    log(f"elongated x{np.exp(stretch):.0f}: GPU forward+backward")
+    gpu = gpu_render(sc, cams, upstream=up)
+    ref = O.render(sc, cams[0], dL_dimg=up[0])
+    _compare_view(gpu["imgs"][0], ref, "elongated")
+    assert gpu["stats"]["pairs"] == ref["M"]
+    _compare_grads(gpu, ref, "elongated")
+    assert rel_err(gpu["w2c"][0], ref["w2c"]) <= GRAD_TOL
+
+
 @pytest.mark.parametrize("case", ["small", "ring3"])
 def test_binning_bit_exact(case):
     if case == "small":
