@@ -54,8 +54,10 @@
  * capacity the kernels skip the binning, the image is background only, the
  * overflow is recorded in the workspace header, and gsr_query_pairs (after a
  * stream synchronisation) reports it with the M needed.  With GSR_FLAG_SYNC
- * the forward synchronises once, after counting pairs, and returns
- * GSR_ERR_CAPACITY (with nothing rendered) when M exceeds the capacity.
+ * the forward synchronises once, after grouping the pairs by tile, and
+ * returns GSR_ERR_CAPACITY (with nothing rendered) when M exceeds the
+ * capacity; it also reads the longest tile list there and sizes the
+ * multi-workgroup sort of lists longer than 4096 entries from it.
  * Without GSR_FLAG_SYNC both passes are free of host synchronisation and of
  * memset nodes, so they can be captured in a HIP graph.
  */
@@ -69,7 +71,7 @@
 extern "C" {
 #endif
 
-#define GSR_ABI_VERSION 1
+#define GSR_ABI_VERSION 2
 
 /* Status codes. */
 #define GSR_OK 0
@@ -83,7 +85,7 @@ extern "C" {
 #define GSR_MAX_VIEWS 32
 
 /* Flags. */
-#define GSR_FLAG_SYNC 1u        /* forward: synchronise once to check the pair capacity */
+#define GSR_FLAG_SYNC 1u        /* forward: synchronise once (pair capacity, long tile lists) */
 #define GSR_FLAG_PERSISTENT 2u  /* compositing as persistent work-queue launches */
 #define GSR_FLAG_STATS 4u       /* forward: also count the work (gsr_query_stats); slower */
 
@@ -136,7 +138,14 @@ typedef struct gsr_launch_config {
        caller: events[2 s] / events[2 s + 1] are recorded on the stream just
        before / after stage s of the pass being enqueued. */
     void *stage_events;
-    int32_t reserved[4];
+    /* Tile lists longer than 4096 entries: a forward with GSR_FLAG_SYNC sizes
+       their multi-workgroup sort itself (from the longest list it measured).
+       Without it, this many merge passes are enqueued (covering lists up to
+       4096 * 2^long_list_passes entries, e.g. from an earlier forward's
+       gsr_stats.longest_list); a list no pass covers is sorted by one
+       workgroup, which is exact but slow for very long lists. */
+    int32_t long_list_passes;
+    int32_t reserved[3];
 } gsr_launch_config;
 
 /* Work counters of the last forward (see gsr_query_stats). */
@@ -146,6 +155,8 @@ typedef struct gsr_stats {
     int64_t evaluations;  /* sum over pixels of list entries evaluated up to the stop */
     int64_t contributors; /* sum over pixels of Gaussians composited */
     int64_t replays;      /* sum over pixels of list positions the backward replays */
+    int64_t long_lists;   /* tiles whose list is longer than 4096 entries */
+    int64_t longest_list; /* length of the longest of those (0 if none) */
 } gsr_stats;
 
 /* Library version (GSR_ABI_VERSION) and status names. */

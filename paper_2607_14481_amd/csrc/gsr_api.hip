@@ -116,6 +116,7 @@ gsr::WsLayout make_layout(uint64_t n, const gsr::ViewTable &vt, uint64_t cap) {
     L.digit_total = take(4 * 256);
     L.ranges = take(8ull * vt.total_tiles);
     L.tile_cut = take(16ull * vt.total_tiles);
+    L.long_tiles = take(4ull * kMaxLongTiles);
     L.pix_T = take(4ull * vt.total_pixels);
     L.pix_n = take(4ull * vt.total_pixels);
     L.partial = take(4ull * kPartialStride * cap);
@@ -150,6 +151,7 @@ struct Ptrs {
     uint4 *item_box;
     uint2 *ranges;
     uint4 *tile_cut;
+    uint32_t *long_tiles;
     float *pix_T;
     uint32_t *pix_n;
     float *partial, *pose_part;
@@ -175,6 +177,7 @@ Ptrs carve(void *ws, const gsr::WsLayout &L) {
     p.item_box = reinterpret_cast<uint4 *>(b + L.item_box);
     p.screen = reinterpret_cast<float4 *>(b + L.screen);
     p.tile_cut = reinterpret_cast<uint4 *>(b + L.tile_cut);
+    p.long_tiles = reinterpret_cast<uint32_t *>(b + L.long_tiles);
     p.hist = reinterpret_cast<uint32_t *>(b + L.hist);
     p.digit_total = reinterpret_cast<uint32_t *>(b + L.digit_total);
     p.ranges = reinterpret_cast<uint2 *>(b + L.ranges);
@@ -289,15 +292,7 @@ int gsr_rasterize_forward(void *ws, size_t ws_bytes, const gsr_gaussians *g, int
     mark.end(GSR_STAGE_COMPACT);
     mark.begin(GSR_STAGE_EMIT);
     launch_pair_offsets(p.vis, p.count, L.items, p.poff, p.chunk_item, L.chunks, p.scan_tmp, p.hdr, st);
-    uint64_t pair_grid = cap;
-    if (flags & GSR_FLAG_SYNC) {
-        WsHeader h;
-        if ((rc = check_hip(hipMemcpyAsync(&h, p.hdr, sizeof(h), hipMemcpyDeviceToHost, st), "header copy"))) return rc;
-        if ((rc = check_hip(hipStreamSynchronize(st), "stream sync"))) return rc;
-        if (h.overflow)
-            return fail(GSR_ERR_CAPACITY, "needs %u pairs, workspace holds %llu", h.n_pairs, (unsigned long long)cap);
-        pair_grid = h.n_pairs;
-    }
+    const uint64_t pair_grid = cap;  // every kernel reads the pair count from the header
     launch_emit_pairs(vt, p.vis, p.poff, p.chunk_item, n, pair_grid, p.rec, p.zkey, p.item_box, p.pkey[0], p.pval[0],
                       p.hdr, st);
     mark.end(GSR_STAGE_EMIT);
@@ -308,8 +303,35 @@ int gsr_rasterize_forward(void *ws, size_t ws_bytes, const gsr_gaussians *g, int
         radix_sort_u32(k2, v2, SortCount{nullptr, p.hdr}, pair_grid, 0, tile_bits(vt.total_tiles), p.hist,
                        L.hist_blocks, p.digit_total, pc, st);
     }
-    launch_tile_ranges(p.pkey[pc], pair_grid, p.ranges, vt.total_tiles, p.hdr, st);
-    launch_tile_depth_sort(p.ranges, vt.total_tiles, p.pval[pc], p.zkey, p.pkey[pc ^ 1], p.pval[pc ^ 1], p.hdr, st);
+    launch_tile_ranges(p.pkey[pc], pair_grid, p.ranges, vt.total_tiles, p.long_tiles, p.hdr, st);
+    // lists longer than one workgroup sorts: runs of kLongWindow, then merge passes
+    int passes = cfg ? std::max(0, std::min(cfg->long_list_passes, kMaxLongPasses)) : 0;
+    uint64_t long_pairs = cap, n_long = kMaxLongTiles;
+    if (flags & GSR_FLAG_SYNC) {
+        WsHeader h;
+        if ((rc = check_hip(hipMemcpyAsync(&h, p.hdr, sizeof(h), hipMemcpyDeviceToHost, st), "header copy"))) return rc;
+        if ((rc = check_hip(hipStreamSynchronize(st), "stream sync"))) return rc;
+        if (h.overflow)
+            return fail(GSR_ERR_CAPACITY, "needs %u pairs, workspace holds %llu", h.n_pairs, (unsigned long long)cap);
+        passes = 0;
+        if (h.n_long > 0 && h.n_long <= kMaxLongTiles) {
+            const uint32_t runs = (h.max_long + kLongWindow - 1) / kLongWindow;
+            while ((1u << passes) < runs && passes < kMaxLongPasses) ++passes;
+        }
+        long_pairs = h.long_pairs;
+        n_long = h.n_long;
+    }
+    const uint32_t chunk_wgs = passes > 0 ? (uint32_t)((long_pairs + kLongWindow - 1) / kLongWindow + n_long) : 0u;
+    const uint32_t merge_wgs = passes > 0 ? (uint32_t)((long_pairs + kMergeWindow - 1) / kMergeWindow + n_long) : 0u;
+    uint32_t *xh = p.pkey[pc ^ 1], *xl = p.pval[pc ^ 1], *yh = p.pkey[pc], *yl = p.pval[pc];
+    launch_tile_depth_sort(p.ranges, vt.total_tiles, p.pval[pc], p.zkey, xh, xl, yh, yl, p.long_tiles, passes,
+                           chunk_wgs, p.hdr, st);
+    for (int q = 0; q < passes; ++q) {
+        // the runs start in x when the pass count is odd, so that the last pass reads x
+        const bool from_x = ((passes - q) & 1) != 0;
+        launch_long_merge(p.ranges, p.long_tiles, p.hdr, q, passes, from_x ? xh : yh, from_x ? xl : yl,
+                          from_x ? yh : xh, from_x ? yl : xl, p.pval[pc], merge_wgs, st);
+    }
     mark.end(GSR_STAGE_TILE_SORT);
     const bool pers = (flags & GSR_FLAG_PERSISTENT) != 0;
     mark.begin(GSR_STAGE_COMPOSITE_FWD);
@@ -394,6 +416,8 @@ int gsr_query_stats(const void *ws, size_t ws_bytes, gsr_stats *out, void *strea
     out->evaluations = (int64_t)h.evaluations;
     out->contributors = (int64_t)h.contributors;
     out->replays = (int64_t)h.replays;
+    out->long_lists = h.n_long;
+    out->longest_list = h.max_long;
     return GSR_OK;
 }
 
@@ -421,7 +445,6 @@ int gsr_export_state(const void *ws, size_t ws_bytes, const gsr_gaussians *g, in
         const void *src;
         size_t bytes;
     } copies[] = {
-        {pair_tiles, p.pkey[pc], 4 * m},
         {pair_items, p.pval[pc], 4 * m},
         {ranges, p.ranges, 8ull * vt.total_tiles},
         {records, p.rec, sizeof(Rec) * L.items},
@@ -429,6 +452,7 @@ int gsr_export_state(const void *ws, size_t ws_bytes, const gsr_gaussians *g, in
         {depth_keys, p.zkey, 4 * L.items},
         {tile_counts, p.count, 4 * L.items},
     };
+    if (pair_tiles && m > 0) launch_expand_ranges(p.ranges, vt.total_tiles, pair_tiles, p.hdr, st);
     for (const Copy &c : copies) {
         if (!c.dst || c.bytes == 0) continue;
         if ((rc = check_hip(hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyDeviceToDevice, st), "export copy"))) return rc;

@@ -44,7 +44,10 @@ struct WsHeader {
     unsigned long long replays;       // sum over pixels of n_contrib
     unsigned long long contributors;  // sum over pixels of Gaussians composited
     uint32_t queue[4];       // persistent-launch work counters
-    uint32_t pad[50];
+    uint32_t n_long;         // tiles whose list is longer than kGroupSortMax
+    uint32_t long_pairs;     // entries in those lists
+    uint32_t max_long;       // the longest of them
+    uint32_t pad[47];
 };
 static_assert(sizeof(WsHeader) == 256, "header is 256 bytes");
 
@@ -79,6 +82,7 @@ struct WsLayout {
     size_t digit_total; // u32[256] radix digit totals
     size_t ranges;      // uint2[total_tiles]
     size_t tile_cut;    // uint4[total_tiles] (positions replayed, depth key and item of the first one not replayed)
+    size_t long_tiles;  // u32[kMaxLongTiles] tiles whose list is longer than kGroupSortMax (any order)
     size_t pix_T;       // float[total_pixels] final transmittance
     size_t pix_n;       // u32[total_pixels] last contributor + 1
     size_t partial;     // float[cap * 9] per-pair moments of the pixel gradients
@@ -93,7 +97,11 @@ constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;     // 2048
 constexpr int kSortThreads = 256;
 constexpr int kSortTile = 4096;                           // elements per sort block
-constexpr int kTileSortCap = 4096;                        // per-tile depth sort in LDS up to this length
+constexpr int kGroupSortMax = 4096;                       // longest list one workgroup sorts in registers
+constexpr uint32_t kMaxLongTiles = 1024;                  // longer lists the multi-workgroup path takes
+constexpr uint32_t kLongWindow = 4096;                    // entries per sorted run of a long list
+constexpr uint32_t kMergeWindow = 2048;                   // outputs per workgroup of a merge pass
+constexpr int kMaxLongPasses = 16;                        // merge passes at most (lists up to 2^28 entries)
 constexpr int kProjThreads = 256;
 constexpr int kPartialStride = 9;                         // floats per pair gradient
 // Pairs are also processed in fixed chunks of consecutive emission-order
@@ -130,10 +138,25 @@ struct SortCount {
 void radix_sort_u32(uint32_t *keys[2], uint32_t *vals[2], SortCount sc, uint64_t n_cap, int begin_bit, int end_bit,
                     uint32_t *hist, uint32_t hist_blocks, uint32_t *digit_total, int &cur, hipStream_t st);
 // Each tile's list (items in ascending id order after the stable tile sort)
-// sorted by (depth key, item); alt_hi/alt_lo: the free ping-pong buffers, used
-// for lists longer than kTileSortCap.
+// sorted by (depth key, item).  Lists longer than kGroupSortMax: with
+// long_passes > 0 (and at most kMaxLongTiles of them), `chunk_wgs` extra
+// workgroups sort them in runs of kLongWindow into the key buffer the first
+// merge pass reads (x when long_passes is odd, else y; hi = depth key,
+// lo = item); lists longer than kLongWindow << long_passes, or all long lists
+// when long_passes == 0, are sorted by one workgroup in global memory
+// (x_hi/x_lo as scratch).
 void launch_tile_depth_sort(const uint2 *ranges, uint32_t total_tiles, uint32_t *pval, const uint32_t *zkey,
-                            uint32_t *alt_hi, uint32_t *alt_lo, const WsHeader *hdr, hipStream_t st);
+                            uint32_t *x_hi, uint32_t *x_lo, uint32_t *y_hi, uint32_t *y_lo,
+                            const uint32_t *long_tiles, int long_passes, uint32_t chunk_wgs, const WsHeader *hdr,
+                            hipStream_t st);
+// Merge pass p of long_passes over the long lists' runs (run length
+// kLongWindow << p); the last pass writes the item ids into pval.
+void launch_long_merge(const uint2 *ranges, const uint32_t *long_tiles, const WsHeader *hdr, int p, int long_passes,
+                       const uint32_t *src_hi, const uint32_t *src_lo, uint32_t *dst_hi, uint32_t *dst_lo,
+                       uint32_t *pval, uint32_t merge_wgs, hipStream_t st);
+// Tile id of every position of the sorted pairs, from the ranges.
+void launch_expand_ranges(const uint2 *ranges, uint32_t total_tiles, uint32_t *pair_tiles, const WsHeader *hdr,
+                          hipStream_t st);
 void launch_reset_queue(WsHeader *h, int which, hipStream_t st);
 void launch_pair_offsets(const uint32_t *vis, const uint32_t *count, uint64_t items_cap,
                          uint32_t *poff, uint32_t *chunk_item, uint64_t chunks_cap, uint32_t *block_tmp,
@@ -142,7 +165,7 @@ void launch_emit_pairs(const ViewTable &vt, const uint32_t *vis, const uint32_t 
                        uint64_t n, uint64_t pair_grid, Rec *rec, const uint32_t *zkey, uint4 *item_box,
                        uint32_t *pkey, uint32_t *pval, const WsHeader *hdr, hipStream_t st);
 void launch_tile_ranges(const uint32_t *pkey, uint64_t cap, uint2 *ranges, uint32_t total_tiles,
-                        const WsHeader *hdr, hipStream_t st);
+                        uint32_t *long_tiles, WsHeader *hdr, hipStream_t st);
 
 void launch_composite_fwd(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
                           const float2 *ulo, const uint32_t *zkey, float3 bg, float *out_rgb, float *out_T,

@@ -523,7 +523,6 @@ void launch_emit_pairs(const ViewTable &vt, const uint32_t *vis, const uint32_t 
 typedef unsigned long long u64;
 constexpr u64 kPadKey = ~0ull;
 constexpr int kBlockBucketMax = 1024;  // bucket path: four waves, up to 4 entries per lane
-constexpr int kGroupSortMax = 4096;    // network in registers: four waves, 16 entries per lane
 
 // v from lane (lane ^ M)
 template <int M>
@@ -615,10 +614,13 @@ __device__ __forceinline__ void register_bitonic(u64 (&key)[E], int lane, int wa
 }
 
 // Sort list[0, len) of item ids by (zkey[item], item); the caller's threads
-// are `W` whole waves and 64 * E * W >= len.
+// are `W` whole waves and 64 * E * W >= len.  The result goes back to list,
+// or, with out_hi non-null, as keys to out_hi (depth key) / out_lo (item).
 template <int E, int W>
 __device__ __forceinline__ void sort_list_regs(uint32_t *__restrict__ list, uint32_t len,
-                                               const uint32_t *__restrict__ zkey, int lane, int wave, uint32_t *xs) {
+                                               const uint32_t *__restrict__ zkey, int lane, int wave, uint32_t *xs,
+                                               uint32_t *__restrict__ out_hi = nullptr,
+                                               uint32_t *__restrict__ out_lo = nullptr) {
     u64 key[E];
     const uint32_t base = (uint32_t)(wave * 64 + lane) * E;
 #pragma unroll
@@ -629,8 +631,16 @@ __device__ __forceinline__ void sort_list_regs(uint32_t *__restrict__ list, uint
     }
     register_bitonic<E, W>(key, lane, wave, xs);
 #pragma unroll
-    for (int r = 0; r < E; ++r)
-        if (base + r < len) list[base + r] = (uint32_t)key[r];
+    for (int r = 0; r < E; ++r) {
+        if (base + r < len) {
+            if (out_hi) {
+                out_hi[base + r] = (uint32_t)(key[r] >> 32);
+                out_lo[base + r] = (uint32_t)key[r];
+            } else {
+                list[base + r] = (uint32_t)key[r];
+            }
+        }
+    }
 }
 
 // Fast path: a counting sort on a bucket index that is a monotone function of
@@ -772,20 +782,63 @@ __device__ void sort_list_global(uint32_t *__restrict__ list, uint32_t len, cons
     __syncthreads();
 }
 
+// Lists longer than kGroupSortMax, when the multi-workgroup path takes them:
+// every listed long tile of at most kLongWindow << passes entries (all of them
+// once they fit the list).  Window e of all their windows of `window` entries,
+// in list order, as (tile, window within it).
+__device__ __forceinline__ bool long_path_on(const WsHeader *hdr, int passes) {
+    return passes > 0 && passes <= kMaxLongPasses && hdr->n_long <= kMaxLongTiles;
+}
+__device__ __forceinline__ bool long_tile_window(const uint2 *__restrict__ ranges,
+                                                 const uint32_t *__restrict__ long_tiles, uint32_t n_long, int passes,
+                                                 uint32_t window, uint32_t e, uint32_t &tile, uint32_t &w) {
+    const uint64_t cover = (uint64_t)kLongWindow << passes;
+    for (uint32_t k = 0; k < n_long; ++k) {
+        const uint32_t t = long_tiles[k];
+        const uint2 rg = ranges[t];
+        const uint32_t len = rg.y - rg.x;
+        if (len > cover) continue;
+        const uint32_t nw = (len + window - 1) / window;
+        if (e < nw) {
+            tile = t;
+            w = e;
+            return true;
+        }
+        e -= nw;
+    }
+    return false;
+}
+
 __global__ __launch_bounds__(256) void k_tile_depth_sort(const uint2 *__restrict__ ranges, uint32_t total_tiles,
                                                          uint32_t *__restrict__ pval, const uint32_t *__restrict__ zkey,
-                                                         uint32_t *__restrict__ alt_hi, uint32_t *__restrict__ alt_lo,
+                                                         uint32_t *__restrict__ x_hi, uint32_t *__restrict__ x_lo,
+                                                         uint32_t *__restrict__ y_hi, uint32_t *__restrict__ y_lo,
+                                                         const uint32_t *__restrict__ long_tiles, int passes,
                                                          const WsHeader *__restrict__ hdr) {
     __shared__ u64 s_buf[kGroupSortMax / 2];  // bucket entries; the network's exchange area (16 KB)
     __shared__ uint32_t s_cnt[kBlockBucketMax];
     __shared__ uint32_t s_red[8];
     if (hdr->overflow) return;  // uniform
+    uint32_t *xs = reinterpret_cast<uint32_t *>(s_buf);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool multi = long_path_on(hdr, passes);
+    if (blockIdx.x >= total_tiles) {
+        // a window of a long list, sorted into a run of the first merge pass's input
+        if (!multi) return;
+        uint32_t t, w;
+        if (!long_tile_window(ranges, long_tiles, hdr->n_long, passes, kLongWindow, blockIdx.x - total_tiles, t, w))
+            return;
+        const uint2 rg = ranges[t];
+        const uint32_t off = rg.x + w * kLongWindow;
+        const uint32_t n = min(kLongWindow, rg.y - off);
+        uint32_t *oh = (passes & 1) ? x_hi : y_hi, *ol = (passes & 1) ? x_lo : y_lo;
+        sort_list_regs<16, 4>(pval + off, n, zkey, lane, wave, xs, oh + off, ol + off);
+        return;
+    }
     const uint32_t t = blockIdx.x;
-    if (t >= total_tiles) return;
     const uint2 rg = ranges[t];
     const uint32_t len = rg.y - rg.x;
     uint32_t *list = pval + rg.x;
-    uint32_t *xs = reinterpret_cast<uint32_t *>(s_buf);
     if (len <= 1) return;
     if (len <= 256)
         sort_list_block<1>(list, len, zkey, s_buf, s_cnt, s_red, xs);
@@ -794,16 +847,136 @@ __global__ __launch_bounds__(256) void k_tile_depth_sort(const uint2 *__restrict
     else if (len <= (uint32_t)kBlockBucketMax)
         sort_list_block<4>(list, len, zkey, s_buf, s_cnt, s_red, xs);
     else if (len <= (uint32_t)kGroupSortMax)
-        sort_list_regs<16, 4>(list, len, zkey, threadIdx.x & 63, threadIdx.x >> 6, xs);
-    else
-        sort_list_global(list, len, zkey, alt_hi + rg.x, alt_lo + rg.x);
+        sort_list_regs<16, 4>(list, len, zkey, lane, wave, xs);
+    else if (!multi || (uint64_t)len > ((uint64_t)kLongWindow << passes))
+        sort_list_global(list, len, zkey, x_hi + rg.x, x_lo + rg.x);
+    // else: the window workgroups and the merge passes sort it
 }
 
 void launch_tile_depth_sort(const uint2 *ranges, uint32_t total_tiles, uint32_t *pval, const uint32_t *zkey,
-                            uint32_t *alt_hi, uint32_t *alt_lo, const WsHeader *hdr, hipStream_t st) {
+                            uint32_t *x_hi, uint32_t *x_lo, uint32_t *y_hi, uint32_t *y_lo,
+                            const uint32_t *long_tiles, int long_passes, uint32_t chunk_wgs, const WsHeader *hdr,
+                            hipStream_t st) {
     if (total_tiles == 0) return;
-    hipLaunchKernelGGL(k_tile_depth_sort, dim3(total_tiles), dim3(256), 0, st, ranges, total_tiles, pval, zkey,
-                       alt_hi, alt_lo, hdr);
+    const uint32_t grid = total_tiles + (long_passes > 0 ? chunk_wgs : 0u);
+    hipLaunchKernelGGL(k_tile_depth_sort, dim3(grid), dim3(256), 0, st, ranges, total_tiles, pval, zkey, x_hi, x_lo,
+                       y_hi, y_lo, long_tiles, long_passes, hdr);
+}
+
+// ---------------------------------------------------------------------------
+// A4d: merge passes over the long lists' sorted runs.  Pass p merges runs of
+// kLongWindow << p pairwise; a workgroup makes kMergeWindow consecutive
+// outputs of one merge.  Its inputs start where the merge path crosses its
+// first and last output (found by one wave each, 64 probes per round), are
+// staged in LDS, and each thread merges 8 outputs from its own crossing.
+// Keys are unique, so every split is unambiguous.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ u64 load_key(const uint32_t *__restrict__ hi, const uint32_t *__restrict__ lo, uint32_t i) {
+    return ((u64)hi[i] << 32) | lo[i];
+}
+
+// Number of elements of A among the first d outputs of merge(A, B): the
+// smallest a in [max(0, d - nB), min(d, nA)] with not (A[a] < B[d - 1 - a]).
+// One whole wave calls it.
+__device__ uint32_t wave_merge_split(const uint32_t *a_hi, const uint32_t *a_lo, uint32_t nA, const uint32_t *b_hi,
+                                     const uint32_t *b_lo, uint32_t nB, uint32_t d, int lane) {
+    uint32_t lo = d > nB ? d - nB : 0u, hi = min(d, nA);
+    while (lo < hi) {
+        const uint32_t step = (hi - lo + 63) / 64;
+        const uint32_t m = lo + (uint32_t)lane * step;
+        const bool probe = m < hi;
+        const bool before = probe && load_key(a_hi, a_lo, m) < load_key(b_hi, b_lo, d - 1 - m);
+        const uint32_t c = (uint32_t)__popcll(__ballot(before));  // probes before the split: a prefix of the lanes
+        const uint32_t nlo = c > 0 ? lo + (c - 1) * step + 1 : lo;
+        const uint32_t nhi = min(hi, lo + c * step);
+        lo = nlo;
+        hi = nhi;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_long_merge(const uint2 *__restrict__ ranges,
+                                                    const uint32_t *__restrict__ long_tiles,
+                                                    const WsHeader *__restrict__ hdr, int p, int passes,
+                                                    const uint32_t *__restrict__ src_hi,
+                                                    const uint32_t *__restrict__ src_lo, uint32_t *__restrict__ dst_hi,
+                                                    uint32_t *__restrict__ dst_lo, uint32_t *__restrict__ pval) {
+    __shared__ u64 sA[kMergeWindow], sB[kMergeWindow];
+    __shared__ uint32_t s_split[2];
+    if (hdr->overflow || !long_path_on(hdr, passes)) return;  // uniform
+    uint32_t t, w;
+    if (!long_tile_window(ranges, long_tiles, hdr->n_long, passes, kMergeWindow, blockIdx.x, t, w)) return;
+    const uint2 rg = ranges[t];
+    const uint32_t L = rg.y - rg.x;
+    const uint32_t o0 = w * kMergeWindow, o1 = min(o0 + kMergeWindow, L);
+    const uint64_t R64 = (uint64_t)kLongWindow << p;  // p < kMaxLongPasses: R < 2^29
+    const uint32_t R = (uint32_t)R64;
+    const uint32_t base = (uint32_t)((o0 / (2 * R64)) * (2 * R64));
+    const uint32_t nA = min(R, L - base), nB = L - base > R ? min(R, L - base - R) : 0u;
+    const uint32_t *ah = src_hi + rg.x + base, *al = src_lo + rg.x + base;
+    const uint32_t *bh = ah + R, *bl = al + R;
+    const bool last = p == passes - 1;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t d0 = o0 - base, d1 = o1 - base;
+    if (wave < 2) {
+        const uint32_t a = wave_merge_split(ah, al, nA, bh, bl, nB, wave == 0 ? d0 : d1, (int)lane);
+        if (lane == 0) s_split[wave] = a;
+    }
+    __syncthreads();
+    const uint32_t a0 = s_split[0], a1 = s_split[1], b0 = d0 - a0, b1 = d1 - a1;
+    const uint32_t na = a1 - a0, nb = b1 - b0;
+    for (uint32_t k = tid; k < na; k += 256) sA[k] = load_key(ah, al, a0 + k);
+    for (uint32_t k = tid; k < nb; k += 256) sB[k] = load_key(bh, bl, b0 + k);
+    __syncthreads();
+    constexpr uint32_t kPer = kMergeWindow / 256;
+    const uint32_t q = tid * kPer;
+    if (q >= na + nb) return;
+    // this thread's crossing of the staged merge
+    uint32_t lo = q > nb ? q - nb : 0u, hi = min(q, na);
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (sA[mid] < sB[q - 1 - mid]) lo = mid + 1;
+        else hi = mid;
+    }
+    uint32_t i = lo, j = q - lo;
+    const uint32_t out = rg.x + o0 + q;
+    const uint32_t nq = min(kPer, na + nb - q);
+    for (uint32_t k = 0; k < nq; ++k) {
+        const bool take_b = i >= na || (j < nb && sB[j] < sA[i]);
+        const u64 v = take_b ? sB[j] : sA[i];
+        i += take_b ? 0u : 1u;
+        j += take_b ? 1u : 0u;
+        if (last) {
+            pval[out + k] = (uint32_t)v;
+        } else {
+            dst_hi[out + k] = (uint32_t)(v >> 32);
+            dst_lo[out + k] = (uint32_t)v;
+        }
+    }
+}
+
+void launch_long_merge(const uint2 *ranges, const uint32_t *long_tiles, const WsHeader *hdr, int p, int long_passes,
+                       const uint32_t *src_hi, const uint32_t *src_lo, uint32_t *dst_hi, uint32_t *dst_lo,
+                       uint32_t *pval, uint32_t merge_wgs, hipStream_t st) {
+    if (merge_wgs == 0) return;
+    hipLaunchKernelGGL(k_long_merge, dim3(merge_wgs), dim3(256), 0, st, ranges, long_tiles, hdr, p, long_passes,
+                       src_hi, src_lo, dst_hi, dst_lo, pval);
+}
+
+// Tile id at every position of the sorted pairs (the export of the lists).
+__global__ __launch_bounds__(256) void k_expand_ranges(const uint2 *__restrict__ ranges, uint32_t total_tiles,
+                                                       uint32_t *__restrict__ pair_tiles,
+                                                       const WsHeader *__restrict__ hdr) {
+    const uint32_t t = blockIdx.x;
+    if (t >= total_tiles || hdr->overflow) return;
+    const uint2 rg = ranges[t];
+    for (uint32_t i = rg.x + threadIdx.x; i < rg.y; i += 256) pair_tiles[i] = t;
+}
+
+void launch_expand_ranges(const uint2 *ranges, uint32_t total_tiles, uint32_t *pair_tiles, const WsHeader *hdr,
+                          hipStream_t st) {
+    if (total_tiles == 0) return;
+    hipLaunchKernelGGL(k_expand_ranges, dim3(total_tiles), dim3(256), 0, st, ranges, total_tiles, pair_tiles, hdr);
 }
 
 // ---------------------------------------------------------------------------
@@ -812,7 +985,8 @@ void launch_tile_depth_sort(const uint2 *ranges, uint32_t total_tiles, uint32_t 
 // own, and marks the tiles in between empty, so no pre-clearing pass is needed.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t *__restrict__ pkey, uint2 *__restrict__ ranges,
-                                                     uint32_t total_tiles, const WsHeader *__restrict__ hdr) {
+                                                     uint32_t total_tiles, uint32_t *__restrict__ long_tiles,
+                                                     WsHeader *__restrict__ hdr) {
     const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     const uint64_t m = hdr->overflow ? 0ull : (uint64_t)hdr->n_pairs;
     if (i > m) return;
@@ -821,7 +995,24 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t *__restrict_
     if (i > 0 && prev == t) return;
     for (int64_t u = prev + 1; u < t; ++u) ranges[u] = make_uint2((uint32_t)i, (uint32_t)i);
     if (i < m) ranges[t].x = (uint32_t)i;
-    if (i > 0) ranges[prev].y = (uint32_t)i;
+    if (i > 0) {
+        ranges[prev].y = (uint32_t)i;
+        // a list longer than kGroupSortMax: find where it starts (the keys are
+        // sorted) and register it for the multi-workgroup sort
+        if (i > (uint64_t)kGroupSortMax && pkey[i - kGroupSortMax - 1] == (uint32_t)prev) {
+            uint64_t lo = 0, hi = i - kGroupSortMax - 1;  // first position holding prev lies in [lo, hi]
+            while (lo < hi) {
+                const uint64_t mid = (lo + hi) >> 1;
+                if (pkey[mid] < (uint32_t)prev) lo = mid + 1;
+                else hi = mid;
+            }
+            const uint32_t len = (uint32_t)(i - lo);
+            const uint32_t k = atomicAdd(&hdr->n_long, 1u);
+            if (k < kMaxLongTiles) long_tiles[k] = (uint32_t)prev;
+            atomicAdd(&hdr->long_pairs, len);
+            atomicMax(&hdr->max_long, len);
+        }
+    }
 }
 
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *__restrict__ p, uint32_t value, uint64_t n) {
@@ -854,11 +1045,11 @@ void launch_reset_queue(WsHeader *h, int which, hipStream_t st) {
     hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(1), 0, st, h, which);
 }
 
-void launch_tile_ranges(const uint32_t *pkey, uint64_t cap, uint2 *ranges, uint32_t total_tiles, const WsHeader *hdr,
-                        hipStream_t st) {
+void launch_tile_ranges(const uint32_t *pkey, uint64_t cap, uint2 *ranges, uint32_t total_tiles,
+                        uint32_t *long_tiles, WsHeader *hdr, hipStream_t st) {
     if (total_tiles == 0) return;
     hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((cap + 1 + 255) / 256)), dim3(256), 0, st, pkey, ranges,
-                       total_tiles, hdr);
+                       total_tiles, long_tiles, hdr);
 }
 
 }  // namespace gsr

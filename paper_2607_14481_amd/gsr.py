@@ -59,7 +59,7 @@ class gsr_gaussian_grads(C.Structure):
 
 class gsr_launch_config(C.Structure):
     _fields_ = [("tile_h", C.c_int32), ("persistent_ctas", C.c_int32), ("stage_events", C.c_void_p),
-                ("reserved", C.c_int32 * 4)]
+                ("long_list_passes", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class gsr_param_set(C.Structure):
@@ -76,7 +76,8 @@ class gsr_adam_config(C.Structure):
 
 class gsr_stats(C.Structure):
     _fields_ = [("visible", C.c_int64), ("pairs", C.c_int64), ("evaluations", C.c_int64),
-                ("contributors", C.c_int64), ("replays", C.c_int64)]
+                ("contributors", C.c_int64), ("replays", C.c_int64), ("long_lists", C.c_int64),
+                ("longest_list", C.c_int64)]
 
 
 STAGES = ("project", "compact", "emit", "tile_sort", "composite_fwd", "composite_bwd", "project_bwd")
@@ -181,11 +182,21 @@ def cameras(cams: Sequence) -> "C.Array[gsr_camera]":
     return arr
 
 
-def launch_config(tile_h: int = 16, persistent_ctas: int = 0) -> gsr_launch_config:
+def launch_config(tile_h: int = 16, persistent_ctas: int = 0, long_list_passes: int = 0) -> gsr_launch_config:
     cfg = gsr_launch_config()
     cfg.tile_h = int(tile_h)
     cfg.persistent_ctas = int(persistent_ctas)
+    cfg.long_list_passes = int(long_list_passes)
     return cfg
+
+
+LONG_LIST_RUN = 4096  # entries one workgroup sorts; longer tile lists are merged from runs of this length
+
+
+def long_list_passes(longest: int) -> int:
+    """Merge passes that cover a tile list of `longest` entries (0 if one workgroup sorts it)."""
+    runs = -(-int(longest) // LONG_LIST_RUN)
+    return 0 if runs <= 1 else (runs - 1).bit_length()
 
 
 def _as_param(t: torch.Tensor, name: str) -> torch.Tensor:

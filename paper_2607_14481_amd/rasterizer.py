@@ -28,7 +28,8 @@ class GaussianRasterizer:
     default synchronous mode every forward checks it once on the host and
     grows the workspace when needed.  With ``sync=False`` the forward never
     waits: the capacity is the last measured pair count times `headroom`, and
-    an overflow is reported by `check_overflow` after the fact.
+    an overflow is reported by `check_overflow` after the fact, which also
+    sizes the sort of tile lists longer than 4096 entries for later forwards.
     """
 
     def __init__(self, cams: Sequence, sh_degree: int, tile_h: int = 16, persistent: bool = False,
@@ -87,6 +88,10 @@ class GaussianRasterizer:
         self.last_pairs = needed
         if ovf or needed * self.headroom > self.capacity:
             self.capacity = max(self.capacity, int(needed * self.headroom) + 1024)
+        # lists longer than one workgroup sorts: enqueue enough merge passes for
+        # the longest one seen (the synchronous forward sizes them itself)
+        longest = gsr.query_stats(ws)["longest_list"]
+        self.cfg.long_list_passes = max(int(self.cfg.long_list_passes), gsr.long_list_passes(longest))
         return ovf
 
     def backward(self, ws: torch.Tensor, params: Sequence[torch.Tensor], world_to_cam: torch.Tensor, bg,

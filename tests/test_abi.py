@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 def test_host_side_argument_checks():
     from paper_2607_14481_amd import gsr
     from paper_2607_14481_amd import scenes as S
-    assert gsr.version() == 1
+    assert gsr.version() == 2
     assert gsr.status_string(gsr.GSR_ERR_CAPACITY) == "GSR_ERR_CAPACITY"
     cam = S.pinhole(128, 96, S.look_at([0, 0, -3]))
     nb1 = gsr.workspace_bytes(1000, [cam], 10_000)

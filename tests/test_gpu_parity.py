@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 from oracle import oracle as O
+from paper_2607_14481_amd import gsr
 from paper_2607_14481_amd import scenes as S
 
 from ._util import GRAD_KEYS, gpu_render, log, oracle_bin_from_gpu_state, rel_err
@@ -133,11 +134,13 @@ def test_binning_bit_exact(case):
 
 @pytest.mark.parametrize("n,step", [(2, 0.25), (63, 0.25), (256, 0.25), (257, 0.25), (512, 0.25), (513, 0.25),
                                     (1024, 0.25), (1025, 0.25), (2049, 0.25), (4096, 0.25), (4097, 0.25), (9000, 0.25),
-                                    (65, 1e-4), (257, 1e-4), (700, 1e-4), (1024, 1e-4), (1000, 0.0)])
+                                    (65, 1e-4), (257, 1e-4), (700, 1e-4), (1024, 1e-4), (1000, 0.0),
+                                    (40000, 1e-4)])
 def test_single_tile_list_lengths(n, step):
     """Every Gaussian lands in one tile, so that tile's list has exactly n
     entries: the lengths at which the per-tile depth sort changes form (1, 2
-    or 4 entries per thread, 16 per thread in registers, global memory).  Depths are
+    or 4 entries per thread, 16 per thread in registers, runs of 4096 merged
+    over several workgroups: one pass above 4096 entries, four at 40000).  Depths are
     rounded to `step` metres: at 0.25 m most keys tie (clustered depths, the
     network path); at 0.1 mm a few keys tie among well-spread ones (the bucket
     path, where the item must still break the tie); 0 leaves them as drawn."""
@@ -152,6 +155,43 @@ def test_single_tile_list_lengths(n, step):
     lens = ranges[:, 1] - ranges[:, 0]
     log(f"single-tile list: n={n} tile lengths {lens.tolist()}")
     assert lens.max() == n
+    assert st["M"] == len(tiles)
+    np.testing.assert_array_equal(st["pair_tiles"].astype(np.uint64), tiles)
+    np.testing.assert_array_equal(st["pair_items"].astype(np.uint64), items)
+
+
+@pytest.mark.parametrize("hint", [False, True])
+def test_long_lists_without_host_sync(hint):
+    """Without the synchronous forward the library cannot measure the longest
+    list before sorting it: with no hint every list above 4096 entries is
+    sorted by one workgroup (exact, slow); with the hint from an earlier
+    forward's stats the runs-and-merges path takes them.  Both must give the
+    oracle's lists."""
+    import torch
+    from paper_2607_14481_amd.rasterizer import GaussianRasterizer
+    from ._util import params_to_device, poses_to_device
+    wl = S.small_view(seed=33, n=12000, width=40, height=24, log_scale_mean=-7.0, xy_half=0.002)
+    m = wl.scene.means.copy()
+    m[:, 2] = np.round(m[:, 2] / 1e-4) * 1e-4
+    sc, cams = wl.scene.with_means(m), wl.cameras
+    rast = GaussianRasterizer(cams, sc.sh_degree, sync=False)
+    rast.capacity = 2 * sc.n
+    params = params_to_device(sc)
+    w2c = poses_to_device(cams)
+    ws = rast.workspace(sc.n)
+    if hint:
+        rast.forward(params, w2c, ws=ws)
+        torch.cuda.synchronize()
+        assert not rast.check_overflow(ws)
+        assert rast.cfg.long_list_passes == 2
+    else:
+        assert rast.cfg.long_list_passes == 0
+    rast.forward(params, w2c, ws=ws)
+    torch.cuda.synchronize()
+    st = gsr.export_state(ws, params, sc.sh_degree, cams, rast.cfg)
+    tiles, items, ranges = oracle_bin_from_gpu_state(st, cams, sc.n)
+    log(f"long lists, hint={hint}: longest {int((ranges[:, 1] - ranges[:, 0]).max())}, "
+        f"stats {gsr.query_stats(ws)}")
     assert st["M"] == len(tiles)
     np.testing.assert_array_equal(st["pair_tiles"].astype(np.uint64), tiles)
     np.testing.assert_array_equal(st["pair_items"].astype(np.uint64), items)
