@@ -131,9 +131,8 @@ def measure_view(wl, steps, warmup, tile_h=16, persistent=False, graph=True):
 
     def step(ws=None, out=None):
         rgb, ws = rast.forward(params, w2c, bg, ws=ws, out=out)
-        diff = rgb - target
-        grad = torch.sign(diff) / numel  # d/d img of mean |img - target|
-        grads, g_w2c, g_tw = rast.backward(ws, params, w2c, bg, rgb, grad)
+        # mean |img - target|: its image gradient is formed inside the backward
+        grads, g_w2c, g_tw = rast.backward_l1(ws, params, w2c, bg, rgb, target)
         return rgb, ws, grads, g_tw
 
     # ---- plain form: synchronous capacity check, one view per launch sequence
@@ -196,14 +195,14 @@ def measure_view(wl, steps, warmup, tile_h=16, persistent=False, graph=True):
             with torch.cuda.stream(s):
                 for _ in range(3):
                     rgb, _ = grast.forward(params, w2c, bg, ws=gws, out=gout)
-                    gr, _, _ = grast.backward(gws, params, w2c, bg, rgb, torch.sign(rgb - target) / numel)
+                    gr, _, _ = grast.backward_l1(gws, params, w2c, bg, rgb, target)
             torch.cuda.current_stream().wait_stream(s)
             torch.cuda.synchronize()
             assert not grast.check_overflow(gws)
             cg = torch.cuda.CUDAGraph()
             with torch.cuda.graph(cg):
                 rgb, _ = grast.forward(params, w2c, bg, ws=gws, out=gout)
-                gr, _, _ = grast.backward(gws, params, w2c, bg, rgb, torch.sign(rgb - target) / numel)
+                gr, _, _ = grast.backward_l1(gws, params, w2c, bg, rgb, target)
             for _ in range(warmup):
                 cg.replay()
             torch.cuda.synchronize()
@@ -252,10 +251,9 @@ def run_keyframe(wl, iterations=30, repeats=3):
         losses = []
         for it in range(1, iterations + 1):
             rgb, ws = rast.forward(params, w2c)
-            diff = rgb - target
             if it == 1 or it == iterations:
-                losses.append(diff.abs().mean())
-            grads, _, twist = rast.backward(ws, params, w2c, (0.0, 0.0, 0.0), rgb, torch.sign(diff) / diff.numel())
+                losses.append((rgb - target).abs().mean())
+            grads, _, twist = rast.backward_l1(ws, params, w2c, (0.0, 0.0, 0.0), rgb, target)
             gsr.adam_step(params, grads, m, v, sc.sh_degree, it, acfg, ws=ws, cams=cams, cfg=rast.cfg)
             gsr.pose_step(w2c, twist, pm, pv, it, 1e-4)
         return losses

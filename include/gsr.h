@@ -204,6 +204,21 @@ int gsr_rasterize_backward(void *ws, size_t ws_bytes, const gsr_gaussians *g, in
                            uint32_t flags, void *stream);
 
 /*
+ * The same backward for the photometric loss itself: the mean absolute error
+ * L = sum |C - target| / (3 sum H_v W_v) over every channel and pixel of all
+ * views (the rendering loss of the optimisation, Sec. 5.2, read as L1), so
+ * that dL/dC = sign(C - target) / (3 sum H_v W_v) is formed inside the
+ * backward compositing instead of being passed in.  target_rgb: device, same
+ * layout as out_rgb.  Other arguments, outputs and errors as for
+ * gsr_rasterize_backward.
+ */
+int gsr_rasterize_backward_l1(void *ws, size_t ws_bytes, const gsr_gaussians *g, int32_t n_views,
+                              const gsr_camera *cams, const float *world_to_cam, const float *bg,
+                              const gsr_launch_config *cfg, const float *out_rgb, const float *target_rgb,
+                              const gsr_gaussian_grads *grads, float *dL_dworld_to_cam, float *dL_dtwist,
+                              uint32_t flags, void *stream);
+
+/*
  * Pair count of the last forward on ws.  Reads the workspace header with a
  * blocking device->host copy on stream (so it waits for the forward).
  * needed: M required; capacity: M the workspace holds; overflowed: 1 if the

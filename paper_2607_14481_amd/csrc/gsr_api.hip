@@ -226,7 +226,98 @@ struct StageMark {
 };
 
 // Number of tile-sort passes decides which ping-pong buffer holds the result.
+// The synchronous forward's header readback: into pinned host memory (one
+// buffer and event per thread and device, created on first use and kept until
+// the process ends) and a spin on the event rather than a blocking stream
+// wait, so the host resumes launching as soon as the copy lands.
+int read_header_now(const gsr::WsHeader *dev_hdr, gsr::WsHeader &out, hipStream_t st) {
+    struct Slot {
+        gsr::WsHeader *host = nullptr;
+        hipEvent_t ev = nullptr;
+    };
+    thread_local Slot slots[64];
+    int dev = 0;
+    int rc = check_hip(hipGetDevice(&dev), "current device");
+    if (rc) return rc;
+    if (dev < 0 || dev >= 64) {  // outside the table: a plain blocking copy
+        if ((rc = check_hip(hipMemcpyAsync(&out, dev_hdr, sizeof(out), hipMemcpyDeviceToHost, st), "header copy")))
+            return rc;
+        return check_hip(hipStreamSynchronize(st), "stream sync");
+    }
+    Slot &s = slots[dev];
+    if (!s.host) {
+        if ((rc = check_hip(hipHostMalloc(reinterpret_cast<void **>(&s.host), sizeof(gsr::WsHeader), 0),
+                            "pinned header buffer")))
+            return rc;
+        if ((rc = check_hip(hipEventCreateWithFlags(&s.ev, hipEventDisableTiming), "header event"))) return rc;
+    }
+    if ((rc = check_hip(hipMemcpyAsync(s.host, dev_hdr, sizeof(out), hipMemcpyDeviceToHost, st), "header copy")))
+        return rc;
+    if ((rc = check_hip(hipEventRecord(s.ev, st), "header event record"))) return rc;
+    for (;;) {
+        const hipError_t e = hipEventQuery(s.ev);
+        if (e == hipSuccess) break;
+        if (e != hipErrorNotReady) return check_hip(e, "header event wait");
+    }
+    std::memcpy(&out, s.host, sizeof(out));
+    return GSR_OK;
+}
+
 int pair_result_buffer(uint32_t total_tiles) { return ((tile_bits(total_tiles) + 7) / 8) & 1; }
+
+}  // namespace
+
+namespace {
+
+int backward_impl(void *ws, size_t ws_bytes, const gsr_gaussians *g, int32_t n_views, const gsr_camera *cams,
+                         const float *world_to_cam, const gsr_launch_config *cfg, const float *out_rgb,
+                         const float *dL_drgb, const float *target_rgb, const gsr_gaussian_grads *grads,
+                         float *dL_dworld_to_cam, float *dL_dtwist, uint32_t flags, void *stream) {
+    using namespace gsr;
+    int rc = check_gaussians(g);
+    if (rc) return rc;
+    ViewTable vt;
+    if ((rc = build_views(n_views, cams, cfg, vt))) return rc;
+    if (!ws || !world_to_cam || !out_rgb || !(dL_drgb || target_rgb) || !grads)
+        return fail(GSR_ERR_INVALID_ARGUMENT,
+                    "ws, world_to_cam, out_rgb, the upstream gradient (or target) and grads must not be NULL");
+    if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacities || !grads->sh))
+        return fail(GSR_ERR_INVALID_ARGUMENT, "a gradient output pointer is NULL");
+    if (g->n > 0 && ((reinterpret_cast<uintptr_t>(grads->quats) | reinterpret_cast<uintptr_t>(grads->sh)) & 15u))
+        return fail(GSR_ERR_INVALID_ARGUMENT, "grads->quats and grads->sh must be 16-byte aligned");
+    WsLayout L;
+    uint64_t cap = 0;
+    if ((rc = layout_from_bytes((uint64_t)g->n, vt, ws_bytes, L, cap))) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Ptrs p = carve(ws, L);
+    const int pc = pair_result_buffer(vt.total_tiles);
+    const bool pers = (flags & GSR_FLAG_PERSISTENT) != 0;
+    const StageMark mark{cfg ? static_cast<hipEvent_t *>(cfg->stage_events) : nullptr, st};
+    mark.begin(GSR_STAGE_COMPOSITE_BWD);
+    if (pers) launch_reset_queue(p.hdr, 1, st);
+    ZeroRows zr{};
+    zr.g = *grads;
+    zr.count = p.count;
+    zr.n = (uint64_t)g->n;
+    zr.n_views = vt.n_views;
+    zr.sh_k = (g->sh_degree + 1) * (g->sh_degree + 1);
+    zr.per_tile = vt.total_tiles ? (zr.n + vt.total_tiles - 1) / vt.total_tiles : 0;
+    Upstream up{dL_drgb, target_rgb, 0.f};
+    if (target_rgb) up.l1_scale = 1.0f / (float)(3.0 * (double)vt.total_pixels);
+    launch_composite_bwd(vt, p.ranges, p.pval[pc], p.rec, p.ulo, out_rgb, up, p.pix_n, p.tile_cut, p.partial,
+                         zr, p.hdr, pers, persistent_ctas(cfg), st);
+    mark.end(GSR_STAGE_COMPOSITE_BWD);
+    mark.begin(GSR_STAGE_PROJECT_BWD);
+    launch_pair_reduce(vt, p.poff, p.chunk_item, (uint64_t)g->n, cap, p.item_box, p.tile_cut, p.partial,
+                       p.screen, p.carry, p.hdr, st);
+    launch_project_bwd(*g, vt, world_to_cam, (uint64_t)g->n, p.rec, p.count, p.vis, p.hdr, p.screen, p.carry, *grads,
+                       p.pose_part, L.pose_blocks, vt.total_tiles == 0, st);
+    if (g->n == 0)  // no Gaussian wrote a partial: the pose gradient is zero
+        launch_fill_u32(reinterpret_cast<uint32_t *>(p.pose_part), 0u, 12ull * vt.n_views * L.pose_blocks, st);
+    launch_pose_finalize(vt, world_to_cam, p.pose_part, L.pose_blocks, dL_dworld_to_cam, dL_dtwist, st);
+    mark.end(GSR_STAGE_PROJECT_BWD);
+    return check_hip(hipGetLastError(), "backward launch");
+}
 
 }  // namespace
 
@@ -309,8 +400,7 @@ int gsr_rasterize_forward(void *ws, size_t ws_bytes, const gsr_gaussians *g, int
     uint64_t long_pairs = cap, n_long = kMaxLongTiles;
     if (flags & GSR_FLAG_SYNC) {
         WsHeader h;
-        if ((rc = check_hip(hipMemcpyAsync(&h, p.hdr, sizeof(h), hipMemcpyDeviceToHost, st), "header copy"))) return rc;
-        if ((rc = check_hip(hipStreamSynchronize(st), "stream sync"))) return rc;
+        if ((rc = read_header_now(p.hdr, h, st))) return rc;
         if (h.overflow)
             return fail(GSR_ERR_CAPACITY, "needs %u pairs, workspace holds %llu", h.n_pairs, (unsigned long long)cap);
         passes = 0;
@@ -346,48 +436,21 @@ int gsr_rasterize_backward(void *ws, size_t ws_bytes, const gsr_gaussians *g, in
                            const gsr_launch_config *cfg, const float *out_rgb, const float *dL_drgb,
                            const gsr_gaussian_grads *grads, float *dL_dworld_to_cam, float *dL_dtwist, uint32_t flags,
                            void *stream) {
-    using namespace gsr;
     (void)bg;
-    int rc = check_gaussians(g);
-    if (rc) return rc;
-    ViewTable vt;
-    if ((rc = build_views(n_views, cams, cfg, vt))) return rc;
-    if (!ws || !world_to_cam || !out_rgb || !dL_drgb || !grads)
-        return fail(GSR_ERR_INVALID_ARGUMENT, "ws, world_to_cam, out_rgb, dL_drgb and grads must not be NULL");
-    if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacities || !grads->sh))
-        return fail(GSR_ERR_INVALID_ARGUMENT, "a gradient output pointer is NULL");
-    if (g->n > 0 && ((reinterpret_cast<uintptr_t>(grads->quats) | reinterpret_cast<uintptr_t>(grads->sh)) & 15u))
-        return fail(GSR_ERR_INVALID_ARGUMENT, "grads->quats and grads->sh must be 16-byte aligned");
-    WsLayout L;
-    uint64_t cap = 0;
-    if ((rc = layout_from_bytes((uint64_t)g->n, vt, ws_bytes, L, cap))) return rc;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const Ptrs p = carve(ws, L);
-    const int pc = pair_result_buffer(vt.total_tiles);
-    const bool pers = (flags & GSR_FLAG_PERSISTENT) != 0;
-    const StageMark mark{cfg ? static_cast<hipEvent_t *>(cfg->stage_events) : nullptr, st};
-    mark.begin(GSR_STAGE_COMPOSITE_BWD);
-    if (pers) launch_reset_queue(p.hdr, 1, st);
-    ZeroRows zr{};
-    zr.g = *grads;
-    zr.count = p.count;
-    zr.n = (uint64_t)g->n;
-    zr.n_views = vt.n_views;
-    zr.sh_k = (g->sh_degree + 1) * (g->sh_degree + 1);
-    zr.per_tile = vt.total_tiles ? (zr.n + vt.total_tiles - 1) / vt.total_tiles : 0;
-    launch_composite_bwd(vt, p.ranges, p.pval[pc], p.rec, p.ulo, out_rgb, dL_drgb, p.pix_n, p.tile_cut, p.partial,
-                         zr, p.hdr, pers, persistent_ctas(cfg), st);
-    mark.end(GSR_STAGE_COMPOSITE_BWD);
-    mark.begin(GSR_STAGE_PROJECT_BWD);
-    launch_pair_reduce(vt, p.poff, p.chunk_item, (uint64_t)g->n, cap, p.item_box, p.tile_cut, p.partial,
-                       p.screen, p.carry, p.hdr, st);
-    launch_project_bwd(*g, vt, world_to_cam, (uint64_t)g->n, p.rec, p.count, p.vis, p.hdr, p.screen, p.carry, *grads,
-                       p.pose_part, L.pose_blocks, vt.total_tiles == 0, st);
-    if (g->n == 0)  // no Gaussian wrote a partial: the pose gradient is zero
-        launch_fill_u32(reinterpret_cast<uint32_t *>(p.pose_part), 0u, 12ull * vt.n_views * L.pose_blocks, st);
-    launch_pose_finalize(vt, world_to_cam, p.pose_part, L.pose_blocks, dL_dworld_to_cam, dL_dtwist, st);
-    mark.end(GSR_STAGE_PROJECT_BWD);
-    return check_hip(hipGetLastError(), "backward launch");
+    if (!dL_drgb) return fail(GSR_ERR_INVALID_ARGUMENT, "dL_drgb must not be NULL");
+    return backward_impl(ws, ws_bytes, g, n_views, cams, world_to_cam, cfg, out_rgb, dL_drgb, nullptr, grads,
+                         dL_dworld_to_cam, dL_dtwist, flags, stream);
+}
+
+int gsr_rasterize_backward_l1(void *ws, size_t ws_bytes, const gsr_gaussians *g, int32_t n_views,
+                              const gsr_camera *cams, const float *world_to_cam, const float *bg,
+                              const gsr_launch_config *cfg, const float *out_rgb, const float *target_rgb,
+                              const gsr_gaussian_grads *grads, float *dL_dworld_to_cam, float *dL_dtwist,
+                              uint32_t flags, void *stream) {
+    (void)bg;
+    if (!target_rgb) return fail(GSR_ERR_INVALID_ARGUMENT, "target_rgb must not be NULL");
+    return backward_impl(ws, ws_bytes, g, n_views, cams, world_to_cam, cfg, out_rgb, nullptr, target_rgb, grads,
+                         dL_dworld_to_cam, dL_dtwist, flags, stream);
 }
 
 int gsr_query_pairs(const void *ws, size_t ws_bytes, int64_t *needed, int64_t *capacity, int32_t *overflowed,

@@ -325,12 +325,15 @@ __device__ __forceinline__ void zero_unseen_rows(const ZeroRows &z, uint32_t t, 
     }
 }
 
+__device__ __forceinline__ float l1_grad(float c, float target, float scale) {
+    return c > target ? scale : (c < target ? -scale : 0.f);
+}
+
 template <int RPL>
 __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uint2 *__restrict__ ranges,
                                                          const uint32_t *__restrict__ pval,
                                                          const Rec *__restrict__ rec, const float2 *__restrict__ ulo,
-                                                         const float *__restrict__ out_rgb,
-                                                         const float *__restrict__ dL_drgb,
+                                                         const float *__restrict__ out_rgb, Upstream up,
                                                          const uint32_t *__restrict__ pix_n,
                                                          const uint4 *__restrict__ tile_cut,
                                                          float *__restrict__ partial, ZeroRows zr, WsHeader *hdr,
@@ -351,7 +354,7 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
         const uint32_t px = c.ox + lx;
         const size_t plane = (size_t)c.width * c.height;
         const float *img = out_rgb + 3 * (size_t)c.pix_off;
-        const float *gimg = dL_drgb + 3 * (size_t)c.pix_off;
+        const float *gimg = (up.target ? up.target : up.grad) + 3 * (size_t)c.pix_off;
         float T[RPL], g0[RPL], g1[RPL], g2[RPL], gout[RPL], gacc[RPL];
         uint32_t ncon[RPL];
 #pragma unroll
@@ -362,10 +365,16 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
             if (px < c.width && py < c.height) {
                 const size_t pix = (size_t)py * c.width + px;
                 ncon[k] = pix_n[c.pix_off + pix];
+                const float i0 = img[pix], i1 = img[plane + pix], i2 = img[2 * plane + pix];
                 g0[k] = gimg[pix];
                 g1[k] = gimg[plane + pix];
                 g2[k] = gimg[2 * plane + pix];
-                gout[k] = g0[k] * img[pix] + g1[k] * img[plane + pix] + g2[k] * img[2 * plane + pix];
+                if (up.target) {  // mean absolute error: dL/dC = sign(C - target) / count
+                    g0[k] = l1_grad(i0, g0[k], up.l1_scale);
+                    g1[k] = l1_grad(i1, g1[k], up.l1_scale);
+                    g2[k] = l1_grad(i2, g2[k], up.l1_scale);
+                }
+                gout[k] = g0[k] * i0 + g1[k] * i1 + g2[k] * i2;
             } else {
                 ncon[k] = 0;
                 g0[k] = g1[k] = g2[k] = gout[k] = 0.f;
@@ -509,7 +518,7 @@ void launch_composite_fwd(const ViewTable &vt, const uint2 *ranges, const uint32
 }
 
 void launch_composite_bwd(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
-                          const float2 *ulo, const float *out_rgb, const float *dL_drgb, const uint32_t *pix_n,
+                          const float2 *ulo, const float *out_rgb, const Upstream &up, const uint32_t *pix_n,
                           const uint4 *tile_cut, float *partial, const ZeroRows &zr, WsHeader *hdr, bool persistent,
                           int persistent_ctas, hipStream_t st) {
     if (vt.total_tiles == 0) return;
@@ -518,7 +527,7 @@ void launch_composite_bwd(const ViewTable &vt, const uint2 *ranges, const uint32
     hipLaunchKernelGGL(k_composite_bwd<R>,                                                                          \
                        dim3(persistent ? (unsigned)resident_ctas(k_composite_bwd<R>, persistent_ctas)               \
                                        : vt.total_tiles),                                                           \
-                       dim3(kWave), 0, st, vt, ranges, pval, rec, ulo, out_rgb, dL_drgb, pix_n, tile_cut, partial,  \
+                       dim3(kWave), 0, st, vt, ranges, pval, rec, ulo, out_rgb, up, pix_n, tile_cut, partial,       \
                        zr, hdr, p)
     switch (vt.tile_h) {
         case 4: GSR_BWD(1); break;

@@ -180,8 +180,15 @@ struct ZeroRows {
     uint64_t n, per_tile;
     int32_t n_views, sh_k;
 };
+// The upstream image gradient: given (grad), or the mean absolute error
+// against a target image, dL/dC = sign(C - target) * l1_scale.
+struct Upstream {
+    const float *grad;
+    const float *target;
+    float l1_scale;
+};
 void launch_composite_bwd(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
-                          const float2 *ulo, const float *out_rgb, const float *dL_drgb, const uint32_t *pix_n,
+                          const float2 *ulo, const float *out_rgb, const Upstream &up, const uint32_t *pix_n,
                           const uint4 *tile_cut, float *partial, const ZeroRows &zr, WsHeader *hdr, bool persistent,
                           int persistent_ctas, hipStream_t st);
 void launch_pair_reduce(const ViewTable &vt, const uint32_t *poff, const uint32_t *chunk_item, uint64_t n,

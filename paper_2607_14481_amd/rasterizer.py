@@ -106,6 +106,21 @@ class GaussianRasterizer:
                                g_w2c, g_tw, self.flags & gsr.GSR_FLAG_PERSISTENT, self.cfg)
         return grads, (g_w2c.reshape(V, 4, 4) if want_pose else None), g_tw
 
+    def backward_l1(self, ws: torch.Tensor, params: Sequence[torch.Tensor], world_to_cam: torch.Tensor, bg,
+                    rgb: torch.Tensor, target: torch.Tensor, want_pose: bool = True):
+        """Backward of the mean absolute error between rgb and target (same
+        planar layout), with dL/drgb formed inside the library."""
+        params = [gsr._as_param(t, nm) for t, nm in zip(params, PARAM_NAMES)]
+        w2c = gsr._as_param(world_to_cam, "world_to_cam").reshape(len(self.cams), 16)
+        grads = [torch.empty_like(t) for t in params]
+        V = len(self.cams)
+        g_w2c = torch.empty((V, 16), dtype=torch.float32, device=self.device) if want_pose else None
+        g_tw = torch.empty((V, 6), dtype=torch.float32, device=self.device) if want_pose else None
+        gsr.rasterize_backward_l1(ws, params, self.sh_degree, self.cams, w2c, bg, rgb,
+                                  gsr._as_param(target, "target"), grads, g_w2c, g_tw,
+                                  self.flags & gsr.GSR_FLAG_PERSISTENT, self.cfg)
+        return grads, (g_w2c.reshape(V, 4, 4) if want_pose else None), g_tw
+
     def split(self, rgb: torch.Tensor) -> List[torch.Tensor]:
         """Planar concatenated images -> list of [3, H, W] views."""
         out, o = [], 0
