@@ -120,8 +120,8 @@ typedef struct gsr_gaussian_grads {
 
 /* Stages of the two passes, for the optional per-stage timing events. */
 #define GSR_STAGE_PROJECT 0        /* forward: per-Gaussian projection */
-#define GSR_STAGE_COMPACT 1        /* forward: visible-item compaction */
-#define GSR_STAGE_EMIT 2           /* forward: pair offsets + pair emission */
+#define GSR_STAGE_COMPACT 1        /* forward: visible-item compaction and pair offsets */
+#define GSR_STAGE_EMIT 2           /* forward: pair emission */
 #define GSR_STAGE_TILE_SORT 3      /* forward: tile sort, tile ranges, per-tile depth sort */
 #define GSR_STAGE_COMPOSITE_FWD 4  /* forward: compositing */
 #define GSR_STAGE_COMPOSITE_BWD 5  /* backward: compositing */

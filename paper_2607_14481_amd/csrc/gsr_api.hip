@@ -101,7 +101,7 @@ gsr::WsLayout make_layout(uint64_t n, const gsr::ViewTable &vt, uint64_t cap) {
     L.ulo = take(sizeof(float2) * items);
     L.zkey = take(4 * items);
     L.count = take(4 * items);
-    L.scan_tmp = take(4 * scan_blocks);
+    L.scan_tmp = take(8 * scan_blocks);
     L.vis = take(4 * items);
     L.poff = take(4 * items);
     L.chunk_item = take(4 * (L.chunks + 1));
@@ -375,14 +375,12 @@ int gsr_rasterize_forward(void *ws, size_t ws_bytes, const gsr_gaussians *g, int
     const StageMark mark{cfg ? static_cast<hipEvent_t *>(cfg->stage_events) : nullptr, st};
 
     mark.begin(GSR_STAGE_PROJECT);
-    launch_reset_header(p.hdr, (uint32_t)cap, st);
-    launch_project_fwd(*g, vt, world_to_cam, n, p.rec, p.ulo, p.zkey, p.count, st);
+    launch_project_fwd(*g, vt, world_to_cam, n, p.rec, p.ulo, p.zkey, p.count, p.hdr, (uint32_t)cap, st);
     mark.end(GSR_STAGE_PROJECT);
     mark.begin(GSR_STAGE_COMPACT);
-    launch_compact_visible(p.count, L.items, p.vis, p.scan_tmp, p.hdr, st);
+    launch_visible_offsets(p.count, L.items, p.vis, p.poff, p.chunk_item, L.chunks, p.scan_tmp, p.hdr, st);
     mark.end(GSR_STAGE_COMPACT);
     mark.begin(GSR_STAGE_EMIT);
-    launch_pair_offsets(p.vis, p.count, L.items, p.poff, p.chunk_item, L.chunks, p.scan_tmp, p.hdr, st);
     const uint64_t pair_grid = cap;  // every kernel reads the pair count from the header
     launch_emit_pairs(vt, p.vis, p.poff, p.chunk_item, n, pair_grid, p.rec, p.zkey, p.item_box, p.pkey[0], p.pval[0],
                       p.hdr, st);

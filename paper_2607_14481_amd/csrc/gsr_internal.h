@@ -117,11 +117,17 @@ __host__ __device__ constexpr uint64_t chunk_count(uint64_t pairs) { return (pai
 void launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t st);
 void launch_reset_header(WsHeader *h, uint32_t cap, hipStream_t st);
 
+// Also resets the workspace header (pair capacity cap) for this forward.
 void launch_project_fwd(const gsr_gaussians &g, const ViewTable &vt, const float *w2c, uint64_t n,
-                        Rec *rec, float2 *ulo, uint32_t *zkey, uint32_t *count, hipStream_t st);
+                        Rec *rec, float2 *ulo, uint32_t *zkey, uint32_t *count, WsHeader *hdr, uint32_t cap,
+                        hipStream_t st);
 
 // Exclusive scans / compaction / sorting / binning.
-void launch_compact_visible(const uint32_t *count, uint64_t items, uint32_t *vis, uint32_t *block_tmp, WsHeader *hdr,
+// Visible items (ascending ids), their pair offsets and each chunk's first
+// item; header: visible and pair counts, overflow.  block_tmp: 2 u32 per
+// block of kScanTile items.
+void launch_visible_offsets(const uint32_t *count, uint64_t items, uint32_t *vis, uint32_t *poff,
+                            uint32_t *chunk_item, uint64_t chunks_cap, uint32_t *block_tmp, WsHeader *hdr,
                             hipStream_t st);
 // Element count of a sort, read on the device: *n_dev, or (hdr set) the pair
 // count, 0 if the binning overflowed.
@@ -158,9 +164,6 @@ void launch_long_merge(const uint2 *ranges, const uint32_t *long_tiles, const Ws
 void launch_expand_ranges(const uint2 *ranges, uint32_t total_tiles, uint32_t *pair_tiles, const WsHeader *hdr,
                           hipStream_t st);
 void launch_reset_queue(WsHeader *h, int which, hipStream_t st);
-void launch_pair_offsets(const uint32_t *vis, const uint32_t *count, uint64_t items_cap,
-                         uint32_t *poff, uint32_t *chunk_item, uint64_t chunks_cap, uint32_t *block_tmp,
-                         WsHeader *hdr, hipStream_t st);
 void launch_emit_pairs(const ViewTable &vt, const uint32_t *vis, const uint32_t *poff, const uint32_t *chunk_item,
                        uint64_t n, uint64_t pair_grid, Rec *rec, const uint32_t *zkey, uint4 *item_box,
                        uint32_t *pkey, uint32_t *pval, const WsHeader *hdr, hipStream_t st);

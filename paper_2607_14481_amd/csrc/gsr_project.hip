@@ -143,8 +143,13 @@ __global__ __launch_bounds__(kProjThreads) void k_project_fwd(gsr_gaussians g, V
                                                               const float *__restrict__ w2c, uint64_t n,
                                                               Rec *__restrict__ rec, float2 *__restrict__ ulo,
                                                               uint32_t *__restrict__ zkey,
-                                                              uint32_t *__restrict__ count) {
+                                                              uint32_t *__restrict__ count,
+                                                              WsHeader *__restrict__ hdr, uint32_t cap) {
     constexpr int K = (DEG + 1) * (DEG + 1);
+    if (blockIdx.x == 0 && threadIdx.x < sizeof(WsHeader) / 4) {
+        // a fresh header for this forward (read first by the visible-item scan)
+        reinterpret_cast<uint32_t *>(hdr)[threadIdx.x] = threadIdx.x == offsetof(WsHeader, pair_capacity) / 4 ? cap : 0u;
+    }
     const uint64_t item = (uint64_t)blockIdx.x * kProjThreads + threadIdx.x;
     if (item >= n * (uint64_t)vt.n_views) return;
     const int v = (int)(item / n);
@@ -252,15 +257,18 @@ __global__ __launch_bounds__(kProjThreads) void k_project_fwd(gsr_gaussians g, V
 }
 
 void launch_project_fwd(const gsr_gaussians &g, const ViewTable &vt, const float *w2c, uint64_t n, Rec *rec,
-                        float2 *ulo, uint32_t *zkey, uint32_t *count, hipStream_t st) {
+                        float2 *ulo, uint32_t *zkey, uint32_t *count, WsHeader *hdr, uint32_t cap, hipStream_t st) {
     const uint64_t items = n * (uint64_t)vt.n_views;
-    if (items == 0) return;
+    if (items == 0) {
+        launch_reset_header(hdr, cap, st);
+        return;
+    }
     const dim3 grid((unsigned)((items + kProjThreads - 1) / kProjThreads));
     switch (g.sh_degree) {
-        case 0: hipLaunchKernelGGL(k_project_fwd<0>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, ulo, zkey, count); break;
-        case 1: hipLaunchKernelGGL(k_project_fwd<1>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, ulo, zkey, count); break;
-        case 2: hipLaunchKernelGGL(k_project_fwd<2>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, ulo, zkey, count); break;
-        default: hipLaunchKernelGGL(k_project_fwd<3>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, ulo, zkey, count); break;
+        case 0: hipLaunchKernelGGL(k_project_fwd<0>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, ulo, zkey, count, hdr, cap); break;
+        case 1: hipLaunchKernelGGL(k_project_fwd<1>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, ulo, zkey, count, hdr, cap); break;
+        case 2: hipLaunchKernelGGL(k_project_fwd<2>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, ulo, zkey, count, hdr, cap); break;
+        default: hipLaunchKernelGGL(k_project_fwd<3>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, ulo, zkey, count, hdr, cap); break;
     }
 }
 

@@ -49,16 +49,6 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t *l
 // Phase 2: one block scans the block sums.  Phase 3: per-block scan + offset,
 // handing each element its exclusive prefix to an epilogue.
 // ---------------------------------------------------------------------------
-struct VisibleFlag {  // value = item visible (tiles touched > 0)
-    const uint32_t *count;
-    __device__ uint32_t operator()(uint64_t i) const { return count[i] > 0u ? 1u : 0u; }
-};
-struct CountOfVisible {  // value = tiles touched by the i-th visible item
-    const uint32_t *items;
-    const uint32_t *count;
-    __device__ uint32_t operator()(uint64_t i) const { return count[items[i]]; }
-};
-
 template <class F>
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(F f, const uint32_t *__restrict__ n_dev, uint64_t n_host,
                                                               uint32_t *__restrict__ block_sums) {
@@ -112,40 +102,6 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t *__restrict__ blo
     }
 }
 
-// Phase 3 for the compaction: visible items get their depth key and id written
-// at their exclusive prefix.
-__global__ __launch_bounds__(kScanThreads) void k_compact_apply(const uint32_t *__restrict__ count, uint64_t n,
-                                                                const uint32_t *__restrict__ block_sums,
-                                                                uint32_t *__restrict__ vis) {
-    __shared__ uint32_t lds[4];
-    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
-    uint32_t flags = 0, cnt = 0;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        const uint64_t i = base + k;
-        const bool vis = i < n && count[i] > 0u;
-        flags |= (vis ? 1u : 0u) << k;
-        cnt += vis;
-    }
-    uint32_t total;
-    uint32_t pos = block_sums[blockIdx.x] + block_exclusive_scan(cnt, lds, total);
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        if (flags & (1u << k)) vis[pos++] = (uint32_t)(base + k);
-    }
-}
-
-void launch_compact_visible(const uint32_t *count, uint64_t items, uint32_t *vis, uint32_t *block_tmp, WsHeader *hdr,
-                            hipStream_t st) {
-    const uint32_t nb = (uint32_t)((items + kScanTile - 1) / kScanTile);
-    if (nb == 0) return;
-    hipLaunchKernelGGL(k_scan_reduce<VisibleFlag>, dim3(nb), dim3(kScanThreads), 0, st, VisibleFlag{count},
-                       (const uint32_t *)nullptr, items, block_tmp);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, block_tmp, nb, &hdr->n_visible,
-                       (WsHeader *)nullptr);
-    hipLaunchKernelGGL(k_compact_apply, dim3(nb), dim3(kScanThreads), 0, st, count, items, block_tmp, vis);
-}
-
 // Ordered compaction of byte flags: out_idx receives, in ascending order, the
 // indices i < n with flags[i] != 0; their number goes to *out_count.
 struct ByteFlag {
@@ -182,51 +138,115 @@ void launch_compact_flags(const uint8_t *flags, uint64_t n, uint32_t *out_idx, u
     hipLaunchKernelGGL(k_flag_compact_apply, dim3(nb), dim3(kScanThreads), 0, st, flags, n, block_tmp, out_idx);
 }
 
-// Phase 3 for the pair offsets: poff[i] = exclusive prefix of the counts of the
-// visible items (the total and the overflow decision are already in the header).  The
-// item whose range holds a chunk's first pair is recorded for that chunk.
-__global__ __launch_bounds__(kScanThreads) void k_offsets_apply(CountOfVisible f,
-                                                                const uint32_t *__restrict__ block_sums,
-                                                                uint32_t *__restrict__ poff,
-                                                                uint32_t *__restrict__ chunk_item,
-                                                                uint64_t chunks_cap, const WsHeader *hdr) {
+// ---------------------------------------------------------------------------
+// A2 in one reduce-then-scan over the items, with two values per item: visible
+// (tiles touched > 0) and its tile count.  An invisible item counts zero tiles,
+// so the pair offset of the k-th visible item is the prefix of the counts over
+// all items before it.  Phase 3 writes the k-th visible item's id and pair
+// offset and, for each chunk of kChunkPairs pair slots whose first pair the
+// item holds, k.  The totals are the visible and pair counts; the block-sum
+// scan takes the overflow decision (pairs > capacity) too.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kScanThreads) void k_vis_reduce(const uint32_t *__restrict__ count, uint64_t n,
+                                                             uint32_t *__restrict__ block_vis,
+                                                             uint32_t *__restrict__ block_pairs) {
     __shared__ uint32_t lds[4];
-    const uint64_t n = hdr->n_visible;
     const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
-    if ((uint64_t)blockIdx.x * kScanTile >= n) return;  // uniform per block
-    uint32_t c[kScanItems];
-    uint32_t acc = 0;
+    uint32_t nv = 0, np = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        c[k] = base + k < n ? f(base + k) : 0u;
-        acc = sat_add(acc, c[k]);
+        const uint32_t c = base + k < n ? count[base + k] : 0u;
+        nv += c > 0u ? 1u : 0u;
+        np = sat_add(np, c);
     }
-    uint32_t total;
-    uint32_t run = sat_add(block_sums[blockIdx.x], block_exclusive_scan(acc, lds, total));
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < n) {
-            poff[base + k] = run;
-            // chunks whose first pair lies in [run, run + c[k])
-            const uint32_t end = sat_add(run, c[k]);
-            for (uint64_t ch = chunk_count(run); ch < chunks_cap && ch * kChunkPairs < end; ++ch)
-                chunk_item[ch] = (uint32_t)(base + k);
-        }
-        run = sat_add(run, c[k]);
+    uint32_t tv, tp;
+    block_exclusive_scan(nv, lds, tv);
+    block_exclusive_scan(np, lds, tp);
+    if (threadIdx.x == 0) {
+        block_vis[blockIdx.x] = tv;
+        block_pairs[blockIdx.x] = tp;
     }
 }
 
-void launch_pair_offsets(const uint32_t *vis, const uint32_t *count, uint64_t items_cap, uint32_t *poff,
-                         uint32_t *chunk_item, uint64_t chunks_cap, uint32_t *block_tmp, WsHeader *hdr,
-                         hipStream_t st) {
-    const uint32_t nb = (uint32_t)((items_cap + kScanTile - 1) / kScanTile);
+// Single workgroup: exclusive scans of both block-sum arrays in place.
+__global__ __launch_bounds__(1024) void k_vis_scan_blocks(uint32_t *__restrict__ block_vis,
+                                                          uint32_t *__restrict__ block_pairs, uint32_t nb,
+                                                          WsHeader *__restrict__ hdr) {
+    __shared__ uint32_t lds[2][16];
+    __shared__ uint32_t carry[2];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (threadIdx.x < 2) carry[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t base = 0; base < nb; base += 1024) {
+        const uint32_t i = base + threadIdx.x;
+        const uint32_t x0 = i < nb ? block_vis[i] : 0u, x1 = i < nb ? block_pairs[i] : 0u;
+        uint32_t inc0 = x0, inc1 = x1;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y0 = __shfl_up(inc0, o, 64), y1 = __shfl_up(inc1, o, 64);
+            if (lane >= o) inc0 += y0, inc1 = sat_add(inc1, y1);
+        }
+        if (lane == 63) lds[0][w] = inc0, lds[1][w] = inc1;
+        __syncthreads();
+        uint32_t before0 = carry[0], before1 = carry[1];
+        for (int k = 0; k < w; ++k) before0 += lds[0][k], before1 = sat_add(before1, lds[1][k]);
+        if (i < nb) {
+            block_vis[i] = before0 + (inc0 - x0);
+            block_pairs[i] = sat_add(before1, inc1 - x1);
+        }
+        __syncthreads();
+        if (threadIdx.x == 1023) carry[0] = before0 + inc0, carry[1] = sat_add(before1, inc1);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        hdr->n_visible = carry[0];
+        hdr->n_pairs = carry[1];
+        hdr->overflow = carry[1] > hdr->pair_capacity ? 1u : 0u;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_vis_apply(const uint32_t *__restrict__ count, uint64_t n,
+                                                            const uint32_t *__restrict__ block_vis,
+                                                            const uint32_t *__restrict__ block_pairs,
+                                                            uint32_t *__restrict__ vis, uint32_t *__restrict__ poff,
+                                                            uint32_t *__restrict__ chunk_item, uint64_t chunks_cap) {
+    __shared__ uint32_t lds[4];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+    uint32_t c[kScanItems], nv = 0, np = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        c[k] = base + k < n ? count[base + k] : 0u;
+        nv += c[k] > 0u ? 1u : 0u;
+        np = sat_add(np, c[k]);
+    }
+    uint32_t tv, tp;
+    uint32_t kv = block_vis[blockIdx.x] + block_exclusive_scan(nv, lds, tv);
+    uint32_t run = sat_add(block_pairs[blockIdx.x], block_exclusive_scan(np, lds, tp));
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (c[k] > 0u) {
+            vis[kv] = (uint32_t)(base + k);
+            poff[kv] = run;
+            // chunks whose first pair lies in [run, run + c)
+            const uint32_t end = sat_add(run, c[k]);
+            for (uint64_t ch = chunk_count(run); ch < chunks_cap && ch * kChunkPairs < end; ++ch)
+                chunk_item[ch] = kv;
+            ++kv;
+            run = end;
+        }
+    }
+}
+
+void launch_visible_offsets(const uint32_t *count, uint64_t items, uint32_t *vis, uint32_t *poff,
+                            uint32_t *chunk_item, uint64_t chunks_cap, uint32_t *block_tmp, WsHeader *hdr,
+                            hipStream_t st) {
+    const uint32_t nb = (uint32_t)((items + kScanTile - 1) / kScanTile);
     if (nb == 0) return;
-    CountOfVisible f{vis, count};
-    hipLaunchKernelGGL(k_scan_reduce<CountOfVisible>, dim3(nb), dim3(kScanThreads), 0, st, f, &hdr->n_visible,
-                       items_cap, block_tmp);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, block_tmp, nb, &hdr->n_pairs, hdr);
-    hipLaunchKernelGGL(k_offsets_apply, dim3(nb), dim3(kScanThreads), 0, st, f, block_tmp, poff, chunk_item,
-                       chunks_cap, (const WsHeader *)hdr);
+    uint32_t *bv = block_tmp, *bp = block_tmp + nb;
+    hipLaunchKernelGGL(k_vis_reduce, dim3(nb), dim3(kScanThreads), 0, st, count, items, bv, bp);
+    hipLaunchKernelGGL(k_vis_scan_blocks, dim3(1), dim3(1024), 0, st, bv, bp, nb, hdr);
+    hipLaunchKernelGGL(k_vis_apply, dim3(nb), dim3(kScanThreads), 0, st, count, items, bv, bp, vis, poff,
+                       chunk_item, chunks_cap);
 }
 
 // ---------------------------------------------------------------------------
