@@ -333,33 +333,17 @@ __global__ __launch_bounds__(kChunkThreads) void k_pair_reduce(ViewTable vt, con
     const uint32_t cend = min(c0 + kChunkPairs, m);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
 
-    // ---- this thread's pairs: values first (their loads overlap the item staging)
+    // ---- this thread's pairs: their items and whether each is ahead of its
+    // tile's cut (pairs past the cut were never written by the backward
+    // compositing: most of a dense scene's pairs, so their values are not read)
     const uint32_t pb = c0 + (uint32_t)tid * kChunkPerThread;
-    uint32_t key[kChunkPerThread];
-    float x[kChunkPerThread][kPartialStride];
-    if (pb + kChunkPerThread <= cend) {
-        const float4 *src = reinterpret_cast<const float4 *>(partial + (size_t)pb * kPartialStride);
-        float4 f[9];
-#pragma unroll
-        for (int j = 0; j < 9; ++j) f[j] = src[j];
-#pragma unroll
-        for (int j = 0; j < 9; ++j) {
-            x[(4 * j + 0) / 9][(4 * j + 0) % 9] = f[j].x;
-            x[(4 * j + 1) / 9][(4 * j + 1) % 9] = f[j].y;
-            x[(4 * j + 2) / 9][(4 * j + 2) % 9] = f[j].z;
-            x[(4 * j + 3) / 9][(4 * j + 3) % 9] = f[j].w;
-        }
-    } else {
-#pragma unroll
-        for (uint32_t u = 0; u < kChunkPerThread; ++u)
-#pragma unroll
-            for (int j = 0; j < kPartialStride; ++j)
-                x[u][j] = pb + u < cend ? partial[(size_t)(pb + u) * kPartialStride + j] : 0.f;
-    }
     uint32_t i_lo;
     const uint32_t nloc =
         load_chunk_items(vt, nullptr, poff, chunk_item, n, nullptr, nullptr, item_box, c, m, nvis, ci, i_lo);
-    // keys and the cut mask (pairs beyond their tile's cut were never written)
+    uint32_t key[kChunkPerThread];
+    bool valid[kChunkPerThread];
+#pragma unroll
+    for (uint32_t u = 0; u < kChunkPerThread; ++u) key[u] = kNoKey, valid[u] = false;
     if (pb < cend) {
         PairWalker pw;
         pw.start(ci, nloc, pb);
@@ -371,16 +355,40 @@ __global__ __launch_bounds__(kChunkThreads) void k_pair_reduce(ViewTable vt, con
                 key[u] = pw.k;
                 const uint4 cut = tile_cut[pw.tile(ci)];
                 const uint32_t zk = ci.zkey[pw.k];
-                const bool valid = zk < cut.y || (zk == cut.y && ci.item[pw.k] < cut.z);
-#pragma unroll
-                for (int j = 0; j < kPartialStride; ++j) x[u][j] = valid ? x[u][j] : 0.f;
-            } else {
-                key[u] = kNoKey;
+                valid[u] = zk < cut.y || (zk == cut.y && ci.item[pw.k] < cut.z);
             }
         }
-    } else {
+    }
+    float x[kChunkPerThread][kPartialStride];
 #pragma unroll
-        for (uint32_t u = 0; u < kChunkPerThread; ++u) key[u] = kNoKey;
+    for (uint32_t u = 0; u < kChunkPerThread; ++u)
+#pragma unroll
+        for (int j = 0; j < kPartialStride; ++j) x[u][j] = 0.f;
+    bool any = false;
+#pragma unroll
+    for (uint32_t u = 0; u < kChunkPerThread; ++u) any |= valid[u];
+    if (any && pb + kChunkPerThread <= cend) {
+        const float4 *src = reinterpret_cast<const float4 *>(partial + (size_t)pb * kPartialStride);
+        float4 f[9];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) f[j] = src[j];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            x[(4 * j + 0) / 9][(4 * j + 0) % 9] = f[j].x;
+            x[(4 * j + 1) / 9][(4 * j + 1) % 9] = f[j].y;
+            x[(4 * j + 2) / 9][(4 * j + 2) % 9] = f[j].z;
+            x[(4 * j + 3) / 9][(4 * j + 3) % 9] = f[j].w;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kChunkPerThread; ++u)
+#pragma unroll
+            for (int j = 0; j < kPartialStride; ++j) x[u][j] = valid[u] ? x[u][j] : 0.f;
+    } else if (any) {
+#pragma unroll
+        for (uint32_t u = 0; u < kChunkPerThread; ++u)
+#pragma unroll
+            for (int j = 0; j < kPartialStride; ++j)
+                x[u][j] = valid[u] ? partial[(size_t)(pb + u) * kPartialStride + j] : 0.f;
     }
 
     // ---- segments inside the thread: head (first), complete middles, tail (last)
