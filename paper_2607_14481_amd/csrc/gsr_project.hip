@@ -514,18 +514,6 @@ __device__ __forceinline__ void item_moments(const float4 *__restrict__ screen, 
     }
 }
 
-template <int K, bool VEC>
-__device__ __forceinline__ void store_sh_row(float *__restrict__ dst, const float (&v)[3 * K]) {
-    if constexpr (VEC) {
-        float4 *d4 = reinterpret_cast<float4 *>(dst);
-#pragma unroll
-        for (int k = 0; k < 3 * K / 4; ++k) d4[k] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
-    } else {
-#pragma unroll
-        for (int k = 0; k < 3 * K; ++k) dst[k] = v[k];
-    }
-}
-
 // Chain rule of one visible (view, Gaussian) item: its screen-space gradient
 // (from the pair moments) back to the Gaussian's parameters (added to gmu, gls,
 // gq, gop and to the SH row gsh: stored by the first view, added to by later
@@ -534,7 +522,7 @@ template <int DEG>
 __device__ __forceinline__ void item_backward(const gsr_gaussians &g, const ViewInfo &cam, const float *__restrict__ w2c,
                                               int v, uint64_t i, uint64_t item, uint32_t cnt,
                                               const Rec *__restrict__ rec, const float4 *__restrict__ screen,
-                                              const float *__restrict__ carry, float *__restrict__ gsh,
+                                              const float *__restrict__ carry, const float *sh_row, float *gsh,
                                               bool &sh_written, float (&gmu)[3], float (&gls)[3], float (&gq)[4],
                                               float &gop, float (&gW)[9], float (&gt)[3]) {
     constexpr int K = (DEG + 1) * (DEG + 1);
@@ -565,43 +553,32 @@ __device__ __forceinline__ void item_backward(const gsr_gaussians &g, const View
     const float dir[3] = {dvec[0] / dn, dvec[1] / dn, dvec[2] / dn};
     float Y[K];
     sh_eval<DEG, float>(dir[0], dir[1], dir[2], Y);
-    float shv[3 * K];
-    if constexpr (kVecSH) {
-        const float4 *src = reinterpret_cast<const float4 *>(g.sh) + (size_t)i * (3 * K / 4);
-#pragma unroll
-        for (int k = 0; k < 3 * K / 4; ++k) {
-            const float4 f = src[k];
-            shv[4 * k] = f.x, shv[4 * k + 1] = f.y, shv[4 * k + 2] = f.z, shv[4 * k + 3] = f.w;
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < 3 * K; ++k) shv[k] = g.sh[(size_t)i * K * 3 + k];
-    }
-    // colour, to know which channels the forward clamped at 0
+    // colour, to know which channels the forward clamped at 0 (the row is read
+    // twice rather than held in registers)
     float col[3] = {0.5f, 0.5f, 0.5f};
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        col[0] = fmaf(shv[3 * k], Y[k], col[0]);
-        col[1] = fmaf(shv[3 * k + 1], Y[k], col[1]);
-        col[2] = fmaf(shv[3 * k + 2], Y[k], col[2]);
+        col[0] = fmaf(sh_row[3 * k], Y[k], col[0]);
+        col[1] = fmaf(sh_row[3 * k + 1], Y[k], col[1]);
+        col[2] = fmaf(sh_row[3 * k + 2], Y[k], col[2]);
     }
     float gc[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) gc[c] = col[c] < 0.f ? 0.f : grgb[c];
-    // coefficient gradients (added to an earlier view's) and the weights of dRGB/ddir
-    float wdir[K], o[3 * K];
+    // coefficient gradients (added to an earlier view's) and the weights of
+    // dRGB/ddir; gsh may be sh_row itself: each coefficient is read before it
+    // is overwritten
+    float wdir[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        o[3 * k] = gc[0] * Y[k];
-        o[3 * k + 1] = gc[1] * Y[k];
-        o[3 * k + 2] = gc[2] * Y[k];
-        wdir[k] = fmaf(gc[0], shv[3 * k], fmaf(gc[1], shv[3 * k + 1], gc[2] * shv[3 * k + 2]));
+        const float s0 = sh_row[3 * k], s1 = sh_row[3 * k + 1], s2 = sh_row[3 * k + 2];
+        wdir[k] = fmaf(gc[0], s0, fmaf(gc[1], s1, gc[2] * s2));
+        float o0 = gc[0] * Y[k], o1 = gc[1] * Y[k], o2 = gc[2] * Y[k];
+        if (sh_written) o0 += gsh[3 * k], o1 += gsh[3 * k + 1], o2 += gsh[3 * k + 2];
+        gsh[3 * k] = o0;
+        gsh[3 * k + 1] = o1;
+        gsh[3 * k + 2] = o2;
     }
-    if (sh_written) {
-#pragma unroll
-        for (int k = 0; k < 3 * K; ++k) o[k] += gsh[k];
-    }
-    store_sh_row<K, kVecSH>(gsh, o);
     sh_written = true;
     float gdx, gdy, gdz;
     sh_grad_dir<DEG>(dir[0], dir[1], dir[2], wdir, gdx, gdy, gdz);
@@ -839,8 +816,8 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(
         const uint64_t item = (uint64_t)v * n + i;
         const uint32_t cnt = live ? count[item] : 0u;
         if (cnt > 0)
-            item_backward<DEG>(g, vt.v[v], w2c, v, i, item, cnt, rec, screen, carry, gsh, sh_written, gmu, gls, gq,
-                               gop, gW, gt);
+            item_backward<DEG>(g, vt.v[v], w2c, v, i, item, cnt, rec, screen, carry, g.sh + (size_t)i * K * 3, gsh,
+                               sh_written, gmu, gls, gq, gop, gW, gt);
         pose_block_partial(gW, gt, red, pose_part, v, pose_blocks);
     }
     if (!live) return;  // its rows were zeroed above (or it is one of the zeroed ones)
@@ -866,28 +843,68 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd_vis(
     const float4 *__restrict__ screen, const float *__restrict__ carry, gsr_gaussian_grads gr,
     float *__restrict__ pose_part, uint32_t pose_blocks) {
     constexpr int K = (DEG + 1) * (DEG + 1);
+    constexpr bool kVec = (3 * K) % 4 == 0;
+    constexpr int kUnit = kVec ? 4 : 1;              // floats per cooperative access
+    constexpr int kUnits = 3 * K / kUnit;            // accesses per SH row
+    constexpr int kStride = kVec ? 3 * K + 4 : 3 * K;  // LDS row stride in floats (16-B aligned when vectorised)
     __shared__ float red[4 * 12];
+    __shared__ __align__(16) float s_sh[4][64 * kStride];
     const uint32_t nvis = hdr->overflow ? 0u : hdr->n_visible;
     if (blockIdx.x * kProjThreads >= nvis) {  // uniform: no item, a zero partial
         if (threadIdx.x < 12) pose_part[(size_t)threadIdx.x * pose_blocks + blockIdx.x] = 0.f;
         return;
     }
     const uint32_t k = blockIdx.x * kProjThreads + threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t wave_first = blockIdx.x * kProjThreads + (uint32_t)wave * 64;
+    const bool live = k < nvis;
+    const uint32_t i = live ? vis[k] : 0u;  // one view: the item is the Gaussian
+    float *rows = s_sh[wave];
+    // the wave's SH rows, staged through LDS with row-contiguous (coalesced)
+    // accesses instead of one 3K-float row per lane
+#pragma unroll 4
+    for (int u = lane; u < 64 * kUnits; u += 64) {
+        const int r = u / kUnits, c = u - r * kUnits;
+        const uint32_t ir = (uint32_t)__shfl((int)i, r, 64);
+        if (wave_first + (uint32_t)r < nvis) {
+            if constexpr (kVec)
+                *reinterpret_cast<float4 *>(rows + r * kStride + 4 * c) =
+                    reinterpret_cast<const float4 *>(g.sh)[(size_t)ir * kUnits + c];
+            else
+                rows[r * kStride + c] = g.sh[(size_t)ir * kUnits + c];
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
     float gW[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gt[3] = {0, 0, 0};
-    if (k < nvis) {
-        const uint64_t i = vis[k];  // one view: the item is the Gaussian
+    if (live) {
         float gmu[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gop = 0.f;
         bool sh_written = false;
-        item_backward<DEG>(g, vt.v[0], w2c, 0, i, i, count[i], rec, screen, carry, gr.sh + (size_t)i * K * 3,
-                           sh_written, gmu, gls, gq, gop, gW, gt);
-        gr.means[3 * i] = gmu[0];
-        gr.means[3 * i + 1] = gmu[1];
-        gr.means[3 * i + 2] = gmu[2];
-        gr.log_scales[3 * i] = gls[0];
-        gr.log_scales[3 * i + 1] = gls[1];
-        gr.log_scales[3 * i + 2] = gls[2];
+        float *row = rows + lane * kStride;  // read, then overwritten with the SH gradient
+        item_backward<DEG>(g, vt.v[0], w2c, 0, i, i, count[i], rec, screen, carry, row, row, sh_written, gmu, gls,
+                           gq, gop, gW, gt);
+        gr.means[3 * (size_t)i] = gmu[0];
+        gr.means[3 * (size_t)i + 1] = gmu[1];
+        gr.means[3 * (size_t)i + 2] = gmu[2];
+        gr.log_scales[3 * (size_t)i] = gls[0];
+        gr.log_scales[3 * (size_t)i + 1] = gls[1];
+        gr.log_scales[3 * (size_t)i + 2] = gls[2];
         reinterpret_cast<float4 *>(gr.quats)[i] = make_float4(gq[0], gq[1], gq[2], gq[3]);
         gr.opacities[i] = gop;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll 4
+    for (int u = lane; u < 64 * kUnits; u += 64) {
+        const int r = u / kUnits, c = u - r * kUnits;
+        const uint32_t ir = (uint32_t)__shfl((int)i, r, 64);
+        if (wave_first + (uint32_t)r < nvis) {
+            if constexpr (kVec)
+                reinterpret_cast<float4 *>(gr.sh)[(size_t)ir * kUnits + c] =
+                    *reinterpret_cast<const float4 *>(rows + r * kStride + 4 * c);
+            else
+                gr.sh[(size_t)ir * kUnits + c] = rows[r * kStride + c];
+        }
     }
     pose_block_partial(gW, gt, red, pose_part, 0, pose_blocks);
 }
