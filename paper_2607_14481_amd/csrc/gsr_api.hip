@@ -308,8 +308,7 @@ int backward_impl(void *ws, size_t ws_bytes, const gsr_gaussians *g, int32_t n_v
                          zr, p.hdr, pers, persistent_ctas(cfg), st);
     mark.end(GSR_STAGE_COMPOSITE_BWD);
     mark.begin(GSR_STAGE_PROJECT_BWD);
-    launch_pair_reduce(vt, p.poff, p.chunk_item, (uint64_t)g->n, cap, p.item_box, p.tile_cut, p.partial,
-                       p.screen, p.carry, p.hdr, st);
+    launch_pair_reduce(p.poff, p.chunk_item, cap, p.item_box, p.tile_cut, p.partial, p.screen, p.carry, p.hdr, st);
     launch_project_bwd(*g, vt, world_to_cam, (uint64_t)g->n, p.rec, p.count, p.vis, p.hdr, p.screen, p.carry, *grads,
                        p.pose_part, L.pose_blocks, vt.total_tiles == 0, st);
     if (g->n == 0)  // no Gaussian wrote a partial: the pose gradient is zero
@@ -378,12 +377,12 @@ int gsr_rasterize_forward(void *ws, size_t ws_bytes, const gsr_gaussians *g, int
     launch_project_fwd(*g, vt, world_to_cam, n, p.rec, p.ulo, p.zkey, p.count, p.hdr, (uint32_t)cap, st);
     mark.end(GSR_STAGE_PROJECT);
     mark.begin(GSR_STAGE_COMPACT);
-    launch_visible_offsets(p.count, L.items, p.vis, p.poff, p.chunk_item, L.chunks, p.scan_tmp, p.hdr, st);
+    launch_visible_offsets(vt, n, p.count, p.rec, p.zkey, L.items, p.vis, p.poff, p.item_box, p.chunk_item, L.chunks,
+                           p.scan_tmp, p.hdr, st);
     mark.end(GSR_STAGE_COMPACT);
     mark.begin(GSR_STAGE_EMIT);
     const uint64_t pair_grid = cap;  // every kernel reads the pair count from the header
-    launch_emit_pairs(vt, p.vis, p.poff, p.chunk_item, n, pair_grid, p.rec, p.zkey, p.item_box, p.pkey[0], p.pval[0],
-                      p.hdr, st);
+    launch_emit_pairs(p.poff, p.chunk_item, p.item_box, pair_grid, p.pkey[0], p.pval[0], p.hdr, st);
     mark.end(GSR_STAGE_EMIT);
     mark.begin(GSR_STAGE_TILE_SORT);
     int pc = 0;

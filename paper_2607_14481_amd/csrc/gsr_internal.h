@@ -93,8 +93,8 @@ struct WsLayout {
 };
 
 constexpr int kScanThreads = 256;
-constexpr int kScanItems = 8;
-constexpr int kScanTile = kScanThreads * kScanItems;     // 2048
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanThreads * kScanItems;     // 1024
 constexpr int kSortThreads = 256;
 constexpr int kSortTile = 4096;                           // elements per sort block
 constexpr int kGroupSortMax = 4096;                       // longest list one workgroup sorts in registers
@@ -123,10 +123,12 @@ void launch_project_fwd(const gsr_gaussians &g, const ViewTable &vt, const float
                         hipStream_t st);
 
 // Exclusive scans / compaction / sorting / binning.
-// Visible items (ascending ids), their pair offsets and each chunk's first
-// item; header: visible and pair counts, overflow.  block_tmp: 2 u32 per
-// block of kScanTile items.
-void launch_visible_offsets(const uint32_t *count, uint64_t items, uint32_t *vis, uint32_t *poff,
+// Visible items (ascending ids), their pair offsets (also into each record's
+// r2.w), their box words (by visible index) and each chunk's first item;
+// header: visible and pair counts, overflow.  block_tmp: 2 u32 per block of
+// kScanTile items.
+void launch_visible_offsets(const ViewTable &vt, uint64_t n, const uint32_t *count, Rec *rec,
+                            const uint32_t *zkey, uint64_t items, uint32_t *vis, uint32_t *poff, uint4 *item_box,
                             uint32_t *chunk_item, uint64_t chunks_cap, uint32_t *block_tmp, WsHeader *hdr,
                             hipStream_t st);
 // Element count of a sort, read on the device: *n_dev, or (hdr set) the pair
@@ -164,8 +166,7 @@ void launch_long_merge(const uint2 *ranges, const uint32_t *long_tiles, const Ws
 void launch_expand_ranges(const uint2 *ranges, uint32_t total_tiles, uint32_t *pair_tiles, const WsHeader *hdr,
                           hipStream_t st);
 void launch_reset_queue(WsHeader *h, int which, hipStream_t st);
-void launch_emit_pairs(const ViewTable &vt, const uint32_t *vis, const uint32_t *poff, const uint32_t *chunk_item,
-                       uint64_t n, uint64_t pair_grid, Rec *rec, const uint32_t *zkey, uint4 *item_box,
+void launch_emit_pairs(const uint32_t *poff, const uint32_t *chunk_item, const uint4 *item_box, uint64_t pair_grid,
                        uint32_t *pkey, uint32_t *pval, const WsHeader *hdr, hipStream_t st);
 void launch_tile_ranges(const uint32_t *pkey, uint64_t cap, uint2 *ranges, uint32_t total_tiles,
                         uint32_t *long_tiles, WsHeader *hdr, hipStream_t st);
@@ -194,9 +195,9 @@ void launch_composite_bwd(const ViewTable &vt, const uint2 *ranges, const uint32
                           const float2 *ulo, const float *out_rgb, const Upstream &up, const uint32_t *pix_n,
                           const uint4 *tile_cut, float *partial, const ZeroRows &zr, WsHeader *hdr, bool persistent,
                           int persistent_ctas, hipStream_t st);
-void launch_pair_reduce(const ViewTable &vt, const uint32_t *poff, const uint32_t *chunk_item, uint64_t n,
-                        uint64_t pair_grid, const uint4 *item_box, const uint4 *tile_cut, const float *partial,
-                        float4 *screen, float *carry, const WsHeader *hdr, hipStream_t st);
+void launch_pair_reduce(const uint32_t *poff, const uint32_t *chunk_item, uint64_t pair_grid, const uint4 *item_box,
+                        const uint4 *tile_cut, const float *partial, float4 *screen, float *carry, const WsHeader *hdr,
+                        hipStream_t st);
 
 // zero_unseen: also write the zero rows of the Gaussians no view saw (when the
 // backward compositing did not).
@@ -269,6 +270,16 @@ __device__ __forceinline__ float wave_sum(float v) {
 
 __device__ __forceinline__ uint32_t pack_u16(uint32_t lo, uint32_t hi) { return lo | (hi << 16); }
 
+// The chip's 8 XCDs (each with its own L2) take a grid's workgroups in turn:
+// workgroup b runs on XCD b % 8.  This maps b to a work index so that each XCD
+// gets one contiguous range of [0, count) (a bijection for b < count), and
+// neighbouring work items, which touch neighbouring data, share an L2.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t count) {
+    const uint32_t q = count / kXcds, r = count % kXcds, x = b % kXcds;
+    return x * q + min(x, r) + b / kXcds;
+}
+
 
 // ---------------------------------------------------------------------------
 // The items whose pairs fall in one chunk of emission-order slots.  The k-th
@@ -288,14 +299,23 @@ struct ChunkItems {
     uint32_t zkey[kChunkPairs + 1];
 };
 
-// The chunk's item range; every thread of the workgroup calls it (it ends
-// with a barrier).  Boxes come from the records (`boxes` NULL, emission) or
-// from the per-index box words emission wrote (later passes: one coalesced
-// 16-byte load instead of gathers through the item id).
-__device__ __forceinline__ uint32_t load_chunk_items(const ViewTable &vt, const uint32_t *__restrict__ vis,
-                                                     const uint32_t *__restrict__ poff,
-                                                     const uint32_t *__restrict__ chunk_item, uint64_t n,
-                                                     const Rec *__restrict__ rec, const uint32_t *__restrict__ zkey,
+// Box word of a visible item: (first tile, box width | tiles per row << 16,
+// depth key, item), from the pixel box in its record's third word (r2).
+__device__ __forceinline__ uint4 item_box_word(const ViewTable &vt, uint64_t n, uint32_t item, const float4 &r2,
+                                               uint32_t z) {
+    const uint32_t bx = __float_as_uint(r2.y), by = __float_as_uint(r2.z);
+    const uint32_t tx0 = (bx & 0xffffu) / kTileW, tx1 = (bx >> 16) / kTileW;
+    const uint32_t ty0 = (by & 0xffffu) / (uint32_t)vt.tile_h;
+    const int v = (int)(item / n);
+    const uint32_t tiles_x = (uint32_t)vt.v[v].tiles_x;
+    return make_uint4(vt.v[v].tile_off + ty0 * tiles_x + tx0, (tx1 - tx0 + 1) | (tiles_x << 16), z, item);
+}
+
+// The chunk's item range, from the box words by visible index (one coalesced
+// 16-byte load per item); every thread of the workgroup calls it (it ends
+// with a barrier).
+__device__ __forceinline__ uint32_t load_chunk_items(const uint32_t *__restrict__ poff,
+                                                     const uint32_t *__restrict__ chunk_item,
                                                      const uint4 *__restrict__ boxes, uint32_t c, uint32_t m,
                                                      uint32_t nvis, ChunkItems &ci, uint32_t &i_lo) {
     const uint32_t c0 = c * kChunkPairs;
@@ -309,25 +329,11 @@ __device__ __forceinline__ uint32_t load_chunk_items(const ViewTable &vt, const 
             continue;
         }
         ci.p0[k] = poff[i];
-        if (boxes) {
-            const uint4 bw = boxes[i];
-            ci.tile0[k] = bw.x;
-            ci.wx[k] = bw.y;
-            ci.zkey[k] = bw.z;
-            ci.item[k] = bw.w;
-        } else {
-            const uint32_t item = vis[i];
-            const float4 r2 = rec[item].r2;
-            const uint32_t bx = __float_as_uint(r2.y), by = __float_as_uint(r2.z);
-            const uint32_t tx0 = (bx & 0xffffu) / kTileW, tx1 = (bx >> 16) / kTileW;
-            const uint32_t ty0 = (by & 0xffffu) / (uint32_t)vt.tile_h;
-            const int v = (int)(item / n);
-            const uint32_t tiles_x = (uint32_t)vt.v[v].tiles_x;
-            ci.tile0[k] = vt.v[v].tile_off + ty0 * tiles_x + tx0;
-            ci.wx[k] = (tx1 - tx0 + 1) | (tiles_x << 16);
-            ci.zkey[k] = zkey[item];
-            ci.item[k] = item;
-        }
+        const uint4 bw = boxes[i];
+        ci.tile0[k] = bw.x;
+        ci.wx[k] = bw.y;
+        ci.zkey[k] = bw.z;
+        ci.item[k] = bw.w;
     }
     __syncthreads();
     return nloc;

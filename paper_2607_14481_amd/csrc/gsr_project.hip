@@ -315,8 +315,8 @@ __device__ __forceinline__ void write_item_sum(const ChunkItems &ci, uint32_t k,
     }
 }
 
-__global__ __launch_bounds__(kChunkThreads) void k_pair_reduce(ViewTable vt, const uint32_t *__restrict__ poff,
-                                                               const uint32_t *__restrict__ chunk_item, uint64_t n,
+__global__ __launch_bounds__(kChunkThreads) void k_pair_reduce(const uint32_t *__restrict__ poff,
+                                                               const uint32_t *__restrict__ chunk_item,
                                                                const uint4 *__restrict__ item_box,
                                                                const uint4 *__restrict__ tile_cut,
                                                                const float *__restrict__ partial,
@@ -338,8 +338,7 @@ __global__ __launch_bounds__(kChunkThreads) void k_pair_reduce(ViewTable vt, con
     // compositing: most of a dense scene's pairs, so their values are not read)
     const uint32_t pb = c0 + (uint32_t)tid * kChunkPerThread;
     uint32_t i_lo;
-    const uint32_t nloc =
-        load_chunk_items(vt, nullptr, poff, chunk_item, n, nullptr, nullptr, item_box, c, m, nvis, ci, i_lo);
+    const uint32_t nloc = load_chunk_items(poff, chunk_item, item_box, c, m, nvis, ci, i_lo);
     uint32_t key[kChunkPerThread];
     bool valid[kChunkPerThread];
 #pragma unroll
@@ -474,13 +473,13 @@ __global__ __launch_bounds__(kChunkThreads) void k_pair_reduce(ViewTable vt, con
     if (kl != kNoKey && kf_next != kl) write_item_sum(ci, kl, c0, cend, c, v, screen, carry);
 }
 
-void launch_pair_reduce(const ViewTable &vt, const uint32_t *poff, const uint32_t *chunk_item, uint64_t n,
-                        uint64_t pair_grid, const uint4 *item_box, const uint4 *tile_cut, const float *partial, float4 *screen, float *carry,
-                        const WsHeader *hdr, hipStream_t st) {
+void launch_pair_reduce(const uint32_t *poff, const uint32_t *chunk_item, uint64_t pair_grid, const uint4 *item_box,
+                        const uint4 *tile_cut, const float *partial, float4 *screen, float *carry, const WsHeader *hdr,
+                        hipStream_t st) {
     const uint64_t chunks = chunk_count(pair_grid);
     if (chunks == 0) return;
-    hipLaunchKernelGGL(k_pair_reduce, dim3((unsigned)chunks), dim3(kChunkThreads), 0, st, vt, poff, chunk_item,
-                       n, item_box, tile_cut, partial, screen, carry, hdr);
+    hipLaunchKernelGGL(k_pair_reduce, dim3((unsigned)chunks), dim3(kChunkThreads), 0, st, poff, chunk_item, item_box,
+                       tile_cut, partial, screen, carry, hdr);
 }
 
 // ---------------------------------------------------------------------------
@@ -526,7 +525,6 @@ __device__ __forceinline__ void item_backward(const gsr_gaussians &g, const View
                                               bool &sh_written, float (&gmu)[3], float (&gls)[3], float (&gq)[4],
                                               float &gop, float (&gW)[9], float (&gt)[3]) {
     constexpr int K = (DEG + 1) * (DEG + 1);
-    constexpr bool kVecSH = (3 * K) % 4 == 0;
     const float4 r0 = rec[item].r0, r1 = rec[item].r1;
     float S[kPartialStride];
     item_moments(screen, carry, item, __float_as_uint(rec[item].r2.w), cnt, S);

@@ -205,10 +205,14 @@ __global__ __launch_bounds__(1024) void k_vis_scan_blocks(uint32_t *__restrict__
     }
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_vis_apply(const uint32_t *__restrict__ count, uint64_t n,
+__global__ __launch_bounds__(kScanThreads) void k_vis_apply(ViewTable vt, uint64_t n_view,
+                                                            const uint32_t *__restrict__ count,
+                                                            Rec *__restrict__ rec,
+                                                            const uint32_t *__restrict__ zkey, uint64_t n,
                                                             const uint32_t *__restrict__ block_vis,
                                                             const uint32_t *__restrict__ block_pairs,
                                                             uint32_t *__restrict__ vis, uint32_t *__restrict__ poff,
+                                                            uint4 *__restrict__ item_box,
                                                             uint32_t *__restrict__ chunk_item, uint64_t chunks_cap) {
     __shared__ uint32_t lds[4];
     const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
@@ -219,14 +223,29 @@ __global__ __launch_bounds__(kScanThreads) void k_vis_apply(const uint32_t *__re
         nv += c[k] > 0u ? 1u : 0u;
         np = sat_add(np, c[k]);
     }
+    // the visible items' boxes and depth keys, all requested before the scans
+    // (the stores below into the same records would otherwise order each load
+    // after the previous item's store)
+    float4 r2[kScanItems];
+    uint32_t z[kScanItems];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (c[k] > 0u) {
+            r2[k] = rec[base + k].r2;
+            z[k] = zkey[base + k];
+        }
+    }
     uint32_t tv, tp;
     uint32_t kv = block_vis[blockIdx.x] + block_exclusive_scan(nv, lds, tv);
     uint32_t run = sat_add(block_pairs[blockIdx.x], block_exclusive_scan(np, lds, tp));
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         if (c[k] > 0u) {
-            vis[kv] = (uint32_t)(base + k);
+            const uint32_t item = (uint32_t)(base + k);
+            vis[kv] = item;
             poff[kv] = run;
+            item_box[kv] = item_box_word(vt, n_view, item, r2[k], z[k]);
+            rec[item].r2.w = __uint_as_float(run);  // the item's first pair, for the later passes
             // chunks whose first pair lies in [run, run + c)
             const uint32_t end = sat_add(run, c[k]);
             for (uint64_t ch = chunk_count(run); ch < chunks_cap && ch * kChunkPairs < end; ++ch)
@@ -237,7 +256,8 @@ __global__ __launch_bounds__(kScanThreads) void k_vis_apply(const uint32_t *__re
     }
 }
 
-void launch_visible_offsets(const uint32_t *count, uint64_t items, uint32_t *vis, uint32_t *poff,
+void launch_visible_offsets(const ViewTable &vt, uint64_t n, const uint32_t *count, Rec *rec,
+                            const uint32_t *zkey, uint64_t items, uint32_t *vis, uint32_t *poff, uint4 *item_box,
                             uint32_t *chunk_item, uint64_t chunks_cap, uint32_t *block_tmp, WsHeader *hdr,
                             hipStream_t st) {
     const uint32_t nb = (uint32_t)((items + kScanTile - 1) / kScanTile);
@@ -245,8 +265,8 @@ void launch_visible_offsets(const uint32_t *count, uint64_t items, uint32_t *vis
     uint32_t *bv = block_tmp, *bp = block_tmp + nb;
     hipLaunchKernelGGL(k_vis_reduce, dim3(nb), dim3(kScanThreads), 0, st, count, items, bv, bp);
     hipLaunchKernelGGL(k_vis_scan_blocks, dim3(1), dim3(1024), 0, st, bv, bp, nb, hdr);
-    hipLaunchKernelGGL(k_vis_apply, dim3(nb), dim3(kScanThreads), 0, st, count, items, bv, bp, vis, poff,
-                       chunk_item, chunks_cap);
+    hipLaunchKernelGGL(k_vis_apply, dim3(nb), dim3(kScanThreads), 0, st, vt, n, count, rec, zkey, items, bv, bp, vis,
+                       poff, item_box, chunk_item, chunks_cap);
 }
 
 // ---------------------------------------------------------------------------
@@ -349,9 +369,12 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
     __shared__ uint32_t lds[4];
     __shared__ uint32_t skey[TILE], sval[TILE];
     const uint64_t n = sc();
-    const uint64_t blk = (uint64_t)blockIdx.x * TILE;
-    if (blk >= n) return;
     const uint32_t nb = (uint32_t)((n + TILE - 1) / TILE);
+    if (blockIdx.x >= nb) return;
+    // neighbouring blocks write neighbouring parts of each digit's output
+    // range (often the same cache lines): keep them on one XCD
+    const uint32_t tb = xcd_contiguous(blockIdx.x, nb);
+    const uint64_t blk = (uint64_t)tb * TILE;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t t = threadIdx.x;
     const uint32_t m = (uint32_t)min((uint64_t)TILE, n - blk);
@@ -369,8 +392,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
         const bool used = t <= mask;
         const uint32_t tot = used ? digit_total[t] : 0u;
         const uint32_t ex = block_exclusive_scan(tot, lds, total);
-        const uint32_t mine = used ? hist[(size_t)t * hist_blocks + blockIdx.x] : 0u;
-        const uint32_t next = !used ? 0u : blockIdx.x + 1 < nb ? hist[(size_t)t * hist_blocks + blockIdx.x + 1] : tot;
+        const uint32_t mine = used ? hist[(size_t)t * hist_blocks + tb] : 0u;
+        const uint32_t next = !used ? 0u : tb + 1 < nb ? hist[(size_t)t * hist_blocks + tb + 1] : tot;
         gbase[t] = ex + mine;
         lbase[t] = block_exclusive_scan(next - mine, lds, total);
     }
@@ -462,16 +485,14 @@ void radix_sort_u32(uint32_t *keys[2], uint32_t *vals[2], SortCount sc, uint64_t
 // writes one chunk of 1024 consecutive pair slots, 4 per thread (16-byte
 // stores, so the writes are coalesced and equal per thread however the tile
 // counts are spread): the chunk's items are staged in LDS and each thread finds
-// its pairs' item by binary search there.  The chunk in which an item's pairs
-// start records its pair offset (in its record) and its box word (by visible
-// index) for the later passes.
+// its pairs' item by binary search there.  The items' box words come from the
+// compaction pass (by visible index: coalesced loads).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kChunkThreads) void k_emit(ViewTable vt, const uint32_t *__restrict__ vis,
-                                                        const uint32_t *__restrict__ poff,
-                                                        const uint32_t *__restrict__ chunk_item, uint64_t n,
-                                                        Rec *__restrict__ rec, const uint32_t *__restrict__ zkey,
-                                                        uint4 *__restrict__ item_box, uint32_t *__restrict__ pkey,
-                                                        uint32_t *__restrict__ pval, const WsHeader *__restrict__ hdr) {
+__global__ __launch_bounds__(kChunkThreads) void k_emit(const uint32_t *__restrict__ poff,
+                                                        const uint32_t *__restrict__ chunk_item,
+                                                        const uint4 *__restrict__ item_box,
+                                                        uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval,
+                                                        const WsHeader *__restrict__ hdr) {
     __shared__ ChunkItems ci;
     if (hdr->overflow) return;
     const uint32_t m = hdr->n_pairs, nvis = hdr->n_visible;
@@ -479,15 +500,7 @@ __global__ __launch_bounds__(kChunkThreads) void k_emit(ViewTable vt, const uint
     if (c0 >= m) return;  // uniform per workgroup
     const uint32_t cend = min(c0 + kChunkPairs, m);
     uint32_t i_lo;
-    const uint32_t nloc =
-        load_chunk_items(vt, vis, poff, chunk_item, n, rec, zkey, nullptr, blockIdx.x, m, nvis, ci, i_lo);
-    for (uint32_t k = threadIdx.x; k < nloc; k += kChunkThreads) {
-        const uint32_t p = ci.p0[k];
-        if (p >= c0 && p < cend) {
-            rec[ci.item[k]].r2.w = __uint_as_float(p);
-            item_box[i_lo + k] = make_uint4(ci.tile0[k], ci.wx[k], ci.zkey[k], ci.item[k]);
-        }
-    }
+    const uint32_t nloc = load_chunk_items(poff, chunk_item, item_box, blockIdx.x, m, nvis, ci, i_lo);
     const uint32_t pb = c0 + threadIdx.x * kChunkPerThread;
     if (pb >= cend) return;
     uint32_t key[kChunkPerThread], val[kChunkPerThread];
@@ -510,13 +523,12 @@ __global__ __launch_bounds__(kChunkThreads) void k_emit(ViewTable vt, const uint
     }
 }
 
-void launch_emit_pairs(const ViewTable &vt, const uint32_t *vis, const uint32_t *poff, const uint32_t *chunk_item,
-                       uint64_t n, uint64_t pair_grid, Rec *rec, const uint32_t *zkey, uint4 *item_box,
+void launch_emit_pairs(const uint32_t *poff, const uint32_t *chunk_item, const uint4 *item_box, uint64_t pair_grid,
                        uint32_t *pkey, uint32_t *pval, const WsHeader *hdr, hipStream_t st) {
     const uint64_t chunks = chunk_count(pair_grid);
     if (chunks == 0) return;
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)chunks), dim3(kChunkThreads), 0, st, vt, vis, poff, chunk_item, n, rec,
-                       zkey, item_box, pkey, pval, hdr);
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)chunks), dim3(kChunkThreads), 0, st, poff, chunk_item, item_box, pkey,
+                       pval, hdr);
 }
 
 // ---------------------------------------------------------------------------
@@ -855,7 +867,9 @@ __global__ __launch_bounds__(256) void k_tile_depth_sort(const uint2 *__restrict
         sort_list_regs<16, 4>(pval + off, n, zkey, lane, wave, xs, oh + off, ol + off);
         return;
     }
-    const uint32_t t = blockIdx.x;
+    // neighbouring tiles share most of their items (whose depth keys are
+    // gathered): keep them on one XCD
+    const uint32_t t = xcd_contiguous(blockIdx.x, total_tiles);
     const uint2 rg = ranges[t];
     const uint32_t len = rg.y - rg.x;
     uint32_t *list = pval + rg.x;
@@ -1000,38 +1014,78 @@ void launch_expand_ranges(const uint2 *ranges, uint32_t total_tiles, uint32_t *p
 }
 
 // ---------------------------------------------------------------------------
-// A5: per-tile [start, end) over the sorted pairs.  The thread at the first
-// pair of each tile (and one more at i = m) closes the previous tile, opens its
-// own, and marks the tiles in between empty, so no pre-clearing pass is needed.
+// A5: per-tile [start, end) over the sorted pairs.  Where the tile key changes
+// (and once more at i = m) the previous tile is closed, the new one opened, and
+// the tiles in between marked empty, so no pre-clearing pass is needed.  Each
+// thread takes kRangeRun consecutive pairs (16-byte loads).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t *__restrict__ pkey, uint2 *__restrict__ ranges,
-                                                     uint32_t total_tiles, uint32_t *__restrict__ long_tiles,
-                                                     WsHeader *__restrict__ hdr) {
-    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    const uint64_t m = hdr->overflow ? 0ull : (uint64_t)hdr->n_pairs;
-    if (i > m) return;
-    const int64_t t = i < m ? (int64_t)pkey[i] : (int64_t)total_tiles;
-    const int64_t prev = i > 0 ? (int64_t)pkey[i - 1] : -1;
-    if (i > 0 && prev == t) return;
+__device__ __forceinline__ void tile_boundary(const uint32_t *__restrict__ pkey, uint2 *__restrict__ ranges,
+                                              uint32_t *__restrict__ long_tiles, WsHeader *__restrict__ hdr,
+                                              uint64_t i, uint64_t m, int64_t prev, int64_t t) {
     for (int64_t u = prev + 1; u < t; ++u) ranges[u] = make_uint2((uint32_t)i, (uint32_t)i);
     if (i < m) ranges[t].x = (uint32_t)i;
-    if (i > 0) {
-        ranges[prev].y = (uint32_t)i;
-        // a list longer than kGroupSortMax: find where it starts (the keys are
-        // sorted) and register it for the multi-workgroup sort
-        if (i > (uint64_t)kGroupSortMax && pkey[i - kGroupSortMax - 1] == (uint32_t)prev) {
-            uint64_t lo = 0, hi = i - kGroupSortMax - 1;  // first position holding prev lies in [lo, hi]
-            while (lo < hi) {
-                const uint64_t mid = (lo + hi) >> 1;
-                if (pkey[mid] < (uint32_t)prev) lo = mid + 1;
-                else hi = mid;
-            }
-            const uint32_t len = (uint32_t)(i - lo);
-            const uint32_t k = atomicAdd(&hdr->n_long, 1u);
-            if (k < kMaxLongTiles) long_tiles[k] = (uint32_t)prev;
-            atomicAdd(&hdr->long_pairs, len);
-            atomicMax(&hdr->max_long, len);
+    if (i == 0) return;
+    ranges[prev].y = (uint32_t)i;
+    // a list longer than kGroupSortMax: find where it starts (the keys are
+    // sorted) and register it for the multi-workgroup sort
+    if (i > (uint64_t)kGroupSortMax && pkey[i - kGroupSortMax - 1] == (uint32_t)prev) {
+        uint64_t lo = 0, hi = i - kGroupSortMax - 1;  // first position holding prev lies in [lo, hi]
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (pkey[mid] < (uint32_t)prev) lo = mid + 1;
+            else hi = mid;
         }
+        const uint32_t len = (uint32_t)(i - lo);
+        const uint32_t k = atomicAdd(&hdr->n_long, 1u);
+        if (k < kMaxLongTiles) long_tiles[k] = (uint32_t)prev;
+        atomicAdd(&hdr->long_pairs, len);
+        atomicMax(&hdr->max_long, len);
+    }
+}
+
+constexpr int kRangeRun = 4;
+__global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t *__restrict__ pkey, uint64_t cap,
+                                                     uint2 *__restrict__ ranges, uint32_t total_tiles,
+                                                     uint32_t *__restrict__ long_tiles, WsHeader *__restrict__ hdr) {
+    const uint64_t i0 = ((uint64_t)blockIdx.x * 256 + threadIdx.x) * kRangeRun;
+    // a whole run inside the buffer is loaded while the pair count is still
+    // in flight (entries past the count are ignored below)
+    uint32_t k[kRangeRun];
+    const bool whole = i0 + kRangeRun <= cap;
+    if (whole) {
+#pragma unroll
+        for (int q = 0; q < kRangeRun / 4; ++q) {
+            const uint4 kk = *reinterpret_cast<const uint4 *>(pkey + i0 + 4 * q);
+            k[4 * q] = kk.x, k[4 * q + 1] = kk.y, k[4 * q + 2] = kk.z, k[4 * q + 3] = kk.w;
+        }
+    }
+    const uint32_t prev_key = i0 > 0 && i0 <= cap ? pkey[i0 - 1] : 0u;
+    const uint64_t m = hdr->overflow ? 0ull : (uint64_t)hdr->n_pairs;
+    if (i0 > m) return;
+    if (!whole || i0 + kRangeRun > m) {
+#pragma unroll
+        for (int j = 0; j < kRangeRun; ++j) k[j] = i0 + j < m ? pkey[i0 + j] : total_tiles;
+    }
+    // positions of this run where the tile changes (and i = m)
+    uint32_t edges = 0;
+    int64_t prev = i0 > 0 ? (int64_t)prev_key : -1;
+#pragma unroll
+    for (int j = 0; j < kRangeRun; ++j) {
+        const int64_t t = i0 + j <= m ? (int64_t)k[j] : prev;  // (k[j] = total_tiles at i = m)
+        edges |= (t != prev ? 1u : 0u) << j;
+        prev = t;
+    }
+    while (edges) {
+        const int j = __builtin_ctz(edges);
+        edges &= edges - 1;
+        // k[j] and the key before it, selected without indexing the array by j
+        int64_t t = 0, before = i0 > 0 ? (int64_t)prev_key : -1;
+#pragma unroll
+        for (int q = 0; q < kRangeRun; ++q) {
+            if (q == j) t = (int64_t)k[q];
+            if (q + 1 == j) before = (int64_t)k[q];
+        }
+        tile_boundary(pkey, ranges, long_tiles, hdr, i0 + j, m, before, t);
     }
 }
 
@@ -1068,7 +1122,8 @@ void launch_reset_queue(WsHeader *h, int which, hipStream_t st) {
 void launch_tile_ranges(const uint32_t *pkey, uint64_t cap, uint2 *ranges, uint32_t total_tiles,
                         uint32_t *long_tiles, WsHeader *hdr, hipStream_t st) {
     if (total_tiles == 0) return;
-    hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((cap + 1 + 255) / 256)), dim3(256), 0, st, pkey, ranges,
+    const uint64_t groups = cap / kRangeRun + 1;  // positions 0..cap, kRangeRun per thread
+    hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((groups + 255) / 256)), dim3(256), 0, st, pkey, cap, ranges,
                        total_tiles, long_tiles, hdr);
 }
 
