@@ -116,7 +116,7 @@ gsr::WsLayout make_layout(uint64_t n, const gsr::ViewTable &vt, uint64_t cap) {
     L.digit_total = take(4 * 256);
     L.ranges = take(8ull * vt.total_tiles);
     L.tile_cut = take(16ull * vt.total_tiles);
-    L.long_tiles = take(4ull * kMaxLongTiles);
+    L.long_tiles = take(4ull * (3 * kMaxLongTiles + 2));
     L.pix_T = take(4ull * vt.total_pixels);
     L.pix_n = take(4ull * vt.total_pixels);
     L.partial = take(4ull * kPartialStride * cap);
@@ -411,6 +411,7 @@ int gsr_rasterize_forward(void *ws, size_t ws_bytes, const gsr_gaussians *g, int
     const uint32_t chunk_wgs = passes > 0 ? (uint32_t)((long_pairs + kLongWindow - 1) / kLongWindow + n_long) : 0u;
     const uint32_t merge_wgs = passes > 0 ? (uint32_t)((long_pairs + kMergeWindow - 1) / kMergeWindow + n_long) : 0u;
     uint32_t *xh = p.pkey[pc ^ 1], *xl = p.pval[pc ^ 1], *yh = p.pkey[pc], *yl = p.pval[pc];
+    if (passes > 0) launch_long_windows(p.ranges, p.long_tiles, passes, p.hdr, st);
     launch_tile_depth_sort(p.ranges, vt.total_tiles, p.pval[pc], p.zkey, xh, xl, yh, yl, p.long_tiles, passes,
                            chunk_wgs, p.hdr, st);
     for (int q = 0; q < passes; ++q) {

@@ -82,7 +82,8 @@ struct WsLayout {
     size_t digit_total; // u32[256] radix digit totals
     size_t ranges;      // uint2[total_tiles]
     size_t tile_cut;    // uint4[total_tiles] (positions replayed, depth key and item of the first one not replayed)
-    size_t long_tiles;  // u32[kMaxLongTiles] tiles whose list is longer than kGroupSortMax (any order)
+    size_t long_tiles;  // u32[kMaxLongTiles] tiles whose list is longer than kGroupSortMax (any order), then
+                        // u32[2][kMaxLongTiles + 1] their first window of kLongWindow / kMergeWindow entries
     size_t pix_T;       // float[total_pixels] final transmittance
     size_t pix_n;       // u32[total_pixels] last contributor + 1
     size_t partial;     // float[cap * 9] per-pair moments of the pixel gradients
@@ -159,6 +160,11 @@ void launch_tile_depth_sort(const uint2 *ranges, uint32_t total_tiles, uint32_t 
                             hipStream_t st);
 // Merge pass p of long_passes over the long lists' runs (run length
 // kLongWindow << p); the last pass writes the item ids into pval.
+// Window offsets of the long lists the multi-workgroup path takes: first
+// window of each of kLongWindow entries (long_tiles + kMaxLongTiles) and of
+// kMergeWindow entries (after those), with the totals at index n_long.
+void launch_long_windows(const uint2 *ranges, uint32_t *long_tiles, int long_passes, const WsHeader *hdr,
+                         hipStream_t st);
 void launch_long_merge(const uint2 *ranges, const uint32_t *long_tiles, const WsHeader *hdr, int p, int long_passes,
                        const uint32_t *src_hi, const uint32_t *src_lo, uint32_t *dst_hi, uint32_t *dst_lo,
                        uint32_t *pval, uint32_t merge_wgs, hipStream_t st);

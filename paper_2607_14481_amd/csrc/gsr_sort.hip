@@ -816,29 +816,76 @@ __device__ void sort_list_global(uint32_t *__restrict__ list, uint32_t len, cons
 
 // Lists longer than kGroupSortMax, when the multi-workgroup path takes them:
 // every listed long tile of at most kLongWindow << passes entries (all of them
-// once they fit the list).  Window e of all their windows of `window` entries,
-// in list order, as (tile, window within it).
+// once they fit the list).  k_long_windows numbers their windows (of
+// kLongWindow entries for the run sort, of kMergeWindow outputs for the merge
+// passes) in list order once per forward; a workgroup then finds its window
+// by a binary search over those offsets.
 __device__ __forceinline__ bool long_path_on(const WsHeader *hdr, int passes) {
     return passes > 0 && passes <= kMaxLongPasses && hdr->n_long <= kMaxLongTiles;
 }
-__device__ __forceinline__ bool long_tile_window(const uint2 *__restrict__ ranges,
-                                                 const uint32_t *__restrict__ long_tiles, uint32_t n_long, int passes,
-                                                 uint32_t window, uint32_t e, uint32_t &tile, uint32_t &w) {
+
+__global__ __launch_bounds__(256) void k_long_windows(const uint2 *__restrict__ ranges,
+                                                      uint32_t *__restrict__ long_tiles, int passes,
+                                                      const WsHeader *__restrict__ hdr) {
+    constexpr int kPer = kMaxLongTiles / 256;
+    __shared__ uint32_t lds[4];
+    if (hdr->overflow || !long_path_on(hdr, passes)) return;  // uniform
+    const uint32_t n_long = hdr->n_long;
     const uint64_t cover = (uint64_t)kLongWindow << passes;
-    for (uint32_t k = 0; k < n_long; ++k) {
-        const uint32_t t = long_tiles[k];
-        const uint2 rg = ranges[t];
-        const uint32_t len = rg.y - rg.x;
-        if (len > cover) continue;
-        const uint32_t nw = (len + window - 1) / window;
-        if (e < nw) {
-            tile = t;
-            w = e;
-            return true;
+    uint32_t na[kPer], nm[kPer], sa = 0, sm = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const uint32_t k = threadIdx.x * kPer + j;
+        na[j] = nm[j] = 0;
+        if (k < n_long) {
+            const uint2 rg = ranges[long_tiles[k]];
+            const uint32_t len = rg.y - rg.x;
+            if ((uint64_t)len <= cover) {
+                na[j] = (len + kLongWindow - 1) / kLongWindow;
+                nm[j] = (len + kMergeWindow - 1) / kMergeWindow;
+            }
         }
-        e -= nw;
+        sa += na[j];
+        sm += nm[j];
     }
-    return false;
+    uint32_t ta, tm;
+    uint32_t ea = block_exclusive_scan(sa, lds, ta);
+    uint32_t em = block_exclusive_scan(sm, lds, tm);
+    uint32_t *wa = long_tiles + kMaxLongTiles, *wm = wa + kMaxLongTiles + 1;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const uint32_t k = threadIdx.x * kPer + j;
+        if (k < n_long) wa[k] = ea, wm[k] = em;
+        ea += na[j];
+        em += nm[j];
+    }
+    if (threadIdx.x == 0) wa[n_long] = ta, wm[n_long] = tm;
+}
+
+void launch_long_windows(const uint2 *ranges, uint32_t *long_tiles, int long_passes, const WsHeader *hdr,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_long_windows, dim3(1), dim3(256), 0, st, ranges, long_tiles, long_passes, hdr);
+}
+
+// Window e of all the long lists' windows (offsets `first`: one of the two
+// tables above) as (tile, window within its list); false past the last.
+__device__ __forceinline__ bool long_tile_window(const uint32_t *__restrict__ long_tiles,
+                                                 const uint32_t *__restrict__ first, uint32_t n_long, uint32_t e,
+                                                 uint32_t &tile, uint32_t &w) {
+    if (n_long == 0 || e >= first[n_long]) return false;
+    // the last list whose first window is at or before e (it has windows: the
+    // next offset, or the total, is above e)
+    uint32_t lo = 0, hi = n_long - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= e)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    tile = long_tiles[lo];
+    w = e - first[lo];
+    return true;
 }
 
 __global__ __launch_bounds__(256) void k_tile_depth_sort(const uint2 *__restrict__ ranges, uint32_t total_tiles,
@@ -858,7 +905,7 @@ __global__ __launch_bounds__(256) void k_tile_depth_sort(const uint2 *__restrict
         // a window of a long list, sorted into a run of the first merge pass's input
         if (!multi) return;
         uint32_t t, w;
-        if (!long_tile_window(ranges, long_tiles, hdr->n_long, passes, kLongWindow, blockIdx.x - total_tiles, t, w))
+        if (!long_tile_window(long_tiles, long_tiles + kMaxLongTiles, hdr->n_long, blockIdx.x - total_tiles, t, w))
             return;
         const uint2 rg = ranges[t];
         const uint32_t off = rg.x + w * kLongWindow;
@@ -867,9 +914,7 @@ __global__ __launch_bounds__(256) void k_tile_depth_sort(const uint2 *__restrict
         sort_list_regs<16, 4>(pval + off, n, zkey, lane, wave, xs, oh + off, ol + off);
         return;
     }
-    // neighbouring tiles share most of their items (whose depth keys are
-    // gathered): keep them on one XCD
-    const uint32_t t = xcd_contiguous(blockIdx.x, total_tiles);
+    const uint32_t t = blockIdx.x;
     const uint2 rg = ranges[t];
     const uint32_t len = rg.y - rg.x;
     uint32_t *list = pval + rg.x;
@@ -939,7 +984,7 @@ __global__ __launch_bounds__(256) void k_long_merge(const uint2 *__restrict__ ra
     __shared__ uint32_t s_split[2];
     if (hdr->overflow || !long_path_on(hdr, passes)) return;  // uniform
     uint32_t t, w;
-    if (!long_tile_window(ranges, long_tiles, hdr->n_long, passes, kMergeWindow, blockIdx.x, t, w)) return;
+    if (!long_tile_window(long_tiles, long_tiles + 2 * kMaxLongTiles + 1, hdr->n_long, blockIdx.x, t, w)) return;
     const uint2 rg = ranges[t];
     const uint32_t L = rg.y - rg.x;
     const uint32_t o0 = w * kMergeWindow, o1 = min(o0 + kMergeWindow, L);
