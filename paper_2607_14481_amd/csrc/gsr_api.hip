@@ -121,6 +121,7 @@ gsr::WsLayout make_layout(uint64_t n, const gsr::ViewTable &vt, uint64_t cap) {
     L.pix_n = take(4ull * vt.total_pixels);
     L.partial = take(4ull * kPartialStride * cap);
     L.pose_part = take(4ull * 12 * vt.n_views * L.pose_blocks);
+    L.view_seg = take(4ull * (GSR_MAX_VIEWS + 1));
     L.total = o;
     return L;
 }
@@ -151,7 +152,7 @@ struct Ptrs {
     uint4 *item_box;
     uint2 *ranges;
     uint4 *tile_cut;
-    uint32_t *long_tiles;
+    uint32_t *long_tiles, *view_seg;
     float *pix_T;
     uint32_t *pix_n;
     float *partial, *pose_part;
@@ -185,6 +186,7 @@ Ptrs carve(void *ws, const gsr::WsLayout &L) {
     p.pix_n = reinterpret_cast<uint32_t *>(b + L.pix_n);
     p.partial = reinterpret_cast<float *>(b + L.partial);
     p.pose_part = reinterpret_cast<float *>(b + L.pose_part);
+    p.view_seg = reinterpret_cast<uint32_t *>(b + L.view_seg);
     return p;
 }
 
@@ -310,7 +312,7 @@ int backward_impl(void *ws, size_t ws_bytes, const gsr_gaussians *g, int32_t n_v
     mark.begin(GSR_STAGE_PROJECT_BWD);
     launch_pair_reduce(p.poff, p.chunk_item, cap, p.item_box, p.tile_cut, p.partial, p.screen, p.carry, p.hdr, st);
     launch_project_bwd(*g, vt, world_to_cam, (uint64_t)g->n, p.rec, p.count, p.vis, p.hdr, p.screen, p.carry, *grads,
-                       p.pose_part, L.pose_blocks, vt.total_tiles == 0, st);
+                       p.pose_part, L.pose_blocks, p.view_seg, vt.total_tiles == 0, st);
     if (g->n == 0)  // no Gaussian wrote a partial: the pose gradient is zero
         launch_fill_u32(reinterpret_cast<uint32_t *>(p.pose_part), 0u, 12ull * vt.n_views * L.pose_blocks, st);
     launch_pose_finalize(vt, world_to_cam, p.pose_part, L.pose_blocks, dL_dworld_to_cam, dL_dtwist, st);

@@ -88,6 +88,7 @@ struct WsLayout {
     size_t pix_n;       // u32[total_pixels] last contributor + 1
     size_t partial;     // float[cap * 9] per-pair moments of the pixel gradients
     size_t pose_part;   // float[views * pose_blocks * 12]
+    size_t view_seg;    // u32[GSR_MAX_VIEWS + 1] first visible index of each view
     size_t total;
     uint64_t items, cap, chunks;
     uint32_t hist_blocks, pose_blocks;
@@ -206,11 +207,11 @@ void launch_pair_reduce(const uint32_t *poff, const uint32_t *chunk_item, uint64
                         hipStream_t st);
 
 // zero_unseen: also write the zero rows of the Gaussians no view saw (when the
-// backward compositing did not).
+// backward compositing did not).  seg: u32[GSR_MAX_VIEWS + 1] scratch.
 void launch_project_bwd(const gsr_gaussians &g, const ViewTable &vt, const float *w2c, uint64_t n,
                         const Rec *rec, const uint32_t *count, const uint32_t *vis, const WsHeader *hdr,
                         const float4 *screen, const float *carry, const gsr_gaussian_grads &gr, float *pose_part,
-                        uint32_t pose_blocks, bool zero_unseen, hipStream_t st);
+                        uint32_t pose_blocks, uint32_t *seg, bool zero_unseen, hipStream_t st);
 void launch_pose_finalize(const ViewTable &vt, const float *w2c, const float *pose_part, uint32_t pose_blocks,
                           float *dL_dw2c, float *dL_dtwist, hipStream_t st);
 

@@ -829,17 +829,20 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(
     gr.opacities[i] = gop;
 }
 
-// The same for a single view, over the visible-item list instead of over all
-// Gaussians: every thread of a block has a seen Gaussian (the list is dense),
-// where the per-block compaction above leaves two of every three threads idle
-// when a third of the Gaussians is seen.  Unseen rows were zeroed by the
-// backward compositing.
+// The same for one view, over its segment of the visible-item list instead of
+// over all Gaussians: every thread of a block has a seen Gaussian (the list is
+// dense), where the per-block compaction above leaves two of every three
+// threads idle when a third of the Gaussians is seen.  Several views run one
+// launch each, in view order: a Gaussian's gradient rows are stored by the
+// first view that sees it and added to by the later ones (the order of the
+// sums above), and rows no view sees were zeroed by the backward compositing.
+// seg (several views): first visible index of each view, and the total.
 template <int DEG>
 __global__ __launch_bounds__(kProjThreads) void k_project_bwd_vis(
-    gsr_gaussians g, ViewTable vt, const float *__restrict__ w2c, const uint32_t *__restrict__ vis,
-    const Rec *__restrict__ rec, const uint32_t *__restrict__ count, const WsHeader *__restrict__ hdr,
-    const float4 *__restrict__ screen, const float *__restrict__ carry, gsr_gaussian_grads gr,
-    float *__restrict__ pose_part, uint32_t pose_blocks) {
+    gsr_gaussians g, ViewTable vt, const float *__restrict__ w2c, uint64_t n, int v, const uint32_t *__restrict__ seg,
+    const uint32_t *__restrict__ vis, const Rec *__restrict__ rec, const uint32_t *__restrict__ count,
+    const WsHeader *__restrict__ hdr, const float4 *__restrict__ screen, const float *__restrict__ carry,
+    gsr_gaussian_grads gr, float *__restrict__ pose_part, uint32_t pose_blocks) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     constexpr bool kVec = (3 * K) % 4 == 0;
     constexpr int kUnit = kVec ? 4 : 1;              // floats per cooperative access
@@ -848,28 +851,33 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd_vis(
     __shared__ float red[4 * 12];
     __shared__ __align__(16) float s_sh[4][64 * kStride];
     const uint32_t nvis = hdr->overflow ? 0u : hdr->n_visible;
-    if (blockIdx.x * kProjThreads >= nvis) {  // uniform: no item, a zero partial
-        if (threadIdx.x < 12) pose_part[(size_t)threadIdx.x * pose_blocks + blockIdx.x] = 0.f;
+    const uint32_t lo = seg ? min(seg[v], nvis) : 0u, hi = seg ? min(seg[v + 1], nvis) : nvis;
+    if (lo + blockIdx.x * kProjThreads >= hi) {  // uniform: no item, a zero partial
+        if (threadIdx.x < 12) pose_part[((size_t)v * 12 + threadIdx.x) * pose_blocks + blockIdx.x] = 0.f;
         return;
     }
-    const uint32_t k = blockIdx.x * kProjThreads + threadIdx.x;
+    const uint32_t k = lo + blockIdx.x * kProjThreads + threadIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint32_t wave_first = blockIdx.x * kProjThreads + (uint32_t)wave * 64;
-    const bool live = k < nvis;
-    const uint32_t i = live ? vis[k] : 0u;  // one view: the item is the Gaussian
+    const uint32_t wave_first = lo + blockIdx.x * kProjThreads + (uint32_t)wave * 64;
+    const bool live = k < hi;
+    const uint64_t item = live ? vis[k] : (uint64_t)v * n;
+    const uint64_t i = item - (uint64_t)v * n;  // the Gaussian
+    // stored by this view (no earlier view saw the Gaussian) or added to
+    bool first = true;
+    for (int u = 0; u < v && live; ++u) first &= count[(uint64_t)u * n + i] == 0u;
     float *rows = s_sh[wave];
     // the wave's SH rows, staged through LDS with row-contiguous (coalesced)
     // accesses instead of one 3K-float row per lane
 #pragma unroll 4
     for (int u = lane; u < 64 * kUnits; u += 64) {
         const int r = u / kUnits, c = u - r * kUnits;
-        const uint32_t ir = (uint32_t)__shfl((int)i, r, 64);
-        if (wave_first + (uint32_t)r < nvis) {
+        const uint64_t ir = (uint64_t)__shfl((long long)i, r, 64);
+        if (wave_first + (uint32_t)r < hi) {
             if constexpr (kVec)
                 *reinterpret_cast<float4 *>(rows + r * kStride + 4 * c) =
-                    reinterpret_cast<const float4 *>(g.sh)[(size_t)ir * kUnits + c];
+                    reinterpret_cast<const float4 *>(g.sh)[ir * kUnits + c];
             else
-                rows[r * kStride + c] = g.sh[(size_t)ir * kUnits + c];
+                rows[r * kStride + c] = g.sh[ir * kUnits + c];
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -878,15 +886,22 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd_vis(
     if (live) {
         float gmu[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gop = 0.f;
         bool sh_written = false;
-        float *row = rows + lane * kStride;  // read, then overwritten with the SH gradient
-        item_backward<DEG>(g, vt.v[0], w2c, 0, i, i, count[i], rec, screen, carry, row, row, sh_written, gmu, gls,
-                           gq, gop, gW, gt);
-        gr.means[3 * (size_t)i] = gmu[0];
-        gr.means[3 * (size_t)i + 1] = gmu[1];
-        gr.means[3 * (size_t)i + 2] = gmu[2];
-        gr.log_scales[3 * (size_t)i] = gls[0];
-        gr.log_scales[3 * (size_t)i + 1] = gls[1];
-        gr.log_scales[3 * (size_t)i + 2] = gls[2];
+        float *row = rows + lane * kStride;  // read, then overwritten with this view's SH gradient
+        item_backward<DEG>(g, vt.v[v], w2c, v, i, item, count[item], rec, screen, carry, row, row, sh_written, gmu,
+                           gls, gq, gop, gW, gt);
+        if (!first) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) gmu[c] += gr.means[3 * i + c], gls[c] += gr.log_scales[3 * i + c];
+            const float4 q = reinterpret_cast<const float4 *>(gr.quats)[i];
+            gq[0] += q.x, gq[1] += q.y, gq[2] += q.z, gq[3] += q.w;
+            gop += gr.opacities[i];
+        }
+        gr.means[3 * i] = gmu[0];
+        gr.means[3 * i + 1] = gmu[1];
+        gr.means[3 * i + 2] = gmu[2];
+        gr.log_scales[3 * i] = gls[0];
+        gr.log_scales[3 * i + 1] = gls[1];
+        gr.log_scales[3 * i + 2] = gls[2];
         reinterpret_cast<float4 *>(gr.quats)[i] = make_float4(gq[0], gq[1], gq[2], gq[3]);
         gr.opacities[i] = gop;
     }
@@ -895,31 +910,67 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd_vis(
 #pragma unroll 4
     for (int u = lane; u < 64 * kUnits; u += 64) {
         const int r = u / kUnits, c = u - r * kUnits;
-        const uint32_t ir = (uint32_t)__shfl((int)i, r, 64);
-        if (wave_first + (uint32_t)r < nvis) {
-            if constexpr (kVec)
-                reinterpret_cast<float4 *>(gr.sh)[(size_t)ir * kUnits + c] =
-                    *reinterpret_cast<const float4 *>(rows + r * kStride + 4 * c);
-            else
-                gr.sh[(size_t)ir * kUnits + c] = rows[r * kStride + c];
+        const uint64_t ir = (uint64_t)__shfl((long long)i, r, 64);
+        const bool add = __shfl((int)!first, r, 64) != 0;
+        if (wave_first + (uint32_t)r < hi) {
+            if constexpr (kVec) {
+                float4 o = *reinterpret_cast<const float4 *>(rows + r * kStride + 4 * c);
+                float4 *dst = reinterpret_cast<float4 *>(gr.sh) + ir * kUnits + c;
+                if (add) {
+                    const float4 e = *dst;
+                    o.x += e.x, o.y += e.y, o.z += e.z, o.w += e.w;
+                }
+                *dst = o;
+            } else {
+                float o = rows[r * kStride + c];
+                if (add) o += gr.sh[ir * kUnits + c];
+                gr.sh[ir * kUnits + c] = o;
+            }
         }
     }
-    pose_block_partial(gW, gt, red, pose_part, 0, pose_blocks);
+    pose_block_partial(gW, gt, red, pose_part, v, pose_blocks);
+}
+
+// First visible index of each view (the list is in ascending item order and
+// item = view * n + Gaussian), and the visible count at index n_views; one
+// thread per entry.
+static_assert(GSR_MAX_VIEWS < 64, "one wave computes the view segments");
+__global__ void k_view_segments(const uint32_t *__restrict__ vis, uint64_t n, int n_views,
+                                const WsHeader *__restrict__ hdr, uint32_t *__restrict__ seg) {
+    const int v = threadIdx.x;
+    if (v > n_views) return;
+    const uint32_t nvis = hdr->overflow ? 0u : hdr->n_visible;
+    const uint64_t key = (uint64_t)v * n;
+    uint32_t a = 0, b = nvis;  // first index whose item is >= key
+    while (a < b) {
+        const uint32_t mid = (a + b) >> 1;
+        if ((uint64_t)vis[mid] < key)
+            a = mid + 1;
+        else
+            b = mid;
+    }
+    seg[v] = a;
 }
 
 void launch_project_bwd(const gsr_gaussians &g, const ViewTable &vt, const float *w2c, uint64_t n, const Rec *rec,
                         const uint32_t *count, const uint32_t *vis, const WsHeader *hdr, const float4 *screen,
                         const float *carry, const gsr_gaussian_grads &gr, float *pose_part, uint32_t pose_blocks,
-                        bool zero_unseen, hipStream_t st) {
+                        uint32_t *seg, bool zero_unseen, hipStream_t st) {
     if (n == 0) return;
     const dim3 grid(pose_blocks);
     const int z = zero_unseen ? 1 : 0;
-    if (vt.n_views == 1 && !zero_unseen) {
-        switch (g.sh_degree) {
-            case 0: hipLaunchKernelGGL(k_project_bwd_vis<0>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, vis, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks); break;
-            case 1: hipLaunchKernelGGL(k_project_bwd_vis<1>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, vis, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks); break;
-            case 2: hipLaunchKernelGGL(k_project_bwd_vis<2>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, vis, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks); break;
-            default: hipLaunchKernelGGL(k_project_bwd_vis<3>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, vis, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks); break;
+    if (!zero_unseen) {
+        // one dense launch per view, in view order
+        if (vt.n_views > 1)
+            hipLaunchKernelGGL(k_view_segments, dim3(1), dim3(64), 0, st, vis, n, vt.n_views, hdr, seg);
+        const uint32_t *sg = vt.n_views > 1 ? seg : nullptr;
+        for (int v = 0; v < vt.n_views; ++v) {
+            switch (g.sh_degree) {
+                case 0: hipLaunchKernelGGL(k_project_bwd_vis<0>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, v, sg, vis, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks); break;
+                case 1: hipLaunchKernelGGL(k_project_bwd_vis<1>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, v, sg, vis, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks); break;
+                case 2: hipLaunchKernelGGL(k_project_bwd_vis<2>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, v, sg, vis, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks); break;
+                default: hipLaunchKernelGGL(k_project_bwd_vis<3>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, v, sg, vis, rec, count, hdr, screen, carry, gr, pose_part, pose_blocks); break;
+            }
         }
         return;
     }
