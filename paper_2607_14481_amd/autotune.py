@@ -54,8 +54,11 @@ class MultiViewStep:
             rgb, ws = rast.forward(self.params, w2c, ws=self.ws[k] if keep_workspaces else None, out=self.out[k])
             if keep_workspaces:
                 self.ws[k], self.out[k] = ws, rgb
-            grad = torch.sign(rgb - tgt) / self.numel
-            grads, g_w2c, _ = rast.backward(ws, self.params, w2c, (0.0, 0.0, 0.0), rgb, grad)
+            if len(self.groups) == 1:  # the call's own mean absolute error is the step's loss
+                grads, g_w2c, _ = rast.backward_l1(ws, self.params, w2c, (0.0, 0.0, 0.0), rgb, tgt)
+            else:
+                grad = torch.sign(rgb - tgt) / self.numel
+                grads, g_w2c, _ = rast.backward(ws, self.params, w2c, (0.0, 0.0, 0.0), rgb, grad)
             total = grads if total is None else [a + b for a, b in zip(total, grads)]
             pose.append(g_w2c)
         return total, torch.cat(pose)

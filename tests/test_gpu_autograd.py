@@ -225,3 +225,45 @@ def test_l1_backward_matches_explicit_upstream(multi):
         assert torch.equal(x, y)
     log(f"l1 backward (multi={multi}): bit-identical; |dmeans| {float(ga[0].abs().max()):.3e}")
 
+
+
+def test_multi_view_step_same_for_every_grouping():
+    """The batched step's loss is the mean absolute error over all views'
+    pixels: all views in one call (upstream formed inside the library) and one
+    view per call (upstream formed by torch, gradients summed) agree, and
+    their gradient matches the oracle's for the same upstream."""
+    import torch
+    from paper_2607_14481_amd.autotune import MultiViewStep
+    from paper_2607_14481_amd.rasterizer import GaussianRasterizer
+    wl = S.multi_view_ring(seed=6, n=12_000, n_views=3)
+    sc = wl.scene
+    sizes = [(144, 96), (96, 80), (200, 120)]
+    cams = [S.pinhole(w, h, c.world_to_cam) for (w, h), c in zip(sizes, wl.cameras)]
+    params = _params(sc, requires_grad=False)
+    w2c = torch.tensor(np.stack([np.asarray(c.world_to_cam, np.float32) for c in cams]), device="cuda")
+    targets = []
+    for v, c in enumerate(cams):
+        r = GaussianRasterizer([c], sc.sh_degree)
+        tw = torch.tensor(S.perturbed_pose(c.world_to_cam, 70 + v)[None], device="cuda")
+        targets.append(r.forward(params, tw)[0].clone())
+    log("multi-view step, 3 views, n=12000: one call vs one call per view")
+    one, g_one = MultiViewStep(cams, sc.sh_degree, params, w2c, targets, views_per_launch=3)()
+    per, g_per = MultiViewStep(cams, sc.sh_degree, params, w2c, targets, views_per_launch=1)()
+    for k, a, b in zip(("means", "log_scales", "quats", "opacities", "sh"), one, per):
+        e = rel_err(a.cpu().numpy(), b.cpu().numpy())
+        log(f"  d{k}: rel diff {e:.2e}")
+        assert e <= 1e-5, k
+    assert rel_err(g_one.cpu().numpy(), g_per.cpu().numpy()) <= 1e-5
+    # the same upstream through the oracle
+    numel = sum(t.numel() for t in targets)
+    ups = []
+    for v, c in enumerate(cams):
+        r = GaussianRasterizer([c], sc.sh_degree)
+        rgb = r.forward(params, w2c[v:v + 1])[0]
+        g = (torch.sign(rgb - targets[v]) / numel).cpu().numpy().reshape(3, c.height, c.width)
+        ups.append(np.ascontiguousarray(g.transpose(1, 2, 0)).astype(np.float64))
+    outs, tot = O.render_views(sc, cams, dL_dimgs=ups)
+    for k, a in zip(("means", "log_scales", "quats", "opacities", "sh"), one):
+        e = rel_err(a.cpu().numpy(), tot[k])
+        log(f"  d{k} vs oracle: {e:.2e}")
+        assert e <= 1e-3, k
