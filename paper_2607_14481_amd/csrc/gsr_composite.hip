@@ -142,15 +142,19 @@ __device__ __forceinline__ uint32_t next_tile(bool persistent, uint32_t *queue, 
     return __shfl(t, 0, kWave);
 }
 
-// Exponent of alpha, e2 = -sigma log2e = a.z dx^2 + a.w dx dy + b.x dy^2, for
-// the pixel at (dx, dy) from the centre.  A lane's pixels share dx, so the dx
-// terms are formed once per Gaussian (RowQuad) and each row evaluates
-// (b.x dy + a.w dx) dy + a.z dx^2 by two fused multiply-adds.
+// Exponent of alpha before the clamp, ex = log2(opacity) - sigma log2e
+// = b.y + a.z dx^2 + a.w dx dy + b.x dy^2, for the pixel at (dx, dy) from the
+// centre.  A lane's pixels share dx, so the dx terms and b.y are formed once
+// per Gaussian (RowQuad) and each row evaluates (b.x dy + a.w dx) dy +
+// (a.z dx^2 + b.y) by two fused multiply-adds.  The quadratic form's sign test
+// (sigma >= 0) is ex <= b.y.
 struct RowQuad {
-    float p, q;  // a.z dx^2, a.w dx
+    float p, q;  // a.z dx^2 + b.y, a.w dx
 };
-__device__ __forceinline__ RowQuad row_quad(const float4 &a, float dx) { return RowQuad{a.z * dx * dx, a.w * dx}; }
-__device__ __forceinline__ float neg_sigma_log2e(const RowQuad &rq, const float4 &b, float dy) {
+__device__ __forceinline__ RowQuad row_quad(const float4 &a, const float4 &b, float dx) {
+    return RowQuad{fmaf(a.z * dx, dx, b.y), a.w * dx};
+}
+__device__ __forceinline__ float alpha_exponent(const RowQuad &rq, const float4 &b, float dy) {
     return fmaf(fmaf(b.x, dy, rq.q), dy, rq.p);
 }
 
@@ -216,16 +220,15 @@ __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uin
                 const uint32_t pos = b0 - rg.x + (uint32_t)j;
                 const float dx = a.x - pxl;
                 const uint32_t smask = slab_mask(d.y);
-                const RowQuad rq = row_quad(a, dx);
+                const RowQuad rq = row_quad(a, b, dx);
 #pragma unroll
                 for (int k = 0; k < RPL; ++k) {
                     if (!(smask & (1u << k))) continue;
                     const float dy = a.y - ((float)(ly + 4 * k) + 0.5f);
-                    const float e2 = neg_sigma_log2e(rq, b, dy);
-                    const float ex = e2 + b.y;
+                    const float ex = alpha_exponent(rq, b, dy);
                     if (__ballot(T[k] > 0.f && ex >= kLog2AlphaSkip) == 0ull) continue;
                     const float alpha = fminf(kAlphaMax, __builtin_amdgcn_exp2f(ex));
-                    const bool ok = e2 <= 0.f && alpha >= kAlphaMin;
+                    const bool ok = ex <= b.y && alpha >= kAlphaMin;
                     const float wa = alpha * T[k];
                     const float Tn = T[k] - wa;  // T (1 - alpha)
                     // a stopped pixel has Tn <= 0 < kTMin, so it never adds again
@@ -406,17 +409,16 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
                         const float4 a = sa[j], b = sb[j], d = sd[j];
                         dx = a.x - pxl;
                         const uint32_t smask = slab_mask(d.y);
-                        const RowQuad rq = row_quad(a, dx);
+                        const RowQuad rq = row_quad(a, b, dx);
 #pragma unroll
                         for (int k = 0; k < RPL; ++k) {
                             if (!(smask & (1u << k))) continue;
                             const float dy = a.y - ((float)(ly + 4 * k) + 0.5f);
-                            const float e2 = neg_sigma_log2e(rq, b, dy);
-                            const float ex = e2 + b.y;
+                            const float ex = alpha_exponent(rq, b, dy);
                             if (__ballot(pos < ncon[k] && ex >= kLog2AlphaSkip) == 0ull) continue;
                             const float araw = __builtin_amdgcn_exp2f(ex);
                             const float alpha = fminf(kAlphaMax, araw);
-                            const bool ok = pos < ncon[k] && e2 <= 0.f && alpha >= kAlphaMin;
+                            const bool ok = pos < ncon[k] && ex <= b.y && alpha >= kAlphaMin;
                             const float w = ok ? alpha * T[k] : 0.f;
                             a_c0 = fmaf(w, g0[k], a_c0);
                             a_c1 = fmaf(w, g1[k], a_c1);
