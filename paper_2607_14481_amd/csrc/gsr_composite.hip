@@ -146,8 +146,10 @@ __device__ __forceinline__ uint32_t next_tile(bool persistent, uint32_t *queue, 
 // = b.y + a.z dx^2 + a.w dx dy + b.x dy^2, for the pixel at (dx, dy) from the
 // centre.  A lane's pixels share dx, so the dx terms and b.y are formed once
 // per Gaussian (RowQuad) and each row evaluates (b.x dy + a.w dx) dy +
-// (a.z dx^2 + b.y) by two fused multiply-adds.  The quadratic form's sign test
-// (sigma >= 0) is ex <= b.y.
+// (a.z dx^2 + b.y) by two fused multiply-adds.  sigma is a positive definite
+// quadratic form (the conic inverts a covariance with the 0.3 I low-pass
+// added), so there is no sign test: an FP32 exponent above b.y is rounding
+// near the centre, where the exact sigma is >= 0 and the Gaussian counts.
 struct RowQuad {
     float p, q;  // a.z dx^2 + b.y, a.w dx
 };
@@ -228,12 +230,13 @@ __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uin
                     const float ex = alpha_exponent(rq, b, dy);
                     if (__ballot(T[k] > 0.f && ex >= kLog2AlphaSkip) == 0ull) continue;
                     const float alpha = fminf(kAlphaMax, __builtin_amdgcn_exp2f(ex));
-                    const bool ok = ex <= b.y && alpha >= kAlphaMin;
+                    const bool ok = alpha >= kAlphaMin;
                     const float wa = alpha * T[k];
                     const float Tn = T[k] - wa;  // T (1 - alpha)
                     // a stopped pixel has Tn <= 0 < kTMin, so it never adds again
-                    const bool stop = ok && Tn < kTMin;
-                    const bool add = ok && !stop;
+                    const bool low = Tn < kTMin;
+                    const bool stop = ok & low;
+                    const bool add = ok & !low;
                     const float w = add ? wa : 0.f;
                     C0[k] = fmaf(b.z, w, C0[k]);
                     C1[k] = fmaf(b.w, w, C1[k]);
@@ -418,7 +421,7 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
                             if (__ballot(pos < ncon[k] && ex >= kLog2AlphaSkip) == 0ull) continue;
                             const float araw = __builtin_amdgcn_exp2f(ex);
                             const float alpha = fminf(kAlphaMax, araw);
-                            const bool ok = pos < ncon[k] && ex <= b.y && alpha >= kAlphaMin;
+                            const bool ok = pos < ncon[k] && alpha >= kAlphaMin;
                             const float w = ok ? alpha * T[k] : 0.f;
                             a_c0 = fmaf(w, g0[k], a_c0);
                             a_c1 = fmaf(w, g1[k], a_c1);
