@@ -541,16 +541,16 @@ void launch_emit_pairs(const uint32_t *poff, const uint32_t *chunk_item, const u
 // at halving distances.  Lists are padded to a power of two with keys above
 // every real key, which the network leaves at the end.
 //
-// A workgroup of four waves takes four tiles.  A list of up to 1024 entries is
-// sorted by one wave, by a bucket pass (below) when the depths allow, else by
-// the network in registers: each lane holds
-// E (1..16) consecutive entries, so comparators closer than E are register
-// operations and the others pair lane l with lane l ^ m, fetched with DPP or
-// ds_swizzle (within 32 lanes) or ds_bpermute; a flip also mirrors the
-// register index.  Lists of 1025..4096 entries are sorted by all four waves
-// (16 entries per lane), exchanging through LDS only for the comparators that
-// cross waves (three steps).  Longer lists run the same network over global
-// memory, one comparator per thread and step.
+// A workgroup of four waves takes one tile.  A list of up to 1024 entries (most
+// tiles) is sorted by a bucket pass (below) when the depths allow, else by the
+// network in registers.  There each lane holds E (1..16) consecutive entries,
+// so comparators closer than E are register operations and the others pair
+// lane l with lane l ^ m, fetched with DPP or ds_swizzle (within 32 lanes) or
+// ds_bpermute, or, across waves, exchanged through LDS; a flip also mirrors
+// the register index.  Lists of 1025..4096 entries take the network with 16
+// entries per lane; longer lists run the multi-workgroup path (below) or, when
+// it is off, the same network over global memory, one comparator per thread
+// and step.
 // ---------------------------------------------------------------------------
 typedef unsigned long long u64;
 constexpr u64 kPadKey = ~0ull;
