@@ -325,26 +325,34 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *__r
     hist[(size_t)threadIdx.x * hist_blocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// One workgroup per digit: exclusive scan of hist[d][0..nb) in place.
+// One workgroup per digit: exclusive scan of hist[d][0..nb) in place, each
+// thread taking kScanRun consecutive blocks per sweep (one sweep up to 2048
+// blocks, 8M elements).
+constexpr int kScanRun = 8;
 template <int TILE>
 __global__ __launch_bounds__(256) void k_radix_scan(uint32_t *__restrict__ hist, uint32_t hist_blocks, SortCount sc,
                                                     uint32_t *__restrict__ digit_total) {
     __shared__ uint32_t lds[4];
-    __shared__ uint32_t carry;
     const uint64_t n = sc();
     const uint32_t nb = (uint32_t)((n + TILE - 1) / TILE);
     uint32_t *row = hist + (size_t)blockIdx.x * hist_blocks;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (uint32_t b0 = 0; b0 < nb; b0 += 256) {
-        const uint32_t b = b0 + threadIdx.x;
-        const uint32_t x = b < nb ? row[b] : 0u;
+    uint32_t carry = 0;
+    for (uint32_t b0 = 0; b0 < nb; b0 += 256 * kScanRun) {
+        const uint32_t bt = b0 + threadIdx.x * kScanRun;
+        uint32_t x[kScanRun], sum = 0;
+#pragma unroll
+        for (int j = 0; j < kScanRun; ++j) {
+            x[j] = bt + j < nb ? row[bt + j] : 0u;
+            sum += x[j];
+        }
         uint32_t total;
-        const uint32_t ex = block_exclusive_scan(x, lds, total);
-        if (b < nb) row[b] = carry + ex;
-        __syncthreads();
-        if (threadIdx.x == 0) carry += total;
-        __syncthreads();
+        uint32_t ex = carry + block_exclusive_scan(sum, lds, total);
+#pragma unroll
+        for (int j = 0; j < kScanRun; ++j) {
+            if (bt + j < nb) row[bt + j] = ex;
+            ex += x[j];
+        }
+        carry += total;
     }
     if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
 }
