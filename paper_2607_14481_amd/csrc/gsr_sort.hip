@@ -142,10 +142,13 @@ void launch_compact_flags(const uint8_t *flags, uint64_t n, uint32_t *out_idx, u
 // A2 in one reduce-then-scan over the items, with two values per item: visible
 // (tiles touched > 0) and its tile count.  An invisible item counts zero tiles,
 // so the pair offset of the k-th visible item is the prefix of the counts over
-// all items before it.  Phase 3 writes the k-th visible item's id and pair
-// offset and, for each chunk of kChunkPairs pair slots whose first pair the
-// item holds, k.  The totals are the visible and pair counts; the block-sum
-// scan takes the overflow decision (pairs > capacity) too.
+// all items before it.  Phase 1 sums each block of kScanTile items; phase 2
+// gives each block the sums of the blocks before it (each block adds them up
+// itself: at most a few thousand L2-resident values, no extra launch) and
+// writes the k-th visible item's id, pair offset and box word and, for each
+// chunk of kChunkPairs pair slots whose first pair the item holds, k.  The
+// last block writes the visible and pair counts and the overflow decision
+// (pairs > capacity).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kScanThreads) void k_vis_reduce(const uint32_t *__restrict__ count, uint64_t n,
                                                              uint32_t *__restrict__ block_vis,
@@ -168,43 +171,6 @@ __global__ __launch_bounds__(kScanThreads) void k_vis_reduce(const uint32_t *__r
     }
 }
 
-// Single workgroup: exclusive scans of both block-sum arrays in place.
-__global__ __launch_bounds__(1024) void k_vis_scan_blocks(uint32_t *__restrict__ block_vis,
-                                                          uint32_t *__restrict__ block_pairs, uint32_t nb,
-                                                          WsHeader *__restrict__ hdr) {
-    __shared__ uint32_t lds[2][16];
-    __shared__ uint32_t carry[2];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (threadIdx.x < 2) carry[threadIdx.x] = 0;
-    __syncthreads();
-    for (uint32_t base = 0; base < nb; base += 1024) {
-        const uint32_t i = base + threadIdx.x;
-        const uint32_t x0 = i < nb ? block_vis[i] : 0u, x1 = i < nb ? block_pairs[i] : 0u;
-        uint32_t inc0 = x0, inc1 = x1;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y0 = __shfl_up(inc0, o, 64), y1 = __shfl_up(inc1, o, 64);
-            if (lane >= o) inc0 += y0, inc1 = sat_add(inc1, y1);
-        }
-        if (lane == 63) lds[0][w] = inc0, lds[1][w] = inc1;
-        __syncthreads();
-        uint32_t before0 = carry[0], before1 = carry[1];
-        for (int k = 0; k < w; ++k) before0 += lds[0][k], before1 = sat_add(before1, lds[1][k]);
-        if (i < nb) {
-            block_vis[i] = before0 + (inc0 - x0);
-            block_pairs[i] = sat_add(before1, inc1 - x1);
-        }
-        __syncthreads();
-        if (threadIdx.x == 1023) carry[0] = before0 + inc0, carry[1] = sat_add(before1, inc1);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        hdr->n_visible = carry[0];
-        hdr->n_pairs = carry[1];
-        hdr->overflow = carry[1] > hdr->pair_capacity ? 1u : 0u;
-    }
-}
-
 __global__ __launch_bounds__(kScanThreads) void k_vis_apply(ViewTable vt, uint64_t n_view,
                                                             const uint32_t *__restrict__ count,
                                                             Rec *__restrict__ rec,
@@ -213,7 +179,8 @@ __global__ __launch_bounds__(kScanThreads) void k_vis_apply(ViewTable vt, uint64
                                                             const uint32_t *__restrict__ block_pairs,
                                                             uint32_t *__restrict__ vis, uint32_t *__restrict__ poff,
                                                             uint4 *__restrict__ item_box,
-                                                            uint32_t *__restrict__ chunk_item, uint64_t chunks_cap) {
+                                                            uint32_t *__restrict__ chunk_item, uint64_t chunks_cap,
+                                                            WsHeader *__restrict__ hdr) {
     __shared__ uint32_t lds[4];
     const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
     uint32_t c[kScanItems], nv = 0, np = 0;
@@ -235,9 +202,24 @@ __global__ __launch_bounds__(kScanThreads) void k_vis_apply(ViewTable vt, uint64
             z[k] = zkey[base + k];
         }
     }
+    // the sums of the blocks before this one
+    uint32_t bv = 0, bp = 0;
+    for (uint32_t j = threadIdx.x; j < blockIdx.x; j += kScanThreads) {
+        bv += block_vis[j];
+        bp = sat_add(bp, block_pairs[j]);
+    }
     uint32_t tv, tp;
-    uint32_t kv = block_vis[blockIdx.x] + block_exclusive_scan(nv, lds, tv);
-    uint32_t run = sat_add(block_pairs[blockIdx.x], block_exclusive_scan(np, lds, tp));
+    block_exclusive_scan(bv, lds, tv);
+    block_exclusive_scan(bp, lds, tp);
+    const uint32_t v0 = tv, p0 = tp;
+    uint32_t kv = v0 + block_exclusive_scan(nv, lds, tv);
+    uint32_t run = sat_add(p0, block_exclusive_scan(np, lds, tp));
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        const uint32_t pairs = sat_add(p0, tp);
+        hdr->n_visible = v0 + tv;
+        hdr->n_pairs = pairs;
+        hdr->overflow = pairs > hdr->pair_capacity ? 1u : 0u;
+    }
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         if (c[k] > 0u) {
@@ -264,9 +246,8 @@ void launch_visible_offsets(const ViewTable &vt, uint64_t n, const uint32_t *cou
     if (nb == 0) return;
     uint32_t *bv = block_tmp, *bp = block_tmp + nb;
     hipLaunchKernelGGL(k_vis_reduce, dim3(nb), dim3(kScanThreads), 0, st, count, items, bv, bp);
-    hipLaunchKernelGGL(k_vis_scan_blocks, dim3(1), dim3(1024), 0, st, bv, bp, nb, hdr);
     hipLaunchKernelGGL(k_vis_apply, dim3(nb), dim3(kScanThreads), 0, st, vt, n, count, rec, zkey, items, bv, bp, vis,
-                       poff, item_box, chunk_item, chunks_cap);
+                       poff, item_box, chunk_item, chunks_cap, hdr);
 }
 
 // ---------------------------------------------------------------------------
