@@ -213,9 +213,9 @@ class Server:
             rgb, _ = rast.forward(params, w2c, (0.0, 0.0, 0.0), ws=ws)
             job = Job(reqs, st, slot, torch.cuda.Event(), rast, ws, rgb, bytes=est)
             if reqs[0].kind == "optimise":
+                # L1 against the request's target, upstream formed inside the backward
                 target = self._target(reqs[0], rgb.numel())
-                grad = torch.sign(rgb - target) / rgb.numel()
-                job.grads, job.pose_grad, _ = rast.backward(ws, params, w2c, (0.0, 0.0, 0.0), rgb, grad)
+                job.grads, job.pose_grad, _ = rast.backward_l1(ws, params, w2c, (0.0, 0.0, 0.0), rgb, target)
             job.done.record(st)
         return job
 
