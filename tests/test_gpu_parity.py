@@ -235,6 +235,31 @@ def test_multi_view_mixed_resolutions():
     _compare_grads(gpu, tot, "ring summed")
 
 
+def test_many_views_with_an_empty_one():
+    """Seven views in one call (the projection backward runs once per view,
+    storing or adding each Gaussian's rows): one view looks away from the
+    scene and sees nothing, the others overlap in the Gaussians they see."""
+    wl = S.multi_view_ring(seed=8, n=6_000, n_views=6)
+    sc = wl.scene
+    sizes = [(72, 56), (96, 64), (48, 48), (120, 80), (64, 96), (80, 40)]
+    cams = [S.pinhole(w, h, c.world_to_cam) for (w, h), c in zip(sizes, wl.cameras)]
+    away = S.look_at([0.0, 0.0, 40.0], target=[0.0, 0.0, 80.0], up=[0.0, 1.0, 0.0]).astype(np.float32)
+    cams.insert(3, S.pinhole(64, 48, away))
+    up = _upstream(41, cams)
+    log("7 views (one sees nothing), n=6000 deg3")
+    gpu = gpu_render(sc, cams, bg=(0.0, 0.0, 0.0), upstream=up)
+    outs, tot = O.render_views(sc, cams, dL_dimgs=up)
+    assert outs[3]["n_contrib"].max() == 0
+    for v in range(len(cams)):
+        _compare_view(gpu["imgs"][v], outs[v], f"view {v}")
+        if v == 3:
+            assert np.all(gpu["w2c"][v] == 0.0) and np.all(gpu["twist"][v] == 0.0)
+        else:
+            assert rel_err(gpu["w2c"][v], outs[v]["w2c"]) <= GRAD_TOL
+            assert rel_err(gpu["twist"][v], outs[v]["twist"]) <= GRAD_TOL
+    _compare_grads(gpu, tot, "7 views summed")
+
+
 @pytest.mark.parametrize("tile_h", [4, 8, 32])
 def test_tile_shape_does_not_change_results(tile_h):
     wl = S.small_view(seed=3, n=2000, width=150, height=110, sh_degree=1)
