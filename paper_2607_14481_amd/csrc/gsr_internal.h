@@ -98,7 +98,7 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 4;
 constexpr int kScanTile = kScanThreads * kScanItems;     // 1024
 constexpr int kSortThreads = 256;
-constexpr int kSortTile = 4096;                           // elements per sort block
+constexpr int kSortTile = 3072;                           // elements per sort block
 constexpr int kGroupSortMax = 4096;                       // longest list one workgroup sorts in registers
 constexpr uint32_t kMaxLongTiles = 1024;                  // longer lists the multi-workgroup path takes
 constexpr uint32_t kLongWindow = 4096;                    // entries per sorted run of a long list

@@ -307,8 +307,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *__r
 }
 
 // One workgroup per digit: exclusive scan of hist[d][0..nb) in place, each
-// thread taking kScanRun consecutive blocks per sweep (one sweep up to 2048
-// blocks, 8M elements).
+// thread taking kScanRun consecutive blocks per sweep (one sweep covers 2048
+// blocks, 6.3M elements at 3072 per block).
 constexpr int kScanRun = 8;
 template <int TILE>
 __global__ __launch_bounds__(256) void k_radix_scan(uint32_t *__restrict__ hist, uint32_t hist_blocks, SortCount sc,
