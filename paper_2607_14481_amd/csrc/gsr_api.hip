@@ -116,6 +116,7 @@ gsr::WsLayout make_layout(uint64_t n, const gsr::ViewTable &vt, uint64_t cap) {
     L.digit_total = take(4 * 256);
     L.ranges = take(8ull * vt.total_tiles);
     L.tile_cut = take(16ull * vt.total_tiles);
+    L.tile_order = take(4ull * kCostBuckets * (1 + vt.total_tiles));
     L.long_tiles = take(4ull * (3 * kMaxLongTiles + 2));
     L.pix_T = take(4ull * vt.total_pixels);
     L.pix_n = take(4ull * vt.total_pixels);
@@ -152,6 +153,7 @@ struct Ptrs {
     uint4 *item_box;
     uint2 *ranges;
     uint4 *tile_cut;
+    uint32_t *tile_order;
     uint32_t *long_tiles, *view_seg;
     float *pix_T;
     uint32_t *pix_n;
@@ -178,6 +180,7 @@ Ptrs carve(void *ws, const gsr::WsLayout &L) {
     p.item_box = reinterpret_cast<uint4 *>(b + L.item_box);
     p.screen = reinterpret_cast<float4 *>(b + L.screen);
     p.tile_cut = reinterpret_cast<uint4 *>(b + L.tile_cut);
+    p.tile_order = reinterpret_cast<uint32_t *>(b + L.tile_order);
     p.long_tiles = reinterpret_cast<uint32_t *>(b + L.long_tiles);
     p.hist = reinterpret_cast<uint32_t *>(b + L.hist);
     p.digit_total = reinterpret_cast<uint32_t *>(b + L.digit_total);
@@ -306,7 +309,7 @@ int backward_impl(void *ws, size_t ws_bytes, const gsr_gaussians *g, int32_t n_v
     zr.per_tile = vt.total_tiles ? (zr.n + vt.total_tiles - 1) / vt.total_tiles : 0;
     Upstream up{dL_drgb, target_rgb, 0.f};
     if (target_rgb) up.l1_scale = 1.0f / (float)(3.0 * (double)vt.total_pixels);
-    launch_composite_bwd(vt, p.ranges, p.pval[pc], p.rec, p.ulo, out_rgb, up, p.pix_n, p.tile_cut, p.partial,
+    launch_composite_bwd(vt, p.ranges, p.pval[pc], p.rec, p.ulo, out_rgb, up, p.pix_n, p.tile_cut, p.tile_order, p.partial,
                          zr, p.hdr, pers, persistent_ctas(cfg), st);
     mark.end(GSR_STAGE_COMPOSITE_BWD);
     mark.begin(GSR_STAGE_PROJECT_BWD);
@@ -393,7 +396,7 @@ int gsr_rasterize_forward(void *ws, size_t ws_bytes, const gsr_gaussians *g, int
         radix_sort_u32(k2, v2, SortCount{nullptr, p.hdr}, pair_grid, 0, tile_bits(vt.total_tiles), p.hist,
                        L.hist_blocks, p.digit_total, pc, st);
     }
-    launch_tile_ranges(p.pkey[pc], pair_grid, p.ranges, vt.total_tiles, p.long_tiles, p.hdr, st);
+    launch_tile_ranges(p.pkey[pc], pair_grid, p.ranges, vt.total_tiles, p.long_tiles, p.tile_order, p.hdr, st);
     // lists longer than one workgroup sorts: runs of kLongWindow, then merge passes
     int passes = cfg ? std::max(0, std::min(cfg->long_list_passes, kMaxLongPasses)) : 0;
     uint64_t long_pairs = cap, n_long = kMaxLongTiles;
@@ -426,7 +429,8 @@ int gsr_rasterize_forward(void *ws, size_t ws_bytes, const gsr_gaussians *g, int
     const bool pers = (flags & GSR_FLAG_PERSISTENT) != 0;
     mark.begin(GSR_STAGE_COMPOSITE_FWD);
     launch_composite_fwd(vt, p.ranges, p.pval[pc], p.rec, p.ulo, p.zkey, bgc, out_rgb, out_T, p.pix_T, p.pix_n,
-                         p.tile_cut, p.hdr, pers, persistent_ctas(cfg), (flags & GSR_FLAG_STATS) != 0, st);
+                         p.tile_cut, p.tile_order, p.hdr, pers, persistent_ctas(cfg), (flags & GSR_FLAG_STATS) != 0,
+                         st);
     mark.end(GSR_STAGE_COMPOSITE_FWD);
     return check_hip(hipGetLastError(), "forward launch");
 }

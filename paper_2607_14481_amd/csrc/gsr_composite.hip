@@ -135,6 +135,38 @@ __device__ __forceinline__ uint32_t slab_mask(float packed) {
 // margin dwarfs the exponential's rounding).
 constexpr float kLog2AlphaSkip = -7.9943534f - 0.01f;  // log2(1/255) - 0.01
 
+// Bucket of a tile's replay count (its backward cost): 16 per octave,
+// floor(16 log2(n + 1)), the top bucket taking everything above 255.
+__device__ __forceinline__ uint32_t cost_bucket(uint32_t n) {
+    return min(kCostBuckets - 1, (uint32_t)(16.f * __log2f((float)n + 1.f)));
+}
+
+// The r-th tile of the backward's schedule: tiles in descending cost buckets
+// (any order within a bucket: tiles are independent, so results do not
+// depend on it), or tile r when the buckets do not hold every tile (a forward
+// that skipped compositing).  One whole wave calls it.
+__device__ __forceinline__ uint32_t tile_by_cost(const uint32_t *__restrict__ order, uint32_t total_tiles,
+                                                 uint32_t r) {
+    const int lane = threadIdx.x & 63;
+    static_assert(kCostBuckets == 2 * kWave, "two buckets per lane");
+    // lane l: buckets 127 - 2l and 126 - 2l (descending cost)
+    const uint32_t b0 = kCostBuckets - 1 - 2 * lane, c0 = order[b0], c1 = order[b0 - 1];
+    uint32_t incl = c0 + c1;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    if ((uint32_t)__shfl((int)incl, 63, 64) != total_tiles) return r;
+    const unsigned long long past = __ballot(r < incl);  // lanes whose buckets end beyond r
+    const int L = __ffsll((long long)past) - 1;
+    const uint32_t before = (uint32_t)__shfl((int)(incl - c0 - c1), L, 64);
+    const uint32_t cL0 = (uint32_t)__shfl((int)c0, L, 64);
+    const uint32_t k = r - before;
+    const uint32_t b = k < cL0 ? kCostBuckets - 1 - 2 * (uint32_t)L : kCostBuckets - 2 - 2 * (uint32_t)L;
+    return order[kCostBuckets + (size_t)b * total_tiles + (k < cL0 ? k : k - cL0)];
+}
+
 __device__ __forceinline__ uint32_t next_tile(bool persistent, uint32_t *queue, uint32_t first, uint32_t &iter) {
     if (!persistent) return iter++ == 0 ? first : 0xffffffffu;
     uint32_t t = 0;
@@ -170,7 +202,8 @@ __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uin
                                                          const uint32_t *__restrict__ zkey, float3 bg,
                                                          float *__restrict__ out_rgb, float *__restrict__ out_T,
                                                          float *__restrict__ pix_T, uint32_t *__restrict__ pix_n,
-                                                         uint4 *__restrict__ tile_cut, WsHeader *hdr, int persistent) {
+                                                         uint4 *__restrict__ tile_cut, uint32_t *__restrict__ tile_order,
+                                                         WsHeader *hdr, int persistent) {
     __shared__ float4 sa[kWave], sb[kWave], sd[kWave];
     const int lane = threadIdx.x;
     const int lx = lane & 15, ly = lane >> 4;
@@ -296,6 +329,10 @@ __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uin
             // entry it does not (above every key when it replays them all)
             const uint32_t item = nmax < len ? pval[rg.x + nmax] : 0xffffffffu;
             tile_cut[t] = make_uint4(nmax, nmax < len ? zkey[item] : 0xffffffffu, item, 0u);
+            // the backward's schedule: this tile in the bucket of its replay count
+            const uint32_t b = cost_bucket(nmax);
+            const uint32_t slot = atomicAdd(&tile_order[b], 1u);
+            tile_order[kCostBuckets + (size_t)b * vt.total_tiles + slot] = t;
         }
     }
 }
@@ -342,6 +379,7 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
                                                          const float *__restrict__ out_rgb, Upstream up,
                                                          const uint32_t *__restrict__ pix_n,
                                                          const uint4 *__restrict__ tile_cut,
+                                                         const uint32_t *__restrict__ tile_order,
                                                          float *__restrict__ partial, ZeroRows zr, WsHeader *hdr,
                                                          int persistent) {
     __shared__ float4 sa[kWave], sb[kWave], sd[kWave];
@@ -353,8 +391,9 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
     const int fq = lane / kPartialStride, fc = lane - fq * kPartialStride;
     uint32_t iter = 0;
     for (;;) {
-        const uint32_t t = next_tile(persistent != 0, &hdr->queue[1], blockIdx.x, iter);
-        if (t >= vt.total_tiles) break;
+        const uint32_t r = next_tile(persistent != 0, &hdr->queue[1], blockIdx.x, iter);
+        if (r >= vt.total_tiles) break;
+        const uint32_t t = tile_by_cost(tile_order, vt.total_tiles, r);  // heaviest tiles first
         zero_unseen_rows(zr, t, hdr->overflow != 0u, lane);
         const TileCtx c = tile_ctx(vt, t);
         const uint32_t px = c.ox + lx;
@@ -500,8 +539,8 @@ static int resident_ctas(Kernel kernel, int requested) {
 
 void launch_composite_fwd(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
                           const float2 *ulo, const uint32_t *zkey, float3 bg, float *out_rgb, float *out_T,
-                          float *pix_T, uint32_t *pix_n, uint4 *tile_cut, WsHeader *hdr, bool persistent,
-                          int persistent_ctas, bool stats, hipStream_t st) {
+                          float *pix_T, uint32_t *pix_n, uint4 *tile_cut, uint32_t *tile_order, WsHeader *hdr,
+                          bool persistent, int persistent_ctas, bool stats, hipStream_t st) {
     if (vt.total_tiles == 0) return;
     const int p = persistent ? 1 : 0;
 #define GSR_FWD(R, S)                                                                                               \
@@ -509,7 +548,7 @@ void launch_composite_fwd(const ViewTable &vt, const uint2 *ranges, const uint32
                        dim3(persistent ? (unsigned)resident_ctas(k_composite_fwd<R, S>, persistent_ctas)            \
                                        : vt.total_tiles),                                                           \
                        dim3(kWave), 0, st, vt, ranges, pval, rec, ulo, zkey, bg, out_rgb, out_T, pix_T, pix_n,      \
-                       tile_cut, hdr, p)
+                       tile_cut, tile_order, hdr, p)
 #define GSR_FWD_RPL(R) \
     if (stats) GSR_FWD(R, true); else GSR_FWD(R, false)
     switch (vt.tile_h) {
@@ -524,16 +563,16 @@ void launch_composite_fwd(const ViewTable &vt, const uint2 *ranges, const uint32
 
 void launch_composite_bwd(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
                           const float2 *ulo, const float *out_rgb, const Upstream &up, const uint32_t *pix_n,
-                          const uint4 *tile_cut, float *partial, const ZeroRows &zr, WsHeader *hdr, bool persistent,
-                          int persistent_ctas, hipStream_t st) {
+                          const uint4 *tile_cut, const uint32_t *tile_order, float *partial, const ZeroRows &zr,
+                          WsHeader *hdr, bool persistent, int persistent_ctas, hipStream_t st) {
     if (vt.total_tiles == 0) return;
     const int p = persistent ? 1 : 0;
 #define GSR_BWD(R)                                                                                                  \
     hipLaunchKernelGGL(k_composite_bwd<R>,                                                                          \
                        dim3(persistent ? (unsigned)resident_ctas(k_composite_bwd<R>, persistent_ctas)               \
                                        : vt.total_tiles),                                                           \
-                       dim3(kWave), 0, st, vt, ranges, pval, rec, ulo, out_rgb, up, pix_n, tile_cut, partial,       \
-                       zr, hdr, p)
+                       dim3(kWave), 0, st, vt, ranges, pval, rec, ulo, out_rgb, up, pix_n, tile_cut, tile_order,    \
+                       partial, zr, hdr, p)
     switch (vt.tile_h) {
         case 4: GSR_BWD(1); break;
         case 8: GSR_BWD(2); break;

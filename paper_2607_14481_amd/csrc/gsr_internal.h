@@ -82,6 +82,7 @@ struct WsLayout {
     size_t digit_total; // u32[256] radix digit totals
     size_t ranges;      // uint2[total_tiles]
     size_t tile_cut;    // uint4[total_tiles] (positions replayed, depth key and item of the first one not replayed)
+    size_t tile_order;  // u32[kCostBuckets] bucket counts, then u32[kCostBuckets][tiles] tile ids per bucket
     size_t long_tiles;  // u32[kMaxLongTiles] tiles whose list is longer than kGroupSortMax (any order), then
                         // u32[2][kMaxLongTiles + 1] their first window of kLongWindow / kMergeWindow entries
     size_t pix_T;       // float[total_pixels] final transmittance
@@ -108,6 +109,9 @@ constexpr int kProjThreads = 256;
 constexpr int kPartialStride = 9;                         // floats per pair gradient
 // Pairs are also processed in fixed chunks of consecutive emission-order
 // slots (A3 emission, A8 reduction): 256 threads x 4 pairs.
+// Backward tile schedule: tiles in descending buckets of their replay count
+// (16 buckets per octave), so that the heaviest start first.
+constexpr uint32_t kCostBuckets = 128;
 constexpr uint32_t kChunkPairs = 1024;
 constexpr uint32_t kChunkThreads = 256;
 constexpr uint32_t kChunkPerThread = kChunkPairs / kChunkThreads;
@@ -175,13 +179,14 @@ void launch_expand_ranges(const uint2 *ranges, uint32_t total_tiles, uint32_t *p
 void launch_reset_queue(WsHeader *h, int which, hipStream_t st);
 void launch_emit_pairs(const uint32_t *poff, const uint32_t *chunk_item, const uint4 *item_box, uint64_t pair_grid,
                        uint32_t *pkey, uint32_t *pval, const WsHeader *hdr, hipStream_t st);
+// Also clears the backward schedule's bucket counts (tile_order).
 void launch_tile_ranges(const uint32_t *pkey, uint64_t cap, uint2 *ranges, uint32_t total_tiles,
-                        uint32_t *long_tiles, WsHeader *hdr, hipStream_t st);
+                        uint32_t *long_tiles, uint32_t *tile_order, WsHeader *hdr, hipStream_t st);
 
 void launch_composite_fwd(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
                           const float2 *ulo, const uint32_t *zkey, float3 bg, float *out_rgb, float *out_T,
-                          float *pix_T, uint32_t *pix_n, uint4 *tile_cut, WsHeader *hdr, bool persistent,
-                          int persistent_ctas, bool stats, hipStream_t st);
+                          float *pix_T, uint32_t *pix_n, uint4 *tile_cut, uint32_t *tile_order, WsHeader *hdr,
+                          bool persistent, int persistent_ctas, bool stats, hipStream_t st);
 // Gradient rows of the Gaussians no view saw are zeroed by the backward
 // compositing (memory work hidden under its ALU work): tile t takes Gaussians
 // [t * per_tile, (t + 1) * per_tile).
@@ -200,8 +205,8 @@ struct Upstream {
 };
 void launch_composite_bwd(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
                           const float2 *ulo, const float *out_rgb, const Upstream &up, const uint32_t *pix_n,
-                          const uint4 *tile_cut, float *partial, const ZeroRows &zr, WsHeader *hdr, bool persistent,
-                          int persistent_ctas, hipStream_t st);
+                          const uint4 *tile_cut, const uint32_t *tile_order, float *partial, const ZeroRows &zr,
+                          WsHeader *hdr, bool persistent, int persistent_ctas, hipStream_t st);
 void launch_pair_reduce(const uint32_t *poff, const uint32_t *chunk_item, uint64_t pair_grid, const uint4 *item_box,
                         const uint4 *tile_cut, const float *partial, float4 *screen, float *carry, const WsHeader *hdr,
                         hipStream_t st);

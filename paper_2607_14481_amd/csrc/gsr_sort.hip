@@ -1080,7 +1080,9 @@ __device__ __forceinline__ void tile_boundary(const uint32_t *__restrict__ pkey,
 constexpr int kRangeRun = 4;
 __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t *__restrict__ pkey, uint64_t cap,
                                                      uint2 *__restrict__ ranges, uint32_t total_tiles,
-                                                     uint32_t *__restrict__ long_tiles, WsHeader *__restrict__ hdr) {
+                                                     uint32_t *__restrict__ long_tiles,
+                                                     uint32_t *__restrict__ tile_order, WsHeader *__restrict__ hdr) {
+    if (blockIdx.x == 0 && threadIdx.x < kCostBuckets) tile_order[threadIdx.x] = 0u;  // filled by the forward
     const uint64_t i0 = ((uint64_t)blockIdx.x * 256 + threadIdx.x) * kRangeRun;
     // a whole run inside the buffer is loaded while the pair count is still
     // in flight (entries past the count are ignored below)
@@ -1154,11 +1156,11 @@ void launch_reset_queue(WsHeader *h, int which, hipStream_t st) {
 }
 
 void launch_tile_ranges(const uint32_t *pkey, uint64_t cap, uint2 *ranges, uint32_t total_tiles,
-                        uint32_t *long_tiles, WsHeader *hdr, hipStream_t st) {
+                        uint32_t *long_tiles, uint32_t *tile_order, WsHeader *hdr, hipStream_t st) {
     if (total_tiles == 0) return;
     const uint64_t groups = cap / kRangeRun + 1;  // positions 0..cap, kRangeRun per thread
     hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((groups + 255) / 256)), dim3(256), 0, st, pkey, cap, ranges,
-                       total_tiles, long_tiles, hdr);
+                       total_tiles, long_tiles, tile_order, hdr);
 }
 
 }  // namespace gsr
