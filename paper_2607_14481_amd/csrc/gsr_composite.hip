@@ -7,9 +7,9 @@
 // back as broadcasts.  With a single wave per tile there is no cross-wave
 // synchronisation in the inner loop, and a row "slab" (the 16 x 4 pixels of
 // one k) is skipped as a whole when the Gaussian's alpha >= 1/255 box misses
-// it.  Both passes take every decision (box slab skip, sigma < 0, alpha <
-// 1/255, the stop) with the same instructions on the same values, so the
-// backward replays exactly the forward's contributors.  The per-pixel updates
+// it.  Both passes take every decision (slab skip, alpha < 1/255, the stop)
+// with the same instructions on the same values, so the backward replays
+// exactly the forward's contributors.  The per-pixel updates
 // are branch-free (selects), so the only branches are wave-uniform.
 //
 // Early stop.  Dense scenes saturate long before the end of a tile's list:
@@ -34,6 +34,11 @@
 // (63 values per row), after which lane r < 63 adds the 32 values of one
 // (Gaussian, moment) in a fixed order (no atomics, deterministic) and the
 // pair's slot in emission order is written once.
+//
+// Schedule.  The forward files every tile in a bucket of its replay count
+// (nmax), and the backward's workgroups take the tiles heaviest first: in
+// tile order the dense centre tiles, dispatched late, left a tail.  Which
+// workgroup takes which tile changes no result.
 #include "gsr_internal.h"
 
 namespace gsr {
