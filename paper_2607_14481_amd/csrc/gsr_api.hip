@@ -393,8 +393,9 @@ int gsr_rasterize_forward(void *ws, size_t ws_bytes, const gsr_gaussians *g, int
     int pc = 0;
     {
         uint32_t *k2[2] = {p.pkey[0], p.pkey[1]}, *v2[2] = {p.pval[0], p.pval[1]};
+        // unstable: the per-tile depth sort fixes the order within a tile
         radix_sort_u32(k2, v2, SortCount{nullptr, p.hdr}, pair_grid, 0, tile_bits(vt.total_tiles), p.hist,
-                       L.hist_blocks, p.digit_total, pc, st);
+                       L.hist_blocks, p.digit_total, pc, false, st);
     }
     launch_tile_ranges(p.pkey[pc], pair_grid, p.ranges, vt.total_tiles, p.long_tiles, p.tile_order, p.hdr, st);
     // lists longer than one workgroup sorts: runs of kLongWindow, then merge passes

@@ -107,11 +107,11 @@ constexpr uint32_t kMergeWindow = 2048;                   // outputs per workgro
 constexpr int kMaxLongPasses = 16;                        // merge passes at most (lists up to 2^28 entries)
 constexpr int kProjThreads = 256;
 constexpr int kPartialStride = 9;                         // floats per pair gradient
-// Pairs are also processed in fixed chunks of consecutive emission-order
-// slots (A3 emission, A8 reduction): 256 threads x 4 pairs.
 // Backward tile schedule: tiles in descending buckets of their replay count
 // (16 buckets per octave), so that the heaviest start first.
 constexpr uint32_t kCostBuckets = 128;
+// Pairs are also processed in fixed chunks of consecutive emission-order
+// slots (A3 emission, A8 reduction): 256 threads x 4 pairs.
 constexpr uint32_t kChunkPairs = 1024;
 constexpr uint32_t kChunkThreads = 256;
 constexpr uint32_t kChunkPerThread = kChunkPairs / kChunkThreads;
@@ -147,11 +147,13 @@ struct SortCount {
         return (uint64_t)*n_dev;
     }
 };
-// Stable LSD sort of (key, value) on bits [begin_bit, end_bit), 8 per pass,
+// LSD sort of (key, value) on bits [begin_bit, end_bit), at most 8 per pass,
 // ping-ponging between keys[cur]/keys[cur ^ 1]; `cur` ends at the result.
+// Stable when `stable`; otherwise equal keys come out in an unspecified order.
 void radix_sort_u32(uint32_t *keys[2], uint32_t *vals[2], SortCount sc, uint64_t n_cap, int begin_bit, int end_bit,
-                    uint32_t *hist, uint32_t hist_blocks, uint32_t *digit_total, int &cur, hipStream_t st);
-// Each tile's list (items in ascending id order after the stable tile sort)
+                    uint32_t *hist, uint32_t hist_blocks, uint32_t *digit_total, int &cur, bool stable,
+                    hipStream_t st);
+// Each tile's list (grouped by the tile sort, in no particular order)
 // sorted by (depth key, item).  Lists longer than kGroupSortMax: with
 // long_passes > 0 (and at most kMaxLongTiles of them), `chunk_wgs` extra
 // workgroups sort them in runs of kLongWindow into the key buffer the first

@@ -2,17 +2,18 @@
 //   A2 scans: visible-item compaction and per-item pair offsets (exclusive
 //      scans in u32 with saturating adds, reduce-then-scan, no spin waits)
 //   A3 emission: (tile, item) pairs, written in ascending item order
-//   A4 radix sort: stable LSD passes of 8 bits over (tile u32, item u32)
+//   A4 radix sort: LSD passes of up to 8 bits over (tile u32, item u32)
 //   A4c per-tile depth order: each tile's list sorted by (depth bits, item)
 //   A5 tile ranges: [start, end) of each tile in the sorted pairs
 //
 // Order of work.  The pairs must end up sorted by (tile, depth bits, item).
 // Rather than sorting 48-bit (tile, depth) keys over all M pairs (six 8-bit
-// passes over the pairs), the pairs are emitted in ascending item order, a
-// stable sort on the tile id alone (ceil(tile_bits / 8) passes, two at 1080p)
-// groups them by tile with each tile's list still in item order, and one
-// workgroup per tile sorts its short list by (depth bits, item) in LDS.  The
-// result is the (tile, depth, item) order exactly.
+// passes over the pairs), the pairs are emitted in ascending item order, an
+// LSD sort on the tile id alone (ceil(tile_bits / 8) passes, two at 1080p)
+// groups them by tile, and one workgroup per tile sorts its short list by
+// (depth bits, item) in LDS.  The result is the (tile, depth, item) order
+// exactly, whatever order a tile's list had before; so the first radix pass
+// need not keep equal digits in input order (only the later ones must).
 //
 // Every kernel reads its element count from the workspace header, so the
 // launch grid can be sized for a capacity and the call needs no host
@@ -254,7 +255,8 @@ void launch_visible_offsets(const ViewTable &vt, uint64_t n, const uint32_t *cou
 // A4: LSD radix sort, one 8-bit digit per pass.
 //   k_radix_hist    per-block digit histogram -> hist[digit][block]
 //   k_radix_scan    per digit: exclusive scan over blocks (in place) + total
-//   k_radix_scatter stable rank within the block (wave ballots), scatter
+//   k_radix_scatter rank within the block (wave ballots, stable; or LDS
+//                   atomics for a first pass that need not be), scatter
 // The element count is read on the device: either *n_dev or, for the pair
 // sort, 0 when the header flags an overflow.
 // ---------------------------------------------------------------------------
@@ -343,8 +345,11 @@ __global__ __launch_bounds__(256) void k_radix_scan(uint32_t *__restrict__ hist,
 // own running digit counts (ballot peers; no block barrier inside the loop).
 // One barrier later the waves' counts become offsets, the block's elements
 // are placed in LDS in digit order, and written out in contiguous runs per
-// digit (coalesced, instead of one random 4-byte write per element).
-template <int TILE>
+// digit (coalesced, instead of one random 4-byte write per element).  With
+// STABLE false (a first pass whose caller does not need equal keys kept in
+// input order) each element takes its rank from an LDS atomic on its wave's
+// digit count instead of the ballots.
+template <int TILE, bool STABLE>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *__restrict__ kin,
                                                                 const uint32_t *__restrict__ vin,
                                                                 uint32_t *__restrict__ kout,
@@ -395,6 +400,10 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
         const uint32_t li = (uint32_t)(w * SortShape<TILE>::kWaveSpan + r * 64 + lane);
         const bool ok = li < m;
         const uint32_t d = (key[r] >> shift) & mask;
+        if constexpr (!STABLE) {
+            pos[r] = ok ? atomicAdd(&wcnt[w][d], 1u) : 0u;
+            continue;
+        }
         const unsigned long long peers = digit_peers(ok, d, bits);
         const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
         const uint32_t before = ok ? wcnt[w][d] : 0u;
@@ -437,7 +446,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
 template <int TILE>
 static void radix_passes(uint32_t *keys[2], uint32_t *vals[2], SortCount sc, uint64_t n_cap, int begin_bit,
                          int end_bit, uint32_t *hist, uint32_t hist_blocks, uint32_t *digit_total, int &cur,
-                         hipStream_t st) {
+                         bool stable, hipStream_t st) {
     const uint32_t nb = (uint32_t)((n_cap + TILE - 1) / TILE);
     // as many 8-bit passes as the key needs, with the bits spread evenly over
     // them (13 bits: 7 + 6): fewer digits per pass means longer runs per digit
@@ -456,16 +465,25 @@ static void radix_passes(uint32_t *keys[2], uint32_t *vals[2], SortCount sc, uin
         hipLaunchKernelGGL(k_radix_hist<TILE>, dim3(nb), dim3(kSortThreads), 0, st, keys[cur], sc, shift, mask, hist,
                            hist_blocks);
         hipLaunchKernelGGL(k_radix_scan<TILE>, dim3(1u << bits), dim3(256), 0, st, hist, hist_blocks, sc, digit_total);
-        hipLaunchKernelGGL(k_radix_scatter<TILE>, dim3(nb), dim3(kSortThreads), 0, st, keys[cur], vals[cur],
-                           keys[cur ^ 1], vals[cur ^ 1], sc, shift, bits, hist, hist_blocks, digit_total);
+        // only the first pass may break ties: every later one keeps the order of the digits below
+        if (pass == 0 && !stable)
+            hipLaunchKernelGGL((k_radix_scatter<TILE, false>), dim3(nb), dim3(kSortThreads), 0, st, keys[cur],
+                               vals[cur], keys[cur ^ 1], vals[cur ^ 1], sc, shift, bits, hist, hist_blocks,
+                               digit_total);
+        else
+            hipLaunchKernelGGL((k_radix_scatter<TILE, true>), dim3(nb), dim3(kSortThreads), 0, st, keys[cur],
+                               vals[cur], keys[cur ^ 1], vals[cur ^ 1], sc, shift, bits, hist, hist_blocks,
+                               digit_total);
         cur ^= 1;
         shift += bits;
     }
 }
 
 void radix_sort_u32(uint32_t *keys[2], uint32_t *vals[2], SortCount sc, uint64_t n_cap, int begin_bit, int end_bit,
-                    uint32_t *hist, uint32_t hist_blocks, uint32_t *digit_total, int &cur, hipStream_t st) {
-    radix_passes<kSortTile>(keys, vals, sc, n_cap, begin_bit, end_bit, hist, hist_blocks, digit_total, cur, st);
+                    uint32_t *hist, uint32_t hist_blocks, uint32_t *digit_total, int &cur, bool stable,
+                    hipStream_t st) {
+    radix_passes<kSortTile>(keys, vals, sc, n_cap, begin_bit, end_bit, hist, hist_blocks, digit_total, cur, stable,
+                            st);
 }
 
 // ---------------------------------------------------------------------------
@@ -521,8 +539,8 @@ void launch_emit_pairs(const uint32_t *poff, const uint32_t *chunk_item, const u
 }
 
 // ---------------------------------------------------------------------------
-// A4c: per-tile depth order.  After the stable tile sort each tile's list holds
-// its items in ascending id order; it is sorted here by the 64-bit key
+// A4c: per-tile depth order.  After the tile sort each tile's list holds its
+// items in no particular order; it is sorted here by the 64-bit key
 // (depth key << 32 | item), the unique order of the compositing definition.
 //
 // The network is bitonic with every comparator oriented low-to-high: each
