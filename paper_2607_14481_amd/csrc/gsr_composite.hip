@@ -496,14 +496,14 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
                     s[6] = a_c0;
                     s[7] = a_c1;
                     s[8] = a_c2;
-                    // add the neighbouring lane (quad_perm [1, 0, 3, 2]); even lanes store the pair sum
+                    // add the neighbouring lane (quad_perm [1, 0, 3, 2]): both lanes of a pair
+                    // hold the same sum (a + b == b + a exactly) and store it to the same
+                    // place, so no lane is masked off and each move folds into its add
 #pragma unroll
                     for (int cc = 0; cc < kPartialStride; ++cc) s[cc] = dpp_add<0xB1, 0xf>(s[cc]);
-                    if ((lane & 1) == 0) {
 #pragma unroll
-                        for (int cc = 0; cc < kPartialStride; ++cc)
-                            red[(lane >> 1) * kRedStride + q * kPartialStride + cc] = s[cc];
-                    }
+                    for (int cc = 0; cc < kPartialStride; ++cc)
+                        red[(lane >> 1) * kRedStride + q * kPartialStride + cc] = s[cc];
                 }
                 __syncthreads();
                 if (lane < kRedCols && j0 + fq < cnt) {

@@ -261,8 +261,11 @@ void launch_sim3_relocate(float *means, float *quats, float *log_scales, uint64_
 // by `row_mask` (other rows add 0).
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float dpp_add(float v) {
-    if constexpr (ROW_MASK == 0xf)  // every lane reads a source lane: no "old" value needed, the move folds into the add
-        return v + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
+    // every lane reads a source lane of its row (the controls used here have
+    // no out-of-range source), so no "old" value is needed; with bound_ctrl
+    // set the compiler folds the move into the add (v_add_f32_dpp)
+    if constexpr (ROW_MASK == 0xf)
+        return v + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, true));
     else
         return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
 }
