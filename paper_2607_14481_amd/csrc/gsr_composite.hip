@@ -484,14 +484,15 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
                             a_sayy = fmaf(say, dy, a_sayy);
                         }
                     }
-                    // S_x S_y S_xx S_xy S_yy (moments of dL/dsigma = -sa), S_o, colour gradient
+                    // the moments of sa (= -dL/dsigma): sums of sa dx, sa dy, sa dx^2,
+                    // sa dx dy, sa dy^2 (the negated S_x .. S_yy of the projection
+                    // backward), then S_o = sum sa and the colour gradient
                     float s[kPartialStride];
-                    const float ndx = -dx;
-                    s[0] = ndx * a_sa;
-                    s[1] = -a_say;
-                    s[2] = ndx * dx * a_sa;
-                    s[3] = ndx * a_say;
-                    s[4] = -a_sayy;
+                    s[0] = dx * a_sa;
+                    s[1] = a_say;
+                    s[2] = dx * s[0];
+                    s[3] = dx * a_say;
+                    s[4] = a_sayy;
                     s[5] = a_sa;
                     s[6] = a_c0;
                     s[7] = a_c1;

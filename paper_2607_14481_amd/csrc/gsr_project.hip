@@ -492,7 +492,9 @@ void launch_pair_reduce(const uint32_t *poff, const uint32_t *chunk_item, uint64
 // with (dx, dy) = (u, v) - pixel, so dL/du = A S_x + B S_y,
 // dL/dv = B S_x + C S_y, dL/d(A, B, C) = (S_xx / 2, S_xy, S_yy / 2) and
 // dL/do = S_o / o, where S_x = sum w dx, S_xx = sum w dx^2, ... over the
-// item's pixels with w = dL/dsigma and S_o = sum alpha dL/dalpha.
+// item's pixels with w = dL/dsigma and S_o = sum alpha dL/dalpha.  The pair
+// moments hold S_x .. S_yy negated (sums of -w dx, ...: the compositing forms
+// them without a sign change per pair).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void item_moments(const float4 *__restrict__ screen, const float *__restrict__ carry,
                                              uint64_t item, uint32_t p0, uint32_t cnt, float S[kPartialStride]) {
@@ -528,8 +530,9 @@ __device__ __forceinline__ void item_backward(const gsr_gaussians &g, const View
     const float4 r0 = rec[item].r0, r1 = rec[item].r1;
     float S[kPartialStride];
     item_moments(screen, carry, item, __float_as_uint(rec[item].r2.w), cnt, S);
-    const float gu = fmaf(r0.z, S[0], r0.w * S[1]), gv = fmaf(r0.w, S[0], r1.x * S[1]);
-    const float gA = 0.5f * S[2], gB = S[3], gC = 0.5f * S[4], go = S[5] / r1.y;
+    // S[0..4] hold the moments of sa = -dL/dsigma: S_x = -S[0], ..., S_yy = -S[4]
+    const float gu = -fmaf(r0.z, S[0], r0.w * S[1]), gv = -fmaf(r0.w, S[0], r1.x * S[1]);
+    const float gA = -0.5f * S[2], gB = -S[3], gC = -0.5f * S[4], go = S[5] / r1.y;
     const float grgb[3] = {S[6], S[7], S[8]};
 
     float W[9], t[3];
