@@ -29,11 +29,13 @@
 // alpha dL/dalpha and of the colour gradient; they are linear in the per-pixel
 // terms, so the conversion to (u, v, conic, opacity) gradients happens once
 // per Gaussian after the reduction over its tiles.  Each lane sums its pixels'
-// terms in registers; neighbouring lanes are added with a DPP swap, and the
-// 32 lane-pair sums are transposed through LDS in groups of seven Gaussians
-// (63 values per row), after which lane r < 63 adds the 32 values of one
-// (Gaussian, moment) in a fixed order (no atomics, deterministic) and the
-// pair's slot in emission order is written once.
+// terms in registers; the lanes of each quad are added with two DPP swaps,
+// and the 16 quad sums are transposed through LDS in groups of seven
+// Gaussians (63 values per row), after which lane r < 63 adds the 16 values
+// of one (Gaussian, moment) in a fixed order (no atomics, deterministic) and
+// the pair's slot in emission order is written once.  (Quads rather than lane
+// pairs halve the transpose buffer, which had held the kernel to 3.5 waves
+// per SIMD.)
 //
 // Schedule.  The forward files every tile in a bucket of its replay count
 // (nmax), and the backward's workgroups take the tiles heaviest first: in
@@ -149,8 +151,10 @@ __device__ __forceinline__ uint32_t cost_bucket(uint32_t n) {
 // The r-th tile of the backward's schedule: tiles in descending cost buckets
 // (any order within a bucket: tiles are independent, so results do not
 // depend on it), or tile r when the buckets do not hold every tile (a forward
-// that skipped compositing).  One whole wave calls it.
-__device__ __forceinline__ uint32_t tile_by_cost(const uint32_t *__restrict__ order, uint32_t total_tiles,
+// that skipped compositing).  One whole wave calls it.  Not inlined: its
+// loop-invariant loads would otherwise be hoisted and held in registers
+// through the tile's loops (13 more VGPRs, one wave fewer per SIMD).
+__device__ __noinline__ uint32_t tile_by_cost(const uint32_t *__restrict__ order, uint32_t total_tiles,
                                                  uint32_t r) {
     const int lane = threadIdx.x & 63;
     static_assert(kCostBuckets == 2 * kWave, "two buckets per lane");
@@ -347,7 +351,7 @@ __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uin
 // ---------------------------------------------------------------------------
 constexpr int kGroup = 7;                          // Gaussians per LDS transpose
 constexpr int kRedCols = kGroup * kPartialStride;  // 63 values per row
-constexpr int kRedRows = kWave / 2;                // lane pairs are summed first
+constexpr int kRedRows = kWave / 4;                // lane quads are summed first
 constexpr int kRedStride = kRedCols + 2;           // odd row stride: conflict-free rows and columns
 
 // Zero gradient rows of the Gaussians of tile t's slice that no view saw, one
@@ -497,14 +501,16 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
                     s[6] = a_c0;
                     s[7] = a_c1;
                     s[8] = a_c2;
-                    // add the neighbouring lane (quad_perm [1, 0, 3, 2]): both lanes of a pair
-                    // hold the same sum (a + b == b + a exactly) and store it to the same
-                    // place, so no lane is masked off and each move folds into its add
-#pragma unroll
-                    for (int cc = 0; cc < kPartialStride; ++cc) s[cc] = dpp_add<0xB1, 0xf>(s[cc]);
+                    // add the lanes of each quad (quad_perm [1, 0, 3, 2], then [2, 3, 0, 1]):
+                    // all four lanes hold the same sum (each step adds a and b as b and a,
+                    // exactly equal) and store it to the same place, so no lane is masked
+                    // off and each move folds into its add
 #pragma unroll
                     for (int cc = 0; cc < kPartialStride; ++cc)
-                        red[(lane >> 1) * kRedStride + q * kPartialStride + cc] = s[cc];
+                        s[cc] = dpp_add<0x4E, 0xf>(dpp_add<0xB1, 0xf>(s[cc]));
+#pragma unroll
+                    for (int cc = 0; cc < kPartialStride; ++cc)
+                        red[(lane >> 2) * kRedStride + q * kPartialStride + cc] = s[cc];
                 }
                 __syncthreads();
                 if (lane < kRedCols && j0 + fq < cnt) {
