@@ -358,6 +358,64 @@ int gsr_hierarchy_cut(const gsr_gaussians *nodes, const int32_t *parent, const i
 int gsr_gather_gaussians(const gsr_gaussians *src, const int32_t *index, int64_t n_index,
                          const gsr_param_set *dst, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Local bundle adjustment (Sec. 4.3, "Local Bundle Adjustment" and "Solver
+ * efficiency"; appendix "Fast Bundle Adjustment"): keyframe poses, one shared
+ * focal length and a fixed set of landmarks, each seen by a fixed subset of
+ * the keyframes, refined by Levenberg-Marquardt steps solved through a dense
+ * Schur complement over the camera unknowns.  All arithmetic is FP64.
+ *
+ * Model: the observation of landmark j in keyframe i predicts
+ *   f (X / Z, Y / Z) + (cx, cy),  X = R_i p_j + t_i  (world-to-camera pose);
+ * residual = prediction - observation; cost = 1/2 sum |residual|^2.  A step
+ * solves (H + lambda diag H) delta = -g with H = J^T J, g = J^T r over the free
+ * poses (left twists exp(xi^) T, xi = (rho, phi), translation first), f and
+ * the landmarks, and is always taken.  Fixed keyframes (free_slot -1) enter
+ * the cost but never move.
+ * ------------------------------------------------------------------------ */
+
+/* Opaque solver plan: the problem's structure, uploaded into the caller's
+   workspace.  Host object, owned by the caller through gsr_ba_plan_destroy. */
+typedef struct gsr_ba_plan gsr_ba_plan;
+
+/* Device workspace bytes for a problem with n_cams keyframes of which n_free
+   are optimised (at most 20), n_landmarks landmarks (1 .. 2^24) and max_obs
+   observation slots per landmark (2 .. 8).  0 with gsr_last_error() set when a
+   size is out of range. */
+size_t gsr_ba_workspace_bytes(int32_t n_cams, int32_t n_free, int32_t n_landmarks, int32_t max_obs);
+
+/*
+ * Checks the structure and uploads it.  free_slot [n_cams] (host): the index of
+ * each optimised keyframe among the optimised ones (a one-to-one map onto
+ * 0 .. n_free-1), -1 for a fixed keyframe.  obs_cam [n_landmarks][max_obs]
+ * (host): the keyframes that see each landmark, valid entries first, -1 after;
+ * every landmark needs at least 2 distinct keyframes.  workspace: device
+ * memory of gsr_ba_workspace_bytes(...) bytes, 256-byte aligned; it must stay
+ * alive, and be used by no other call, while the plan is used.  Blocking:
+ * returns when the upload on `stream` has finished.  *plan receives the plan
+ * (NULL on error).  Fails with GSR_ERR_UNSUPPORTED when the device cannot hold
+ * the reduced system in one workgroup's LDS.
+ */
+int gsr_ba_plan_create(int32_t n_cams, const int32_t *free_slot, int32_t n_landmarks, int32_t max_obs,
+                       const int32_t *obs_cam, void *workspace, size_t workspace_bytes, void *stream, gsr_ba_plan **plan);
+
+/* Frees the host plan (not the workspace).  NULL is accepted. */
+int gsr_ba_plan_destroy(gsr_ba_plan *plan);
+
+/*
+ * Runs `iterations` steps on `stream` (asynchronous; no allocation, no host
+ * synchronisation, so a caller may capture it in a graph).  Device arrays,
+ * updated in place: poses [n_cams][3][4] (row-major R | t), focal [1],
+ * landmarks [n_landmarks][3].  obs_uv [n_landmarks][max_obs][2] (device): the
+ * observed pixel of each valid slot (unused slots are not read).  (cx, cy):
+ * principal point.  lambda >= 0: damping.  costs: NULL, or device
+ * [iterations + 1] receiving the cost before each step and after the last.
+ * Every observed point must stay in front of its camera (Z > 0).  Calls that
+ * share a plan must not overlap.
+ */
+int gsr_ba_solve(const gsr_ba_plan *plan, double *poses, double *focal, double cx, double cy, double *landmarks,
+                 const double *obs_uv, int32_t iterations, double lambda, double *costs, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,8 +5,10 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "gsr_internal.h"
 
@@ -724,6 +726,210 @@ int gsr_gather_gaussians(const gsr_gaussians *src, const int32_t *index, int64_t
         return fail(GSR_ERR_INVALID_ARGUMENT, "dst quats and sh must be 16-byte aligned");
     launch_gather_gaussians(*src, index, (uint64_t)n_index, *dst, static_cast<hipStream_t>(stream));
     return check_hip(hipGetLastError(), "gather launch");
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Local bundle adjustment.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct BaLayout {
+    size_t obs_rec, lm_rec, S, dc, obs_cam, free_slot, slot_cam, block_ab, block_off, pairs, total;
+};
+
+BaLayout ba_layout(int n_cams, int n_free, int K, int M) {
+    BaLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) & ~size_t(255);
+        return o;
+    };
+    const size_t D = 6 * (size_t)n_free + 1, nblk = (size_t)n_free * (n_free + 1) / 2;
+    const size_t max_pairs = (size_t)K * ((size_t)M + (size_t)M * (M - 1) / 2);
+    L.obs_rec = take((size_t)K * M * gsr::kBaRecStride * sizeof(double));
+    L.lm_rec = take((size_t)K * gsr::kBaLmStride * sizeof(double));
+    L.S = take((D * D + D) * sizeof(double));
+    L.dc = take(D * sizeof(double));
+    L.obs_cam = take((size_t)K * M * sizeof(int32_t));
+    L.free_slot = take((size_t)n_cams * sizeof(int32_t));
+    L.slot_cam = take((size_t)(n_free > 0 ? n_free : 1) * sizeof(int32_t));
+    L.block_ab = take((nblk > 0 ? nblk : 1) * sizeof(int2));
+    L.block_off = take((nblk + 1) * sizeof(uint32_t));
+    L.pairs = take((max_pairs > 0 ? max_pairs : 1) * sizeof(int2));
+    L.total = off;
+    return L;
+}
+
+bool ba_sizes_ok(int32_t n_cams, int32_t n_free, int32_t K, int32_t M) {
+    return n_cams >= 1 && n_cams <= 65535 && n_free >= 0 && n_free <= n_cams && n_free <= gsr::kBaMaxFree && K >= 1 &&
+           K <= (1 << 24) && M >= 2 && M <= gsr::kBaMaxObs;
+}
+
+}  // namespace
+
+struct gsr_ba_plan {
+    char *ws;
+    BaLayout L;
+    int n_cams, F, K, M, D, nblk;
+};
+
+extern "C" {
+
+size_t gsr_ba_workspace_bytes(int32_t n_cams, int32_t n_free, int32_t n_landmarks, int32_t max_obs) {
+    if (!ba_sizes_ok(n_cams, n_free, n_landmarks, max_obs)) {
+        fail(GSR_ERR_INVALID_ARGUMENT, "sizes outside n_cams 1..65535, n_free 0..min(n_cams, %d), n_landmarks 1..2^24, "
+                                       "max_obs 2..%d", gsr::kBaMaxFree, gsr::kBaMaxObs);
+        return 0;
+    }
+    return ba_layout(n_cams, n_free, n_landmarks, max_obs).total;
+}
+
+int gsr_ba_plan_create(int32_t n_cams, const int32_t *free_slot, int32_t n_landmarks, int32_t max_obs,
+                       const int32_t *obs_cam, void *workspace, size_t workspace_bytes, void *stream, gsr_ba_plan **plan) {
+    using namespace gsr;
+    if (!plan) return fail(GSR_ERR_INVALID_ARGUMENT, "plan is NULL");
+    *plan = nullptr;
+    if (!free_slot || !obs_cam || !workspace) return fail(GSR_ERR_INVALID_ARGUMENT, "a pointer is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) & 255u) return fail(GSR_ERR_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
+    if (n_cams < 1 || n_cams > 65535) return fail(GSR_ERR_INVALID_ARGUMENT, "n_cams=%d outside 1..65535", n_cams);
+    int F = 0;
+    for (int i = 0; i < n_cams; ++i) F += free_slot[i] >= 0;
+    if (F > kBaMaxFree) return fail(GSR_ERR_UNSUPPORTED, "%d free keyframes (at most %d)", F, kBaMaxFree);
+    if (!ba_sizes_ok(n_cams, F, n_landmarks, max_obs))
+        return fail(GSR_ERR_INVALID_ARGUMENT, "n_landmarks=%d or max_obs=%d out of range (1..2^24, 2..%d)", n_landmarks,
+                    max_obs, kBaMaxObs);
+    std::vector<int32_t> slot_cam(F > 0 ? F : 1, -1);
+    for (int i = 0; i < n_cams; ++i) {
+        const int s = free_slot[i];
+        if (s < -1 || s >= F || (s >= 0 && slot_cam[s] >= 0))
+            return fail(GSR_ERR_INVALID_ARGUMENT, "free_slot must map the free keyframes one-to-one onto 0..%d", F - 1);
+        if (s >= 0) slot_cam[s] = i;
+    }
+    const int K = n_landmarks, M = max_obs;
+    for (int j = 0; j < K; ++j) {
+        int cnt = 0;
+        for (int k = 0; k < M; ++k) {
+            const int c = obs_cam[(size_t)j * M + k];
+            if (c < 0) continue;
+            if (c >= n_cams || k != cnt)
+                return fail(GSR_ERR_INVALID_ARGUMENT, "landmark %d: keyframe indices must be in 0..%d and come first", j,
+                            n_cams - 1);
+            for (int q = 0; q < k; ++q)
+                if (obs_cam[(size_t)j * M + q] == c)
+                    return fail(GSR_ERR_INVALID_ARGUMENT, "landmark %d: keyframe %d observed twice", j, c);
+            ++cnt;
+        }
+        if (cnt < 2) return fail(GSR_ERR_INVALID_ARGUMENT, "landmark %d has %d observations (at least 2)", j, cnt);
+    }
+    const BaLayout L = ba_layout(n_cams, F, K, M);
+    if (workspace_bytes < L.total) return fail(GSR_ERR_WORKSPACE_TOO_SMALL, "workspace %zu < %zu bytes", workspace_bytes, L.total);
+    const int D = 6 * F + 1, nblk = F * (F + 1) / 2;
+    int dev = 0, lds_max = 0;
+    int rc = check_hip(hipGetDevice(&dev), "current device");
+    if (rc) return rc;
+    if ((rc = check_hip(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "LDS limit")))
+        return rc;
+    const size_t lds = ba_solve_lds_bytes(D);
+    if (lds > (size_t)lds_max) return fail(GSR_ERR_UNSUPPORTED, "reduced system needs %zu bytes of LDS (%d available)", lds, lds_max);
+    if ((rc = check_hip(ba_allow_lds(lds), "LDS attribute"))) return rc;
+    // observation-pair lists of the reduced system's blocks (a <= b), each in landmark order
+    std::vector<std::vector<int2>> lists((size_t)nblk);
+    auto block_of = [F](int a, int b) { return a * F - a * (a - 1) / 2 + (b - a); };
+    int slot[kBaMaxObs];
+    for (int j = 0; j < K; ++j) {
+        for (int k = 0; k < M; ++k) {
+            const int c = obs_cam[(size_t)j * M + k];
+            slot[k] = c >= 0 ? free_slot[c] : -1;
+        }
+        for (int k1 = 0; k1 < M; ++k1) {
+            if (slot[k1] < 0) continue;
+            const int o1 = j * M + k1;
+            lists[block_of(slot[k1], slot[k1])].push_back(make_int2(o1, o1));
+            for (int k2 = k1 + 1; k2 < M; ++k2) {
+                if (slot[k2] < 0) continue;
+                const int o2 = j * M + k2;
+                if (slot[k1] < slot[k2]) lists[block_of(slot[k1], slot[k2])].push_back(make_int2(o1, o2));
+                else lists[block_of(slot[k2], slot[k1])].push_back(make_int2(o2, o1));
+            }
+        }
+    }
+    std::vector<int2> block_ab(nblk > 0 ? nblk : 1), pairs;
+    std::vector<uint32_t> block_off(nblk + 1, 0);
+    for (int a = 0, b = 0; a < F; ++a)
+        for (int q = a; q < F; ++q, ++b) {
+            block_ab[b] = make_int2(a, q);
+            block_off[b] = (uint32_t)pairs.size();
+            pairs.insert(pairs.end(), lists[b].begin(), lists[b].end());
+        }
+    block_off[nblk] = (uint32_t)pairs.size();
+    if (pairs.empty()) pairs.push_back(make_int2(0, 0));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *ws = static_cast<char *>(workspace);
+    const struct {
+        size_t off;
+        const void *src;
+        size_t bytes;
+    } up[] = {{L.obs_cam, obs_cam, (size_t)K * M * 4},
+              {L.free_slot, free_slot, (size_t)n_cams * 4},
+              {L.slot_cam, slot_cam.data(), slot_cam.size() * 4},
+              {L.block_ab, block_ab.data(), block_ab.size() * sizeof(int2)},
+              {L.block_off, block_off.data(), block_off.size() * 4},
+              {L.pairs, pairs.data(), pairs.size() * sizeof(int2)}};
+    for (const auto &u : up)
+        if ((rc = check_hip(hipMemcpyAsync(ws + u.off, u.src, u.bytes, hipMemcpyHostToDevice, st), "structure upload")))
+            return rc;
+    if ((rc = check_hip(hipStreamSynchronize(st), "stream sync"))) return rc;
+    gsr_ba_plan *p = static_cast<gsr_ba_plan *>(std::malloc(sizeof(gsr_ba_plan)));
+    if (!p) return fail(GSR_ERR_CAPACITY, "out of host memory");
+    *p = gsr_ba_plan{ws, L, n_cams, F, K, M, D, nblk};
+    *plan = p;
+    return GSR_OK;
+}
+
+int gsr_ba_plan_destroy(gsr_ba_plan *plan) {
+    std::free(plan);
+    return GSR_OK;
+}
+
+int gsr_ba_solve(const gsr_ba_plan *plan, double *poses, double *focal, double cx, double cy, double *landmarks,
+                 const double *obs_uv, int32_t iterations, double lambda, double *costs, void *stream) {
+    using namespace gsr;
+    if (!plan) return fail(GSR_ERR_INVALID_ARGUMENT, "plan is NULL");
+    if (!poses || !focal || !landmarks || !obs_uv) return fail(GSR_ERR_INVALID_ARGUMENT, "a device pointer is NULL");
+    if (iterations < 0 || iterations > 1000000) return fail(GSR_ERR_INVALID_ARGUMENT, "iterations=%d outside 0..10^6", iterations);
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(GSR_ERR_INVALID_ARGUMENT, "lambda must be finite and >= 0");
+    if (!std::isfinite(cx) || !std::isfinite(cy)) return fail(GSR_ERR_INVALID_ARGUMENT, "principal point must be finite");
+    const BaLayout &L = plan->L;
+    char *ws = plan->ws;
+    BaArgs A{};
+    A.poses = poses;
+    A.focal = focal;
+    A.landmarks = landmarks;
+    A.obs_uv = obs_uv;
+    A.obs_cam = reinterpret_cast<const int32_t *>(ws + L.obs_cam);
+    A.free_slot = reinterpret_cast<const int32_t *>(ws + L.free_slot);
+    A.slot_cam = reinterpret_cast<const int32_t *>(ws + L.slot_cam);
+    A.block_ab = reinterpret_cast<const int2 *>(ws + L.block_ab);
+    A.pairs = reinterpret_cast<const int2 *>(ws + L.pairs);
+    A.block_off = reinterpret_cast<const uint32_t *>(ws + L.block_off);
+    A.obs_rec = reinterpret_cast<double *>(ws + L.obs_rec);
+    A.lm_rec = reinterpret_cast<double *>(ws + L.lm_rec);
+    A.S = reinterpret_cast<double *>(ws + L.S);
+    A.dc = reinterpret_cast<double *>(ws + L.dc);
+    A.costs = costs;
+    A.cx = cx;
+    A.cy = cy;
+    A.lambda = lambda;
+    A.K = plan->K;
+    A.M = plan->M;
+    A.F = plan->F;
+    A.D = plan->D;
+    A.nblk = plan->nblk;
+    launch_ba_iterations(A, iterations, static_cast<hipStream_t>(stream));
+    return check_hip(hipGetLastError(), "bundle adjustment launch");
 }
 
 }  // extern "C"

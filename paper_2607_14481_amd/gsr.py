@@ -30,7 +30,8 @@ EXPORTED = ("gsr_version", "gsr_status_string", "gsr_last_error", "gsr_workspace
             "gsr_rasterize_forward", "gsr_rasterize_backward", "gsr_rasterize_backward_l1", "gsr_query_pairs",
             "gsr_query_stats",
             "gsr_export_state", "gsr_adam_step", "gsr_pose_step", "gsr_sim3_relocate",
-            "gsr_hierarchy_cut_scratch_bytes", "gsr_hierarchy_cut", "gsr_gather_gaussians")
+            "gsr_hierarchy_cut_scratch_bytes", "gsr_hierarchy_cut", "gsr_gather_gaussians",
+            "gsr_ba_workspace_bytes", "gsr_ba_plan_create", "gsr_ba_plan_destroy", "gsr_ba_solve")
 
 
 class GsrError(RuntimeError):
@@ -137,6 +138,14 @@ def lib():
                                         sz, vp, C.POINTER(C.c_int64), vp]
         L.gsr_gather_gaussians.restype = C.c_int
         L.gsr_gather_gaussians.argtypes = [C.POINTER(gsr_gaussians), vp, C.c_int64, C.POINTER(gsr_param_set), vp]
+        L.gsr_ba_workspace_bytes.restype = sz
+        L.gsr_ba_workspace_bytes.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32]
+        L.gsr_ba_plan_create.restype = C.c_int
+        L.gsr_ba_plan_create.argtypes = [C.c_int32, vp, C.c_int32, C.c_int32, vp, vp, sz, vp, C.POINTER(vp)]
+        L.gsr_ba_plan_destroy.restype = C.c_int
+        L.gsr_ba_plan_destroy.argtypes = [vp]
+        L.gsr_ba_solve.restype = C.c_int
+        L.gsr_ba_solve.argtypes = [vp, vp, vp, C.c_double, C.c_double, vp, vp, C.c_int32, C.c_double, vp, vp]
         _lib = L
     return _lib
 
@@ -402,3 +411,60 @@ def gather_gaussians(src: Sequence[torch.Tensor], sh_degree: int, index: torch.T
     g = gaussians_struct(*src, sh_degree)
     _check(lib().gsr_gather_gaussians(C.byref(g), _ptr(index), m, C.byref(param_set(dst)), _stream_ptr(stream)))
     return dst
+
+
+# ----------------------------------------------------------------------------
+# local bundle adjustment
+# ----------------------------------------------------------------------------
+
+def ba_workspace_bytes(n_cams: int, n_free: int, n_landmarks: int, max_obs: int) -> int:
+    n = lib().gsr_ba_workspace_bytes(n_cams, n_free, n_landmarks, max_obs)
+    if n == 0:
+        raise GsrError(GSR_ERR_INVALID_ARGUMENT, last_error())
+    return n
+
+
+class BAPlan:
+    """The structure of one bundle-adjustment problem (which keyframes are
+    free, which keyframes see which landmark) uploaded into a device
+    workspace this object owns.  free_slot: int32 [n_cams]; obs_cam: int32
+    [n_landmarks, max_obs] (host arrays or CPU tensors)."""
+
+    def __init__(self, free_slot, obs_cam, device="cuda", stream=None):
+        fs = torch.as_tensor(free_slot, dtype=torch.int32).contiguous().cpu()
+        oc = torch.as_tensor(obs_cam, dtype=torch.int32).contiguous().cpu()
+        if oc.dim() != 2:
+            raise ValueError("obs_cam must be [n_landmarks, max_obs]")
+        self.n_cams, (self.n_landmarks, self.max_obs) = int(fs.numel()), oc.shape
+        self.n_free = int((fs >= 0).sum())
+        nbytes = ba_workspace_bytes(self.n_cams, self.n_free, self.n_landmarks, self.max_obs)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        handle = C.c_void_p()
+        _check(lib().gsr_ba_plan_create(self.n_cams, _ptr(fs), self.n_landmarks, self.max_obs, _ptr(oc),
+                                        _ptr(self.ws), nbytes, _stream_ptr(stream), C.byref(handle)))
+        self._handle = handle
+
+    def __del__(self):
+        h = getattr(self, "_handle", None)
+        if h is not None and _lib is not None:
+            _lib.gsr_ba_plan_destroy(h)
+            self._handle = None
+
+
+def ba_solve(plan: BAPlan, poses: torch.Tensor, focal: torch.Tensor, principal, landmarks: torch.Tensor,
+             obs_uv: torch.Tensor, iterations: int, lam: float, costs: Optional[torch.Tensor] = None, stream=None):
+    """`iterations` damped Gauss-Newton steps on the device tensors (float64,
+    contiguous, updated in place): poses [n_cams, 3, 4], focal [1],
+    landmarks [n_landmarks, 3]; obs_uv [n_landmarks, max_obs, 2]; costs
+    (optional) [iterations + 1] receives the cost before each step and after
+    the last."""
+    for name, t, shape in (("poses", poses, (plan.n_cams, 3, 4)), ("focal", focal, (1,)),
+                           ("landmarks", landmarks, (plan.n_landmarks, 3)),
+                           ("obs_uv", obs_uv, (plan.n_landmarks, plan.max_obs, 2))):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shape:
+            raise ValueError(f"{name} must be a contiguous float64 device tensor of shape {shape}")
+    if costs is not None and (costs.dtype != torch.float64 or not costs.is_cuda or costs.numel() < iterations + 1):
+        raise ValueError("costs must be a float64 device tensor of at least iterations + 1 entries")
+    _check(lib().gsr_ba_solve(plan._handle, _ptr(poses), _ptr(focal), float(principal[0]), float(principal[1]),
+                              _ptr(landmarks), _ptr(obs_uv), int(iterations), float(lam), _ptr(costs),
+                              _stream_ptr(stream)))

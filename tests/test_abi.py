@@ -57,3 +57,44 @@ def test_host_side_argument_checks():
     with pytest.raises(gsr.GsrError):
         gsr.workspace_bytes(10, [cam], 100, gsr.launch_config(tile_h=12))
     assert "tile_h" in gsr.last_error()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_bundle_adjustment_host_checks():
+    """Sizing and the structure checks of the plan run on the host before any
+    device call, so they work without a GPU."""
+    import numpy as np
+    from paper_2607_14481_amd import gsr
+    n1 = gsr.ba_workspace_bytes(20, 16, 10_000, 8)
+    n2 = gsr.ba_workspace_bytes(20, 16, 20_000, 8)
+    assert n2 > n1 > 0 and n1 % 256 == 0
+    for bad in ((20, 21, 100, 8), (20, 16, 0, 8), (20, 16, 100, 9), (20, 16, 100, 1), (0, 0, 100, 2)):
+        with pytest.raises(gsr.GsrError):
+            gsr.ba_workspace_bytes(*bad)
+    L = gsr.lib()
+    fake_ws = C.c_void_p(1 << 20)   # never dereferenced: every case fails its checks first
+
+    def create(free_slot, obs_cam, ws_bytes=1 << 40):
+        fs = np.ascontiguousarray(free_slot, np.int32)
+        oc = np.ascontiguousarray(obs_cam, np.int32)
+        h = C.c_void_p()
+        rc = L.gsr_ba_plan_create(len(fs), fs.ctypes.data_as(C.c_void_p), oc.shape[0], oc.shape[1],
+                                  oc.ctypes.data_as(C.c_void_p), fake_ws, ws_bytes, None, C.byref(h))
+        return rc, gsr.last_error(), h.value
+
+    ok_fs = [0, -1, 1, 2]
+    cases = [
+        (ok_fs, [[0, 0, -1], [1, 2, -1]], "twice"),            # a keyframe twice in one landmark
+        (ok_fs, [[0, -1, -1], [1, 2, 3]], "observations"),     # one observation only
+        (ok_fs, [[0, -1, 1], [1, 2, 3]], "come first"),        # a gap before a valid slot
+        (ok_fs, [[0, 4, -1], [1, 2, 3]], "keyframe indices"),  # keyframe out of range
+        ([0, 0, 1, 2], [[0, 1, -1], [1, 2, 3]], "one-to-one"),  # two keyframes in one slot
+        ([0, 5, 1, 2], [[0, 1, -1], [1, 2, 3]], "one-to-one"),  # slot out of range
+        (list(range(21)), [[0, 1, -1]], "free keyframes"),     # more free keyframes than supported
+    ]
+    for fs, oc, msg in cases:
+        rc, err, h = create(fs, oc)
+        assert rc != gsr.GSR_OK and h is None and msg in err, (fs, oc, err)
+    rc, err, _ = create(ok_fs, [[0, 1, -1], [1, 2, 3]], ws_bytes=1024)
+    assert rc == gsr.GSR_ERR_WORKSPACE_TOO_SMALL
+    assert L.gsr_ba_plan_destroy(None) == gsr.GSR_OK

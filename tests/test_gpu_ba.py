@@ -1,0 +1,151 @@
+"""GPU parity of the local bundle adjustment (gsr_ba_* through the C ABI)
+against the FP64 oracle on the same seeded problems.
+
+Both sides compute in FP64 and differ only in summation order, so the bar is
+a relative 1e-8 on every pose entry, landmark coordinate, the focal length
+and the costs after the steps (a step amplifies rounding by the system's
+conditioning, here far below 1e4).  Edge cases: every keyframe free, every
+keyframe fixed (the reduced system is the focal length alone), landmarks
+seen by all eight slots, a landmark count that leaves the last workgroup
+ragged, one iteration and zero iterations."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import ba as B
+from paper_2607_14481_amd.ba_scenes import make_problem
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-8
+
+
+def _gsr():
+    from paper_2607_14481_amd import gsr
+    return gsr
+
+
+def _oracle(P, iters, lam):
+    lm, cam, uv = P.flat_observations()
+    pr = {"free_slot": P.free_slot, "c": np.array(P.principal), "obs_lm": lm, "obs_cam": cam, "obs_uv": uv}
+    st = {"poses": P.init_poses, "f": P.init_focal, "landmarks": P.init_landmarks}
+    return B.solve(pr, st, iters, lam)
+
+
+def _device(P):
+    d = "cuda"
+    return (torch.tensor(P.init_poses, dtype=torch.float64, device=d),
+            torch.tensor([P.init_focal], dtype=torch.float64, device=d),
+            torch.tensor(P.init_landmarks, dtype=torch.float64, device=d),
+            torch.tensor(P.obs_uv, dtype=torch.float64, device=d))
+
+
+def _gpu(P, iters, lam, plan=None):
+    gsr = _gsr()
+    plan = plan or gsr.BAPlan(P.free_slot, P.obs_cam)
+    poses, focal, pts, uv = _device(P)
+    costs = torch.zeros(iters + 1, dtype=torch.float64, device="cuda")
+    gsr.ba_solve(plan, poses, focal, P.principal, pts, uv, iters, lam, costs)
+    torch.cuda.synchronize()
+    return {"poses": poses.cpu().numpy(), "f": float(focal.item()), "landmarks": pts.cpu().numpy()}, \
+        costs.cpu().numpy()
+
+
+def _close(a, b, what):
+    scale = max(np.abs(b).max(), 1e-300)
+    err = np.abs(np.asarray(a) - np.asarray(b)).max() / scale
+    assert err <= RTOL, f"{what}: relative error {err:.3e}"
+
+
+def _compare(P, iters, lam=1e-4):
+    print(f"[ba] n_cams={P.n_cams} free={int((P.free_slot >= 0).sum())} K={P.n_landmarks} M={P.max_obs} "
+          f"iters={iters}", flush=True)
+    st_o, costs_o = _oracle(P, iters, lam)
+    st_g, costs_g = _gpu(P, iters, lam)
+    _close(st_g["poses"], st_o["poses"], "poses")
+    _close(st_g["landmarks"], st_o["landmarks"], "landmarks")
+    _close(st_g["f"], st_o["f"], "focal")
+    np.testing.assert_allclose(costs_g, costs_o, rtol=RTOL, atol=0)
+    fixed = P.free_slot < 0
+    assert np.array_equal(st_g["poses"][fixed], P.init_poses[fixed])
+    return st_g, costs_g
+
+
+@pytest.mark.parametrize("kw", [
+    dict(n_cams=6, n_landmarks=37, n_fixed=2, max_obs=4),
+    dict(n_cams=6, n_landmarks=37, n_fixed=0, max_obs=4),
+    dict(n_cams=5, n_landmarks=50, n_fixed=5, max_obs=3),
+    dict(n_cams=9, n_landmarks=33, n_fixed=3, max_obs=8, min_obs=8),
+])
+def test_one_step_matches_oracle(kw):
+    P = make_problem(11, pixel_noise=0.5, **kw)
+    _compare(P, 1)
+
+
+def test_ten_steps_match_oracle_on_a_window_of_twenty():
+    P = make_problem(12, n_cams=20, n_landmarks=1500, n_fixed=4, max_obs=8, pixel_noise=0.5)
+    _, costs = _compare(P, 10)
+    # monotone down to the noise floor, where successive costs agree to rounding
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(costs, costs[1:]))
+    # at the optimum 1/2 sum r^2 is about 1/2 * 0.5^2 per residual coordinate
+    assert costs[-1] < 0.5 * 0.25 * 2 * int((P.obs_cam >= 0).sum())
+
+
+def test_zero_iterations_reports_the_cost_only():
+    P = make_problem(13, n_cams=6, n_landmarks=40, n_fixed=2, max_obs=4, pixel_noise=0.5)
+    st, costs = _compare(P, 0)
+    assert np.array_equal(st["poses"], P.init_poses) and np.array_equal(st["landmarks"], P.init_landmarks)
+
+
+def test_large_damping_step():
+    P = make_problem(14, n_cams=8, n_landmarks=80, n_fixed=2, max_obs=5, pixel_noise=0.5)
+    _compare(P, 2, lam=10.0)
+
+
+def test_full_size_two_steps_match_oracle():
+    # 20 keyframes (4 fixed), 10,000 landmarks, up to 8 observations each
+    P = make_problem(0, pixel_noise=0.5)
+    _compare(P, 2)
+
+
+def test_full_size_noise_free_converges_to_ground_truth_and_is_deterministic():
+    P = make_problem(1)
+    gsr = _gsr()
+    plan = gsr.BAPlan(P.free_slot, P.obs_cam)
+    st, costs = _gpu(P, 10, 1e-4, plan)
+    assert costs[0] > 1e4 and costs[-1] < 1e-12 * costs[0]
+    np.testing.assert_allclose(st["poses"], P.gt_poses, atol=1e-7)
+    np.testing.assert_allclose(st["landmarks"], P.gt_landmarks, atol=1e-7)
+    assert abs(st["f"] - P.gt_focal) < 1e-6
+    st2, costs2 = _gpu(P, 10, 1e-4, plan)
+    assert np.array_equal(st["poses"], st2["poses"]) and np.array_equal(st["landmarks"], st2["landmarks"])
+    assert np.array_equal(costs, costs2)
+
+
+def test_graph_replays_match_eager():
+    P = make_problem(15, n_cams=20, n_landmarks=3000, n_fixed=4, max_obs=8, pixel_noise=0.5)
+    gsr = _gsr()
+    plan = gsr.BAPlan(P.free_slot, P.obs_cam)
+    ref, ref_costs = _gpu(P, 10, 1e-4, plan)
+    init = _device(P)
+    poses, focal, pts, uv = [t.clone() for t in init]
+    costs = torch.zeros(11, dtype=torch.float64, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        gsr.ba_solve(plan, poses, focal, P.principal, pts, uv, 10, 1e-4, costs)   # warm-up outside capture
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        gsr.ba_solve(plan, poses, focal, P.principal, pts, uv, 10, 1e-4, costs)
+    for rep in range(3):
+        poses.copy_(init[0]); focal.copy_(init[1]); pts.copy_(init[2])
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(poses.cpu().numpy(), ref["poses"]), rep
+        assert np.array_equal(pts.cpu().numpy(), ref["landmarks"]), rep
+        assert np.array_equal(costs.cpu().numpy(), ref_costs), rep
+        _ = (torch.randn(1000, device="cuda") * 2).sum().item()   # unrelated eager work between replays
