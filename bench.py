@@ -428,6 +428,94 @@ def run_serving(seconds, rate=200.0, start=500_000, per_keyframe=10_000, period=
     return out
 
 
+def run_local_ba(iters=10, repeats=30, cpu_baseline=True):
+    """Local bundle adjustment at the paper's timing size: 20 keyframes (4 fixed),
+    10,000 landmarks seen by 2-8 consecutive keyframes each, focal length
+    optimised, `iters` damped Gauss-Newton steps in FP64.  Timed from the
+    device-resident start state (reset by a copy outside the timed region),
+    eager launches and one captured graph."""
+    import numpy as np
+    import torch
+    from paper_2607_14481_amd import gsr
+    from paper_2607_14481_amd.ba_scenes import make_problem
+
+    P = make_problem(0, pixel_noise=0.5)
+    t0 = time.time()
+    plan = gsr.BAPlan(P.free_slot, P.obs_cam)
+    torch.cuda.synchronize()
+    plan_ms = (time.time() - t0) * 1e3
+    d = "cuda"
+    init = (torch.tensor(P.init_poses, dtype=torch.float64, device=d),
+            torch.tensor([P.init_focal], dtype=torch.float64, device=d),
+            torch.tensor(P.init_landmarks, dtype=torch.float64, device=d))
+    uv = torch.tensor(P.obs_uv, dtype=torch.float64, device=d)
+    poses, focal, pts = [t.clone() for t in init]
+    costs = torch.zeros(iters + 1, dtype=torch.float64, device=d)
+
+    def reset():
+        poses.copy_(init[0]); focal.copy_(init[1]); pts.copy_(init[2])
+
+    def solve():
+        gsr.ba_solve(plan, poses, focal, P.principal, pts, uv, iters, 1e-4, costs)
+
+    for _ in range(3):
+        reset(); solve()
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        ms = []
+        for _ in range(repeats):
+            reset()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(); fn(); b.record()
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        return float(np.median(ms)), float(np.min(ms))
+
+    eager_med, eager_min = timed(solve)
+    c = costs.cpu().numpy()
+    graph_med = graph_min = None
+    try:
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            reset(); solve()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            solve()
+        graph_med, graph_min = timed(g.replay)
+        same = bool(np.array_equal(costs.cpu().numpy(), c))
+    except Exception as e:  # pragma: no cover - reported, not fatal
+        log(f"[bench] BA graph capture failed: {e}")
+        same = None
+    n_obs = int((P.obs_cam >= 0).sum())
+    out = {"workload": f"local BA: 20 keyframes (4 fixed), 10,000 landmarks, {n_obs} observations (2-8 consecutive "
+                       f"keyframes per landmark), focal length optimised, {iters} LM iterations, FP64",
+           "ms_per_solve": round(eager_med, 4), "ms_per_solve_min": round(eager_min, 4),
+           "graph_ms_per_solve": round(graph_med, 4) if graph_med else None,
+           "graph_ms_per_solve_min": round(graph_min, 4) if graph_min else None,
+           "graph_matches_eager": same,
+           "ms_per_iteration": round(eager_med / iters, 4),
+           "plan_create_ms": round(plan_ms, 3),
+           "cost_first_last": [float(c[0]), float(c[-1])],
+           "paper_ms_rtx4090": 15.9}
+    if cpu_baseline:
+        from oracle import ba as B
+        lm, cam, ouv = P.flat_observations()
+        pr = {"free_slot": P.free_slot, "c": np.array(P.principal), "obs_lm": lm, "obs_cam": cam, "obs_uv": ouv}
+        st = {"poses": P.init_poses, "f": P.init_focal, "landmarks": P.init_landmarks}
+        t = time.time()
+        B.apply_step(pr, st, B.step_schur(pr, st, 1e-4))
+        t_it = time.time() - t
+        out["cpu_baseline"] = {"value": round(t_it * iters * 1e3, 1), "unit": "ms per solve", "cores": 1,
+                               "kind": "oracle", "sample": f"one of the {iters} iterations at full size "
+                                                           f"({t_it:.2f} s), times {iters}; numpy FP64"}
+    log(f"[bench] local BA: {eager_med:.3f} ms eager, {graph_med} ms graph per {iters}-iteration solve")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -445,6 +533,9 @@ def main():
                     help="skip the small-view, 200k-at-1080p and level-of-detail measurements")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="length of the Poisson request window of the serving measurement (0: skip)")
+    ap.add_argument("--no-ba", action="store_true", help="skip the local bundle-adjustment measurement")
+    ap.add_argument("--ba-only", action="store_true",
+                    help="measure only the local bundle adjustment and print its JSON object")
     ap.add_argument("--copy-calibration", action="store_true",
                     help=f"first run {COPY_CAL_REPS} plain device copies of {COPY_CAL_MIB} MiB (the reference "
                          "kernel that scales HBM byte counters)")
@@ -462,6 +553,9 @@ def main():
 
     torch.cuda.init()
     dev = torch.device("cuda:0")
+    if args.ba_only:
+        print(json.dumps(run_local_ba(cpu_baseline=not args.no_cpu_baseline)), flush=True)
+        return
     if args.copy_calibration:
         src = torch.ones(COPY_CAL_MIB << 18, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -518,6 +612,9 @@ def main():
     served = None
     if args.serve_seconds > 0:
         served = run_serving(args.serve_seconds)
+
+    # ---- the local bundle adjustment (20 keyframes x 10,000 landmarks, 10 iterations)
+    local_ba = None if args.no_ba else run_local_ba(cpu_baseline=not args.no_cpu_baseline)
 
     # ---- roofline of the dominant kernel (compositing, ALU-bound)
     comp = {"composite_fwd": stage_ms["composite_fwd"], "composite_bwd": stage_ms["composite_bwd"]}
@@ -589,6 +686,7 @@ def main():
         "keyframe_optimisation": keyframe,
         "batched_views": ring,
         "serving": served,
+        "local_ba": local_ba,
     }
     print(json.dumps(out), flush=True)
 

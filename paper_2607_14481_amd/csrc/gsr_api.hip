@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "gsr_ba.h"
 #include "gsr_internal.h"
 
 namespace {
@@ -751,7 +752,7 @@ BaLayout ba_layout(int n_cams, int n_free, int K, int M) {
     const size_t max_pairs = (size_t)K * ((size_t)M + (size_t)M * (M - 1) / 2);
     L.obs_rec = take((size_t)K * M * gsr::kBaRecStride * sizeof(double));
     L.lm_rec = take((size_t)K * gsr::kBaLmStride * sizeof(double));
-    L.S = take((D * D + D) * sizeof(double));
+    L.S = take(gsr::kBaAsmSplit * (D + 1) * (D + 1) * sizeof(double));   // partial systems (pitch D + 1) + rhs + cost
     L.dc = take(D * sizeof(double));
     L.obs_cam = take((size_t)K * M * sizeof(int32_t));
     L.free_slot = take((size_t)n_cams * sizeof(int32_t));
@@ -832,9 +833,9 @@ int gsr_ba_plan_create(int32_t n_cams, const int32_t *free_slot, int32_t n_landm
     if (rc) return rc;
     if ((rc = check_hip(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "LDS limit")))
         return rc;
-    const size_t lds = ba_solve_lds_bytes(D);
+    const size_t lds = ba_lds_bytes(D);
     if (lds > (size_t)lds_max) return fail(GSR_ERR_UNSUPPORTED, "reduced system needs %zu bytes of LDS (%d available)", lds, lds_max);
-    if ((rc = check_hip(ba_allow_lds(lds), "LDS attribute"))) return rc;
+    if ((rc = check_hip(ba_allow_lds(D), "LDS attribute"))) return rc;
     // observation-pair lists of the reduced system's blocks (a <= b), each in landmark order
     std::vector<std::vector<int2>> lists((size_t)nblk);
     auto block_of = [F](int a, int b) { return a * F - a * (a - 1) / 2 + (b - a); };

@@ -14,13 +14,14 @@
 //                   (damped, inverted in closed form), and for every
 //                   observation in a free keyframe the pieces of the Schur
 //                   complement it contributes (below);
-//   k_ba_assemble   one workgroup per block (a, b) of the reduced camera
-//                   system, walking a host-built list of observation pairs
-//                   in a fixed order (deterministic, no atomics), plus one
-//                   workgroup for the focal-length entry and the cost;
-//   k_ba_solve      one workgroup: LDL^T of the reduced system in LDS, one
-//                   barrier per column, the forward solve riding along as
-//                   an extra column; the backward solve in one wave;
+//   k_ba_assemble   workgroups per block (a, b) of the reduced camera
+//                   system, each walking its part of a host-built list of
+//                   observation pairs in a fixed order (deterministic, no
+//                   atomics) into a partial system, plus workgroups for the
+//                   focal-length entry and the cost;
+//   k_ba_solve      one workgroup: adds the partial systems, then a blocked
+//                   Cholesky in LDS with the forward solve riding along, and
+//                   the backward solve in one wave;
 //   k_ba_update     landmark back-substitution and update, and the SE(3)
 //                   retraction of the free poses and the focal step.
 //
@@ -33,7 +34,7 @@
 // and per landmark y_f = Hinv b_f, h_g = Hinv g_p, Jf^T Jf, y_f . b_f,
 // Jf^T r - y_f . g_p and its share of the cost.  Off-diagonal blocks are
 // -sum over shared landmarks of Y_{o_a} B_{o_b}^T.
-#include "gsr_internal.h"
+#include "gsr_ba.h"
 
 namespace gsr {
 
@@ -47,29 +48,63 @@ constexpr int kRB = 0, kRY = 18, kRD = 36, kRDg = 57, kRC = 63, kRS = 69;
 // offsets inside a landmark record
 constexpr int kLYf = 0, kLHg = 3, kLFf = 6, kLFs = 7, kLSf = 8, kLCost = 9;
 
+// One DPP step on a double (both 32-bit halves moved alike): v + v moved
+// across lanes by `ctrl`, only in the rows enabled by `row_mask` (others add 0).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_add_d(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    int lo = (int)(unsigned)b, hi = (int)(unsigned)(b >> 32);
+    if constexpr (ROW_MASK == 0xf) {
+        lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xf, 0xf, true);
+        hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xf, 0xf, true);
+    } else {
+        lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, 0xf, false);
+        hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, 0xf, false);
+    }
+    return v + __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over an 8-lane group (one landmark's observation slots): two quad swaps
+// give each lane its quad's sum, the half-row mirror adds the other quad's.
+// Additions pair the same operands on every lane, so all 8 lanes hold the
+// bit-identical total.
 __device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-    for (int m = 1; m < kLanesPerLm; m <<= 1) v += __shfl_xor(v, m, kLanesPerLm);
-    return v;
+    v = dpp_add_d<0xB1, 0xf>(v);   // quad_perm [1, 0, 3, 2]
+    v = dpp_add_d<0x4E, 0xf>(v);   // quad_perm [2, 3, 0, 1]
+    return dpp_add_d<0x141, 0xf>(v);  // row_half_mirror
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m, 64);
-    return v;
+// Sum over the 64 lanes of a wave in a fixed order: quad swaps, half-row and
+// row mirrors leave each lane with its 16-lane row's sum, two row broadcasts
+// gather the rows into row 3; lane 63's total is returned to every lane.
+__device__ __forceinline__ double wave_sum_d(double v) {
+    v = dpp_add_d<0xB1, 0xf>(v);   // quad_perm [1, 0, 3, 2]
+    v = dpp_add_d<0x4E, 0xf>(v);   // quad_perm [2, 3, 0, 1]
+    v = dpp_add_d<0x141, 0xf>(v);  // row_half_mirror
+    v = dpp_add_d<0x140, 0xf>(v);  // row_mirror
+    v = dpp_add_d<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v = dpp_add_d<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    return readlane_d(v, 63);
 }
 
-// Sum of N per-thread accumulators over a 256-thread block, in a fixed
-// order: every wave reduces by butterfly, then thread t < N adds the four
-// wave sums of value t in wave order.  Result valid in red[t] (all threads
-// may read it after the trailing barrier).
+// Sum of N per-thread accumulators over the 256-thread block in a fixed
+// order (deterministic): wave sums, then thread t adds the four waves' value
+// t in wave order.  red: 5 N doubles of LDS; returns the N sums (in LDS,
+// valid for every thread).
 template <int N>
-__device__ __forceinline__ void block_sum(double (&acc)[N], double *red) {
+__device__ __forceinline__ const double *block_sum(const double (&acc)[N], double *red) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int t = 0; t < N; ++t) {
-        const double s = wave_sum(acc[t]);
-        if (lane == 0) red[w * N + t] = s;
+        const double v = wave_sum_d(acc[t]);
+        if (lane == 0) red[w * N + t] = v;
     }
     __syncthreads();
     if (threadIdx.x < N) {
@@ -77,7 +112,12 @@ __device__ __forceinline__ void block_sum(double (&acc)[N], double *red) {
         red[4 * N + t] = ((red[t] + red[N + t]) + red[2 * N + t]) + red[3 * N + t];
     }
     __syncthreads();
+    return red + 4 * N;
 }
+
+// A partial system: D rows of pitch D + 1 (even, as D = 6F + 1 is odd, so rows
+// are 16-byte aligned), then the right-hand side (D), the cost and a pad.
+__device__ __forceinline__ size_t part_stride(int D) { return (size_t)(D + 1) * (D + 1); }
 
 struct ObsGeom {
     double r[2], jx[2][6], jf[2], jp[2][3];
@@ -167,8 +207,7 @@ __global__ void __launch_bounds__(kBaThreads) k_ba_landmark(BaArgs A, int cost_o
         L[kLCost] = cost;
     }
     if (cam < 0 || A.free_slot[cam] < 0) return;
-    double *R = A.obs_rec + o * kBaRecStride;
-    double B[6][3], Y[6][3];
+    double B[6][3], Y[6][3], rec[kBaRecStride];
 #pragma unroll
     for (int i = 0; i < 6; ++i)
 #pragma unroll
@@ -181,8 +220,8 @@ __global__ void __launch_bounds__(kBaThreads) k_ba_landmark(BaArgs A, int cost_o
     for (int i = 0; i < 6; ++i)
 #pragma unroll
         for (int u = 0; u < 3; ++u) {
-            R[kRB + 3 * i + u] = B[i][u];
-            R[kRY + 3 * i + u] = Y[i][u];
+            rec[kRB + 3 * i + u] = B[i][u];
+            rec[kRY + 3 * i + u] = Y[i][u];
         }
     int t = 0;
 #pragma unroll
@@ -191,43 +230,65 @@ __global__ void __launch_bounds__(kBaThreads) k_ba_landmark(BaArgs A, int cost_o
         for (int q = i; q < 6; ++q) {
             const double jj = fma(g.jx[0][i], g.jx[0][q], g.jx[1][i] * g.jx[1][q]);
             const double yb = fma(Y[i][0], B[q][0], fma(Y[i][1], B[q][1], Y[i][2] * B[q][2]));
-            R[kRD + t++] = jj - yb;
-            if (q == i) R[kRDg + i] = jj;
+            rec[kRD + t++] = jj - yb;
+            if (q == i) rec[kRDg + i] = jj;
         }
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-        R[kRC + i] = fma(g.jx[0][i], g.jf[0], g.jx[1][i] * g.jf[1]) -
-                     fma(Y[i][0], bf[0], fma(Y[i][1], bf[1], Y[i][2] * bf[2]));
-        R[kRS + i] = fma(g.jx[0][i], g.r[0], g.jx[1][i] * g.r[1]) -
-                     fma(Y[i][0], gp[0], fma(Y[i][1], gp[1], Y[i][2] * gp[2]));
+        rec[kRC + i] = fma(g.jx[0][i], g.jf[0], g.jx[1][i] * g.jf[1]) -
+                       fma(Y[i][0], bf[0], fma(Y[i][1], bf[1], Y[i][2] * bf[2]));
+        rec[kRS + i] = fma(g.jx[0][i], g.r[0], g.jx[1][i] * g.r[1]) -
+                       fma(Y[i][0], gp[0], fma(Y[i][1], gp[1], Y[i][2] * gp[2]));
     }
+    rec[kBaRecStride - 1] = 0.0;
+    // records are 608 bytes from a 256-byte aligned base: 16-byte stores
+    double2 *R = reinterpret_cast<double2 *>(A.obs_rec + o * kBaRecStride);
+#pragma unroll
+    for (int q = 0; q < kBaRecStride / 2; ++q) R[q] = make_double2(rec[2 * q], rec[2 * q + 1]);
 }
 
-// Blocks 0 .. nblk-1: block (a, b) of the reduced system from its pair list;
-// block nblk: the focal-length diagonal entry, its right-hand side and the cost.
-__global__ void __launch_bounds__(kBaThreads) k_ba_assemble(BaArgs A, int iter) {
+// Blocks x = 0 .. nblk-1: block (a, b) of the reduced system from its pair
+// list; block x = nblk: the focal-length diagonal entry, its right-hand side
+// and the cost.  Each is split over kBaAsmSplit workgroups (y) that take
+// consecutive parts of the list (of the landmarks) and write a partial system
+// of their own; the solve adds the partials in order.
+__global__ void __launch_bounds__(kBaThreads) k_ba_assemble(BaArgs A) {
     __shared__ double red[5 * 39];
-    const int D = A.D, fcol = D - 1;
-    double *S = A.S, *s = A.S + (uint64_t)D * D;
+    const int D = A.D, SP = D + 1, fcol = D - 1;
+    const int part = blockIdx.y;
+    double *S = A.S + part * part_stride(D), *s = S + (uint64_t)D * SP;
     if ((int)blockIdx.x == A.nblk) {
+        const int j0 = (int)((int64_t)A.K * part / kBaAsmSplit), j1 = (int)((int64_t)A.K * (part + 1) / kBaAsmSplit);
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int j = threadIdx.x; j < A.K; j += kBaThreads) {
-            const double *L = A.lm_rec + (uint64_t)j * kBaLmStride;
-            acc[0] += L[kLFf];
-            acc[1] += L[kLFs];
-            acc[2] += L[kLSf];
-            acc[3] += L[kLCost];
+        for (int jb = j0 + threadIdx.x; jb < j1; jb += 4 * kBaThreads) {   // 4 landmarks' loads in flight
+            double v[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = jb + u * kBaThreads;
+                const double *L = A.lm_rec + (uint64_t)j * kBaLmStride;
+                const bool ok = j < j1;
+                v[u][0] = ok ? L[kLFf] : 0.0;
+                v[u][1] = ok ? L[kLFs] : 0.0;
+                v[u][2] = ok ? L[kLSf] : 0.0;
+                v[u][3] = ok ? L[kLCost] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) acc[t] += v[u][t];
         }
-        block_sum<4>(acc, red);
+        const double *sum = block_sum(acc, red);
         if (threadIdx.x == 0) {
-            S[(uint64_t)fcol * D + fcol] = red[16] * (1.0 + A.lambda) - red[17];
-            s[fcol] = red[18];
-            if (A.costs) A.costs[iter] = red[19];
+            S[(uint64_t)fcol * SP + fcol] = sum[0] * (1.0 + A.lambda) - sum[1];
+            s[fcol] = sum[2];
+            s[D] = sum[3];   // the cost slot after the right-hand side
         }
         return;
     }
     const int2 ab = A.block_ab[blockIdx.x];
-    const uint32_t e0 = A.block_off[blockIdx.x], e1 = A.block_off[blockIdx.x + 1];
+    const uint32_t b0 = A.block_off[blockIdx.x], len = A.block_off[blockIdx.x + 1] - b0;
+    const uint32_t e0 = b0 + (uint32_t)((uint64_t)len * part / kBaAsmSplit);
+    const uint32_t e1 = b0 + (uint32_t)((uint64_t)len * (part + 1) / kBaAsmSplit);
     const int ra = 6 * ab.x, rb = 6 * ab.y;
     if (ab.x == ab.y) {
         double acc[39];
@@ -238,20 +299,19 @@ __global__ void __launch_bounds__(kBaThreads) k_ba_assemble(BaArgs A, int iter) 
 #pragma unroll
             for (int t = 0; t < 39; ++t) acc[t] += R[t];
         }
-        block_sum<39>(acc, red);
-        const double *sum = red + 4 * 39;
+        const double *sum = block_sum(acc, red);
         for (int t = threadIdx.x; t < 36; t += kBaThreads) {
             const int i = t / 6, q = t % 6;
             const int lo = i < q ? i : q, hi = i < q ? q : i;
             const int tri = lo * 6 - lo * (lo - 1) / 2 + (hi - lo);   // packed upper-triangle index
             double v = sum[tri];
             if (i == q) v += A.lambda * sum[21 + i];
-            S[(uint64_t)(ra + i) * D + ra + q] = v;
+            S[(uint64_t)(ra + i) * SP + ra + q] = v;
         }
         if (threadIdx.x < 6) {
             const int i = threadIdx.x;
-            S[(uint64_t)(ra + i) * D + fcol] = sum[27 + i];
-            S[(uint64_t)fcol * D + ra + i] = sum[27 + i];
+            S[(uint64_t)(ra + i) * SP + fcol] = sum[27 + i];
+            S[(uint64_t)fcol * SP + ra + i] = sum[27 + i];
             s[ra + i] = sum[33 + i];
         }
         return;
@@ -275,55 +335,158 @@ __global__ void __launch_bounds__(kBaThreads) k_ba_assemble(BaArgs A, int iter) 
             for (int q = 0; q < 6; ++q)
                 acc[6 * i + q] += fma(y[3 * i], b[3 * q], fma(y[3 * i + 1], b[3 * q + 1], y[3 * i + 2] * b[3 * q + 2]));
     }
-    block_sum<36>(acc, red);
-    const double *sum = red + 4 * 36;
+    const double *sum = block_sum(acc, red);
     for (int t = threadIdx.x; t < 36; t += kBaThreads) {
         const int i = t / 6, q = t % 6;
-        S[(uint64_t)(ra + i) * D + rb + q] = -sum[t];
-        S[(uint64_t)(rb + q) * D + ra + i] = -sum[t];
+        S[(uint64_t)(ra + i) * SP + rb + q] = -sum[t];
+        S[(uint64_t)(rb + q) * SP + ra + i] = -sum[t];
     }
 }
 
-// LDL^T of the reduced system S (D x D, symmetric positive definite after
-// damping) without pivoting, then dc = -S^-1 s.  Thread (i, h) owns row i and
-// the columns of parity h; step k folds column k into the trailing lower
-// triangle, A[i][q] -= A[i][k] A[q][k] / A[k][k] for k < q <= i, and does the
-// same to the right-hand side.  Afterwards d_k = A[k][k], L_ik = A[i][k] / d_k.
-__global__ void __launch_bounds__(kBaThreads) k_ba_solve(BaArgs A) {
+// Cholesky S = L L^T of the reduced system (D x D, symmetric positive definite
+// after damping) in LDS, right-looking in column blocks of 8, then
+// dc = -S^-1 s.  Per block: wave 0 factors the 8 x 8 diagonal block in
+// registers (lane = row * 8 + column) and solves its part of L z = s; every
+// row below solves its panel row against it and folds it into its z entry;
+// 4 x 4 tiles of the trailing lower triangle take the rank-8 update.  Three
+// barriers per block.  Finally wave 0 solves L^T x = z a column at a time.
+__global__ void __launch_bounds__(kBaThreads) k_ba_solve(BaArgs A, int iter) {
     extern __shared__ double lds[];
-    // odd row pitch: the column walks of the update (one row per lane) then hit
-    // distinct LDS banks
+    // odd row pitch: column walks (one row per lane) hit distinct LDS banks
     const int D = A.D, P = D | 1;
-    double *M = lds, *rhs = lds + (uint64_t)D * P;
-    const double *S = A.S, *s = A.S + (uint64_t)D * D;
-    for (int t = threadIdx.x; t < D * D; t += kBaThreads) {
-        const int r = t / D, c = t % D;
-        if (c <= r) M[r * P + c] = S[t];
+    double *M = lds, *rhs = lds + (uint64_t)D * P, *dinv = rhs + D;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const size_t ps = part_stride(D);
+    // lower triangle of the sum of the partial systems, as column pairs of
+    // 16-byte loads, 8 pairs x kBaAsmSplit partials in flight per thread
+    {
+        const int SP = D + 1, half = SP / 2, items = D * half;
+        for (int base = tid; base < items; base += 8 * kBaThreads) {
+            double2 v[8][kBaAsmSplit];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int it = base + u * kBaThreads, r = it / half, cp = it - r * half;
+                const bool ok = it < items && 2 * cp <= r;
+#pragma unroll
+                for (int q = 0; q < kBaAsmSplit; ++q)
+                    v[u][q] = ok ? *reinterpret_cast<const double2 *>(A.S + q * ps + (size_t)r * SP + 2 * cp)
+                                 : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int it = base + u * kBaThreads, r = it / half, cp = it - r * half;
+                if (it < items && 2 * cp <= r) {
+                    double2 w = v[u][0];
+#pragma unroll
+                    for (int q = 1; q < kBaAsmSplit; ++q) {
+                        w.x += v[u][q].x;
+                        w.y += v[u][q].y;
+                    }
+                    M[r * P + 2 * cp] = w.x;
+                    if (2 * cp + 1 <= r) M[r * P + 2 * cp + 1] = w.y;
+                }
+            }
+        }
     }
-    for (int t = threadIdx.x; t < D; t += kBaThreads) rhs[t] = s[t];
+    for (int t = tid; t <= D; t += kBaThreads) {   // right-hand side and (t = D) the cost
+        const size_t at = (size_t)D * (D + 1) + t;
+        double v = A.S[at];
+#pragma unroll
+        for (int q = 1; q < kBaAsmSplit; ++q) v += A.S[q * ps + at];
+        if (t < D) rhs[t] = v;
+        else if (A.costs) A.costs[iter] = v;
+    }
     __syncthreads();
-    const int i = threadIdx.x & 127, h = threadIdx.x >> 7;
-    for (int k = 0; k < D - 1; ++k) {
-        if (i > k && i < D) {
-            const double l = M[i * P + k] / M[k * P + k];
-            for (int q = k + 1 + h; q <= i; q += 2) M[i * P + q] = fma(-l, M[q * P + k], M[i * P + q]);
-            if (h == 0) rhs[i] = fma(-l, rhs[k], rhs[i]);
+    for (int k0 = 0; k0 < D; k0 += 8) {
+        const int nb = D - k0 < 8 ? D - k0 : 8, k1 = k0 + nb;
+        if (tid < 64) {
+            // rows/columns past the block's end are padded with the identity
+            const int r = lane >> 3, c = lane & 7;
+            const bool in = r < nb && c <= r;
+            double a = in ? M[(k0 + r) * P + k0 + c] : (r == c ? 1.0 : 0.0);
+            double y = (c == 0 && r < nb) ? rhs[k0 + r] : 0.0;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const double inv = rsqrt(readlane_d(a, j * 9)), ljj = readlane_d(a, j * 9) * inv;
+                if (c == j) a = r == j ? ljj : (r > j ? a * inv : a);
+                const double lrj = __shfl(a, r * 8 + j, 64), lcj = __shfl(a, c * 8 + j, 64);
+                if (c > j && r >= c) a = fma(-lrj, lcj, a);
+                const double zj = readlane_d(y, j * 8) * inv;
+                if (c == 0) y = r == j ? zj : (r > j ? fma(-lrj, zj, y) : y);
+            }
+            if (in) M[(k0 + r) * P + k0 + c] = a;
+            if (r == c && r < nb) dinv[k0 + r] = 1.0 / a;
+            if (c == 0 && r < nb) rhs[k0 + r] = y;
+        }
+        __syncthreads();
+        if (k1 + tid < D) {
+            const int i = k1 + tid;
+            double x[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) x[m] = m < nb ? M[i * P + k0 + m] : 0.0;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                if (m >= nb) break;
+                double v = x[m];
+#pragma unroll
+                for (int q = 0; q < m; ++q) v = fma(-x[q], M[(k0 + m) * P + k0 + q], v);
+                x[m] = v * dinv[k0 + m];
+            }
+            double rr = rhs[i];
+#pragma unroll
+            for (int m = 0; m < 8; ++m)
+                if (m < nb) {
+                    M[i * P + k0 + m] = x[m];
+                    rr = fma(-x[m], rhs[k0 + m], rr);
+                }
+            rhs[i] = rr;
+        }
+        __syncthreads();
+        const int n = D - k1;
+        if (n > 0) {
+            const int T = (n + 3) >> 2, ntiles = T * (T + 1) / 2;
+            for (int t = tid; t < ntiles; t += kBaThreads) {
+                int ti = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
+                while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+                while (ti * (ti + 1) / 2 > t) --ti;
+                const int tj = t - ti * (ti + 1) / 2;
+                const int i0 = k1 + 4 * ti, j0 = k1 + 4 * tj;
+                double li[4][8], lj[4][8];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int m = 0; m < 8; ++m) {
+                        li[u][m] = (i0 + u < D && m < nb) ? M[(i0 + u) * P + k0 + m] : 0.0;
+                        lj[u][m] = (j0 + u < D && m < nb) ? M[(j0 + u) * P + k0 + m] : 0.0;
+                    }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = i0 + u, j = j0 + v;
+                        if (i < D && j <= i) {
+                            double acc = M[i * P + j];
+#pragma unroll
+                            for (int m = 0; m < 8; ++m) acc = fma(-li[u][m], lj[v][m], acc);
+                            M[i * P + j] = acc;
+                        }
+                    }
+            }
         }
         __syncthreads();
     }
-    // rhs now holds z with L z = s; x solves D L^T x = z, done by wave 0:
-    // lane owns entries lane, lane + 64; x_q final once all rows below q folded in.
-    if (threadIdx.x >= 64) return;
-    const int lane = threadIdx.x;
-    double y0 = lane < D ? rhs[lane] / M[lane * P + lane] : 0.0;
-    double y1 = lane + 64 < D ? rhs[lane + 64] / M[(lane + 64) * P + lane + 64] : 0.0;
+    // L^T x = z by wave 0: lane owns entries lane and lane + 64; x_q is final
+    // once every row below q has been folded in.
+    if (tid >= 64) return;
+    const double di0 = lane < D ? dinv[lane] : 0.0, di1 = lane + 64 < D ? dinv[lane + 64] : 0.0;
+    double y0 = lane < D ? rhs[lane] : 0.0, y1 = lane + 64 < D ? rhs[lane + 64] : 0.0;
     for (int q = D - 1; q > 0; --q) {
-        const double xq = __shfl(q < 64 ? y0 : y1, q & 63, 64);
-        if (lane < q) y0 = fma(-M[q * P + lane] / M[lane * P + lane], xq, y0);
-        if (lane + 64 < q) y1 = fma(-M[q * P + lane + 64] / M[(lane + 64) * P + lane + 64], xq, y1);
+        const double xq = q < 64 ? readlane_d(y0 * di0, q) : readlane_d(y1 * di1, q - 64);
+        if (lane < q) y0 = fma(-M[q * P + lane], xq, y0);
+        if (lane + 64 < q) y1 = fma(-M[q * P + lane + 64], xq, y1);
     }
-    if (lane < D) A.dc[lane] = -y0;
-    if (lane + 64 < D) A.dc[lane + 64] = -y1;
+    if (lane < D) A.dc[lane] = -y0 * di0;
+    if (lane + 64 < D) A.dc[lane + 64] = -y1 * di1;
 }
 
 // SE(3) exponential of (rho, phi): R = I + a [phi]x + b [phi]x^2,
@@ -402,27 +565,38 @@ __global__ void __launch_bounds__(kBaThreads) k_ba_update(BaArgs A) {
 __global__ void __launch_bounds__(kBaThreads) k_ba_cost(BaArgs A, int iter) {
     __shared__ double red[5];
     double acc[1] = {0.0};
-    for (int j = threadIdx.x; j < A.K; j += kBaThreads) acc[0] += A.lm_rec[(uint64_t)j * kBaLmStride + kLCost];
-    block_sum<1>(acc, red);
-    if (threadIdx.x == 0 && A.costs) A.costs[iter] = red[4];
+    for (int j0 = threadIdx.x; j0 < A.K; j0 += 8 * kBaThreads) {   // 8 loads in flight per thread
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int j = j0 + u * kBaThreads;
+            v[u] = j < A.K ? A.lm_rec[(uint64_t)j * kBaLmStride + kLCost] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[0] += v[u];
+    }
+    const double *sum = block_sum(acc, red);
+    if (threadIdx.x == 0 && A.costs) A.costs[iter] = sum[0];
 }
 
 }  // namespace
 
-size_t ba_solve_lds_bytes(int D) { return ((size_t)D * (D | 1) + D) * sizeof(double); }
+size_t ba_solve_lds_bytes(int D) { return ((size_t)D * (D | 1) + 2 * (size_t)D) * sizeof(double); }
 
-hipError_t ba_allow_lds(size_t bytes) {
+size_t ba_lds_bytes(int D) { return ba_solve_lds_bytes(D); }
+
+hipError_t ba_allow_lds(int D) {
     return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ba_solve), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)bytes);
+                               (int)ba_solve_lds_bytes(D));
 }
 
 void launch_ba_iterations(const BaArgs &A, int iterations, hipStream_t st) {
     const unsigned lm_blocks = (unsigned)(((uint64_t)A.K * kLanesPerLm + kBaThreads - 1) / kBaThreads);
-    const size_t lds = ba_solve_lds_bytes(A.D);
+    const size_t solve_lds = ba_solve_lds_bytes(A.D);
     for (int it = 0; it < iterations; ++it) {
         hipLaunchKernelGGL(k_ba_landmark, dim3(lm_blocks), dim3(kBaThreads), 0, st, A, 0);
-        hipLaunchKernelGGL(k_ba_assemble, dim3((unsigned)A.nblk + 1), dim3(kBaThreads), 0, st, A, it);
-        hipLaunchKernelGGL(k_ba_solve, dim3(1), dim3(kBaThreads), lds, st, A);
+        hipLaunchKernelGGL(k_ba_assemble, dim3((unsigned)A.nblk + 1, kBaAsmSplit), dim3(kBaThreads), 0, st, A);
+        hipLaunchKernelGGL(k_ba_solve, dim3(1), dim3(kBaThreads), solve_lds, st, A, it);
         hipLaunchKernelGGL(k_ba_update, dim3(lm_blocks + 1), dim3(kBaThreads), 0, st, A);
     }
     hipLaunchKernelGGL(k_ba_landmark, dim3(lm_blocks), dim3(kBaThreads), 0, st, A, 1);

@@ -396,25 +396,4 @@ struct PairWalker {
     }
 };
 
-// ---- local bundle adjustment (FP64) ----
-constexpr int kBaMaxObs = 8;       // observation slots per landmark (lanes per landmark)
-constexpr int kBaMaxFree = 20;     // free keyframes: reduced system of 6 * 20 + 1 unknowns
-constexpr int kBaRecStride = 76;   // doubles per observation record (75 used)
-constexpr int kBaLmStride = 12;    // doubles per landmark record (10 used)
-
-struct BaArgs {
-    double *poses, *focal, *landmarks;
-    const double *obs_uv;
-    const int32_t *obs_cam, *free_slot, *slot_cam;
-    const int2 *block_ab, *pairs;
-    const uint32_t *block_off;
-    double *obs_rec, *lm_rec, *S, *dc, *costs;
-    double cx, cy, lambda;
-    int K, M, F, D, nblk;
-};
-
-size_t ba_solve_lds_bytes(int D);
-hipError_t ba_allow_lds(size_t bytes);
-void launch_ba_iterations(const BaArgs &A, int iterations, hipStream_t st);
-
 }  // namespace gsr
