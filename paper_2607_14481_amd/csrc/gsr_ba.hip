@@ -420,25 +420,31 @@ __global__ void __launch_bounds__(kBaThreads) k_ba_solve(BaArgs A, int iter) {
         }
         __syncthreads();
         if (k1 + tid < D) {
+            // every LDS read first (the block's factor and its z entries are the
+            // same for all rows: broadcasts), then the dependent chain in registers
             const int i = k1 + tid;
-            double x[8];
-#pragma unroll
-            for (int m = 0; m < 8; ++m) x[m] = m < nb ? M[i * P + k0 + m] : 0.0;
+            double x[8], lb[8][8], di[8], zb[8];
 #pragma unroll
             for (int m = 0; m < 8; ++m) {
-                if (m >= nb) break;
+                x[m] = m < nb ? M[i * P + k0 + m] : 0.0;
+                di[m] = m < nb ? dinv[k0 + m] : 0.0;
+                zb[m] = m < nb ? rhs[k0 + m] : 0.0;
+#pragma unroll
+                for (int q = 0; q < m; ++q) lb[m][q] = m < nb ? M[(k0 + m) * P + k0 + q] : 0.0;
+            }
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
                 double v = x[m];
 #pragma unroll
-                for (int q = 0; q < m; ++q) v = fma(-x[q], M[(k0 + m) * P + k0 + q], v);
-                x[m] = v * dinv[k0 + m];
+                for (int q = 0; q < m; ++q) v = fma(-x[q], lb[m][q], v);
+                x[m] = v * di[m];
             }
             double rr = rhs[i];
 #pragma unroll
+            for (int m = 0; m < 8; ++m) rr = fma(-x[m], zb[m], rr);   // x[m] = 0 past the block
+#pragma unroll
             for (int m = 0; m < 8; ++m)
-                if (m < nb) {
-                    M[i * P + k0 + m] = x[m];
-                    rr = fma(-x[m], rhs[k0 + m], rr);
-                }
+                if (m < nb) M[i * P + k0 + m] = x[m];
             rhs[i] = rr;
         }
         __syncthreads();
@@ -459,17 +465,28 @@ __global__ void __launch_bounds__(kBaThreads) k_ba_solve(BaArgs A, int iter) {
                         li[u][m] = (i0 + u < D && m < nb) ? M[(i0 + u) * P + k0 + m] : 0.0;
                         lj[u][m] = (j0 + u < D && m < nb) ? M[(j0 + u) * P + k0 + m] : 0.0;
                     }
+                // all 16 entries read before any is written back, so the chains
+                // of the entries overlap instead of waiting on each other
+                double acc[4][4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const int i = i0 + u, j = j0 + v;
-                        if (i < D && j <= i) {
-                            double acc = M[i * P + j];
+                        acc[u][v] = (i < D && j <= i) ? M[i * P + j] : 0.0;
+                    }
 #pragma unroll
-                            for (int m = 0; m < 8; ++m) acc = fma(-li[u][m], lj[v][m], acc);
-                            M[i * P + j] = acc;
-                        }
+                for (int m = 0; m < 8; ++m)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) acc[u][v] = fma(-li[u][m], lj[v][m], acc[u][v]);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = i0 + u, j = j0 + v;
+                        if (i < D && j <= i) M[i * P + j] = acc[u][v];
                     }
             }
         }
@@ -480,7 +497,24 @@ __global__ void __launch_bounds__(kBaThreads) k_ba_solve(BaArgs A, int iter) {
     if (tid >= 64) return;
     const double di0 = lane < D ? dinv[lane] : 0.0, di1 = lane + 64 < D ? dinv[lane + 64] : 0.0;
     double y0 = lane < D ? rhs[lane] : 0.0, y1 = lane + 64 < D ? rhs[lane + 64] : 0.0;
-    for (int q = D - 1; q > 0; --q) {
+    // rows of L read four at a time ahead of the dependent steps that use them
+    int q = D - 1;
+    for (; q >= 4; q -= 4) {
+        double m0[4], m1[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            m0[u] = lane < q - u ? M[(q - u) * P + lane] : 0.0;
+            m1[u] = lane + 64 < q - u ? M[(q - u) * P + lane + 64] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int r = q - u;
+            const double xr = r < 64 ? readlane_d(y0 * di0, r) : readlane_d(y1 * di1, r - 64);
+            y0 = fma(-m0[u], xr, y0);
+            y1 = fma(-m1[u], xr, y1);
+        }
+    }
+    for (; q > 0; --q) {
         const double xq = q < 64 ? readlane_d(y0 * di0, q) : readlane_d(y1 * di1, q - 64);
         if (lane < q) y0 = fma(-M[q * P + lane], xq, y0);
         if (lane + 64 < q) y1 = fma(-M[q * P + lane + 64], xq, y1);
