@@ -7,7 +7,8 @@ and the costs after the steps (a step amplifies rounding by the system's
 conditioning, here far below 1e4).  Edge cases: every keyframe free, every
 keyframe fixed (the reduced system is the focal length alone), landmarks
 seen by all eight slots, a landmark count that leaves the last workgroup
-ragged, one iteration and zero iterations."""
+ragged, the largest reduced system (20 free keyframes), one iteration and
+zero iterations."""
 import numpy as np
 import pytest
 
@@ -81,6 +82,13 @@ def _compare(P, iters, lam=1e-4):
 def test_one_step_matches_oracle(kw):
     P = make_problem(11, pixel_noise=0.5, **kw)
     _compare(P, 1)
+
+
+def test_largest_reduced_system():
+    # 20 free keyframes: 121 camera-side unknowns, the most the solve's LDS holds
+    P = make_problem(16, n_cams=24, n_landmarks=300, n_fixed=4, max_obs=8, pixel_noise=0.5)
+    assert int((P.free_slot >= 0).sum()) == 20
+    _compare(P, 2)
 
 
 def test_ten_steps_match_oracle_on_a_window_of_twenty():
