@@ -737,7 +737,7 @@ int gsr_gather_gaussians(const gsr_gaussians *src, const int32_t *index, int64_t
 namespace {
 
 struct BaLayout {
-    size_t obs_rec, lm_rec, S, dc, obs_cam, free_slot, slot_cam, block_ab, block_off, pairs, total;
+    size_t obs_rec, lm_rec, S, dc, obs_cam, free_slot, slot_cam, block_ab, block_off, pairs, rec_pos, total;
 };
 
 BaLayout ba_layout(int n_cams, int n_free, int K, int M) {
@@ -760,6 +760,7 @@ BaLayout ba_layout(int n_cams, int n_free, int K, int M) {
     L.block_ab = take((nblk > 0 ? nblk : 1) * sizeof(int2));
     L.block_off = take((nblk + 1) * sizeof(uint32_t));
     L.pairs = take((max_pairs > 0 ? max_pairs : 1) * sizeof(int2));
+    L.rec_pos = take((size_t)K * M * sizeof(int32_t));
     L.total = off;
     return L;
 }
@@ -857,6 +858,15 @@ int gsr_ba_plan_create(int32_t n_cams, const int32_t *free_slot, int32_t n_landm
             }
         }
     }
+    // records are stored keyframe-major (free slot, then landmark): a diagonal
+    // block's list is then one contiguous run of records, and the two sides of
+    // an off-diagonal block's pairs advance through two runs
+    std::vector<int32_t> rec_pos((size_t)K * M, -1);
+    int32_t next_rec = 0;
+    for (int a = 0; a < F; ++a)
+        for (const int2 &e : lists[block_of(a, a)]) rec_pos[e.x] = next_rec++;
+    for (auto &l : lists)
+        for (int2 &e : l) e = make_int2(rec_pos[e.x], rec_pos[e.y]);
     std::vector<int2> block_ab(nblk > 0 ? nblk : 1), pairs;
     std::vector<uint32_t> block_off(nblk + 1, 0);
     for (int a = 0, b = 0; a < F; ++a)
@@ -878,7 +888,8 @@ int gsr_ba_plan_create(int32_t n_cams, const int32_t *free_slot, int32_t n_landm
               {L.slot_cam, slot_cam.data(), slot_cam.size() * 4},
               {L.block_ab, block_ab.data(), block_ab.size() * sizeof(int2)},
               {L.block_off, block_off.data(), block_off.size() * 4},
-              {L.pairs, pairs.data(), pairs.size() * sizeof(int2)}};
+              {L.pairs, pairs.data(), pairs.size() * sizeof(int2)},
+              {L.rec_pos, rec_pos.data(), rec_pos.size() * 4}};
     for (const auto &u : up)
         if ((rc = check_hip(hipMemcpyAsync(ws + u.off, u.src, u.bytes, hipMemcpyHostToDevice, st), "structure upload")))
             return rc;
@@ -915,6 +926,7 @@ int gsr_ba_solve(const gsr_ba_plan *plan, double *poses, double *focal, double c
     A.slot_cam = reinterpret_cast<const int32_t *>(ws + L.slot_cam);
     A.block_ab = reinterpret_cast<const int2 *>(ws + L.block_ab);
     A.pairs = reinterpret_cast<const int2 *>(ws + L.pairs);
+    A.rec_pos = reinterpret_cast<const int32_t *>(ws + L.rec_pos);
     A.block_off = reinterpret_cast<const uint32_t *>(ws + L.block_off);
     A.obs_rec = reinterpret_cast<double *>(ws + L.obs_rec);
     A.lm_rec = reinterpret_cast<double *>(ws + L.lm_rec);

@@ -16,6 +16,7 @@ struct BaArgs {
     double *poses, *focal, *landmarks;
     const double *obs_uv;
     const int32_t *obs_cam, *free_slot, *slot_cam;
+    const int32_t *rec_pos;   // record index of each observation slot in a free keyframe (keyframe-major), else -1
     const int2 *block_ab, *pairs;
     const uint32_t *block_off;
     double *obs_rec, *lm_rec, *S, *dc, *costs;

@@ -18,7 +18,9 @@
 //                   system, each walking its part of a host-built list of
 //                   observation pairs in a fixed order (deterministic, no
 //                   atomics) into a partial system, plus workgroups for the
-//                   focal-length entry and the cost;
+//                   focal-length entry and the cost; the records are stored
+//                   keyframe-major, so a diagonal block reads one contiguous
+//                   run of them;
 //   k_ba_solve      one workgroup: adds the partial systems, then a blocked
 //                   Cholesky in LDS with the forward solve riding along, and
 //                   the backward solve in one wave;
@@ -241,8 +243,9 @@ __global__ void __launch_bounds__(kBaThreads) k_ba_landmark(BaArgs A, int cost_o
                        fma(Y[i][0], gp[0], fma(Y[i][1], gp[1], Y[i][2] * gp[2]));
     }
     rec[kBaRecStride - 1] = 0.0;
-    // records are 608 bytes from a 256-byte aligned base: 16-byte stores
-    double2 *R = reinterpret_cast<double2 *>(A.obs_rec + o * kBaRecStride);
+    // records (keyframe-major, see the pair lists) are 608 bytes from a
+    // 256-byte aligned base: 16-byte stores
+    double2 *R = reinterpret_cast<double2 *>(A.obs_rec + (uint64_t)A.rec_pos[o] * kBaRecStride);
 #pragma unroll
     for (int q = 0; q < kBaRecStride / 2; ++q) R[q] = make_double2(rec[2 * q], rec[2 * q + 1]);
 }
@@ -584,7 +587,7 @@ __global__ void __launch_bounds__(kBaThreads) k_ba_update(BaArgs A) {
     const int slot = cam >= 0 ? A.free_slot[cam] : -1;
     double v[3] = {0.0, 0.0, 0.0};
     if (slot >= 0) {
-        const double *Y = A.obs_rec + o * kBaRecStride + kRY;
+        const double *Y = A.obs_rec + (uint64_t)A.rec_pos[o] * kBaRecStride + kRY;
         const double *dc = A.dc + 6 * slot;
         for (int i = 0; i < 6; ++i)
             for (int u = 0; u < 3; ++u) v[u] = fma(Y[3 * i + u], dc[i], v[u]);
