@@ -349,15 +349,17 @@ __global__ void __launch_bounds__(kBaThreads) k_ba_assemble(BaArgs A) {
 // Cholesky S = L L^T of the reduced system (D x D, symmetric positive definite
 // after damping) in LDS, right-looking in column blocks of 8, then
 // dc = -S^-1 s.  Per block: wave 0 factors the 8 x 8 diagonal block in
-// registers (lane = row * 8 + column) and solves its part of L z = s; every
-// row below solves its panel row against it and folds it into its z entry;
-// 4 x 4 tiles of the trailing lower triangle take the rank-8 update.  Three
-// barriers per block.  Finally wave 0 solves L^T x = z a column at a time.
+// registers (lane = row * 8 + column) and solves its part of L z = s while the
+// other waves file the previous block's panel; then 4 x 4 tiles of the
+// trailing lower triangle each solve the panel rows they need against the
+// block and take the rank-8 update, the first tile of each row band keeping
+// its rows' panel and folding them into z.  Two barriers per block.  Finally
+// wave 0 solves L^T x = z a column at a time.
 __global__ void __launch_bounds__(kBaThreads) k_ba_solve(BaArgs A, int iter) {
     extern __shared__ double lds[];
     // odd row pitch: column walks (one row per lane) hit distinct LDS banks
     const int D = A.D, P = D | 1;
-    double *M = lds, *rhs = lds + (uint64_t)D * P, *dinv = rhs + D;
+    double *M = lds, *rhs = lds + (uint64_t)D * P, *dinv = rhs + D, *pan = dinv + D;   // pan: [D][8]
     const int tid = threadIdx.x, lane = tid & 63;
     const size_t ps = part_stride(D);
     // lower triangle of the sum of the partial systems, as column pairs of
@@ -420,39 +422,25 @@ __global__ void __launch_bounds__(kBaThreads) k_ba_solve(BaArgs A, int iter) {
             if (in) M[(k0 + r) * P + k0 + c] = a;
             if (r == c && r < nb) dinv[k0 + r] = 1.0 / a;
             if (c == 0 && r < nb) rhs[k0 + r] = y;
+        } else if (k0 > 0) {
+            // meanwhile the other waves file the previous block's panel (rows
+            // k0.., columns k0 - 8 .. k0 - 1) into the factor
+            for (int e = tid - 64; e < (D - k0) * 8; e += kBaThreads - 64)
+                M[(k0 + (e >> 3)) * P + k0 - 8 + (e & 7)] = pan[(k0 + (e >> 3)) * 8 + (e & 7)];
         }
         __syncthreads();
-        if (k1 + tid < D) {
-            // every LDS read first (the block's factor and its z entries are the
-            // same for all rows: broadcasts), then the dependent chain in registers
-            const int i = k1 + tid;
-            double x[8], lb[8][8], di[8], zb[8];
-#pragma unroll
-            for (int m = 0; m < 8; ++m) {
-                x[m] = m < nb ? M[i * P + k0 + m] : 0.0;
-                di[m] = m < nb ? dinv[k0 + m] : 0.0;
-                zb[m] = m < nb ? rhs[k0 + m] : 0.0;
-#pragma unroll
-                for (int q = 0; q < m; ++q) lb[m][q] = m < nb ? M[(k0 + m) * P + k0 + q] : 0.0;
-            }
-#pragma unroll
-            for (int m = 0; m < 8; ++m) {
-                double v = x[m];
-#pragma unroll
-                for (int q = 0; q < m; ++q) v = fma(-x[q], lb[m][q], v);
-                x[m] = v * di[m];
-            }
-            double rr = rhs[i];
-#pragma unroll
-            for (int m = 0; m < 8; ++m) rr = fma(-x[m], zb[m], rr);   // x[m] = 0 past the block
-#pragma unroll
-            for (int m = 0; m < 8; ++m)
-                if (m < nb) M[i * P + k0 + m] = x[m];
-            rhs[i] = rr;
-        }
-        __syncthreads();
-        const int n = D - k1;
+        const int n = D - k1;   // n > 0 implies a full block (nb = 8)
         if (n > 0) {
+            // the factor's 8 x 8 block, its reciprocal diagonal and z entries:
+            // the same for every thread (broadcast reads)
+            double lb[8][8], di[8], zb[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                di[m] = dinv[k0 + m];
+                zb[m] = rhs[k0 + m];
+#pragma unroll
+                for (int q = 0; q < m; ++q) lb[m][q] = M[(k0 + m) * P + k0 + q];
+            }
             const int T = (n + 3) >> 2, ntiles = T * (T + 1) / 2;
             for (int t = tid; t < ntiles; t += kBaThreads) {
                 int ti = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
@@ -460,16 +448,16 @@ __global__ void __launch_bounds__(kBaThreads) k_ba_solve(BaArgs A, int iter) {
                 while (ti * (ti + 1) / 2 > t) --ti;
                 const int tj = t - ti * (ti + 1) / 2;
                 const int i0 = k1 + 4 * ti, j0 = k1 + 4 * tj;
+                // the panel rows of this tile (L[row][k0..k1) = A[row][k0..k1) L_blk^-T),
+                // recomputed by every tile that needs them: no panel phase, no barrier
                 double li[4][8], lj[4][8];
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
 #pragma unroll
                     for (int m = 0; m < 8; ++m) {
-                        li[u][m] = (i0 + u < D && m < nb) ? M[(i0 + u) * P + k0 + m] : 0.0;
-                        lj[u][m] = (j0 + u < D && m < nb) ? M[(j0 + u) * P + k0 + m] : 0.0;
+                        li[u][m] = i0 + u < D ? M[(i0 + u) * P + k0 + m] : 0.0;
+                        lj[u][m] = j0 + u < D ? M[(j0 + u) * P + k0 + m] : 0.0;
                     }
-                // all 16 entries read before any is written back, so the chains
-                // of the entries overlap instead of waiting on each other
                 double acc[4][4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
@@ -478,6 +466,34 @@ __global__ void __launch_bounds__(kBaThreads) k_ba_solve(BaArgs A, int iter) {
                         const int i = i0 + u, j = j0 + v;
                         acc[u][v] = (i < D && j <= i) ? M[i * P + j] : 0.0;
                     }
+#pragma unroll
+                for (int m = 0; m < 8; ++m)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        double vi = li[u][m], vj = lj[u][m];
+#pragma unroll
+                        for (int q = 0; q < m; ++q) {
+                            vi = fma(-li[u][q], lb[m][q], vi);
+                            vj = fma(-lj[u][q], lb[m][q], vj);
+                        }
+                        li[u][m] = vi * di[m];
+                        lj[u][m] = vj * di[m];
+                    }
+                if (tj == 0) {
+                    // the first tile of each row band files its rows' panel and
+                    // folds them into z (one owner per row)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (i0 + u < D) {
+                            double rr = rhs[i0 + u];
+#pragma unroll
+                            for (int m = 0; m < 8; ++m) {
+                                pan[(i0 + u) * 8 + m] = li[u][m];
+                                rr = fma(-li[u][m], zb[m], rr);
+                            }
+                            rhs[i0 + u] = rr;
+                        }
+                }
 #pragma unroll
                 for (int m = 0; m < 8; ++m)
 #pragma unroll
@@ -618,7 +634,7 @@ __global__ void __launch_bounds__(kBaThreads) k_ba_cost(BaArgs A, int iter) {
 
 }  // namespace
 
-size_t ba_solve_lds_bytes(int D) { return ((size_t)D * (D | 1) + 2 * (size_t)D) * sizeof(double); }
+size_t ba_solve_lds_bytes(int D) { return ((size_t)D * (D | 1) + 10 * (size_t)D) * sizeof(double); }
 
 size_t ba_lds_bytes(int D) { return ba_solve_lds_bytes(D); }
 
