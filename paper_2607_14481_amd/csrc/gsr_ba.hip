@@ -44,6 +44,7 @@ namespace {
 
 constexpr int kLanesPerLm = kBaMaxObs;   // 8
 constexpr int kBaThreads = 256;
+constexpr int kSolveThreads = 512;    // the solve: 2 waves per SIMD to overlap its dependent chains
 
 // offsets inside an observation record
 constexpr int kRB = 0, kRY = 18, kRD = 36, kRDg = 57, kRC = 63, kRS = 69;
@@ -350,12 +351,12 @@ __global__ void __launch_bounds__(kBaThreads) k_ba_assemble(BaArgs A) {
 // after damping) in LDS, right-looking in column blocks of 8, then
 // dc = -S^-1 s.  Per block: wave 0 factors the 8 x 8 diagonal block in
 // registers (lane = row * 8 + column) and solves its part of L z = s while the
-// other waves file the previous block's panel; then 4 x 4 tiles of the
+// other waves file the previous block's panel; then 2 x 2 tiles of the
 // trailing lower triangle each solve the panel rows they need against the
 // block and take the rank-8 update, the first tile of each row band keeping
 // its rows' panel and folding them into z.  Two barriers per block.  Finally
 // wave 0 solves L^T x = z a column at a time.
-__global__ void __launch_bounds__(kBaThreads) k_ba_solve(BaArgs A, int iter) {
+__global__ void __launch_bounds__(kSolveThreads) k_ba_solve(BaArgs A, int iter) {
     extern __shared__ double lds[];
     // odd row pitch: column walks (one row per lane) hit distinct LDS banks
     const int D = A.D, P = D | 1;
@@ -363,14 +364,14 @@ __global__ void __launch_bounds__(kBaThreads) k_ba_solve(BaArgs A, int iter) {
     const int tid = threadIdx.x, lane = tid & 63;
     const size_t ps = part_stride(D);
     // lower triangle of the sum of the partial systems, as column pairs of
-    // 16-byte loads, 8 pairs x kBaAsmSplit partials in flight per thread
+    // 16-byte loads, 2 pairs x kBaAsmSplit partials in flight per thread
     {
         const int SP = D + 1, half = SP / 2, items = D * half;
-        for (int base = tid; base < items; base += 8 * kBaThreads) {
-            double2 v[8][kBaAsmSplit];
+        for (int base = tid; base < items; base += 2 * kSolveThreads) {
+            double2 v[2][kBaAsmSplit];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int it = base + u * kBaThreads, r = it / half, cp = it - r * half;
+            for (int u = 0; u < 2; ++u) {
+                const int it = base + u * kSolveThreads, r = it / half, cp = it - r * half;
                 const bool ok = it < items && 2 * cp <= r;
 #pragma unroll
                 for (int q = 0; q < kBaAsmSplit; ++q)
@@ -378,8 +379,8 @@ __global__ void __launch_bounds__(kBaThreads) k_ba_solve(BaArgs A, int iter) {
                                  : make_double2(0.0, 0.0);
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int it = base + u * kBaThreads, r = it / half, cp = it - r * half;
+            for (int u = 0; u < 2; ++u) {
+                const int it = base + u * kSolveThreads, r = it / half, cp = it - r * half;
                 if (it < items && 2 * cp <= r) {
                     double2 w = v[u][0];
 #pragma unroll
@@ -393,7 +394,7 @@ __global__ void __launch_bounds__(kBaThreads) k_ba_solve(BaArgs A, int iter) {
             }
         }
     }
-    for (int t = tid; t <= D; t += kBaThreads) {   // right-hand side and (t = D) the cost
+    for (int t = tid; t <= D; t += kSolveThreads) {   // right-hand side and (t = D) the cost
         const size_t at = (size_t)D * (D + 1) + t;
         double v = A.S[at];
 #pragma unroll
@@ -425,65 +426,62 @@ __global__ void __launch_bounds__(kBaThreads) k_ba_solve(BaArgs A, int iter) {
         } else if (k0 > 0) {
             // meanwhile the other waves file the previous block's panel (rows
             // k0.., columns k0 - 8 .. k0 - 1) into the factor
-            for (int e = tid - 64; e < (D - k0) * 8; e += kBaThreads - 64)
+            for (int e = tid - 64; e < (D - k0) * 8; e += kSolveThreads - 64)
                 M[(k0 + (e >> 3)) * P + k0 - 8 + (e & 7)] = pan[(k0 + (e >> 3)) * 8 + (e & 7)];
         }
         __syncthreads();
         const int n = D - k1;   // n > 0 implies a full block (nb = 8)
         if (n > 0) {
-            // the factor's 8 x 8 block, its reciprocal diagonal and z entries:
-            // the same for every thread (broadcast reads)
-            double lb[8][8], di[8], zb[8];
-#pragma unroll
-            for (int m = 0; m < 8; ++m) {
-                di[m] = dinv[k0 + m];
-                zb[m] = rhs[k0 + m];
-#pragma unroll
-                for (int q = 0; q < m; ++q) lb[m][q] = M[(k0 + m) * P + k0 + q];
-            }
-            const int T = (n + 3) >> 2, ntiles = T * (T + 1) / 2;
-            for (int t = tid; t < ntiles; t += kBaThreads) {
+            // the factor's 8 x 8 block, its reciprocal diagonal and z entries are
+            // the same for every thread: read from LDS where used (broadcasts)
+            const double *lb = M + k0 * P + k0, *di = dinv + k0, *zb = rhs + k0;
+            const int T = (n + 1) >> 1, ntiles = T * (T + 1) / 2;
+            for (int t = tid; t < ntiles; t += kSolveThreads) {
                 int ti = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
                 while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
                 while (ti * (ti + 1) / 2 > t) --ti;
                 const int tj = t - ti * (ti + 1) / 2;
-                const int i0 = k1 + 4 * ti, j0 = k1 + 4 * tj;
+                const int i0 = k1 + 2 * ti, j0 = k1 + 2 * tj;
                 // the panel rows of this tile (L[row][k0..k1) = A[row][k0..k1) L_blk^-T),
                 // recomputed by every tile that needs them: no panel phase, no barrier
-                double li[4][8], lj[4][8];
+                double li[2][8], lj[2][8];
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+                for (int u = 0; u < 2; ++u)
 #pragma unroll
                     for (int m = 0; m < 8; ++m) {
                         li[u][m] = i0 + u < D ? M[(i0 + u) * P + k0 + m] : 0.0;
                         lj[u][m] = j0 + u < D ? M[(j0 + u) * P + k0 + m] : 0.0;
                     }
-                double acc[4][4];
+                double acc[2][2];
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+                for (int u = 0; u < 2; ++u)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
+                    for (int v = 0; v < 2; ++v) {
                         const int i = i0 + u, j = j0 + v;
                         acc[u][v] = (i < D && j <= i) ? M[i * P + j] : 0.0;
                     }
 #pragma unroll
-                for (int m = 0; m < 8; ++m)
+                for (int m = 0; m < 8; ++m) {
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        double vi = li[u][m], vj = lj[u][m];
+                    for (int q = 0; q < m; ++q) {
+                        const double l = lb[m * P + q];
 #pragma unroll
-                        for (int q = 0; q < m; ++q) {
-                            vi = fma(-li[u][q], lb[m][q], vi);
-                            vj = fma(-lj[u][q], lb[m][q], vj);
+                        for (int u = 0; u < 2; ++u) {
+                            li[u][m] = fma(-li[u][q], l, li[u][m]);
+                            lj[u][m] = fma(-lj[u][q], l, lj[u][m]);
                         }
-                        li[u][m] = vi * di[m];
-                        lj[u][m] = vj * di[m];
                     }
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        li[u][m] *= di[m];
+                        lj[u][m] *= di[m];
+                    }
+                }
                 if (tj == 0) {
                     // the first tile of each row band files its rows' panel and
                     // folds them into z (one owner per row)
 #pragma unroll
-                    for (int u = 0; u < 4; ++u)
+                    for (int u = 0; u < 2; ++u)
                         if (i0 + u < D) {
                             double rr = rhs[i0 + u];
 #pragma unroll
@@ -497,13 +495,13 @@ __global__ void __launch_bounds__(kBaThreads) k_ba_solve(BaArgs A, int iter) {
 #pragma unroll
                 for (int m = 0; m < 8; ++m)
 #pragma unroll
-                    for (int u = 0; u < 4; ++u)
+                    for (int u = 0; u < 2; ++u)
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) acc[u][v] = fma(-li[u][m], lj[v][m], acc[u][v]);
+                        for (int v = 0; v < 2; ++v) acc[u][v] = fma(-li[u][m], lj[v][m], acc[u][v]);
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+                for (int u = 0; u < 2; ++u)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
+                    for (int v = 0; v < 2; ++v) {
                         const int i = i0 + u, j = j0 + v;
                         if (i < D && j <= i) M[i * P + j] = acc[u][v];
                     }
@@ -649,7 +647,7 @@ void launch_ba_iterations(const BaArgs &A, int iterations, hipStream_t st) {
     for (int it = 0; it < iterations; ++it) {
         hipLaunchKernelGGL(k_ba_landmark, dim3(lm_blocks), dim3(kBaThreads), 0, st, A, 0);
         hipLaunchKernelGGL(k_ba_assemble, dim3((unsigned)A.nblk + 1, kBaAsmSplit), dim3(kBaThreads), 0, st, A);
-        hipLaunchKernelGGL(k_ba_solve, dim3(1), dim3(kBaThreads), solve_lds, st, A, it);
+        hipLaunchKernelGGL(k_ba_solve, dim3(1), dim3(kSolveThreads), solve_lds, st, A, it);
         hipLaunchKernelGGL(k_ba_update, dim3(lm_blocks + 1), dim3(kBaThreads), 0, st, A);
     }
     hipLaunchKernelGGL(k_ba_landmark, dim3(lm_blocks), dim3(kBaThreads), 0, st, A, 1);
