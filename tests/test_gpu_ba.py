@@ -106,6 +106,12 @@ def test_zero_iterations_reports_the_cost_only():
     assert np.array_equal(st["poses"], P.init_poses) and np.array_equal(st["landmarks"], P.init_landmarks)
 
 
+def test_undamped_gauss_newton_steps():
+    # lambda = 0: plain Gauss-Newton (every landmark block is full rank here)
+    P = make_problem(17, n_cams=8, n_landmarks=120, n_fixed=2, max_obs=6, pixel_noise=0.5)
+    _compare(P, 3, lam=0.0)
+
+
 def test_large_damping_step():
     P = make_problem(14, n_cams=8, n_landmarks=80, n_fixed=2, max_obs=5, pixel_noise=0.5)
     _compare(P, 2, lam=10.0)
