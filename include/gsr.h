@@ -411,9 +411,10 @@ int gsr_ba_plan_destroy(gsr_ba_plan *plan);
  * principal point.  lambda >= 0: damping.  costs: NULL, or device
  * [iterations + 1] receiving the cost before each step and after the last.
  * Every observed point must stay in front of its camera (Z > 0).  A landmark
- * whose damped 3x3 block is exactly singular (possible only with lambda = 0)
- * keeps its position and adds nothing to the step.  Calls that share a plan
- * must not overlap.
+ * whose damped 3x3 block is exactly singular (in practice only with
+ * lambda = 0) is not eliminated: its inverse is taken as zero, so it keeps its
+ * position and its observations enter the camera system without the Schur
+ * correction.  Calls that share a plan must not overlap.
  */
 int gsr_ba_solve(const gsr_ba_plan *plan, double *poses, double *focal, double cx, double cy, double *landmarks,
                  const double *obs_uv, int32_t iterations, double lambda, double *costs, void *stream);
