@@ -156,3 +156,20 @@ def test_every_step_lowers_the_cost_on_a_noisy_problem():
     # at the optimum the residual is at the noise level: 1/2 sum r^2 ~ 1/2 * 0.25 per coordinate
     n = 2 * int((P.obs_cam >= 0).sum())
     assert costs[-1] < 0.5 * 0.25 * n
+
+
+def test_generator_builds_the_stated_structure():
+    P = make_problem(0)
+    assert P.n_cams == 20 and P.n_landmarks == 10_000 and P.max_obs == 8
+    assert int((P.free_slot < 0).sum()) == 4
+    assert sorted(P.free_slot[P.free_slot >= 0].tolist()) == list(range(16))
+    counts = (P.obs_cam >= 0).sum(axis=1)
+    assert counts.min() == 2 and counts.max() == 8
+    for j in range(0, P.n_landmarks, 97):   # runs of consecutive keyframes, valid slots first
+        row = P.obs_cam[j]
+        m = int(counts[j])
+        assert (row[m:] == -1).all() and (np.diff(row[:m]) == 1).all()
+    # every landmark in front of every camera that sees it, at depth above 1.4
+    lm, cam, _ = P.flat_observations()
+    X = np.einsum("oab,ob->oa", P.gt_poses[cam, :, :3], P.gt_landmarks[lm]) + P.gt_poses[cam, :, 3]
+    assert X[:, 2].min() > 1.4
