@@ -570,7 +570,11 @@ static void or_project_backward(int64_t i, int sh_degree, const double *means, c
 /*
  * or_render: one view.
  *   out_img [H*W*3], out_T [H*W], out_n [H*W] (last contributor position + 1
- *   within the pixel's tile list), out_ambig [H*W] (nullable).
+ *   within the pixel's tile list), out_ambig [H*W] (nullable): 0, or the
+ *   reasons the pixel's result is decided by a rounding-sensitive comparison
+ *   (bit 0: an alpha near 1/255, bit 1: near the 0.99 clamp, bit 2: a
+ *   transmittance near the stop threshold, bit 3: two consecutive
+ *   contributors with equal float32 depth).
  *   tile_mask [n_tiles] (nullable): only listed tiles are rendered and
  *   differentiated; other pixels are left untouched.
  *   dL_dimg (nullable): upstream gradient [H*W*3].  When given, parameter
@@ -651,16 +655,16 @@ int64_t or_render(int64_t n, int sh_degree, const double *means, const double *l
                     if (sig < 0.0) continue;
                     e = exp(-sig);
                     araw = g->opacity * e;
-                    if (fabs(araw - opts->alpha_min) < opts->eps_alpha) ambig = 1;
-                    if (fabs(araw - opts->alpha_max) < opts->eps_alpha) ambig = 1;
+                    if (fabs(araw - opts->alpha_min) < opts->eps_alpha) ambig |= 1;
+                    if (fabs(araw - opts->alpha_max) < opts->eps_alpha) ambig |= 2;
                     alpha = araw < opts->alpha_max ? araw : opts->alpha_max;
                     if (alpha < opts->alpha_min) continue;
                     Tn = T * (1.0 - alpha);
-                    if (fabs(Tn - opts->t_min) < opts->eps_t) ambig = 1;
+                    if (fabs(Tn - opts->t_min) < opts->eps_t) ambig |= 4;
                     {
                         float zf;
                         memcpy(&zf, &g->zbits, 4);
-                        if (have_prev && fabsf(zf - zprev) <= (float)opts->eps_z_rel * zf) ambig = 1;
+                        if (have_prev && fabsf(zf - zprev) <= (float)opts->eps_z_rel * zf) ambig |= 8;
                         zprev = zf;
                         have_prev = 1;
                     }

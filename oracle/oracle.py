@@ -104,7 +104,9 @@ def render(scene, cam, bg=(0.0, 0.0, 0.0), tile=(16, 16), tile_mask=None, dL_dim
            want_screen=False, **opt_kw) -> dict:
     """Forward (and, with dL_dimg, backward) of one view in float64.
 
-    Returns img [H, W, 3], T [H, W], n_contrib [H, W], ambig [H, W] (bool),
+    Returns img [H, W, 3], T [H, W], n_contrib [H, W], ambig [H, W] (bool;
+    ambig_why holds the reasons as bits: 1 alpha near 1/255, 2 near the 0.99
+    clamp, 4 transmittance near the stop, 8 a float32 depth tie),
     M (pair count) and, with dL_dimg, gradients of every parameter, the 4x4
     pose gradient ``w2c`` and its 6-DoF twist (translation first).
     """
@@ -137,7 +139,7 @@ def render(scene, cam, bg=(0.0, 0.0, 0.0), tile=(16, 16), tile_mask=None, dL_dim
                     _ptr(img, dp), _ptr(T, dp), _ptr(nc, C.c_int32), _ptr(amb, C.c_uint8),
                     _ptr(g, dp), _ptr(gm, dp), _ptr(gl, dp), _ptr(gq, dp), _ptr(go, dp), _ptr(gs, dp),
                     _ptr(gw, dp), _ptr(gscr, dp))
-    out.update(img=img, T=T, n_contrib=nc, ambig=amb.astype(bool), M=int(m))
+    out.update(img=img, T=T, n_contrib=nc, ambig=amb.astype(bool), ambig_why=amb, M=int(m))
     if dL_dimg is not None:
         out.update(means=gm, log_scales=gl, quats=gq, opacities=go, sh=gs, w2c=gw.reshape(4, 4),
                    twist=pose_twist(gw.reshape(4, 4), cam.world_to_cam))

@@ -54,6 +54,7 @@ class Request:
     t_admit: float = float("nan")
     t_done: float = float("nan")
     retries: int = 0
+    call_views: int = 0        # views of the call that served it (renders may be grouped)
     result: Optional[dict] = None
 
     @property
@@ -112,6 +113,7 @@ class GrowingScene:
                      for k, shp in shapes.items()}
         self.n = 0
         self.keyframes = 0
+        self.start = int(start)
         self._append(self._draw(base_seed - 1, start))
 
     def _draw(self, seed: int, count: int) -> S.Scene:
@@ -138,6 +140,17 @@ class GrowingScene:
     def params(self, version: int):
         return [self.bufs[k][:version] for k in PARAM_NAMES]
 
+    def host_scene(self, version: int) -> S.Scene:
+        """The first `version` Gaussians, drawn again on the host from the
+        same seeds (for checks against a reference renderer)."""
+        parts = [self._draw(self.base_seed - 1, self.start)]
+        k = 0
+        while sum(p.n for p in parts) < version:
+            parts.append(self._draw(self.base_seed + k, self.per_keyframe))
+            k += 1
+        cat = {f: np.concatenate([np.asarray(getattr(p, f)) for p in parts])[:version] for f in PARAM_NAMES}
+        return S.Scene(sh_degree=self.sh_degree, **cat)
+
 
 # ----------------------------------------------------------------------------
 # the server
@@ -154,13 +167,22 @@ class Job:
     rgb: torch.Tensor
     grads: Optional[list] = None
     pose_grad: Optional[torch.Tensor] = None
+    upstream: Optional[torch.Tensor] = None
     bytes: int = 0
 
 
 class Server:
     def __init__(self, scene: GrowingScene, slots: int = 4, group_renders: bool = True, max_group_views: int = 8,
                  hbm_budget: Optional[int] = None, keep_results: bool = False, pair_density: float = 3.0e-6,
-                 safety: float = 1.5, tile_h: int = 16):
+                 safety: float = 1.5, tile_h: int = 16, loss: str = "l1"):
+        """loss: "l1" (mean absolute error against the request's seeded
+        U(0, 1) target, its image gradient formed inside the backward) or
+        "upstream" (the backward takes a seeded N(0, 1) image gradient
+        directly: every output is then a fixed function of the request's
+        inputs, which is what a reference comparison needs)."""
+        if loss not in ("l1", "upstream"):
+            raise ValueError(f"loss {loss!r}")
+        self.loss = loss
         self.scene = scene
         self.slots = max(1, int(slots))
         self.group = bool(group_renders)
@@ -176,9 +198,13 @@ class Server:
         self.hbm_budget = int(hbm_budget)
         self.streams = [torch.cuda.Stream() for _ in range(self.slots)]
         self.slot_ws: List[Optional[torch.Tensor]] = [None] * self.slots
-        self.in_flight_bytes = 0
+        # admission accounting: every slot's resident workspace counts, busy
+        # or idle, plus the outputs of the calls in flight
+        self.resident_ws_bytes = 0
+        self.in_flight_bytes = 0   # outputs (images, gradients) of the calls in flight
         self.peak_bytes = 0
         self.peak_bytes_shared = 0  # peak while two or more calls were in flight
+        self.peak_allocated = 0     # measured: allocator peak above the start of the last run
 
     # -- sizing --------------------------------------------------------------
     def _capacity(self, n: int, cams) -> int:
@@ -186,25 +212,45 @@ class Server:
         return int(self.pair_density * n * px * self.safety) + 4096
 
     def _estimate(self, reqs: List[Request]):
+        """(pair capacity, workspace bytes, bytes of the call's outputs):
+        images, plus for an optimise call its target or upstream image, the
+        parameter gradients and the pose gradients."""
         cams = [c for r in reqs for c in r.cams]
         n = max(r.version for r in reqs)
         cap = self._capacity(n, cams)
         ws_bytes = gsr.workspace_bytes(n, cams, cap, gsr.launch_config(self.tile_h))
         px = sum(c.width * c.height for c in cams)
         out = 3 * px * 4 * (2 if reqs[0].kind == "optimise" else 1)
-        grads = n * 4 * (11 + 3 * (self.scene.sh_degree + 1) ** 2) if reqs[0].kind == "optimise" else 0
-        return cap, ws_bytes, ws_bytes + out + grads
+        grads = (n * 4 * (11 + 3 * (self.scene.sh_degree + 1) ** 2) + 88 * len(cams)
+                 if reqs[0].kind == "optimise" else 0)
+        return cap, ws_bytes, out + grads
+
+    def _slot_growth(self, slot: int, ws_bytes: int) -> int:
+        """Bytes the slot's resident workspace would grow by for ws_bytes."""
+        ws = self.slot_ws[slot]
+        have = 0 if ws is None else ws.numel()
+        return 0 if have >= ws_bytes else int(ws_bytes * 1.25) - have
+
+    def _device_bytes(self) -> int:
+        return self.resident_ws_bytes + self.in_flight_bytes
 
     # -- launching -----------------------------------------------------------
     def _launch(self, reqs: List[Request], slot: int, cap: int, ws_bytes: int, est: int) -> Job:
         cams = [c for r in reqs for c in r.cams]
         n = reqs[0].version
+        for r in reqs:
+            r.call_views = len(cams)
         st = self.streams[slot]
         with torch.cuda.stream(st):
             ws = self.slot_ws[slot]
             if ws is None or ws.numel() < ws_bytes:
+                if ws is not None:
+                    self.resident_ws_bytes -= ws.numel()
+                self.slot_ws[slot] = None
+                del ws
                 ws = torch.empty(int(ws_bytes * 1.25), dtype=torch.uint8, device=self.scene.device)
                 self.slot_ws[slot] = ws
+                self.resident_ws_bytes += ws.numel()
             rast = GaussianRasterizer(cams, self.scene.sh_degree, tile_h=self.tile_h, sync=False,
                                       device=self.scene.device)
             params = self.scene.params(n)
@@ -213,9 +259,14 @@ class Server:
             rgb, _ = rast.forward(params, w2c, (0.0, 0.0, 0.0), ws=ws)
             job = Job(reqs, st, slot, torch.cuda.Event(), rast, ws, rgb, bytes=est)
             if reqs[0].kind == "optimise":
-                # L1 against the request's target, upstream formed inside the backward
-                target = self._target(reqs[0], rgb.numel())
-                job.grads, job.pose_grad, _ = rast.backward_l1(ws, params, w2c, (0.0, 0.0, 0.0), rgb, target)
+                if self.loss == "l1":
+                    # L1 against the request's target, upstream formed inside the backward
+                    target = self._target(reqs[0], rgb.numel())
+                    job.grads, job.pose_grad, _ = rast.backward_l1(ws, params, w2c, (0.0, 0.0, 0.0), rgb, target)
+                else:
+                    job.upstream = self._upstream(reqs[0], rgb.numel())
+                    job.grads, job.pose_grad, _ = rast.backward(ws, params, w2c, (0.0, 0.0, 0.0), rgb,
+                                                                job.upstream)
             job.done.record(st)
         return job
 
@@ -223,6 +274,11 @@ class Server:
         g = torch.Generator(device=self.scene.device)
         g.manual_seed(req.target_seed)
         return torch.rand(numel, generator=g, device=self.scene.device)
+
+    def _upstream(self, req: Request, numel: int) -> torch.Tensor:
+        g = torch.Generator(device=self.scene.device)
+        g.manual_seed(req.target_seed)
+        return torch.randn(numel, generator=g, device=self.scene.device)
 
     # -- the loop ------------------------------------------------------------
     def run(self, requests: List[Request], keyframe_period: float = 0.5, start_n: Optional[int] = None,
@@ -240,6 +296,9 @@ class Server:
         pending = collections.deque()
         retry = collections.deque()
         in_flight: Dict[int, Job] = {}
+        torch.cuda.synchronize(self.scene.device)
+        base_alloc = torch.cuda.memory_allocated(self.scene.device)
+        torch.cuda.reset_peak_memory_stats(self.scene.device)
         free_slots = list(range(self.slots))
         nxt = 0
         done = 0
@@ -264,17 +323,20 @@ class Server:
                 tdone = clock()
                 del in_flight[slot]
                 free_slots.append(slot)
-                self.in_flight_bytes -= job.bytes
                 needed, cap, ovf = gsr.query_pairs(job.ws, job.stream)
                 px = sum(c.width * c.height for r in job.reqs for c in r.cams)
                 self.pair_density = max(self.pair_density, needed / max(1, job.reqs[0].version * px))
                 if ovf:
+                    self.in_flight_bytes -= job.bytes
                     for r in job.reqs:
                         r.retries += 1
                         retry.append(r)
+                    del job
                     continue
                 self._finish(job, tdone)
+                self.in_flight_bytes -= job.bytes
                 done += len(job.reqs)
+                del job  # its outputs go back to the allocator now, not at the next completion
             # admissions
             while free_slots and (retry or pending):
                 src = retry if retry else pending
@@ -290,17 +352,26 @@ class Server:
                             group.append(r)
                             views += len(r.cams)
                 cap, ws_bytes, est = self._estimate(group)
-                if self.in_flight_bytes + est > self.hbm_budget and in_flight:
-                    break  # wait for memory to free up
+                # the slot whose resident workspace needs the least growth
+                slot = min(free_slots, key=lambda k: (self._slot_growth(k, ws_bytes), k))
+                need = self._slot_growth(slot, ws_bytes) + est
+                if self._device_bytes() + need > self.hbm_budget:
+                    # idle slots give back their workspaces first
+                    for k in free_slots:
+                        if k != slot and self.slot_ws[k] is not None:
+                            self.resident_ws_bytes -= self.slot_ws[k].numel()
+                            self.slot_ws[k] = None
+                    if self._device_bytes() + need > self.hbm_budget and in_flight:
+                        break  # wait for memory to free up (a call larger than the budget runs alone)
                 for r in group:
                     src.remove(r)
                     r.t_admit = clock()
-                slot = free_slots.pop()
+                free_slots.remove(slot)
                 self.in_flight_bytes += est
-                self.peak_bytes = max(self.peak_bytes, self.in_flight_bytes)
-                if in_flight:
-                    self.peak_bytes_shared = max(self.peak_bytes_shared, self.in_flight_bytes)
                 in_flight[slot] = self._launch(group, slot, cap, ws_bytes, est)
+                self.peak_bytes = max(self.peak_bytes, self._device_bytes())
+                if len(in_flight) > 1:
+                    self.peak_bytes_shared = max(self.peak_bytes_shared, self._device_bytes())
             if not in_flight and not pending and not retry and nxt < len(reqs):
                 wait = (reqs[nxt].t_arrival - clock()) / time_scale
                 if wait > 0:
@@ -308,26 +379,37 @@ class Server:
             elif in_flight:
                 time.sleep(0.00005)
         wall = clock()
+        torch.cuda.synchronize(self.scene.device)
+        self.peak_allocated = torch.cuda.max_memory_allocated(self.scene.device) - base_alloc
         return self._summary(reqs, wall)
 
     def _finish(self, job: Job, tdone: float):
+        """Results of a completed call.  The copies run on the call's own
+        stream, where its outputs were allocated: once the job is dropped the
+        allocator may hand those blocks to the slot's next call, which that
+        stream orders after the copies."""
         off = 0
-        for r in job.reqs:
-            r.t_done = tdone
+        with torch.cuda.stream(job.stream):
+            for r in job.reqs:
+                r.t_done = tdone
+                if self.keep:
+                    res = {}
+                    views = []
+                    for c in r.cams:
+                        k = 3 * c.width * c.height
+                        views.append(job.rgb[off:off + k].detach().clone())
+                        off += k
+                    res["rgb"] = views
+                    if job.grads is not None:
+                        res["grads"] = [g.detach().clone() for g in job.grads]
+                        res["pose_grad"] = job.pose_grad.detach().clone()
+                    if job.upstream is not None:
+                        res["upstream"] = job.upstream.detach().clone()
+                    r.result = res
+                else:
+                    off += sum(3 * c.width * c.height for c in r.cams)
             if self.keep:
-                res = {}
-                views = []
-                for c in r.cams:
-                    k = 3 * c.width * c.height
-                    views.append(job.rgb[off:off + k].detach().clone())
-                    off += k
-                res["rgb"] = views
-                if job.grads is not None:
-                    res["grads"] = [g.detach().clone() for g in job.grads]
-                    res["pose_grad"] = job.pose_grad.detach().clone()
-                r.result = res
-            else:
-                off += sum(3 * c.width * c.height for c in r.cams)
+                job.stream.synchronize()
 
     def _summary(self, reqs: List[Request], wall: float) -> dict:
         lat = np.array([r.t_done - r.t_arrival for r in reqs]) * 1e3
@@ -349,6 +431,7 @@ class Server:
             "pixel_gaussians_per_s": px_g / wall,
             "retries": int(sum(r.retries for r in reqs)),
             "peak_inflight_bytes": int(self.peak_bytes),
+            "peak_allocated_bytes": int(self.peak_allocated),
             "peak_shared_inflight_bytes": int(self.peak_bytes_shared),
             "hbm_budget": int(self.hbm_budget),
             "by_kind": by_kind,

@@ -14,31 +14,13 @@ from oracle import oracle as O
 from paper_2607_14481_amd import gsr
 from paper_2607_14481_amd import scenes as S
 
-from ._util import GRAD_KEYS, gpu_render, log, oracle_bin_from_gpu_state, rel_err
+from ._util import (GRAD_KEYS, GRAD_TOL, IMG_TOL, compare_grads, compare_view, gpu_render, log,
+                    oracle_bin_from_gpu_state, rel_err)
 
 pytestmark = pytest.mark.gpu
 
-IMG_TOL = 1e-4
-GRAD_TOL = 1e-3
-
-
-def _compare_view(gpu_img, ref, label):
-    amb = ref["ambig"]
-    diff = np.abs(gpu_img.astype(np.float64) - ref["img"])
-    ok = ~amb
-    worst = float(diff[ok].max()) if ok.any() else 0.0
-    worst_amb = float(diff[amb].max()) if amb.any() else 0.0
-    log(f"{label}: max|d img| = {worst:.3e} over {ok.sum()} px; ambiguous px = {int(amb.sum())} "
-        f"(max|d| there {worst_amb:.3e})")
-    assert worst <= IMG_TOL, label
-    assert amb.mean() < 1e-3
-
-
-def _compare_grads(gpu, ref, label, keys=GRAD_KEYS):
-    for k in keys:
-        e = rel_err(gpu[k], ref[k])
-        log(f"{label}: rel err d{k} = {e:.3e}")
-        assert e <= GRAD_TOL, (label, k, e)
+_compare_view = compare_view
+_compare_grads = compare_grads
 
 
 def _upstream(seed, cams):
