@@ -35,8 +35,10 @@
  * laid out [3][H_v][W_v], views concatenated in order.
  *
  * Memory and ownership.  Every buffer passed in is owned by the caller.  The
- * library never allocates or frees device memory and keeps no mutable global
- * state.  Device pointers must be 16-byte aligned.  The workspace carries the
+ * library never allocates or frees device memory, and holds no host buffers,
+ * events or other state between calls apart from each thread's last-error
+ * message (and the host plans of the bundle adjustment, owned by the caller
+ * through gsr_ba_plan_destroy).  Device pointers must be 16-byte aligned.  The workspace carries the
  * forward pass's state to the backward pass: do not reuse it for another
  * forward between a forward and its backward.  One workspace per in-flight
  * iteration; calls on different workspaces and streams are independent.
@@ -71,7 +73,7 @@
 extern "C" {
 #endif
 
-#define GSR_ABI_VERSION 2
+#define GSR_ABI_VERSION 3
 
 /* Status codes. */
 #define GSR_OK 0
@@ -145,7 +147,15 @@ typedef struct gsr_launch_config {
        gsr_stats.longest_list); a list no pass covers is sorted by one
        workgroup, which is exact but slow for very long lists. */
     int32_t long_list_passes;
-    int32_t reserved[3];
+    int32_t reserved0;
+    /* NULL, or a device int64: only Gaussians i < *active_count take part in
+       the call (i < n always); the others are treated as culled (no pairs,
+       zero gradients) and their parameters are never read.  It lets a size
+       computed on the device, such as the count gsr_hierarchy_cut writes,
+       drive the rasterizer without a host round trip (n is then the capacity
+       of the parameter arrays and sizes the workspace).  Must be the same
+       for a forward and its backward. */
+    const int64_t *active_count;
 } gsr_launch_config;
 
 /* Work counters of the last forward (see gsr_query_stats). */
@@ -342,27 +352,38 @@ size_t gsr_hierarchy_cut_scratch_bytes(int64_t n_nodes);
  * leaves), device int32.  With S(i) = max(fx, fy) exp(max_a log_scale_a(i)) /
  * |mean(i) - camera centre| (double precision), node i is in the cut when it
  * is a leaf or S(i) < tau, and every ancestor has children and S >= tau.
- * cut_nodes [n] (device) receives the cut in ascending node order and *n_cut
- * (host) its size.  world_to_cam: device [16] of the view.  scratch: device
- * memory of gsr_hierarchy_cut_scratch_bytes(n) bytes, 256-byte aligned.
- * Blocking: waits for `stream` to read the count.  Ancestor chains longer than
- * 64 (or cyclic parent links) end the chain: such a node is not in the cut.
+ * cut_nodes [n] (device) receives the cut in ascending node order.  Its size
+ * goes to n_cut_device (device int64, written on `stream`, so that a gather
+ * and a rasterization enqueued after it can read it without a host round
+ * trip: see gsr_gather_gaussians and gsr_launch_config.active_count) and/or
+ * to *n_cut (host); at least one of the two must be given, and with n_cut the
+ * call blocks until the count has been read back.  world_to_cam: device [16]
+ * of the view.  scratch: device memory of gsr_hierarchy_cut_scratch_bytes(n)
+ * bytes, 256-byte aligned, used only during the call's kernels.  Without
+ * n_cut the call neither allocates nor synchronises, so it can be captured in
+ * a HIP graph.  Ancestor chains longer than 64 (or cyclic parent links) end
+ * the chain: such a node is not in the cut.
  */
 int gsr_hierarchy_cut(const gsr_gaussians *nodes, const int32_t *parent, const int32_t *child_count,
                       const gsr_camera *cam, const float *world_to_cam, float tau, void *scratch,
-                      size_t scratch_bytes, int32_t *cut_nodes, int64_t *n_cut, void *stream);
+                      size_t scratch_bytes, int32_t *cut_nodes, int64_t *n_cut_device, int64_t *n_cut,
+                      void *stream);
 
-/* Copies rows index[0 .. n_index) of src into rows 0 .. n_index of dst (all
-   five arrays; src->sh_degree gives the SH row length), e.g. to rasterize a
-   cut.  index: device int32, each in [0, src->n). */
-int gsr_gather_gaussians(const gsr_gaussians *src, const int32_t *index, int64_t n_index,
+/* Copies rows index[0 .. m) of src into rows 0 .. m of dst (all five arrays;
+   src->sh_degree gives the SH row length), e.g. to rasterize a cut.  index:
+   device int32, each in [0, src->n).  m = n_index, or, when count (a device
+   int64, e.g. the n_cut_device of gsr_hierarchy_cut on the same stream) is
+   given, min(*count, n_index) read on the device; rows of dst from m on are
+   left untouched.  Never synchronises. */
+int gsr_gather_gaussians(const gsr_gaussians *src, const int32_t *index, int64_t n_index, const int64_t *count,
                          const gsr_param_set *dst, void *stream);
 
 /* ------------------------------------------------------------------------
- * Local bundle adjustment (Sec. 4.3, "Local Bundle Adjustment" and "Solver
- * efficiency"; appendix "Fast Bundle Adjustment"): keyframe poses, one shared
- * focal length and a fixed set of landmarks, each seen by a fixed subset of
- * the keyframes, refined by Levenberg-Marquardt steps solved through a dense
+ * Local bundle adjustment (Sec. 5.1, "Local Bundle Adjustment" and "Solver
+ * efficiency"; appendix "Details on Local Pose Reconstruction", paragraph
+ * "Fast Bundle Adjustment"): keyframe poses, one shared focal length and a
+ * fixed set of landmarks, each seen by a fixed subset of the keyframes,
+ * refined by Levenberg-Marquardt steps solved through a dense
  * Schur complement over the camera unknowns.  All arithmetic is FP64.
  *
  * Model: the observation of landmark j in keyframe i predicts

@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY: nothing in the product imports this module.  Plain
 numpy (scipy's matrix exponential for the pose retraction), written from the
 definitions with no blocking or fusion.
 
-The problem is the paper's local BA (Sec. 4.3, "Local Bundle Adjustment", and
+The problem is the paper's local BA (Sec. 5.1, "Local Bundle Adjustment", and
 the appendix paragraph "Fast Bundle Adjustment"): N keyframes of which n_f are
 held fixed, K landmarks each observed by a fixed subset of the keyframes, GPU
 residual and Jacobian kernels and a dense Schur complement; its runtime is

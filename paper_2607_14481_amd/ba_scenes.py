@@ -9,7 +9,7 @@ what it returns.
 The paper times its local BA on a synthesized problem with 20 keyframes and
 10,000 landmarks, 4 of the keyframes held fixed, each landmark seen by a fixed
 covisibility-chosen subset of the keyframes, and the focal length optimised
-(Sec. 4.3 and the BA runtime table).  The recipe here:
+(Sec. 5.1 and the BA runtime table).  The recipe here:
 
 * keyframes on a 120-degree arc of radius 4 around the origin, with small
   height jitter, each looking at the origin (x right, y down, z forward);

@@ -233,44 +233,16 @@ struct StageMark {
     }
 };
 
-// Number of tile-sort passes decides which ping-pong buffer holds the result.
-// The synchronous forward's header readback: into pinned host memory (one
-// buffer and event per thread and device, created on first use and kept until
-// the process ends) and a spin on the event rather than a blocking stream
-// wait, so the host resumes launching as soon as the copy lands.
+// The synchronous forward's header readback: a copy into the caller's stack
+// frame on the forward's stream, then a wait for that stream.  The library
+// keeps no host buffers or events of its own.
 int read_header_now(const gsr::WsHeader *dev_hdr, gsr::WsHeader &out, hipStream_t st) {
-    struct Slot {
-        gsr::WsHeader *host = nullptr;
-        hipEvent_t ev = nullptr;
-    };
-    thread_local Slot slots[64];
-    int dev = 0;
-    int rc = check_hip(hipGetDevice(&dev), "current device");
+    int rc = check_hip(hipMemcpyAsync(&out, dev_hdr, sizeof(out), hipMemcpyDeviceToHost, st), "header copy");
     if (rc) return rc;
-    if (dev < 0 || dev >= 64) {  // outside the table: a plain blocking copy
-        if ((rc = check_hip(hipMemcpyAsync(&out, dev_hdr, sizeof(out), hipMemcpyDeviceToHost, st), "header copy")))
-            return rc;
-        return check_hip(hipStreamSynchronize(st), "stream sync");
-    }
-    Slot &s = slots[dev];
-    if (!s.host) {
-        if ((rc = check_hip(hipHostMalloc(reinterpret_cast<void **>(&s.host), sizeof(gsr::WsHeader), 0),
-                            "pinned header buffer")))
-            return rc;
-        if ((rc = check_hip(hipEventCreateWithFlags(&s.ev, hipEventDisableTiming), "header event"))) return rc;
-    }
-    if ((rc = check_hip(hipMemcpyAsync(s.host, dev_hdr, sizeof(out), hipMemcpyDeviceToHost, st), "header copy")))
-        return rc;
-    if ((rc = check_hip(hipEventRecord(s.ev, st), "header event record"))) return rc;
-    for (;;) {
-        const hipError_t e = hipEventQuery(s.ev);
-        if (e == hipSuccess) break;
-        if (e != hipErrorNotReady) return check_hip(e, "header event wait");
-    }
-    std::memcpy(&out, s.host, sizeof(out));
-    return GSR_OK;
+    return check_hip(hipStreamSynchronize(st), "stream sync");
 }
 
+// Number of tile-sort passes decides which ping-pong buffer holds the result.
 int pair_result_buffer(uint32_t total_tiles) { return ((tile_bits(total_tiles) + 7) / 8) & 1; }
 
 }  // namespace
@@ -382,7 +354,8 @@ int gsr_rasterize_forward(void *ws, size_t ws_bytes, const gsr_gaussians *g, int
     const StageMark mark{cfg ? static_cast<hipEvent_t *>(cfg->stage_events) : nullptr, st};
 
     mark.begin(GSR_STAGE_PROJECT);
-    launch_project_fwd(*g, vt, world_to_cam, n, p.rec, p.ulo, p.zkey, p.count, p.hdr, (uint32_t)cap, st);
+    launch_project_fwd(*g, vt, world_to_cam, n, p.rec, p.ulo, p.zkey, p.count, p.hdr, (uint32_t)cap,
+                       cfg ? cfg->active_count : nullptr, st);
     mark.end(GSR_STAGE_PROJECT);
     mark.begin(GSR_STAGE_COMPACT);
     launch_visible_offsets(vt, n, p.count, p.rec, p.zkey, L.items, p.vis, p.poff, p.item_box, p.chunk_item, L.chunks,
@@ -684,21 +657,26 @@ size_t gsr_hierarchy_cut_scratch_bytes(int64_t n_nodes) {
 
 int gsr_hierarchy_cut(const gsr_gaussians *nodes, const int32_t *parent, const int32_t *child_count,
                       const gsr_camera *cam, const float *world_to_cam, float tau, void *scratch, size_t scratch_bytes,
-                      int32_t *cut_nodes, int64_t *n_cut, void *stream) {
+                      int32_t *cut_nodes, int64_t *n_cut_device, int64_t *n_cut, void *stream) {
     using namespace gsr;
-    if (!nodes || !cam || !n_cut) return fail(GSR_ERR_INVALID_ARGUMENT, "nodes, cam and n_cut must not be NULL");
+    if (!nodes || !cam) return fail(GSR_ERR_INVALID_ARGUMENT, "nodes and cam must not be NULL");
+    if (!n_cut && !n_cut_device) return fail(GSR_ERR_INVALID_ARGUMENT, "n_cut and n_cut_device are both NULL");
     if (nodes->n < 0 || nodes->n > 0x7fffffffll)
         return fail(GSR_ERR_INVALID_ARGUMENT, "n=%lld outside 0..2^31-1", (long long)nodes->n);
     if (!(tau > 0.f)) return fail(GSR_ERR_INVALID_ARGUMENT, "tau must be positive");
     const uint64_t n = (uint64_t)nodes->n;
-    *n_cut = 0;
-    if (n == 0) return GSR_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (n_cut) *n_cut = 0;
+    if (n == 0) {
+        if (!n_cut_device) return GSR_OK;
+        launch_store_count_i64(nullptr, n_cut_device, st);
+        return check_hip(hipGetLastError(), "cut count launch");
+    }
     if (!nodes->means || !nodes->log_scales || !parent || !child_count || !world_to_cam || !scratch || !cut_nodes)
         return fail(GSR_ERR_INVALID_ARGUMENT, "a device pointer is NULL");
     if (reinterpret_cast<uintptr_t>(scratch) & 255u) return fail(GSR_ERR_INVALID_ARGUMENT, "scratch must be 256-byte aligned");
     const CutScratch L = cut_scratch_layout(n);
     if (scratch_bytes < L.total) return fail(GSR_ERR_WORKSPACE_TOO_SMALL, "scratch %zu < %zu bytes", scratch_bytes, L.total);
-    hipStream_t st = static_cast<hipStream_t>(stream);
     char *b = static_cast<char *>(scratch);
     uint8_t *descend = reinterpret_cast<uint8_t *>(b + L.descend), *in_cut = reinterpret_cast<uint8_t *>(b + L.in_cut);
     uint32_t *count = reinterpret_cast<uint32_t *>(b + L.count);
@@ -706,16 +684,18 @@ int gsr_hierarchy_cut(const gsr_gaussians *nodes, const int32_t *parent, const i
                                std::max(cam->fx, cam->fy), tau, descend, in_cut, st);
     launch_compact_flags(in_cut, n, reinterpret_cast<uint32_t *>(cut_nodes), reinterpret_cast<uint32_t *>(b + L.block_tmp),
                          count, st);
+    if (n_cut_device) launch_store_count_i64(count, n_cut_device, st);
+    int rc = check_hip(hipGetLastError(), "cut launch");
+    if (rc || !n_cut) return rc;
     uint32_t h = 0;
-    int rc = check_hip(hipMemcpyAsync(&h, count, 4, hipMemcpyDeviceToHost, st), "cut count copy");
-    if (rc) return rc;
+    if ((rc = check_hip(hipMemcpyAsync(&h, count, 4, hipMemcpyDeviceToHost, st), "cut count copy"))) return rc;
     if ((rc = check_hip(hipStreamSynchronize(st), "stream sync"))) return rc;
     *n_cut = h;
     return GSR_OK;
 }
 
-int gsr_gather_gaussians(const gsr_gaussians *src, const int32_t *index, int64_t n_index, const gsr_param_set *dst,
-                         void *stream) {
+int gsr_gather_gaussians(const gsr_gaussians *src, const int32_t *index, int64_t n_index, const int64_t *count,
+                         const gsr_param_set *dst, void *stream) {
     using namespace gsr;
     int rc = check_gaussians(src);
     if (rc) return rc;
@@ -725,7 +705,7 @@ int gsr_gather_gaussians(const gsr_gaussians *src, const int32_t *index, int64_t
         return fail(GSR_ERR_INVALID_ARGUMENT, "index or a destination array is NULL");
     if ((reinterpret_cast<uintptr_t>(dst->quats) | reinterpret_cast<uintptr_t>(dst->sh)) & 15u)
         return fail(GSR_ERR_INVALID_ARGUMENT, "dst quats and sh must be 16-byte aligned");
-    launch_gather_gaussians(*src, index, (uint64_t)n_index, *dst, static_cast<hipStream_t>(stream));
+    launch_gather_gaussians(*src, index, (uint64_t)n_index, count, *dst, static_cast<hipStream_t>(stream));
     return check_hip(hipGetLastError(), "gather launch");
 }
 

@@ -1,6 +1,7 @@
 // gsr_ba.hip -- local bundle adjustment with a dense Schur complement on
-// gfx950, in FP64 (Sec. 4.3, "Local Bundle Adjustment" and "Solver
-// efficiency"; appendix "Fast Bundle Adjustment").
+// gfx950, in FP64 (Sec. 5.1, "Local Bundle Adjustment" and "Solver
+// efficiency"; appendix "Details on Local Pose Reconstruction", paragraph
+// "Fast Bundle Adjustment").
 //
 // Unknowns: the free keyframe poses (a left twist (rho, phi) each, translation
 // first), one shared focal length f, and the landmarks.  Residual of the

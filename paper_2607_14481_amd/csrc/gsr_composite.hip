@@ -532,21 +532,16 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
 }
 
 // Workgroups of a persistent launch: as many as can be resident at once
-// (occupancy of this kernel x compute units), unless the caller fixed it.
+// (occupancy of this kernel x compute units of the current device, queried at
+// each launch: nothing is cached between calls), unless the caller fixed it.
 template <typename Kernel>
 static int resident_ctas(Kernel kernel, int requested) {
     if (requested > 0) return requested;
-    static int cache[64][2];  // per device: (compute units, blocks per CU); written once, same value each time
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
-    if (cache[dev][0] == 0) {
-        int cus = 0, per = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kWave, 0) != hipSuccess || per <= 0) per = 8;
-        cache[dev][1] = per;
-        cache[dev][0] = cus;
-    }
-    return cache[dev][0] * cache[dev][1];
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kWave, 0) != hipSuccess || per <= 0) per = 8;
+    return cus * per;
 }
 
 void launch_composite_fwd(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,

@@ -71,8 +71,9 @@ void launch_hierarchy_cut_flags(const float *means, const float *log_scales, con
 // row), quaternions as float4, opacities as floats, SH as float4 when a row is
 // a multiple of 16 bytes, else as floats.
 template <int K>
-__global__ __launch_bounds__(256) void k_gather(gsr_gaussians src, const int32_t *__restrict__ index, uint64_t n_out,
-                                                gsr_param_set dst) {
+__global__ __launch_bounds__(256) void k_gather(gsr_gaussians src, const int32_t *__restrict__ index, uint64_t n_max,
+                                                const int64_t *__restrict__ count, gsr_param_set dst) {
+    const uint64_t n_out = count ? (uint64_t)min((int64_t)n_max, max(*count, (int64_t)0)) : n_max;
     constexpr bool kVec = (3 * K) % 4 == 0;
     constexpr uint64_t kShUnits = kVec ? 3 * K / 4 : 3 * K;  // SH units per row
     const uint64_t s0 = 3 * n_out, s1 = s0 + 3 * n_out, s2 = s1 + n_out, s3 = s2 + n_out;
@@ -102,16 +103,25 @@ __global__ __launch_bounds__(256) void k_gather(gsr_gaussians src, const int32_t
     }
 }
 
-void launch_gather_gaussians(const gsr_gaussians &src, const int32_t *index, uint64_t n_out, const gsr_param_set &dst,
-                             hipStream_t st) {
+void launch_gather_gaussians(const gsr_gaussians &src, const int32_t *index, uint64_t n_out, const int64_t *count,
+                             const gsr_param_set &dst, hipStream_t st) {
     if (n_out == 0) return;
     const dim3 grid(4096);  // grid-stride walk
     switch (src.sh_degree) {
-        case 0: hipLaunchKernelGGL(k_gather<1>, grid, dim3(256), 0, st, src, index, n_out, dst); break;
-        case 1: hipLaunchKernelGGL(k_gather<4>, grid, dim3(256), 0, st, src, index, n_out, dst); break;
-        case 2: hipLaunchKernelGGL(k_gather<9>, grid, dim3(256), 0, st, src, index, n_out, dst); break;
-        default: hipLaunchKernelGGL(k_gather<16>, grid, dim3(256), 0, st, src, index, n_out, dst); break;
+        case 0: hipLaunchKernelGGL(k_gather<1>, grid, dim3(256), 0, st, src, index, n_out, count, dst); break;
+        case 1: hipLaunchKernelGGL(k_gather<4>, grid, dim3(256), 0, st, src, index, n_out, count, dst); break;
+        case 2: hipLaunchKernelGGL(k_gather<9>, grid, dim3(256), 0, st, src, index, n_out, count, dst); break;
+        default: hipLaunchKernelGGL(k_gather<16>, grid, dim3(256), 0, st, src, index, n_out, count, dst); break;
     }
+}
+
+// The cut's size as the device int64 that gathers and rasterizations read.
+__global__ void k_store_count_i64(const uint32_t *__restrict__ count, int64_t *__restrict__ out) {
+    if (threadIdx.x == 0) *out = count ? (int64_t)*count : 0;
+}
+
+void launch_store_count_i64(const uint32_t *count, int64_t *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_store_count_i64, dim3(1), dim3(64), 0, st, count, out);
 }
 
 }  // namespace gsr

@@ -126,7 +126,7 @@ void launch_reset_header(WsHeader *h, uint32_t cap, hipStream_t st);
 // Also resets the workspace header (pair capacity cap) for this forward.
 void launch_project_fwd(const gsr_gaussians &g, const ViewTable &vt, const float *w2c, uint64_t n,
                         Rec *rec, float2 *ulo, uint32_t *zkey, uint32_t *count, WsHeader *hdr, uint32_t cap,
-                        hipStream_t st);
+                        const int64_t *active, hipStream_t st);
 
 // Exclusive scans / compaction / sorting / binning.
 // Visible items (ascending ids), their pair offsets (also into each record's
@@ -231,8 +231,9 @@ inline uint64_t scan_blocks_for(uint64_t n) { return (n + kScanTile - 1) / kScan
 void launch_hierarchy_cut_flags(const float *means, const float *log_scales, const int32_t *parent,
                                 const int32_t *child_count, uint64_t n, const float *w2c, float focal, float tau,
                                 uint8_t *descend, uint8_t *in_cut, hipStream_t st);
-void launch_gather_gaussians(const gsr_gaussians &src, const int32_t *index, uint64_t n_out, const gsr_param_set &dst,
-                             hipStream_t st);
+void launch_gather_gaussians(const gsr_gaussians &src, const int32_t *index, uint64_t n_out, const int64_t *count,
+                             const gsr_param_set &dst, hipStream_t st);
+void launch_store_count_i64(const uint32_t *count, int64_t *out, hipStream_t st);
 
 // Parameter updates (gsr_update.hip).
 struct AdamScalars {

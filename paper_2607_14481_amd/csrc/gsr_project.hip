@@ -144,7 +144,8 @@ __global__ __launch_bounds__(kProjThreads) void k_project_fwd(gsr_gaussians g, V
                                                               Rec *__restrict__ rec, float2 *__restrict__ ulo,
                                                               uint32_t *__restrict__ zkey,
                                                               uint32_t *__restrict__ count,
-                                                              WsHeader *__restrict__ hdr, uint32_t cap) {
+                                                              WsHeader *__restrict__ hdr, uint32_t cap,
+                                                              const int64_t *__restrict__ active) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     if (blockIdx.x == 0 && threadIdx.x < sizeof(WsHeader) / 4) {
         // a fresh header for this forward (read first by the visible-item scan)
@@ -154,6 +155,11 @@ __global__ __launch_bounds__(kProjThreads) void k_project_fwd(gsr_gaussians g, V
     if (item >= n * (uint64_t)vt.n_views) return;
     const int v = (int)(item / n);
     const uint64_t i = item - (uint64_t)v * n;
+    if (active && (int64_t)i >= *active) {  // beyond the device-given count: culled, nothing read
+        zkey[item] = kCulledKey;
+        count[item] = 0;
+        return;
+    }
     const ViewInfo cam = vt.v[v];
 
     float Wf[9], tf[3];
@@ -257,7 +263,8 @@ __global__ __launch_bounds__(kProjThreads) void k_project_fwd(gsr_gaussians g, V
 }
 
 void launch_project_fwd(const gsr_gaussians &g, const ViewTable &vt, const float *w2c, uint64_t n, Rec *rec,
-                        float2 *ulo, uint32_t *zkey, uint32_t *count, WsHeader *hdr, uint32_t cap, hipStream_t st) {
+                        float2 *ulo, uint32_t *zkey, uint32_t *count, WsHeader *hdr, uint32_t cap,
+                        const int64_t *active, hipStream_t st) {
     const uint64_t items = n * (uint64_t)vt.n_views;
     if (items == 0) {
         launch_reset_header(hdr, cap, st);
@@ -265,10 +272,10 @@ void launch_project_fwd(const gsr_gaussians &g, const ViewTable &vt, const float
     }
     const dim3 grid((unsigned)((items + kProjThreads - 1) / kProjThreads));
     switch (g.sh_degree) {
-        case 0: hipLaunchKernelGGL(k_project_fwd<0>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, ulo, zkey, count, hdr, cap); break;
-        case 1: hipLaunchKernelGGL(k_project_fwd<1>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, ulo, zkey, count, hdr, cap); break;
-        case 2: hipLaunchKernelGGL(k_project_fwd<2>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, ulo, zkey, count, hdr, cap); break;
-        default: hipLaunchKernelGGL(k_project_fwd<3>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, ulo, zkey, count, hdr, cap); break;
+        case 0: hipLaunchKernelGGL(k_project_fwd<0>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, ulo, zkey, count, hdr, cap, active); break;
+        case 1: hipLaunchKernelGGL(k_project_fwd<1>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, ulo, zkey, count, hdr, cap, active); break;
+        case 2: hipLaunchKernelGGL(k_project_fwd<2>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, ulo, zkey, count, hdr, cap, active); break;
+        default: hipLaunchKernelGGL(k_project_fwd<3>, grid, dim3(kProjThreads), 0, st, g, vt, w2c, n, rec, ulo, zkey, count, hdr, cap, active); break;
     }
 }
 

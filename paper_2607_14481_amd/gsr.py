@@ -61,7 +61,7 @@ class gsr_gaussian_grads(C.Structure):
 
 class gsr_launch_config(C.Structure):
     _fields_ = [("tile_h", C.c_int32), ("persistent_ctas", C.c_int32), ("stage_events", C.c_void_p),
-                ("long_list_passes", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("long_list_passes", C.c_int32), ("reserved0", C.c_int32), ("active_count", C.c_void_p)]
 
 
 class gsr_param_set(C.Structure):
@@ -135,9 +135,10 @@ def lib():
         L.gsr_hierarchy_cut_scratch_bytes.argtypes = [C.c_int64]
         L.gsr_hierarchy_cut.restype = C.c_int
         L.gsr_hierarchy_cut.argtypes = [C.POINTER(gsr_gaussians), vp, vp, C.POINTER(gsr_camera), vp, C.c_float, vp,
-                                        sz, vp, C.POINTER(C.c_int64), vp]
+                                        sz, vp, vp, C.POINTER(C.c_int64), vp]
         L.gsr_gather_gaussians.restype = C.c_int
-        L.gsr_gather_gaussians.argtypes = [C.POINTER(gsr_gaussians), vp, C.c_int64, C.POINTER(gsr_param_set), vp]
+        L.gsr_gather_gaussians.argtypes = [C.POINTER(gsr_gaussians), vp, C.c_int64, vp, C.POINTER(gsr_param_set),
+                                           vp]
         L.gsr_ba_workspace_bytes.restype = sz
         L.gsr_ba_workspace_bytes.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32]
         L.gsr_ba_plan_create.restype = C.c_int
@@ -194,11 +195,18 @@ def cameras(cams: Sequence) -> "C.Array[gsr_camera]":
     return arr
 
 
-def launch_config(tile_h: int = 16, persistent_ctas: int = 0, long_list_passes: int = 0) -> gsr_launch_config:
+def launch_config(tile_h: int = 16, persistent_ctas: int = 0, long_list_passes: int = 0,
+                  active_count: Optional[torch.Tensor] = None) -> gsr_launch_config:
+    """active_count: None, or a one-element int64 device tensor (see
+    gsr_launch_config.active_count); the caller keeps it alive."""
     cfg = gsr_launch_config()
     cfg.tile_h = int(tile_h)
     cfg.persistent_ctas = int(persistent_ctas)
     cfg.long_list_passes = int(long_list_passes)
+    if active_count is not None:
+        if active_count.dtype != torch.int64 or not active_count.is_cuda:
+            raise TypeError("active_count must be an int64 GPU tensor")
+        cfg.active_count = active_count.data_ptr()
     return cfg
 
 
@@ -384,10 +392,7 @@ def sim3_relocate(params: Sequence[torch.Tensor], keyframe_of: torch.Tensor, sim
                                    _ptr(sim3), int(sim3.shape[0]), _stream_ptr(stream)))
 
 
-def hierarchy_cut(nodes: Sequence[torch.Tensor], sh_degree: int, parent: torch.Tensor, child_count: torch.Tensor,
-                  cam, world_to_cam: torch.Tensor, tau: float = 1.5, scratch: Optional[torch.Tensor] = None,
-                  out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
-    """Node indices (int32, ascending) of the per-view cut; see gsr_hierarchy_cut."""
+def _cut_args(nodes, parent, child_count, scratch, out):
     n = int(nodes[0].shape[0])
     if parent.dtype != torch.int32 or child_count.dtype != torch.int32:
         raise TypeError("parent and child_count must be int32")
@@ -396,20 +401,57 @@ def hierarchy_cut(nodes: Sequence[torch.Tensor], sh_degree: int, parent: torch.T
         scratch = torch.empty(max(need, 1), dtype=torch.uint8, device=nodes[0].device)
     if out is None or out.numel() < n:
         out = torch.empty(max(n, 1), dtype=torch.int32, device=nodes[0].device)
+    return scratch, out
+
+
+def hierarchy_cut(nodes: Sequence[torch.Tensor], sh_degree: int, parent: torch.Tensor, child_count: torch.Tensor,
+                  cam, world_to_cam: torch.Tensor, tau: float = 1.5, scratch: Optional[torch.Tensor] = None,
+                  out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Node indices (int32, ascending) of the per-view cut; see
+    gsr_hierarchy_cut.  Blocking: the size is read back to the host."""
+    scratch, out = _cut_args(nodes, parent, child_count, scratch, out)
     g = gaussians_struct(*nodes, sh_degree)
     arr = cameras([cam])
     n_cut = C.c_int64()
     _check(lib().gsr_hierarchy_cut(C.byref(g), _ptr(parent), _ptr(child_count), arr, _ptr(world_to_cam), float(tau),
-                                   _ptr(scratch), scratch.numel(), _ptr(out), C.byref(n_cut), _stream_ptr(stream)))
+                                   _ptr(scratch), scratch.numel(), _ptr(out), None, C.byref(n_cut),
+                                   _stream_ptr(stream)))
     return out[:n_cut.value]
 
 
-def gather_gaussians(src: Sequence[torch.Tensor], sh_degree: int, index: torch.Tensor, stream=None):
-    """New contiguous tensors holding rows `index` of the five arrays."""
+def hierarchy_cut_async(nodes: Sequence[torch.Tensor], sh_degree: int, parent: torch.Tensor,
+                        child_count: torch.Tensor, cam, world_to_cam: torch.Tensor, tau: float,
+                        scratch: torch.Tensor, out: torch.Tensor, count: torch.Tensor, stream=None) -> None:
+    """The cut without a host round trip: node indices into out[:count] and
+    their number into the int64 device tensor `count`, enqueued on the stream
+    (capturable in a graph)."""
+    if count.dtype != torch.int64 or not count.is_cuda:
+        raise TypeError("count must be an int64 GPU tensor")
+    scratch, out2 = _cut_args(nodes, parent, child_count, scratch, out)
+    if out2 is not out:
+        raise ValueError("out must hold one index per node")
+    g = gaussians_struct(*nodes, sh_degree)
+    arr = cameras([cam])
+    _check(lib().gsr_hierarchy_cut(C.byref(g), _ptr(parent), _ptr(child_count), arr, _ptr(world_to_cam), float(tau),
+                                   _ptr(scratch), scratch.numel(), _ptr(out), _ptr(count), None,
+                                   _stream_ptr(stream)))
+
+
+def gather_gaussians(src: Sequence[torch.Tensor], sh_degree: int, index: torch.Tensor, stream=None,
+                     count: Optional[torch.Tensor] = None, dst: Optional[Sequence[torch.Tensor]] = None):
+    """Rows `index` of the five arrays in contiguous tensors (new ones unless
+    `dst` is given).  count: None, or an int64 device tensor: only the first
+    min(count, len(index)) rows are copied (see gsr_gather_gaussians)."""
     m = int(index.numel())
-    dst = [torch.empty((m,) + tuple(t.shape[1:]), dtype=t.dtype, device=t.device) for t in src]
+    if dst is None:
+        dst = [torch.empty((m,) + tuple(t.shape[1:]), dtype=t.dtype, device=t.device) for t in src]
+    elif any(int(t.shape[0]) < m for t in dst):
+        raise ValueError("dst arrays must hold len(index) rows")
+    if count is not None and (count.dtype != torch.int64 or not count.is_cuda):
+        raise TypeError("count must be an int64 GPU tensor")
     g = gaussians_struct(*src, sh_degree)
-    _check(lib().gsr_gather_gaussians(C.byref(g), _ptr(index), m, C.byref(param_set(dst)), _stream_ptr(stream)))
+    _check(lib().gsr_gather_gaussians(C.byref(g), _ptr(index), m, _ptr(count), C.byref(param_set(dst)),
+                                      _stream_ptr(stream)))
     return dst
 
 

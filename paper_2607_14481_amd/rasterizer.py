@@ -34,12 +34,17 @@ class GaussianRasterizer:
 
     def __init__(self, cams: Sequence, sh_degree: int, tile_h: int = 16, persistent: bool = False,
                  sync: bool = True, headroom: float = 1.3, min_capacity: int = 1 << 16,
-                 persistent_ctas: int = 0, device=None):
+                 persistent_ctas: int = 0, device=None, active_count: Optional[torch.Tensor] = None):
+        """active_count: None, or a one-element int64 device tensor holding how
+        many leading Gaussians take part (the rest of the parameter arrays is
+        capacity and is never read), e.g. the size of a level-of-detail cut
+        computed on the device."""
         if len(cams) < 1 or len(cams) > gsr.GSR_MAX_VIEWS:
             raise ValueError(f"1..{gsr.GSR_MAX_VIEWS} views per call")
         self.cams = list(cams)
         self.sh_degree = int(sh_degree)
-        self.cfg = gsr.launch_config(tile_h, persistent_ctas)
+        self.active_count = active_count  # kept alive: the launch config holds its address
+        self.cfg = gsr.launch_config(tile_h, persistent_ctas, active_count=active_count)
         self.persistent = bool(persistent)
         self.sync = bool(sync)
         self.headroom = float(headroom)

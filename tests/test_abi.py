@@ -37,7 +37,8 @@ def test_library_exports_every_declared_symbol():
 def test_host_side_argument_checks():
     from paper_2607_14481_amd import gsr
     from paper_2607_14481_amd import scenes as S
-    assert gsr.version() == 2
+    assert gsr.version() == 3
+    assert C.sizeof(gsr.gsr_launch_config) == 32
     assert gsr.status_string(gsr.GSR_ERR_CAPACITY) == "GSR_ERR_CAPACITY"
     cam = S.pinhole(128, 96, S.look_at([0, 0, -3]))
     nb1 = gsr.workspace_bytes(1000, [cam], 10_000)
@@ -98,3 +99,22 @@ def test_bundle_adjustment_host_checks():
     rc, err, _ = create(ok_fs, [[0, 1, -1], [1, 2, 3]], ws_bytes=1024)
     assert rc == gsr.GSR_ERR_WORKSPACE_TOO_SMALL
     assert L.gsr_ba_plan_destroy(None) == gsr.GSR_OK
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_hierarchy_cut_host_checks():
+    """The cut needs somewhere to put its size (host and/or device); checked
+    before any device call."""
+    from paper_2607_14481_amd import gsr
+    from paper_2607_14481_amd import scenes as S
+    L = gsr.lib()
+    g = gsr.gsr_gaussians()
+    g.n, g.sh_degree = 10, 0
+    cams = gsr.cameras([S.pinhole(64, 48, S.look_at([0, 0, -3]))])
+    rc = L.gsr_hierarchy_cut(C.byref(g), None, None, cams, None, 1.5, None, 0, None, None, None, None)
+    assert rc == gsr.GSR_ERR_INVALID_ARGUMENT and "n_cut" in gsr.last_error()
+    n_cut = C.c_int64(-1)
+    g.n = 0  # an empty hierarchy has an empty cut
+    assert L.gsr_hierarchy_cut(C.byref(g), None, None, cams, None, 1.5, None, 0, None, None, C.byref(n_cut),
+                               None) == gsr.GSR_OK
+    assert n_cut.value == 0

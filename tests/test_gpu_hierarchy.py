@@ -83,3 +83,99 @@ def test_street_hierarchy_cut_and_gather():
     pick = cut.cpu().numpy()
     np.testing.assert_array_equal(sub[0].cpu().numpy(), h.nodes.means[pick])
     np.testing.assert_array_equal(sub[4].cpu().numpy(), h.nodes.sh[pick])
+
+
+def test_cut_gather_rasterize_captured_in_one_graph():
+    """Cut, gather and a rasterizer step (forward + backward) enqueued with no
+    host round trip: the cut writes its size to a device scalar, the gather
+    and the rasterizer read it.  The whole step is captured in one graph and
+    replayed with eager work in between; every replay must equal the eager
+    path that reads the cut size back (bit-identical images and parameter
+    gradients), and the image must match the FP64 oracle rendering the
+    oracle's cut."""
+    import torch
+    from oracle import oracle as O
+    from paper_2607_14481_amd import gsr
+    from paper_2607_14481_amd.rasterizer import GaussianRasterizer
+    rng = np.random.default_rng(31)
+    n = 6000
+    means = np.c_[rng.uniform(0, 300, n), rng.uniform(-3, 3, n), rng.uniform(0, 3, n)]
+    h = H.build(S._gaussian_body(rng, means, 2), levels=4)
+    eye = np.array([-1.0, 0.0, 1.5])
+    cam = S.pinhole(192, 128, S.look_at(eye, eye + [1.0, 0.05, 0.0]))
+    tau = 1.5
+    nn = h.nodes.n
+    nodes = params_to_device(h.nodes)
+    parent = torch.tensor(h.parent.astype(np.int32), device="cuda")
+    counts = torch.tensor(h.child_count.astype(np.int32), device="cuda")
+    w2c = torch.tensor(np.asarray(cam.world_to_cam, np.float32), device="cuda")
+    up = torch.tensor(S.random_upstream(5, (3 * cam.height * cam.width,)), device="cuda")
+
+    # eager reference: blocking cut, gather of exactly the cut, plain call
+    cut = gsr.hierarchy_cut(nodes, 2, parent, counts, cam, w2c, tau)
+    m = int(cut.numel())
+    sub = gsr.gather_gaussians(nodes, 2, cut)
+    ref_rast = GaussianRasterizer([cam], 2)
+    rgb_ref, ws_ref = ref_rast.forward(sub, w2c[None])
+    g_ref, gw_ref, _ = ref_rast.backward(ws_ref, sub, w2c[None], (0.0, 0.0, 0.0), rgb_ref, up)
+    torch.cuda.synchronize()
+    log(f"graph cut: {nn} nodes, cut {m}")
+    assert 0 < m < nn
+
+    # device-count path in fixed-capacity buffers
+    scratch = torch.empty(gsr.lib().gsr_hierarchy_cut_scratch_bytes(nn), dtype=torch.uint8, device="cuda")
+    idx = torch.empty(nn, dtype=torch.int32, device="cuda")
+    count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    buf = [torch.full_like(t, float("nan")) for t in nodes]  # rows past the count are never read
+    rast = GaussianRasterizer([cam], 2, sync=False, active_count=count)
+    rast.capacity = int(gsr.query_pairs(ws_ref)[0] * 2) + 4096
+    ws = rast.workspace(nn)
+    rgb = torch.empty_like(rgb_ref)
+
+    def step():
+        gsr.hierarchy_cut_async(nodes, 2, parent, counts, cam, w2c, tau, scratch, idx, count)
+        gsr.gather_gaussians(nodes, 2, idx, count=count, dst=buf)
+        rast.forward(buf, w2c[None], ws=ws, out=rgb)
+        return rast.backward(ws, buf, w2c[None], (0.0, 0.0, 0.0), rgb, up)
+
+    def same(grads, gw, what):
+        assert int(count.item()) == m, what
+        assert torch.equal(idx[:m], cut), what
+        assert torch.equal(rgb, rgb_ref), what
+        for a, b in zip(grads, g_ref):
+            assert torch.equal(a[:m], b), what
+            assert float(a[m:].abs().max()) == 0.0, what
+        torch.testing.assert_close(gw, gw_ref, rtol=1e-6, atol=1e-9)
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        grads, gw, _ = step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    assert not rast.check_overflow(ws)
+    same(grads, gw, "eager, device count")
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        grads, gw, _ = step()
+    for rep in range(3):
+        count.zero_()
+        rgb.fill_(-1.0)
+        for t in grads:
+            t.fill_(float("nan"))
+        graph.replay()
+        torch.cuda.synchronize()
+        same(grads, gw, f"replay {rep}")
+        # eager work of the program between replays
+        _ = gsr.hierarchy_cut(nodes, 2, parent, counts, cam, w2c, tau)
+        torch.cuda.synchronize()
+    # the oracle's own cut, rendered by the FP64 oracle
+    ref_cut = HC.cut(h.nodes.means, h.nodes.log_scales, h.parent, np.asarray(cam.world_to_cam, np.float32),
+                     max(cam.fx, cam.fy), tau)
+    assert np.array_equal(ref_cut, cut.cpu().numpy())
+    o = O.render(h.nodes.subset(ref_cut), cam)
+    img = rgb.cpu().numpy().reshape(3, cam.height, cam.width).transpose(1, 2, 0)
+    ok = ~o["ambig"]
+    err = float(np.abs(img - o["img"])[ok].max())
+    log(f"graph cut: image vs oracle max|d| {err:.3e}")
+    assert err <= 1e-4
