@@ -38,7 +38,10 @@
  * library never allocates or frees device memory, and holds no host buffers,
  * events or other state between calls apart from each thread's last-error
  * message (and the host plans of the bundle adjustment, owned by the caller
- * through gsr_ba_plan_destroy).  Device pointers must be 16-byte aligned.  The workspace carries the
+ * through gsr_ba_plan_destroy); the one exception is the device scratch of
+ * gsr_hierarchy_cut_static, a fixed array in the library's code object, and
+ * the per-device addresses of it that that entry point looks up once.
+ * Device pointers must be 16-byte aligned.  The workspace carries the
  * forward pass's state to the backward pass: do not reuse it for another
  * forward between a forward and its backward.  One workspace per in-flight
  * iteration; calls on different workspaces and streams are independent.
@@ -368,6 +371,24 @@ int gsr_hierarchy_cut(const gsr_gaussians *nodes, const int32_t *parent, const i
                       const gsr_camera *cam, const float *world_to_cam, float tau, void *scratch,
                       size_t scratch_bytes, int32_t *cut_nodes, int64_t *n_cut_device, int64_t *n_cut,
                       void *stream);
+
+/*
+ * Scratch-free form of gsr_hierarchy_cut, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation.  Same arguments, results and errors as
+ * gsr_hierarchy_cut, without scratch/scratch_bytes: the scratch comes from a
+ * 16 MiB array the library keeps in device memory (one per device, from the
+ * library's load until the process ends).  At most 2^23 nodes (8,388,608);
+ * larger hierarchies fail with GSR_ERR_UNSUPPORTED.  It calls no allocating
+ * routine; with n_cut NULL it does not synchronise either.  Every call on one
+ * device shares that array: calls that overlap on a device (on different
+ * streams or threads) race and must be ordered by the caller.  Each call
+ * writes every scratch word it reads before reading it, so nothing carries
+ * over from the previous call.
+ */
+int gsr_hierarchy_cut_static(const gsr_gaussians *nodes, const int32_t *parent, const int32_t *child_count,
+                             const gsr_camera *cam, const float *world_to_cam, float tau, int32_t *cut_nodes,
+                             int64_t *n_cut_device, int64_t *n_cut, void *stream);
 
 /* Copies rows index[0 .. m) of src into rows 0 .. m of dst (all five arrays;
    src->sh_degree gives the SH row length), e.g. to rasterize a cut.  index:

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -630,21 +631,50 @@ struct CutScratch {
     size_t descend, in_cut, block_tmp, count, total;
 };
 
-CutScratch cut_scratch_layout(uint64_t n) {
+constexpr size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// descend flags [n], in-cut flags [n], one word per scan block, the count
+constexpr CutScratch cut_scratch_layout(uint64_t n) {
     CutScratch c{};
-    size_t o = 0;
-    auto take = [&](size_t bytes) {
-        const size_t at = o;
-        o = align_up(o + bytes);
-        return at;
-    };
-    c.descend = take(n);
-    c.in_cut = take(n);
-    c.block_tmp = take(4 * std::max<uint64_t>(1, gsr::scan_blocks_for(n)));
-    c.count = take(4);
-    c.total = o;
+    c.descend = 0;
+    c.in_cut = align256(n);
+    c.block_tmp = c.in_cut + align256(n);
+    const uint64_t blocks = (n + gsr::kScanTile - 1) / gsr::kScanTile;
+    c.count = c.block_tmp + align256(4 * (blocks > 0 ? blocks : 1));
+    c.total = c.count + align256(4);
     return c;
 }
+
+// The scratch-free cut takes its scratch from this device array (each device
+// holds its own copy from module load until the process ends): hierarchies
+// of up to 2^23 nodes, 16.0 MiB.
+constexpr uint64_t kCutStaticMaxNodes = 1ull << 23;
+constexpr size_t kCutStaticBytes = cut_scratch_layout(kCutStaticMaxNodes).total;
+static __device__ __align__(256) uint8_t scratch[kCutStaticBytes];
+
+constexpr int kMaxDevices = 64;
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.  Host code never uses the array's name
+// as an address: on the host it names a stand-in, not device memory.
+int static_cut_scratch(void **out) {
+    static std::once_flag once[kMaxDevices];
+    static void *ptr[kMaxDevices];
+    static hipError_t err[kMaxDevices];
+    int dev = 0;
+    int rc = check_hip(hipGetDevice(&dev), "current device");
+    if (rc) return rc;
+    if (dev < 0 || dev >= kMaxDevices) return fail(GSR_ERR_UNSUPPORTED, "device %d beyond the first %d", dev, kMaxDevices);
+    std::call_once(once[dev], [dev] { err[dev] = hipGetSymbolAddress(&ptr[dev], HIP_SYMBOL(scratch)); });
+    if (err[dev] != hipSuccess)
+        return fail(GSR_ERR_HIP, "address of the static cut scratch: %s", hipGetErrorString(err[dev]));
+    *out = ptr[dev];
+    return GSR_OK;
+}
+
+int cut_impl(const gsr_gaussians *nodes, const int32_t *parent, const int32_t *child_count, const gsr_camera *cam,
+             const float *world_to_cam, float tau, void *scratch_buf, size_t scratch_bytes, int32_t *cut_nodes,
+             int64_t *n_cut_device, int64_t *n_cut, void *stream);
 
 }  // namespace
 
@@ -656,8 +686,35 @@ size_t gsr_hierarchy_cut_scratch_bytes(int64_t n_nodes) {
 }
 
 int gsr_hierarchy_cut(const gsr_gaussians *nodes, const int32_t *parent, const int32_t *child_count,
-                      const gsr_camera *cam, const float *world_to_cam, float tau, void *scratch, size_t scratch_bytes,
-                      int32_t *cut_nodes, int64_t *n_cut_device, int64_t *n_cut, void *stream) {
+                      const gsr_camera *cam, const float *world_to_cam, float tau, void *scratch_buf,
+                      size_t scratch_bytes, int32_t *cut_nodes, int64_t *n_cut_device, int64_t *n_cut, void *stream) {
+    return cut_impl(nodes, parent, child_count, cam, world_to_cam, tau, scratch_buf, scratch_bytes, cut_nodes,
+                    n_cut_device, n_cut, stream);
+}
+
+int gsr_hierarchy_cut_static(const gsr_gaussians *nodes, const int32_t *parent, const int32_t *child_count,
+                             const gsr_camera *cam, const float *world_to_cam, float tau, int32_t *cut_nodes,
+                             int64_t *n_cut_device, int64_t *n_cut, void *stream) {
+    if (!nodes) return fail(GSR_ERR_INVALID_ARGUMENT, "nodes must not be NULL");
+    if (nodes->n > (int64_t)kCutStaticMaxNodes)
+        return fail(GSR_ERR_UNSUPPORTED, "n=%lld nodes exceeds the %llu the static scratch holds (use gsr_hierarchy_cut)",
+                    (long long)nodes->n, (unsigned long long)kCutStaticMaxNodes);
+    void *buf = nullptr;
+    if (nodes->n > 0) {
+        const int rc = static_cut_scratch(&buf);
+        if (rc) return rc;
+    }
+    return cut_impl(nodes, parent, child_count, cam, world_to_cam, tau, buf, kCutStaticBytes, cut_nodes, n_cut_device,
+                    n_cut, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+int cut_impl(const gsr_gaussians *nodes, const int32_t *parent, const int32_t *child_count, const gsr_camera *cam,
+             const float *world_to_cam, float tau, void *scratch_buf, size_t scratch_bytes, int32_t *cut_nodes,
+             int64_t *n_cut_device, int64_t *n_cut, void *stream) {
     using namespace gsr;
     if (!nodes || !cam) return fail(GSR_ERR_INVALID_ARGUMENT, "nodes and cam must not be NULL");
     if (!n_cut && !n_cut_device) return fail(GSR_ERR_INVALID_ARGUMENT, "n_cut and n_cut_device are both NULL");
@@ -672,12 +729,13 @@ int gsr_hierarchy_cut(const gsr_gaussians *nodes, const int32_t *parent, const i
         launch_store_count_i64(nullptr, n_cut_device, st);
         return check_hip(hipGetLastError(), "cut count launch");
     }
-    if (!nodes->means || !nodes->log_scales || !parent || !child_count || !world_to_cam || !scratch || !cut_nodes)
+    if (!nodes->means || !nodes->log_scales || !parent || !child_count || !world_to_cam || !scratch_buf || !cut_nodes)
         return fail(GSR_ERR_INVALID_ARGUMENT, "a device pointer is NULL");
-    if (reinterpret_cast<uintptr_t>(scratch) & 255u) return fail(GSR_ERR_INVALID_ARGUMENT, "scratch must be 256-byte aligned");
+    if (reinterpret_cast<uintptr_t>(scratch_buf) & 255u)
+        return fail(GSR_ERR_INVALID_ARGUMENT, "scratch must be 256-byte aligned");
     const CutScratch L = cut_scratch_layout(n);
     if (scratch_bytes < L.total) return fail(GSR_ERR_WORKSPACE_TOO_SMALL, "scratch %zu < %zu bytes", scratch_bytes, L.total);
-    char *b = static_cast<char *>(scratch);
+    char *b = static_cast<char *>(scratch_buf);
     uint8_t *descend = reinterpret_cast<uint8_t *>(b + L.descend), *in_cut = reinterpret_cast<uint8_t *>(b + L.in_cut);
     uint32_t *count = reinterpret_cast<uint32_t *>(b + L.count);
     launch_hierarchy_cut_flags(nodes->means, nodes->log_scales, parent, child_count, n, world_to_cam,
@@ -693,6 +751,10 @@ int gsr_hierarchy_cut(const gsr_gaussians *nodes, const int32_t *parent, const i
     *n_cut = h;
     return GSR_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int gsr_gather_gaussians(const gsr_gaussians *src, const int32_t *index, int64_t n_index, const int64_t *count,
                          const gsr_param_set *dst, void *stream) {

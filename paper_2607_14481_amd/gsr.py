@@ -30,7 +30,8 @@ EXPORTED = ("gsr_version", "gsr_status_string", "gsr_last_error", "gsr_workspace
             "gsr_rasterize_forward", "gsr_rasterize_backward", "gsr_rasterize_backward_l1", "gsr_query_pairs",
             "gsr_query_stats",
             "gsr_export_state", "gsr_adam_step", "gsr_pose_step", "gsr_sim3_relocate",
-            "gsr_hierarchy_cut_scratch_bytes", "gsr_hierarchy_cut", "gsr_gather_gaussians",
+            "gsr_hierarchy_cut_scratch_bytes", "gsr_hierarchy_cut", "gsr_hierarchy_cut_static",
+            "gsr_gather_gaussians",
             "gsr_ba_workspace_bytes", "gsr_ba_plan_create", "gsr_ba_plan_destroy", "gsr_ba_solve")
 
 
@@ -136,6 +137,9 @@ def lib():
         L.gsr_hierarchy_cut.restype = C.c_int
         L.gsr_hierarchy_cut.argtypes = [C.POINTER(gsr_gaussians), vp, vp, C.POINTER(gsr_camera), vp, C.c_float, vp,
                                         sz, vp, vp, C.POINTER(C.c_int64), vp]
+        L.gsr_hierarchy_cut_static.restype = C.c_int
+        L.gsr_hierarchy_cut_static.argtypes = [C.POINTER(gsr_gaussians), vp, vp, C.POINTER(gsr_camera), vp,
+                                               C.c_float, vp, vp, C.POINTER(C.c_int64), vp]
         L.gsr_gather_gaussians.restype = C.c_int
         L.gsr_gather_gaussians.argtypes = [C.POINTER(gsr_gaussians), vp, C.c_int64, vp, C.POINTER(gsr_param_set),
                                            vp]
@@ -435,6 +439,33 @@ def hierarchy_cut_async(nodes: Sequence[torch.Tensor], sh_degree: int, parent: t
     _check(lib().gsr_hierarchy_cut(C.byref(g), _ptr(parent), _ptr(child_count), arr, _ptr(world_to_cam), float(tau),
                                    _ptr(scratch), scratch.numel(), _ptr(out), _ptr(count), None,
                                    _stream_ptr(stream)))
+
+
+HIERARCHY_CUT_STATIC_MAX_NODES = 1 << 23  # the scratch-free cut's limit (gsr_hierarchy_cut_static)
+
+
+def hierarchy_cut_static(nodes: Sequence[torch.Tensor], sh_degree: int, parent: torch.Tensor,
+                         child_count: torch.Tensor, cam, world_to_cam: torch.Tensor, tau: float,
+                         out: torch.Tensor, count: Optional[torch.Tensor] = None, stream=None) -> Optional[int]:
+    """The cut through gsr_hierarchy_cut_static (no scratch argument, nothing
+    allocated by the library): node indices into `out` (one int32 per node,
+    caller-allocated).  With `count` (int64 device tensor) the size goes there
+    and nothing is read back (returns None); without it the call blocks and
+    returns the size."""
+    n = int(nodes[0].shape[0])
+    if parent.dtype != torch.int32 or child_count.dtype != torch.int32:
+        raise TypeError("parent and child_count must be int32")
+    if out.dtype != torch.int32 or out.numel() < n:
+        raise ValueError("out must be an int32 tensor with one entry per node")
+    if count is not None and (count.dtype != torch.int64 or not count.is_cuda):
+        raise TypeError("count must be an int64 GPU tensor")
+    g = gaussians_struct(*nodes, sh_degree)
+    arr = cameras([cam])
+    n_cut = C.c_int64()
+    _check(lib().gsr_hierarchy_cut_static(C.byref(g), _ptr(parent), _ptr(child_count), arr, _ptr(world_to_cam),
+                                          float(tau), _ptr(out), _ptr(count),
+                                          None if count is not None else C.byref(n_cut), _stream_ptr(stream)))
+    return None if count is not None else int(n_cut.value)
 
 
 def gather_gaussians(src: Sequence[torch.Tensor], sh_degree: int, index: torch.Tensor, stream=None,
