@@ -78,6 +78,24 @@ TRAFFIC_PROFILES = {"headline": "headline_1080p_1M"}
 OTHER_WORKLOADS = ("small_view", "single_view_1080p", "lod_cut")
 
 
+def host_cpu():
+    """Logical CPUs this process may use and the host CPU's model name."""
+    import subprocess
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        nproc = os.cpu_count()
+    model = None
+    try:
+        for line in subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:  # pragma: no cover - reported as unknown
+        pass
+    return {"nproc": nproc, "model": model}
+
+
 def make_workload(name):
     from paper_2607_14481_amd import scenes as S
     if name == "headline":
@@ -249,9 +267,16 @@ def run_keyframe(wl, iterations=30, repeats=3):
             for k in ("means", "log_scales", "quats", "opacities", "sh")]
     rast = GaussianRasterizer(cams, sc.sh_degree)
     tw2c = torch.tensor(np.asarray(wl.target_cameras[0].world_to_cam, np.float32)[None], device=dev)
-    target, _ = rast.forward(base, tw2c)
+    target, tws = rast.forward(base, tw2c)
     target = target.clone()
     acfg = gsr.adam_config(sparse=True)
+    # the loop never waits for the host: the pair capacity (and the long-list
+    # passes) come from a synchronous forward; overflow is checked after
+    assert not rast.check_overflow(tws)
+    del tws
+    rast.sync = False
+    ws = rast.workspace(sc.n)
+    rgb = torch.empty_like(target)
 
     def keyframe():
         params = [t.clone() for t in base]
@@ -261,27 +286,54 @@ def run_keyframe(wl, iterations=30, repeats=3):
         pm, pv = torch.zeros((1, 6), device=dev), torch.zeros((1, 6), device=dev)
         losses = []
         for it in range(1, iterations + 1):
-            rgb, ws = rast.forward(params, w2c)
+            rast.forward(params, w2c, ws=ws, out=rgb)
             if it == 1 or it == iterations:
                 losses.append((rgb - target).abs().mean())
             grads, _, twist = rast.backward_l1(ws, params, w2c, (0.0, 0.0, 0.0), rgb, target)
             gsr.adam_step(params, grads, m, v, sc.sh_degree, it, acfg, ws=ws, cams=cams, cfg=rast.cfg)
             gsr.pose_step(w2c, twist, pm, pv, it, 1e-4)
-        return losses
+        return losses, params, grads, m, v
 
     keyframe()
     torch.cuda.synchronize()
+    assert not rast.check_overflow(ws), "pair capacity overflowed during the keyframe optimisation"
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record()
     for _ in range(repeats):
-        losses = keyframe()
+        losses, params, grads, m, v = keyframe()
     b.record()
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / repeats
+    assert not rast.check_overflow(ws), "pair capacity overflowed during the keyframe optimisation"
     first, last = float(losses[0]), float(losses[-1])
+    # the fused Adam step alone: dense (every Gaussian) and sparse (those the
+    # last forward saw), HIP events on the stream it runs on
+    n = sc.n
+    floats = sum(int(t[0].numel()) for t in params)  # floats per Gaussian
+    seen = int(gsr.query_stats(ws)["visible"])
+    adam = {}
+    for name, cfg_sparse in (("dense", False), ("sparse", True)):
+        ac = gsr.adam_config(sparse=cfg_sparse)
+        reps = 20
+        for it in range(3):
+            gsr.adam_step(params, grads, m, v, sc.sh_degree, 100 + it, ac, ws=ws, cams=cams, cfg=rast.cfg)
+        torch.cuda.synchronize()
+        a.record()
+        for it in range(reps):
+            gsr.adam_step(params, grads, m, v, sc.sh_degree, 200 + it, ac, ws=ws, cams=cams, cfg=rast.cfg)
+        b.record()
+        torch.cuda.synchronize()
+        us_a = a.elapsed_time(b) / reps * 1e3
+        rows = n if not cfg_sparse else seen
+        # per updated float: parameter, gradient and both moments read, three written;
+        # the sparse step also reads each Gaussian's per-view tile count
+        nbytes = rows * floats * 28 + (n * 4 if cfg_sparse else 0)
+        adam[name] = {"gaussians_updated": rows, "us": round(us_a, 2), "algorithmic_bytes": nbytes,
+                      "GB_per_s": round(nbytes / us_a / 1e3, 1),
+                      "frac_of_hbm_peak": round(nbytes / us_a / 1e3 / PEAK_HBM_GBS, 4)}
+        log(f"[bench] adam {name}: {us_a:.1f} us, {nbytes / us_a / 1e3:.0f} GB/s")
     log(f"[bench] keyframe: {iterations} iterations in {ms:.2f} ms; L1 {first:.5f} -> {last:.5f}")
     # loop-closure relocation of all Gaussians
-    n = sc.n
     rng = np.random.default_rng(0)
     kf = torch.tensor(rng.integers(0, 100, n).astype(np.int32), device=dev)
     q = rng.standard_normal((100, 4))
@@ -304,6 +356,8 @@ def run_keyframe(wl, iterations=30, repeats=3):
                         "pose Adam + SE(3) retraction",
             "iterations": iterations, "ms_per_keyframe": round(ms, 3),
             "ms_per_iteration": round(ms / iterations, 4), "l1_first": round(first, 6), "l1_last": round(last, 6),
+            "form": "host-sync-free forward (pair capacity from a synchronous forward of the start state)",
+            "adam_step": adam,
             "sim3_relocation": {"gaussians": n, "keyframes": 100, "us": round(us, 2),
                                 "algorithmic_bytes": nbytes, "GB_per_s": round(nbytes / us / 1e3, 1)}}
 
@@ -343,9 +397,64 @@ def run_lod_cut_gpu(wl, reps=10):
     row = 4 * (3 + 3 + 4 + 1 + 48)
     log(f"[bench] lod cut on the GPU: {cut.numel()} of {h.nodes.n} nodes in {ms_cut:.3f} ms (same as host: {same}); "
         f"gather {ms_gather:.3f} ms")
-    return {"nodes": int(h.nodes.n), "cut": int(cut.numel()), "same_as_host_cut": same,
+
+    # the whole level-of-detail step with no host round trip: the cut writes its
+    # size to a device scalar that the gather and the rasterizer read; cut,
+    # gather, forward and L1 backward are captured in one graph and replayed
+    from paper_2607_14481_amd.rasterizer import GaussianRasterizer
+    nn = int(h.nodes.n)
+    tw2c = torch.tensor(np.asarray(wl.target_cameras[0].world_to_cam, np.float32)[None], device=dev)
+    target, _ = GaussianRasterizer([cam], 3).forward(sub, tw2c)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    idx = torch.empty(nn, dtype=torch.int32, device=dev)
+    buf = [torch.empty_like(t) for t in nodes]
+    rast = GaussianRasterizer([cam], 3, active_count=count)
+    gsr.hierarchy_cut_async(nodes, 3, parent, counts, cam, w2c, 1.5, scratch, idx, count)
+    gsr.gather_gaussians(nodes, 3, idx, count=count, dst=buf)
+    rgb, ws0 = rast.forward(buf, w2c[None])  # synchronous: sizes the pair capacity and long-list passes
+    assert not rast.check_overflow(ws0)
+    del ws0
+    rast.sync = False
+    ws = rast.workspace(nn)
+
+    def step():
+        gsr.hierarchy_cut_async(nodes, 3, parent, counts, cam, w2c, 1.5, scratch, idx, count)
+        gsr.gather_gaussians(nodes, 3, idx, count=count, dst=buf)
+        rast.forward(buf, w2c[None], ws=ws, out=rgb)
+        return rast.backward_l1(ws, buf, w2c[None], (0.0, 0.0, 0.0), rgb, target)
+
+    graph_ms = None
+    try:
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            for _ in range(3):
+                step()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step()
+        for _ in range(3):
+            g.replay()
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            g.replay()
+        b.record()
+        torch.cuda.synchronize()
+        graph_ms = a.elapsed_time(b) / reps
+        assert int(count.item()) == cut.numel() and not rast.check_overflow(ws)
+        log(f"[bench] lod step (cut + gather + fwd + bwd) in one graph: {graph_ms:.3f} ms")
+    except Exception as e:  # reported, never hidden
+        log(f"[bench] lod step graph failed: {e!r}")
+        graph_ms = repr(e)
+    return {"nodes": nn, "cut": int(cut.numel()), "same_as_host_cut": same,
             "cut_ms_blocking": round(ms_cut, 4), "gather_ms": round(ms_gather, 4),
-            "gather_GB_per_s": round(2 * row * cut.numel() / (ms_gather * 1e-3) / 1e9, 1)}
+            "gather_GB_per_s": round(2 * row * cut.numel() / (ms_gather * 1e-3) / 1e9, 1),
+            "step_in_one_graph_ms": round(graph_ms, 4) if isinstance(graph_ms, float) else graph_ms,
+            "step_in_one_graph_note": "cut (size to a device scalar) + gather + forward + L1 backward, arrays and "
+                                      "workspace sized for all nodes, replayed from one HIP graph"}
 
 
 def run_ring(steps, warmup):
@@ -402,29 +511,46 @@ def run_ring(steps, warmup):
             "autotune_ms": tuned["ms"]}
 
 
-def run_serving(seconds, rate=200.0, start=500_000, per_keyframe=10_000, period=0.5, seed=5):
+def run_serving(seconds, rate=200.0, start=2_900_000, per_keyframe=10_000, period=0.5, seed=5,
+                overload_rate=1000.0, overload_seconds=3.0):
     """Poisson arrivals (mean `rate`/s) of render / optimise requests (50/50;
     resolutions uniform over 256x256..1920x1080; optimise = 1-4 views, fwd+bwd
-    vs a U(0,1) target) against a scene that starts at `start` Gaussians and
-    grows by `per_keyframe` every `period` seconds.  Returns latency/throughput
-    for one request at a time and for continuous batching."""
+    vs a U(0,1) target) against a scene that grows by `per_keyframe` every
+    `period` seconds.  The configured schedule grows 500k -> 3M Gaussians over
+    125 s; this window is its last `seconds` (the scene starts at `start`, so
+    that it ends at >= 3M).  Returns latency/throughput for one request at a
+    time and for continuous batching, at the configured rate and at an
+    overload rate where throughput separates the two modes."""
     import torch
     from paper_2607_14481_amd.serve import GrowingScene, Server, make_requests
-    kfs = int(seconds / period) + 2
     out = {"arrival_rate_per_s": rate, "window_s": seconds, "start_gaussians": start,
-           "growth": f"{per_keyframe} Gaussians per {period} s keyframe"}
+           "growth": f"{per_keyframe} Gaussians per {period} s keyframe",
+           "window_note": "the last seconds of the 500k -> 3M schedule (scene built at its size there)"}
+    runs = (("rate", rate, seconds, seed), ("overload", overload_rate, overload_seconds, seed + 7))
     for name, slots, group in (("one_at_a_time", 1, False), ("continuous_batching", 4, True)):
-        scene = GrowingScene(capacity=start + per_keyframe * kfs, start=start, per_keyframe=per_keyframe)
-        warm = make_requests(seed + 1000, rate=rate, duration=0.1)
-        Server(scene, slots=slots, group_renders=group).run(warm, keyframe_period=1e9, bind_versions=True)
-        torch.cuda.synchronize()
-        reqs = make_requests(seed, rate=rate, duration=seconds)
-        st = Server(scene, slots=slots, group_renders=group).run(reqs, keyframe_period=period)
-        log(f"[bench] serving {name}: {st['requests']} req, p50 {st['p50_ms']:.2f} ms, p99 {st['p99_ms']:.2f} ms, "
-            f"{st['throughput_req_s']:.1f} req/s, final {st['final_gaussians']} Gaussians")
-        out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
-        del scene
-        torch.cuda.empty_cache()
+        for tag, lam, dur, sd in runs:
+            kfs = int(dur / period) + 2
+            scene = GrowingScene(capacity=start + per_keyframe * kfs, start=start, per_keyframe=per_keyframe)
+            warm = make_requests(seed + 1000, rate=lam, duration=0.1)
+            ws = Server(scene, slots=slots, group_renders=group)
+            ws.run(warm, keyframe_period=1e9, bind_versions=True)
+            torch.cuda.synchronize()
+            reqs = make_requests(sd, rate=lam, duration=dur)
+            # the measured server starts from the pair-count model the warm-up learned
+            st = Server(scene, slots=slots, group_renders=group, pair_rate=ws.pair_rate).run(
+                reqs, keyframe_period=period)
+            del ws
+            log(f"[bench] serving {name} at {lam:g}/s: {st['requests']} req, p50 {st['p50_ms']:.2f} ms, "
+                f"p99 {st['p99_ms']:.2f} ms, {st['throughput_req_s']:.1f} req/s, final {st['final_gaussians']} "
+                "Gaussians")
+            res = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
+            res["arrival_rate_per_s"] = lam
+            if tag == "rate":
+                out[name] = res
+            else:
+                out.setdefault("overload", {})[name] = res
+            del scene
+            torch.cuda.empty_cache()
     return out
 
 
@@ -663,11 +789,17 @@ def main():
             O.render(scene, cam, bg=(0.0, 0.0, 0.0), dL_dimg=g)
             return time.time() - t
 
-        tfb = oracle_iteration(sc, cams[0])
+        oracle_iteration(sc, cams[0])  # warm-up
+        runs = [oracle_iteration(sc, cams[0]) for _ in range(5)]
+        tfb = float(np.median(runs))
+        host = host_cpu()
         cpu = {"value": round(1.0 / tfb, 5), "unit": "iters/s", "cores": 1, "kind": "oracle",
-               "sample": f"one full fwd+bwd iteration of the same view and scene ({tfb:.1f} s), "
-                         "single-threaded C, FP64"}
-        log(f"[bench] oracle fwd+bwd {tfb:.1f}s")
+               "sample": f"median of 5 full fwd+bwd iterations of the same view and scene after one warm-up "
+                         f"({', '.join(f'{t:.2f}' for t in runs)} s), single-threaded C, FP64",
+               "host_nproc": host["nproc"], "host_cpu_model": host["model"],
+               "note": "the oracle is serial C: its summation order is the definition the GPU is checked "
+                       "against, so it is timed on one core and not parallelised"}
+        log(f"[bench] oracle fwd+bwd median {tfb:.2f}s of {runs}")
         if others:
             cpu["other_workloads_s_per_iter"] = {}
             for name, o in others.items():

@@ -156,6 +156,8 @@ class GrowingScene:
 # the server
 # ----------------------------------------------------------------------------
 
+PX_REF = 1920 * 1080
+
 @dataclass
 class Job:
     reqs: List[Request]
@@ -173,7 +175,7 @@ class Job:
 
 class Server:
     def __init__(self, scene: GrowingScene, slots: int = 4, group_renders: bool = True, max_group_views: int = 8,
-                 hbm_budget: Optional[int] = None, keep_results: bool = False, pair_density: float = 3.0e-6,
+                 hbm_budget: Optional[int] = None, keep_results: bool = False, pair_rate: float = 1.0,
                  safety: float = 1.5, tile_h: int = 16, loss: str = "l1"):
         """loss: "l1" (mean absolute error against the request's seeded
         U(0, 1) target, its image gradient formed inside the backward) or
@@ -190,8 +192,9 @@ class Server:
         self.keep = bool(keep_results)
         self.safety = float(safety)
         self.tile_h = int(tile_h)
-        # pairs per (Gaussian x pixel) seen so far: sizes the pair capacity
-        self.pair_density = float(pair_density)
+        # pairs per Gaussian and per unit of view weight (largest seen so far):
+        # sizes the pair capacity
+        self.pair_rate = float(pair_rate)
         if hbm_budget is None:
             free, _ = torch.cuda.mem_get_info()
             hbm_budget = int(free * 0.8)
@@ -207,9 +210,17 @@ class Server:
         self.peak_allocated = 0     # measured: allocator peak above the start of the last run
 
     # -- sizing --------------------------------------------------------------
+    @staticmethod
+    def _view_weight(cams) -> float:
+        """Pair count model: a Gaussian covers at least one tile of a view it
+        sees, and its tile span grows with the view's resolution (focal length
+        = width), so M ~ n * sum_v (1 + pixels_v / 1080p).  A model
+        proportional to pixels alone, learned on small views, overestimates
+        large ones many times over."""
+        return sum(1.0 + c.width * c.height / PX_REF for c in cams)
+
     def _capacity(self, n: int, cams) -> int:
-        px = sum(c.width * c.height for c in cams)
-        return int(self.pair_density * n * px * self.safety) + 4096
+        return int(self.pair_rate * n * self._view_weight(cams) * self.safety) + 4096
 
     def _estimate(self, reqs: List[Request]):
         """(pair capacity, workspace bytes, bytes of the call's outputs):
@@ -324,8 +335,8 @@ class Server:
                 del in_flight[slot]
                 free_slots.append(slot)
                 needed, cap, ovf = gsr.query_pairs(job.ws, job.stream)
-                px = sum(c.width * c.height for r in job.reqs for c in r.cams)
-                self.pair_density = max(self.pair_density, needed / max(1, job.reqs[0].version * px))
+                w = self._view_weight([c for r in job.reqs for c in r.cams])
+                self.pair_rate = max(self.pair_rate, needed / max(1.0, job.reqs[0].version * w))
                 if ovf:
                     self.in_flight_bytes -= job.bytes
                     for r in job.reqs:

@@ -71,20 +71,20 @@ def test_results_same_alone_and_in_the_mix():
 
 def test_admission_respects_the_hbm_budget():
     from paper_2607_14481_amd.serve import Server
-    # a first run learns the pair density (pairs per Gaussian and pixel), so
-    # that the estimates below are the ones admission will use
+    # a first run learns the pair rate (the pair-count model's coefficient),
+    # so that the estimates below are the ones admission will use
     learn = Server(_scene(), slots=4, group_renders=False)
     learn.run(_requests(seed=8, n_max=12), keyframe_period=0.02)
-    density = learn.pair_density
+    rate = learn.pair_rate
     reqs = _requests(seed=8, n_max=12)
     scene = _scene()
-    probe = Server(scene, slots=4, pair_density=density)
+    probe = Server(scene, slots=4, pair_rate=rate)
     for r in reqs:  # the versions run() binds (arrival-time scene size)
         r.version = scene.version_at(r.t_arrival, START, 0.02)
     # a call's footprint: its workspace as a slot allocates it, plus outputs
     foot = [int(e[1] * 1.25) + e[2] for e in (probe._estimate([r]) for r in reqs)]
     budget = int(max(foot) * 1.5)  # at most one or two requests fit at a time
-    srv = Server(scene, slots=4, hbm_budget=budget, group_renders=False, pair_density=density)
+    srv = Server(scene, slots=4, hbm_budget=budget, group_renders=False, pair_rate=rate)
     st = srv.run(reqs, keyframe_period=0.02)
     log(f"budget {budget}: accounted peak {st['peak_inflight_bytes']}, with 2+ calls "
         f"{st['peak_shared_inflight_bytes']}, allocator peak {st['peak_allocated_bytes']}")
@@ -105,7 +105,7 @@ def test_pair_capacity_overflow_recovers():
     from paper_2607_14481_amd.serve import Server
     reqs = _requests(seed=9, n_max=10)
     scene = _scene()
-    srv = Server(scene, slots=3, keep_results=True, pair_density=1e-12)  # every first try overflows
+    srv = Server(scene, slots=3, keep_results=True, pair_rate=1e-9)  # every first try overflows
     st = srv.run(reqs, keyframe_period=0.02)
     log(f"retries {st['retries']}")
     assert st["retries"] >= 1
