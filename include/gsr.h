@@ -390,6 +390,43 @@ int gsr_hierarchy_cut_static(const gsr_gaussians *nodes, const int32_t *parent, 
                              const gsr_camera *cam, const float *world_to_cam, float tau, int32_t *cut_nodes,
                              int64_t *n_cut_device, int64_t *n_cut, void *stream);
 
+/* Most merge levels gsr_hierarchy_build builds. */
+#define GSR_MAX_HIERARCHY_LEVELS 30
+
+/*
+ * Node layout of a hierarchy built by gsr_hierarchy_build (host only): level 0
+ * holds the n_leaves leaves, level l + 1 one node per run of `branching`
+ * consecutive level-l nodes (the last run may be shorter), for `levels`
+ * merge levels or until a level has a single node.  *n_levels receives the
+ * number of levels including the leaves; level_start [levels + 2] (may be
+ * NULL) receives the first node of each level and, after the last, the node
+ * count.  1 <= n_leaves < 2^31, 0 <= levels <= GSR_MAX_HIERARCHY_LEVELS,
+ * 2 <= branching <= 64.
+ */
+int gsr_hierarchy_layout(int64_t n_leaves, int32_t levels, int32_t branching, int64_t *level_start,
+                         int32_t *n_levels);
+
+/*
+ * Builds (or refreshes, after the leaves changed) every inner node of a
+ * hierarchy on the device (Sec. 7.1: groups of Gaussians are merged into one
+ * node by a KL-divergence criterion).  nodes: parameter arrays holding every
+ * node in the layout of gsr_hierarchy_layout; rows [0, n_leaves) are the
+ * leaves, already in their grouping order (e.g. along a space-filling curve),
+ * and are only read; the rows of the inner nodes are overwritten.  A parent
+ * is the Gaussian that minimises KL(mixture || single) for the mixture of its
+ * children weighted by opacity w_i = o_i / sum o (the mixture's mean and
+ * covariance, computed in double precision), with opacity 1 - prod(1 - o_i)
+ * and the w-weighted mean of the children's SH coefficients; its covariance
+ * is stored as log-scales (eigenvalues ascending, variances below 1e-12
+ * raised to it) and a unit quaternion with w >= 0 (eigenvectors, determinant
+ * +1).  The children of a node must not all have zero opacity.  parent [n]
+ * (-1 for roots) and child_count [n] (0 for leaves), device int32, receive
+ * the links the level-of-detail cut reads.  Asynchronous on `stream`; no
+ * allocation.
+ */
+int gsr_hierarchy_build(const gsr_param_set *nodes, int32_t sh_degree, int64_t n_leaves, int32_t levels,
+                        int32_t branching, int32_t *parent, int32_t *child_count, void *stream);
+
 /* Copies rows index[0 .. m) of src into rows 0 .. m of dst (all five arrays;
    src->sh_degree gives the SH row length), e.g. to rasterize a cut.  index:
    device int32, each in [0, src->n).  m = n_index, or, when count (a device

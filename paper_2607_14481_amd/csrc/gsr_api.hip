@@ -756,6 +756,49 @@ int cut_impl(const gsr_gaussians *nodes, const int32_t *parent, const int32_t *c
 
 extern "C" {
 
+int gsr_hierarchy_layout(int64_t n_leaves, int32_t levels, int32_t branching, int64_t *level_start,
+                         int32_t *n_levels) {
+    if (n_leaves < 1 || n_leaves > 0x7fffffffll)
+        return fail(GSR_ERR_INVALID_ARGUMENT, "n_leaves=%lld outside 1..2^31-1", (long long)n_leaves);
+    if (levels < 0 || levels > GSR_MAX_HIERARCHY_LEVELS)
+        return fail(GSR_ERR_INVALID_ARGUMENT, "levels=%d outside 0..%d", levels, GSR_MAX_HIERARCHY_LEVELS);
+    if (branching < 2 || branching > 64) return fail(GSR_ERR_INVALID_ARGUMENT, "branching=%d outside 2..64", branching);
+    if (!n_levels) return fail(GSR_ERR_INVALID_ARGUMENT, "n_levels must not be NULL");
+    int64_t at = 0, n = n_leaves;
+    int32_t l = 0;
+    if (level_start) level_start[0] = 0;
+    for (;;) {
+        at += n;
+        ++l;
+        if (level_start) level_start[l] = at;
+        if (l - 1 == levels || n <= 1) break;
+        n = (n + branching - 1) / branching;
+        if (at + n > 0x7fffffffll) return fail(GSR_ERR_INVALID_ARGUMENT, "more than 2^31-1 nodes");
+    }
+    *n_levels = l;
+    return GSR_OK;
+}
+
+int gsr_hierarchy_build(const gsr_param_set *nodes, int32_t sh_degree, int64_t n_leaves, int32_t levels,
+                        int32_t branching, int32_t *parent, int32_t *child_count, void *stream) {
+    using namespace gsr;
+    int64_t ls[GSR_MAX_HIERARCHY_LEVELS + 2];
+    int32_t nl = 0;
+    int rc = gsr_hierarchy_layout(n_leaves, levels, branching, ls, &nl);
+    if (rc) return rc;
+    if (sh_degree < 0 || sh_degree > 3) return fail(GSR_ERR_UNSUPPORTED, "sh_degree=%d (supported: 0..3)", sh_degree);
+    if (!nodes || !parent || !child_count) return fail(GSR_ERR_INVALID_ARGUMENT, "nodes, parent and child_count must not be NULL");
+    const float *const ptrs[5] = {nodes->means, nodes->log_scales, nodes->quats, nodes->opacities, nodes->sh};
+    if ((rc = check_param_set(ptrs, ((sh_degree + 1) * (sh_degree + 1) * 3) % 4 == 0, "nodes"))) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    launch_fill_i32(child_count, 0, (uint64_t)n_leaves, st);                          // leaves
+    launch_fill_i32(parent + ls[nl - 1], -1, (uint64_t)(ls[nl] - ls[nl - 1]), st);  // roots
+    for (int32_t l = 0; l + 1 < nl; ++l)
+        launch_hierarchy_level(*nodes, sh_degree, (uint64_t)ls[l], (uint64_t)(ls[l + 1] - ls[l]), (uint64_t)ls[l + 1],
+                               (uint32_t)branching, parent, child_count, st);
+    return check_hip(hipGetLastError(), "hierarchy build launch");
+}
+
 int gsr_gather_gaussians(const gsr_gaussians *src, const int32_t *index, int64_t n_index, const int64_t *count,
                          const gsr_param_set *dst, void *stream) {
     using namespace gsr;

@@ -234,6 +234,10 @@ void launch_hierarchy_cut_flags(const float *means, const float *log_scales, con
 void launch_gather_gaussians(const gsr_gaussians &src, const int32_t *index, uint64_t n_out, const int64_t *count,
                              const gsr_param_set &dst, hipStream_t st);
 void launch_store_count_i64(const uint32_t *count, int64_t *out, hipStream_t st);
+void launch_hierarchy_level(const gsr_param_set &nodes, int sh_degree, uint64_t child_base, uint64_t n_child,
+                            uint64_t parent_base, uint32_t branching, int32_t *parent, int32_t *child_count,
+                            hipStream_t st);
+void launch_fill_i32(int32_t *p, int32_t value, uint64_t n, hipStream_t st);
 
 // Parameter updates (gsr_update.hip).
 struct AdamScalars {

@@ -31,7 +31,7 @@ EXPORTED = ("gsr_version", "gsr_status_string", "gsr_last_error", "gsr_workspace
             "gsr_query_stats",
             "gsr_export_state", "gsr_adam_step", "gsr_pose_step", "gsr_sim3_relocate",
             "gsr_hierarchy_cut_scratch_bytes", "gsr_hierarchy_cut", "gsr_hierarchy_cut_static",
-            "gsr_gather_gaussians",
+            "gsr_hierarchy_layout", "gsr_hierarchy_build", "gsr_gather_gaussians",
             "gsr_ba_workspace_bytes", "gsr_ba_plan_create", "gsr_ba_plan_destroy", "gsr_ba_solve")
 
 
@@ -140,6 +140,11 @@ def lib():
         L.gsr_hierarchy_cut_static.restype = C.c_int
         L.gsr_hierarchy_cut_static.argtypes = [C.POINTER(gsr_gaussians), vp, vp, C.POINTER(gsr_camera), vp,
                                                C.c_float, vp, vp, C.POINTER(C.c_int64), vp]
+        L.gsr_hierarchy_layout.restype = C.c_int
+        L.gsr_hierarchy_layout.argtypes = [C.c_int64, C.c_int32, C.c_int32, vp, C.POINTER(C.c_int32)]
+        L.gsr_hierarchy_build.restype = C.c_int
+        L.gsr_hierarchy_build.argtypes = [C.POINTER(gsr_param_set), C.c_int32, C.c_int64, C.c_int32, C.c_int32, vp,
+                                          vp, vp]
         L.gsr_gather_gaussians.restype = C.c_int
         L.gsr_gather_gaussians.argtypes = [C.POINTER(gsr_gaussians), vp, C.c_int64, vp, C.POINTER(gsr_param_set),
                                            vp]
@@ -439,6 +444,39 @@ def hierarchy_cut_async(nodes: Sequence[torch.Tensor], sh_degree: int, parent: t
     _check(lib().gsr_hierarchy_cut(C.byref(g), _ptr(parent), _ptr(child_count), arr, _ptr(world_to_cam), float(tau),
                                    _ptr(scratch), scratch.numel(), _ptr(out), _ptr(count), None,
                                    _stream_ptr(stream)))
+
+
+GSR_MAX_HIERARCHY_LEVELS = 30
+
+
+def hierarchy_layout(n_leaves: int, levels: int, branching: int = 8):
+    """First node of every level (leaves = level 0) and, last, the node count;
+    see gsr_hierarchy_layout (host only)."""
+    import numpy as np
+    ls = np.zeros(GSR_MAX_HIERARCHY_LEVELS + 2, np.int64)
+    nl = C.c_int32()
+    _check(lib().gsr_hierarchy_layout(int(n_leaves), int(levels), int(branching),
+                                      C.c_void_p(ls.ctypes.data), C.byref(nl)))
+    return ls[:nl.value + 1].copy()
+
+
+def hierarchy_build(nodes: Sequence[torch.Tensor], sh_degree: int, n_leaves: int, levels: int, branching: int = 8,
+                    parent: Optional[torch.Tensor] = None, child_count: Optional[torch.Tensor] = None, stream=None):
+    """Builds the inner nodes of a hierarchy in place (see gsr_hierarchy_build):
+    `nodes` hold every node (leaves first, in their grouping order).  Returns
+    (parent, child_count) int32 device tensors."""
+    n = int(nodes[0].shape[0])
+    ls = hierarchy_layout(n_leaves, levels, branching)
+    if n < int(ls[-1]):
+        raise ValueError(f"node arrays hold {n} rows, the hierarchy has {int(ls[-1])} nodes")
+    dev = nodes[0].device
+    if parent is None:
+        parent = torch.empty(n, dtype=torch.int32, device=dev)
+    if child_count is None:
+        child_count = torch.empty(n, dtype=torch.int32, device=dev)
+    _check(lib().gsr_hierarchy_build(C.byref(param_set(nodes)), int(sh_degree), int(n_leaves), int(levels),
+                                     int(branching), _ptr(parent), _ptr(child_count), _stream_ptr(stream)))
+    return parent, child_count
 
 
 HIERARCHY_CUT_STATIC_MAX_NODES = 1 << 23  # the scratch-free cut's limit (gsr_hierarchy_cut_static)

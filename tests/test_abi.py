@@ -118,3 +118,24 @@ def test_hierarchy_cut_host_checks():
     assert L.gsr_hierarchy_cut(C.byref(g), None, None, cams, None, 1.5, None, 0, None, None, C.byref(n_cut),
                                None) == gsr.GSR_OK
     assert n_cut.value == 0
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_hierarchy_layout_host_only():
+    """The node layout of a device-built hierarchy (host arithmetic only)
+    matches the host builder's levels, including ragged last groups and the
+    early stop at a single root."""
+    import numpy as np
+    from paper_2607_14481_amd import gsr
+    from paper_2607_14481_amd import hierarchy as H
+    from paper_2607_14481_amd import scenes as S
+    rng = np.random.default_rng(0)
+    for n, levels in ((1, 3), (8, 2), (9, 2), (1000, 7), (4097, 3)):
+        leaves = S._gaussian_body(rng, rng.uniform(-1, 1, (n, 3)), 0)
+        h = H.build(leaves, levels)
+        np.testing.assert_array_equal(gsr.hierarchy_layout(n, levels, 8), h.level_start)
+    assert list(gsr.hierarchy_layout(10, 0, 8)) == [0, 10]
+    assert list(gsr.hierarchy_layout(19, 5, 4)) == [0, 19, 24, 26, 27]
+    for bad in ((0, 3, 8), (10, -1, 8), (10, 3, 1), (10, 31, 8)):
+        with pytest.raises(gsr.GsrError):
+            gsr.hierarchy_layout(*bad)

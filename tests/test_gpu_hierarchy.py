@@ -179,3 +179,110 @@ def test_cut_gather_rasterize_captured_in_one_graph():
     err = float(np.abs(img - o["img"])[ok].max())
     log(f"graph cut: image vs oracle max|d| {err:.3e}")
     assert err <= 1e-4
+
+
+def _cov_from(ls, q):
+    from oracle import hierarchy_merge as M
+    return M.covariance(ls, q)
+
+
+def _compare_node(gpu, ref, label):
+    """One node: mean, covariance (from the stored log-scales and quaternion),
+    sorted scales, opacity, SH."""
+    mean, ls, q, o, sh = gpu
+    scale = max(1.0, float(np.abs(ref["mean"]).max()))
+    assert np.abs(mean - ref["mean"]).max() <= 2e-6 * scale, label
+    cg, cr = _cov_from(ls, q), ref["cov"]
+    assert np.linalg.norm(cg - cr) <= 1e-5 * np.linalg.norm(cr), label
+    assert np.abs(np.sort(ls) - np.sort(ref["log_scales"])).max() <= 1e-5, label
+    assert abs(o - ref["opacity"]) <= 1e-6, label
+    assert np.abs(sh - ref["sh"]).max() <= 1e-5 * max(1.0, float(np.abs(ref["sh"]).max())), label
+
+
+@pytest.mark.parametrize("n_leaves,levels,branching,deg", [(3001, 4, 8, 3), (777, 5, 4, 0), (64, 3, 8, 1),
+                                                            (1000, 6, 3, 2)])
+def test_build_against_the_oracle_merge(n_leaves, levels, branching, deg):
+    """Every inner node of a GPU-built hierarchy against the FP64 oracle's
+    level-by-level build from the same leaves (ragged last groups, the
+    paper's groups of 4 and the workload's groups of 8)."""
+    import torch
+    from oracle import hierarchy_merge as M
+    from paper_2607_14481_amd import gsr
+    rng = np.random.default_rng(n_leaves)
+    means = np.c_[rng.uniform(0, 50, n_leaves), rng.uniform(-3, 3, n_leaves), rng.uniform(0, 3, n_leaves)]
+    leaves = S._gaussian_body(rng, means, deg)
+    ls = gsr.hierarchy_layout(n_leaves, levels, branching)
+    total = int(ls[-1])
+    K = (deg + 1) ** 2
+    bufs = [torch.zeros((total,) + shp, dtype=torch.float32, device="cuda")
+            for shp in ((3,), (3,), (4,), (), (K, 3))]
+    for b, k in zip(bufs, ("means", "log_scales", "quats", "opacities", "sh")):
+        b[:n_leaves] = torch.tensor(np.asarray(getattr(leaves, k), np.float32), device="cuda")
+    parent, counts = gsr.hierarchy_build(bufs, deg, n_leaves, levels, branching)
+    torch.cuda.synchronize()
+    got = [b.cpu().numpy().astype(np.float64) for b in bufs]
+    ref = M.build_levels(leaves.means, leaves.log_scales, leaves.quats, leaves.opacities, leaves.sh, levels,
+                         branching)
+    assert [len(x) for x in ref] == list(np.diff(ls))
+    for l in range(1, len(ref)):
+        for j, r in enumerate(ref[l]):
+            i = int(ls[l]) + j
+            _compare_node([got[0][i], got[1][i], got[2][i], got[3][i], got[4][i]], r, f"level {l} node {j}")
+    # links: the parent of node i of level l is node i // branching of level l + 1
+    par, cnt = parent.cpu().numpy(), counts.cpu().numpy()
+    for l in range(len(ref)):
+        idx = np.arange(int(ls[l]), int(ls[l + 1]))
+        if l + 1 < len(ref):
+            np.testing.assert_array_equal(par[idx], int(ls[l + 1]) + (idx - int(ls[l])) // branching)
+        else:
+            assert np.all(par[idx] == -1)
+        if l == 0:
+            assert np.all(cnt[idx] == 0)
+        else:
+            n_prev = int(ls[l] - ls[l - 1])
+            exp = np.minimum(branching, n_prev - (idx - int(ls[l])) * branching)
+            np.testing.assert_array_equal(cnt[idx], exp)
+    log(f"build {n_leaves} leaves x {levels} levels (b={branching}, deg {deg}): {total} nodes match the oracle")
+
+
+def test_build_street_4M_leaves():
+    """The 4M-leaf street hierarchy built on the GPU from the leaves in their
+    Morton order: at every level a sample of parents against the oracle's
+    merge of the GPU's own children (the same FP32 inputs), and the cut for the
+    workload's camera against the oracle cut of the GPU-built tree."""
+    import torch
+    from oracle import hierarchy_merge as M
+    from paper_2607_14481_amd import gsr
+    leaves, cam, _ = S.street_leaves()
+    h = H.build(leaves, 7)  # host build: its first level holds the leaves in Morton order
+    n_leaves = int(h.level_start[1])
+    ls = gsr.hierarchy_layout(n_leaves, 7, 8)
+    assert np.array_equal(ls, h.level_start)
+    total = int(ls[-1])
+    bufs = [torch.zeros((total,) + shp, dtype=torch.float32, device="cuda") for shp in ((3,), (3,), (4,), (), (16, 3))]
+    for b, k in zip(bufs, ("means", "log_scales", "quats", "opacities", "sh")):
+        b[:n_leaves] = torch.tensor(np.asarray(getattr(h.nodes, k)[:n_leaves], np.float32), device="cuda")
+    parent, counts = gsr.hierarchy_build(bufs, 3, n_leaves, 7, 8)
+    torch.cuda.synchronize()
+    got = [b.cpu().numpy() for b in bufs]
+    rng = np.random.default_rng(9)
+    checked = 0
+    for l in range(1, len(ls) - 1):
+        lo, hi = int(ls[l]), int(ls[l + 1])
+        for i in rng.choice(np.arange(lo, hi), min(200, hi - lo), replace=False):
+            c0 = int(ls[l - 1]) + (int(i) - lo) * 8
+            c1 = min(c0 + 8, int(ls[l]))
+            r = M.merge_group(*[got[k][c0:c1].astype(np.float64) for k in range(5)])
+            _compare_node([got[k][i].astype(np.float64) for k in range(5)], r, f"street level {l} node {i}")
+            checked += 1
+    np.testing.assert_array_equal(parent.cpu().numpy(), h.parent)
+    np.testing.assert_array_equal(counts.cpu().numpy(), h.child_count)
+    # the cut of the GPU-built tree
+    w2c = torch.tensor(np.asarray(cam.world_to_cam, np.float32), device="cuda")
+    cut = gsr.hierarchy_cut(bufs, 3, parent, counts, cam, w2c, 1.5).cpu().numpy()
+    ref = HC.cut(got[0], got[1], h.parent, np.asarray(cam.world_to_cam, np.float32), max(cam.fx, cam.fy), 1.5)
+    amb = HC.ambiguous(got[0], got[1], np.asarray(cam.world_to_cam, np.float32), max(cam.fx, cam.fy), 1.5)
+    log(f"street build: {total} nodes, {checked} sampled parents match the oracle merge; cut {cut.size} "
+        f"(oracle {ref.size}, ties {int(amb.sum())})")
+    if amb.sum() == 0:
+        np.testing.assert_array_equal(cut, ref)
