@@ -23,7 +23,10 @@
 // Backward.  Front to back again (nothing per (pixel, Gaussian) is stored):
 // from the forward's output C_out and the running accumulation, the colour
 // behind contributor k is B_k = C_out - sum_{j<=k} c_j a_j T_j; only its
-// projection on the upstream gradient g is needed, g.B_k = g.C_out - sum.
+// projection on the upstream gradient g is needed, kept as one running value
+// g.B = g.C_out - sum, from which alpha dL/dalpha = w g.c - g.B alpha / (1 - alpha)
+// (w = alpha T).  A Gaussian that no lane reaches in any row skips the
+// reduction: its moments are zero and the finalising lanes write zeros.
 // Per pair the kernel produces nine moments over the tile's pixels: with
 // w = dL/dsigma, the sums of w dx, w dy, w dx^2, w dx dy, w dy^2, of
 // alpha dL/dalpha and of the colour gradient; they are linear in the per-pixel
@@ -409,13 +412,14 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
         const size_t plane = (size_t)c.width * c.height;
         const float *img = out_rgb + 3 * (size_t)c.pix_off;
         const float *gimg = (up.target ? up.target : up.grad) + 3 * (size_t)c.pix_off;
-        float T[RPL], g0[RPL], g1[RPL], g2[RPL], gout[RPL], gacc[RPL];
+        // gB = g . (colour still to come behind the current position): g . C_out
+        // before the first contributor, reduced by each contribution
+        float T[RPL], g0[RPL], g1[RPL], g2[RPL], gB[RPL];
         uint32_t ncon[RPL];
 #pragma unroll
         for (int k = 0; k < RPL; ++k) {
             const uint32_t py = c.oy + ly + 4 * k;
             T[k] = 1.f;
-            gacc[k] = 0.f;
             if (px < c.width && py < c.height) {
                 const size_t pix = (size_t)py * c.width + px;
                 ncon[k] = pix_n[c.pix_off + pix];
@@ -428,10 +432,10 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
                     g1[k] = l1_grad(i1, g1[k], up.l1_scale);
                     g2[k] = l1_grad(i2, g2[k], up.l1_scale);
                 }
-                gout[k] = g0[k] * i0 + g1[k] * i1 + g2[k] * i2;
+                gB[k] = g0[k] * i0 + g1[k] * i1 + g2[k] * i2;
             } else {
                 ncon[k] = 0;
-                g0[k] = g1[k] = g2[k] = gout[k] = 0.f;
+                g0[k] = g1[k] = g2[k] = gB[k] = 0.f;
             }
         }
         const uint2 rg = ranges[t];
@@ -449,12 +453,14 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
             __syncthreads();
             const int cnt = (int)min((uint32_t)kWave, end - b0);
             for (int j0 = 0; j0 < cnt; j0 += kGroup) {
+                uint32_t zq = 0;  // Gaussians of the group with all moments zero
 #pragma unroll
                 for (int q = 0; q < kGroup; ++q) {
                     const int j = j0 + q;
                     // per-lane sums over the rows: colour-gradient weights w, sa = alpha
                     // dL/dalpha, sa dy and sa dy^2 (the rows share dx)
                     float a_c0 = 0.f, a_c1 = 0.f, a_c2 = 0.f, a_sa = 0.f, a_say = 0.f, a_sayy = 0.f, dx = 0.f;
+                    bool live = false;  // wave-uniform: some lane reached some row of this Gaussian
                     if (j < cnt) {
                         const uint32_t pos = b0 - rg.x + (uint32_t)j;
                         const float4 a = sa[j], b = sb[j], d = sd[j];
@@ -467,6 +473,7 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
                             const float dy = a.y - ((float)(ly + 4 * k) + 0.5f);
                             const float ex = alpha_exponent(rq, b, dy);
                             if (__ballot(pos < ncon[k] && ex >= kLog2AlphaSkip) == 0ull) continue;
+                            live = true;
                             const float araw = __builtin_amdgcn_exp2f(ex);
                             const float alpha = fminf(kAlphaMax, araw);
                             const bool ok = pos < ncon[k] && alpha >= kAlphaMin;
@@ -475,52 +482,59 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
                             a_c1 = fmaf(w, g1[k], a_c1);
                             a_c2 = fmaf(w, g2[k], a_c2);
                             const float grgb = fmaf(g0[k], b.z, fmaf(g1[k], b.w, g2[k] * d.x));
-                            gacc[k] = fmaf(w, grgb, gacc[k]);
-                            const float one_m = 1.f - alpha;
-                            const float dalpha =
-                                fmaf(T[k], grgb, -(gout[k] - gacc[k]) * __builtin_amdgcn_rcpf(one_m));
+                            // alpha dL/dalpha = alpha T g.c - alpha g.B / (1 - alpha), with
+                            // B the colour behind this Gaussian: w = alpha T where it
+                            // contributes, and gB already excludes its own term
+                            const float t1 = w * grgb;
+                            gB[k] -= t1;
+                            const float ar = alpha * __builtin_amdgcn_rcpf(1.f - alpha);
                             T[k] -= w;  // T (1 - alpha) where the Gaussian contributed
                             // dL/dsigma = -sa, alpha dL/dalpha = sa (zero through the 0.99 clamp)
-                            const float sa_ = (ok && araw < kAlphaMax) ? dalpha * alpha : 0.f;
+                            const float sa_ = (ok && araw < kAlphaMax) ? fmaf(-gB[k], ar, t1) : 0.f;
                             a_sa += sa_;
                             const float say = sa_ * dy;
                             a_say += say;
                             a_sayy = fmaf(say, dy, a_sayy);
                         }
                     }
-                    // the moments of sa (= -dL/dsigma): sums of sa dx, sa dy, sa dx^2,
-                    // sa dx dy, sa dy^2 (the negated S_x .. S_yy of the projection
-                    // backward), then S_o = sum sa and the colour gradient
-                    float s[kPartialStride];
-                    s[0] = dx * a_sa;
-                    s[1] = a_say;
-                    s[2] = dx * s[0];
-                    s[3] = dx * a_say;
-                    s[4] = a_sayy;
-                    s[5] = a_sa;
-                    s[6] = a_c0;
-                    s[7] = a_c1;
-                    s[8] = a_c2;
-                    // add the lanes of each quad (quad_perm [1, 0, 3, 2], then [2, 3, 0, 1]):
-                    // all four lanes hold the same sum (each step adds a and b as b and a,
-                    // exactly equal) and store it to the same place, so no lane is masked
-                    // off and each move folds into its add
+                    if (!live) zq |= 1u << q;  // every moment is zero: the finaliser writes 0
+                    if (live) {
+                        // the moments of sa (= -dL/dsigma): sums of sa dx, sa dy, sa dx^2,
+                        // sa dx dy, sa dy^2 (the negated S_x .. S_yy of the projection
+                        // backward), then S_o = sum sa and the colour gradient
+                        float s[kPartialStride];
+                        s[0] = dx * a_sa;
+                        s[1] = a_say;
+                        s[2] = dx * s[0];
+                        s[3] = dx * a_say;
+                        s[4] = a_sayy;
+                        s[5] = a_sa;
+                        s[6] = a_c0;
+                        s[7] = a_c1;
+                        s[8] = a_c2;
+                        // add the lanes of each quad (quad_perm [1, 0, 3, 2], then [2, 3, 0, 1]):
+                        // all four lanes hold the same sum (each step adds a and b as b and a,
+                        // exactly equal) and store it to the same place, so no lane is masked
+                        // off and each move folds into its add
 #pragma unroll
-                    for (int cc = 0; cc < kPartialStride; ++cc)
-                        s[cc] = dpp_add<0x4E, 0xf>(dpp_add<0xB1, 0xf>(s[cc]));
+                        for (int cc = 0; cc < kPartialStride; ++cc)
+                            s[cc] = dpp_add<0x4E, 0xf>(dpp_add<0xB1, 0xf>(s[cc]));
 #pragma unroll
-                    for (int cc = 0; cc < kPartialStride; ++cc)
-                        red[(lane >> 2) * kRedStride + q * kPartialStride + cc] = s[cc];
+                        for (int cc = 0; cc < kPartialStride; ++cc)
+                            red[(lane >> 2) * kRedStride + q * kPartialStride + cc] = s[cc];
+                    }
                 }
                 __syncthreads();
                 if (lane < kRedCols && j0 + fq < cnt) {
                     float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+                    if (!((zq >> fq) & 1u)) {
 #pragma unroll
-                    for (int r = 0; r < kRedRows; r += 4) {
-                        p0 += red[(r + 0) * kRedStride + lane];
-                        p1 += red[(r + 1) * kRedStride + lane];
-                        p2 += red[(r + 2) * kRedStride + lane];
-                        p3 += red[(r + 3) * kRedStride + lane];
+                        for (int r = 0; r < kRedRows; r += 4) {
+                            p0 += red[(r + 0) * kRedStride + lane];
+                            p1 += red[(r + 1) * kRedStride + lane];
+                            p2 += red[(r + 2) * kRedStride + lane];
+                            p3 += red[(r + 3) * kRedStride + lane];
+                        }
                     }
                     const uint32_t p = __float_as_uint(sd[j0 + fq].z);
                     partial[(size_t)p * kPartialStride + fc] = (p0 + p1) + (p2 + p3);
