@@ -398,6 +398,29 @@ def run_lod_cut_gpu(wl, reps=10):
     log(f"[bench] lod cut on the GPU: {cut.numel()} of {h.nodes.n} nodes in {ms_cut:.3f} ms (same as host: {same}); "
         f"gather {ms_gather:.3f} ms")
 
+    # the hierarchy itself built on the GPU from the Morton-ordered leaves: all
+    # seven merge levels (moment-matched merges in FP64, SH means), timed
+    n_leaves = int(h.level_start[1])
+    levels = int(len(h.level_start) - 2)
+    built = [torch.zeros_like(t) for t in nodes]
+    for dst_t, src_t in zip(built, nodes):
+        dst_t[:n_leaves] = src_t[:n_leaves]
+    bparent, bcount = gsr.hierarchy_build(built, 3, n_leaves, levels, 8)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        gsr.hierarchy_build(built, 3, n_leaves, levels, 8, parent=bparent, child_count=bcount)
+    b.record()
+    torch.cuda.synchronize()
+    ms_build = a.elapsed_time(b) / reps
+    same_links = bool(torch.equal(bparent, parent) and torch.equal(bcount, counts))
+    # algorithmic bytes: each inner node reads its children's rows and writes its own
+    inner = int(h.level_start[-1]) - n_leaves
+    build_bytes = (int(h.level_start[-2]) + inner) * row + 8 * int(h.level_start[-1])
+    log(f"[bench] hierarchy build on the GPU: {levels} levels over {n_leaves} leaves in {ms_build:.3f} ms "
+        f"(links as the host build: {same_links})")
+    del built
+
     # the whole level-of-detail step with no host round trip: the cut writes its
     # size to a device scalar that the gather and the rasterizer read; cut,
     # gather, forward and L1 backward are captured in one graph and replayed
@@ -452,6 +475,9 @@ def run_lod_cut_gpu(wl, reps=10):
     return {"nodes": nn, "cut": int(cut.numel()), "same_as_host_cut": same,
             "cut_ms_blocking": round(ms_cut, 4), "gather_ms": round(ms_gather, 4),
             "gather_GB_per_s": round(2 * row * cut.numel() / (ms_gather * 1e-3) / 1e9, 1),
+            "hierarchy_build": {"leaves": n_leaves, "levels": levels, "inner_nodes": inner, "ms": round(ms_build, 4),
+                                "links_same_as_host_build": same_links, "algorithmic_bytes": build_bytes,
+                                "GB_per_s": round(build_bytes / (ms_build * 1e-3) / 1e9, 1)},
             "step_in_one_graph_ms": round(graph_ms, 4) if isinstance(graph_ms, float) else graph_ms,
             "step_in_one_graph_note": "cut (size to a device scalar) + gather + forward + L1 backward, arrays and "
                                       "workspace sized for all nodes, replayed from one HIP graph"}
@@ -702,12 +728,25 @@ def main():
         print(json.dumps(run_local_ba(cpu_baseline=not args.no_cpu_baseline)), flush=True)
         return
     if args.copy_calibration:
+        # reference kernels of known traffic for the HBM byte counters: a plain
+        # copy (reads and writes COPY_CAL_MIB), a read-only reduction over the
+        # same buffer (a sum: reads COPY_CAL_MIB), and a gather of random
+        # 64-byte rows (reads and writes 64 B per row, in 64-byte pieces)
         src = torch.ones(COPY_CAL_MIB << 18, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         for _ in range(COPY_CAL_REPS):
             dst.copy_(src)
+        tot = torch.zeros((), device=dev)
+        for _ in range(COPY_CAL_REPS):
+            tot += src.sum()
+        rows = src.view(-1, 16)
+        pick = torch.randperm(rows.shape[0], device=dev)[: rows.shape[0] // 4]
+        for _ in range(COPY_CAL_REPS):
+            torch.index_select(rows, 0, pick, out=dst.view(-1, 16)[: pick.numel()])
         torch.cuda.synchronize()
-        del src, dst
+        log(f"[bench] calibration: copy {COPY_CAL_MIB} MiB, sum {COPY_CAL_MIB} MiB, gather {pick.numel()} rows "
+            f"of 64 B ({pick.numel() * 64 / 2**20:.0f} MiB), {COPY_CAL_REPS} times each")
+        del src, dst, rows, pick
     t0 = time.time()
     wl, desc = make_workload(args.workload)
     sc, cams = wl.scene, wl.cameras
