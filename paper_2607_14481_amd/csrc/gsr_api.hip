@@ -116,10 +116,11 @@ gsr::WsLayout make_layout(uint64_t n, const gsr::ViewTable &vt, uint64_t cap) {
     L.pkey[1] = take(4 * cap);
     L.pval[0] = take(4 * cap);
     L.pval[1] = take(4 * cap);
+    L.pflag = take((cap + 3) & ~uint64_t(3));
     L.hist = take(4ull * 256 * L.hist_blocks);
     L.digit_total = take(4 * 256);
     L.ranges = take(8ull * vt.total_tiles);
-    L.tile_cut = take(16ull * vt.total_tiles);
+    L.tile_cut = take(4ull * vt.total_tiles);
     L.tile_order = take(4ull * kCostBuckets * (1 + vt.total_tiles));
     L.long_tiles = take(4ull * (3 * kMaxLongTiles + 2));
     L.pix_T = take(4ull * vt.total_pixels);
@@ -151,12 +152,12 @@ struct Ptrs {
     gsr::WsHeader *hdr;
     gsr::Rec *rec;
     float2 *ulo;
-    uint32_t *zkey, *count, *scan_tmp, *vis, *poff, *chunk_item, *pkey[2], *pval[2], *hist, *digit_total;
+    uint32_t *zkey, *count, *scan_tmp, *vis, *poff, *chunk_item, *pkey[2], *pval[2], *hist, *digit_total, *pflag;
     float4 *screen;
     float *carry;
     uint4 *item_box;
     uint2 *ranges;
-    uint4 *tile_cut;
+    uint32_t *tile_cut;
     uint32_t *tile_order;
     uint32_t *long_tiles, *view_seg;
     float *pix_T;
@@ -177,13 +178,14 @@ Ptrs carve(void *ws, const gsr::WsLayout &L) {
         p.pkey[k] = reinterpret_cast<uint32_t *>(b + L.pkey[k]);
         p.pval[k] = reinterpret_cast<uint32_t *>(b + L.pval[k]);
     }
+    p.pflag = reinterpret_cast<uint32_t *>(b + L.pflag);
     p.vis = reinterpret_cast<uint32_t *>(b + L.vis);
     p.poff = reinterpret_cast<uint32_t *>(b + L.poff);
     p.chunk_item = reinterpret_cast<uint32_t *>(b + L.chunk_item);
     p.carry = reinterpret_cast<float *>(b + L.carry);
     p.item_box = reinterpret_cast<uint4 *>(b + L.item_box);
     p.screen = reinterpret_cast<float4 *>(b + L.screen);
-    p.tile_cut = reinterpret_cast<uint4 *>(b + L.tile_cut);
+    p.tile_cut = reinterpret_cast<uint32_t *>(b + L.tile_cut);
     p.tile_order = reinterpret_cast<uint32_t *>(b + L.tile_order);
     p.long_tiles = reinterpret_cast<uint32_t *>(b + L.long_tiles);
     p.hist = reinterpret_cast<uint32_t *>(b + L.hist);
@@ -286,10 +288,10 @@ int backward_impl(void *ws, size_t ws_bytes, const gsr_gaussians *g, int32_t n_v
     Upstream up{dL_drgb, target_rgb, 0.f};
     if (target_rgb) up.l1_scale = 1.0f / (float)(3.0 * (double)vt.total_pixels);
     launch_composite_bwd(vt, p.ranges, p.pval[pc], p.rec, p.ulo, out_rgb, up, p.pix_n, p.tile_cut, p.tile_order, p.partial,
-                         zr, p.hdr, pers, persistent_ctas(cfg), st);
+                         reinterpret_cast<uint8_t *>(p.pflag), zr, p.hdr, pers, persistent_ctas(cfg), st);
     mark.end(GSR_STAGE_COMPOSITE_BWD);
     mark.begin(GSR_STAGE_PROJECT_BWD);
-    launch_pair_reduce(p.poff, p.chunk_item, cap, p.item_box, p.tile_cut, p.partial, p.screen, p.carry, p.hdr, st);
+    launch_pair_reduce(p.poff, p.chunk_item, cap, p.item_box, p.pflag, p.partial, p.screen, p.carry, p.hdr, st);
     launch_project_bwd(*g, vt, world_to_cam, (uint64_t)g->n, p.rec, p.count, p.vis, p.hdr, p.screen, p.carry, *grads,
                        p.pose_part, L.pose_blocks, p.view_seg, vt.total_tiles == 0, st);
     if (g->n == 0)  // no Gaussian wrote a partial: the pose gradient is zero
@@ -364,7 +366,7 @@ int gsr_rasterize_forward(void *ws, size_t ws_bytes, const gsr_gaussians *g, int
     mark.end(GSR_STAGE_COMPACT);
     mark.begin(GSR_STAGE_EMIT);
     const uint64_t pair_grid = cap;  // every kernel reads the pair count from the header
-    launch_emit_pairs(p.poff, p.chunk_item, p.item_box, pair_grid, p.pkey[0], p.pval[0], p.hdr, st);
+    launch_emit_pairs(p.poff, p.chunk_item, p.item_box, pair_grid, p.pkey[0], p.pval[0], p.pflag, p.hdr, st);
     mark.end(GSR_STAGE_EMIT);
     mark.begin(GSR_STAGE_TILE_SORT);
     int pc = 0;
@@ -406,7 +408,7 @@ int gsr_rasterize_forward(void *ws, size_t ws_bytes, const gsr_gaussians *g, int
     mark.end(GSR_STAGE_TILE_SORT);
     const bool pers = (flags & GSR_FLAG_PERSISTENT) != 0;
     mark.begin(GSR_STAGE_COMPOSITE_FWD);
-    launch_composite_fwd(vt, p.ranges, p.pval[pc], p.rec, p.ulo, p.zkey, bgc, out_rgb, out_T, p.pix_T, p.pix_n,
+    launch_composite_fwd(vt, p.ranges, p.pval[pc], p.rec, p.ulo, bgc, out_rgb, out_T, p.pix_T, p.pix_n,
                          p.tile_cut, p.tile_order, p.hdr, pers, persistent_ctas(cfg), (flags & GSR_FLAG_STATS) != 0,
                          st);
     mark.end(GSR_STAGE_COMPOSITE_FWD);

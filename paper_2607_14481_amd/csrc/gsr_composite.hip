@@ -14,11 +14,10 @@
 //
 // Early stop.  Dense scenes saturate long before the end of a tile's list:
 // the forward records per tile the number of list positions any of its
-// pixels used (nmax) and, for the first unused position, the (depth key,
-// item) of its Gaussian -- the list's sort key.  The backward replays only
-// [start, start + nmax), and the per-Gaussian reduction skips pairs whose key
-// is at or beyond a tile's cut, so unused pairs cost neither a replay nor a
-// write.
+// pixels used (nmax).  The backward replays only [start, start + nmax) and
+// flags the pair slots of those positions as it stages their records; the
+// per-Gaussian reduction reads the moments of flagged slots only, so unused
+// pairs cost neither a replay nor a write nor a read.
 //
 // Backward.  Front to back again (nothing per (pixel, Gaussian) is stored):
 // from the forward's output C_out and the running accumulation, the colour
@@ -211,10 +210,10 @@ template <int RPL, bool STATS>
 __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uint2 *__restrict__ ranges,
                                                          const uint32_t *__restrict__ pval,
                                                          const Rec *__restrict__ rec, const float2 *__restrict__ ulo,
-                                                         const uint32_t *__restrict__ zkey, float3 bg,
+                                                         float3 bg,
                                                          float *__restrict__ out_rgb, float *__restrict__ out_T,
                                                          float *__restrict__ pix_T, uint32_t *__restrict__ pix_n,
-                                                         uint4 *__restrict__ tile_cut, uint32_t *__restrict__ tile_order,
+                                                         uint32_t *__restrict__ tile_cut, uint32_t *__restrict__ tile_order,
                                                          WsHeader *hdr, int persistent) {
     __shared__ float4 sa[kWave], sb[kWave], sd[kWave];
     const int lane = threadIdx.x;
@@ -337,10 +336,7 @@ __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uin
             }
         }
         if (lane == 0) {
-            // positions the backward replays, and the sort key of the first
-            // entry it does not (above every key when it replays them all)
-            const uint32_t item = nmax < len ? pval[rg.x + nmax] : 0xffffffffu;
-            tile_cut[t] = make_uint4(nmax, nmax < len ? zkey[item] : 0xffffffffu, item, 0u);
+            tile_cut[t] = nmax;  // positions the backward replays
             // the backward's schedule: this tile in the bucket of its replay count
             const uint32_t b = cost_bucket(nmax);
             const uint32_t slot = atomicAdd(&tile_order[b], 1u);
@@ -390,10 +386,10 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
                                                          const Rec *__restrict__ rec, const float2 *__restrict__ ulo,
                                                          const float *__restrict__ out_rgb, Upstream up,
                                                          const uint32_t *__restrict__ pix_n,
-                                                         const uint4 *__restrict__ tile_cut,
+                                                         const uint32_t *__restrict__ tile_cut,
                                                          const uint32_t *__restrict__ tile_order,
-                                                         float *__restrict__ partial, ZeroRows zr, WsHeader *hdr,
-                                                         int persistent) {
+                                                         float *__restrict__ partial, uint8_t *__restrict__ pflag,
+                                                         ZeroRows zr, WsHeader *hdr, int persistent) {
     __shared__ float4 sa[kWave], sb[kWave], sd[kWave];
     __shared__ float red[kRedRows * kRedStride];
     const int lane = threadIdx.x;
@@ -439,7 +435,7 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
             }
         }
         const uint2 rg = ranges[t];
-        const uint32_t end = rg.x + tile_cut[t].x;  // positions any pixel of the tile used
+        const uint32_t end = rg.x + tile_cut[t];  // positions any pixel of the tile used
         for (uint32_t b0 = rg.x; b0 < end; b0 += kWave) {
             const uint32_t idx = b0 + lane;
             if (idx < end) {
@@ -449,6 +445,7 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
                 sa[lane] = a;
                 sb[lane] = b;
                 sd[lane] = d;
+                pflag[__float_as_uint(d.z)] = 1;  // this pair's moments get written: the reduction reads them
             }
             __syncthreads();
             const int cnt = (int)min((uint32_t)kWave, end - b0);
@@ -483,14 +480,14 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
                             a_c2 = fmaf(w, g2[k], a_c2);
                             const float grgb = fmaf(g0[k], b.z, fmaf(g1[k], b.w, g2[k] * d.x));
                             // alpha dL/dalpha = alpha T g.c - alpha g.B / (1 - alpha), with
-                            // B the colour behind this Gaussian: w = alpha T where it
-                            // contributes, and gB already excludes its own term
-                            const float t1 = w * grgb;
-                            gB[k] -= t1;
-                            const float ar = alpha * __builtin_amdgcn_rcpf(1.f - alpha);
+                            // B the colour behind this Gaussian; with w = alpha T and
+                            // T' = T (1 - alpha) that is w (g.c - g.B / T') (w = 0 where
+                            // the Gaussian does not contribute)
+                            gB[k] = fmaf(-w, grgb, gB[k]);
                             T[k] -= w;  // T (1 - alpha) where the Gaussian contributed
+                            const float h = fmaf(-gB[k], __builtin_amdgcn_rcpf(T[k]), grgb);
                             // dL/dsigma = -sa, alpha dL/dalpha = sa (zero through the 0.99 clamp)
-                            const float sa_ = (ok && araw < kAlphaMax) ? fmaf(-gB[k], ar, t1) : 0.f;
+                            const float sa_ = (araw < kAlphaMax ? w : 0.f) * h;
                             a_sa += sa_;
                             const float say = sa_ * dy;
                             a_say += say;
@@ -559,8 +556,8 @@ static int resident_ctas(Kernel kernel, int requested) {
 }
 
 void launch_composite_fwd(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
-                          const float2 *ulo, const uint32_t *zkey, float3 bg, float *out_rgb, float *out_T,
-                          float *pix_T, uint32_t *pix_n, uint4 *tile_cut, uint32_t *tile_order, WsHeader *hdr,
+                          const float2 *ulo, float3 bg, float *out_rgb, float *out_T, float *pix_T,
+                          uint32_t *pix_n, uint32_t *tile_cut, uint32_t *tile_order, WsHeader *hdr,
                           bool persistent, int persistent_ctas, bool stats, hipStream_t st) {
     if (vt.total_tiles == 0) return;
     const int p = persistent ? 1 : 0;
@@ -568,7 +565,7 @@ void launch_composite_fwd(const ViewTable &vt, const uint2 *ranges, const uint32
     hipLaunchKernelGGL((k_composite_fwd<R, S>),                                                                     \
                        dim3(persistent ? (unsigned)resident_ctas(k_composite_fwd<R, S>, persistent_ctas)            \
                                        : vt.total_tiles),                                                           \
-                       dim3(kWave), 0, st, vt, ranges, pval, rec, ulo, zkey, bg, out_rgb, out_T, pix_T, pix_n,      \
+                       dim3(kWave), 0, st, vt, ranges, pval, rec, ulo, bg, out_rgb, out_T, pix_T, pix_n,            \
                        tile_cut, tile_order, hdr, p)
 #define GSR_FWD_RPL(R) \
     if (stats) GSR_FWD(R, true); else GSR_FWD(R, false)
@@ -584,8 +581,8 @@ void launch_composite_fwd(const ViewTable &vt, const uint2 *ranges, const uint32
 
 void launch_composite_bwd(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
                           const float2 *ulo, const float *out_rgb, const Upstream &up, const uint32_t *pix_n,
-                          const uint4 *tile_cut, const uint32_t *tile_order, float *partial, const ZeroRows &zr,
-                          WsHeader *hdr, bool persistent, int persistent_ctas, hipStream_t st) {
+                          const uint32_t *tile_cut, const uint32_t *tile_order, float *partial, uint8_t *pflag,
+                          const ZeroRows &zr, WsHeader *hdr, bool persistent, int persistent_ctas, hipStream_t st) {
     if (vt.total_tiles == 0) return;
     const int p = persistent ? 1 : 0;
 #define GSR_BWD(R)                                                                                                  \
@@ -593,7 +590,7 @@ void launch_composite_bwd(const ViewTable &vt, const uint2 *ranges, const uint32
                        dim3(persistent ? (unsigned)resident_ctas(k_composite_bwd<R>, persistent_ctas)               \
                                        : vt.total_tiles),                                                           \
                        dim3(kWave), 0, st, vt, ranges, pval, rec, ulo, out_rgb, up, pix_n, tile_cut, tile_order,    \
-                       partial, zr, hdr, p)
+                       partial, pflag, zr, hdr, p)
     switch (vt.tile_h) {
         case 4: GSR_BWD(1); break;
         case 8: GSR_BWD(2); break;

@@ -78,10 +78,11 @@ struct WsLayout {
     size_t screen;      // float4[items * 3] per-item sums of the pair moments
     size_t pkey[2];     // u32[cap] tile keys ping-pong
     size_t pval[2];     // u32[cap] item ids ping-pong
+    size_t pflag;       // u8[cap] per pair slot (emission order): 1 once the backward compositing wrote its moments
     size_t hist;        // u32[256 * max_blocks] radix histograms
     size_t digit_total; // u32[256] radix digit totals
     size_t ranges;      // uint2[total_tiles]
-    size_t tile_cut;    // uint4[total_tiles] (positions replayed, depth key and item of the first one not replayed)
+    size_t tile_cut;    // u32[total_tiles]: list positions any pixel of the tile used (the backward replays those)
     size_t tile_order;  // u32[kCostBuckets] bucket counts, then u32[kCostBuckets][tiles] tile ids per bucket
     size_t long_tiles;  // u32[kMaxLongTiles] tiles whose list is longer than kGroupSortMax (any order), then
                         // u32[2][kMaxLongTiles + 1] their first window of kLongWindow / kMergeWindow entries
@@ -180,14 +181,14 @@ void launch_expand_ranges(const uint2 *ranges, uint32_t total_tiles, uint32_t *p
                           hipStream_t st);
 void launch_reset_queue(WsHeader *h, int which, hipStream_t st);
 void launch_emit_pairs(const uint32_t *poff, const uint32_t *chunk_item, const uint4 *item_box, uint64_t pair_grid,
-                       uint32_t *pkey, uint32_t *pval, const WsHeader *hdr, hipStream_t st);
+                       uint32_t *pkey, uint32_t *pval, uint32_t *pflag, const WsHeader *hdr, hipStream_t st);
 // Also clears the backward schedule's bucket counts (tile_order).
 void launch_tile_ranges(const uint32_t *pkey, uint64_t cap, uint2 *ranges, uint32_t total_tiles,
                         uint32_t *long_tiles, uint32_t *tile_order, WsHeader *hdr, hipStream_t st);
 
 void launch_composite_fwd(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
-                          const float2 *ulo, const uint32_t *zkey, float3 bg, float *out_rgb, float *out_T,
-                          float *pix_T, uint32_t *pix_n, uint4 *tile_cut, uint32_t *tile_order, WsHeader *hdr,
+                          const float2 *ulo, float3 bg, float *out_rgb, float *out_T, float *pix_T,
+                          uint32_t *pix_n, uint32_t *tile_cut, uint32_t *tile_order, WsHeader *hdr,
                           bool persistent, int persistent_ctas, bool stats, hipStream_t st);
 // Gradient rows of the Gaussians no view saw are zeroed by the backward
 // compositing (memory work hidden under its ALU work): tile t takes Gaussians
@@ -207,10 +208,10 @@ struct Upstream {
 };
 void launch_composite_bwd(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
                           const float2 *ulo, const float *out_rgb, const Upstream &up, const uint32_t *pix_n,
-                          const uint4 *tile_cut, const uint32_t *tile_order, float *partial, const ZeroRows &zr,
-                          WsHeader *hdr, bool persistent, int persistent_ctas, hipStream_t st);
+                          const uint32_t *tile_cut, const uint32_t *tile_order, float *partial, uint8_t *pflag,
+                          const ZeroRows &zr, WsHeader *hdr, bool persistent, int persistent_ctas, hipStream_t st);
 void launch_pair_reduce(const uint32_t *poff, const uint32_t *chunk_item, uint64_t pair_grid, const uint4 *item_box,
-                        const uint4 *tile_cut, const float *partial, float4 *screen, float *carry, const WsHeader *hdr,
+                        const uint32_t *pflag, const float *partial, float4 *screen, float *carry, const WsHeader *hdr,
                         hipStream_t st);
 
 // zero_unseen: also write the zero rows of the Gaussians no view saw (when the

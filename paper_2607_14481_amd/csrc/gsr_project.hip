@@ -286,9 +286,11 @@ void launch_project_fwd(const gsr_gaussians &g, const ViewTable &vt, const float
 // from one to thousands (splats near the camera), so the work is split by
 // pairs, not by items: a workgroup takes one chunk of 1024 consecutive pair
 // slots, 4 per thread (nine float4 loads per thread, coalesced).  Pairs whose
-// tile stopped before reaching the item (its (depth key, item) at or beyond
-// the tile's cut) were never written by the backward compositing and count as
-// zero.
+// tile stopped before reaching the item were never written by the backward
+// compositing and count as zero: the emission clears one flag byte per slot
+// and the backward compositing sets the flags of the slots it replays, so the
+// flags (4 per thread, one 32-bit load) tell which moments to load without
+// finding each pair's tile first.
 //
 // Within the chunk a segmented inclusive scan over the threads (keys = local
 // item index, wave-level shuffles then a carry across the four waves) gives
@@ -325,7 +327,7 @@ __device__ __forceinline__ void write_item_sum(const ChunkItems &ci, uint32_t k,
 __global__ __launch_bounds__(kChunkThreads) void k_pair_reduce(const uint32_t *__restrict__ poff,
                                                                const uint32_t *__restrict__ chunk_item,
                                                                const uint4 *__restrict__ item_box,
-                                                               const uint4 *__restrict__ tile_cut,
+                                                               const uint32_t *__restrict__ pflag,
                                                                const float *__restrict__ partial,
                                                                float4 *__restrict__ screen, float *__restrict__ carry,
                                                                const WsHeader *__restrict__ hdr) {
@@ -340,30 +342,17 @@ __global__ __launch_bounds__(kChunkThreads) void k_pair_reduce(const uint32_t *_
     const uint32_t cend = min(c0 + kChunkPairs, m);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
 
-    // ---- this thread's pairs: their items and whether each is ahead of its
-    // tile's cut (pairs past the cut were never written by the backward
-    // compositing: most of a dense scene's pairs, so their values are not read)
+    // ---- this thread's pairs and whether the backward compositing wrote
+    // their moments (pairs past the positions their tile replayed were never
+    // reached: most of a dense scene's pairs, so their values are not read).
+    // The flags and the moments are loaded before the chunk's items, so their
+    // latency overlaps.
     const uint32_t pb = c0 + (uint32_t)tid * kChunkPerThread;
-    uint32_t i_lo;
-    const uint32_t nloc = load_chunk_items(poff, chunk_item, item_box, c, m, nvis, ci, i_lo);
-    uint32_t key[kChunkPerThread];
     bool valid[kChunkPerThread];
+    {
+        const uint32_t f4 = pb < cend ? pflag[pb / 4] : 0u;
 #pragma unroll
-    for (uint32_t u = 0; u < kChunkPerThread; ++u) key[u] = kNoKey, valid[u] = false;
-    if (pb < cend) {
-        PairWalker pw;
-        pw.start(ci, nloc, pb);
-#pragma unroll
-        for (uint32_t u = 0; u < kChunkPerThread; ++u) {
-            const uint32_t p = pb + u;
-            if (p < cend) {
-                if (u > 0) pw.next(ci, nloc, p);
-                key[u] = pw.k;
-                const uint4 cut = tile_cut[pw.tile(ci)];
-                const uint32_t zk = ci.zkey[pw.k];
-                valid[u] = zk < cut.y || (zk == cut.y && ci.item[pw.k] < cut.z);
-            }
-        }
+        for (uint32_t u = 0; u < kChunkPerThread; ++u) valid[u] = pb + u < cend && ((f4 >> (8 * u)) & 0xffu) != 0;
     }
     float x[kChunkPerThread][kPartialStride];
 #pragma unroll
@@ -395,6 +384,22 @@ __global__ __launch_bounds__(kChunkThreads) void k_pair_reduce(const uint32_t *_
 #pragma unroll
             for (int j = 0; j < kPartialStride; ++j)
                 x[u][j] = valid[u] ? partial[(size_t)(pb + u) * kPartialStride + j] : 0.f;
+    }
+    uint32_t i_lo;
+    const uint32_t nloc = load_chunk_items(poff, chunk_item, item_box, c, m, nvis, ci, i_lo);
+    uint32_t key[kChunkPerThread];
+#pragma unroll
+    for (uint32_t u = 0; u < kChunkPerThread; ++u) key[u] = kNoKey;
+    if (pb < cend) {
+        uint32_t k = find_chunk_item(ci, nloc, pb);
+#pragma unroll
+        for (uint32_t u = 0; u < kChunkPerThread; ++u) {
+            const uint32_t p = pb + u;
+            if (p < cend) {
+                while (k + 1 < nloc && ci.p0[k + 1] <= p) ++k;
+                key[u] = k;
+            }
+        }
     }
 
     // ---- segments inside the thread: head (first), complete middles, tail (last)
@@ -481,12 +486,12 @@ __global__ __launch_bounds__(kChunkThreads) void k_pair_reduce(const uint32_t *_
 }
 
 void launch_pair_reduce(const uint32_t *poff, const uint32_t *chunk_item, uint64_t pair_grid, const uint4 *item_box,
-                        const uint4 *tile_cut, const float *partial, float4 *screen, float *carry, const WsHeader *hdr,
+                        const uint32_t *pflag, const float *partial, float4 *screen, float *carry, const WsHeader *hdr,
                         hipStream_t st) {
     const uint64_t chunks = chunk_count(pair_grid);
     if (chunks == 0) return;
     hipLaunchKernelGGL(k_pair_reduce, dim3((unsigned)chunks), dim3(kChunkThreads), 0, st, poff, chunk_item, item_box,
-                       tile_cut, partial, screen, carry, hdr);
+                       pflag, partial, screen, carry, hdr);
 }
 
 // ---------------------------------------------------------------------------

@@ -499,7 +499,7 @@ __global__ __launch_bounds__(kChunkThreads) void k_emit(const uint32_t *__restri
                                                         const uint32_t *__restrict__ chunk_item,
                                                         const uint4 *__restrict__ item_box,
                                                         uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval,
-                                                        const WsHeader *__restrict__ hdr) {
+                                                        uint32_t *__restrict__ pflag, const WsHeader *__restrict__ hdr) {
     __shared__ ChunkItems ci;
     if (hdr->overflow) return;
     const uint32_t m = hdr->n_pairs, nvis = hdr->n_visible;
@@ -510,6 +510,7 @@ __global__ __launch_bounds__(kChunkThreads) void k_emit(const uint32_t *__restri
     const uint32_t nloc = load_chunk_items(poff, chunk_item, item_box, blockIdx.x, m, nvis, ci, i_lo);
     const uint32_t pb = c0 + threadIdx.x * kChunkPerThread;
     if (pb >= cend) return;
+    pflag[pb / 4] = 0u;  // the four slots' "moments written" flags, set by the backward compositing
     uint32_t key[kChunkPerThread], val[kChunkPerThread];
     PairWalker pw;
     pw.start(ci, nloc, pb);
@@ -531,11 +532,12 @@ __global__ __launch_bounds__(kChunkThreads) void k_emit(const uint32_t *__restri
 }
 
 void launch_emit_pairs(const uint32_t *poff, const uint32_t *chunk_item, const uint4 *item_box, uint64_t pair_grid,
-                       uint32_t *pkey, uint32_t *pval, const WsHeader *hdr, hipStream_t st) {
+                       uint32_t *pkey, uint32_t *pval, uint32_t *pflag, const WsHeader *hdr, hipStream_t st) {
+    static_assert(kChunkPerThread == 4, "one 32-bit word of slot flags per thread");
     const uint64_t chunks = chunk_count(pair_grid);
     if (chunks == 0) return;
     hipLaunchKernelGGL(k_emit, dim3((unsigned)chunks), dim3(kChunkThreads), 0, st, poff, chunk_item, item_box, pkey,
-                       pval, hdr);
+                       pval, pflag, hdr);
 }
 
 // ---------------------------------------------------------------------------
