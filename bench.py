@@ -251,6 +251,38 @@ def measure_view(wl, steps, warmup, tile_h=16, persistent=False, graph=True):
             "graph_ms": graph_ms, "graph_err": graph_err}
 
 
+def copy_rates(sizes_mb=(8, 16, 32, 64, 128, 256, 512), reps=40):
+    """Rate of a plain device copy (torch's copy kernel, half the bytes read,
+    half written) by the bytes one launch moves, launches back to back on one
+    stream as in a step: the HBM rate a memory-bound kernel of that size can
+    reach on this GPU, ramp-up and tail included.  Successive copies use
+    successive regions of 1 GiB pools, so the data is not cache-resident."""
+    import torch
+    pool_floats = 1 << 28
+    src = torch.ones(pool_floats, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    out = {}
+    for mb in sizes_mb:
+        n = (mb << 20) // 8
+        slots = pool_floats // n
+
+        def run(k):
+            for i in range(k):
+                o = (i % slots) * n
+                dst[o:o + n].copy_(src[o:o + n])
+
+        run(3)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run(reps)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        out[f"{mb}MB"] = {"us": round(us, 2), "TB_s": round((mb << 20) / (us * 1e-6) / 1e12, 3)}
+    del src, dst
+    return out
+
+
 def run_keyframe(wl, iterations=30, repeats=3):
     """The paper's per-keyframe optimisation (Sec. 5.2): `iterations` steps of
     forward, L1 loss, backward, fused Adam on the Gaussians the forward saw,
@@ -756,6 +788,10 @@ def main():
     ms_plain, ms_instrumented, stage_ms, stats = m["ms_plain"], m["ms_instrumented"], m["stage_ms"], m["stats"]
     graph_ms, graph_err = m["graph_ms"], m["graph_err"]
 
+    copy_rate = copy_rates()
+    log("[bench] plain copy rate by bytes per launch: " +
+        ", ".join(f"{k} {v['TB_s']} TB/s ({v['us']} us)" for k, v in copy_rate.items()))
+
     # ---- the other single-view workloads: small view, 200k at 1080p, the level-of-detail cut
     others = None
     if not args.no_other_workloads:
@@ -870,6 +906,7 @@ def main():
         "ms_per_step_with_stage_events": round(ms_instrumented, 4),
         "work": stats,
         "roofline": roofline,
+        "copy_rate_by_size": copy_rate,
         "cpu_baseline": cpu,
         "other_workloads": ({k: {a: b for a, b in v.items() if a != "_wl"} for k, v in others.items()}
                             if others else None),
