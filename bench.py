@@ -788,9 +788,11 @@ def main():
     ms_plain, ms_instrumented, stage_ms, stats = m["ms_plain"], m["ms_instrumented"], m["stage_ms"], m["stats"]
     graph_ms, graph_err = m["graph_ms"], m["graph_err"]
 
-    copy_rate = copy_rates()
-    log("[bench] plain copy rate by bytes per launch: " +
-        ", ".join(f"{k} {v['TB_s']} TB/s ({v['us']} us)" for k, v in copy_rate.items()))
+    copy_rate = None
+    if not args.copy_calibration:  # (a counter run keeps its copies to the calibration ones)
+        copy_rate = copy_rates()
+        log("[bench] plain copy rate by bytes per launch: " +
+            ", ".join(f"{k} {v['TB_s']} TB/s ({v['us']} us)" for k, v in copy_rate.items()))
 
     # ---- the other single-view workloads: small view, 200k at 1080p, the level-of-detail cut
     others = None
