@@ -291,7 +291,7 @@ int backward_impl(void *ws, size_t ws_bytes, const gsr_gaussians *g, int32_t n_v
                          reinterpret_cast<uint8_t *>(p.pflag), zr, p.hdr, pers, persistent_ctas(cfg), st);
     mark.end(GSR_STAGE_COMPOSITE_BWD);
     mark.begin(GSR_STAGE_PROJECT_BWD);
-    launch_pair_reduce(p.poff, p.chunk_item, cap, p.item_box, p.pflag, p.partial, p.screen, p.carry, p.hdr, st);
+    launch_pair_reduce(p.poff, p.chunk_item, cap, p.vis, p.pflag, p.partial, p.screen, p.carry, p.hdr, st);
     launch_project_bwd(*g, vt, world_to_cam, (uint64_t)g->n, p.rec, p.count, p.vis, p.hdr, p.screen, p.carry, *grads,
                        p.pose_part, L.pose_blocks, p.view_seg, vt.total_tiles == 0, st);
     if (g->n == 0)  // no Gaussian wrote a partial: the pose gradient is zero

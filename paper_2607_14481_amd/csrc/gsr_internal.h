@@ -210,7 +210,7 @@ void launch_composite_bwd(const ViewTable &vt, const uint2 *ranges, const uint32
                           const float2 *ulo, const float *out_rgb, const Upstream &up, const uint32_t *pix_n,
                           const uint32_t *tile_cut, const uint32_t *tile_order, float *partial, uint8_t *pflag,
                           const ZeroRows &zr, WsHeader *hdr, bool persistent, int persistent_ctas, hipStream_t st);
-void launch_pair_reduce(const uint32_t *poff, const uint32_t *chunk_item, uint64_t pair_grid, const uint4 *item_box,
+void launch_pair_reduce(const uint32_t *poff, const uint32_t *chunk_item, uint64_t pair_grid, const uint32_t *vis,
                         const uint32_t *pflag, const float *partial, float4 *screen, float *carry, const WsHeader *hdr,
                         hipStream_t st);
 

@@ -293,8 +293,9 @@ void launch_project_fwd(const gsr_gaussians &g, const ViewTable &vt, const float
 // finding each pair's tile first.
 //
 // Within the chunk a segmented inclusive scan over the threads (keys = local
-// item index, wave-level shuffles then a carry across the four waves) gives
-// each item's sum at the thread holding its last pair.  Items that lie wholly
+// item index; in each wave DPP row shifts and row broadcasts, which stay in
+// the VALU, then a carry across the four waves) gives each item's sum at the
+// thread holding its last pair.  Items that lie wholly
 // in the chunk are written to `screen`; an item that starts before the chunk
 // leaves its part of this chunk in carry[c][0], one that ends after it in
 // carry[c][1], and A9 adds an item's parts from its first chunk to its last
@@ -303,7 +304,63 @@ void launch_project_fwd(const gsr_gaussians &g, const ViewTable &vt, const float
 // ---------------------------------------------------------------------------
 constexpr uint32_t kNoKey = 0xffffffffu;
 
-__device__ __forceinline__ void write_item_sum(const ChunkItems &ci, uint32_t k, uint32_t c0, uint32_t cend,
+// The chunk's items as the reduction needs them: first pair slot and item id
+// (p0[nloc] is the end of the last one).  Item ids come from the visible list.
+struct ChunkSlots {
+    uint32_t p0[kChunkPairs + 2];
+    uint32_t item[kChunkPairs + 1];
+};
+
+__device__ __forceinline__ uint32_t load_chunk_slots(const uint32_t *__restrict__ poff,
+                                                     const uint32_t *__restrict__ chunk_item,
+                                                     const uint32_t *__restrict__ vis, uint32_t c, uint32_t m,
+                                                     uint32_t nvis, ChunkSlots &cs) {
+    const uint32_t c0 = c * kChunkPairs;
+    const uint32_t i_lo = chunk_item[c];
+    const uint32_t i_hi = c0 + kChunkPairs < m ? chunk_item[c + 1] : nvis - 1;
+    const uint32_t nloc = i_hi - i_lo + 1;
+    for (uint32_t k = threadIdx.x; k <= nloc; k += kChunkThreads) {
+        const uint32_t i = i_lo + k;
+        if (k == nloc) {
+            cs.p0[k] = i < nvis ? poff[i] : m;
+            continue;
+        }
+        cs.p0[k] = poff[i];
+        cs.item[k] = vis[i];
+    }
+    __syncthreads();
+    return nloc;
+}
+
+// largest local index k < nloc with p0[k] <= p (p0[0] <= p holds)
+__device__ __forceinline__ uint32_t find_chunk_slot(const ChunkSlots &cs, uint32_t nloc, uint32_t p) {
+    uint32_t lo = 0, hi = nloc - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (cs.p0[mid] <= p)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// One step of a segmented inclusive scan over the wave: (v, f) takes the
+// (value, segment-start) pair of the lane `CTRL` names (rows outside ROW_MASK,
+// and lanes without a source, take (0, false)) and combines
+// (v_src, f_src) + (v, f) = (f ? v : v_src + v, f_src | f).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void seg_scan_step(float (&v)[kPartialStride], bool &f) {
+    const bool fs = __builtin_amdgcn_update_dpp(0, f ? 1 : 0, CTRL, ROW_MASK, 0xf, false) != 0;
+#pragma unroll
+    for (int j = 0; j < kPartialStride; ++j) {
+        const float o = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[j]), CTRL, ROW_MASK, 0xf, false));
+        v[j] = f ? v[j] : o + v[j];
+    }
+    f = f || fs;
+}
+
+__device__ __forceinline__ void write_item_sum(const ChunkSlots &ci, uint32_t k, uint32_t c0, uint32_t cend,
                                                uint32_t c, const float v[kPartialStride], float4 *__restrict__ screen,
                                                float *__restrict__ carry) {
     const bool before = ci.p0[k] < c0, after = ci.p0[k + 1] > cend;
@@ -326,12 +383,12 @@ __device__ __forceinline__ void write_item_sum(const ChunkItems &ci, uint32_t k,
 
 __global__ __launch_bounds__(kChunkThreads) void k_pair_reduce(const uint32_t *__restrict__ poff,
                                                                const uint32_t *__restrict__ chunk_item,
-                                                               const uint4 *__restrict__ item_box,
+                                                               const uint32_t *__restrict__ vis,
                                                                const uint32_t *__restrict__ pflag,
                                                                const float *__restrict__ partial,
                                                                float4 *__restrict__ screen, float *__restrict__ carry,
                                                                const WsHeader *__restrict__ hdr) {
-    __shared__ ChunkItems ci;
+    __shared__ ChunkSlots ci;
     __shared__ uint32_t s_kf[kChunkThreads], s_kl[kChunkThreads];
     __shared__ float s_wv[4][kPartialStride];
     __shared__ uint32_t s_wf[4];
@@ -385,13 +442,12 @@ __global__ __launch_bounds__(kChunkThreads) void k_pair_reduce(const uint32_t *_
             for (int j = 0; j < kPartialStride; ++j)
                 x[u][j] = valid[u] ? partial[(size_t)(pb + u) * kPartialStride + j] : 0.f;
     }
-    uint32_t i_lo;
-    const uint32_t nloc = load_chunk_items(poff, chunk_item, item_box, c, m, nvis, ci, i_lo);
+    const uint32_t nloc = load_chunk_slots(poff, chunk_item, vis, c, m, nvis, ci);
     uint32_t key[kChunkPerThread];
 #pragma unroll
     for (uint32_t u = 0; u < kChunkPerThread; ++u) key[u] = kNoKey;
     if (pb < cend) {
-        uint32_t k = find_chunk_item(ci, nloc, pb);
+        uint32_t k = find_chunk_slot(ci, nloc, pb);
 #pragma unroll
         for (uint32_t u = 0; u < kChunkPerThread; ++u) {
             const uint32_t p = pb + u;
@@ -435,20 +491,14 @@ __global__ __launch_bounds__(kChunkThreads) void k_pair_reduce(const uint32_t *_
 
     // ---- segmented inclusive scan of the tails: (v, f) with f = "a segment starts in range"
     bool f = multi || kl_prev != kf;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        float o[kPartialStride];
-#pragma unroll
-        for (int j = 0; j < kPartialStride; ++j) o[j] = __shfl_up(v[j], d, kWave);
-        const bool of = __shfl_up((int)f, d, kWave) != 0;
-        if (lane >= d) {
-            if (!f) {
-#pragma unroll
-                for (int j = 0; j < kPartialStride; ++j) v[j] = o[j] + v[j];
-            }
-            f = f || of;
-        }
-    }
+    // Hillis-Steele within each row of 16 lanes, then the row totals by two
+    // row broadcasts (lane 15 into rows 1 and 3, lane 31 into rows 2 and 3)
+    seg_scan_step<0x111, 0xf>(v, f);  // row_shr:1
+    seg_scan_step<0x112, 0xf>(v, f);  // row_shr:2
+    seg_scan_step<0x114, 0xf>(v, f);  // row_shr:4
+    seg_scan_step<0x118, 0xf>(v, f);  // row_shr:8
+    seg_scan_step<0x142, 0xa>(v, f);  // row_bcast:15
+    seg_scan_step<0x143, 0xc>(v, f);  // row_bcast:31
     if (lane == kWave - 1) {
 #pragma unroll
         for (int j = 0; j < kPartialStride; ++j) s_wv[wv][j] = v[j];
@@ -470,10 +520,8 @@ __global__ __launch_bounds__(kChunkThreads) void k_pair_reduce(const uint32_t *_
     // inclusive value of the previous thread's tail segment
     float prev[kPartialStride];
 #pragma unroll
-    for (int j = 0; j < kPartialStride; ++j) {
-        const float up = __shfl_up(v[j], 1, kWave);
-        prev[j] = lane == 0 ? cin[j] : up;
-    }
+    for (int j = 0; j < kPartialStride; ++j)  // wave_shr:1, lane 0 keeps cin
+        prev[j] = __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(cin[j]), __float_as_int(v[j]), 0x138, 0xf, 0xf, false));
 
     // ---- finished segments
     if (multi && kf != kNoKey) {  // the head segment ends in this thread
@@ -485,12 +533,12 @@ __global__ __launch_bounds__(kChunkThreads) void k_pair_reduce(const uint32_t *_
     if (kl != kNoKey && kf_next != kl) write_item_sum(ci, kl, c0, cend, c, v, screen, carry);
 }
 
-void launch_pair_reduce(const uint32_t *poff, const uint32_t *chunk_item, uint64_t pair_grid, const uint4 *item_box,
+void launch_pair_reduce(const uint32_t *poff, const uint32_t *chunk_item, uint64_t pair_grid, const uint32_t *vis,
                         const uint32_t *pflag, const float *partial, float4 *screen, float *carry, const WsHeader *hdr,
                         hipStream_t st) {
     const uint64_t chunks = chunk_count(pair_grid);
     if (chunks == 0) return;
-    hipLaunchKernelGGL(k_pair_reduce, dim3((unsigned)chunks), dim3(kChunkThreads), 0, st, poff, chunk_item, item_box,
+    hipLaunchKernelGGL(k_pair_reduce, dim3((unsigned)chunks), dim3(kChunkThreads), 0, st, poff, chunk_item, vis,
                        pflag, partial, screen, carry, hdr);
 }
 
