@@ -162,12 +162,7 @@ __device__ __noinline__ uint32_t tile_by_cost(const uint32_t *__restrict__ order
     static_assert(kCostBuckets == 2 * kWave, "two buckets per lane");
     // lane l: buckets 127 - 2l and 126 - 2l (descending cost)
     const uint32_t b0 = kCostBuckets - 1 - 2 * lane, c0 = order[b0], c1 = order[b0 - 1];
-    uint32_t incl = c0 + c1;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = (uint32_t)__shfl_up((int)incl, o, 64);
-        if (lane >= o) incl += y;
-    }
+    const uint32_t incl = wave_inclusive_scan(c0 + c1, [](uint32_t a, uint32_t b) { return a + b; });
     if ((uint32_t)__shfl((int)incl, 63, 64) != total_tiles) return r;
     const unsigned long long past = __ballot(r < incl);  // lanes whose buckets end beyond r
     const int L = __ffsll((long long)past) - 1;

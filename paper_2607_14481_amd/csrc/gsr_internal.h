@@ -291,6 +291,22 @@ __device__ __forceinline__ float wave_sum(float v) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave, `add` combining, with DPP
+// moves that stay in the VALU: Hillis-Steele row shifts by 1, 2, 4 and 8
+// within each row of 16 lanes, then the row totals by two row broadcasts
+// (lane 15 into rows 1 and 3, lane 31 into rows 2 and 3).  Lanes without a
+// source lane, and rows a broadcast skips, combine with 0.
+template <class Add>
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x, Add add) {
+    x = add(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false));  // row_shr:1
+    x = add(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false));  // row_shr:2
+    x = add(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false));  // row_shr:4
+    x = add(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false));  // row_shr:8
+    x = add(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    x = add(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return x;
+}
+
 __device__ __forceinline__ uint32_t pack_u16(uint32_t lo, uint32_t hi) { return lo | (hi << 16); }
 
 // The chip's 8 XCDs (each with its own L2) take a grid's workgroups in turn:

@@ -30,12 +30,7 @@ __device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) {
 // Block-wide exclusive scan of one value per thread (256 threads), saturating.
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t *lds /* [4] */, uint32_t &total) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint32_t inc = x;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(inc, o, 64);
-        if (lane >= o) inc = sat_add(inc, y);
-    }
+    const uint32_t inc = wave_inclusive_scan(x, sat_add);
     if (lane == 63) lds[w] = inc;
     __syncthreads();
     uint32_t before = 0;
@@ -82,12 +77,7 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t *__restrict__ blo
     for (uint32_t base = 0; base < nb; base += 1024) {
         const uint32_t i = base + threadIdx.x;
         const uint32_t x = i < nb ? block_sums[i] : 0u;
-        uint32_t inc = x;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(inc, o, 64);
-            if (lane >= o) inc = sat_add(inc, y);
-        }
+        const uint32_t inc = wave_inclusive_scan(x, sat_add);
         if (lane == 63) lds[w] = inc;
         __syncthreads();
         uint32_t before = carry;
