@@ -313,8 +313,7 @@ __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uin
                 nmax = max(nmax, last[k]);
             }
         }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) nmax = max(nmax, (uint32_t)__shfl_xor((int)nmax, o, kWave));
+        nmax = wave_reduce(nmax, 0u, [](uint32_t a, uint32_t b) { return max(a, b); });
         if constexpr (STATS) {
             // work counters for the measurement harness (integer adds: order independent)
             unsigned long long e = evals, rp = replays, cc = contrib;

@@ -307,6 +307,21 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x, Add add) {
     return x;
 }
 
+// Reduction over the 64 lanes of a wave with `op` (associative and
+// commutative, `identity` its neutral value), by the DPP pattern of wave_sum;
+// every lane gets the result.
+template <class Op>
+__device__ __forceinline__ uint32_t wave_reduce(uint32_t x, uint32_t identity, Op op) {
+    const int id = (int)identity;
+    x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)x, 0xB1, 0xf, 0xf, false));   // quad_perm [1, 0, 3, 2]
+    x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)x, 0x4E, 0xf, 0xf, false));   // quad_perm [2, 3, 0, 1]
+    x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)x, 0x141, 0xf, 0xf, false));  // row_half_mirror
+    x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)x, 0x140, 0xf, 0xf, false));  // row_mirror
+    x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)x, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)x, 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
 __device__ __forceinline__ uint32_t pack_u16(uint32_t lo, uint32_t hi) { return lo | (hi << 16); }
 
 // The chip's 8 XCDs (each with its own L2) take a grid's workgroups in turn:

@@ -688,14 +688,10 @@ __device__ __forceinline__ void sort_list_regs(uint32_t *__restrict__ list, uint
 constexpr uint32_t kMaxBucket = 16;
 
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, 64));
-    return v;
+    return wave_reduce(v, 0xffffffffu, [](uint32_t a, uint32_t b) { return min(a, b); });
 }
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
-    return v;
+    return wave_reduce(v, 0u, [](uint32_t a, uint32_t b) { return max(a, b); });
 }
 
 template <int E>
