@@ -272,10 +272,9 @@ __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uin
                     const bool ok = alpha >= kAlphaMin;
                     const float wa = alpha * T[k];
                     const float Tn = T[k] - wa;  // T (1 - alpha)
-                    // a stopped pixel has Tn <= 0 < kTMin, so it never adds again
-                    const bool low = Tn < kTMin;
-                    const bool stop = ok & low;
-                    const bool add = ok & !low;
+                    // a stopped pixel has Tn <= 0 < kTMin, so it never adds again; the
+                    // pixel stops where ok holds and add does not
+                    const bool add = ok & (Tn >= kTMin);
                     const float w = add ? wa : 0.f;
                     C0[k] = fmaf(b.z, w, C0[k]);
                     C1[k] = fmaf(b.w, w, C1[k]);
@@ -283,9 +282,9 @@ __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uin
                     last[k] = add ? pos + 1 : last[k];
                     if constexpr (STATS) {
                         ncontrib[k] += add ? 1u : 0u;
-                        stop_at[k] = (stop && T[k] > 0.f) ? pos : stop_at[k];
+                        stop_at[k] = (ok && !add && T[k] > 0.f) ? pos : stop_at[k];
                     }
-                    T[k] = add ? Tn : (stop ? -fabsf(T[k]) : T[k]);
+                    T[k] = add ? Tn : (ok ? -fabsf(T[k]) : T[k]);
                 }
             }
             __syncthreads();
