@@ -24,7 +24,10 @@
 // behind contributor k is B_k = C_out - sum_{j<=k} c_j a_j T_j; only its
 // projection on the upstream gradient g is needed, kept as one running value
 // g.B = g.C_out - sum, from which alpha dL/dalpha = w g.c - g.B alpha / (1 - alpha)
-// (w = alpha T).  A Gaussian that no lane reaches in any row skips the
+// (w = alpha T); with g.B taken after the Gaussian's own term and
+// T' = T (1 - alpha) that is w (g.c - g.B / T'), one reciprocal per row and
+// one fused multiply-add for the update of g.B.  A Gaussian that no lane
+// reaches in any row skips the
 // reduction: its moments are zero and the finalising lanes write zeros.
 // Per pair the kernel produces nine moments over the tile's pixels: with
 // w = dL/dsigma, the sums of w dx, w dy, w dx^2, w dx dy, w dy^2, of
