@@ -96,6 +96,69 @@ def host_cpu():
     return {"nproc": nproc, "model": model}
 
 
+def _oracle_tile_share(rank, procs, ready, start, results):
+    """One process of the all-core oracle timing: the unmodified oracle's
+    fwd + bwd of the headline view restricted to one band of tile rows (its
+    tile mask: those tiles' lists and pixels are the full render's, and the
+    oracle drops the Gaussians that touch none of them).  Rendering starts
+    when every process is ready."""
+    import numpy as np
+    from oracle import oracle as O
+    wl, _ = make_workload("headline")
+    sc, cam = wl.scene, wl.cameras[0]
+    tx, ty = O.tile_grid(cam)
+    row = np.arange(tx * ty) // tx
+    mask = ((row * procs) // ty == rank).astype(np.uint8)
+    rng = np.random.default_rng(0)
+    shape = (cam.height, cam.width, 3)
+    g = np.sign(rng.standard_normal(shape)) / float(np.prod(shape))  # L1-shaped upstream
+    ready.put(rank)
+    start.wait()
+    t = time.time()
+    O.render(sc, cam, bg=(0.0, 0.0, 0.0), tile_mask=mask, dL_dimg=g)
+    results.put((rank, time.time() - t, time.time()))
+
+
+def oracle_all_cores(procs, timeout=300.0):
+    """Wall time of one headline fwd + bwd of the oracle split by tiles over
+    `procs` fresh processes (spawned: no GPU state), from the moment all are
+    ready to the last one's end.  Each process also projects and bins every
+    Gaussian, the part a tile split does not divide.  Raises if a process
+    ends early or the run exceeds `timeout` seconds."""
+    import multiprocessing as mp
+    import queue as q
+    ctx = mp.get_context("spawn")
+    ready, results, start = ctx.Queue(), ctx.Queue(), ctx.Event()
+    ps = [ctx.Process(target=_oracle_tile_share, args=(r, procs, ready, start, results)) for r in range(procs)]
+    for p in ps:
+        p.start()
+
+    def collect(src, n, deadline):
+        out = []
+        while len(out) < n:
+            try:
+                out.append(src.get(timeout=1.0))
+            except q.Empty:
+                if any(p.exitcode not in (None, 0) for p in ps):
+                    raise RuntimeError("an oracle process ended early")
+                if time.time() > deadline:
+                    raise RuntimeError("oracle processes timed out")
+        return out
+
+    try:
+        deadline = time.time() + timeout
+        collect(ready, procs, deadline)
+        t0 = time.time()
+        start.set()
+        res = collect(results, procs, deadline)
+    finally:
+        for p in ps:
+            p.join(timeout=30)
+            if p.is_alive():
+                p.terminate()
+    return max(r[2] for r in res) - t0, sorted(r[1] for r in res)
+
+
 def make_workload(name):
     from paper_2607_14481_amd import scenes as S
     if name == "headline":
@@ -877,6 +940,19 @@ def main():
                "note": "the oracle is serial C: its summation order is the definition the GPU is checked "
                        "against, so it is timed on one core and not parallelised"}
         log(f"[bench] oracle fwd+bwd median {tfb:.2f}s of {runs}")
+        procs = max(1, min(16, host["nproc"]))
+        try:
+            walls = [oracle_all_cores(procs)[0] for _ in range(3)]
+            wall = float(np.median(walls))
+            cpu["all_cores"] = {
+                "value": round(1.0 / wall, 4), "unit": "iters/s", "cores": procs,
+                "sample": f"median of 3 ({', '.join(f'{w:.2f}' for w in walls)} s wall): the same fwd+bwd "
+                          f"split into {procs} bands of tile rows, one process each, each the unmodified oracle "
+                          f"on its band's tiles (every process still projects all Gaussians)"}
+            log(f"[bench] oracle fwd+bwd on {procs} processes: median {wall:.2f}s wall of {walls}")
+        except RuntimeError as e:
+            cpu["all_cores"] = {"error": str(e)}
+            log(f"[bench] oracle on {procs} processes failed: {e}")
         if others:
             cpu["other_workloads_s_per_iter"] = {}
             for name, o in others.items():
