@@ -42,13 +42,15 @@ def test_small_view_forward_backward_parity():
     assert rel_err(gpu["twist"][0], ref["twist"]) <= GRAD_TOL
 
 
-@pytest.mark.parametrize("stretch,opacity", [(2.5, None), (4.0, 0.02)])
+@pytest.mark.parametrize("stretch,opacity", [(2.5, None), (4.0, 0.02), (2.5, 0.995), (4.0, 0.985)])
 def test_elongated_gaussians_parity(stretch, opacity):
     """Needle-like Gaussians at every orientation: their alpha >= 1/255 box
     holds many tiles that the ellipse itself misses, the case where the
     compositing narrows each staged Gaussian's rows to the ellipse's extent
     within the tile's columns.  A faint variant puts the ellipse's edge near
-    the threshold everywhere."""
+    the threshold everywhere; two near-opaque ones put the 0.99 clamp at
+    every centre (opacity 0.995) or just out of reach (0.985), the two ways
+    the compositing's rows may take the clamp."""
     wl = S.small_view(seed=21, n=1200, width=176, height=144, log_scale_mean=-3.0)
     sc = wl.scene
     ls = sc.log_scales.copy()
