@@ -185,9 +185,12 @@ def make_workload(name):
     return wl, desc
 
 
-def measure_view(wl, steps, warmup, tile_h=16, persistent=False, graph=True):
+def measure_view(wl, steps, warmup, tile_h=16, persistent=False, graph=True, fused=True):
     """Times one workload's step (fwd + L1 + bwd incl. pose) in the plain form,
-    again with per-stage HIP events, and replayed from a HIP graph."""
+    again with per-stage HIP events, and replayed from a HIP graph.  fused: the
+    step is one gsr_rasterize_step_l1 call (compositing forward and backward
+    fused per tile); the two-pass form (forward, then backward_l1) is timed
+    as well for comparison."""
     import numpy as np
     import torch
     from paper_2607_14481_amd import gsr
@@ -211,11 +214,17 @@ def measure_view(wl, steps, warmup, tile_h=16, persistent=False, graph=True):
     target = target.clone()
     numel = target.numel()
 
-    def step(ws=None, out=None):
-        rgb, ws = rast.forward(params, w2c, bg, ws=ws, out=out)
+    def two_pass(ws=None, out=None, r=rast):
+        rgb, ws = r.forward(params, w2c, bg, ws=ws, out=out)
         # mean |img - target|: its image gradient is formed inside the backward
-        grads, g_w2c, g_tw = rast.backward_l1(ws, params, w2c, bg, rgb, target)
+        grads, g_w2c, g_tw = r.backward_l1(ws, params, w2c, bg, rgb, target)
         return rgb, ws, grads, g_tw
+
+    def one_call(ws=None, out=None, r=rast):
+        rgb, ws, grads, g_w2c, g_tw = r.step_l1(params, w2c, bg, target, ws=ws, out=out)
+        return rgb, ws, grads, g_tw
+
+    step = one_call if fused else two_pass
 
     # ---- plain form: one view per launch sequence, as a training loop runs it:
     # the warm-up steps (synchronous) size the pair capacity and the long-list
@@ -246,6 +255,19 @@ def measure_view(wl, steps, warmup, tile_h=16, persistent=False, graph=True):
     ms_plain = start.elapsed_time(end) / steps
     assert not rast.check_overflow(ws), "pair capacity overflowed during the timed steps"
     log(f"[bench] plain: {ms_plain:.3f} ms/step")
+    ms_two_pass = None
+    if fused:  # the same steps as two library calls, for comparison
+        for _ in range(2):
+            two_pass(ws, out)
+        torch.cuda.synchronize()
+        start.record()
+        for _ in range(steps):
+            two_pass(ws, out)
+        end.record()
+        torch.cuda.synchronize()
+        ms_two_pass = start.elapsed_time(end) / steps
+        assert not rast.check_overflow(ws)
+        log(f"[bench] two-pass form: {ms_two_pass:.3f} ms/step")
 
     # the same steps again with HIP events recorded by the library between its
     # stages, on the stream the kernels run on (per-stage and per-kernel times)
@@ -284,17 +306,16 @@ def measure_view(wl, steps, warmup, tile_h=16, persistent=False, graph=True):
             gout = torch.empty_like(target)
             s = torch.cuda.Stream()
             s.wait_stream(torch.cuda.current_stream())
+            gstep = one_call if fused else two_pass
             with torch.cuda.stream(s):
                 for _ in range(3):
-                    rgb, _ = grast.forward(params, w2c, bg, ws=gws, out=gout)
-                    gr, _, _ = grast.backward_l1(gws, params, w2c, bg, rgb, target)
+                    gstep(gws, gout, grast)
             torch.cuda.current_stream().wait_stream(s)
             torch.cuda.synchronize()
             assert not grast.check_overflow(gws)
             cg = torch.cuda.CUDAGraph()
             with torch.cuda.graph(cg):
-                rgb, _ = grast.forward(params, w2c, bg, ws=gws, out=gout)
-                gr, _, _ = grast.backward_l1(gws, params, w2c, bg, rgb, target)
+                gstep(gws, gout, grast)
             for _ in range(warmup):
                 cg.replay()
             torch.cuda.synchronize()
@@ -311,7 +332,7 @@ def measure_view(wl, steps, warmup, tile_h=16, persistent=False, graph=True):
             log(f"[bench] graph form failed: {graph_err}")
 
     return {"ms_plain": ms_plain, "ms_instrumented": ms_instrumented, "stage_ms": stage_ms, "stats": stats,
-            "graph_ms": graph_ms, "graph_err": graph_err}
+            "graph_ms": graph_ms, "graph_err": graph_err, "ms_two_pass": ms_two_pass, "fused": fused}
 
 
 def copy_rates(sizes_mb=(8, 16, 32, 64, 128, 256, 512), reps=40):
@@ -381,10 +402,10 @@ def run_keyframe(wl, iterations=30, repeats=3):
         pm, pv = torch.zeros((1, 6), device=dev), torch.zeros((1, 6), device=dev)
         losses = []
         for it in range(1, iterations + 1):
-            rast.forward(params, w2c, ws=ws, out=rgb)
+            # forward, L1 loss and backward in one library call
+            _, _, grads, _, twist = rast.step_l1(params, w2c, (0.0, 0.0, 0.0), target, ws=ws, out=rgb)
             if it == 1 or it == iterations:
                 losses.append((rgb - target).abs().mean())
-            grads, _, twist = rast.backward_l1(ws, params, w2c, (0.0, 0.0, 0.0), rgb, target)
             gsr.adam_step(params, grads, m, v, sc.sh_degree, it, acfg, ws=ws, cams=cams, cfg=rast.cfg)
             gsr.pose_step(w2c, twist, pm, pv, it, 1e-4)
         return losses, params, grads, m, v
@@ -790,6 +811,8 @@ def main():
     ap.add_argument("--workload", default="headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--two-pass", action="store_true",
+                    help="time the step as forward then backward_l1 instead of one fused call")
     ap.add_argument("--tile-h", type=int, default=16)
     ap.add_argument("--persistent", action="store_true", help="compositing as persistent work-queue launches")
     ap.add_argument("--no-ring", action="store_true", help="skip the batched 8-view measurement")
@@ -847,7 +870,8 @@ def main():
     sc, cams = wl.scene, wl.cameras
     log(f"[bench] workload {args.workload}: n={sc.n} view {cams[0].width}x{cams[0].height} "
         f"(inputs built in {time.time() - t0:.1f}s)")
-    m = measure_view(wl, args.steps, args.warmup, args.tile_h, args.persistent, not args.no_graph)
+    m = measure_view(wl, args.steps, args.warmup, args.tile_h, args.persistent, not args.no_graph,
+                     fused=not args.two_pass)
     ms_plain, ms_instrumented, stage_ms, stats = m["ms_plain"], m["ms_instrumented"], m["stage_ms"], m["stats"]
     graph_ms, graph_err = m["graph_ms"], m["graph_err"]
 
@@ -901,20 +925,24 @@ def main():
     # ---- the local bundle adjustment (20 keyframes x 10,000 landmarks, 10 iterations)
     local_ba = None if args.no_ba else run_local_ba(cpu_baseline=not args.no_cpu_baseline)
 
-    # ---- roofline of the dominant kernel (compositing, ALU-bound)
-    comp = {"composite_fwd": stage_ms["composite_fwd"], "composite_bwd": stage_ms["composite_bwd"]}
-    dom = max(comp, key=comp.get)
-    if dom == "composite_bwd":
-        flops = FLOPS_BWD_EVAL * stats["replays"] + FLOPS_BWD_CONTRIB * stats["contributors"]
+    # ---- roofline of the dominant kernel (compositing, ALU-bound): the fused
+    # compositing of the one-call step (timed as the forward compositing stage,
+    # doing the forward's and the backward's work), else the larger of the two
+    fwd_flops = FLOPS_FWD_EVAL * stats["evaluations"] + FLOPS_FWD_CONTRIB * stats["contributors"]
+    bwd_flops = FLOPS_BWD_EVAL * stats["replays"] + FLOPS_BWD_CONTRIB * stats["contributors"]
+    if m["fused"]:
+        dom, flops, dom_ms = "composite_step", fwd_flops + bwd_flops, stage_ms["composite_fwd"]
     else:
-        flops = FLOPS_FWD_EVAL * stats["evaluations"] + FLOPS_FWD_CONTRIB * stats["contributors"]
-    achieved = flops / (comp[dom] * 1e-3) / 1e12
+        comp = {"composite_fwd": stage_ms["composite_fwd"], "composite_bwd": stage_ms["composite_bwd"]}
+        dom = max(comp, key=comp.get)
+        flops, dom_ms = (bwd_flops if dom == "composite_bwd" else fwd_flops), comp[dom]
+    achieved = flops / (dom_ms * 1e-3) / 1e12
     traffic = measured_traffic(args.workload, dom)
     roofline = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                 "traffic": traffic["bytes"] if traffic else None,
                 "traffic_note": traffic["note"] if traffic else "no byte-counter profile of the current kernel sources",
-                "algorithmic_flops": int(flops), "ms": round(comp[dom], 4)}
+                "algorithmic_flops": int(flops), "ms": round(dom_ms, 4)}
 
     # ---- CPU baseline: the FP64 oracle as it stands, one full iteration
     cpu = None
@@ -976,10 +1004,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "n_gaussians": sc.n,
                    "resolution": f"{cams[0].width}x{cams[0].height}", "sh_degree": sc.sh_degree,
-                   "form": "plain: one view per launch sequence, no host synchronisation in the timed steps (pair capacity and long-list passes sized by synchronous warm-up steps, overflow checked after)",
+                   "form": ("plain: one view per launch sequence, " + ("one gsr_rasterize_step_l1 call per step (compositing forward and backward fused per tile)" if m["fused"] else "forward then backward_l1") + ", no host synchronisation in the timed steps (pair capacity and long-list passes sized by synchronous warm-up steps, overflow checked after)"),
                    "tile": f"16x{args.tile_h}", "persistent": bool(args.persistent)},
         "graph_form": {"iters_per_s": round(1000.0 / graph_ms, 3) if graph_ms else None,
                        "ms_per_step": round(graph_ms, 4) if graph_ms else None, "error": graph_err},
+        "two_pass_form": ({"iters_per_s": round(1000.0 / m["ms_two_pass"], 3),
+                           "ms_per_step": round(m["ms_two_pass"], 4),
+                           "note": "the same step as gsr_rasterize_forward then gsr_rasterize_backward_l1"}
+                          if m["ms_two_pass"] else None),
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "ms_per_step_with_stage_events": round(ms_instrumented, 4),
         "work": stats,

@@ -232,6 +232,25 @@ int gsr_rasterize_backward_l1(void *ws, size_t ws_bytes, const gsr_gaussians *g,
                               uint32_t flags, void *stream);
 
 /*
+ * Forward and the backward of the mean absolute error (as
+ * gsr_rasterize_backward_l1) in one call: the compositing forward and
+ * backward run fused per tile (Sec. 5.2's rendering loss, whose gradient at a
+ * pixel needs only that pixel's own colour), so the backward's replay of a
+ * tile follows its forward in the same workgroup.  Outputs: out_rgb and out_T
+ * as gsr_rasterize_forward, grads, dL_dworld_to_cam and dL_dtwist as
+ * gsr_rasterize_backward; bitwise the same values as the two calls, and the
+ * same workspace state afterwards (a later gsr_rasterize_backward on ws is
+ * valid).  target_rgb: device, layout of out_rgb.  Flags as for the forward;
+ * with GSR_FLAG_STATS the two passes run separately (the work counters come
+ * from the forward's kernel).  Errors: those of both passes.
+ */
+int gsr_rasterize_step_l1(void *ws, size_t ws_bytes, const gsr_gaussians *g, int32_t n_views,
+                          const gsr_camera *cams, const float *world_to_cam, const float *bg,
+                          const gsr_launch_config *cfg, const float *target_rgb, float *out_rgb, float *out_T,
+                          const gsr_gaussian_grads *grads, float *dL_dworld_to_cam, float *dL_dtwist, uint32_t flags,
+                          void *stream);
+
+/*
  * Pair count of the last forward on ws.  Reads the workspace header with a
  * blocking device->host copy on stream (so it waits for the forward).
  * needed: M required; capacity: M the workspace holds; overflowed: 1 if the

@@ -2,8 +2,10 @@
 
 Picks, by measurement on the workload itself, how many views go into one
 launch sequence, the tile height (16 x {8, 16, 32} pixels; results are
-independent of it because tile membership is the exact alpha >= 1/255 box)
-and whether compositing runs as persistent work-queue launches.  Results are
+independent of it because tile membership is the exact alpha >= 1/255 box),
+whether compositing runs as persistent work-queue launches and, when all
+views go into one call, whether that call is the fused one-call step
+(gsr_rasterize_step_l1; bitwise the same results as forward + backward_l1).  Results are
 cached in a JSON file keyed by the workload's signature and the device.
 """
 from __future__ import annotations
@@ -28,10 +30,11 @@ def signature(n: int, sh_degree: int, cams: Sequence) -> str:
 class MultiViewStep:
     """One optimisation step over all views: forward, L1 loss against the
     targets, backward; gradients summed over views.  Views are split into
-    launch groups of `views_per_launch`."""
+    launch groups of `views_per_launch`; with one group and `fused`, the step
+    is one gsr_rasterize_step_l1 call."""
 
     def __init__(self, cams, sh_degree, params, w2c, targets, views_per_launch=8, tile_h=16, persistent=False,
-                 sync=True, capacity_hint: Optional[List[int]] = None):
+                 sync=True, capacity_hint: Optional[List[int]] = None, fused: bool = False):
         self.params = params
         self.groups = []
         V = len(cams)
@@ -44,6 +47,7 @@ class MultiViewStep:
             tgt = torch.cat([targets[i] for i in idx])
             self.groups.append((rast, w2c[idx].contiguous(), tgt))
         self.numel = sum(t.numel() for t in targets)
+        self.fused = bool(fused) and len(self.groups) == 1
         self.ws = [None] * len(self.groups)
         self.out = [None] * len(self.groups)
 
@@ -51,6 +55,12 @@ class MultiViewStep:
         total = None
         pose = []
         for k, (rast, w2c, tgt) in enumerate(self.groups):
+            if self.fused:  # the call's own mean absolute error is the step's loss
+                rgb, ws, grads, g_w2c, _ = rast.step_l1(self.params, w2c, (0.0, 0.0, 0.0), tgt,
+                                                        ws=self.ws[k] if keep_workspaces else None, out=self.out[k])
+                if keep_workspaces:
+                    self.ws[k], self.out[k] = ws, rgb
+                return grads, g_w2c
             rgb, ws = rast.forward(self.params, w2c, ws=self.ws[k] if keep_workspaces else None, out=self.out[k])
             if keep_workspaces:
                 self.ws[k], self.out[k] = ws, rgb
@@ -79,7 +89,8 @@ def _time(step, steps, warmup):
 
 def autotune(cams, sh_degree, params, w2c, targets, candidates: Optional[List[Dict]] = None, steps: int = 5,
              warmup: int = 2, cache_path: Optional[str] = DEFAULT_CACHE, log=None) -> Dict:
-    """Returns {"best": config, "ms": {config_key: ms}}; config = dict(views_per_launch, tile_h, persistent)."""
+    """Returns {"best": config, "ms": {config_key: ms}}; config = dict(views_per_launch, tile_h, persistent,
+    fused)."""
     V = len(cams)
     n = int(params[0].shape[0])
     sig = signature(n, sh_degree, cams)
@@ -94,14 +105,16 @@ def autotune(cams, sh_degree, params, w2c, targets, candidates: Optional[List[Di
         return cache[sig]
     if candidates is None:
         vpl = sorted({v for v in (1, 2, 4, 8, V) if v <= V})
-        candidates = [dict(views_per_launch=v, tile_h=th, persistent=p)
-                      for v in vpl for th in (8, 16, 32) for p in (False, True)]
+        candidates = [dict(views_per_launch=v, tile_h=th, persistent=p, fused=f)
+                      for v in vpl for th in (8, 16, 32) for p in (False, True)
+                      for f in ((False, True) if v >= V else (False,))]
     results = {}
     best, best_ms = None, float("inf")
     for cand in candidates:
         step = MultiViewStep(cams, sh_degree, params, w2c, targets, **cand)
         ms = _time(step, steps, warmup)
-        key = f"v{cand['views_per_launch']}_th{cand['tile_h']}_p{int(cand['persistent'])}"
+        key = f"v{cand['views_per_launch']}_th{cand['tile_h']}_p{int(cand['persistent'])}" + \
+            ("_fused" if cand.get("fused") else "")
         results[key] = round(ms, 4)
         if log:
             log(f"[autotune] {key}: {ms:.3f} ms")

@@ -252,6 +252,50 @@ int pair_result_buffer(uint32_t total_tiles) { return ((tile_bits(total_tiles) +
 
 namespace {
 
+// Checks of the backward's arguments (those of the forward are checked by it).
+int check_backward_args(const gsr_gaussians *g, const void *ws, const float *world_to_cam, const float *out_rgb,
+                        const float *upstream, const gsr_gaussian_grads *grads) {
+    if (!ws || !world_to_cam || !out_rgb || !upstream || !grads)
+        return fail(GSR_ERR_INVALID_ARGUMENT,
+                    "ws, world_to_cam, out_rgb, the upstream gradient (or target) and grads must not be NULL");
+    if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacities || !grads->sh))
+        return fail(GSR_ERR_INVALID_ARGUMENT, "a gradient output pointer is NULL");
+    if (g->n > 0 && ((reinterpret_cast<uintptr_t>(grads->quats) | reinterpret_cast<uintptr_t>(grads->sh)) & 15u))
+        return fail(GSR_ERR_INVALID_ARGUMENT, "grads->quats and grads->sh must be 16-byte aligned");
+    return GSR_OK;
+}
+
+// The backward compositing's rows of unseen Gaussians to zero (see ZeroRows).
+gsr::ZeroRows zero_rows(const gsr_gaussians *g, const gsr::ViewTable &vt, const gsr_gaussian_grads *grads,
+                        const Ptrs &p) {
+    gsr::ZeroRows zr{};
+    zr.g = *grads;
+    zr.count = p.count;
+    zr.n = (uint64_t)g->n;
+    zr.n_views = vt.n_views;
+    zr.sh_k = (g->sh_degree + 1) * (g->sh_degree + 1);
+    zr.per_tile = vt.total_tiles ? (zr.n + vt.total_tiles - 1) / vt.total_tiles : 0;
+    return zr;
+}
+
+float l1_scale_of(const gsr::ViewTable &vt) { return 1.0f / (float)(3.0 * (double)vt.total_pixels); }
+
+// A8, A9 and the pose gradient, after the backward compositing.
+int backward_tail(const gsr_gaussians *g, const gsr::ViewTable &vt, const float *world_to_cam,
+                  const gsr::WsLayout &L, uint64_t cap, const Ptrs &p, const gsr_gaussian_grads *grads,
+                  float *dL_dworld_to_cam, float *dL_dtwist, const StageMark &mark, hipStream_t st) {
+    using namespace gsr;
+    mark.begin(GSR_STAGE_PROJECT_BWD);
+    launch_pair_reduce(p.poff, p.chunk_item, cap, p.vis, p.pflag, p.partial, p.screen, p.carry, p.hdr, st);
+    launch_project_bwd(*g, vt, world_to_cam, (uint64_t)g->n, p.rec, p.count, p.vis, p.hdr, p.screen, p.carry, *grads,
+                       p.pose_part, L.pose_blocks, p.view_seg, vt.total_tiles == 0, st);
+    if (g->n == 0)  // no Gaussian wrote a partial: the pose gradient is zero
+        launch_fill_u32(reinterpret_cast<uint32_t *>(p.pose_part), 0u, 12ull * vt.n_views * L.pose_blocks, st);
+    launch_pose_finalize(vt, world_to_cam, p.pose_part, L.pose_blocks, dL_dworld_to_cam, dL_dtwist, st);
+    mark.end(GSR_STAGE_PROJECT_BWD);
+    return check_hip(hipGetLastError(), "backward launch");
+}
+
 int backward_impl(void *ws, size_t ws_bytes, const gsr_gaussians *g, int32_t n_views, const gsr_camera *cams,
                          const float *world_to_cam, const gsr_launch_config *cfg, const float *out_rgb,
                          const float *dL_drgb, const float *target_rgb, const gsr_gaussian_grads *grads,
@@ -261,13 +305,7 @@ int backward_impl(void *ws, size_t ws_bytes, const gsr_gaussians *g, int32_t n_v
     if (rc) return rc;
     ViewTable vt;
     if ((rc = build_views(n_views, cams, cfg, vt))) return rc;
-    if (!ws || !world_to_cam || !out_rgb || !(dL_drgb || target_rgb) || !grads)
-        return fail(GSR_ERR_INVALID_ARGUMENT,
-                    "ws, world_to_cam, out_rgb, the upstream gradient (or target) and grads must not be NULL");
-    if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacities || !grads->sh))
-        return fail(GSR_ERR_INVALID_ARGUMENT, "a gradient output pointer is NULL");
-    if (g->n > 0 && ((reinterpret_cast<uintptr_t>(grads->quats) | reinterpret_cast<uintptr_t>(grads->sh)) & 15u))
-        return fail(GSR_ERR_INVALID_ARGUMENT, "grads->quats and grads->sh must be 16-byte aligned");
+    if ((rc = check_backward_args(g, ws, world_to_cam, out_rgb, dL_drgb ? dL_drgb : target_rgb, grads))) return rc;
     WsLayout L;
     uint64_t cap = 0;
     if ((rc = layout_from_bytes((uint64_t)g->n, vt, ws_bytes, L, cap))) return rc;
@@ -278,27 +316,95 @@ int backward_impl(void *ws, size_t ws_bytes, const gsr_gaussians *g, int32_t n_v
     const StageMark mark{cfg ? static_cast<hipEvent_t *>(cfg->stage_events) : nullptr, st};
     mark.begin(GSR_STAGE_COMPOSITE_BWD);
     if (pers) launch_reset_queue(p.hdr, 1, st);
-    ZeroRows zr{};
-    zr.g = *grads;
-    zr.count = p.count;
-    zr.n = (uint64_t)g->n;
-    zr.n_views = vt.n_views;
-    zr.sh_k = (g->sh_degree + 1) * (g->sh_degree + 1);
-    zr.per_tile = vt.total_tiles ? (zr.n + vt.total_tiles - 1) / vt.total_tiles : 0;
+    const ZeroRows zr = zero_rows(g, vt, grads, p);
     Upstream up{dL_drgb, target_rgb, 0.f};
-    if (target_rgb) up.l1_scale = 1.0f / (float)(3.0 * (double)vt.total_pixels);
+    if (target_rgb) up.l1_scale = l1_scale_of(vt);
     launch_composite_bwd(vt, p.ranges, p.pval[pc], p.rec, p.ulo, out_rgb, up, p.pix_n, p.tile_cut, p.tile_order, p.partial,
                          reinterpret_cast<uint8_t *>(p.pflag), zr, p.hdr, pers, persistent_ctas(cfg), st);
     mark.end(GSR_STAGE_COMPOSITE_BWD);
-    mark.begin(GSR_STAGE_PROJECT_BWD);
-    launch_pair_reduce(p.poff, p.chunk_item, cap, p.vis, p.pflag, p.partial, p.screen, p.carry, p.hdr, st);
-    launch_project_bwd(*g, vt, world_to_cam, (uint64_t)g->n, p.rec, p.count, p.vis, p.hdr, p.screen, p.carry, *grads,
-                       p.pose_part, L.pose_blocks, p.view_seg, vt.total_tiles == 0, st);
-    if (g->n == 0)  // no Gaussian wrote a partial: the pose gradient is zero
-        launch_fill_u32(reinterpret_cast<uint32_t *>(p.pose_part), 0u, 12ull * vt.n_views * L.pose_blocks, st);
-    launch_pose_finalize(vt, world_to_cam, p.pose_part, L.pose_blocks, dL_dworld_to_cam, dL_dtwist, st);
-    mark.end(GSR_STAGE_PROJECT_BWD);
-    return check_hip(hipGetLastError(), "backward launch");
+    return backward_tail(g, vt, world_to_cam, L, cap, p, grads, dL_dworld_to_cam, dL_dtwist, mark, st);
+}
+
+// Checks of the forward's arguments; on success vt, L, cap and p describe the
+// workspace.
+int forward_setup(void *ws, size_t ws_bytes, const gsr_gaussians *g, int32_t n_views, const gsr_camera *cams,
+                  const float *world_to_cam, const float *bg, const gsr_launch_config *cfg, const float *out_rgb,
+                  gsr::ViewTable &vt, gsr::WsLayout &L, uint64_t &cap, Ptrs &p) {
+    using namespace gsr;
+    int rc = check_gaussians(g);
+    if (rc) return rc;
+    if ((rc = build_views(n_views, cams, cfg, vt))) return rc;
+    if (!ws || !world_to_cam || !bg || !out_rgb)
+        return fail(GSR_ERR_INVALID_ARGUMENT, "ws, world_to_cam, bg and out_rgb must not be NULL");
+    if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(GSR_ERR_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
+    if ((uint64_t)g->n * (uint64_t)n_views >= 0x7fffffffull)
+        return fail(GSR_ERR_INVALID_ARGUMENT, "n * n_views must stay below 2^31");
+    if ((rc = layout_from_bytes((uint64_t)g->n, vt, ws_bytes, L, cap))) return rc;
+    p = carve(ws, L);
+    return GSR_OK;
+}
+
+// A1-A5 of a forward (projection, compaction, emission, tile sort, ranges,
+// per-tile depth sort); pc: the pair buffer holding the sorted lists.  With
+// length_order, the depth sort also files every tile by its list length in
+// tile_order (the fused compositing's schedule).
+int forward_binning(const gsr_gaussians *g, const gsr::ViewTable &vt, const float *world_to_cam,
+                    const gsr_launch_config *cfg, const gsr::WsLayout &L, uint64_t cap, const Ptrs &p, uint32_t flags,
+                    bool length_order, const StageMark &mark, hipStream_t st, int &pc) {
+    using namespace gsr;
+    int rc = GSR_OK;
+    const uint64_t n = (uint64_t)g->n;
+    mark.begin(GSR_STAGE_PROJECT);
+    launch_project_fwd(*g, vt, world_to_cam, n, p.rec, p.ulo, p.zkey, p.count, p.hdr, (uint32_t)cap,
+                       cfg ? cfg->active_count : nullptr, st);
+    mark.end(GSR_STAGE_PROJECT);
+    mark.begin(GSR_STAGE_COMPACT);
+    launch_visible_offsets(vt, n, p.count, p.rec, p.zkey, L.items, p.vis, p.poff, p.item_box, p.chunk_item, L.chunks,
+                           p.scan_tmp, p.hdr, st);
+    mark.end(GSR_STAGE_COMPACT);
+    mark.begin(GSR_STAGE_EMIT);
+    const uint64_t pair_grid = cap;  // every kernel reads the pair count from the header
+    launch_emit_pairs(p.poff, p.chunk_item, p.item_box, pair_grid, p.pkey[0], p.pval[0], p.pflag, p.hdr, st);
+    mark.end(GSR_STAGE_EMIT);
+    mark.begin(GSR_STAGE_TILE_SORT);
+    pc = 0;
+    {
+        uint32_t *k2[2] = {p.pkey[0], p.pkey[1]}, *v2[2] = {p.pval[0], p.pval[1]};
+        // unstable: the per-tile depth sort fixes the order within a tile
+        radix_sort_u32(k2, v2, SortCount{nullptr, p.hdr}, pair_grid, 0, tile_bits(vt.total_tiles), p.hist,
+                       L.hist_blocks, p.digit_total, pc, false, st);
+    }
+    launch_tile_ranges(p.pkey[pc], pair_grid, p.ranges, vt.total_tiles, p.long_tiles, p.tile_order, p.hdr, st);
+    // lists longer than one workgroup sorts: runs of kLongWindow, then merge passes
+    int passes = cfg ? std::max(0, std::min(cfg->long_list_passes, kMaxLongPasses)) : 0;
+    uint64_t long_pairs = cap, n_long = kMaxLongTiles;
+    if (flags & GSR_FLAG_SYNC) {
+        WsHeader h;
+        if ((rc = read_header_now(p.hdr, h, st))) return rc;
+        if (h.overflow)
+            return fail(GSR_ERR_CAPACITY, "needs %u pairs, workspace holds %llu", h.n_pairs, (unsigned long long)cap);
+        passes = 0;
+        if (h.n_long > 0 && h.n_long <= kMaxLongTiles) {
+            const uint32_t runs = (h.max_long + kLongWindow - 1) / kLongWindow;
+            while ((1u << passes) < runs && passes < kMaxLongPasses) ++passes;
+        }
+        long_pairs = h.long_pairs;
+        n_long = h.n_long;
+    }
+    const uint32_t chunk_wgs = passes > 0 ? (uint32_t)((long_pairs + kLongWindow - 1) / kLongWindow + n_long) : 0u;
+    const uint32_t merge_wgs = passes > 0 ? (uint32_t)((long_pairs + kMergeWindow - 1) / kMergeWindow + n_long) : 0u;
+    uint32_t *xh = p.pkey[pc ^ 1], *xl = p.pval[pc ^ 1], *yh = p.pkey[pc], *yl = p.pval[pc];
+    if (passes > 0) launch_long_windows(p.ranges, p.long_tiles, passes, p.hdr, st);
+    launch_tile_depth_sort(p.ranges, vt.total_tiles, p.pval[pc], p.zkey, xh, xl, yh, yl, p.long_tiles, passes,
+                           chunk_wgs, length_order ? p.tile_order : nullptr, p.tile_cut, p.hdr, st);
+    for (int q = 0; q < passes; ++q) {
+        // the runs start in x when the pass count is odd, so that the last pass reads x
+        const bool from_x = ((passes - q) & 1) != 0;
+        launch_long_merge(p.ranges, p.long_tiles, p.hdr, q, passes, from_x ? xh : yh, from_x ? xl : yl,
+                          from_x ? yh : xh, from_x ? yl : xl, p.pval[pc], merge_wgs, st);
+    }
+    mark.end(GSR_STAGE_TILE_SORT);
+    return GSR_OK;
 }
 
 }  // namespace
@@ -337,80 +443,21 @@ int gsr_rasterize_forward(void *ws, size_t ws_bytes, const gsr_gaussians *g, int
                           const gsr_camera *cams, const float *world_to_cam, const float *bg,
                           const gsr_launch_config *cfg, float *out_rgb, float *out_T, uint32_t flags, void *stream) {
     using namespace gsr;
-    int rc = check_gaussians(g);
-    if (rc) return rc;
     ViewTable vt;
-    if ((rc = build_views(n_views, cams, cfg, vt))) return rc;
-    if (!ws || !world_to_cam || !bg || !out_rgb)
-        return fail(GSR_ERR_INVALID_ARGUMENT, "ws, world_to_cam, bg and out_rgb must not be NULL");
-    if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(GSR_ERR_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
-    if ((uint64_t)g->n * (uint64_t)n_views >= 0x7fffffffull)
-        return fail(GSR_ERR_INVALID_ARGUMENT, "n * n_views must stay below 2^31");
     WsLayout L;
     uint64_t cap = 0;
-    if ((rc = layout_from_bytes((uint64_t)g->n, vt, ws_bytes, L, cap))) return rc;
+    Ptrs p;
+    int rc = forward_setup(ws, ws_bytes, g, n_views, cams, world_to_cam, bg, cfg, out_rgb, vt, L, cap, p);
+    if (rc) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const Ptrs p = carve(ws, L);
-    const uint64_t n = (uint64_t)g->n;
-    const float3 bgc = make_float3(bg[0], bg[1], bg[2]);
-
     const StageMark mark{cfg ? static_cast<hipEvent_t *>(cfg->stage_events) : nullptr, st};
-
-    mark.begin(GSR_STAGE_PROJECT);
-    launch_project_fwd(*g, vt, world_to_cam, n, p.rec, p.ulo, p.zkey, p.count, p.hdr, (uint32_t)cap,
-                       cfg ? cfg->active_count : nullptr, st);
-    mark.end(GSR_STAGE_PROJECT);
-    mark.begin(GSR_STAGE_COMPACT);
-    launch_visible_offsets(vt, n, p.count, p.rec, p.zkey, L.items, p.vis, p.poff, p.item_box, p.chunk_item, L.chunks,
-                           p.scan_tmp, p.hdr, st);
-    mark.end(GSR_STAGE_COMPACT);
-    mark.begin(GSR_STAGE_EMIT);
-    const uint64_t pair_grid = cap;  // every kernel reads the pair count from the header
-    launch_emit_pairs(p.poff, p.chunk_item, p.item_box, pair_grid, p.pkey[0], p.pval[0], p.pflag, p.hdr, st);
-    mark.end(GSR_STAGE_EMIT);
-    mark.begin(GSR_STAGE_TILE_SORT);
     int pc = 0;
-    {
-        uint32_t *k2[2] = {p.pkey[0], p.pkey[1]}, *v2[2] = {p.pval[0], p.pval[1]};
-        // unstable: the per-tile depth sort fixes the order within a tile
-        radix_sort_u32(k2, v2, SortCount{nullptr, p.hdr}, pair_grid, 0, tile_bits(vt.total_tiles), p.hist,
-                       L.hist_blocks, p.digit_total, pc, false, st);
-    }
-    launch_tile_ranges(p.pkey[pc], pair_grid, p.ranges, vt.total_tiles, p.long_tiles, p.tile_order, p.hdr, st);
-    // lists longer than one workgroup sorts: runs of kLongWindow, then merge passes
-    int passes = cfg ? std::max(0, std::min(cfg->long_list_passes, kMaxLongPasses)) : 0;
-    uint64_t long_pairs = cap, n_long = kMaxLongTiles;
-    if (flags & GSR_FLAG_SYNC) {
-        WsHeader h;
-        if ((rc = read_header_now(p.hdr, h, st))) return rc;
-        if (h.overflow)
-            return fail(GSR_ERR_CAPACITY, "needs %u pairs, workspace holds %llu", h.n_pairs, (unsigned long long)cap);
-        passes = 0;
-        if (h.n_long > 0 && h.n_long <= kMaxLongTiles) {
-            const uint32_t runs = (h.max_long + kLongWindow - 1) / kLongWindow;
-            while ((1u << passes) < runs && passes < kMaxLongPasses) ++passes;
-        }
-        long_pairs = h.long_pairs;
-        n_long = h.n_long;
-    }
-    const uint32_t chunk_wgs = passes > 0 ? (uint32_t)((long_pairs + kLongWindow - 1) / kLongWindow + n_long) : 0u;
-    const uint32_t merge_wgs = passes > 0 ? (uint32_t)((long_pairs + kMergeWindow - 1) / kMergeWindow + n_long) : 0u;
-    uint32_t *xh = p.pkey[pc ^ 1], *xl = p.pval[pc ^ 1], *yh = p.pkey[pc], *yl = p.pval[pc];
-    if (passes > 0) launch_long_windows(p.ranges, p.long_tiles, passes, p.hdr, st);
-    launch_tile_depth_sort(p.ranges, vt.total_tiles, p.pval[pc], p.zkey, xh, xl, yh, yl, p.long_tiles, passes,
-                           chunk_wgs, p.hdr, st);
-    for (int q = 0; q < passes; ++q) {
-        // the runs start in x when the pass count is odd, so that the last pass reads x
-        const bool from_x = ((passes - q) & 1) != 0;
-        launch_long_merge(p.ranges, p.long_tiles, p.hdr, q, passes, from_x ? xh : yh, from_x ? xl : yl,
-                          from_x ? yh : xh, from_x ? yl : xl, p.pval[pc], merge_wgs, st);
-    }
-    mark.end(GSR_STAGE_TILE_SORT);
+    if ((rc = forward_binning(g, vt, world_to_cam, cfg, L, cap, p, flags, false, mark, st, pc))) return rc;
     const bool pers = (flags & GSR_FLAG_PERSISTENT) != 0;
     mark.begin(GSR_STAGE_COMPOSITE_FWD);
-    launch_composite_fwd(vt, p.ranges, p.pval[pc], p.rec, p.ulo, bgc, out_rgb, out_T, p.pix_T, p.pix_n,
-                         p.tile_cut, p.tile_order, p.hdr, pers, persistent_ctas(cfg), (flags & GSR_FLAG_STATS) != 0,
-                         st);
+    launch_composite_fwd(vt, p.ranges, p.pval[pc], p.rec, p.ulo, make_float3(bg[0], bg[1], bg[2]), out_rgb, out_T,
+                         p.pix_T, p.pix_n, p.tile_cut, p.tile_order, p.hdr, pers, persistent_ctas(cfg),
+                         (flags & GSR_FLAG_STATS) != 0, st);
     mark.end(GSR_STAGE_COMPOSITE_FWD);
     return check_hip(hipGetLastError(), "forward launch");
 }
@@ -435,6 +482,46 @@ int gsr_rasterize_backward_l1(void *ws, size_t ws_bytes, const gsr_gaussians *g,
     if (!target_rgb) return fail(GSR_ERR_INVALID_ARGUMENT, "target_rgb must not be NULL");
     return backward_impl(ws, ws_bytes, g, n_views, cams, world_to_cam, cfg, out_rgb, nullptr, target_rgb, grads,
                          dL_dworld_to_cam, dL_dtwist, flags, stream);
+}
+
+int gsr_rasterize_step_l1(void *ws, size_t ws_bytes, const gsr_gaussians *g, int32_t n_views,
+                          const gsr_camera *cams, const float *world_to_cam, const float *bg,
+                          const gsr_launch_config *cfg, const float *target_rgb, float *out_rgb, float *out_T,
+                          const gsr_gaussian_grads *grads, float *dL_dworld_to_cam, float *dL_dtwist, uint32_t flags,
+                          void *stream) {
+    using namespace gsr;
+    if (!target_rgb) return fail(GSR_ERR_INVALID_ARGUMENT, "target_rgb must not be NULL");
+    if (flags & GSR_FLAG_STATS) {
+        // the work counters come from the forward kernel: run the two passes
+        int rc = gsr_rasterize_forward(ws, ws_bytes, g, n_views, cams, world_to_cam, bg, cfg, out_rgb, out_T, flags,
+                                       stream);
+        if (rc) return rc;
+        return gsr_rasterize_backward_l1(ws, ws_bytes, g, n_views, cams, world_to_cam, bg, cfg, out_rgb, target_rgb,
+                                         grads, dL_dworld_to_cam, dL_dtwist, flags, stream);
+    }
+    ViewTable vt;
+    WsLayout L;
+    uint64_t cap = 0;
+    Ptrs p;
+    int rc = forward_setup(ws, ws_bytes, g, n_views, cams, world_to_cam, bg, cfg, out_rgb, vt, L, cap, p);
+    if (rc) return rc;
+    if ((rc = check_backward_args(g, ws, world_to_cam, out_rgb, target_rgb, grads))) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const StageMark mark{cfg ? static_cast<hipEvent_t *>(cfg->stage_events) : nullptr, st};
+    int pc = 0;
+    if ((rc = forward_binning(g, vt, world_to_cam, cfg, L, cap, p, flags, true, mark, st, pc))) return rc;
+    const bool pers = (flags & GSR_FLAG_PERSISTENT) != 0;
+    // the fused compositing is timed as the forward compositing stage; the
+    // backward compositing stage is empty
+    mark.begin(GSR_STAGE_COMPOSITE_FWD);
+    launch_composite_step(vt, p.ranges, p.pval[pc], p.rec, p.ulo, make_float3(bg[0], bg[1], bg[2]), target_rgb,
+                          l1_scale_of(vt), out_rgb, out_T, p.pix_T, p.pix_n, p.tile_cut, p.tile_order, p.partial,
+                          reinterpret_cast<uint8_t *>(p.pflag), zero_rows(g, vt, grads, p), p.hdr, pers,
+                          persistent_ctas(cfg), st);
+    mark.end(GSR_STAGE_COMPOSITE_FWD);
+    mark.begin(GSR_STAGE_COMPOSITE_BWD);
+    mark.end(GSR_STAGE_COMPOSITE_BWD);
+    return backward_tail(g, vt, world_to_cam, L, cap, p, grads, dL_dworld_to_cam, dL_dtwist, mark, st);
 }
 
 int gsr_query_pairs(const void *ws, size_t ws_bytes, int64_t *needed, int64_t *capacity, int32_t *overflowed,

@@ -46,6 +46,17 @@
 // (nmax), and the backward's workgroups take the tiles heaviest first: in
 // tile order the dense centre tiles, dispatched late, left a tail.  Which
 // workgroup takes which tile changes no result.
+//
+// Fused step.  For the mean absolute error the upstream gradient of a pixel
+// is a function of that pixel's colour alone, so k_composite_step runs a
+// tile's forward and, in the same workgroup, its backward: the two tile
+// passes are the functions the separate kernels call, so the results are
+// theirs bit for bit, but a SIMD then holds waves in both phases (the
+// backward's arithmetic fills the forward's latency) and the forward's
+// per-pixel state never leaves registers.  Its schedule cannot use this
+// step's replay counts, which exist only after the forward; it takes the
+// tile's list length, capped by the replay count the workspace holds from the
+// previous step.
 #include "gsr_internal.h"
 
 namespace gsr {
@@ -147,12 +158,6 @@ __device__ __forceinline__ uint32_t slab_mask(float packed) {
 // margin dwarfs the exponential's rounding).
 constexpr float kLog2AlphaSkip = -7.9943534f - 0.01f;  // log2(1/255) - 0.01
 
-// Bucket of a tile's replay count (its backward cost): 16 per octave,
-// floor(16 log2(n + 1)), the top bucket taking everything above 255.
-__device__ __forceinline__ uint32_t cost_bucket(uint32_t n) {
-    return min(kCostBuckets - 1, (uint32_t)(16.f * __log2f((float)n + 1.f)));
-}
-
 // The r-th tile of the backward's schedule: tiles in descending cost buckets
 // (any order within a bucket: tiles are independent, so results do not
 // depend on it), or tile r when the buckets do not hold every tile (a forward
@@ -204,6 +209,77 @@ __device__ __forceinline__ float alpha_exponent(const RowQuad &rq, const float4 
 // ---------------------------------------------------------------------------
 // A6: forward
 // ---------------------------------------------------------------------------
+// One tile's forward pass over its sorted list, from the per-pixel state
+// (T > 0: the pixel is still compositing; T < 0: it stopped, or lies outside
+// the image, and -T is its final transmittance) to the accumulated colours
+// and, per pixel, the list position after its last contributor (last).  With
+// STATS also the contributor count and the position of the stop.
+template <int RPL, bool STATS>
+__device__ __forceinline__ void tile_forward(const ViewTable &vt, const TileCtx &c, uint2 rg,
+                                             const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
+                                             const float2 *__restrict__ ulo, float4 *sa, float4 *sb, float4 *sd,
+                                             int lane, int ly, float pxl, float (&T)[RPL], float (&C0)[RPL],
+                                             float (&C1)[RPL], float (&C2)[RPL], uint32_t (&last)[RPL],
+                                             uint32_t (&ncontrib)[RPL], uint32_t (&stop_at)[RPL]) {
+    for (uint32_t b0 = rg.x; b0 < rg.y; b0 += kWave) {
+        bool any_live = false;
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) any_live |= T[k] > 0.f;
+        if (__ballot(any_live) == 0ull) break;
+        const uint32_t idx = b0 + lane;
+        if (idx < rg.y) {
+            const uint32_t item = pval[idx];
+            float4 a, b, d;
+            stage_record(rec[item], ulo[item], c, (uint32_t)vt.tile_h, a, b, d);
+            sa[lane] = a;
+            sb[lane] = b;
+            sd[lane] = d;
+        }
+        __syncthreads();
+        const int cnt = (int)min((uint32_t)kWave, rg.y - b0);
+        for (int j = 0; j < cnt; ++j) {
+            if ((j & 15) == 15) {  // leave the batch once every pixel of the tile has stopped
+                bool any = false;
+#pragma unroll
+                for (int k = 0; k < RPL; ++k) any |= T[k] > 0.f;
+                if (__ballot(any) == 0ull) break;
+            }
+            const float4 a = sa[j], b = sb[j], d = sd[j];
+            const uint32_t pos = b0 - rg.x + (uint32_t)j;
+            const float dx = a.x - pxl;
+            const uint32_t smask = slab_mask(d.y);
+            const RowQuad rq = row_quad(a, b, dx);
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) {
+                if (!(smask & (1u << k))) continue;
+                const float dy = a.y - ((float)(ly + 4 * k) + 0.5f);
+                const float ex = alpha_exponent(rq, b, dy);
+                if (__ballot(T[k] > 0.f && ex >= kLog2AlphaSkip) == 0ull) continue;
+                const float alpha = fminf(kAlphaMax, __builtin_amdgcn_exp2f(ex));
+                const bool ok = alpha >= kAlphaMin;
+                const float wa = alpha * T[k];
+                const float Tn = T[k] - wa;  // T (1 - alpha)
+                // a stopped pixel has Tn <= 0 < kTMin, so it never adds again; the
+                // pixel stops where ok holds and add does not
+                const bool add = ok & (Tn >= kTMin);
+                const float w = add ? wa : 0.f;
+                C0[k] = fmaf(b.z, w, C0[k]);
+                C1[k] = fmaf(b.w, w, C1[k]);
+                C2[k] = fmaf(d.x, w, C2[k]);
+                last[k] = add ? pos + 1 : last[k];
+                if constexpr (STATS) {
+                    ncontrib[k] += add ? 1u : 0u;
+                    stop_at[k] = (ok && !add && T[k] > 0.f) ? pos : stop_at[k];
+                }
+                // (two selects: written as one nested select, the compiler branched on it)
+                const float Ts = ok ? -fabsf(T[k]) : T[k];
+                T[k] = add ? Tn : Ts;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 template <int RPL, bool STATS>
 __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uint2 *__restrict__ ranges,
                                                          const uint32_t *__restrict__ pval,
@@ -223,8 +299,6 @@ __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uin
         if (t >= vt.total_tiles) break;
         const TileCtx c = tile_ctx(vt, t);
         const uint32_t px = c.ox + lx;
-        // T > 0: the pixel is still compositing; T < 0: it stopped (or lies outside
-        // the image) and -T is its final transmittance
         float T[RPL], C0[RPL], C1[RPL], C2[RPL];
         uint32_t last[RPL], stop_at[RPL], ncontrib[RPL];
 #pragma unroll
@@ -237,61 +311,8 @@ __global__ __launch_bounds__(kWave) void k_composite_fwd(ViewTable vt, const uin
             stop_at[k] = 0xffffffffu;
         }
         const uint2 rg = ranges[t];
-        for (uint32_t b0 = rg.x; b0 < rg.y; b0 += kWave) {
-            bool any_live = false;
-#pragma unroll
-            for (int k = 0; k < RPL; ++k) any_live |= T[k] > 0.f;
-            if (__ballot(any_live) == 0ull) break;
-            const uint32_t idx = b0 + lane;
-            if (idx < rg.y) {
-                const uint32_t item = pval[idx];
-                float4 a, b, d;
-                stage_record(rec[item], ulo[item], c, (uint32_t)vt.tile_h, a, b, d);
-                sa[lane] = a;
-                sb[lane] = b;
-                sd[lane] = d;
-            }
-            __syncthreads();
-            const int cnt = (int)min((uint32_t)kWave, rg.y - b0);
-            for (int j = 0; j < cnt; ++j) {
-                if ((j & 15) == 15) {  // leave the batch once every pixel of the tile has stopped
-                    bool any = false;
-#pragma unroll
-                    for (int k = 0; k < RPL; ++k) any |= T[k] > 0.f;
-                    if (__ballot(any) == 0ull) break;
-                }
-                const float4 a = sa[j], b = sb[j], d = sd[j];
-                const uint32_t pos = b0 - rg.x + (uint32_t)j;
-                const float dx = a.x - pxl;
-                const uint32_t smask = slab_mask(d.y);
-                const RowQuad rq = row_quad(a, b, dx);
-#pragma unroll
-                for (int k = 0; k < RPL; ++k) {
-                    if (!(smask & (1u << k))) continue;
-                    const float dy = a.y - ((float)(ly + 4 * k) + 0.5f);
-                    const float ex = alpha_exponent(rq, b, dy);
-                    if (__ballot(T[k] > 0.f && ex >= kLog2AlphaSkip) == 0ull) continue;
-                    const float alpha = fminf(kAlphaMax, __builtin_amdgcn_exp2f(ex));
-                    const bool ok = alpha >= kAlphaMin;
-                    const float wa = alpha * T[k];
-                    const float Tn = T[k] - wa;  // T (1 - alpha)
-                    // a stopped pixel has Tn <= 0 < kTMin, so it never adds again; the
-                    // pixel stops where ok holds and add does not
-                    const bool add = ok & (Tn >= kTMin);
-                    const float w = add ? wa : 0.f;
-                    C0[k] = fmaf(b.z, w, C0[k]);
-                    C1[k] = fmaf(b.w, w, C1[k]);
-                    C2[k] = fmaf(d.x, w, C2[k]);
-                    last[k] = add ? pos + 1 : last[k];
-                    if constexpr (STATS) {
-                        ncontrib[k] += add ? 1u : 0u;
-                        stop_at[k] = (ok && !add && T[k] > 0.f) ? pos : stop_at[k];
-                    }
-                    T[k] = add ? Tn : (ok ? -fabsf(T[k]) : T[k]);
-                }
-            }
-            __syncthreads();
-        }
+        tile_forward<RPL, STATS>(vt, c, rg, pval, rec, ulo, sa, sb, sd, lane, ly, pxl, T, C0, C1, C2, last, ncontrib,
+                                 stop_at);
         // outputs
         const uint32_t len = rg.y - rg.x;
         uint32_t evals = 0, replays = 0, contrib = 0, nmax = 0;
@@ -376,6 +397,124 @@ __device__ __forceinline__ float l1_grad(float c, float target, float scale) {
     return c > target ? scale : (c < target ? -scale : 0.f);
 }
 
+// One tile's backward pass over list positions [rg.x, end): the per-pixel
+// state starts at T = 1, the upstream gradient g = dL/dC (g0, g1, g2), gB =
+// g . C_out and the contributor count ncon; the pass writes the nine moments
+// of every replayed pair to `partial` (at its slot in emission order) and
+// flags the slot.
+template <int RPL>
+__device__ __forceinline__ void tile_backward(const ViewTable &vt, const TileCtx &c, uint2 rg, uint32_t end,
+                                              const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
+                                              const float2 *__restrict__ ulo, float4 *sa, float4 *sb, float4 *sd,
+                                              float *red, int lane, int ly, float pxl, int fq, int fc,
+                                              float (&T)[RPL], const float (&g0)[RPL], const float (&g1)[RPL],
+                                              const float (&g2)[RPL], float (&gB)[RPL], const uint32_t (&ncon)[RPL],
+                                              float *__restrict__ partial, uint8_t *__restrict__ pflag) {
+    for (uint32_t b0 = rg.x; b0 < end; b0 += kWave) {
+        const uint32_t idx = b0 + lane;
+        if (idx < end) {
+            const uint32_t item = pval[idx];
+            float4 a, b, d;
+            stage_record(rec[item], ulo[item], c, (uint32_t)vt.tile_h, a, b, d);
+            sa[lane] = a;
+            sb[lane] = b;
+            sd[lane] = d;
+            pflag[__float_as_uint(d.z)] = 1;  // this pair's moments get written: the reduction reads them
+        }
+        __syncthreads();
+        const int cnt = (int)min((uint32_t)kWave, end - b0);
+        for (int j0 = 0; j0 < cnt; j0 += kGroup) {
+            uint32_t zq = 0;  // Gaussians of the group with all moments zero
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) {
+                const int j = j0 + q;
+                // per-lane sums over the rows: colour-gradient weights w, sa = alpha
+                // dL/dalpha, sa dy and sa dy^2 (the rows share dx)
+                float a_c0 = 0.f, a_c1 = 0.f, a_c2 = 0.f, a_sa = 0.f, a_say = 0.f, a_sayy = 0.f, dx = 0.f;
+                bool live = false;  // wave-uniform: some lane reached some row of this Gaussian
+                if (j < cnt) {
+                    const uint32_t pos = b0 - rg.x + (uint32_t)j;
+                    const float4 a = sa[j], b = sb[j], d = sd[j];
+                    dx = a.x - pxl;
+                    const uint32_t smask = slab_mask(d.y);
+                    const RowQuad rq = row_quad(a, b, dx);
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k) {
+                        if (!(smask & (1u << k))) continue;
+                        const float dy = a.y - ((float)(ly + 4 * k) + 0.5f);
+                        const float ex = alpha_exponent(rq, b, dy);
+                        if (__ballot(pos < ncon[k] && ex >= kLog2AlphaSkip) == 0ull) continue;
+                        live = true;
+                        const float araw = __builtin_amdgcn_exp2f(ex);
+                        const float alpha = fminf(kAlphaMax, araw);
+                        const bool ok = pos < ncon[k] && alpha >= kAlphaMin;
+                        const float w = ok ? alpha * T[k] : 0.f;
+                        a_c0 = fmaf(w, g0[k], a_c0);
+                        a_c1 = fmaf(w, g1[k], a_c1);
+                        a_c2 = fmaf(w, g2[k], a_c2);
+                        const float grgb = fmaf(g0[k], b.z, fmaf(g1[k], b.w, g2[k] * d.x));
+                        // alpha dL/dalpha = alpha T g.c - alpha g.B / (1 - alpha), with
+                        // B the colour behind this Gaussian; with w = alpha T and
+                        // T' = T (1 - alpha) that is w (g.c - g.B / T') (w = 0 where
+                        // the Gaussian does not contribute)
+                        gB[k] = fmaf(-w, grgb, gB[k]);
+                        T[k] -= w;  // T (1 - alpha) where the Gaussian contributed
+                        const float h = fmaf(-gB[k], __builtin_amdgcn_rcpf(T[k]), grgb);
+                        // dL/dsigma = -sa, alpha dL/dalpha = sa (zero through the 0.99 clamp)
+                        const float sa_ = (araw < kAlphaMax ? w : 0.f) * h;
+                        a_sa += sa_;
+                        const float say = sa_ * dy;
+                        a_say += say;
+                        a_sayy = fmaf(say, dy, a_sayy);
+                    }
+                }
+                if (!live) zq |= 1u << q;  // every moment is zero: the finaliser writes 0
+                if (live) {
+                    // the moments of sa (= -dL/dsigma): sums of sa dx, sa dy, sa dx^2,
+                    // sa dx dy, sa dy^2 (the negated S_x .. S_yy of the projection
+                    // backward), then S_o = sum sa and the colour gradient
+                    float s[kPartialStride];
+                    s[0] = dx * a_sa;
+                    s[1] = a_say;
+                    s[2] = dx * s[0];
+                    s[3] = dx * a_say;
+                    s[4] = a_sayy;
+                    s[5] = a_sa;
+                    s[6] = a_c0;
+                    s[7] = a_c1;
+                    s[8] = a_c2;
+                    // add the lanes of each quad (quad_perm [1, 0, 3, 2], then [2, 3, 0, 1]):
+                    // all four lanes hold the same sum (each step adds a and b as b and a,
+                    // exactly equal) and store it to the same place, so no lane is masked
+                    // off and each move folds into its add
+#pragma unroll
+                    for (int cc = 0; cc < kPartialStride; ++cc)
+                        s[cc] = dpp_add<0x4E, 0xf>(dpp_add<0xB1, 0xf>(s[cc]));
+#pragma unroll
+                    for (int cc = 0; cc < kPartialStride; ++cc)
+                        red[(lane >> 2) * kRedStride + q * kPartialStride + cc] = s[cc];
+                }
+            }
+            __syncthreads();
+            if (lane < kRedCols && j0 + fq < cnt) {
+                float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+                if (!((zq >> fq) & 1u)) {
+#pragma unroll
+                    for (int r = 0; r < kRedRows; r += 4) {
+                        p0 += red[(r + 0) * kRedStride + lane];
+                        p1 += red[(r + 1) * kRedStride + lane];
+                        p2 += red[(r + 2) * kRedStride + lane];
+                        p3 += red[(r + 3) * kRedStride + lane];
+                    }
+                }
+                const uint32_t p = __float_as_uint(sd[j0 + fq].z);
+                partial[(size_t)p * kPartialStride + fc] = (p0 + p1) + (p2 + p3);
+            }
+            __syncthreads();
+        }
+    }
+}
+
 template <int RPL>
 __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uint2 *__restrict__ ranges,
                                                          const uint32_t *__restrict__ pval,
@@ -424,7 +563,7 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
                     g1[k] = l1_grad(i1, g1[k], up.l1_scale);
                     g2[k] = l1_grad(i2, g2[k], up.l1_scale);
                 }
-                gB[k] = g0[k] * i0 + g1[k] * i1 + g2[k] * i2;
+                gB[k] = fmaf(g2[k], i2, fmaf(g1[k], i1, g0[k] * i0));
             } else {
                 ncon[k] = 0;
                 g0[k] = g1[k] = g2[k] = gB[k] = 0.f;
@@ -432,109 +571,94 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
         }
         const uint2 rg = ranges[t];
         const uint32_t end = rg.x + tile_cut[t];  // positions any pixel of the tile used
-        for (uint32_t b0 = rg.x; b0 < end; b0 += kWave) {
-            const uint32_t idx = b0 + lane;
-            if (idx < end) {
-                const uint32_t item = pval[idx];
-                float4 a, b, d;
-                stage_record(rec[item], ulo[item], c, (uint32_t)vt.tile_h, a, b, d);
-                sa[lane] = a;
-                sb[lane] = b;
-                sd[lane] = d;
-                pflag[__float_as_uint(d.z)] = 1;  // this pair's moments get written: the reduction reads them
-            }
-            __syncthreads();
-            const int cnt = (int)min((uint32_t)kWave, end - b0);
-            for (int j0 = 0; j0 < cnt; j0 += kGroup) {
-                uint32_t zq = 0;  // Gaussians of the group with all moments zero
+        tile_backward<RPL>(vt, c, rg, end, pval, rec, ulo, sa, sb, sd, red, lane, ly, pxl, fq, fc, T, g0, g1, g2, gB,
+                           ncon, partial, pflag);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// A6 + A7 for the photometric loss in one pass over the tiles: a workgroup
+// composites its tile forward, forms dL/dC = sign(C - target) * l1_scale of
+// the tile's pixels from the colours it has just accumulated (the gradient of
+// a pixel depends on its own colour only), and replays the tile backward,
+// with the same two tile passes as the kernels above, so that the image, the
+// workspace state and the moments are theirs bit for bit.  What changes is the
+// schedule: a SIMD holds waves in both phases, so the backward's arithmetic
+// fills the forward's latency, and the forward's per-pixel state stays in
+// registers.  A fused tile lasts both passes, so a heavy tile dispatched late
+// leaves a long tail: the tiles are taken in descending buckets of min(list
+// length, the replay count the workspace holds from its previous step),
+// filed by the per-tile depth sort (exact for a repeated step, the list length
+// on a fresh workspace; any order gives the same results).
+// ---------------------------------------------------------------------------
+template <int RPL>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(5))) void k_composite_step(
+    ViewTable vt, const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
+    const float2 *__restrict__ ulo, float3 bg, const float *__restrict__ target, float l1_scale,
+    float *__restrict__ out_rgb, float *__restrict__ out_T, float *__restrict__ pix_T, uint32_t *__restrict__ pix_n,
+    uint32_t *__restrict__ tile_cut, const uint32_t *__restrict__ tile_order, float *__restrict__ partial,
+    uint8_t *__restrict__ pflag, ZeroRows zr, WsHeader *hdr, int persistent) {
+    __shared__ float4 sa[kWave], sb[kWave], sd[kWave];
+    __shared__ float red[kRedRows * kRedStride];
+    const int lane = threadIdx.x;
+    const int lx = lane & 15, ly = lane >> 4;
+    const float pxl = (float)lx + 0.5f;
+    const int fq = lane / kPartialStride, fc = lane - fq * kPartialStride;
+    uint32_t iter = 0;
+    for (;;) {
+        const uint32_t r = next_tile(persistent != 0, &hdr->queue[0], blockIdx.x, iter);
+        if (r >= vt.total_tiles) break;
+        const uint32_t t = tile_by_cost(tile_order, vt.total_tiles, r);
+        zero_unseen_rows(zr, t, hdr->overflow != 0u, lane);
+        const TileCtx c = tile_ctx(vt, t);
+        const uint32_t px = c.ox + lx;
+        const uint2 rg = ranges[t];
+        float T[RPL], C0[RPL], C1[RPL], C2[RPL];
+        uint32_t last[RPL], unused0[RPL], unused1[RPL];
 #pragma unroll
-                for (int q = 0; q < kGroup; ++q) {
-                    const int j = j0 + q;
-                    // per-lane sums over the rows: colour-gradient weights w, sa = alpha
-                    // dL/dalpha, sa dy and sa dy^2 (the rows share dx)
-                    float a_c0 = 0.f, a_c1 = 0.f, a_c2 = 0.f, a_sa = 0.f, a_say = 0.f, a_sayy = 0.f, dx = 0.f;
-                    bool live = false;  // wave-uniform: some lane reached some row of this Gaussian
-                    if (j < cnt) {
-                        const uint32_t pos = b0 - rg.x + (uint32_t)j;
-                        const float4 a = sa[j], b = sb[j], d = sd[j];
-                        dx = a.x - pxl;
-                        const uint32_t smask = slab_mask(d.y);
-                        const RowQuad rq = row_quad(a, b, dx);
-#pragma unroll
-                        for (int k = 0; k < RPL; ++k) {
-                            if (!(smask & (1u << k))) continue;
-                            const float dy = a.y - ((float)(ly + 4 * k) + 0.5f);
-                            const float ex = alpha_exponent(rq, b, dy);
-                            if (__ballot(pos < ncon[k] && ex >= kLog2AlphaSkip) == 0ull) continue;
-                            live = true;
-                            const float araw = __builtin_amdgcn_exp2f(ex);
-                            const float alpha = fminf(kAlphaMax, araw);
-                            const bool ok = pos < ncon[k] && alpha >= kAlphaMin;
-                            const float w = ok ? alpha * T[k] : 0.f;
-                            a_c0 = fmaf(w, g0[k], a_c0);
-                            a_c1 = fmaf(w, g1[k], a_c1);
-                            a_c2 = fmaf(w, g2[k], a_c2);
-                            const float grgb = fmaf(g0[k], b.z, fmaf(g1[k], b.w, g2[k] * d.x));
-                            // alpha dL/dalpha = alpha T g.c - alpha g.B / (1 - alpha), with
-                            // B the colour behind this Gaussian; with w = alpha T and
-                            // T' = T (1 - alpha) that is w (g.c - g.B / T') (w = 0 where
-                            // the Gaussian does not contribute)
-                            gB[k] = fmaf(-w, grgb, gB[k]);
-                            T[k] -= w;  // T (1 - alpha) where the Gaussian contributed
-                            const float h = fmaf(-gB[k], __builtin_amdgcn_rcpf(T[k]), grgb);
-                            // dL/dsigma = -sa, alpha dL/dalpha = sa (zero through the 0.99 clamp)
-                            const float sa_ = (araw < kAlphaMax ? w : 0.f) * h;
-                            a_sa += sa_;
-                            const float say = sa_ * dy;
-                            a_say += say;
-                            a_sayy = fmaf(say, dy, a_sayy);
-                        }
-                    }
-                    if (!live) zq |= 1u << q;  // every moment is zero: the finaliser writes 0
-                    if (live) {
-                        // the moments of sa (= -dL/dsigma): sums of sa dx, sa dy, sa dx^2,
-                        // sa dx dy, sa dy^2 (the negated S_x .. S_yy of the projection
-                        // backward), then S_o = sum sa and the colour gradient
-                        float s[kPartialStride];
-                        s[0] = dx * a_sa;
-                        s[1] = a_say;
-                        s[2] = dx * s[0];
-                        s[3] = dx * a_say;
-                        s[4] = a_sayy;
-                        s[5] = a_sa;
-                        s[6] = a_c0;
-                        s[7] = a_c1;
-                        s[8] = a_c2;
-                        // add the lanes of each quad (quad_perm [1, 0, 3, 2], then [2, 3, 0, 1]):
-                        // all four lanes hold the same sum (each step adds a and b as b and a,
-                        // exactly equal) and store it to the same place, so no lane is masked
-                        // off and each move folds into its add
-#pragma unroll
-                        for (int cc = 0; cc < kPartialStride; ++cc)
-                            s[cc] = dpp_add<0x4E, 0xf>(dpp_add<0xB1, 0xf>(s[cc]));
-#pragma unroll
-                        for (int cc = 0; cc < kPartialStride; ++cc)
-                            red[(lane >> 2) * kRedStride + q * kPartialStride + cc] = s[cc];
-                    }
-                }
-                __syncthreads();
-                if (lane < kRedCols && j0 + fq < cnt) {
-                    float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
-                    if (!((zq >> fq) & 1u)) {
-#pragma unroll
-                        for (int r = 0; r < kRedRows; r += 4) {
-                            p0 += red[(r + 0) * kRedStride + lane];
-                            p1 += red[(r + 1) * kRedStride + lane];
-                            p2 += red[(r + 2) * kRedStride + lane];
-                            p3 += red[(r + 3) * kRedStride + lane];
-                        }
-                    }
-                    const uint32_t p = __float_as_uint(sd[j0 + fq].z);
-                    partial[(size_t)p * kPartialStride + fc] = (p0 + p1) + (p2 + p3);
-                }
-                __syncthreads();
-            }
+        for (int k = 0; k < RPL; ++k) {
+            const uint32_t py = c.oy + ly + 4 * k;
+            T[k] = (px < c.width && py < c.height) ? 1.f : -1.f;
+            C0[k] = C1[k] = C2[k] = 0.f;
+            last[k] = 0;
         }
+        tile_forward<RPL, false>(vt, c, rg, pval, rec, ulo, sa, sb, sd, lane, ly, pxl, T, C0, C1, C2, last, unused0,
+                                 unused1);
+        // outputs, and the backward's start: g = dL/dC, gB = g . C_out
+        const size_t plane = (size_t)c.width * c.height;
+        float *img = out_rgb + 3 * (size_t)c.pix_off;
+        const float *tgt = target + 3 * (size_t)c.pix_off;
+        float g0[RPL], g1[RPL], g2[RPL], gB[RPL];
+        uint32_t ncon[RPL], nmax = 0;
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+            const uint32_t py = c.oy + ly + 4 * k;
+            if (px < c.width && py < c.height) {
+                const size_t pix = (size_t)py * c.width + px;
+                const float Tf = fabsf(T[k]);
+                const float i0 = C0[k] + Tf * bg.x, i1 = C1[k] + Tf * bg.y, i2 = C2[k] + Tf * bg.z;
+                img[pix] = i0;
+                img[plane + pix] = i1;
+                img[2 * plane + pix] = i2;
+                pix_T[c.pix_off + pix] = Tf;
+                pix_n[c.pix_off + pix] = last[k];
+                if (out_T) out_T[c.pix_off + pix] = Tf;
+                nmax = max(nmax, last[k]);
+                ncon[k] = last[k];
+                g0[k] = l1_grad(i0, tgt[pix], l1_scale);
+                g1[k] = l1_grad(i1, tgt[plane + pix], l1_scale);
+                g2[k] = l1_grad(i2, tgt[2 * plane + pix], l1_scale);
+                gB[k] = fmaf(g2[k], i2, fmaf(g1[k], i1, g0[k] * i0));
+            } else {
+                ncon[k] = 0;
+                g0[k] = g1[k] = g2[k] = gB[k] = 0.f;
+            }
+            T[k] = 1.f;
+        }
+        nmax = wave_reduce(nmax, 0u, [](uint32_t a, uint32_t b) { return max(a, b); });
+        if (lane == 0) tile_cut[t] = nmax;
+        tile_backward<RPL>(vt, c, rg, rg.x + nmax, pval, rec, ulo, sa, sb, sd, red, lane, ly, pxl, fq, fc, T, g0, g1,
+                           g2, gB, ncon, partial, pflag);
     }
 }
 
@@ -594,6 +718,29 @@ void launch_composite_bwd(const ViewTable &vt, const uint2 *ranges, const uint32
         default: GSR_BWD(4); break;
     }
 #undef GSR_BWD
+}
+
+
+void launch_composite_step(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
+                           const float2 *ulo, float3 bg, const float *target, float l1_scale, float *out_rgb,
+                           float *out_T, float *pix_T, uint32_t *pix_n, uint32_t *tile_cut,
+                           const uint32_t *tile_order, float *partial, uint8_t *pflag, const ZeroRows &zr,
+                           WsHeader *hdr, bool persistent, int persistent_ctas, hipStream_t st) {
+    if (vt.total_tiles == 0) return;
+    const int p = persistent ? 1 : 0;
+#define GSR_STEP(R)                                                                                                 \
+    hipLaunchKernelGGL(k_composite_step<R>,                                                                         \
+                       dim3(persistent ? (unsigned)resident_ctas(k_composite_step<R>, persistent_ctas)              \
+                                       : vt.total_tiles),                                                           \
+                       dim3(kWave), 0, st, vt, ranges, pval, rec, ulo, bg, target, l1_scale, out_rgb, out_T, pix_T, \
+                       pix_n, tile_cut, tile_order, partial, pflag, zr, hdr, p)
+    switch (vt.tile_h) {
+        case 4: GSR_STEP(1); break;
+        case 8: GSR_STEP(2); break;
+        case 32: GSR_STEP(8); break;
+        default: GSR_STEP(4); break;
+    }
+#undef GSR_STEP
 }
 
 }  // namespace gsr

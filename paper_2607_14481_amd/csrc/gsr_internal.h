@@ -111,6 +111,11 @@ constexpr int kPartialStride = 9;                         // floats per pair gra
 // Backward tile schedule: tiles in descending buckets of their replay count
 // (16 buckets per octave), so that the heaviest start first.
 constexpr uint32_t kCostBuckets = 128;
+// Bucket of a tile's cost (its replay count, or its list length): 16 per
+// octave, floor(16 log2(n + 1)), the top bucket taking everything above 255.
+__device__ __forceinline__ uint32_t cost_bucket(uint32_t n) {
+    return min(kCostBuckets - 1, (uint32_t)(16.f * __log2f((float)n + 1.f)));
+}
 // Pairs are also processed in fixed chunks of consecutive emission-order
 // slots (A3 emission, A8 reduction): 256 threads x 4 pairs.
 constexpr uint32_t kChunkPairs = 1024;
@@ -161,10 +166,13 @@ void radix_sort_u32(uint32_t *keys[2], uint32_t *vals[2], SortCount sc, uint64_t
 // merge pass reads (x when long_passes is odd, else y; hi = depth key,
 // lo = item); lists longer than kLongWindow << long_passes, or all long lists
 // when long_passes == 0, are sorted by one workgroup in global memory
-// (x_hi/x_lo as scratch).
+// (x_hi/x_lo as scratch).  length_order (or NULL): every tile is filed in
+// the bucket of its list length (the layout of WsLayout::tile_order, whose
+// counts launch_tile_ranges cleared), the schedule of the fused compositing.
 void launch_tile_depth_sort(const uint2 *ranges, uint32_t total_tiles, uint32_t *pval, const uint32_t *zkey,
                             uint32_t *x_hi, uint32_t *x_lo, uint32_t *y_hi, uint32_t *y_lo,
-                            const uint32_t *long_tiles, int long_passes, uint32_t chunk_wgs, const WsHeader *hdr,
+                            const uint32_t *long_tiles, int long_passes, uint32_t chunk_wgs,
+                            uint32_t *length_order, const uint32_t *cost_hint, const WsHeader *hdr,
                             hipStream_t st);
 // Merge pass p of long_passes over the long lists' runs (run length
 // kLongWindow << p); the last pass writes the item ids into pval.
@@ -210,6 +218,16 @@ void launch_composite_bwd(const ViewTable &vt, const uint2 *ranges, const uint32
                           const float2 *ulo, const float *out_rgb, const Upstream &up, const uint32_t *pix_n,
                           const uint32_t *tile_cut, const uint32_t *tile_order, float *partial, uint8_t *pflag,
                           const ZeroRows &zr, WsHeader *hdr, bool persistent, int persistent_ctas, hipStream_t st);
+// A6 and A7 fused for the mean absolute error against `target` (dL/dC =
+// sign(C - target) * l1_scale): the forward's outputs and workspace state
+// (image, out_T, pix_T, pix_n, tile_cut) and the backward's (moments, slot
+// flags, zeroed rows) in one launch; tiles in the order of `tile_order` as
+// filed by launch_tile_depth_sort's length_order.
+void launch_composite_step(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
+                           const float2 *ulo, float3 bg, const float *target, float l1_scale, float *out_rgb,
+                           float *out_T, float *pix_T, uint32_t *pix_n, uint32_t *tile_cut,
+                           const uint32_t *tile_order, float *partial, uint8_t *pflag, const ZeroRows &zr,
+                           WsHeader *hdr, bool persistent, int persistent_ctas, hipStream_t st);
 void launch_pair_reduce(const uint32_t *poff, const uint32_t *chunk_item, uint64_t pair_grid, const uint32_t *vis,
                         const uint32_t *pflag, const float *partial, float4 *screen, float *carry, const WsHeader *hdr,
                         hipStream_t st);

@@ -888,6 +888,8 @@ __global__ __launch_bounds__(256) void k_tile_depth_sort(const uint2 *__restrict
                                                          uint32_t *__restrict__ x_hi, uint32_t *__restrict__ x_lo,
                                                          uint32_t *__restrict__ y_hi, uint32_t *__restrict__ y_lo,
                                                          const uint32_t *__restrict__ long_tiles, int passes,
+                                                         uint32_t *__restrict__ length_order,
+                                                         const uint32_t *__restrict__ cost_hint,
                                                          const WsHeader *__restrict__ hdr) {
     __shared__ u64 s_buf[kGroupSortMax / 2];  // bucket entries; the network's exchange area (16 KB)
     __shared__ uint32_t s_cnt[kBlockBucketMax];
@@ -913,6 +915,11 @@ __global__ __launch_bounds__(256) void k_tile_depth_sort(const uint2 *__restrict
     const uint2 rg = ranges[t];
     const uint32_t len = rg.y - rg.x;
     uint32_t *list = pval + rg.x;
+    if (length_order && threadIdx.x == 0) {
+        const uint32_t b = cost_bucket(min(len, cost_hint[t]));
+        const uint32_t slot = atomicAdd(&length_order[b], 1u);
+        length_order[kCostBuckets + (size_t)b * total_tiles + slot] = t;
+    }
     if (len <= 1) return;
     if (len <= 256)
         sort_list_block<1>(list, len, zkey, s_buf, s_cnt, s_red, xs);
@@ -929,12 +936,13 @@ __global__ __launch_bounds__(256) void k_tile_depth_sort(const uint2 *__restrict
 
 void launch_tile_depth_sort(const uint2 *ranges, uint32_t total_tiles, uint32_t *pval, const uint32_t *zkey,
                             uint32_t *x_hi, uint32_t *x_lo, uint32_t *y_hi, uint32_t *y_lo,
-                            const uint32_t *long_tiles, int long_passes, uint32_t chunk_wgs, const WsHeader *hdr,
+                            const uint32_t *long_tiles, int long_passes, uint32_t chunk_wgs,
+                            uint32_t *length_order, const uint32_t *cost_hint, const WsHeader *hdr,
                             hipStream_t st) {
     if (total_tiles == 0) return;
     const uint32_t grid = total_tiles + (long_passes > 0 ? chunk_wgs : 0u);
     hipLaunchKernelGGL(k_tile_depth_sort, dim3(grid), dim3(256), 0, st, ranges, total_tiles, pval, zkey, x_hi, x_lo,
-                       y_hi, y_lo, long_tiles, long_passes, hdr);
+                       y_hi, y_lo, long_tiles, long_passes, length_order, cost_hint, hdr);
 }
 
 // ---------------------------------------------------------------------------

@@ -27,7 +27,8 @@ GSR_FLAG_PERSISTENT = 2
 GSR_FLAG_STATS = 4
 
 EXPORTED = ("gsr_version", "gsr_status_string", "gsr_last_error", "gsr_workspace_bytes",
-            "gsr_rasterize_forward", "gsr_rasterize_backward", "gsr_rasterize_backward_l1", "gsr_query_pairs",
+            "gsr_rasterize_forward", "gsr_rasterize_backward", "gsr_rasterize_backward_l1",
+            "gsr_rasterize_step_l1", "gsr_query_pairs",
             "gsr_query_stats",
             "gsr_export_state", "gsr_adam_step", "gsr_pose_step", "gsr_sim3_relocate",
             "gsr_hierarchy_cut_scratch_bytes", "gsr_hierarchy_cut", "gsr_hierarchy_cut_static",
@@ -115,6 +116,10 @@ def lib():
                                              C.POINTER(gsr_gaussian_grads), vp, vp, C.c_uint32, vp]
         L.gsr_rasterize_backward_l1.restype = C.c_int
         L.gsr_rasterize_backward_l1.argtypes = L.gsr_rasterize_backward.argtypes
+        L.gsr_rasterize_step_l1.restype = C.c_int
+        L.gsr_rasterize_step_l1.argtypes = [vp, sz, C.POINTER(gsr_gaussians), C.c_int32, C.POINTER(gsr_camera),
+                                            vp, C.POINTER(C.c_float), C.POINTER(gsr_launch_config), vp, vp, vp,
+                                            C.POINTER(gsr_gaussian_grads), vp, vp, C.c_uint32, vp]
         L.gsr_query_pairs.restype = C.c_int
         L.gsr_query_pairs.argtypes = [vp, sz, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32), vp]
         L.gsr_query_stats.restype = C.c_int
@@ -299,6 +304,25 @@ def rasterize_backward_l1(ws: torch.Tensor, params: Sequence[torch.Tensor], sh_d
                                            bgc, C.byref(cfg) if cfg is not None else None, _ptr(out_rgb),
                                            _ptr(target_rgb), C.byref(gr), _ptr(dL_dworld_to_cam), _ptr(dL_dtwist),
                                            int(flags), _stream_ptr(stream)))
+
+
+def rasterize_step_l1(ws: torch.Tensor, params: Sequence[torch.Tensor], sh_degree: int, cams: Sequence,
+                      world_to_cam: torch.Tensor, bg: Sequence[float], target_rgb: torch.Tensor,
+                      out_rgb: torch.Tensor, grads: Sequence[torch.Tensor],
+                      dL_dworld_to_cam: Optional[torch.Tensor] = None, dL_dtwist: Optional[torch.Tensor] = None,
+                      out_T: Optional[torch.Tensor] = None, flags: int = 0,
+                      cfg: Optional[gsr_launch_config] = None, stream=None):
+    """Forward and the backward of the mean absolute error against target_rgb
+    in one call (the compositing passes fused per tile)."""
+    g = gaussians_struct(*params, sh_degree)
+    gr = gsr_gaussian_grads()
+    gr.means, gr.log_scales, gr.quats, gr.opacities, gr.sh = [_ptr(t) for t in grads]
+    arr = cameras(cams)
+    bgc = (C.c_float * 3)(*[float(x) for x in bg])
+    _check(lib().gsr_rasterize_step_l1(_ptr(ws), ws.numel(), C.byref(g), len(cams), arr, _ptr(world_to_cam), bgc,
+                                       C.byref(cfg) if cfg is not None else None, _ptr(target_rgb), _ptr(out_rgb),
+                                       _ptr(out_T), C.byref(gr), _ptr(dL_dworld_to_cam), _ptr(dL_dtwist),
+                                       int(flags), _stream_ptr(stream)))
 
 
 def query_pairs(ws: torch.Tensor, stream=None):

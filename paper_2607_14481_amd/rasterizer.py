@@ -126,6 +126,35 @@ class GaussianRasterizer:
                                   self.flags & gsr.GSR_FLAG_PERSISTENT, self.cfg)
         return grads, (g_w2c.reshape(V, 4, 4) if want_pose else None), g_tw
 
+    def step_l1(self, params: Sequence[torch.Tensor], world_to_cam: torch.Tensor, bg, target: torch.Tensor,
+                ws: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None, want_pose: bool = True):
+        """Forward and the backward of the mean absolute error against target
+        in one library call: the same image, gradients and workspace state as
+        forward() then backward_l1().  Returns (rgb, ws, grads, 4x4 pose
+        gradients, twist gradients)."""
+        params = [gsr._as_param(t, nm) for t, nm in zip(params, PARAM_NAMES)]
+        w2c = gsr._as_param(world_to_cam, "world_to_cam").reshape(len(self.cams), 16)
+        tgt = gsr._as_param(target, "target")
+        n = int(params[0].shape[0])
+        rgb = out if out is not None else torch.empty(3 * self.total_pixels, dtype=torch.float32, device=self.device)
+        grads = [torch.empty_like(t) for t in params]
+        V = len(self.cams)
+        g_w2c = torch.empty((V, 16), dtype=torch.float32, device=self.device) if want_pose else None
+        g_tw = torch.empty((V, 6), dtype=torch.float32, device=self.device) if want_pose else None
+        for _ in range(8):
+            if ws is None:
+                ws = self.workspace(n)
+            try:
+                gsr.rasterize_step_l1(ws, params, self.sh_degree, self.cams, w2c, bg, tgt, rgb, grads, g_w2c, g_tw,
+                                      None, self.flags, self.cfg)
+            except gsr.CapacityError:
+                needed, _, _ = gsr.query_pairs(ws)
+                self.capacity = max(self.capacity, int(needed * self.headroom) + 1024)
+                ws = None
+                continue
+            return rgb, ws, grads, (g_w2c.reshape(V, 4, 4) if want_pose else None), g_tw
+        raise RuntimeError("pair capacity did not converge")
+
     def split(self, rgb: torch.Tensor) -> List[torch.Tensor]:
         """Planar concatenated images -> list of [3, H, W] views."""
         out, o = [], 0

@@ -267,14 +267,16 @@ class Server:
             params = self.scene.params(n)
             w2c = torch.tensor(np.stack([np.asarray(c.world_to_cam, np.float32) for c in cams]),
                                device=self.scene.device)
-            rgb, _ = rast.forward(params, w2c, (0.0, 0.0, 0.0), ws=ws)
-            job = Job(reqs, st, slot, torch.cuda.Event(), rast, ws, rgb, bytes=est)
-            if reqs[0].kind == "optimise":
-                if self.loss == "l1":
-                    # L1 against the request's target, upstream formed inside the backward
-                    target = self._target(reqs[0], rgb.numel())
-                    job.grads, job.pose_grad, _ = rast.backward_l1(ws, params, w2c, (0.0, 0.0, 0.0), rgb, target)
-                else:
+            if reqs[0].kind == "optimise" and self.loss == "l1":
+                # forward, L1 against the request's target and backward in one call
+                target = self._target(reqs[0], 3 * rast.total_pixels)
+                rgb, _, grads, pose_grad, _ = rast.step_l1(params, w2c, (0.0, 0.0, 0.0), target, ws=ws)
+                job = Job(reqs, st, slot, torch.cuda.Event(), rast, ws, rgb, bytes=est)
+                job.grads, job.pose_grad = grads, pose_grad
+            else:
+                rgb, _ = rast.forward(params, w2c, (0.0, 0.0, 0.0), ws=ws)
+                job = Job(reqs, st, slot, torch.cuda.Event(), rast, ws, rgb, bytes=est)
+                if reqs[0].kind == "optimise":
                     job.upstream = self._upstream(reqs[0], rgb.numel())
                     job.grads, job.pose_grad, _ = rast.backward(ws, params, w2c, (0.0, 0.0, 0.0), rgb,
                                                                 job.upstream)

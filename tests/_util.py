@@ -158,3 +158,16 @@ def compare_grads(gpu, ref, label, keys=GRAD_KEYS, tol=GRAD_TOL):
         e = rel_err(gpu[k], ref[k])
         log(f"{label}: rel err d{k} = {e:.3e}")
         assert e <= tol, (label, k, e)
+
+
+_SHARED = {}
+
+
+def lod_workload():
+    """The level-of-detail view (4M-leaf street hierarchy, 1.5 px cut), built
+    once per test session: its build takes ~20 s on the host."""
+    if "lod" not in _SHARED:
+        from paper_2607_14481_amd import hierarchy
+        _SHARED["lod"] = hierarchy.lod_workload()
+        log(f"lod cut: {_SHARED['lod'].meta}")
+    return _SHARED["lod"]

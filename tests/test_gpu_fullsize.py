@@ -18,7 +18,7 @@ import pytest
 from oracle import oracle as O
 from paper_2607_14481_amd import scenes as S
 
-from ._util import (GRAD_KEYS, GRAD_TOL, compare_grads, compare_view, gpu_render, log,
+from ._util import (GRAD_KEYS, GRAD_TOL, compare_grads, compare_view, gpu_render, lod_workload, log,
                     oracle_bin_from_gpu_state, rel_err)
 
 pytestmark = pytest.mark.gpu
@@ -76,15 +76,8 @@ def test_single_view_1080p_200k_full_parity():
     _full_parity(S.single_view_1080p(), seed=102, bg=(0.1, 0.1, 0.1))
 
 
-_LOD = {}
-
-
 def _lod():
-    if "wl" not in _LOD:
-        from paper_2607_14481_amd import hierarchy
-        _LOD["wl"] = hierarchy.lod_workload()
-        log(f"lod cut: {_LOD['wl'].meta}")
-    return _LOD["wl"]
+    return lod_workload()
 
 
 def test_lod_cut_1080p_full_parity():
