@@ -899,6 +899,7 @@ def main():
                             "plain_ms_per_step": round(om["ms_plain"], 4),
                             "graph_iters_per_s": round(1000.0 / om["graph_ms"], 3) if om["graph_ms"] else None,
                             "graph_ms_per_step": round(om["graph_ms"], 4) if om["graph_ms"] else None,
+                            "two_pass_ms_per_step": round(om["ms_two_pass"], 4) if om["ms_two_pass"] else None,
                             "graph_error": om["graph_err"],
                             "stage_ms": {k: round(v, 4) for k, v in om["stage_ms"].items()},
                             "work": om["stats"], "meta": owl.meta, "_wl": owl}

@@ -346,11 +346,12 @@ int forward_setup(void *ws, size_t ws_bytes, const gsr_gaussians *g, int32_t n_v
 
 // A1-A5 of a forward (projection, compaction, emission, tile sort, ranges,
 // per-tile depth sort); pc: the pair buffer holding the sorted lists.  With
-// length_order, the depth sort also files every tile by its list length in
-// tile_order (the fused compositing's schedule).
+// schedule, every tile is also filed in tile_order by min(list length, the
+// replay count tile_cut holds from the previous step): the fused
+// compositing's schedule.
 int forward_binning(const gsr_gaussians *g, const gsr::ViewTable &vt, const float *world_to_cam,
                     const gsr_launch_config *cfg, const gsr::WsLayout &L, uint64_t cap, const Ptrs &p, uint32_t flags,
-                    bool length_order, const StageMark &mark, hipStream_t st, int &pc) {
+                    bool schedule, const StageMark &mark, hipStream_t st, int &pc) {
     using namespace gsr;
     int rc = GSR_OK;
     const uint64_t n = (uint64_t)g->n;
@@ -396,7 +397,7 @@ int forward_binning(const gsr_gaussians *g, const gsr::ViewTable &vt, const floa
     uint32_t *xh = p.pkey[pc ^ 1], *xl = p.pval[pc ^ 1], *yh = p.pkey[pc], *yl = p.pval[pc];
     if (passes > 0) launch_long_windows(p.ranges, p.long_tiles, passes, p.hdr, st);
     launch_tile_depth_sort(p.ranges, vt.total_tiles, p.pval[pc], p.zkey, xh, xl, yh, yl, p.long_tiles, passes,
-                           chunk_wgs, length_order ? p.tile_order : nullptr, p.tile_cut, p.hdr, st);
+                           chunk_wgs, schedule ? p.tile_order : nullptr, p.tile_cut, p.hdr, st);
     for (int q = 0; q < passes; ++q) {
         // the runs start in x when the pass count is odd, so that the last pass reads x
         const bool from_x = ((passes - q) & 1) != 0;

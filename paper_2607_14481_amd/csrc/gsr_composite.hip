@@ -588,8 +588,8 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(ViewTable vt, const uin
 // registers.  A fused tile lasts both passes, so a heavy tile dispatched late
 // leaves a long tail: the tiles are taken in descending buckets of min(list
 // length, the replay count the workspace holds from its previous step),
-// filed by the per-tile depth sort (exact for a repeated step, the list length
-// on a fresh workspace; any order gives the same results).
+// filed by a workgroup of the per-tile depth sort (exact for a repeated step,
+// the list length on a fresh workspace; any order gives the same results).
 // ---------------------------------------------------------------------------
 template <int RPL>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(5))) void k_composite_step(

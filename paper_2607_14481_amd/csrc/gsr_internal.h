@@ -166,14 +166,15 @@ void radix_sort_u32(uint32_t *keys[2], uint32_t *vals[2], SortCount sc, uint64_t
 // merge pass reads (x when long_passes is odd, else y; hi = depth key,
 // lo = item); lists longer than kLongWindow << long_passes, or all long lists
 // when long_passes == 0, are sorted by one workgroup in global memory
-// (x_hi/x_lo as scratch).  length_order (or NULL): every tile is filed in
-// the bucket of its list length (the layout of WsLayout::tile_order, whose
-// counts launch_tile_ranges cleared), the schedule of the fused compositing.
+// (x_hi/x_lo as scratch).  sched (or NULL): one more workgroup files the
+// fused compositing's schedule there (layout of WsLayout::tile_order): every
+// tile in the bucket of min(its list length, cost_hint[t]), cost_hint being
+// the previous step's replay count per tile (any values: only the order of
+// the tiles depends on them).
 void launch_tile_depth_sort(const uint2 *ranges, uint32_t total_tiles, uint32_t *pval, const uint32_t *zkey,
                             uint32_t *x_hi, uint32_t *x_lo, uint32_t *y_hi, uint32_t *y_lo,
-                            const uint32_t *long_tiles, int long_passes, uint32_t chunk_wgs,
-                            uint32_t *length_order, const uint32_t *cost_hint, const WsHeader *hdr,
-                            hipStream_t st);
+                            const uint32_t *long_tiles, int long_passes, uint32_t chunk_wgs, uint32_t *sched,
+                            const uint32_t *cost_hint, const WsHeader *hdr, hipStream_t st);
 // Merge pass p of long_passes over the long lists' runs (run length
 // kLongWindow << p); the last pass writes the item ids into pval.
 // Window offsets of the long lists the multi-workgroup path takes: first
@@ -222,7 +223,7 @@ void launch_composite_bwd(const ViewTable &vt, const uint2 *ranges, const uint32
 // sign(C - target) * l1_scale): the forward's outputs and workspace state
 // (image, out_T, pix_T, pix_n, tile_cut) and the backward's (moments, slot
 // flags, zeroed rows) in one launch; tiles in the order of `tile_order` as
-// filed by launch_tile_depth_sort's length_order.
+// filed by launch_tile_depth_sort's sched.
 void launch_composite_step(const ViewTable &vt, const uint2 *ranges, const uint32_t *pval, const Rec *rec,
                            const float2 *ulo, float3 bg, const float *target, float l1_scale, float *out_rgb,
                            float *out_T, float *pix_T, uint32_t *pix_n, uint32_t *tile_cut,

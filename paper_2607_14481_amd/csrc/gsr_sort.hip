@@ -883,26 +883,69 @@ __device__ __forceinline__ bool long_tile_window(const uint32_t *__restrict__ lo
     return true;
 }
 
+// The fused compositing's schedule, filed by one workgroup: every tile in the
+// bucket of min(its list length, cost_hint[t]).  Each bucket has room for
+// every tile, so filing needs only a slot counter per bucket, kept in LDS
+// (`slots`): returning atomics on global counters serialise across the chip
+// when most tiles share a few buckets, as they do, while LDS atomics resolve
+// the lanes that collide within one instruction.  kSched tiles per thread are
+// loaded together.
+constexpr int kSched = 16;
+__device__ void file_schedule(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ cost_hint,
+                              uint32_t total_tiles, uint32_t *__restrict__ order, uint32_t *slots) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    if (tid < (int)kCostBuckets) slots[tid] = 0u;
+    __syncthreads();
+    for (uint32_t base = 0; base < total_tiles; base += (uint32_t)(nt * kSched)) {
+        uint32_t b[kSched];
+#pragma unroll
+        for (int q = 0; q < kSched; ++q) {
+            const uint32_t t = base + (uint32_t)(q * nt + tid);
+            b[q] = kCostBuckets;  // none
+            if (t < total_tiles) {
+                const uint2 rg = ranges[t];
+                b[q] = cost_bucket(min(rg.y - rg.x, cost_hint[t]));
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kSched; ++q) {
+            if (b[q] < kCostBuckets) {
+                const uint32_t slot = atomicAdd(&slots[b[q]], 1u);
+                order[kCostBuckets + (size_t)b[q] * total_tiles + slot] = base + (uint32_t)(q * nt + tid);
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < (int)kCostBuckets) order[tid] = slots[tid];
+}
+
 __global__ __launch_bounds__(256) void k_tile_depth_sort(const uint2 *__restrict__ ranges, uint32_t total_tiles,
                                                          uint32_t *__restrict__ pval, const uint32_t *__restrict__ zkey,
                                                          uint32_t *__restrict__ x_hi, uint32_t *__restrict__ x_lo,
                                                          uint32_t *__restrict__ y_hi, uint32_t *__restrict__ y_lo,
                                                          const uint32_t *__restrict__ long_tiles, int passes,
-                                                         uint32_t *__restrict__ length_order,
+                                                         uint32_t *__restrict__ sched,
                                                          const uint32_t *__restrict__ cost_hint,
                                                          const WsHeader *__restrict__ hdr) {
     __shared__ u64 s_buf[kGroupSortMax / 2];  // bucket entries; the network's exchange area (16 KB)
     __shared__ uint32_t s_cnt[kBlockBucketMax];
     __shared__ uint32_t s_red[8];
-    if (hdr->overflow) return;  // uniform
+    if (hdr->overflow) return;  // uniform (no schedule either: the fused compositing falls back to tile order)
     uint32_t *xs = reinterpret_cast<uint32_t *>(s_buf);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const bool multi = long_path_on(hdr, passes);
-    if (blockIdx.x >= total_tiles) {
+    // with a schedule to file, workgroup 0 files it (overlapping the sorts)
+    // and the tiles start at workgroup 1
+    if (sched && blockIdx.x == 0) {
+        file_schedule(ranges, cost_hint, total_tiles, sched, s_cnt);
+        return;
+    }
+    const uint32_t bid = blockIdx.x - (sched ? 1u : 0u);
+    if (bid >= total_tiles) {
         // a window of a long list, sorted into a run of the first merge pass's input
         if (!multi) return;
         uint32_t t, w;
-        if (!long_tile_window(long_tiles, long_tiles + kMaxLongTiles, hdr->n_long, blockIdx.x - total_tiles, t, w))
+        if (!long_tile_window(long_tiles, long_tiles + kMaxLongTiles, hdr->n_long, bid - total_tiles, t, w))
             return;
         const uint2 rg = ranges[t];
         const uint32_t off = rg.x + w * kLongWindow;
@@ -911,15 +954,10 @@ __global__ __launch_bounds__(256) void k_tile_depth_sort(const uint2 *__restrict
         sort_list_regs<16, 4>(pval + off, n, zkey, lane, wave, xs, oh + off, ol + off);
         return;
     }
-    const uint32_t t = blockIdx.x;
+    const uint32_t t = bid;
     const uint2 rg = ranges[t];
     const uint32_t len = rg.y - rg.x;
     uint32_t *list = pval + rg.x;
-    if (length_order && threadIdx.x == 0) {
-        const uint32_t b = cost_bucket(min(len, cost_hint[t]));
-        const uint32_t slot = atomicAdd(&length_order[b], 1u);
-        length_order[kCostBuckets + (size_t)b * total_tiles + slot] = t;
-    }
     if (len <= 1) return;
     if (len <= 256)
         sort_list_block<1>(list, len, zkey, s_buf, s_cnt, s_red, xs);
@@ -936,13 +974,12 @@ __global__ __launch_bounds__(256) void k_tile_depth_sort(const uint2 *__restrict
 
 void launch_tile_depth_sort(const uint2 *ranges, uint32_t total_tiles, uint32_t *pval, const uint32_t *zkey,
                             uint32_t *x_hi, uint32_t *x_lo, uint32_t *y_hi, uint32_t *y_lo,
-                            const uint32_t *long_tiles, int long_passes, uint32_t chunk_wgs,
-                            uint32_t *length_order, const uint32_t *cost_hint, const WsHeader *hdr,
-                            hipStream_t st) {
+                            const uint32_t *long_tiles, int long_passes, uint32_t chunk_wgs, uint32_t *sched,
+                            const uint32_t *cost_hint, const WsHeader *hdr, hipStream_t st) {
     if (total_tiles == 0) return;
-    const uint32_t grid = total_tiles + (long_passes > 0 ? chunk_wgs : 0u);
+    const uint32_t grid = total_tiles + (long_passes > 0 ? chunk_wgs : 0u) + (sched ? 1u : 0u);
     hipLaunchKernelGGL(k_tile_depth_sort, dim3(grid), dim3(256), 0, st, ranges, total_tiles, pval, zkey, x_hi, x_lo,
-                       y_hi, y_lo, long_tiles, long_passes, length_order, cost_hint, hdr);
+                       y_hi, y_lo, long_tiles, long_passes, sched, cost_hint, hdr);
 }
 
 // ---------------------------------------------------------------------------
