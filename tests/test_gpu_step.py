@@ -249,3 +249,24 @@ def test_step_full_size_matches_two_passes(name):
         got = rast.step_l1(params, w2c, bg, target, ws=ws)
         _assert_same(ref, got, f"{name} step {k}")
     assert not rast.check_overflow(ws)
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_step_ring_8_views_as_autotuned_matches_two_passes(persistent):
+    """The 8-view ring at full size in the configuration the autotuner picks
+    (all views in one call, 16x32 tiles, the one-call step)."""
+    import torch
+    from paper_2607_14481_amd.rasterizer import GaussianRasterizer
+    if "ring" not in _BIG:
+        _BIG["ring"] = S.multi_view_ring()
+    wl = _BIG["ring"]
+    sc, cams = wl.scene, wl.cameras
+    rast = GaussianRasterizer(cams, sc.sh_degree, tile_h=32, persistent=persistent)
+    params, w2c = params_to_device(sc), poses_to_device(cams)
+    bg = (0.0, 0.0, 0.0)
+    img, _ = rast.forward(params, w2c, bg)
+    target, _ = _target_near(img, 41)
+    ref = _two_pass(rast, params, w2c, bg, target)
+    got = rast.step_l1(params, w2c, bg, target)
+    _assert_same(ref, got, f"8-view ring, 16x32 tiles, persistent={persistent}")
+    torch.cuda.synchronize()
