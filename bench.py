@@ -335,6 +335,54 @@ def measure_view(wl, steps, warmup, tile_h=16, persistent=False, graph=True, fus
             "graph_ms": graph_ms, "graph_err": graph_err, "ms_two_pass": ms_two_pass, "fused": fused}
 
 
+TILE_HEIGHTS = (4, 8, 16, 32)
+
+
+def pick_tile_h(wl, persistent=False, steps=5, fused=True, heights=TILE_HEIGHTS):
+    """The tile height (16 x h pixels) at which this workload's step runs
+    fastest, by a short timing of each (results do not depend on it: tile
+    membership is the exact alpha >= 1/255 box).  Returns (h, {h: ms})."""
+    import numpy as np
+    import torch
+    from paper_2607_14481_amd.rasterizer import GaussianRasterizer
+    dev = torch.device("cuda:0")
+    sc, cams = wl.scene, wl.cameras
+    params = [torch.tensor(np.asarray(getattr(sc, k), np.float32), device=dev)
+              for k in ("means", "log_scales", "quats", "opacities", "sh")]
+    w2c = torch.tensor(np.asarray(cams[0].world_to_cam, np.float32)[None], device=dev)
+    bg = (0.0, 0.0, 0.0)
+    times = {}
+    for h in heights:
+        rast = GaussianRasterizer(cams, sc.sh_degree, tile_h=h, persistent=persistent, device=dev)
+        target, ws = rast.forward(params, w2c, bg)  # (any target: only the time is used)
+        target = target.clone()
+        assert not rast.check_overflow(ws)
+        rast.sync = False
+        ws = rast.workspace(sc.n)
+
+        def step():
+            if fused:
+                rast.step_l1(params, w2c, bg, target, ws=ws)
+            else:
+                rgb, w = rast.forward(params, w2c, bg, ws=ws)
+                rast.backward_l1(w, params, w2c, bg, rgb, target)
+        for _ in range(2):
+            step()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            step()
+        b.record()
+        torch.cuda.synchronize()
+        assert not rast.check_overflow(ws)
+        times[h] = round(a.elapsed_time(b) / steps, 4)
+        del rast, ws
+    best = min(times, key=times.get)
+    log(f"[bench] tile height by measurement: {best} ({times})")
+    return best, times
+
+
 def copy_rates(sizes_mb=(8, 16, 32, 64, 128, 256, 512), reps=40):
     """Rate of a plain device copy (torch's copy kernel, half the bytes read,
     half written) by the bytes one launch moves, launches back to back on one
@@ -813,7 +861,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--two-pass", action="store_true",
                     help="time the step as forward then backward_l1 instead of one fused call")
-    ap.add_argument("--tile-h", type=int, default=16)
+    ap.add_argument("--tile-h", type=int, default=0,
+                    help="tile height 4, 8, 16 or 32 (width 16); 0: each workload's fastest, by a short timing")
     ap.add_argument("--persistent", action="store_true", help="compositing as persistent work-queue launches")
     ap.add_argument("--no-ring", action="store_true", help="skip the batched 8-view measurement")
     ap.add_argument("--no-keyframe", action="store_true",
@@ -870,7 +919,9 @@ def main():
     sc, cams = wl.scene, wl.cameras
     log(f"[bench] workload {args.workload}: n={sc.n} view {cams[0].width}x{cams[0].height} "
         f"(inputs built in {time.time() - t0:.1f}s)")
-    m = measure_view(wl, args.steps, args.warmup, args.tile_h, args.persistent, not args.no_graph,
+    tile_h, tile_ms = (args.tile_h, None) if args.tile_h else pick_tile_h(wl, args.persistent,
+                                                                           fused=not args.two_pass)
+    m = measure_view(wl, args.steps, args.warmup, tile_h, args.persistent, not args.no_graph,
                      fused=not args.two_pass)
     ms_plain, ms_instrumented, stage_ms, stats = m["ms_plain"], m["ms_instrumented"], m["stage_ms"], m["stats"]
     graph_ms, graph_err = m["graph_ms"], m["graph_err"]
@@ -891,10 +942,12 @@ def main():
             t0 = time.time()
             owl, odesc = make_workload(name)
             log(f"[bench] workload {name}: n={owl.scene.n} (inputs built in {time.time() - t0:.1f}s)")
-            om = measure_view(owl, max(10, args.steps // 2), max(3, args.warmup // 2), args.tile_h,
+            oth, oth_ms = (args.tile_h, None) if args.tile_h else pick_tile_h(owl, args.persistent)
+            om = measure_view(owl, max(10, args.steps // 2), max(3, args.warmup // 2), oth,
                               args.persistent, not args.no_graph)
             others[name] = {"workload": odesc, "n_gaussians": owl.scene.n,
                             "resolution": f"{owl.cameras[0].width}x{owl.cameras[0].height}",
+                            "tile": f"16x{oth}", "tile_ms_by_height": oth_ms,
                             "plain_iters_per_s": round(1000.0 / om["ms_plain"], 3),
                             "plain_ms_per_step": round(om["ms_plain"], 4),
                             "graph_iters_per_s": round(1000.0 / om["graph_ms"], 3) if om["graph_ms"] else None,
@@ -1006,7 +1059,7 @@ def main():
         "config": {"workload": f"{args.workload}: {desc}", "n_gaussians": sc.n,
                    "resolution": f"{cams[0].width}x{cams[0].height}", "sh_degree": sc.sh_degree,
                    "form": ("plain: one view per launch sequence, " + ("one gsr_rasterize_step_l1 call per step (compositing forward and backward fused per tile)" if m["fused"] else "forward then backward_l1") + ", no host synchronisation in the timed steps (pair capacity and long-list passes sized by synchronous warm-up steps, overflow checked after)"),
-                   "tile": f"16x{args.tile_h}", "persistent": bool(args.persistent)},
+                   "tile": f"16x{tile_h}", "tile_ms_by_height": tile_ms, "persistent": bool(args.persistent)},
         "graph_form": {"iters_per_s": round(1000.0 / graph_ms, 3) if graph_ms else None,
                        "ms_per_step": round(graph_ms, 4) if graph_ms else None, "error": graph_err},
         "two_pass_form": ({"iters_per_s": round(1000.0 / m["ms_two_pass"], 3),
