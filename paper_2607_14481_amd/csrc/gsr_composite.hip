@@ -470,6 +470,10 @@ __device__ __forceinline__ void tile_backward(const ViewTable &vt, const TileCtx
                 }
                 if (!live) zq |= 1u << q;  // every moment is zero: the finaliser writes 0
                 if (live) {
+                    // (no contraction: a product contracted into the first DPP add
+                    // costs a separate lane move, and its four quad lanes would no
+                    // longer add a and b as b and a)
+#pragma clang fp contract(off)
                     // the moments of sa (= -dL/dsigma): sums of sa dx, sa dy, sa dx^2,
                     // sa dx dy, sa dy^2 (the negated S_x .. S_yy of the projection
                     // backward), then S_o = sum sa and the colour gradient
