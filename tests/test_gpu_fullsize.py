@@ -24,13 +24,13 @@ from ._util import (GRAD_KEYS, GRAD_TOL, compare_grads, compare_view, gpu_render
 pytestmark = pytest.mark.gpu
 
 
-def _full_parity(wl, seed, bg=(0.0, 0.0, 0.0)):
+def _full_parity(wl, seed, bg=(0.0, 0.0, 0.0), tile_h=16):
     sc, cam = wl.scene, wl.cameras[0]
     up = S.random_upstream(seed, (cam.height, cam.width, 3))
-    log(f"{wl.name}: GPU fwd+bwd n={sc.n} {cam.width}x{cam.height} (host-sync-free forward)")
-    gpu = gpu_render(sc, [cam], bg=bg, upstream=[up], bench_form=True)
+    log(f"{wl.name}: GPU fwd+bwd n={sc.n} {cam.width}x{cam.height}, 16x{tile_h} tiles (host-sync-free forward)")
+    gpu = gpu_render(sc, [cam], bg=bg, upstream=[up], bench_form=True, tile_h=tile_h)
     log(f"{wl.name}: oracle fwd+bwd over the whole view")
-    ref = O.render(sc, cam, bg=bg, dL_dimg=up)
+    ref = O.render(sc, cam, bg=bg, dL_dimg=up, tile=(16, tile_h))  # (the pair count depends on the tile shape)
     compare_view(gpu["imgs"][0], ref, wl.name)
     assert gpu["stats"]["pairs"] == ref["M"]
     compare_grads(gpu, ref, wl.name)
@@ -80,8 +80,10 @@ def _lod():
     return lod_workload()
 
 
-def test_lod_cut_1080p_full_parity():
-    _full_parity(_lod(), seed=103)
+@pytest.mark.parametrize("tile_h", [16, 8])
+def test_lod_cut_1080p_full_parity(tile_h):
+    """At 16x16 tiles and at the 16x8 tiles the benchmark picks for this view."""
+    _full_parity(_lod(), seed=103, tile_h=tile_h)
 
 
 @pytest.mark.parametrize("bench_form", [False, True])

@@ -223,17 +223,18 @@ def _big(name):
     return _BIG[name]
 
 
-@pytest.mark.parametrize("name", ["headline", "lod_cut"])
-def test_step_full_size_matches_two_passes(name):
+@pytest.mark.parametrize("name,tile_h", [("headline", 16), ("lod_cut", 16), ("lod_cut", 8)])
+def test_step_full_size_matches_two_passes(name, tile_h):
     """The 1080p, 1M-Gaussian headline view as the benchmark runs it (a
     synchronous step sizes the capacity, then steps without host
     synchronisation reuse one workspace), and the level-of-detail view whose
-    longest tile lists need seven merge passes."""
+    longest tile lists need seven merge passes at 16x16 tiles (six at the
+    16x8 tiles the benchmark picks for it)."""
     import torch
     from paper_2607_14481_amd.rasterizer import GaussianRasterizer
     wl = _big(name)
     sc, cams = wl.scene, wl.cameras[:1]
-    rast = GaussianRasterizer(cams, sc.sh_degree)
+    rast = GaussianRasterizer(cams, sc.sh_degree, tile_h=tile_h)
     params, w2c = params_to_device(sc), poses_to_device(cams)
     bg = (0.0, 0.0, 0.0)
     img, ws0 = rast.forward(params, w2c, bg)
@@ -247,7 +248,7 @@ def test_step_full_size_matches_two_passes(name):
            for x in ref]
     for k in range(2):  # the second step's schedule comes from the first's replay counts
         got = rast.step_l1(params, w2c, bg, target, ws=ws)
-        _assert_same(ref, got, f"{name} step {k}")
+        _assert_same(ref, got, f"{name} 16x{tile_h} step {k}")
     assert not rast.check_overflow(ws)
 
 
