@@ -410,6 +410,11 @@ __device__ __forceinline__ void tile_backward(const ViewTable &vt, const TileCtx
                                               float (&T)[RPL], const float (&g0)[RPL], const float (&g1)[RPL],
                                               const float (&g2)[RPL], float (&gB)[RPL], const uint32_t (&ncon)[RPL],
                                               float *__restrict__ partial, uint8_t *__restrict__ pflag) {
+    // per-lane sums over one Gaussian's rows: colour-gradient weights w,
+    // sa = alpha dL/dalpha, sa dy and sa dy^2 (the rows share dx); zero
+    // between Gaussians (a Gaussian no lane reaches leaves them so, and the
+    // reduction of one that some lane reaches resets them)
+    float a_c0 = 0.f, a_c1 = 0.f, a_c2 = 0.f, a_sa = 0.f, a_say = 0.f, a_sayy = 0.f;
     for (uint32_t b0 = rg.x; b0 < end; b0 += kWave) {
         const uint32_t idx = b0 + lane;
         if (idx < end) {
@@ -428,9 +433,7 @@ __device__ __forceinline__ void tile_backward(const ViewTable &vt, const TileCtx
 #pragma unroll
             for (int q = 0; q < kGroup; ++q) {
                 const int j = j0 + q;
-                // per-lane sums over the rows: colour-gradient weights w, sa = alpha
-                // dL/dalpha, sa dy and sa dy^2 (the rows share dx)
-                float a_c0 = 0.f, a_c1 = 0.f, a_c2 = 0.f, a_sa = 0.f, a_say = 0.f, a_sayy = 0.f, dx = 0.f;
+                float dx = 0.f;
                 bool live = false;  // wave-uniform: some lane reached some row of this Gaussian
                 if (j < cnt) {
                     const uint32_t pos = b0 - rg.x + (uint32_t)j;
@@ -497,6 +500,7 @@ __device__ __forceinline__ void tile_backward(const ViewTable &vt, const TileCtx
 #pragma unroll
                     for (int cc = 0; cc < kPartialStride; ++cc)
                         red[(lane >> 2) * kRedStride + q * kPartialStride + cc] = s[cc];
+                    a_c0 = a_c1 = a_c2 = a_sa = a_say = a_sayy = 0.f;
                 }
             }
             __syncthreads();

@@ -27,14 +27,17 @@ def _upstream(seed, cams):
     return [S.random_upstream(seed + v, (c.height, c.width, 3)) for v, c in enumerate(cams)]
 
 
-def test_small_view_forward_backward_parity():
+@pytest.mark.parametrize("tile_h", [16, 8, 4])
+def test_small_view_forward_backward_parity(tile_h):
+    """The small view of the benchmark, at 16x16 tiles and at the smaller
+    tiles its tile-height timing picks."""
     wl = S.small_view(seed=1)
     sc, cams = wl.scene, wl.cameras
     up = _upstream(7, cams)
     bg = (0.1, 0.2, 0.3)
-    log("small_view 128x128 n=1000: GPU forward+backward")
-    gpu = gpu_render(sc, cams, bg=bg, upstream=up)
-    ref = O.render(sc, cams[0], bg=bg, dL_dimg=up[0])
+    log(f"small_view 128x128 n=1000, 16x{tile_h} tiles: GPU forward+backward")
+    gpu = gpu_render(sc, cams, bg=bg, upstream=up, tile_h=tile_h)
+    ref = O.render(sc, cams[0], bg=bg, dL_dimg=up[0], tile=(16, tile_h))
     _compare_view(gpu["imgs"][0], ref, "small_view")
     assert gpu["stats"]["pairs"] == ref["M"]
     _compare_grads(gpu, ref, "small_view")
