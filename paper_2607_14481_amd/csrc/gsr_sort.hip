@@ -172,14 +172,20 @@ __global__ __launch_bounds__(kScanThreads) void k_vis_apply(ViewTable vt, uint64
                                                             uint4 *__restrict__ item_box,
                                                             uint32_t *__restrict__ chunk_item, uint64_t chunks_cap,
                                                             WsHeader *__restrict__ hdr) {
-    __shared__ uint32_t lds[4];
-    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
-    uint32_t c[kScanItems], nv = 0, np = 0;
+    // The block's kScanTile items in kScanItems rounds of kScanThreads
+    // consecutive ones (round k, thread t: item base + k kScanThreads + t), so
+    // that every load and store of a round is row-contiguous across the wave.
+    // Per wave and round: the inclusive totals of the visible flags and the
+    // pair counts; last, the wave's part of the sums of the blocks before.
+    constexpr int kV = kScanItems * 2;
+    __shared__ uint32_t s_w[4][kV + 2];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    uint32_t c[kScanItems];
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        c[k] = base + k < n ? count[base + k] : 0u;
-        nv += c[k] > 0u ? 1u : 0u;
-        np = sat_add(np, c[k]);
+        const uint64_t it = base + (uint64_t)k * kScanThreads + tid;
+        c[k] = it < n ? count[it] : 0u;
     }
     // the visible items' boxes and depth keys, all requested before the scans
     // (the stores below into the same records would otherwise order each load
@@ -189,42 +195,67 @@ __global__ __launch_bounds__(kScanThreads) void k_vis_apply(ViewTable vt, uint64
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         if (c[k] > 0u) {
-            r2[k] = rec[base + k].r2;
-            z[k] = zkey[base + k];
+            const uint64_t it = base + (uint64_t)k * kScanThreads + tid;
+            r2[k] = rec[it].r2;
+            z[k] = zkey[it];
         }
     }
     // the sums of the blocks before this one
     uint32_t bv = 0, bp = 0;
-    for (uint32_t j = threadIdx.x; j < blockIdx.x; j += kScanThreads) {
+    for (uint32_t j = tid; j < blockIdx.x; j += kScanThreads) {
         bv += block_vis[j];
         bp = sat_add(bp, block_pairs[j]);
     }
-    uint32_t tv, tp;
-    block_exclusive_scan(bv, lds, tv);
-    block_exclusive_scan(bp, lds, tp);
-    const uint32_t v0 = tv, p0 = tp;
-    uint32_t kv = v0 + block_exclusive_scan(nv, lds, tv);
-    uint32_t run = sat_add(p0, block_exclusive_scan(np, lds, tp));
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
-        const uint32_t pairs = sat_add(p0, tp);
-        hdr->n_visible = v0 + tv;
-        hdr->n_pairs = pairs;
-        hdr->overflow = pairs > hdr->pair_capacity ? 1u : 0u;
+    bv = wave_reduce(bv, 0u, sat_add);
+    bp = wave_reduce(bp, 0u, sat_add);
+    uint32_t fv[kScanItems], fp[kScanItems];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        fv[k] = wave_inclusive_scan(c[k] > 0u ? 1u : 0u, sat_add);
+        fp[k] = wave_inclusive_scan(c[k], sat_add);
+    }
+    if (lane == kWave - 1) {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) s_w[w][k] = fv[k], s_w[w][kScanItems + k] = fp[k];
+        s_w[w][kV] = bv;
+        s_w[w][kV + 1] = bp;
+    }
+    __syncthreads();
+    uint32_t v0 = 0, p0 = 0;  // visible items and pairs before the current round
+#pragma unroll
+    for (int ww = 0; ww < 4; ++ww) v0 = sat_add(v0, s_w[ww][kV]), p0 = sat_add(p0, s_w[ww][kV + 1]);
+    uint32_t kv[kScanItems], run[kScanItems];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        uint32_t ov = 0, op = 0, tv = 0, tp = 0;  // waves before this one; the whole round
+#pragma unroll
+        for (int ww = 0; ww < 4; ++ww) {
+            if (ww < w) ov = sat_add(ov, s_w[ww][k]), op = sat_add(op, s_w[ww][kScanItems + k]);
+            tv = sat_add(tv, s_w[ww][k]);
+            tp = sat_add(tp, s_w[ww][kScanItems + k]);
+        }
+        kv[k] = sat_add(sat_add(v0, ov), fv[k] - (c[k] > 0u ? 1u : 0u));
+        run[k] = sat_add(sat_add(p0, op), fp[k] - c[k]);
+        v0 = sat_add(v0, tv);
+        p0 = sat_add(p0, tp);
+    }
+    if (blockIdx.x == gridDim.x - 1 && tid == 0) {
+        hdr->n_visible = v0;
+        hdr->n_pairs = p0;
+        hdr->overflow = p0 > hdr->pair_capacity ? 1u : 0u;
     }
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         if (c[k] > 0u) {
-            const uint32_t item = (uint32_t)(base + k);
-            vis[kv] = item;
-            poff[kv] = run;
-            item_box[kv] = item_box_word(vt, n_view, item, r2[k], z[k]);
-            rec[item].r2.w = __uint_as_float(run);  // the item's first pair, for the later passes
+            const uint32_t item = (uint32_t)(base + (uint64_t)k * kScanThreads + tid);
+            vis[kv[k]] = item;
+            poff[kv[k]] = run[k];
+            item_box[kv[k]] = item_box_word(vt, n_view, item, r2[k], z[k]);
+            rec[item].r2.w = __uint_as_float(run[k]);  // the item's first pair, for the later passes
             // chunks whose first pair lies in [run, run + c)
-            const uint32_t end = sat_add(run, c[k]);
-            for (uint64_t ch = chunk_count(run); ch < chunks_cap && ch * kChunkPairs < end; ++ch)
-                chunk_item[ch] = kv;
-            ++kv;
-            run = end;
+            const uint32_t end = sat_add(run[k], c[k]);
+            for (uint64_t ch = chunk_count(run[k]); ch < chunks_cap && ch * kChunkPairs < end; ++ch)
+                chunk_item[ch] = kv[k];
         }
     }
 }
