@@ -291,7 +291,8 @@ int backward_tail(const gsr_gaussians *g, const gsr::ViewTable &vt, const float 
                        p.pose_part, L.pose_blocks, p.view_seg, vt.total_tiles == 0, st);
     if (g->n == 0)  // no Gaussian wrote a partial: the pose gradient is zero
         launch_fill_u32(reinterpret_cast<uint32_t *>(p.pose_part), 0u, 12ull * vt.n_views * L.pose_blocks, st);
-    launch_pose_finalize(vt, world_to_cam, p.pose_part, L.pose_blocks, dL_dworld_to_cam, dL_dtwist, st);
+    launch_pose_finalize(vt, world_to_cam, p.pose_part, L.pose_blocks, p.hdr, p.view_seg, vt.total_tiles != 0,
+                         dL_dworld_to_cam, dL_dtwist, st);
     mark.end(GSR_STAGE_PROJECT_BWD);
     return check_hip(hipGetLastError(), "backward launch");
 }

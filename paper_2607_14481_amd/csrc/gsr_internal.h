@@ -239,8 +239,11 @@ void launch_project_bwd(const gsr_gaussians &g, const ViewTable &vt, const float
                         const Rec *rec, const uint32_t *count, const uint32_t *vis, const WsHeader *hdr,
                         const float4 *screen, const float *carry, const gsr_gaussian_grads &gr, float *pose_part,
                         uint32_t pose_blocks, uint32_t *seg, bool zero_unseen, hipStream_t st);
+// dense: the partials come from the per-view launches over the visible items
+// (only the blocks with items are summed; seg as for launch_project_bwd).
 void launch_pose_finalize(const ViewTable &vt, const float *w2c, const float *pose_part, uint32_t pose_blocks,
-                          float *dL_dw2c, float *dL_dtwist, hipStream_t st);
+                          const WsHeader *hdr, const uint32_t *seg, bool dense, float *dL_dw2c, float *dL_dtwist,
+                          hipStream_t st);
 
 // Ordered compaction of byte flags (gsr_sort.hip).
 void launch_compact_flags(const uint8_t *flags, uint64_t n, uint32_t *out_idx, uint32_t *block_tmp,

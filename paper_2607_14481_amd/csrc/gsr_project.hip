@@ -1052,21 +1052,31 @@ void launch_project_bwd(const gsr_gaussians &g, const ViewTable &vt, const float
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(768) void k_pose_finalize(const float *__restrict__ w2c,
                                                        const float *__restrict__ pose_part, uint32_t pose_blocks,
+                                                       const WsHeader *__restrict__ hdr,
+                                                       const uint32_t *__restrict__ seg, int dense,
                                                        float *__restrict__ dL_dw2c, float *__restrict__ dL_dtwist) {
     // one workgroup per view, one wave per entry of the top 3x4 block
     __shared__ float G[16];
     const int v = blockIdx.x;
     const int k = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the dense backward's grid is sized by capacity: only the blocks that had
+    // items of this view's segment wrote a nonzero partial
+    uint32_t used = pose_blocks;
+    if (dense) {
+        const uint32_t nvis = hdr->overflow ? 0u : hdr->n_visible;
+        const uint32_t lo = seg ? min(seg[v], nvis) : 0u, hi = seg ? min(seg[v + 1], nvis) : nvis;
+        used = min(pose_blocks, (hi - lo + (uint32_t)kProjThreads - 1u) / (uint32_t)kProjThreads);
+    }
     const float *src = pose_part + ((size_t)v * 12 + k) * pose_blocks;
     float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;  // independent loads in flight
     uint32_t b = lane;
-    for (; b + 192 < pose_blocks; b += 256) {
+    for (; b + 192 < used; b += 256) {
         acc0 += src[b];
         acc1 += src[b + 64];
         acc2 += src[b + 128];
         acc3 += src[b + 192];
     }
-    for (; b < pose_blocks; b += 64) acc0 += src[b];
+    for (; b < used; b += 64) acc0 += src[b];
     const float acc = wave_sum((acc0 + acc1) + (acc2 + acc3));
     if (lane == 0) G[k] = acc;
     if (threadIdx.x == 0) G[12] = G[13] = G[14] = G[15] = 0.f;
@@ -1090,10 +1100,11 @@ __global__ __launch_bounds__(768) void k_pose_finalize(const float *__restrict__
 }
 
 void launch_pose_finalize(const ViewTable &vt, const float *w2c, const float *pose_part, uint32_t pose_blocks,
-                          float *dL_dw2c, float *dL_dtwist, hipStream_t st) {
+                          const WsHeader *hdr, const uint32_t *seg, bool dense, float *dL_dw2c, float *dL_dtwist,
+                          hipStream_t st) {
     if (!dL_dw2c && !dL_dtwist) return;
-    hipLaunchKernelGGL(k_pose_finalize, dim3(vt.n_views), dim3(768), 0, st, w2c, pose_part, pose_blocks, dL_dw2c,
-                       dL_dtwist);
+    hipLaunchKernelGGL(k_pose_finalize, dim3(vt.n_views), dim3(768), 0, st, w2c, pose_part, pose_blocks, hdr,
+                       vt.n_views > 1 ? seg : nullptr, dense ? 1 : 0, dL_dw2c, dL_dtwist);
 }
 
 }  // namespace gsr
