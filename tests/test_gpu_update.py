@@ -95,6 +95,58 @@ def test_sparse_adam_updates_only_what_the_forward_saw():
     _compare(_host(M), refM, "sparse adam exp_avg")
 
 
+@pytest.mark.parametrize("deg,n_views", [(0, 1), (1, 3), (2, 2), (3, 1), (3, 4)])
+def test_sparse_adam_is_the_dense_step_on_the_seen_rows(deg, n_views):
+    """Every SH row width, one view and several overlapping ones: the sparse
+    step (which walks the visible-item list, each Gaussian by the first view
+    that saw it) leaves unseen rows untouched bit for bit, gives the seen rows
+    exactly what the dense step gives them, two steps running, and matches the
+    oracle restricted to the union of the views' visible sets."""
+    import torch
+    from paper_2607_14481_amd import gsr
+    from paper_2607_14481_amd.rasterizer import GaussianRasterizer
+    from ._util import params_to_device, poses_to_device
+    wl = S.small_view(seed=20 + deg, n=3000 + 17 * deg, width=96, height=72, sh_degree=deg, xy_half=2.5)
+    sc, cam = wl.scene, wl.cameras[0]
+    # further views: the first pose turned and moved a little (overlapping sets)
+    cams = [cam] + [cam.copy_with_pose(S.perturbed_pose(cam.world_to_cam, seed=40 + v, degrees=12.0, metres=0.4))
+                    for v in range(1, n_views)]
+    vis = np.zeros(sc.n, bool)
+    per_view = []
+    for c in cams:
+        pv = O.project(sc, c)["visible"]
+        per_view.append(int(pv.sum()))
+        vis |= pv
+    log(f"sparse adam deg {deg}, {n_views} views: {int(vis.sum())} of {sc.n} seen (per view {per_view})")
+    assert 0 < vis.sum() < sc.n
+    if n_views > 1:
+        assert sum(per_view) > vis.sum()  # the views overlap: some Gaussians are listed more than once
+    rast = GaussianRasterizer(cams, sc.sh_degree)
+    params = params_to_device(sc)
+    _, ws = rast.forward(params, poses_to_device(cams))
+    rng = np.random.default_rng(30 + deg)
+    host = {k: np.asarray(getattr(sc, k), np.float32) for k in KEYS}
+    grads = [{k: rng.standard_normal(host[k].shape).astype(np.float32) for k in KEYS} for _ in range(2)]
+    zero = {k: np.zeros_like(host[k]) for k in KEYS}
+    P_s, M_s, V_s = _dev(host), _dev(zero), _dev(zero)
+    P_d, M_d, V_d = _dev(host), _dev(zero), _dev(zero)
+    refP, refM, refV = host, zero, zero
+    for step, g in enumerate(grads, start=1):
+        gsr.adam_step(P_s, _dev(g), M_s, V_s, sc.sh_degree, step, _acfg(gsr, sparse=True), ws=ws, cams=cams,
+                      cfg=rast.cfg)
+        gsr.adam_step(P_d, _dev(g), M_d, V_d, sc.sh_degree, step, _acfg(gsr))
+        refP, refM, refV = U.adam(refP, g, refM, refV, step, LRS, 0.9, 0.999, 1e-8, visible=vis)
+    torch.cuda.synchronize()
+    for got, dense, base in ((P_s, P_d, host), (M_s, M_d, zero), (V_s, V_d, zero)):
+        hs, hd = _host(got), _host(dense)
+        for k in KEYS:
+            np.testing.assert_array_equal(hs[k][~vis], base[k][~vis].astype(np.float64), err_msg=k)
+            np.testing.assert_array_equal(hs[k][vis], hd[k][vis], err_msg=k)
+    _compare(_host(P_s), refP, "sparse adam params")
+    _compare(_host(M_s), refM, "sparse adam exp_avg")
+    _compare(_host(V_s), refV, "sparse adam exp_avg_sq", rtol=1e-4, atol=1e-9)
+
+
 def test_pose_step_matches_oracle():
     import torch
     from paper_2607_14481_amd import gsr
