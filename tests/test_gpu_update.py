@@ -147,6 +147,74 @@ def test_sparse_adam_is_the_dense_step_on_the_seen_rows(deg, n_views):
     _compare(_host(V_s), refV, "sparse adam exp_avg_sq", rtol=1e-4, atol=1e-9)
 
 
+@pytest.mark.parametrize("deg", [1, 3])
+def test_keyframe_loop_matches_the_oracle_step_by_step(deg):
+    """The keyframe optimisation as timed (the one-call L1 step on a reused
+    workspace with no host synchronisation, the sparse Adam step on that
+    workspace, the pose step on the twist gradient), three iterations.  Each
+    iteration is checked from the state the GPU reached before it: the image,
+    Gaussian and twist gradients against the oracle's render of that state,
+    then the parameters and the pose against the oracle's update applied to
+    the GPU's gradients.  The target lies 0.05..0.1 from the start image, so
+    the sign of C - target, the L1 gradient, is the same on both sides."""
+    import torch
+    from paper_2607_14481_amd import gsr
+    from paper_2607_14481_amd.rasterizer import GaussianRasterizer
+    from ._util import (GRAD_KEYS, GRAD_TOL, compare_grads, compare_view, params_to_device, planar_to_hwc,
+                        poses_to_device, rel_err)
+    wl = S.small_view(seed=50 + deg, n=2500, width=96, height=72, sh_degree=deg, xy_half=2.0)
+    sc, cam = wl.scene, wl.cameras[0]
+    bg = (0.0, 0.0, 0.0)
+    img0 = O.render(sc, cam, bg=bg)["img"]
+    rng = np.random.default_rng(60 + deg)
+    sgn = np.where(rng.random(img0.shape) < 0.5, -1.0, 1.0)
+    tgt = img0 + sgn * rng.uniform(0.05, 0.1, img0.shape)
+    up = -sgn / float(img0.size)  # dL/dC = sign(C - target) / (3 H W) while |C - C0| < 0.05
+    target = torch.tensor(np.ascontiguousarray(tgt.transpose(2, 0, 1)).reshape(-1).astype(np.float32), device="cuda")
+
+    rast = GaussianRasterizer([cam], sc.sh_degree)
+    params, w2c = params_to_device(sc), poses_to_device([cam])
+    rast.forward(params, w2c, bg)  # a synchronous forward sizes the pair capacity
+    rast.sync = False
+    ws = rast.workspace(sc.n)
+    rgb = torch.empty_like(target)
+    m = [torch.zeros_like(t) for t in params]
+    v = [torch.zeros_like(t) for t in params]
+    pm, pv = torch.zeros((1, 6), device="cuda"), torch.zeros((1, 6), device="cuda")
+    acfg, lr_pose = _acfg(gsr, sparse=True), 1e-4
+    def host(ts):
+        return {k: t.cpu().numpy().astype(np.float64) for k, t in zip(KEYS, ts)}
+
+    for it in (1, 2, 3):
+        P, M, V = host(params), host(m), host(v)
+        T, PM, PV = w2c.cpu().numpy()[0].astype(np.float64), pm.cpu().numpy(), pv.cpu().numpy()
+        _, _, grads, _, twist = rast.step_l1(params, w2c, bg, target, ws=ws, out=rgb)
+        G = {k: t.cpu().numpy() for k, t in zip(KEYS, grads)}
+        tw = twist.cpu().numpy()
+        gsr.adam_step(params, grads, m, v, sc.sh_degree, it, acfg, ws=ws, cams=[cam], cfg=rast.cfg)
+        gsr.pose_step(w2c, twist, pm, pv, it, lr_pose, eps=1e-8)
+        torch.cuda.synchronize()
+        assert not rast.check_overflow(ws)
+        # the step against the oracle at the state before it
+        state = S.Scene(*(P[k].astype(np.float32) for k in KEYS), sc.sh_degree)
+        c_t = cam.copy_with_pose(T.astype(np.float32))
+        ref = O.render(state, c_t, bg=bg, dL_dimg=up)
+        compare_view(planar_to_hwc(rgb, [c_t])[0], ref, f"keyframe deg {deg} it {it}")
+        compare_grads({k: G[k].astype(np.float64) for k in GRAD_KEYS}, {k: ref[k] for k in GRAD_KEYS},
+                      f"keyframe deg {deg} it {it}")
+        assert rel_err(tw[0], ref["twist"]) <= GRAD_TOL
+        # the updates against the oracle's, from the GPU's gradients
+        seen = O.project(state, c_t)["visible"]
+        refP, refM, refV = U.adam(P, G, M, V, it, LRS, 0.9, 0.999, 1e-8, visible=seen)
+        _compare(host(params), refP, f"keyframe it {it} params")
+        _compare(host(m), refM, f"keyframe it {it} exp_avg")
+        refT, _, _ = U.pose_step(T[None], tw, PM, PV, it, lr_pose, 0.9, 0.999, 1e-8)
+        np.testing.assert_allclose(w2c.cpu().numpy()[0], refT[0], atol=2e-6, rtol=0)
+        moved = np.abs(refT[0] - T).max()
+        log(f"keyframe deg {deg} it {it}: {int(seen.sum())} of {sc.n} seen, pose moved {moved:.2e}")
+        assert 0 < seen.sum() < sc.n and moved > 1e-5  # a real sparse step, a real pose step
+
+
 def test_pose_step_matches_oracle():
     import torch
     from paper_2607_14481_amd import gsr
