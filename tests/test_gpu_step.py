@@ -271,3 +271,46 @@ def test_step_ring_8_views_as_autotuned_matches_two_passes(persistent):
     got = rast.step_l1(params, w2c, bg, target)
     _assert_same(ref, got, f"8-view ring, 16x32 tiles, persistent={persistent}")
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_step_graph_replays_match_eager(persistent):
+    """The one-call step captured in a HIP graph, as the benchmark's graph form
+    runs it (no host synchronisation, capacity from an eager step): every
+    replay, with other eager work through the library between replays, gives
+    the eager step's image and gradients bit for bit.  The replays carry the
+    fused kernel's schedule (the previous step's replay counts) and, with
+    persistent compositing, its work-queue counters from one to the next."""
+    import torch
+    from paper_2607_14481_amd.rasterizer import GaussianRasterizer
+    sc, cams = _views("ring3_sh3")
+    bg = (0.0, 0.0, 0.0)
+    params, w2c = params_to_device(sc), poses_to_device(cams)
+    eager = GaussianRasterizer(cams, sc.sh_degree, persistent=persistent)
+    img, _ = eager.forward(params, w2c, bg)
+    target, _ = _target_near(img, 31)
+    ref = eager.step_l1(params, w2c, bg, target)
+    torch.cuda.synchronize()
+    assert not eager.check_overflow(ref[1])  # records the pair count
+    g = GaussianRasterizer(cams, sc.sh_degree, persistent=persistent, sync=False)
+    g.capacity = int(eager.last_pairs * 1.2) + 1024
+    ws = g.workspace(sc.n)
+    out = torch.empty_like(img)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(2):
+            g.step_l1(params, w2c, bg, target, ws=ws, out=out)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        got = g.step_l1(params, w2c, bg, target, ws=ws, out=out)
+    for rep in range(4):
+        junk = GaussianRasterizer(cams, sc.sh_degree)
+        junk.step_l1([params[0] * 1.01] + params[1:], w2c, bg, target)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert not g.check_overflow(ws)
+        _assert_same(ref, got, f"graph replay {rep} (persistent {persistent})")
