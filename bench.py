@@ -526,7 +526,7 @@ def run_keyframe(wl, iterations=30, repeats=3):
                                 "algorithmic_bytes": nbytes, "GB_per_s": round(nbytes / us / 1e3, 1)}}
 
 
-def run_lod_cut_gpu(wl, reps=10):
+def run_lod_cut_gpu(wl, reps=10, tile_h=16):
     """The level-of-detail cut on the GPU for the street hierarchy (all nodes
     resident in HBM): cut selection (blocking: includes reading the count
     back) and the gather of the cut's rows, checked against the host cut."""
@@ -587,7 +587,7 @@ def run_lod_cut_gpu(wl, reps=10):
 
     # the whole level-of-detail step with no host round trip: the cut writes its
     # size to a device scalar that the gather and the rasterizer read; cut,
-    # gather, forward and L1 backward are captured in one graph and replayed
+    # gather and the one-call L1 step are captured in one graph and replayed
     from paper_2607_14481_amd.rasterizer import GaussianRasterizer
     nn = int(h.nodes.n)
     tw2c = torch.tensor(np.asarray(wl.target_cameras[0].world_to_cam, np.float32)[None], device=dev)
@@ -595,7 +595,7 @@ def run_lod_cut_gpu(wl, reps=10):
     count = torch.zeros(1, dtype=torch.int64, device=dev)
     idx = torch.empty(nn, dtype=torch.int32, device=dev)
     buf = [torch.empty_like(t) for t in nodes]
-    rast = GaussianRasterizer([cam], 3, active_count=count)
+    rast = GaussianRasterizer([cam], 3, tile_h=tile_h, active_count=count)
     gsr.hierarchy_cut_async(nodes, 3, parent, counts, cam, w2c, 1.5, scratch, idx, count)
     gsr.gather_gaussians(nodes, 3, idx, count=count, dst=buf)
     rgb, ws0 = rast.forward(buf, w2c[None])  # synchronous: sizes the pair capacity and long-list passes
@@ -607,8 +607,7 @@ def run_lod_cut_gpu(wl, reps=10):
     def step():
         gsr.hierarchy_cut_async(nodes, 3, parent, counts, cam, w2c, 1.5, scratch, idx, count)
         gsr.gather_gaussians(nodes, 3, idx, count=count, dst=buf)
-        rast.forward(buf, w2c[None], ws=ws, out=rgb)
-        return rast.backward_l1(ws, buf, w2c[None], (0.0, 0.0, 0.0), rgb, target)
+        return rast.step_l1(buf, w2c[None], (0.0, 0.0, 0.0), target, ws=ws, out=rgb)
 
     graph_ms = None
     try:
@@ -632,7 +631,7 @@ def run_lod_cut_gpu(wl, reps=10):
         torch.cuda.synchronize()
         graph_ms = a.elapsed_time(b) / reps
         assert int(count.item()) == cut.numel() and not rast.check_overflow(ws)
-        log(f"[bench] lod step (cut + gather + fwd + bwd) in one graph: {graph_ms:.3f} ms")
+        log(f"[bench] lod step (cut + gather + one-call step) in one graph: {graph_ms:.3f} ms")
     except Exception as e:  # reported, never hidden
         log(f"[bench] lod step graph failed: {e!r}")
         graph_ms = repr(e)
@@ -643,7 +642,7 @@ def run_lod_cut_gpu(wl, reps=10):
                                 "links_same_as_host_build": same_links, "algorithmic_bytes": build_bytes,
                                 "GB_per_s": round(build_bytes / (ms_build * 1e-3) / 1e9, 1)},
             "step_in_one_graph_ms": round(graph_ms, 4) if isinstance(graph_ms, float) else graph_ms,
-            "step_in_one_graph_note": "cut (size to a device scalar) + gather + forward + L1 backward, arrays and "
+            "step_in_one_graph_note": f"cut (size to a device scalar) + gather + the one-call L1 step at 16x{tile_h} tiles, arrays and "
                                       "workspace sized for all nodes, replayed from one HIP graph"}
 
 
@@ -957,7 +956,7 @@ def main():
                             "stage_ms": {k: round(v, 4) for k, v in om["stage_ms"].items()},
                             "work": om["stats"], "meta": owl.meta, "_wl": owl}
             if name == "lod_cut":
-                others[name]["gpu_cut"] = run_lod_cut_gpu(owl)
+                others[name]["gpu_cut"] = run_lod_cut_gpu(owl, tile_h=oth)
             del om
             torch.cuda.empty_cache()
 

@@ -85,14 +85,15 @@ def test_street_hierarchy_cut_and_gather():
     np.testing.assert_array_equal(sub[4].cpu().numpy(), h.nodes.sh[pick])
 
 
-def test_cut_gather_rasterize_captured_in_one_graph():
-    """Cut, gather and a rasterizer step (forward + backward) enqueued with no
-    host round trip: the cut writes its size to a device scalar, the gather
-    and the rasterizer read it.  The whole step is captured in one graph and
-    replayed with eager work in between; every replay must equal the eager
-    path that reads the cut size back (bit-identical images and parameter
-    gradients), and the image must match the FP64 oracle rendering the
-    oracle's cut."""
+@pytest.mark.parametrize("one_call", [False, True])
+def test_cut_gather_rasterize_captured_in_one_graph(one_call):
+    """Cut, gather and a rasterizer step (forward + backward, or the one-call
+    L1 step) enqueued with no host round trip: the cut writes its size to a
+    device scalar, the gather and the rasterizer read it.  The whole step is
+    captured in one graph and replayed with eager work in between; every
+    replay must equal the eager path that reads the cut size back
+    (bit-identical images and parameter gradients), and the image must match
+    the FP64 oracle rendering the oracle's cut."""
     import torch
     from oracle import oracle as O
     from paper_2607_14481_amd import gsr
@@ -117,7 +118,11 @@ def test_cut_gather_rasterize_captured_in_one_graph():
     sub = gsr.gather_gaussians(nodes, 2, cut)
     ref_rast = GaussianRasterizer([cam], 2)
     rgb_ref, ws_ref = ref_rast.forward(sub, w2c[None])
-    g_ref, gw_ref, _ = ref_rast.backward(ws_ref, sub, w2c[None], (0.0, 0.0, 0.0), rgb_ref, up)
+    target = rgb_ref + 0.03 * torch.sign(up)  # for the one-call L1 step
+    if one_call:
+        rgb_ref, ws_ref, g_ref, gw_ref, _ = ref_rast.step_l1(sub, w2c[None], (0.0, 0.0, 0.0), target)
+    else:
+        g_ref, gw_ref, _ = ref_rast.backward(ws_ref, sub, w2c[None], (0.0, 0.0, 0.0), rgb_ref, up)
     torch.cuda.synchronize()
     log(f"graph cut: {nn} nodes, cut {m}")
     assert 0 < m < nn
@@ -135,6 +140,9 @@ def test_cut_gather_rasterize_captured_in_one_graph():
     def step():
         gsr.hierarchy_cut_async(nodes, 2, parent, counts, cam, w2c, tau, scratch, idx, count)
         gsr.gather_gaussians(nodes, 2, idx, count=count, dst=buf)
+        if one_call:
+            _, _, grads, gw, gt = rast.step_l1(buf, w2c[None], (0.0, 0.0, 0.0), target, ws=ws, out=rgb)
+            return grads, gw, gt
         rast.forward(buf, w2c[None], ws=ws, out=rgb)
         return rast.backward(ws, buf, w2c[None], (0.0, 0.0, 0.0), rgb, up)
 
